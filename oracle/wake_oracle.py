@@ -1,0 +1,446 @@
+"""Plain, slow CPU oracle of the gridless quasistatic plasma-ring model.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+runs this file; only the tests, the smoke check and the CPU-baseline leg of
+the benchmark do.  It shares no code with the HIP path.
+
+What it computes (paper: "Gridless quasistatic model", Sec. "Numerical
+integration of wakefields", "Key algorithmic adjustments", Fig. 2 right
+column, Appendix "Solve recursive system"):  electron plasma rings (q=-1,
+m=1) over an immobile ion species, marched in xi = -zeta, one slice at a
+time:
+
+  sort rings radially -> gather beam/laser sources -> psi, d_rho psi,
+  d_zeta psi -> gamma -> A, B, C -> two-point recursion for B_theta^(p)
+  -> Adams-Bashforth-2 push.
+
+Every floating-point quantity is IEEE binary64 except the sums that cancel
+(the Gauss/log sums of the psi family, eqs. dpsi_dr and psi, and the ion
+node fields), which are accumulated in 80-bit extended precision and rounded
+to binary64 once.  The two-point recursion (eq. ai_bi with b_0=0, a_N=0) is
+solved as the linear system it defines, with LAPACK's banded LU (partial
+pivoting); the paper's shooting procedure is kept as ``solve_shooting``.
+
+Readings taken where the paper is silent, garbled or self-inconsistent
+(numbered as in the design notes, R1..R13):
+  R1  electrons carry q=-1, m=1; psibar = 1 + psi = gamma - u_z.
+  R2  d_zeta psi = +sum_{rho_k>rho} q w u/(rho psibar)   (the printed sum is
+      its negative; derived by differentiating eq. psi with eq. motion_2).
+  R3  ponderomotive term: du_r/dzeta gets +q^2 d_rho|a|^2/(4 m^2 psibar)
+      and B_i gets -q^3 w d_rho|a|^2/(4 m^2 rho psibar^2)  (printed sign of
+      eq. motion_1 and the missing 1/4 in eq. b_coeffs_2 overruled).
+  R4  the extra w/rho prefactor in the source decomposition is dropped.
+  R5  modified weight w^_j = w_j/2 - n_j dr_j^2/8, a fixed per-ring constant.
+  R6  at ring i: d_rho psi uses S_<i + w^_i;  d_zeta psi gives ring i the
+      weight w_i - w^_i;  B^(p)_i = B^- + (w^_i/w_i) C_i.
+  R7  ties in rho are ordered by ring id.
+  R8  AB2 starts with an Euler step on slice 0 (f_prev := f).
+  R9  a ring whose radius becomes negative is reflected: rho, u_r and the
+      stored AB2 history change sign.
+  R10 psibar <= 0 or any non-finite result stops the solve (breakdown).
+  R11 immobile ions: one ion ring per electron ring at its initial radius
+      with the same weight; node fields use w^; they are gathered to the
+      electron radii by linear interpolation (Sec. "Key algorithmic
+      adjustments"), with virtual nodes at rho=0 (d_rho psi = 0) and at the
+      plasma edge R_p, and the exact exterior field beyond R_p.
+  R12 beam particles are deposited in xi with linear (cloud-in-cell)
+      weights onto the slice nodes xi_n = n dxi; radially each particle is a
+      thin ring, counted below rho when r_k < rho (strict).
+  R13 laser: |a|^2 = a0^2 exp(-2 rho^2/w0^2) exp(-2 (xi-xi_L)^2/L^2).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.linalg import solve_banded
+
+LD = np.longdouble
+Q_E = -1.0   # electron charge (R1)
+M_E = 1.0    # electron mass
+Q_ION = 1.0  # singly charged ions (R11)
+
+BREAKDOWN = -5
+
+
+# ---------------------------------------------------------------------------
+# set-up (Sec. "Discretization of plasma species into macroparticles")
+# ---------------------------------------------------------------------------
+def ring_weights(r0, dr, dens=None):
+    """Ring weight w_j = n_j0 rho_j0 dr_j (eq. macroparticle_weight) and the
+    modified weight w^_j = w_j/2 - n_j0 dr_j^2/8 (Key algorithmic adjustments,
+    reading R5)."""
+    n = np.ones_like(r0) if dens is None else np.asarray(dens, np.float64)
+    w = n * r0 * dr
+    wh = w / 2.0 - n * dr * dr / 8.0
+    return w, wh
+
+
+def _gauss_log_sums(rho_l, w_l, wh_l, q):
+    """Fields of one species at its own sorted ring radii, extended precision.
+
+    eq. dpsi_dr : d_rho psi(rho) = -(1/rho) sum_{rho_k<rho} q w_k
+    eq. psi     : psi(rho) = -sum_k q w_k ln max(rho, rho_k)
+    At the ring itself the ring contributes w^ to the Gauss sum (R6); psi is
+    continuous there.  Returns (psi, d_rho psi, psi on the axis).
+    """
+    csum = np.cumsum(w_l)
+    below = np.concatenate([np.zeros(1, LD), csum[:-1]])        # sum_{k<i} w_k
+    lnr = np.log(rho_l)
+    wl = w_l * lnr
+    rsum = np.cumsum(wl[::-1])[::-1]                              # sum_{k>=i}
+    above = np.concatenate([rsum[1:], np.zeros(1, LD)])          # sum_{k>i}
+    dpsi = -q * (below + wh_l) / rho_l
+    psi = -q * ((below + w_l) * lnr + above)
+    psi_axis = -q * rsum[0]
+    return psi, dpsi, psi_axis
+
+
+class IonNodes:
+    """Immobile ion rings at the initial radii (reading R11)."""
+
+    def __init__(self, r0, w, wh):
+        r0_l, w_l, wh_l = r0.astype(LD), w.astype(LD), wh.astype(LD)
+        psi, dpsi, psi_axis = _gauss_log_sums(r0_l, w_l, wh_l, Q_ION)
+        self.Q = np.cumsum(w_l)[-1]
+        self.Rp = None
+        self.r = None
+        self._psi = psi
+        self._dpsi = dpsi
+        self._psi_axis = psi_axis
+        self._r0 = r0
+
+    def finish(self, Rp):
+        self.Rp = LD(Rp)
+        self.r = np.concatenate([[LD(0)], self._r0.astype(LD), [self.Rp]])
+        self.psi = np.concatenate([[self._psi_axis], self._psi,
+                                   [-Q_ION * self.Q * np.log(self.Rp)]])
+        self.dpsi = np.concatenate([[LD(0)], self._dpsi,
+                                    [-Q_ION * self.Q / self.Rp]])
+        return self
+
+    def at(self, rho):
+        """Ion psi and d_rho psi at radii rho: linear interpolation between the
+        bracketing nodes, j = last node with r_j < rho (Key algorithmic
+        adjustments); exact exterior field beyond the plasma edge."""
+        rho_l = np.asarray(rho).astype(LD)
+        j = np.searchsorted(self.r, rho_l, side="left") - 1
+        outside = j >= len(self.r) - 1
+        jj = np.clip(j, 0, len(self.r) - 2)
+        r_lo, r_hi = self.r[jj], self.r[jj + 1]
+        t = (rho_l - r_lo) / (r_hi - r_lo)
+        psi = (1 - t) * self.psi[jj] + t * self.psi[jj + 1]
+        dpsi = (1 - t) * self.dpsi[jj] + t * self.dpsi[jj + 1]
+        if np.any(outside):
+            ro = rho_l[outside]
+            psi[outside] = -Q_ION * self.Q * np.log(ro)
+            dpsi[outside] = -Q_ION * self.Q / ro
+        return psi, dpsi
+
+
+# ---------------------------------------------------------------------------
+# sources (Sec. "Numerical integration of wakefields": B_theta^(b) from the
+# beam charge; Fig. 2 "gather sources")
+# ---------------------------------------------------------------------------
+class BeamTable:
+    """Per-slice radial charge table of all particle beams (reading R12).
+
+    Lambda_n(rho) = (1/(2 pi dxi)) sum_{k: r_k<rho} q_k w_k c_{k,n}
+    with c_{k,n} the linear weight of particle k on node n; then
+    B^(b)(rho) = Lambda_n(rho) / rho  (Gauss law of the beam equation).
+    """
+
+    def __init__(self, beams, dxi, n_xi):
+        self.n_xi = n_xi
+        nodes, rs, qs = [], [], []
+        for b in beams:
+            x, y = np.asarray(b.x, np.float64), np.asarray(b.y, np.float64)
+            r = np.sqrt(x * x + y * y)
+            t = np.asarray(b.xi, np.float64) / dxi
+            n0 = np.floor(t)
+            f = t - n0
+            qw = b.q * np.asarray(b.w, np.float64)
+            for node, c in ((n0, 1.0 - f), (n0 + 1.0, f)):
+                keep = (node >= 0) & (node <= n_xi - 1) & (c > 0)
+                nodes.append(node[keep].astype(np.int64))
+                rs.append(r[keep])
+                qs.append(qw[keep] * c[keep])
+        if nodes:
+            node = np.concatenate(nodes)
+            r = np.concatenate(rs)
+            qc = np.concatenate(qs)
+        else:
+            node = np.zeros(0, np.int64)
+            r = np.zeros(0)
+            qc = np.zeros(0)
+        order = np.lexsort((r, node))
+        self.node, self.r, self.qc = node[order], r[order], qc[order]
+        self.off = np.searchsorted(self.node, np.arange(n_xi + 1), side="left")
+        self.inv = LD(1) / (LD(2) * LD(math.pi) * LD(dxi))
+
+    def lam(self, n, rho):
+        lo, hi = self.off[n], self.off[n + 1]
+        if hi == lo:
+            return np.zeros_like(rho)
+        cum = np.cumsum(self.qc[lo:hi].astype(LD)) * self.inv
+        cnt = np.searchsorted(self.r[lo:hi], rho, side="left")
+        out = np.zeros(rho.shape, LD)
+        nz = cnt > 0
+        out[nz] = cum[cnt[nz] - 1]
+        return out.astype(np.float64)
+
+
+def analytic_lambda(src, xi, rho):
+    """Charge within rho of a bi-Gaussian beam per unit xi and radian."""
+    s2 = src.sigma_r ** 2
+    lon = math.exp(-((xi - src.xi_c) ** 2) / (2.0 * src.sigma_xi ** 2))
+    return src.q * src.n_peak * lon * s2 * (-np.expm1(-rho * rho / (2.0 * s2)))
+
+
+def laser_terms(src, xi, rho):
+    """|a|^2 and d_rho |a|^2 of a frozen Gaussian envelope (reading R13)."""
+    lon = math.exp(-2.0 * (xi - src.xi_l) ** 2 / (src.L ** 2))
+    a2 = src.a0 ** 2 * np.exp(-2.0 * rho * rho / (src.w0 ** 2)) * lon
+    return a2, -(4.0 * rho / (src.w0 ** 2)) * a2
+
+
+# ---------------------------------------------------------------------------
+# the per-slice steps
+# ---------------------------------------------------------------------------
+def psi_family(rho, w, wh, ions):
+    """psi and d_rho psi at sorted electron rings plus the ion species
+    (eqs. dpsi_dr, psi; species summed after interpolation, R11).
+    Returns binary64 (psi, dpsi, psi_axis)."""
+    rho_l = rho.astype(LD)
+    psi_e, dpsi_e, axis_e = _gauss_log_sums(rho_l, w.astype(LD), wh.astype(LD), Q_E)
+    psi_i, dpsi_i = ions.at(rho_l)
+    psi = (psi_e + psi_i).astype(np.float64)
+    dpsi = (dpsi_e + dpsi_i).astype(np.float64)
+    axis = float(axis_e + ions.psi[0])
+    return psi, dpsi, axis
+
+
+def local_quantities(psi, u, a2):
+    """psibar = 1 - (q/m) psi and gamma from eq. plasma_particle_motion_4."""
+    psibar = 1.0 - (Q_E / M_E) * psi
+    gamma = (1.0 + u * u + psibar * psibar
+             + (Q_E * Q_E) / (2.0 * M_E * M_E) * a2) / (2.0 * psibar)
+    return psibar, gamma
+
+
+def dzeta_psi(rho, u, w, wh, psibar):
+    """d_zeta psi at sorted rings (eq. dpsi_dzeta with reading R2, R6):
+    sum over the rings outside of q w u/(rho psibar), ring itself with
+    weight w - w^.  Returns (dzpsi at rings, dzpsi on the axis)."""
+    c = (Q_E * u / (rho * psibar)).astype(LD)
+    term = w.astype(LD) * c
+    rsum = np.cumsum(term[::-1])[::-1]
+    above = np.concatenate([rsum[1:], np.zeros(1, LD)])
+    own = (w - wh).astype(LD) * c
+    return (above + own).astype(np.float64), float(rsum[0]) if len(rsum) else 0.0
+
+
+def coefficients(rho, u, w, psibar, gamma, dpsi, dzpsi, bb, da2, q=Q_E, m=M_E):
+    """A_i, B_i, C_i of eqs. b_coeffs_1-3 (readings R3, R4)."""
+    wr = w / rho
+    A = wr * (q * q / m) / psibar
+    B = (-wr * (q * q / m) * gamma * dpsi / psibar ** 2
+         + wr * (q * q / m) * bb / psibar
+         - wr * (q ** 3 / (4.0 * m * m)) * da2 / psibar ** 2
+         - q * w / rho ** 2 * u * u / psibar ** 2
+         + wr * (q * q / m) * u * u * dpsi / psibar ** 3
+         - wr * (q * q / m) * u * dzpsi / psibar ** 2)
+    C = q * wr * (gamma / psibar - 1.0) - q * wr * u * u / psibar ** 2
+    return A, B, C
+
+
+def transfer(A, B, C, rho):
+    """Matrix M_i and offset s_i of eq. ai_bi: x_i = M_i x_{i-1} + s_i."""
+    M = np.empty((len(rho), 2, 2))
+    M[:, 0, 0] = 1.0 + A * rho / 2.0
+    M[:, 0, 1] = A / (2.0 * rho)
+    M[:, 1, 0] = -A * rho ** 3 / 2.0
+    M[:, 1, 1] = 1.0 - A * rho / 2.0
+    s = np.empty((len(rho), 2))
+    s[:, 0] = (2.0 * B + A * C) / 4.0
+    s[:, 1] = rho * (4.0 * C - 2.0 * B * rho - A * C * rho) / 4.0
+    return M, s
+
+
+def solve_recursion(M, s):
+    """Solve x_i = M_i x_{i-1} + s_i (i=1..N) with b_0 = 0 and a_N = 0
+    (eq. ai_bi) as one banded linear system in (a_0, b_0, ..., a_N, b_N).
+    Returns arrays a, b of length N+1."""
+    n = M.shape[0]
+    nu = 2 * n + 2
+    # banded storage with 2 lower and 1 upper diagonals: entry (row r,
+    # column c) sits at ab[1 + r - c, c]
+    ab = np.zeros((4, nu))
+    rhs = np.zeros(nu)
+    i = np.arange(1, n + 1)
+    ra, rb = 2 * i - 1, 2 * i          # rows of the a_i and b_i equations
+    ca, cb = 2 * i - 2, 2 * i - 1      # columns of a_{i-1}, b_{i-1}
+    ab[1 + 0 - 1, 1] = 1.0                                   # b_0 = 0
+    ab[1 + ra - ca, ca] = -M[:, 0, 0]
+    ab[1 + ra - cb, cb] = -M[:, 0, 1]
+    ab[1 + ra - 2 * i, 2 * i] = 1.0
+    ab[1 + rb - ca, ca] = -M[:, 1, 0]
+    ab[1 + rb - cb, cb] = -M[:, 1, 1]
+    ab[1 + rb - (2 * i + 1), 2 * i + 1] = 1.0
+    rhs[ra] = s[:, 0]
+    rhs[rb] = s[:, 1]
+    ab[1 + (nu - 1) - 2 * n, 2 * n] = 1.0                    # a_N = 0
+    z = solve_banded((2, 1), ab, rhs)
+    return z[0::2].copy(), z[1::2].copy()
+
+
+def solve_shooting(M, s):
+    """The paper's appendix procedure: a_i = K_i a_0 + T_i, b_i = U_i a_0 + P_i
+    with (K,U) from (1,0) and (T,P) from (0,0), then a_0 = -T_N/K_N."""
+    n = M.shape[0]
+    KU = np.zeros((n + 1, 2)); KU[0] = (1.0, 0.0)
+    TP = np.zeros((n + 1, 2))
+    for i in range(1, n + 1):
+        KU[i] = M[i - 1] @ KU[i - 1]
+        TP[i] = M[i - 1] @ TP[i - 1] + s[i - 1]
+    a0 = -TP[n, 0] / KU[n, 0]
+    return KU[:, 0] * a0 + TP[:, 0], KU[:, 1] * a0 + TP[:, 1]
+
+
+def b_plasma_at_rings(a, b, rho, C, w, wh):
+    """B^(p) at ring i: the inner-side value a_{i-1} rho_i + b_{i-1}/rho_i
+    (eq. b_theta_plasma) plus the fraction w^/w of its jump C_i (R6)."""
+    return a[:-1] * rho + b[:-1] / rho + (wh / w) * C
+
+
+def forces(u, psibar, gamma, dpsi, bt, da2, q=Q_E, m=M_E):
+    """Right-hand sides in xi = -zeta of eqs. plasma_particle_motion_1-2
+    (reading R3 for the ponderomotive term)."""
+    f_rho = u / psibar
+    f_u = -((q / m) * (gamma * dpsi / psibar - bt)
+            + (q * q) / (4.0 * m * m) * da2 / psibar)
+    return f_rho, f_u
+
+
+# ---------------------------------------------------------------------------
+# driver (Fig. 2 right column)
+# ---------------------------------------------------------------------------
+class RingOracle:
+    """One instance: ring set, slice grid and frozen sources."""
+
+    def __init__(self, r0, dr, dxi, n_xi, sources=(), dens=None):
+        self.r0 = np.asarray(r0, np.float64)
+        self.dr = np.asarray(dr, np.float64)
+        self.N = len(self.r0)
+        self.dxi = float(dxi)
+        self.n_xi = int(n_xi)
+        self.w, self.wh = ring_weights(self.r0, self.dr, dens)
+        self.Rp = float(self.r0[-1] + self.dr[-1] / 2.0)
+        self.ions = IonNodes(self.r0, self.w, self.wh).finish(self.Rp)
+        beams = [s for s in sources if getattr(s, "kind", "") == "particles"]
+        self.analytic = [s for s in sources if getattr(s, "kind", "") == "gaussian"]
+        self.lasers = [s for s in sources if getattr(s, "kind", "") == "laser"]
+        self.table = BeamTable(beams, self.dxi, self.n_xi)
+
+    def initial_state(self):
+        z = np.zeros(self.N)
+        return dict(rho=self.r0.copy(), u=z.copy(), fr=z.copy(), fu=z.copy())
+
+    def sources_at(self, n, rho):
+        xi = n * self.dxi
+        lam = self.table.lam(n, rho)
+        for s in self.analytic:
+            lam = lam + analytic_lambda(s, xi, rho)
+        bb = lam / rho
+        a2 = np.zeros_like(rho)
+        da2 = np.zeros_like(rho)
+        for s in self.lasers:
+            x, dx = laser_terms(s, xi, rho)
+            a2 = a2 + x
+            da2 = da2 + dx
+        return bb, a2, da2
+
+    def slice(self, n, state, push=True, keep=False):
+        """Fields at slice n and the state pushed to slice n+1.
+        ``state`` arrays are indexed by ring id.  Returns (out, new_state)
+        with out['status'] = 0 or BREAKDOWN."""
+        ids = np.lexsort((np.arange(self.N), state["rho"]))          # R7
+        rho = state["rho"][ids]
+        u = state["u"][ids]
+        w, wh = self.w[ids], self.wh[ids]
+        bb, a2, da2 = self.sources_at(n, rho)
+        psi, dpsi, psi_axis = psi_family(rho, w, wh, self.ions)
+        psibar, gamma = local_quantities(psi, u, a2)
+        out = dict(status=0)
+        if not np.all(psibar > 0) or not np.all(np.isfinite(psibar)):  # R10
+            out["status"] = BREAKDOWN
+            return out, None
+        dzpsi, dz_axis = dzeta_psi(rho, u, w, wh, psibar)
+        A, B, C = coefficients(rho, u, w, psibar, gamma, dpsi, dzpsi, bb, da2)
+        M, s = transfer(A, B, C, rho)
+        a, b = solve_recursion(M, s)
+        bp = b_plasma_at_rings(a, b, rho, C, w, wh)
+        bt = bb + bp
+        new = None
+        fr = fu = None
+        if push:
+            fr, fu = forces(u, psibar, gamma, dpsi, bt, da2)
+            if n == 0:                                                # R8
+                fr_p, fu_p = fr, fu
+            else:
+                fr_p, fu_p = state["fr"][ids], state["fu"][ids]
+            rho_n = rho + self.dxi * (1.5 * fr - 0.5 * fr_p)
+            u_n = u + self.dxi * (1.5 * fu - 0.5 * fu_p)
+            frs, fus = fr.copy(), fu.copy()
+            neg = rho_n < 0                                           # R9
+            rho_n[neg] = -rho_n[neg]
+            u_n[neg] = -u_n[neg]
+            frs[neg] = -frs[neg]
+            fus[neg] = -fus[neg]
+            new = {k: np.empty(self.N) for k in ("rho", "u", "fr", "fu")}
+            new["rho"][ids], new["u"][ids] = rho_n, u_n
+            new["fr"][ids], new["fu"][ids] = frs, fus
+        check = [psi, dpsi, dzpsi, bt]
+        if new is not None:
+            check += [new["rho"], new["u"]]
+        if not all(np.all(np.isfinite(c)) for c in check):             # R10
+            out["status"] = BREAKDOWN
+            return out, None
+
+        def by_id(x):
+            y = np.empty(self.N)
+            y[ids] = x
+            return y
+
+        out.update(psi=by_id(psi), er_bt=by_id(-dpsi), ez=by_id(-dzpsi),
+                   bt=by_id(bt), rho=by_id(rho), u=by_id(u),
+                   psi_axis=psi_axis, ez_axis=-dz_axis)
+        if keep:
+            out.update(order=ids, A=A, B=B, C=C, M=M, s=s, a=a, b=b,
+                       bb=bb, a2=a2, da2=da2, psibar=psibar, gamma=gamma,
+                       dpsi_sorted=dpsi, dzpsi_sorted=dzpsi, bp=bp)
+        return out, new
+
+    def run(self, first=0, count=None, state=None, record_stride=1):
+        """March slices [first, first+count).  Returns a dict with per-slice
+        on-axis lineouts, snapshots every ``record_stride`` slices (by ring
+        id), the final state and the breakdown slice (-1 if none)."""
+        if count is None:
+            count = self.n_xi - first
+        if state is None:
+            state = self.initial_state()
+        rec = {}
+        axis = np.full((count, 2), np.nan)
+        breakdown = -1
+        for k in range(count):
+            n = first + k
+            out, new = self.slice(n, state, push=(n < self.n_xi - 1))
+            if out["status"] != 0:
+                breakdown = n
+                break
+            axis[k] = (out["psi_axis"], out["ez_axis"])
+            if record_stride and (n % record_stride == 0 or k == count - 1):
+                rec[n] = {q: out[q] for q in ("psi", "er_bt", "ez", "bt", "rho", "u")}
+            if new is not None:
+                state = new
+        return dict(axis=axis, snap=rec, state=state, breakdown=breakdown)

@@ -1,0 +1,515 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test checks one part of the oracle against an independent source:
+brute-force pairwise sums in 40-digit arithmetic, the jump conditions of the
+B_theta equation solved densely, the paper's shooting procedure, closed-form
+linear wakes derived from the quasistatic Maxwell equations, convergence
+order, and finite-difference consistency with the Maxwell equations.  The
+mutation tests at the end plant mistakes in the oracle (on the CPU) and
+check that a pin fails.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import wake_oracle as O
+from paper_2603_16623_amd import workloads as W
+
+mpmath.mp.dps = 40
+
+
+def _random_state(rng, n, spread=0.3):
+    r0, dr = W.geometric_rings(n, 0.01, 2.0)
+    rho = r0 * np.exp(rng.normal(0.0, spread, n))     # unsorted, crossed
+    u = rng.normal(0.0, 0.2, n)
+    return r0, dr, rho, u
+
+
+# ---------------------------------------------------------------------------
+# weights (eq. macroparticle_weight, modified weight)
+# ---------------------------------------------------------------------------
+def test_weights_integrate_density():
+    r0, dr = W.uniform_rings(200, 5.0)
+    w, wh = O.ring_weights(r0, dr)
+    # uniform density: total charge per radian is R^2/2
+    assert math.isclose(math.fsum(w), 12.5, rel_tol=1e-14)
+    # modified weight = charge between the inner edge and the ring centre
+    for j in (0, 7, 199):
+        exact = 0.5 * (r0[j] ** 2 - (r0[j] - dr[j] / 2) ** 2)
+        assert math.isclose(wh[j], exact, rel_tol=1e-13)
+    dens = 1.0 + r0 ** 2
+    w2, wh2 = O.ring_weights(r0, dr, dens)
+    j = 50
+    lo = r0[j] - dr[j] / 2
+    assert math.isclose(wh2[j], dens[j] * 0.5 * (r0[j] ** 2 - lo ** 2), rel_tol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# psi family against pairwise brute force (eqs. dpsi_dr, psi)
+# ---------------------------------------------------------------------------
+def _bf_fields(rho, w, wh, r0):
+    """Direct pairwise sums for electrons at rho and ions at r0 (40 digits)."""
+    n = len(rho)
+    mp = mpmath.mpf
+    Q = mpmath.fsum(mp(x) for x in w)
+    Rp = None
+    # ion node fields (q = +1) at the ion radii, self with w^
+    nodes_r = [mp(0)] + [mp(x) for x in r0]
+    ion_psi = [-mpmath.fsum(mp(w[j]) * mpmath.log(mp(r0[j])) for j in range(n))]
+    ion_dpsi = [mp(0)]
+    for k in range(n):
+        ion_psi.append(-mpmath.fsum(mp(w[j]) * mpmath.log(max(mp(r0[k]), mp(r0[j])))
+                                    for j in range(n)))
+        below = mpmath.fsum(mp(w[j]) for j in range(n) if r0[j] < r0[k])
+        ion_dpsi.append(-(below + mp(wh[k])) / mp(r0[k]))
+    return nodes_r, ion_psi, ion_dpsi, Q
+
+
+def test_psi_family_matches_pairwise_sums():
+    rng = np.random.default_rng(11)
+    n = 40
+    r0, dr, rho, u = _random_state(rng, n)
+    w, wh = O.ring_weights(r0, dr)
+    Rp = r0[-1] + dr[-1] / 2
+    nodes_r, ion_psi, ion_dpsi, Q = _bf_fields(rho, w, wh, r0)
+    nodes_r.append(mpmath.mpf(Rp))
+    ion_psi.append(-Q * mpmath.log(mpmath.mpf(Rp)))
+    ion_dpsi.append(-Q / mpmath.mpf(Rp))
+    ids = np.lexsort((np.arange(n), rho))
+    psi, dpsi, axis = O.psi_family(rho[ids], w[ids], wh[ids],
+                                   O.IonNodes(r0, w, wh).finish(Rp))
+    mp = mpmath.mpf
+    scale = 0.0
+    errs = []
+    for pos, i in enumerate(ids):
+        ri = mp(rho[i])
+        e_psi = mpmath.fsum(mp(w[j]) * mpmath.log(max(ri, mp(rho[j]))) for j in range(n))
+        e_dpsi = (mpmath.fsum(mp(w[j]) for j in range(n) if rho[j] < rho[i]) + mp(wh[i])) / ri
+        if ri > nodes_r[-1]:
+            i_psi, i_dpsi = -Q * mpmath.log(ri), -Q / ri
+        else:
+            j = max(k for k in range(len(nodes_r)) if nodes_r[k] < ri)
+            t = (ri - nodes_r[j]) / (nodes_r[j + 1] - nodes_r[j])
+            i_psi = (1 - t) * ion_psi[j] + t * ion_psi[j + 1]
+            i_dpsi = (1 - t) * ion_dpsi[j] + t * ion_dpsi[j + 1]
+        bp, bd = float(e_psi + i_psi), float(e_dpsi + i_dpsi)
+        scale = max(scale, abs(bp), abs(bd))
+        errs.append(max(abs(psi[pos] - bp), abs(dpsi[pos] - bd)))
+    assert max(errs) <= 1e-15 * max(scale, 1.0)
+    bf_axis = float(mpmath.fsum(mp(w[j]) * (mpmath.log(mp(rho[j])) - mpmath.log(mp(r0[j])))
+                                for j in range(n)))
+    assert abs(axis - bf_axis) <= 1e-15
+
+
+def test_dzeta_psi_matches_pairwise_sum():
+    rng = np.random.default_rng(12)
+    n = 33
+    r0, dr, rho, u = _random_state(rng, n)
+    w, wh = O.ring_weights(r0, dr)
+    psibar = 1.0 + rng.uniform(-0.3, 0.5, n)
+    ids = np.lexsort((np.arange(n), rho))
+    dz, dz_axis = O.dzeta_psi(rho[ids], u[ids], w[ids], wh[ids], psibar[ids])
+    # d_zeta psi(rho) = - d/dxi sum_k w_k ln max(rho, rho_k) with
+    # d rho_k / d xi = u_k / psibar_k: only rings outside rho contribute.
+    for pos, i in enumerate(ids):
+        outer = [w[k] * u[k] / (rho[k] * psibar[k]) for k in range(n) if rho[k] > rho[i]]
+        own = (w[i] - wh[i]) * u[i] / (rho[i] * psibar[i])
+        assert math.isclose(dz[pos], -(math.fsum(outer) + own), rel_tol=1e-13, abs_tol=1e-16)
+    assert math.isclose(dz_axis, -math.fsum(w * u / (rho * psibar)), rel_tol=1e-13)
+
+
+def test_unperturbed_plasma_has_zero_fields():
+    """No sources: the electron and ion sums cancel exactly and rings stay."""
+    for r0, dr in (W.uniform_rings(300, 5.0), W.geometric_rings(300, 1e-3, 6.0)):
+        o = O.RingOracle(r0, dr, 0.01, 25, [])
+        res = o.run(record_stride=1)
+        assert res["breakdown"] == -1
+        for n, snap in res["snap"].items():
+            for q in ("psi", "er_bt", "ez", "bt"):
+                assert np.max(np.abs(snap[q])) <= 1e-15, (n, q)
+        assert np.array_equal(res["state"]["rho"], r0)
+        assert np.max(np.abs(res["state"]["u"])) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# the two-point recursion (eq. ai_bi) and the appendix shooting
+# ---------------------------------------------------------------------------
+def _random_coeffs(rng, n, r_max):
+    r0, dr = W.uniform_rings(n, r_max)
+    rho = r0 * np.exp(rng.normal(0, 0.02, n))
+    rho.sort()
+    w, _ = O.ring_weights(r0, dr)
+    psibar = rng.uniform(0.4, 1.6, n)
+    A = w / (rho * psibar)
+    B = rng.normal(0.0, 1e-2, n)
+    C = rng.normal(0.0, 1e-2, n)
+    return rho, A, B, C
+
+
+def test_recursion_solution_satisfies_jump_conditions():
+    """Between rings B = a rho + b/rho; across ring i, B jumps by C_i and
+    2(a_i - a_{i-1}) = A_i <B>_i + B_i (integrating the B_theta equation
+    over the delta sheet), with b_0 = 0 and a_N = 0."""
+    rng = np.random.default_rng(3)
+    rho, A, B, C = _random_coeffs(rng, 200, 5.0)
+    M, s = O.transfer(A, B, C, rho)
+    a, b = O.solve_recursion(M, s)
+    assert abs(a[-1]) < 1e-15 * np.abs(a).max()
+    assert abs(b[0]) < 1e-15 * np.abs(b).max()
+    Bm = a[:-1] * rho + b[:-1] / rho
+    Bp = a[1:] * rho + b[1:] / rho
+    scale = np.abs(C).max()
+    assert np.max(np.abs((Bp - Bm) - C)) < 1e-12 * scale
+    lhs = 2.0 * (a[1:] - a[:-1])
+    rhs = A * 0.5 * (Bp + Bm) + B
+    assert np.max(np.abs(lhs - rhs)) < 1e-11 * np.abs(rhs).max()
+
+
+def test_recursion_matches_dense_lu_and_mpmath():
+    rng = np.random.default_rng(4)
+    rho, A, B, C = _random_coeffs(rng, 30, 3.0)
+    M, s = O.transfer(A, B, C, rho)
+    a, b = O.solve_recursion(M, s)
+    n = len(rho)
+    # dense system in the unknowns (a_0, b_0, ..., a_N, b_N)
+    mat = np.zeros((2 * n + 2, 2 * n + 2)); rhs = np.zeros(2 * n + 2)
+    mat[0, 1] = 1.0
+    for i in range(1, n + 1):
+        mat[2 * i - 1, 2 * i - 2:2 * i] = -M[i - 1, 0]; mat[2 * i - 1, 2 * i] = 1.0
+        mat[2 * i, 2 * i - 2:2 * i] = -M[i - 1, 1]; mat[2 * i, 2 * i + 1] = 1.0
+        rhs[2 * i - 1:2 * i + 1] = s[i - 1]
+    mat[-1, 2 * n] = 1.0
+    z = np.linalg.solve(mat, rhs)
+    assert np.allclose(a, z[0::2], rtol=0, atol=1e-14 * np.abs(z).max())
+    assert np.allclose(b, z[1::2], rtol=0, atol=1e-14 * np.abs(z).max())
+    zm = mpmath.lu_solve(mpmath.matrix(mat.tolist()), mpmath.matrix(rhs.tolist()))
+    zm = np.array([float(x) for x in zm])
+    assert np.max(np.abs(z - zm)) < 1e-14 * np.abs(zm).max()
+
+
+def test_recursion_matches_paper_shooting_within_its_conditioning():
+    """The appendix shooting solves the same system; it loses digits as the
+    growing mode K_N ~ I_1(R_p) (here R_p = 5) amplifies rounding."""
+    rng = np.random.default_rng(5)
+    rho, A, B, C = _random_coeffs(rng, 500, 5.0)
+    M, s = O.transfer(A, B, C, rho)
+    a, b = O.solve_recursion(M, s)
+    a2, b2 = O.solve_shooting(M, s)
+    growth = special.i1(5.0) * special.i0(5.0)
+    assert np.max(np.abs(a - a2)) < 1e-14 * growth * np.abs(a).max()
+    assert np.max(np.abs(b - b2)) < 1e-14 * growth * np.abs(b).max()
+
+
+# ---------------------------------------------------------------------------
+# beam table (Gauss law of the beam charge, linear weights in xi)
+# ---------------------------------------------------------------------------
+def test_beam_table_matches_direct_sum_and_conserves_charge():
+    rng = np.random.default_rng(6)
+    dxi, n_xi = 0.05, 120
+    p = W.gaussian_particles(rng, 2000, 1.0, 0.2, 0.6, 3.0)
+    tab = O.BeamTable([p], dxi, n_xi)
+    r = np.sqrt(p.x ** 2 + p.y ** 2)
+    rho = np.sort(rng.uniform(0.0, 0.8, 50))
+    for n in (10, 59, 60, 61, 100):
+        lam = tab.lam(n, rho)
+        for k, rr in enumerate(rho):
+            tot = 0.0
+            terms = []
+            for j in range(len(r)):
+                c = max(0.0, 1.0 - abs(p.xi[j] / dxi - n))
+                if c > 0 and r[j] < rr:
+                    terms.append(p.q * p.w[j] * c)
+            tot = math.fsum(terms) / (2 * math.pi * dxi)
+            assert math.isclose(lam[k], tot, rel_tol=1e-12, abs_tol=1e-15)
+    inside = (p.xi > dxi) & (p.xi < (n_xi - 2) * dxi)
+    big = np.array([1e9])
+    total = math.fsum(tab.lam(n, big)[0] for n in range(n_xi)) * 2 * math.pi * dxi
+    assert math.isclose(total, p.q * p.w[inside].sum(), rel_tol=1e-3)
+
+
+def test_gamma_is_on_the_mass_shell():
+    """eqs. motion_3/4: gamma - u_z = psibar and
+    gamma^2 = 1 + u_r^2 + u_z^2 + |a|^2/2 (averaged quiver)."""
+    rng = np.random.default_rng(7)
+    psi = rng.uniform(-0.5, 2.0, 100)
+    u = rng.normal(0, 1, 100)
+    a2 = rng.uniform(0, 3, 100)
+    psibar, gamma = O.local_quantities(psi, u, a2)
+    uz = gamma - psibar
+    assert np.allclose(psibar, 1.0 + psi)
+    assert np.allclose(gamma ** 2, 1 + u ** 2 + uz ** 2 + a2 / 2, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# closed-form linear wakes
+# ---------------------------------------------------------------------------
+def _radial_green(sigma_r, rho):
+    """R(rho), R'(rho) with (lap_perp - 1) R = -exp(-rho^2/2 sigma^2)."""
+    g = lambda r: r * math.exp(-r * r / (2 * sigma_r ** 2))
+    top = 12 * sigma_r
+    R = np.empty(len(rho)); dR = np.empty(len(rho))
+    for k, x in enumerate(rho):
+        lo = integrate.quad(lambda r: g(r) * special.i0(r), 0, min(x, top), limit=200)[0]
+        hi = integrate.quad(lambda r: g(r) * special.k0(r), x, max(x, top), limit=200)[0] if x < top else 0.0
+        if x == 0.0:          # K0 lo -> 0 at the axis
+            R[k], dR[k] = hi, 0.0
+            continue
+        R[k] = special.k0(x) * lo + special.i0(x) * hi
+        dR[k] = -special.k1(x) * lo + special.i1(x) * hi
+    return R, dR
+
+
+def _long_response(xi, prof):
+    """Z(xi) = int_0^xi sin(xi-x) prof(x) dx and Z'(xi)."""
+    Z = integrate.quad(lambda x: math.sin(xi - x) * prof(x), 0, xi, limit=400)[0]
+    dZ = integrate.quad(lambda x: math.cos(xi - x) * prof(x), 0, xi, limit=400)[0]
+    return Z, dZ
+
+
+@pytest.fixture(scope="module")
+def linear_beam_run():
+    nb = 1e-4
+    inst = W.config1(analytic=True, n_peak=nb)
+    o = O.RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources)
+    return inst, nb, o.run(record_stride=100)
+
+
+def test_linear_beam_wake_closed_form(linear_beam_run):
+    """Weak bi-Gaussian electron driver: psi = n_b R(rho) Z(xi),
+    E_z = n_b R Z', E_r - B_theta = -n_b R' Z, B_theta = n_b G(xi) R'."""
+    inst, nb, res = linear_beam_run
+    s = inst.sources[0]
+    prof = lambda x: math.exp(-(x - s.xi_c) ** 2 / (2 * s.sigma_xi ** 2))
+    R0, _ = _radial_green(s.sigma_r, np.array([0.0]))
+    # R(0) in closed form: (s^2/2) e^{s^2/2} E1(s^2/2)
+    h = s.sigma_r ** 2 / 2
+    assert math.isclose(R0[0], h * math.exp(h) * special.exp1(h), rel_tol=1e-8)
+    amp = 0.0; err = 0.0
+    for n in range(100, inst.n_xi, 50):
+        Z, dZ = _long_response(n * inst.dxi, prof)
+        ez = nb * R0[0] * dZ
+        amp = max(amp, abs(ez))
+        err = max(err, abs(res["axis"][n, 1] - ez))
+        err = max(err, abs(res["axis"][n, 0] - nb * R0[0] * Z))
+    assert amp > 2e-6
+    assert err < 3e-3 * amp
+    # sign: the head of an electron driver decelerates it (E_z > 0)
+    assert res["axis"][200, 1] > 0
+    rings = np.array([0, 5, 20, 40, 80])
+    R, dR = _radial_green(s.sigma_r, inst.r0[rings])
+    for n in (300, 700, 1100):
+        snap = res["snap"][n]
+        xi = n * inst.dxi
+        Z, dZ = _long_response(xi, prof)
+        G = prof(xi)
+        scale = nb * np.abs(dR).max()
+        assert np.max(np.abs(snap["psi"][rings] - nb * R * Z)) < 5e-3 * nb * R0[0]
+        assert np.max(np.abs(snap["er_bt"][rings] + nb * dR * Z)) < 1e-2 * scale
+        assert np.max(np.abs(snap["bt"][rings] - nb * G * dR)) < 1e-2 * scale + 1e-3 * nb
+
+
+def test_linear_laser_wake_closed_form():
+    """Weak Gaussian laser: (d_xi^2 + 1) psi = |a|^2/4 locally in rho and
+    B_theta vanishes at order a0^2."""
+    r0, dr = W.uniform_rings(400, 8.0)
+    a0 = 0.01
+    las = W.GaussianLaser(a0, 2.0, 1.0, 2.0)
+    o = O.RingOracle(r0, dr, 0.01, 800, [las])
+    res = o.run(record_stride=100)
+    assert res["breakdown"] == -1
+    # far-wake amplitude on axis: (a0^2/4) sqrt(pi/2) L exp(-L^2/8)
+    amp_th = a0 ** 2 / 4 * math.sqrt(math.pi / 2) * math.exp(-1 / 8)
+    rings = np.array([0, 30, 60, 100, 150])
+    for n in (300, 500, 700):
+        xi = n * 0.01
+        Z, _ = _long_response(xi, lambda x: math.exp(-2 * (x - 2.0) ** 2))
+        th = a0 ** 2 / 4 * np.exp(-2 * r0[rings] ** 2 / 4.0) * Z
+        snap = res["snap"][n]
+        assert np.max(np.abs(snap["psi"][rings] - th)) < 2e-2 * amp_th
+        assert np.max(np.abs(snap["bt"])) < 2e-2 * amp_th
+    assert abs(np.abs(res["axis"][400:, 0]).max() - amp_th) < 2e-2 * amp_th
+
+
+# ---------------------------------------------------------------------------
+# convergence and Maxwell consistency in the nonlinear regime
+# ---------------------------------------------------------------------------
+def _nonlinear(n_rings=60, dxi=0.01, xi_end=3.0, n_peak=1.5, laser=False):
+    r0, dr = W.geometric_rings(n_rings, 0.01, 3.0)
+    src = [W.GaussianBeam(-1.0, n_peak, 0.3, 0.4, 1.2)]
+    if laser:
+        src.append(W.GaussianLaser(1.2, 1.0, 0.5, 0.8))
+    n_xi = int(round(xi_end / dxi)) + 1
+    return O.RingOracle(r0, dr, dxi, n_xi, src)
+
+
+def test_ab2_is_second_order():
+    finals = []
+    for dxi in (0.02, 0.01, 0.005):
+        o = _nonlinear(dxi=dxi)
+        res = o.run(record_stride=0)
+        assert res["breakdown"] == -1
+        finals.append(res["state"]["rho"])
+    ratio = np.linalg.norm(finals[0] - finals[1]) / np.linalg.norm(finals[1] - finals[2])
+    assert 3.3 < ratio < 4.8, ratio
+
+
+def _records(o):
+    res = o.run(record_stride=1)
+    assert res["breakdown"] == -1
+    return res
+
+
+@pytest.mark.parametrize("laser", [False, True])
+def test_axis_ez_is_xi_derivative_of_psi(laser):
+    """E_z = -d_zeta psi = d_xi psi (eq. lorentz_gauge_1) on the axis,
+    checked against a centred difference of the computed psi(0)."""
+    o = _nonlinear(dxi=0.002, xi_end=2.5, laser=laser)
+    res = o.run(record_stride=0)
+    psi0, ez0 = res["axis"][:, 0], res["axis"][:, 1]
+    fd = (psi0[2:] - psi0[:-2]) / (2 * o.dxi)
+    scale = np.abs(ez0).max()
+    assert scale > 0.05
+    assert np.max(np.abs(fd - ez0[1:-1])) < 2e-4 * scale
+
+
+@pytest.mark.parametrize("laser", [False, True])
+def test_bp_slope_is_xi_derivative_of_outer_current(laser):
+    """Integrating the B_theta equation from between rings i, i+1 to
+    infinity: 2 a_i = d_xi sum_{k>i} w_k u_k/(rho_k psibar_k)
+    (eqs. phi_b_eq_3, fluid_from_mp_3, a_N = 0)."""
+    o = _nonlinear(dxi=0.002, xi_end=2.0, laser=laser, n_rings=50)
+    state = o.initial_state()
+    outs = []
+    for n in range(o.n_xi - 1):
+        out, state = o.slice(n, state, keep=True)
+        outs.append(out)
+    checked = 0
+    worst = 0.0
+    scale = 0.0
+    for n in range(200, o.n_xi - 2, 97):
+        prv, cur, nxt = outs[n - 1], outs[n], outs[n + 1]
+
+        def outer(out, i):
+            ids = out["order"]
+            rho = out["rho"][ids]; u = out["u"][ids]
+            v = o.w[ids] * u / (rho * out["psibar"])
+            return set(ids[i:].tolist()), math.fsum(v[i:])
+
+        for i in range(1, o.N):
+            s0, v0 = outer(prv, i); s1, _ = outer(cur, i); s2, v2 = outer(nxt, i)
+            if not (s0 == s1 == s2):
+                continue
+            fd = (v2 - v0) / (2 * o.dxi)
+            worst = max(worst, abs(2 * cur["a"][i] - fd))
+            scale = max(scale, abs(fd))
+            checked += 1
+    assert checked > 200
+    assert scale > 1e-2
+    assert worst < 1e-3 * scale, (worst, scale)
+
+
+def _ampere_error(o, slices):
+    """Integrating the Ampere equation (maxwell_qsa_4) for B^(p) from the
+    axis to a radius rho between two rings:
+        rho B^(p)(rho) = sum_{rho_k<rho} q w_k u_z,k/psibar_k
+                         + d/dxi sum_k v_k min(rho, rho_k)^2 / 2,
+    with E_z(rho) = sum_{rho_k>rho} v_k, v_k = w_k u_k/(rho_k psibar_k)
+    (eqs. fluid_from_mp_4, dpsi_dzeta).  Returns the worst relative misfit
+    of the solved a_i rho + b_i/rho over the given slices."""
+    state = o.initial_state()
+    outs = []
+    for n in range(max(slices) + 2):
+        out, state = o.slice(n, state, keep=True)
+        outs.append(out)
+    worst = scale = 0.0
+    checked = 0
+    for n in slices:
+        prv, cur, nxt = outs[n - 1], outs[n], outs[n + 1]
+        ids = cur["order"]
+        rho = cur["rho"][ids]
+        g = np.empty(o.N); g[ids] = cur["gamma"]
+        pb = np.empty(o.N); pb[ids] = cur["psibar"]
+        for i in range(o.N - 1):
+            rm = 0.5 * (rho[i] + rho[i + 1])
+            if any(set(np.nonzero(out["rho"] < rm)[0]) != set(ids[:i + 1])
+                   for out in (prv, nxt)):
+                continue
+
+            def F(out):
+                pbk = np.empty(o.N); pbk[out["order"]] = out["psibar"]
+                v = o.w * out["u"] / (out["rho"] * pbk)
+                return math.fsum(v * np.minimum(rm, out["rho"]) ** 2 / 2)
+
+            below = ids[:i + 1]
+            jz = O.Q_E * math.fsum(o.w[below] * (g[below] / pb[below] - 1.0))
+            rhs = jz + (F(nxt) - F(prv)) / (2 * o.dxi)
+            lhs = rm * (cur["a"][i + 1] * rm + cur["b"][i + 1] / rm)
+            worst = max(worst, abs(lhs - rhs))
+            scale = max(scale, abs(rhs))
+            checked += 1
+    assert checked > 50
+    return worst / scale
+
+
+@pytest.mark.parametrize("laser", [False, True])
+def test_bp_matches_integrated_ampere_law(laser):
+    o = _nonlinear(dxi=0.002, xi_end=2.0, laser=laser, n_rings=40)
+    assert _ampere_error(o, [300, 500, 700]) < 1.5e-3
+
+
+# ---------------------------------------------------------------------------
+# mutation checks: each planted mistake must fail a pin above
+# ---------------------------------------------------------------------------
+_MUTATIONS = ["drop_u2_in_C", "scale_C", "drop_dzpsi_in_B", "laser_no_quarter", "bb_sign"]
+
+
+@pytest.mark.parametrize("mutation", _MUTATIONS)
+def test_planted_coefficient_mistakes_break_the_ampere_pin(monkeypatch, mutation):
+    orig = O.coefficients
+
+    def bad(rho, u, w, psibar, gamma, dpsi, dzpsi, bb, da2, q=O.Q_E, m=O.M_E):
+        A, B, C = orig(rho, u, w, psibar, gamma, dpsi, dzpsi, bb, da2)
+        wr = w / rho
+        if mutation == "drop_u2_in_C":
+            C = C + q * wr * u * u / psibar ** 2
+        elif mutation == "scale_C":
+            C = 1.1 * C
+        elif mutation == "drop_dzpsi_in_B":
+            B = B + wr * u * dzpsi / psibar ** 2
+        elif mutation == "laser_no_quarter":
+            B = B - 3.0 * wr * (q ** 3 / (4.0 * m * m)) * da2 / psibar ** 2
+        elif mutation == "bb_sign":
+            B = B - 2.0 * wr * bb / psibar
+        return A, B, C
+
+    monkeypatch.setattr(O, "coefficients", bad)
+    o = _nonlinear(dxi=0.002, xi_end=2.0, laser=True, n_rings=40)
+    assert _ampere_error(o, [300, 500, 700]) > 5e-3
+
+
+def test_planted_dzeta_sign_breaks_the_axis_pin(monkeypatch):
+    orig = O.dzeta_psi
+    monkeypatch.setattr(O, "dzeta_psi", lambda *a: tuple(-x for x in orig(*a)))
+    o = _nonlinear(dxi=0.002, xi_end=2.0)
+    res = o.run(record_stride=0)
+    psi0, ez0 = res["axis"][:, 0], res["axis"][:, 1]
+    fd = (psi0[2:] - psi0[:-2]) / (2 * o.dxi)
+    assert np.max(np.abs(fd - ez0[1:-1])) > 0.5 * np.abs(ez0).max()
+
+
+def test_planted_force_sign_breaks_the_laser_closed_form(monkeypatch):
+    orig = O.forces
+
+    def bad(u, psibar, gamma, dpsi, bt, da2, q=O.Q_E, m=O.M_E):
+        fr, fu = orig(u, psibar, gamma, dpsi, bt, da2)
+        return fr, fu + 2 * (q * q) / (4.0 * m * m) * da2 / psibar   # printed sign
+    monkeypatch.setattr(O, "forces", bad)
+    r0, dr = W.uniform_rings(200, 6.0)
+    o = O.RingOracle(r0, dr, 0.01, 500, [W.GaussianLaser(0.01, 2.0, 1.0, 2.0)])
+    res = o.run(record_stride=0)
+    Z, _ = _long_response(4.0, lambda x: math.exp(-2 * (x - 2.0) ** 2))
+    th = 0.01 ** 2 / 4 * Z
+    assert abs(res["axis"][400, 0] - th) > 0.5 * abs(th)
