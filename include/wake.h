@@ -1,0 +1,199 @@
+/*
+ * wake.h - C ABI of the MI355X (gfx950) gridless quasistatic plasma-ring
+ * wake solver.
+ *
+ * The model is the paper's gridless quasistatic model ("Gridless
+ * quasistatic model for efficient simulation of plasma-based
+ * accelerators", Sec. "Gridless quasistatic model" and Appendix "Solve
+ * recursive system"): an axisymmetric electron plasma, discretised into
+ * delta-function rings (Sec. "Discretization of plasma species into
+ * macroparticles"), over an immobile ion species, responds to frozen
+ * ultra-relativistic beams and a frozen laser envelope.  The window is
+ * marched in xi = -zeta (normalised units: lengths in k_p^-1, densities in
+ * n0) one slice at a time: sort rings radially, gather sources, compute
+ * psi, d_rho psi, d_zeta psi (eqs. dpsi_dr, psi, dpsi_dzeta), gamma
+ * (eq. plasma_particle_motion_4), B_theta^(p) from the two-point recursion
+ * (eqs. b_theta_plasma, ai_bi, b_coeffs_1-3) and push (r, u_r) with
+ * second-order Adams-Bashforth (eqs. plasma_particle_motion_1-2).
+ *
+ * Conventions.  Electrons carry q = -1, m = 1, so psibar = 1 + psi.
+ * Fields are reported at slice nodes xi_n = n * dxi, n = 0 .. n_xi-1, at
+ * every ring, indexed by ring id (its index in the wake_plasma arrays):
+ *   psi, E_r - B_theta (= -d_rho psi), E_z (= d_xi psi), B_theta,
+ * and on the axis psi(0) and E_z(0) for every slice.
+ *
+ * Errors.  Every int-returning call returns WAKE_OK (0) or a negative
+ * wake_status; no C++ exception crosses this boundary.  Every computation
+ * runs in HIP kernels on the device current at wake_create; there is no CPU
+ * path.  A context is used from one host thread at a time.
+ *
+ * Memory.  Pointers passed in are owned by the caller.  Host input arrays
+ * are copied before the call returns.  Output pointers are host memory
+ * unless the call's dst_is_device flag is set, in which case they are
+ * device pointers on the context's device (e.g. torch tensor data).
+ */
+#ifndef WAKE_H
+#define WAKE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wake_ctx wake_ctx;
+typedef struct wake_batch wake_batch;
+
+enum wake_status {
+  WAKE_OK = 0,
+  WAKE_EINVAL = -1,      /* an argument is out of range or inconsistent */
+  WAKE_ENOMEM = -2,      /* device or host allocation failed */
+  WAKE_EDEVICE = -3,     /* a HIP runtime call failed */
+  WAKE_ESTATE = -4,      /* call out of order (e.g. slice not yet solved) */
+  WAKE_EBREAKDOWN = -5,  /* psibar <= 0 or a non-finite value: the quasistatic
+                            description broke down; the solve stopped there */
+  WAKE_ENOTREC = -6      /* the requested slice was not recorded */
+};
+
+enum wake_source_kind {
+  WAKE_BEAM_PARTICLES = 1, /* macroparticles (x, y, xi, w) with charge q each */
+  WAKE_BEAM_GAUSSIAN = 2,  /* analytic bi-Gaussian density n_peak exp(-r^2/2sr^2 - (xi-xi_c)^2/2sx^2) */
+  WAKE_LASER_GAUSSIAN = 3  /* frozen envelope |a|^2 = a0^2 exp(-2 r^2/w0^2 - 2 (xi-xi_l)^2/L^2) */
+};
+
+/* Plasma column (Sec. "Discretization of plasma species into macroparticles").
+ * Ring j starts at r0[j] = sum_{k<j} dr[k] + dr[j]/2 (checked to 1e-9
+ * relative), carries weight w_j = dens[j] r0[j] dr[j] (eq. macroparticle_weight)
+ * and the modified self weight w_j/2 - dens[j] dr[j]^2/8 (Sec. "Key
+ * algorithmic adjustments").  Immobile ions sit at the same radii with the
+ * same weights.  r0 must be strictly increasing, dr > 0, dens > 0. */
+typedef struct {
+  int32_t n_rings;
+  const double *r0;   /* [n_rings] host */
+  const double *dr;   /* [n_rings] host */
+  const double *dens; /* [n_rings] host, NULL = uniform density 1 */
+} wake_plasma;
+
+/* Longitudinal window: fields at xi_n = n * dxi for n = 0 .. n_xi-1
+ * (the plasma is unperturbed at xi = 0, Fig. 2 "initialize at zeta = 0").
+ * record_stride > 0 keeps a full snapshot (all six ring quantities) every
+ * record_stride slices; 0 keeps only the last solved slice. */
+typedef struct {
+  double dxi;
+  int32_t n_xi;
+  int32_t record_stride;
+} wake_domain;
+
+/* One driver or witness.  Beams are ultra-relativistic and frozen
+ * (Sec. "Theoretical framework"); B_theta^(b) at a ring is the beam charge
+ * inside its radius over the radius (Gauss law of the beam equation).
+ * Particles are deposited in xi with linear weights onto the slice nodes.
+ * Fields not used by `kind` are ignored. */
+typedef struct {
+  int32_t kind;                  /* wake_source_kind */
+  double q;                      /* charge of each beam particle (-1: electrons) */
+  int64_t n;                     /* number of particles (PARTICLES) */
+  const double *x, *y, *xi, *w;  /* [n] host: positions and number weights (n0 k_p^-3) */
+  double n_peak, sigma_r, sigma_xi, xi_c; /* GAUSSIAN beam */
+  double a0, w0, L, xi_l;        /* LASER_GAUSSIAN */
+} wake_source;
+
+/* Create a solver for one plasma column and window on the current HIP
+ * device.  hip_stream: a hipStream_t to run on, or NULL for a stream of the
+ * context's own.  Uploads the rings and builds the weights and ion tables
+ * on the device.  *out is NULL on failure. */
+int wake_create(wake_ctx **out, const wake_plasma *plasma, const wake_domain *domain,
+                void *hip_stream);
+
+/* Add one source; only before the first wake_solve / wake_prepare.
+ * At most 8 analytic sources (Gaussian beams and lasers together). */
+int wake_add_beam(wake_ctx *ctx, const wake_source *src);
+
+/* Build the beam table and everything else the march needs (done
+ * implicitly by the first wake_solve).  Synchronous. */
+int wake_prepare(wake_ctx *ctx);
+
+/* March slices [first_slice, first_slice + n_slices) on the context's
+ * stream (asynchronous).  first_slice must equal the context's next slice
+ * (0 after create, the end of the previous solve, or the slice given to
+ * wake_set_state).  A breakdown stops the march at its slice and is
+ * reported by wake_status / wake_fields. */
+int wake_solve(wake_ctx *ctx, int32_t first_slice, int32_t n_slices);
+
+/* Fields at the rings of one solved slice, indexed by ring id: psi,
+ * E_r - B_theta, E_z, B_theta, and the ring radius and radial momentum at
+ * that slice.  slice = -1 means the last slice of the most recent solve;
+ * otherwise the slice must be a recorded one (multiple of record_stride).
+ * NULL outputs are skipped.  Synchronizes the context's stream. */
+int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, double *ez,
+                double *bt, double *rho, double *ur, int32_t dst_is_device);
+
+/* psi(0) and E_z(0) of every slice [n_xi each]; slices not solved yet hold
+ * stale values.  Synchronizes. */
+int wake_lineout(wake_ctx *ctx, double *psi_axis, double *ez_axis, int32_t dst_is_device);
+
+/* Ring state at the context's next slice, indexed by ring id: radius,
+ * radial momentum and the Adams-Bashforth history (d rho/d xi and
+ * d u_r/d xi of the previous slice).  *slice receives the next slice.
+ * Synchronizes. */
+int wake_get_state(wake_ctx *ctx, int32_t *slice, double *rho, double *ur, double *f_rho,
+                   double *f_u, int32_t dst_is_device);
+
+/* Replace the ring state (by ring id) and make `slice` the next slice.
+ * f_rho/f_u may be NULL (zero history; slice 0 ignores it anyway).
+ * Radii must be > 0 and finite. */
+int wake_set_state(wake_ctx *ctx, int32_t slice, const double *rho, const double *ur,
+                   const double *f_rho, const double *f_u, int32_t src_is_device);
+
+/* Back to slice 0 with the rings at rest (asynchronous). */
+int wake_reset(wake_ctx *ctx);
+
+/* Breakdown slice (-1 if none) and next slice.  Synchronizes. */
+int wake_status(wake_ctx *ctx, int32_t *breakdown_slice, int32_t *next_slice);
+
+/* Wait for the context's stream. */
+int wake_sync(wake_ctx *ctx);
+
+/* Device bytes a context of this size holds (for admission control). */
+int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_t record_stride);
+
+void wake_destroy(wake_ctx *ctx);
+const char *wake_strerror(int code);
+
+/* ---------------------------------------------------------------------
+ * Tiling of the marcher: a workgroup of `threads` threads owns one
+ * instance; each thread owns `rings_per_thread` consecutive rings of a
+ * tile.  Instances larger than a tile are processed tile by tile.  The
+ * available (threads, rings_per_thread) pairs are enumerated below; the
+ * choice changes summation order only (results agree to rounding).
+ * --------------------------------------------------------------------- */
+int wake_tiling_count(void);
+int wake_tiling_get(int32_t index, int32_t *threads, int32_t *rings_per_thread);
+int wake_set_tiling(int32_t threads, int32_t rings_per_thread);
+int wake_get_tiling(int32_t *threads, int32_t *rings_per_thread);
+/* resident workgroups per compute unit for a tiling (occupancy) */
+int wake_tiling_occupancy(int32_t threads, int32_t rings_per_thread);
+
+/* ---------------------------------------------------------------------
+ * Batched form: many independent contexts (same device) marched by one
+ * persistent launch; workgroups take instances longest-first from a device
+ * counter.  Per-instance results equal those of solving alone with the same
+ * tiling.
+ * --------------------------------------------------------------------- */
+int wake_batch_create(wake_batch **out, wake_ctx *const *ctxs, int32_t n, void *hip_stream);
+/* Advance every instance by up to n_slices (-1: to its window end) from its
+ * next slice.  Asynchronous on the batch stream. */
+int wake_batch_solve(wake_batch *b, int32_t n_slices);
+/* Capture "reset every instance to slice 0, then march the whole window"
+ * into a HIP graph (grid = workgroups resident on the device, or
+ * `grid` if > 0); wake_batch_replay launches it. */
+int wake_batch_capture(wake_batch *b, int32_t grid);
+int wake_batch_replay(wake_batch *b);
+int wake_batch_sync(wake_batch *b);
+void wake_batch_destroy(wake_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAKE_H */

@@ -47,6 +47,9 @@ Readings taken where the paper is silent, garbled or self-inconsistent
       weights onto the slice nodes xi_n = n dxi; radially each particle is a
       thin ring, counted below rho when r_k < rho (strict).
   R13 laser: |a|^2 = a0^2 exp(-2 rho^2/w0^2) exp(-2 (xi-xi_L)^2/L^2).
+  R14 (numerics, not model) ln rho is evaluated as ln r0 + log1p((rho-r0)/r0)
+      so that its rounding, multiplied by the enclosed charge in eq. psi,
+      stays proportional to the ring displacement.
 """
 from __future__ import annotations
 
@@ -76,17 +79,17 @@ def ring_weights(r0, dr, dens=None):
     return w, wh
 
 
-def _gauss_log_sums(rho_l, w_l, wh_l, q):
+def _gauss_log_sums(rho_l, w_l, wh_l, q, lnr):
     """Fields of one species at its own sorted ring radii, extended precision.
 
     eq. dpsi_dr : d_rho psi(rho) = -(1/rho) sum_{rho_k<rho} q w_k
     eq. psi     : psi(rho) = -sum_k q w_k ln max(rho, rho_k)
     At the ring itself the ring contributes w^ to the Gauss sum (R6); psi is
-    continuous there.  Returns (psi, d_rho psi, psi on the axis).
+    continuous there.  lnr = ln(rho_l).  Returns (psi, d_rho psi, psi on the
+    axis).
     """
     csum = np.cumsum(w_l)
     below = np.concatenate([np.zeros(1, LD), csum[:-1]])        # sum_{k<i} w_k
-    lnr = np.log(rho_l)
     wl = w_l * lnr
     rsum = np.cumsum(wl[::-1])[::-1]                              # sum_{k>=i}
     above = np.concatenate([rsum[1:], np.zeros(1, LD)])          # sum_{k>i}
@@ -101,7 +104,7 @@ class IonNodes:
 
     def __init__(self, r0, w, wh):
         r0_l, w_l, wh_l = r0.astype(LD), w.astype(LD), wh.astype(LD)
-        psi, dpsi, psi_axis = _gauss_log_sums(r0_l, w_l, wh_l, Q_ION)
+        psi, dpsi, psi_axis = _gauss_log_sums(r0_l, w_l, wh_l, Q_ION, np.log(r0_l))
         self.Q = np.cumsum(w_l)[-1]
         self.Rp = None
         self.r = None
@@ -207,12 +210,22 @@ def laser_terms(src, xi, rho):
 # ---------------------------------------------------------------------------
 # the per-slice steps
 # ---------------------------------------------------------------------------
-def psi_family(rho, w, wh, ions):
+def ring_log(rho, r0):
+    """ln(rho) of rings whose initial radius is r0, evaluated as
+    ln r0 + log1p((rho - r0)/r0) in extended precision (reading R14): the
+    psi sums multiply ln rho by the enclosed charge, so its rounding must
+    scale with the ring's displacement, not with |ln rho|."""
+    r0_l = np.asarray(r0).astype(LD)
+    return np.log(r0_l) + np.log1p((np.asarray(rho).astype(LD) - r0_l) / r0_l)
+
+
+def psi_family(rho, w, wh, ions, r0):
     """psi and d_rho psi at sorted electron rings plus the ion species
-    (eqs. dpsi_dr, psi; species summed after interpolation, R11).
-    Returns binary64 (psi, dpsi, psi_axis)."""
+    (eqs. dpsi_dr, psi; species summed after interpolation, R11).  r0 are
+    the rings' initial radii.  Returns binary64 (psi, dpsi, psi_axis)."""
     rho_l = rho.astype(LD)
-    psi_e, dpsi_e, axis_e = _gauss_log_sums(rho_l, w.astype(LD), wh.astype(LD), Q_E)
+    psi_e, dpsi_e, axis_e = _gauss_log_sums(rho_l, w.astype(LD), wh.astype(LD), Q_E,
+                                            ring_log(rho, r0))
     psi_i, dpsi_i = ions.at(rho_l)
     psi = (psi_e + psi_i).astype(np.float64)
     dpsi = (dpsi_e + dpsi_i).astype(np.float64)
@@ -369,7 +382,7 @@ class RingOracle:
         u = state["u"][ids]
         w, wh = self.w[ids], self.wh[ids]
         bb, a2, da2 = self.sources_at(n, rho)
-        psi, dpsi, psi_axis = psi_family(rho, w, wh, self.ions)
+        psi, dpsi, psi_axis = psi_family(rho, w, wh, self.ions, self.r0[ids])
         psibar, gamma = local_quantities(psi, u, a2)
         out = dict(status=0)
         if not np.all(psibar > 0) or not np.all(np.isfinite(psibar)):  # R10

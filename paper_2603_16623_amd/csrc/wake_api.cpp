@@ -1,0 +1,720 @@
+// Host runtime of the C ABI in include/wake.h: argument checking, device
+// memory (one arena per context), beam-table build and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/wake.h"
+#include "wake_common.h"
+#include "wake_launch.h"
+
+namespace {
+
+int g_nt = 256, g_k = 4;   // marcher tiling used by new launches
+
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  template <class T>
+  T* take(size_t n) {
+    used = (used + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + used);
+    used += n * sizeof(T);
+    return p;
+  }
+};
+
+struct Layout {
+  size_t bytes = 0;
+  int lut_n = 0;
+};
+
+int lut_size(int N, double Rp, double min_dr) {
+  double want = std::ceil(2.0 * Rp / min_dr);
+  double cap = 16.0 * N + 4096.0;
+  double lo = 2.0 * N;
+  double v = std::min(std::max(want, lo), cap);
+  return (int)v;
+}
+
+// Bytes of the per-context arena (must mirror carve()).
+size_t arena_bytes(int N, int n_xi, int stride, int lut_n) {
+  const size_t n_rec = stride > 0 ? (size_t)(n_xi + stride - 1) / stride : 0;
+  const size_t tsc = (size_t)(N / 2 + 1024) * 5;
+  size_t d = 0, i = 0;
+  d += 4 * (size_t)N;               // w, wh, ln r0 (dd)
+  d += 5 * (size_t)(N + 2);         // ion tables
+  d += 4;                           // tot0, Q
+  i += (size_t)lut_n + 1;           // lut
+  d += 8 * (size_t)N;               // rho, u, fr, fu x2
+  i += 2 * (size_t)N;               // id x2
+  d += WAKE_NSCR * (size_t)N;       // scratch
+  d += tsc;                         // tile scratch
+  d += 2 * (size_t)N;               // skey_r x2
+  i += 4 * (size_t)N;               // skey_i, skey_p x2
+  d += 2 * (size_t)n_xi;            // axis
+  d += n_rec * OUT_N * (size_t)N;   // snapshots
+  d += OUT_N * (size_t)N;           // last
+  i += CTL_NWORDS;                  // ctl
+  d += 4 * (size_t)N;               // staging
+  return d * 8 + i * 4 + 40 * 256;  // + alignment slack
+}
+
+}  // namespace
+
+struct wake_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  WakeInst I;
+  WakeInst* d_inst = nullptr;
+  int32_t* d_counter = nullptr;
+  Arena arena;
+  double* staging = nullptr;   // 4N doubles
+  // beam table (persistent part)
+  char* beam_mem = nullptr;
+  // pending particle sources (host copies until the table is built)
+  std::vector<double> px, py, pxi, pw, pq;
+  bool prepared = false;
+  int next = 0;
+  hipStream_t pending = nullptr;   // batch stream that last marched this context
+};
+
+struct wake_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<wake_ctx*> ctxs;
+  WakeInst* d_insts = nullptr;
+  int32_t* d_counter = nullptr;
+  int cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static int dev_err(hipError_t e) { return e == hipErrorOutOfMemory ? WAKE_ENOMEM : WAKE_EDEVICE; }
+
+#define HIP_TRY(x)                              \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return dev_err(e_);   \
+  } while (0)
+
+extern "C" const char* wake_strerror(int code) {
+  switch (code) {
+    case WAKE_OK: return "ok";
+    case WAKE_EINVAL: return "invalid argument";
+    case WAKE_ENOMEM: return "out of memory";
+    case WAKE_EDEVICE: return "HIP runtime error";
+    case WAKE_ESTATE: return "call out of order";
+    case WAKE_EBREAKDOWN: return "quasistatic breakdown (psibar <= 0 or non-finite value)";
+    case WAKE_ENOTREC: return "slice not recorded";
+    default: return "unknown error";
+  }
+}
+
+extern "C" int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles,
+                                  int32_t record_stride) {
+  if (n_rings <= 0 || n_xi <= 0 || n_particles < 0 || record_stride < 0) return -1;
+  const int lut_n = 16 * n_rings + 4096;
+  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, lut_n);
+  // persistent beam table: offsets + (r, cumulative charge) per entry
+  b += 4 * (int64_t)(n_xi + 1) + 16 * 2 * n_particles + 1024;
+  // transient build buffers (particles, counts, padded entries)
+  b += 40 * n_particles + 20 * (int64_t)(n_xi + 1) + 24 * 4 * n_particles + 2048;
+  b += sizeof(WakeInst) + 512;
+  return b;
+}
+
+static void release(wake_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->arena.base) (void)hipFree(c->arena.base);
+  if (c->beam_mem) (void)hipFree(c->beam_mem);
+  if (c->d_inst) (void)hipFree(c->d_inst);
+  if (c->d_counter) (void)hipFree(c->d_counter);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" void wake_destroy(wake_ctx* ctx) { release(ctx); }
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom,
+                           void* hip_stream) {
+  if (!out) return WAKE_EINVAL;
+  *out = nullptr;
+  if (!plasma || !dom || plasma->n_rings <= 0 || !plasma->r0 || !plasma->dr) return WAKE_EINVAL;
+  const int N = plasma->n_rings;
+  if (N > (1 << 28)) return WAKE_EINVAL;
+  if (!finite_pos(dom->dxi) || dom->n_xi <= 0 || dom->record_stride < 0) return WAKE_EINVAL;
+  // ring geometry: r0_j = sum_{k<j} dr_k + dr_j/2, strictly increasing
+  double edge = 0.0, min_dr = INFINITY;
+  for (int j = 0; j < N; ++j) {
+    const double d = plasma->dr[j], r = plasma->r0[j];
+    if (!finite_pos(d) || !finite_pos(r)) return WAKE_EINVAL;
+    if (j > 0 && !(r > plasma->r0[j - 1])) return WAKE_EINVAL;
+    const double want = edge + 0.5 * d;
+    if (std::fabs(r - want) > 1e-9 * want) return WAKE_EINVAL;
+    if (plasma->dens && !finite_pos(plasma->dens[j])) return WAKE_EINVAL;
+    edge += d;
+    min_dr = std::min(min_dr, d);
+  }
+  wake_ctx* c = new (std::nothrow) wake_ctx();
+  if (!c) return WAKE_ENOMEM;
+  std::memset(&c->I, 0, sizeof(WakeInst));
+  if (hipGetDevice(&c->device) != hipSuccess) { release(c); return WAKE_EDEVICE; }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      release(c);
+      return WAKE_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  WakeInst& I = c->I;
+  I.N = N;
+  I.n_xi = dom->n_xi;
+  I.stride = dom->record_stride;
+  I.dxi = dom->dxi;
+  I.Rp = plasma->r0[N - 1] + plasma->dr[N - 1] / 2.0;
+  I.lut_n = lut_size(N, I.Rp, min_dr);
+  I.lut_scale = (double)I.lut_n / I.Rp;
+  I.inv2pidxi = 1.0 / (2.0 * M_PI * I.dxi);
+  const size_t bytes = arena_bytes(N, I.n_xi, I.stride, I.lut_n);
+  hipError_t e = hipMalloc(&c->arena.base, bytes);
+  if (e != hipSuccess) { c->arena.base = nullptr; release(c); return dev_err(e); }
+  c->arena.size = bytes;
+  Arena& A = c->arena;
+  const size_t n_rec = I.stride > 0 ? (size_t)(I.n_xi + I.stride - 1) / I.stride : 0;
+  I.w = A.take<double>(N);
+  I.wh = A.take<double>(N);
+  I.L0_hi = A.take<double>(N);
+  I.L0_lo = A.take<double>(N);
+  I.ion_r = A.take<double>(N + 2);
+  I.ion_dp_hi = A.take<double>(N + 2);
+  I.ion_dp_lo = A.take<double>(N + 2);
+  I.ion_ps_hi = A.take<double>(N + 2);
+  I.ion_ps_lo = A.take<double>(N + 2);
+  I.tot0 = A.take<double>(4);
+  I.ion_lut = A.take<int32_t>(I.lut_n + 1);
+  for (int b = 0; b < 2; ++b) {
+    I.rho[b] = A.take<double>(N);
+    I.u[b] = A.take<double>(N);
+    I.fr[b] = A.take<double>(N);
+    I.fu[b] = A.take<double>(N);
+    I.id[b] = A.take<int32_t>(N);
+  }
+  I.scr = A.take<double>((size_t)WAKE_NSCR * N);
+  I.tscr = A.take<double>((size_t)(N / 2 + 1024) * 5);
+  for (int b = 0; b < 2; ++b) {
+    I.skey_r[b] = A.take<double>(N);
+    I.skey_i[b] = A.take<int32_t>(N);
+    I.skey_p[b] = A.take<int32_t>(N);
+  }
+  I.axis = A.take<double>(2 * (size_t)I.n_xi);
+  I.snap = n_rec ? A.take<double>(n_rec * OUT_N * N) : nullptr;
+  I.last = A.take<double>((size_t)OUT_N * N);
+  I.ctl = A.take<int32_t>(CTL_NWORDS);
+  c->staging = A.take<double>(4 * (size_t)N);
+  if (A.used > A.size) { release(c); return WAKE_ENOMEM; }
+  e = hipMalloc(&c->d_inst, sizeof(WakeInst));
+  if (e == hipSuccess) e = hipMalloc(&c->d_counter, 64);
+  if (e != hipSuccess) { release(c); return dev_err(e); }
+  // upload the ring geometry into the staging area and build constants
+  double* d_r0 = c->staging;
+  double* d_dr = c->staging + N;
+  double* d_dn = plasma->dens ? c->staging + 2 * (size_t)N : nullptr;
+  e = hipMemcpyAsync(d_r0, plasma->r0, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_dr, plasma->dr, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && d_dn)
+    e = hipMemcpyAsync(d_dn, plasma->dens, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(I.axis, 0, sizeof(double) * 2 * I.n_xi, c->stream);
+  if (e == hipSuccess) e = launch_init(I, d_r0, d_dr, d_dn, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) { release(c); return dev_err(e); }
+  *out = c;
+  return WAKE_OK;
+}
+
+extern "C" int wake_add_beam(wake_ctx* c, const wake_source* s) {
+  if (!c || !s) return WAKE_EINVAL;
+  if (c->prepared) return WAKE_ESTATE;
+  WakeInst& I = c->I;
+  if (s->kind == WAKE_BEAM_PARTICLES) {
+    if (s->n < 0 || !std::isfinite(s->q)) return WAKE_EINVAL;
+    if (s->n > 0 && (!s->x || !s->y || !s->xi || !s->w)) return WAKE_EINVAL;
+    if ((int64_t)c->px.size() + s->n > (int64_t)1 << 29) return WAKE_EINVAL;
+    for (int64_t k = 0; k < s->n; ++k)
+      if (!std::isfinite(s->x[k]) || !std::isfinite(s->y[k]) || !std::isfinite(s->xi[k]) ||
+          !std::isfinite(s->w[k]))
+        return WAKE_EINVAL;
+    try {
+      c->px.insert(c->px.end(), s->x, s->x + s->n);
+      c->py.insert(c->py.end(), s->y, s->y + s->n);
+      c->pxi.insert(c->pxi.end(), s->xi, s->xi + s->n);
+      c->pw.insert(c->pw.end(), s->w, s->w + s->n);
+      c->pq.insert(c->pq.end(), (size_t)s->n, s->q);
+    } catch (...) {
+      return WAKE_ENOMEM;
+    }
+    return WAKE_OK;
+  }
+  if (s->kind != WAKE_BEAM_GAUSSIAN && s->kind != WAKE_LASER_GAUSSIAN) return WAKE_EINVAL;
+  if (I.n_an >= WAKE_MAX_ANALYTIC) return WAKE_EINVAL;
+  WakeAnalytic a;
+  std::memset(&a, 0, sizeof(a));
+  a.kind = s->kind;
+  if (s->kind == WAKE_BEAM_GAUSSIAN) {
+    if (!std::isfinite(s->q) || !std::isfinite(s->n_peak) || !finite_pos(s->sigma_r) ||
+        !finite_pos(s->sigma_xi) || !std::isfinite(s->xi_c))
+      return WAKE_EINVAL;
+    a.q = s->q; a.n_peak = s->n_peak; a.sigma_r = s->sigma_r; a.sigma_xi = s->sigma_xi; a.xi_c = s->xi_c;
+  } else {
+    if (!std::isfinite(s->a0) || !finite_pos(s->w0) || !finite_pos(s->L) || !std::isfinite(s->xi_l))
+      return WAKE_EINVAL;
+    a.a0 = s->a0; a.w0 = s->w0; a.L = s->L; a.xi_l = s->xi_l;
+    I.has_laser = 1;
+  }
+  I.an[I.n_an++] = a;
+  return WAKE_OK;
+}
+
+extern "C" int wake_prepare(wake_ctx* c) {
+  if (!c) return WAKE_EINVAL;
+  if (c->prepared) return WAKE_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  WakeInst& I = c->I;
+  const int64_t np = (int64_t)c->px.size();
+  const int n_xi = I.n_xi;
+  const int64_t ne = 2 * np;            // at most two nodes per particle
+  const int64_t npad = 4 * np + 4;      // power-of-two padded entries
+  // persistent: offsets + (r, cumulative charge)
+  const size_t pbytes = 4 * (size_t)(n_xi + 1) + 256 + 16 * (size_t)ne + 512;
+  HIP_TRY(hipMalloc(&c->beam_mem, pbytes));
+  {
+    Arena P;
+    P.base = c->beam_mem;
+    P.size = pbytes;
+    I.boff = P.take<int32_t>(n_xi + 1);
+    double* br = P.take<double>(std::max<int64_t>(ne, 1));
+    double* bc = P.take<double>(std::max<int64_t>(ne, 1));
+    I.br = br;
+    I.bcum = bc;
+    I.nb = (int32_t)ne;
+    if (np > 0) {
+      const size_t tbytes = 40 * (size_t)np + 20 * (size_t)(n_xi + 1) + 24 * (size_t)npad + 4096;
+      char* tmp = nullptr;
+      HIP_TRY(hipMalloc(&tmp, tbytes));
+      Arena Tm;
+      Tm.base = tmp;
+      Tm.size = tbytes;
+      double* x = Tm.take<double>(np);
+      double* y = Tm.take<double>(np);
+      double* xi = Tm.take<double>(np);
+      double* w = Tm.take<double>(np);
+      double* q = Tm.take<double>(np);
+      int32_t* cnt = Tm.take<int32_t>(n_xi + 1);
+      int32_t* cnt2 = Tm.take<int32_t>(n_xi + 1);
+      int32_t* cursor = Tm.take<int32_t>(n_xi + 1);
+      int32_t* poff = Tm.take<int32_t>(n_xi + 1);
+      double* er = Tm.take<double>(npad);
+      double* eq = Tm.take<double>(npad);
+      int64_t* ek = Tm.take<int64_t>(npad);
+      hipError_t e = hipSuccess;
+      const size_t sz = sizeof(double) * np;
+      e = hipMemcpyAsync(x, c->px.data(), sz, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(y, c->py.data(), sz, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(xi, c->pxi.data(), sz, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(w, c->pw.data(), sz, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(q, c->pq.data(), sz, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = launch_beam_table(x, y, xi, w, q, np, I.dxi, n_xi, cnt, cnt2, cursor,
+                              const_cast<int32_t*>(I.boff), poff, er, eq, ek, br, bc, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      (void)hipFree(tmp);
+      if (e != hipSuccess) return dev_err(e);
+      // the table holds only entries that landed on a node
+      int32_t total = 0;
+      HIP_TRY(hipMemcpy(&total, I.boff + n_xi, sizeof(int32_t), hipMemcpyDeviceToHost));
+      I.nb = total;
+    } else {
+      HIP_TRY(hipMemsetAsync(const_cast<int32_t*>(I.boff), 0, 4 * (size_t)(n_xi + 1), c->stream));
+      I.nb = 0;
+    }
+  }
+  std::vector<double>().swap(c->px);
+  std::vector<double>().swap(c->py);
+  std::vector<double>().swap(c->pxi);
+  std::vector<double>().swap(c->pw);
+  std::vector<double>().swap(c->pq);
+  HIP_TRY(march_prepare(g_nt, g_k));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->prepared = true;
+  return WAKE_OK;
+}
+
+static int drain(wake_ctx* c) {
+  if (c->pending) {
+    HIP_TRY(hipStreamSynchronize(c->pending));
+    c->pending = nullptr;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+static int read_ctl(wake_ctx* c, int32_t ctl[CTL_NWORDS]) {
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  HIP_TRY(hipMemcpy(ctl, c->I.ctl, sizeof(int32_t) * CTL_NWORDS, hipMemcpyDeviceToHost));
+  return WAKE_OK;
+}
+
+static int launch_one(wake_ctx* c, int first, int count) {
+  WakeInst& I = c->I;
+  I.first = first;
+  I.count = count;
+  HIP_TRY(hipMemcpyAsync(c->d_inst, &I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_march(g_nt, g_k, c->d_inst, 1, c->d_counter, 1, c->stream));
+  return WAKE_OK;
+}
+
+extern "C" int wake_solve(wake_ctx* c, int32_t first, int32_t count) {
+  if (!c) return WAKE_EINVAL;
+  if (count < 0 || first < 0 || (int64_t)first + count > c->I.n_xi) return WAKE_EINVAL;
+  if (first != c->next) return WAKE_ESTATE;
+  if (count == 0) return WAKE_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  r = wake_prepare(c);
+  if (r != WAKE_OK) return r;
+  r = launch_one(c, first, count);
+  if (r != WAKE_OK) return r;
+  c->next = first + count;
+  return WAKE_OK;
+}
+
+extern "C" int wake_sync(wake_ctx* c) {
+  if (!c) return WAKE_EINVAL;
+  return drain(c);
+}
+
+extern "C" int wake_status(wake_ctx* c, int32_t* brk, int32_t* next) {
+  if (!c) return WAKE_EINVAL;
+  int32_t ctl[CTL_NWORDS];
+  int r = read_ctl(c, ctl);
+  if (r != WAKE_OK) return r;
+  if (ctl[CTL_BREAK] >= 0) c->next = ctl[CTL_NEXT];
+  if (brk) *brk = ctl[CTL_BREAK];
+  if (next) *next = ctl[CTL_BREAK] >= 0 ? ctl[CTL_NEXT] : c->next;
+  return WAKE_OK;
+}
+
+static int copy_out(double* dst, const double* src, size_t n, int dev, hipStream_t s) {
+  if (!dst) return WAKE_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, sizeof(double) * n,
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  return WAKE_OK;
+}
+
+extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt, double* ez,
+                           double* bt, double* rho, double* ur, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  const WakeInst& I = c->I;
+  int32_t ctl[CTL_NWORDS];
+  int r = read_ctl(c, ctl);
+  if (r != WAKE_OK) return r;
+  const int brk = ctl[CTL_BREAK];
+  const double* base;
+  if (slice == -1) {
+    if (c->next == 0 && brk < 0) return WAKE_ESTATE;
+    if (brk >= 0) return WAKE_EBREAKDOWN;
+    base = I.last;
+  } else {
+    if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
+    if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
+    if (slice >= c->next) return WAKE_ESTATE;
+    if (I.stride <= 0 || slice % I.stride != 0) return WAKE_ENOTREC;
+    base = I.snap + (size_t)(slice / I.stride) * OUT_N * I.N;
+  }
+  const size_t N = I.N;
+  double* outs[OUT_N] = {psi, erbt, ez, bt, rho, ur};
+  for (int q = 0; q < OUT_N; ++q) {
+    r = copy_out(outs[q], base + q * N, N, dev, c->stream);
+    if (r != WAKE_OK) return r;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+extern "C" int wake_lineout(wake_ctx* c, double* psi_axis, double* ez_axis, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const size_t n = c->I.n_xi;
+  if (psi_axis)
+    HIP_TRY(hipMemcpy2DAsync(psi_axis, sizeof(double), c->I.axis, 2 * sizeof(double), sizeof(double),
+                             n, kind, c->stream));
+  if (ez_axis)
+    HIP_TRY(hipMemcpy2DAsync(ez_axis, sizeof(double), c->I.axis + 1, 2 * sizeof(double),
+                             sizeof(double), n, kind, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+extern "C" int wake_get_state(wake_ctx* c, int32_t* slice, double* rho, double* ur, double* f_rho,
+                              double* f_u, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  int32_t brk = -1, next = 0;
+  int r = wake_status(c, &brk, &next);
+  if (r != WAKE_OK) return r;
+  const size_t N = c->I.N;
+  double* st = c->staging;
+  HIP_TRY(launch_state_by_id(c->I, st, st + N, st + 2 * N, st + 3 * N, c->stream));
+  double* outs[4] = {rho, ur, f_rho, f_u};
+  for (int q = 0; q < 4; ++q) {
+    r = copy_out(outs[q], st + q * N, N, dev, c->stream);
+    if (r != WAKE_OK) return r;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (slice) *slice = next;
+  return WAKE_OK;
+}
+
+extern "C" int wake_set_state(wake_ctx* c, int32_t slice, const double* rho, const double* ur,
+                              const double* f_rho, const double* f_u, int32_t dev) {
+  if (!c || !rho || !ur) return WAKE_EINVAL;
+  if (slice < 0 || slice >= c->I.n_xi) return WAKE_EINVAL;
+  const size_t N = c->I.N;
+  if (!dev) {
+    for (size_t i = 0; i < N; ++i)
+      if (!finite_pos(rho[i]) || !std::isfinite(ur[i])) return WAKE_EINVAL;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  double* st = c->staging;
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(hipMemcpyAsync(st, rho, sizeof(double) * N, kind, c->stream));
+  HIP_TRY(hipMemcpyAsync(st + N, ur, sizeof(double) * N, kind, c->stream));
+  if (f_rho) HIP_TRY(hipMemcpyAsync(st + 2 * N, f_rho, sizeof(double) * N, kind, c->stream));
+  if (f_u) HIP_TRY(hipMemcpyAsync(st + 3 * N, f_u, sizeof(double) * N, kind, c->stream));
+  HIP_TRY(launch_state_set(c->I, st, st + N, f_rho ? st + 2 * N : nullptr,
+                           f_u ? st + 3 * N : nullptr, slice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->next = slice;
+  return WAKE_OK;
+}
+
+extern "C" int wake_reset(wake_ctx* c) {
+  if (!c) return WAKE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  HIP_TRY(hipMemcpyAsync(c->d_inst, &c->I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_reset(c->d_inst, 1, c->stream));
+  c->next = 0;
+  return WAKE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tiling
+// ---------------------------------------------------------------------------
+extern "C" int wake_tiling_count(void) { return march_config_count(); }
+
+extern "C" int wake_tiling_get(int32_t idx, int32_t* nt, int32_t* k) {
+  int a, b;
+  if (!nt || !k || march_config(idx, &a, &b) != 0) return WAKE_EINVAL;
+  *nt = a;
+  *k = b;
+  return WAKE_OK;
+}
+
+static bool tiling_ok(int nt, int k) {
+  for (int i = 0; i < march_config_count(); ++i) {
+    int a, b;
+    march_config(i, &a, &b);
+    if (a == nt && b == k) return true;
+  }
+  return false;
+}
+
+extern "C" int wake_set_tiling(int32_t nt, int32_t k) {
+  if (!tiling_ok(nt, k)) return WAKE_EINVAL;
+  HIP_TRY(march_prepare(nt, k));
+  g_nt = nt;
+  g_k = k;
+  return WAKE_OK;
+}
+
+extern "C" int wake_get_tiling(int32_t* nt, int32_t* k) {
+  if (!nt || !k) return WAKE_EINVAL;
+  *nt = g_nt;
+  *k = g_k;
+  return WAKE_OK;
+}
+
+extern "C" int wake_tiling_occupancy(int32_t nt, int32_t k) {
+  if (!tiling_ok(nt, k)) return WAKE_EINVAL;
+  if (march_prepare(nt, k) != hipSuccess) return WAKE_EDEVICE;
+  return march_occupancy(nt, k);
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+static void batch_release(wake_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_insts) (void)hipFree(b->d_insts);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+extern "C" void wake_batch_destroy(wake_batch* b) { batch_release(b); }
+
+extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_t n, void* stream) {
+  if (!out) return WAKE_EINVAL;
+  *out = nullptr;
+  if (!ctxs || n <= 0) return WAKE_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return WAKE_EINVAL;
+  wake_batch* b = new (std::nothrow) wake_batch();
+  if (!b) return WAKE_ENOMEM;
+  b->device = ctxs[0]->device;
+  for (int i = 0; i < n; ++i) {
+    if (ctxs[i]->device != b->device) { batch_release(b); return WAKE_EINVAL; }
+    int r = wake_prepare(ctxs[i]);
+    if (r != WAKE_OK) { batch_release(b); return r; }
+  }
+  b->ctxs.assign(ctxs, ctxs + n);
+  if (stream) {
+    b->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      batch_release(b);
+      return WAKE_EDEVICE;
+    }
+    b->own_stream = true;
+  }
+  b->cap = n;
+  if (hipMalloc(&b->d_insts, sizeof(WakeInst) * n) != hipSuccess ||
+      hipMalloc(&b->d_counter, 64) != hipSuccess) {
+    batch_release(b);
+    return WAKE_ENOMEM;
+  }
+  *out = b;
+  return WAKE_OK;
+}
+
+static int device_cus(int dev) {
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  return cu > 0 ? cu : 1;
+}
+
+// Fill the device descriptor array with (first, count) per instance, longest
+// first.  Returns the number of instances with work.
+static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vector<WakeInst>& v) {
+  v.clear();
+  for (wake_ctx* c : b->ctxs) {
+    const int first = from_zero ? 0 : c->next;
+    int count = c->I.n_xi - first;
+    if (n_slices >= 0) count = std::min(count, (int)n_slices);
+    if (count <= 0) continue;
+    WakeInst I = c->I;
+    I.first = first;
+    I.count = count;
+    v.push_back(I);
+  }
+  std::stable_sort(v.begin(), v.end(), [](const WakeInst& a, const WakeInst& c) {
+    return (int64_t)a.N * a.count > (int64_t)c.N * c.count;
+  });
+  return (int)v.size();
+}
+
+extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
+  if (!b) return WAKE_EINVAL;
+  HIP_TRY(hipSetDevice(b->device));
+  for (wake_ctx* c : b->ctxs) {
+    int r = drain(c);
+    if (r != WAKE_OK) return r;
+  }
+  std::vector<WakeInst> v;
+  const int n = batch_stage(b, n_slices, false, v);
+  if (n == 0) return WAKE_OK;
+  HIP_TRY(hipMemcpyAsync(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice, b->stream));
+  const int occ = std::max(1, march_occupancy(g_nt, g_k));
+  const int grid = std::min(n, occ * device_cus(b->device));
+  HIP_TRY(launch_march(g_nt, g_k, b->d_insts, n, b->d_counter, grid, b->stream));
+  for (wake_ctx* c : b->ctxs) {
+    int count = c->I.n_xi - c->next;
+    if (n_slices >= 0) count = std::min(count, (int)n_slices);
+    if (count > 0) c->next += count;
+    c->pending = b->stream;
+  }
+  return WAKE_OK;
+}
+
+extern "C" int wake_batch_capture(wake_batch* b, int32_t grid) {
+  if (!b) return WAKE_EINVAL;
+  HIP_TRY(hipSetDevice(b->device));
+  for (wake_ctx* c : b->ctxs) {
+    int r = drain(c);
+    if (r != WAKE_OK) return r;
+  }
+  std::vector<WakeInst> v;
+  const int n = batch_stage(b, -1, true, v);
+  if (n == 0) return WAKE_EINVAL;
+  HIP_TRY(hipMemcpy(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice));
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  const int occ = std::max(1, march_occupancy(g_nt, g_k));
+  int g = grid > 0 ? grid : occ * device_cus(b->device);
+  g = std::min(g, n);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = launch_reset(b->d_insts, n, b->stream);
+  if (e == hipSuccess) e = launch_march(g_nt, g_k, b->d_insts, n, b->d_counter, g, b->stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return dev_err(e != hipSuccess ? e : e2);
+  }
+  b->graph = graph;
+  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  for (wake_ctx* c : b->ctxs) c->next = 0;
+  return WAKE_OK;
+}
+
+extern "C" int wake_batch_replay(wake_batch* b) {
+  if (!b || !b->exec) return WAKE_ESTATE;
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  for (wake_ctx* c : b->ctxs) {
+    c->next = c->I.n_xi;
+    c->pending = b->stream;
+  }
+  return WAKE_OK;
+}
+
+extern "C" int wake_batch_sync(wake_batch* b) {
+  if (!b) return WAKE_EINVAL;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return WAKE_OK;
+}

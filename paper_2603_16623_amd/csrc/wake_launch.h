@@ -1,0 +1,24 @@
+// Host-callable kernel launchers (defined in wake_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "wake_common.h"
+
+hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, const double* dens,
+                       hipStream_t s);
+hipError_t launch_beam_table(const double* x, const double* y, const double* xi, const double* w,
+                             const double* q, int64_t np, double dxi, int n_xi, int32_t* cnt,
+                             int32_t* cnt2, int32_t* cursor, int32_t* off, int32_t* poff, double* er,
+                             double* eq, int64_t* ek, double* br, double* bcum, hipStream_t s);
+hipError_t launch_zero(int32_t* p, int n, hipStream_t s);
+hipError_t launch_state_by_id(const WakeInst& I, double* rho, double* u, double* fr, double* fu,
+                              hipStream_t s);
+hipError_t launch_state_set(const WakeInst& I, const double* rho, const double* u, const double* fr,
+                            const double* fu, int slice, hipStream_t s);
+hipError_t launch_reset(const WakeInst* d_insts, int n_insts, hipStream_t s);
+
+int march_config_count();
+int march_config(int idx, int* nt, int* k);
+hipError_t launch_march(int nt, int k, const WakeInst* d_insts, int n_insts, int32_t* counter,
+                        int grid, hipStream_t s);
+int march_occupancy(int nt, int k);
+hipError_t march_prepare(int nt, int k);

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of ``libwake.so`` (C ABI declared in include/wake.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Functions carry the C names; ``WakeSolver`` and ``WakeBatch``
+wrap a context / batch handle and raise ``WakeError`` on a negative status.
+Host arrays are numpy float64; device arrays may be any object with
+``data_ptr()`` (e.g. torch CUDA tensors), passed with ``device=True``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwake.so")
+
+WAKE_OK, WAKE_EINVAL, WAKE_ENOMEM, WAKE_EDEVICE = 0, -1, -2, -3
+WAKE_ESTATE, WAKE_EBREAKDOWN, WAKE_ENOTREC = -4, -5, -6
+WAKE_BEAM_PARTICLES, WAKE_BEAM_GAUSSIAN, WAKE_LASER_GAUSSIAN = 1, 2, 3
+
+
+class WakeError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class _Plasma(C.Structure):
+    _fields_ = [("n_rings", C.c_int32), ("r0", C.c_void_p), ("dr", C.c_void_p),
+                ("dens", C.c_void_p)]
+
+
+class _Domain(C.Structure):
+    _fields_ = [("dxi", C.c_double), ("n_xi", C.c_int32), ("record_stride", C.c_int32)]
+
+
+class _Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("q", C.c_double), ("n", C.c_int64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("xi", C.c_void_p), ("w", C.c_void_p),
+                ("n_peak", C.c_double), ("sigma_r", C.c_double), ("sigma_xi", C.c_double),
+                ("xi_c", C.c_double), ("a0", C.c_double), ("w0", C.c_double), ("L", C.c_double),
+                ("xi_l", C.c_double)]
+
+
+_I, _P, _D, _I64 = C.c_int32, C.c_void_p, C.c_double, C.c_int64
+_SIGS = {
+    "wake_create": (_I, [C.POINTER(_P), C.POINTER(_Plasma), C.POINTER(_Domain), _P]),
+    "wake_add_beam": (_I, [_P, C.POINTER(_Source)]),
+    "wake_prepare": (_I, [_P]),
+    "wake_solve": (_I, [_P, _I, _I]),
+    "wake_fields": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _I]),
+    "wake_lineout": (_I, [_P, _P, _P, _I]),
+    "wake_get_state": (_I, [_P, C.POINTER(_I), _P, _P, _P, _P, _I]),
+    "wake_set_state": (_I, [_P, _I, _P, _P, _P, _P, _I]),
+    "wake_reset": (_I, [_P]),
+    "wake_status": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
+    "wake_sync": (_I, [_P]),
+    "wake_footprint": (_I64, [_I, _I, _I64, _I]),
+    "wake_destroy": (None, [_P]),
+    "wake_strerror": (C.c_char_p, [_I]),
+    "wake_tiling_count": (_I, []),
+    "wake_tiling_get": (_I, [_I, C.POINTER(_I), C.POINTER(_I)]),
+    "wake_set_tiling": (_I, [_I, _I]),
+    "wake_get_tiling": (_I, [C.POINTER(_I), C.POINTER(_I)]),
+    "wake_tiling_occupancy": (_I, [_I, _I]),
+    "wake_batch_create": (_I, [C.POINTER(_P), C.POINTER(_P), _I, _P]),
+    "wake_batch_solve": (_I, [_P, _I]),
+    "wake_batch_capture": (_I, [_P, _I]),
+    "wake_batch_replay": (_I, [_P]),
+    "wake_batch_sync": (_I, [_P]),
+    "wake_batch_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built: there is
+    no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2603_16623_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().wake_strerror(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != WAKE_OK:
+        raise WakeError(code, what)
+
+
+def _host(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _source_struct(src) -> tuple:
+    """Marshal one workload source object into a wake_source (keeps arrays alive)."""
+    s = _Source()
+    keep = []
+    kind = getattr(src, "kind")
+    if kind == "particles":
+        s.kind = WAKE_BEAM_PARTICLES
+        s.q = float(src.q)
+        arrs = [_host(getattr(src, f)) for f in ("x", "y", "xi", "w")]
+        s.n = len(arrs[0])
+        s.x, s.y, s.xi, s.w = (a.ctypes.data for a in arrs)
+        keep = arrs
+    elif kind == "gaussian":
+        s.kind = WAKE_BEAM_GAUSSIAN
+        s.q, s.n_peak = float(src.q), float(src.n_peak)
+        s.sigma_r, s.sigma_xi, s.xi_c = float(src.sigma_r), float(src.sigma_xi), float(src.xi_c)
+    elif kind == "laser":
+        s.kind = WAKE_LASER_GAUSSIAN
+        s.a0, s.w0, s.L, s.xi_l = float(src.a0), float(src.w0), float(src.L), float(src.xi_l)
+    else:
+        raise ValueError(f"unknown source kind {kind!r}")
+    return s, keep
+
+
+def wake_footprint(n_rings: int, n_xi: int, n_particles: int, record_stride: int = 0) -> int:
+    return int(load().wake_footprint(n_rings, n_xi, n_particles, record_stride))
+
+
+def wake_tiling_count() -> int:
+    return int(load().wake_tiling_count())
+
+
+def wake_tiling_get(i: int):
+    a, b = _I(), _I()
+    _check(load().wake_tiling_get(i, C.byref(a), C.byref(b)), "wake_tiling_get")
+    return a.value, b.value
+
+
+def wake_set_tiling(threads: int, rings_per_thread: int):
+    _check(load().wake_set_tiling(threads, rings_per_thread), "wake_set_tiling")
+
+
+def wake_get_tiling():
+    a, b = _I(), _I()
+    _check(load().wake_get_tiling(C.byref(a), C.byref(b)), "wake_get_tiling")
+    return a.value, b.value
+
+
+def wake_tiling_occupancy(threads: int, rings_per_thread: int) -> int:
+    r = int(load().wake_tiling_occupancy(threads, rings_per_thread))
+    if r < 0:
+        raise WakeError(r, "wake_tiling_occupancy")
+    return r
+
+
+class WakeSolver:
+    """One context: a ring column, a window and its sources."""
+
+    def __init__(self, r0, dr, dxi: float, n_xi: int, sources: Sequence = (), dens=None,
+                 record_stride: int = 0, stream: Optional[int] = None):
+        lib = load()
+        self._lib = lib
+        self.r0, self.dr = _host(r0), _host(dr)
+        self.dens = None if dens is None else _host(dens)
+        self.N, self.n_xi, self.dxi = len(self.r0), int(n_xi), float(dxi)
+        self.record_stride = int(record_stride)
+        pl = _Plasma(self.N, self.r0.ctypes.data, self.dr.ctypes.data,
+                     None if self.dens is None else self.dens.ctypes.data)
+        dm = _Domain(self.dxi, self.n_xi, self.record_stride)
+        h = _P()
+        _check(lib.wake_create(C.byref(h), C.byref(pl), C.byref(dm), stream), "wake_create")
+        self.h = h
+        for s in sources:
+            self.wake_add_beam(s)
+
+    @classmethod
+    def from_instance(cls, inst, record_stride: int = 0, stream=None):
+        return cls(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens,
+                   record_stride, stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._lib.wake_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def wake_add_beam(self, src):
+        s, keep = _source_struct(src)
+        _check(self._lib.wake_add_beam(self.h, C.byref(s)), "wake_add_beam")
+        del keep
+
+    def wake_prepare(self):
+        _check(self._lib.wake_prepare(self.h), "wake_prepare")
+
+    def wake_solve(self, first: int = 0, count: Optional[int] = None):
+        if count is None:
+            count = self.n_xi - first
+        _check(self._lib.wake_solve(self.h, first, count), "wake_solve")
+
+    def wake_sync(self):
+        _check(self._lib.wake_sync(self.h), "wake_sync")
+
+    def wake_reset(self):
+        _check(self._lib.wake_reset(self.h), "wake_reset")
+
+    def wake_status(self):
+        b, n = _I(), _I()
+        _check(self._lib.wake_status(self.h, C.byref(b), C.byref(n)), "wake_status")
+        return b.value, n.value
+
+    def wake_fields(self, slice_: int = -1, out=None, device: bool = False):
+        """dict of psi, er_bt, ez, bt, rho, ur (by ring id) at a slice."""
+        names = ("psi", "er_bt", "ez", "bt", "rho", "ur")
+        if out is None:
+            out = {k: np.empty(self.N) for k in names}
+        ptrs = [_ptr(out.get(k)) for k in names]
+        _check(self._lib.wake_fields(self.h, slice_, *ptrs, int(device)), "wake_fields")
+        return out
+
+    def wake_lineout(self):
+        psi, ez = np.empty(self.n_xi), np.empty(self.n_xi)
+        _check(self._lib.wake_lineout(self.h, psi.ctypes.data, ez.ctypes.data, 0), "wake_lineout")
+        return psi, ez
+
+    def wake_get_state(self):
+        names = ("rho", "ur", "f_rho", "f_u")
+        out = {k: np.empty(self.N) for k in names}
+        sl = _I()
+        _check(self._lib.wake_get_state(self.h, C.byref(sl), *[out[k].ctypes.data for k in names], 0),
+               "wake_get_state")
+        out["slice"] = sl.value
+        return out
+
+    def wake_set_state(self, slice_: int, rho, ur, f_rho=None, f_u=None):
+        arrs = [_host(rho), _host(ur), None if f_rho is None else _host(f_rho),
+                None if f_u is None else _host(f_u)]
+        _check(self._lib.wake_set_state(self.h, slice_, *[_ptr(a) for a in arrs], 0),
+               "wake_set_state")
+
+
+class WakeBatch:
+    """Many contexts marched by one persistent launch."""
+
+    def __init__(self, solvers: Sequence[WakeSolver], stream: Optional[int] = None):
+        lib = load()
+        self._lib = lib
+        self.solvers = list(solvers)
+        arr = (_P * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = _P()
+        _check(lib.wake_batch_create(C.byref(h), arr, len(self.solvers), stream), "wake_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._lib.wake_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def wake_batch_solve(self, n_slices: int = -1):
+        _check(self._lib.wake_batch_solve(self.h, n_slices), "wake_batch_solve")
+
+    def wake_batch_capture(self, grid: int = 0):
+        _check(self._lib.wake_batch_capture(self.h, grid), "wake_batch_capture")
+
+    def wake_batch_replay(self):
+        _check(self._lib.wake_batch_replay(self.h), "wake_batch_replay")
+
+    def wake_batch_sync(self):
+        _check(self._lib.wake_batch_sync(self.h), "wake_batch_sync")

@@ -35,12 +35,19 @@ def geometric_ratio(n: int, d_min: float, r_max: float) -> float:
     """Ratio g with d_min * (g**n - 1) / (g - 1) == r_max (bisection)."""
     if d_min * n >= r_max:
         raise ValueError("d_min * n already exceeds r_max")
-    lo, hi = 1.0 + 1e-15, 2.0
-    while d_min * (hi ** n - 1) / (hi - 1) < r_max:
-        hi = 1.0 + 2 * (hi - 1.0)
+
+    def extent(g):
+        x = n * math.log(g)
+        if x > 700.0:
+            return math.inf
+        return d_min * math.expm1(x) / (g - 1.0)
+
+    lo, hi = 1.0 + 1e-15, 1.0 + 1.0 / n
+    while extent(hi) < r_max:
+        hi = 1.0 + 2.0 * (hi - 1.0)
     for _ in range(200):
         mid = 0.5 * (lo + hi)
-        if d_min * math.expm1(n * math.log(mid)) / (mid - 1) < r_max:
+        if extent(mid) < r_max:
             lo = mid
         else:
             hi = mid

@@ -1,0 +1,332 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Per-slice cases feed both sides the identical ring state at slice n and
+compare the fields at n and the state pushed to n+1.  End-to-end cases
+compare whole marches (linear regime) to 1e-8.
+
+Tolerance reading.  Fields: max_i |gpu - oracle| <= 1e-12 * F_n, with F_n
+the slice's field scale: the largest magnitude among psi, E_r - B_theta,
+E_z, B_theta, the beam field B^(b) and the B_theta jumps C_i at that slice.
+B^(p) is assembled from the jumps C_i and can be orders of magnitude smaller
+than them (behind a linear driver, or under a weak laser), so it is measured
+against the scale of what it is computed from.  Ring state: elementwise,
+1e-12 of the largest magnitude of each quantity.  Both sides accumulate the
+cancelling Gauss/log sums beyond binary64, so what remains is O(1e-16)
+rounding times the O(1e2..1e3) cancellation of the B^(p) products.
+"""
+import numpy as np
+import pytest
+
+from oracle.wake_oracle import RingOracle
+from paper_2603_16623_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("psi", "er_bt", "ez", "bt")
+TOL_SLICE = 1e-12
+TOL_E2E = 1e-8
+
+
+@pytest.fixture(scope="module")
+def wk():
+    from paper_2603_16623_amd import wake
+    wake.load()
+    yield wake
+    wake.wake_set_tiling(256, 4)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel(gpu, ref, scale=None):
+    if scale is None:
+        scale = float(np.max(np.abs(ref))) if ref.size else 0.0
+    return float(np.max(np.abs(gpu - ref))) / (scale if scale > 0 else 1.0)
+
+
+def _field_tol(F):
+    """Absolute field tolerance of a slice: 1e-12 of its field scale, or the
+    unperturbed-plasma bound 1e-15 when every field vanishes."""
+    return TOL_SLICE * F if F > 0 else 1e-15
+
+
+def _field_scale(ref):
+    """Field scale F_n of one oracle slice (fields, beam field, B jumps)."""
+    parts = [np.abs(ref[q]).max() for q in FIELDS]
+    parts += [np.abs(ref["C"]).max(), np.abs(ref["bb"]).max(), abs(ref["psi_axis"]),
+              abs(ref["ez_axis"])]
+    return float(max(parts))
+
+
+def _oracle(inst):
+    return RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+
+
+def _advance(o, state, n0, n1):
+    for n in range(n0, n1):
+        _, state = o.slice(n, state)
+        assert state is not None
+    return state
+
+
+def _case(name):
+    if name == "blowout-geometric":
+        return W.small_instance(7, n_rings=300, n_xi=200, n_peak=4.0, sigma_r=0.1, dxi=0.01)
+    if name == "laser-beam":
+        return W.small_instance(8, n_rings=257, n_xi=200, n_peak=1.0, laser=True, dxi=0.01)
+    if name == "uniform-linear":
+        return W.config1(analytic=False, n_part=4000)
+    if name == "multitile-1200":
+        return W.small_instance(9, n_rings=1200, n_xi=150, n_peak=3.0, sigma_r=0.2, dxi=0.01)
+    raise KeyError(name)
+
+
+SLICE_CASES = [
+    ("blowout-geometric", (256, 4), (0, 1, 60, 130, 199)),
+    ("blowout-geometric", (256, 2), (0, 90, 150)),      # 300 rings, tile 512 (ragged)
+    ("laser-beam", (256, 4), (0, 40, 100, 170)),
+    ("uniform-linear", (256, 4), (0, 250, 700)),
+    ("multitile-1200", (256, 2), (0, 70, 120)),         # 3 tiles, ragged tail
+    ("multitile-1200", (512, 2), (100,)),
+    ("multitile-1200", (256, 8), (110,)),
+]
+
+
+@pytest.mark.parametrize("case,tiling,slices", SLICE_CASES)
+def test_slice_parity_on_identical_state(wk, case, tiling, slices):
+    inst = _case(case)
+    o = _oracle(inst)
+    wk.wake_set_tiling(*tiling)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    state = o.initial_state()
+    at = 0
+    for n in slices:
+        state = _advance(o, state, at, n)
+        at = n
+        ref, new = o.slice(n, state, push=n < inst.n_xi - 1, keep=True)
+        assert ref["status"] == 0
+        F = _field_scale(ref)
+        _say(f"slice parity {case} tiling={tiling} slice={n} N={inst.n_rings} F={F:.3e}")
+        s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(n, 1)
+        got = s.wake_fields(n)
+        for q in FIELDS:
+            e = float(np.max(np.abs(got[q] - ref[q])))
+            assert e <= _field_tol(F), (case, n, q, e, F)
+        assert np.array_equal(got["rho"], state["rho"])
+        if new is not None:
+            st = s.wake_get_state()
+            assert st["slice"] == n + 1
+            for a, b in (("rho", "rho"), ("ur", "u"), ("f_rho", "fr"), ("f_u", "fu")):
+                assert _rel(st[a], new[b]) <= TOL_SLICE, (case, n, a, _rel(st[a], new[b]))
+        lp, le = s.wake_lineout()
+        assert abs(lp[n] - ref["psi_axis"]) <= _field_tol(F)
+        assert abs(le[n] - ref["ez_axis"]) <= _field_tol(F)
+    s.close()
+
+
+def test_linear_end_to_end(wk):
+    """Linear-regime driver (1000 rings x 1200 slices, 10^4 particles)."""
+    wk.wake_set_tiling(256, 4)
+    inst = W.config1()
+    _say("e2e linear 1000x1200")
+    ref = _oracle(inst).run(record_stride=100)
+    s = wk.WakeSolver.from_instance(inst, record_stride=100)
+    s.wake_solve(0, inst.n_xi)
+    assert s.wake_status() == (-1, inst.n_xi)
+    lp, le = s.wake_lineout()
+    assert _rel(lp, ref["axis"][:, 0]) <= TOL_E2E
+    assert _rel(le, ref["axis"][:, 1]) <= TOL_E2E
+    for n in range(0, inst.n_xi, 100):
+        got = s.wake_fields(n)
+        for q in FIELDS:
+            assert _rel(got[q], ref["snap"][n][q]) <= TOL_E2E, (n, q)
+        assert _rel(got["rho"], ref["snap"][n]["rho"]) <= TOL_E2E
+        assert _rel(got["ur"], ref["snap"][n]["u"]) <= TOL_E2E
+    last = s.wake_fields(-1)
+    for q in FIELDS:
+        assert _rel(last[q], ref["snap"][inst.n_xi - 1][q]) <= TOL_E2E
+    s.close()
+
+
+def test_analytic_linear_end_to_end_and_closed_form_sign(wk):
+    inst = W.config1(analytic=True, n_peak=1e-3)
+    _say("e2e analytic linear")
+    ref = _oracle(inst).run(record_stride=0)
+    s = wk.WakeSolver.from_instance(inst)
+    s.wake_solve(0, inst.n_xi)
+    lp, le = s.wake_lineout()
+    assert _rel(le, ref["axis"][:, 1]) <= TOL_E2E
+    assert _rel(lp, ref["axis"][:, 0]) <= TOL_E2E
+    assert le[200] > 0   # the head of an electron driver decelerates it
+    s.close()
+
+
+def test_unperturbed_plasma_stays_at_rest(wk):
+    r0, dr = W.geometric_rings(700, 1e-3, 5.0)
+    _say("unperturbed 700 rings")
+    s = wk.WakeSolver(r0, dr, 0.01, 40, [], record_stride=1)
+    s.wake_solve(0, 40)
+    for n in (0, 17, 39):
+        f = s.wake_fields(n)
+        for q in FIELDS:
+            assert np.max(np.abs(f[q])) <= 1e-15, (n, q)
+    st = s.wake_get_state()
+    assert np.max(np.abs(st["rho"] - r0)) <= 1e-15 * r0.max()
+    assert np.max(np.abs(st["ur"])) <= 1e-15
+    s.close()
+
+
+def test_unsorted_injected_state_is_sorted_first(wk):
+    """Heavily crossed rings (a random state) give the same slice."""
+    rng = np.random.default_rng(21)
+    inst = W.small_instance(3, n_rings=500, n_xi=50, n_peak=2.0)
+    o = _oracle(inst)
+    state = o.initial_state()
+    state["rho"] = inst.r0 * np.exp(rng.normal(0, 0.2, inst.n_rings))
+    state["u"] = rng.normal(0, 0.1, inst.n_rings)
+    state["fr"] = rng.normal(0, 0.1, inst.n_rings)
+    state["fu"] = rng.normal(0, 0.1, inst.n_rings)
+    for tiling in ((256, 4), (256, 2)):
+        wk.wake_set_tiling(*tiling)
+        _say(f"unsorted state tiling={tiling}")
+        ref, new = o.slice(20, state, keep=True)
+        F = _field_scale(ref)
+        s = wk.WakeSolver.from_instance(inst, record_stride=1)
+        s.wake_set_state(20, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(20, 1)
+        got = s.wake_fields(20)
+        for q in FIELDS:
+            assert float(np.max(np.abs(got[q] - ref[q]))) <= _field_tol(F), (tiling, q)
+        st = s.wake_get_state()
+        assert _rel(st["rho"], new["rho"]) <= TOL_SLICE
+        assert _rel(st["ur"], new["u"]) <= TOL_SLICE
+        s.close()
+
+
+def test_breakdown_is_reported_at_the_same_slice(wk):
+    inst = W.small_instance(4, n_rings=200, n_xi=30, n_peak=1.0)
+    o = _oracle(inst)
+    state = o.initial_state()
+    state["rho"] = 0.5 * inst.r0          # compressed column: psibar < 0
+    ref, _ = o.slice(5, state)
+    assert ref["status"] == O_BREAKDOWN
+    _say("breakdown case")
+    wk.wake_set_tiling(256, 4)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    s.wake_set_state(5, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(5, 3)
+    assert s.wake_status()[0] == 5
+    with pytest.raises(wk.WakeError) as e:
+        s.wake_fields(5)
+    assert e.value.code == wk.WAKE_EBREAKDOWN
+    st = s.wake_get_state()
+    assert st["slice"] == 5
+    s.close()
+
+
+O_BREAKDOWN = -5
+
+
+def test_edge_sizes(wk):
+    """One ring; one slice; ragged first tile; no particles in the window."""
+    wk.wake_set_tiling(256, 4)
+    cases = []
+    r0, dr = W.uniform_rings(1, 2.0)
+    cases.append(("one ring", r0, dr, 0.05, 20, [W.GaussianBeam(-1.0, 0.5, 0.5, 0.3, 0.6)]))
+    r0, dr = W.uniform_rings(37, 3.0)
+    cases.append(("one slice", r0, dr, 0.05, 1, [W.GaussianBeam(-1.0, 0.5, 0.5, 0.3, 0.0)]))
+    rng = np.random.default_rng(2)
+    far = W.gaussian_particles(rng, 500, 1.0, 0.2, 0.1, 100.0)   # all beyond the window
+    r0, dr = W.geometric_rings(1025, 1e-3, 4.0)
+    cases.append(("ragged 1025", r0, dr, 0.02, 30, [far, W.GaussianBeam(-1.0, 2.0, 0.2, 0.2, 0.3)]))
+    for name, r0, dr, dxi, n_xi, src in cases:
+        _say(f"edge case {name}")
+        o = RingOracle(r0, dr, dxi, n_xi, src)
+        ref = o.run(record_stride=1)
+        s = wk.WakeSolver(r0, dr, dxi, n_xi, src, record_stride=1)
+        s.wake_solve(0, n_xi)
+        for n in range(0, n_xi, max(1, n_xi // 4)):
+            got = s.wake_fields(n)
+            for q in FIELDS:
+                assert _rel(got[q], ref["snap"][n][q]) <= 1e-10, (name, n, q)
+        s.close()
+
+
+def test_particle_radius_rounding_matches_numpy(wk):
+    """The beam table's radii are computed exactly like the oracle's
+    (sqrt(x*x + y*y), no contraction, correctly rounded sqrt): fields
+    agree on a slice where many particles sit near ring radii."""
+    rng = np.random.default_rng(5)
+    r0, dr = W.uniform_rings(400, 2.0)
+    p = W.gaussian_particles(rng, 20000, 1.0, 0.4, 0.05, 0.5)
+    o = RingOracle(r0, dr, 0.01, 60, [p])
+    ref = o.run(record_stride=1)
+    s = wk.WakeSolver(r0, dr, 0.01, 60, [p], record_stride=1)
+    s.wake_solve(0, 60)
+    for n in (45, 50, 55):
+        got = s.wake_fields(n)
+        assert _rel(got["bt"], ref["snap"][n]["bt"]) <= 1e-10
+    s.close()
+
+
+def test_batched_equals_alone_bitwise(wk):
+    wk.wake_set_tiling(256, 4)
+    rng = np.random.default_rng(44)
+    insts = [W.batched_instance(rng, n, 120, n_drv=3000, n_wit=1000, r_max=4.0)
+             for n in (300, 1500, 777, 64, 2100)]
+    _say("batched vs alone")
+    alone = []
+    for inst in insts:
+        s = wk.WakeSolver.from_instance(inst, record_stride=40)
+        s.wake_solve(0, inst.n_xi)
+        alone.append((s.wake_fields(40), s.wake_lineout(), s.wake_get_state()))
+        s.close()
+    solvers = [wk.WakeSolver.from_instance(inst, record_stride=40) for inst in insts]
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_solve(60)     # two chunks: continuous-batching style resume
+    b.wake_batch_solve(-1)
+    b.wake_batch_sync()
+    for s, (f, (lp, le), st) in zip(solvers, alone):
+        g = s.wake_fields(40)
+        for q in FIELDS:
+            assert np.array_equal(g[q], f[q]), q
+        glp, gle = s.wake_lineout()
+        assert np.array_equal(glp, lp) and np.array_equal(gle, le)
+        gst = s.wake_get_state()
+        assert np.array_equal(gst["rho"], st["rho"])
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_graph_replays_match_eager(wk):
+    wk.wake_set_tiling(256, 4)
+    rng = np.random.default_rng(45)
+    insts = [W.batched_instance(rng, n, 80, n_drv=2000, n_wit=500, r_max=4.0) for n in (200, 900, 450)]
+    _say("graph replay")
+    eager = []
+    for inst in insts:
+        s = wk.WakeSolver.from_instance(inst)
+        s.wake_solve(0, inst.n_xi)
+        eager.append((s.wake_lineout(), s.wake_get_state()["rho"]))
+        s.close()
+    solvers = [wk.WakeSolver.from_instance(inst) for inst in insts]
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_capture()
+    for rep in range(3):
+        b.wake_batch_replay()
+        b.wake_batch_sync()
+        for s, ((lp, le), rho) in zip(solvers, eager):
+            glp, gle = s.wake_lineout()
+            assert np.array_equal(gle, le), rep
+            assert np.array_equal(s.wake_get_state()["rho"], rho), rep
+        # eager work of the program between replays
+        x = wk.WakeSolver.from_instance(insts[0])
+        x.wake_solve(0, 10)
+        x.wake_sync()
+        x.close()
+    b.close()
+    for s in solvers:
+        s.close()

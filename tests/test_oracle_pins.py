@@ -80,7 +80,7 @@ def test_psi_family_matches_pairwise_sums():
     ion_dpsi.append(-Q / mpmath.mpf(Rp))
     ids = np.lexsort((np.arange(n), rho))
     psi, dpsi, axis = O.psi_family(rho[ids], w[ids], wh[ids],
-                                   O.IonNodes(r0, w, wh).finish(Rp))
+                                   O.IonNodes(r0, w, wh).finish(Rp), r0[ids])
     mp = mpmath.mpf
     scale = 0.0
     errs = []
