@@ -1,0 +1,210 @@
+"""Benchmark of the gridless ring solve on one MI355X.
+
+One step = one pass of the whole hot path over one batch: every instance of
+the batched workload (512 independent instances, ring counts log-uniform in
+[1000, 8000], geometric spacing from 1e-4 to r=8, driver + witness beams,
+2000 slices each) is reset to slice 0 and marched through its whole window
+by one persistent launch replayed from a HIP graph.  value = ring-slice
+updates per second over the timed steps (inputs resident in HBM).
+
+Also reported: the plain single-instance path (the same kernels, one
+instance per launch, instances of the same batch marched one after the
+other), the batched/plain ratio, the roofline of the march kernel from live
+HIP-event timings, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ring-slice updates/s batched+served vs plain (FP64, 1e-8 rel); p50/p99 latency"
+PEAK_FP64_VECTOR = 78.6e12       # FP64 vector FLOP/s of MI355X (256 CU x 2.4 GHz x 128)
+PEAK_HBM = 8.0e12                 # HBM3E bytes/s
+
+# Algorithmic work per ring-slice of the method (one ring, one slice), counted
+# from the sequential algorithm with double-double sums as their binary64
+# operations (two_sum 6, two_prod 2 with fma, dd add 20, dd mul-by-double 10,
+# dd divide-by-double 12); fma counts 2, divide and log1p/exp count 1.
+#   psi family  : w ln(rho) (log1p + dd add + dd mul 32), prefix dd sums (40),
+#                 psi_e (dd mul + dd add 30), d_rho psi_e (dd add + dd div 32),
+#                 ion interpolation (2 x (dd sub + dd mul + dd add) 100),
+#                 two roundings (2)                                       236
+#   local       : psibar, gamma, v, A                                     14
+#   d_zeta psi  : suffix sum and own term                                  4
+#   A, B, C, s  : coefficients and offset vector                          40
+#   recursion   : growing mode (M g, 8 with the matrix), decaying mode (8),
+#                 det[g,s], det[s,h] (6), prefix/suffix sums (2), x (10),
+#                 B^(p) (6)                                               40
+#   push        : forces (8), AB2 (8), next-slice ln rho (dd mul + add 31) 47
+ALG_FLOPS_PER_RING_SLICE = 236 + 14 + 4 + 40 + 40 + 47
+# Ring state that must be read and written once per slice (rho, u_r and the
+# two AB2 history terms, 8 B each, in and out) plus the per-ring constants
+# read (w, w^, ln r0 as double-double, r0: 40 B) and the id (4 B in, 4 B out).
+ALG_BYTES_PER_RING_SLICE = 32 + 32 + 40 + 8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_batch(wake, insts, stream):
+    solvers = [wake.WakeSolver.from_instance(inst, stream=stream) for inst in insts]
+    for s in solvers:
+        s.wake_prepare()
+    batch = wake.WakeBatch(solvers, stream=stream)
+    return solvers, batch
+
+
+def cpu_baseline(insts, budget_s: float = 15.0):
+    """Time the oracle on a bounded sample (whole instances, first slices)."""
+    from oracle.wake_oracle import RingOracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:                       # pragma: no cover
+        limiter = None
+    done = 0
+    t0 = time.perf_counter()
+    sample = []
+    for inst in insts:
+        o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources)
+        state = o.initial_state()
+        n = 0
+        while n < inst.n_xi - 1 and time.perf_counter() - t0 < budget_s:
+            _, state = o.slice(n, state)
+            n += 1
+            done += inst.n_rings
+        sample.append(f"{inst.n_rings} rings x {n} slices")
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return dict(value=done / dt, unit="ring-slice updates/s", cores=1, kind="oracle",
+                sample="oracle (numpy, 1 thread) on the first instances of the batch: "
+                       + "; ".join(sample) + f"; {done} ring-slices in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-inst", type=int, default=512)
+    ap.add_argument("--n-xi", type=int, default=2000)
+    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--tiling", type=str, default="")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the "
+              "batched instances would shard across GPUs with no exchange, but that "
+              "path is not built or measured here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_16623_amd import wake, workloads as W
+    wake.load()
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    # a stream of our own (default priority) made current, so that the
+    # library's launches and torch's timing events share one stream
+    tstream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(tstream)
+    stream = tstream.cuda_stream
+    if args.tiling:
+        nt, k = (int(x) for x in args.tiling.split(","))
+        wake.wake_set_tiling(nt, k)
+    nt, k = wake.wake_get_tiling()
+
+    log(f"building {args.n_inst} instances x {args.n_xi} slices")
+    insts = W.config3(n_inst=args.n_inst, n_xi=args.n_xi)
+    work = sum(i.ring_slices for i in insts)
+    solvers, batch = build_batch(wake, insts, stream)
+    batch.wake_batch_capture()
+    log("warmup")
+    for _ in range(args.warmup):
+        batch.wake_batch_replay()
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        batch.wake_batch_replay()
+        b.record()
+        log("step done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    breakdowns = sum(1 for s in solvers if s.wake_status()[0] >= 0)
+    value = work * args.steps / wall
+    avg_kernel_s = float(np.mean(kernel_ms)) / 1e3
+
+    # plain single-instance path: the same instances one launch at a time
+    log("plain path")
+    sample = insts[: args.plain_sample]
+    plain_solvers = [wake.WakeSolver.from_instance(i, stream=stream) for i in sample]
+    for s in plain_solvers:
+        s.wake_prepare()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for s in plain_solvers:
+        s.wake_solve(0, s.n_xi)
+    torch.cuda.synchronize()
+    tplain = time.perf_counter() - tp
+    plain_value = sum(i.ring_slices for i in sample) / tplain
+
+    flops = ALG_FLOPS_PER_RING_SLICE * work
+    achieved = flops / avg_kernel_s
+    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_VECTOR / 1e12,
+                unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR, traffic=None,
+                kernel="wake_march_kernel", kernel_ms=float(np.mean(kernel_ms)),
+                alg_flops_per_ring_slice=ALG_FLOPS_PER_RING_SLICE,
+                hbm_alg_GBps=ALG_BYTES_PER_RING_SLICE * work / avg_kernel_s / 1e9)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ring-slice updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched-{args.n_inst}x[1000,8000]rings-x{args.n_xi}slices",
+                   "instances": args.n_inst, "ring_slices_per_step": work,
+                   "tiling": [nt, k], "breakdowns": breakdowns},
+        "plain_single_instance": {"value": plain_value, "unit": "ring-slice updates/s",
+                                  "instances": len(sample)},
+        "batched_vs_plain": value / plain_value,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_budget)
+    batch.close()
+    for s in solvers + plain_solvers:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
