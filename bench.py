@@ -124,9 +124,9 @@ def main():
     torch.cuda.set_stream(tstream)
     stream = tstream.cuda_stream
     if args.tiling:
-        nt, k = (int(x) for x in args.tiling.split(","))
-        wake.wake_set_tiling(nt, k)
-    nt, k = wake.wake_get_tiling()
+        nt, wpc = (int(x) for x in args.tiling.split(","))
+        wake.wake_set_tiling(nt, wpc)
+    nt, wpc = wake.wake_get_tiling()
 
     log(f"building {args.n_inst} instances x {args.n_xi} slices")
     insts = W.config3(n_inst=args.n_inst, n_xi=args.n_xi)
@@ -191,7 +191,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batched-{args.n_inst}x[1000,8000]rings-x{args.n_xi}slices",
                    "instances": args.n_inst, "ring_slices_per_step": work,
-                   "tiling": [nt, k], "breakdowns": breakdowns},
+                   "tiling": {"threads": nt, "wgs_per_cu": wpc}, "breakdowns": breakdowns},
         "plain_single_instance": {"value": plain_value, "unit": "ring-slice updates/s",
                                   "instances": len(sample)},
         "batched_vs_plain": value / plain_value,

@@ -161,18 +161,21 @@ void wake_destroy(wake_ctx *ctx);
 const char *wake_strerror(int code);
 
 /* ---------------------------------------------------------------------
- * Tiling of the marcher: a workgroup of `threads` threads owns one
- * instance; each thread owns `rings_per_thread` consecutive rings of a
- * tile.  Instances larger than a tile are processed tile by tile.  The
- * available (threads, rings_per_thread) pairs are enumerated below; the
+ * Tiling of the marcher.  A workgroup of `threads` threads owns one instance;
+ * thread t owns the ceil(n_rings / threads) consecutive rings (in radial
+ * order) starting at t * ceil(n_rings / threads).  `threads` is fixed for a
+ * context when it is created (256, 512 or 1024).  Persistent launches place
+ * `wgs_per_cu` workgroups on each compute unit (0: as many as fit).  The
  * choice changes summation order only (results agree to rounding).
+ * wake_tiling_get returns the threads of entry `index` and how many such
+ * workgroups fit on one compute unit.
  * --------------------------------------------------------------------- */
 int wake_tiling_count(void);
-int wake_tiling_get(int32_t index, int32_t *threads, int32_t *rings_per_thread);
-int wake_set_tiling(int32_t threads, int32_t rings_per_thread);
-int wake_get_tiling(int32_t *threads, int32_t *rings_per_thread);
-/* resident workgroups per compute unit for a tiling (occupancy) */
-int wake_tiling_occupancy(int32_t threads, int32_t rings_per_thread);
+int wake_tiling_get(int32_t index, int32_t *threads, int32_t *wgs_per_cu);
+int wake_set_tiling(int32_t threads, int32_t wgs_per_cu);
+int wake_get_tiling(int32_t *threads, int32_t *wgs_per_cu);
+/* workgroups of `threads` threads resident per compute unit (occupancy) */
+int wake_tiling_occupancy(int32_t threads, int32_t wgs_per_cu);
 
 /* ---------------------------------------------------------------------
  * Batched form: many independent contexts (same device) marched by one

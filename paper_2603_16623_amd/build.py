@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwake.so")
-SOURCES = [os.path.join(CSRC, "wake_kernels.hip"), os.path.join(CSRC, "wake_api.cpp")]
+SOURCES = [os.path.join(CSRC, "wake_march.hip"), os.path.join(CSRC, "wake_beam.hip"),
+           os.path.join(CSRC, "wake_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -14,7 +14,8 @@
 
 namespace {
 
-int g_nt = 256, g_k = 4;   // marcher tiling used by new launches
+int g_nt = 512;      // workgroup threads of new contexts (slot layout)
+int g_wpc = 0;       // workgroups per compute unit of persistent launches (0: occupancy)
 
 struct Arena {
   char* base = nullptr;
@@ -28,40 +29,27 @@ struct Arena {
   }
 };
 
-struct Layout {
-  size_t bytes = 0;
-  int lut_n = 0;
-};
-
-int lut_size(int N, double Rp, double min_dr) {
-  double want = std::ceil(2.0 * Rp / min_dr);
-  double cap = 16.0 * N + 4096.0;
-  double lo = 2.0 * N;
-  double v = std::min(std::max(want, lo), cap);
-  return (int)v;
-}
-
-// Bytes of the per-context arena (must mirror carve()).
-size_t arena_bytes(int N, int n_xi, int stride, int lut_n) {
+// Bytes of the per-context arena (mirrors the carving in wake_create).
+// S = slots of the per-ring arrays (C * nt >= N).
+size_t arena_bytes(int N, int n_xi, int stride, int nt) {
+  const size_t C = (size_t)(N + nt - 1) / nt;
+  const size_t S = C * nt;
   const size_t n_rec = stride > 0 ? (size_t)(n_xi + stride - 1) / stride : 0;
-  const size_t tsc = (size_t)(N / 2 + 1024) * 5;
   size_t d = 0, i = 0;
-  d += 4 * (size_t)N;               // w, wh, ln r0 (dd)
-  d += 5 * (size_t)(N + 2);         // ion tables
-  d += 4;                           // tot0, Q
-  i += (size_t)lut_n + 1;           // lut
-  d += 8 * (size_t)N;               // rho, u, fr, fu x2
-  i += 2 * (size_t)N;               // id x2
-  d += WAKE_NSCR * (size_t)N;       // scratch
-  d += tsc;                         // tile scratch
-  d += 2 * (size_t)N;               // skey_r x2
-  i += 4 * (size_t)N;               // skey_i, skey_p x2
-  d += 2 * (size_t)n_xi;            // axis
-  d += n_rec * OUT_N * (size_t)N;   // snapshots
-  d += OUT_N * (size_t)N;           // last
-  i += CTL_NWORDS;                  // ctl
-  d += 4 * (size_t)N;               // staging
-  return d * 8 + i * 4 + 40 * 256;  // + alignment slack
+  d += 6 * (size_t)N;                       // w, wh, r0, 1/r0, ln r0 (dd)
+  d += WAKE_ION_REC * (size_t)(N + 1);      // ion interval records
+  d += 4;                                   // tot0, Q
+  d += 8 * S;                               // rho, u, fr, fu x2
+  i += 4 * S;                               // id, hint x2
+  d += 9 * S;                               // scratch
+  d += 2 * (size_t)N;                       // sort keys x2
+  i += 4 * (size_t)N + (size_t)N + S;       // sort ids/slots x2, free slots, flags
+  d += 2 * (size_t)n_xi;                    // axis
+  d += n_rec * OUT_N * (size_t)N;           // snapshots
+  d += OUT_N * (size_t)N;                   // last
+  i += CTL_NWORDS;                          // ctl
+  d += 4 * (size_t)N;                       // staging
+  return d * 8 + i * 4 + 64 * 256;          // + alignment slack
 }
 
 }  // namespace
@@ -120,8 +108,7 @@ extern "C" const char* wake_strerror(int code) {
 extern "C" int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles,
                                   int32_t record_stride) {
   if (n_rings <= 0 || n_xi <= 0 || n_particles < 0 || record_stride < 0) return -1;
-  const int lut_n = 16 * n_rings + 4096;
-  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, lut_n);
+  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, g_nt);
   // persistent beam table: offsets + (r, cumulative charge) per entry
   b += 4 * (int64_t)(n_xi + 1) + 16 * 2 * n_particles + 1024;
   // transient build buffers (particles, counts, padded entries)
@@ -185,10 +172,11 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
   I.stride = dom->record_stride;
   I.dxi = dom->dxi;
   I.Rp = plasma->r0[N - 1] + plasma->dr[N - 1] / 2.0;
-  I.lut_n = lut_size(N, I.Rp, min_dr);
-  I.lut_scale = (double)I.lut_n / I.Rp;
   I.inv2pidxi = 1.0 / (2.0 * M_PI * I.dxi);
-  const size_t bytes = arena_bytes(N, I.n_xi, I.stride, I.lut_n);
+  I.nt = g_nt;
+  I.C = (N + g_nt - 1) / g_nt;
+  const size_t S = (size_t)I.C * I.nt;
+  const size_t bytes = arena_bytes(N, I.n_xi, I.stride, I.nt);
   hipError_t e = hipMalloc(&c->arena.base, bytes);
   if (e != hipSuccess) { c->arena.base = nullptr; release(c); return dev_err(e); }
   c->arena.size = bytes;
@@ -196,29 +184,36 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
   const size_t n_rec = I.stride > 0 ? (size_t)(I.n_xi + I.stride - 1) / I.stride : 0;
   I.w = A.take<double>(N);
   I.wh = A.take<double>(N);
-  I.L0_hi = A.take<double>(N);
-  I.L0_lo = A.take<double>(N);
-  I.ion_r = A.take<double>(N + 2);
-  I.ion_dp_hi = A.take<double>(N + 2);
-  I.ion_dp_lo = A.take<double>(N + 2);
-  I.ion_ps_hi = A.take<double>(N + 2);
-  I.ion_ps_lo = A.take<double>(N + 2);
+  I.r0 = A.take<double>(N);
+  I.ir0 = A.take<double>(N);
+  I.L0h = A.take<double>(N);
+  I.L0l = A.take<double>(N);
+  I.ion = A.take<double>((size_t)WAKE_ION_REC * (N + 1));
   I.tot0 = A.take<double>(4);
-  I.ion_lut = A.take<int32_t>(I.lut_n + 1);
   for (int b = 0; b < 2; ++b) {
-    I.rho[b] = A.take<double>(N);
-    I.u[b] = A.take<double>(N);
-    I.fr[b] = A.take<double>(N);
-    I.fu[b] = A.take<double>(N);
-    I.id[b] = A.take<int32_t>(N);
+    I.rho[b] = A.take<double>(S);
+    I.u[b] = A.take<double>(S);
+    I.fr[b] = A.take<double>(S);
+    I.fu[b] = A.take<double>(S);
+    I.id[b] = A.take<int32_t>(S);
+    I.hint[b] = A.take<int32_t>(S);
   }
-  I.scr = A.take<double>((size_t)WAKE_NSCR * N);
-  I.tscr = A.take<double>((size_t)(N / 2 + 1024) * 5);
+  I.lnh = A.take<double>(S);
+  I.lnl = A.take<double>(S);
+  I.psi = A.take<double>(S);
+  I.dpsi = A.take<double>(S);
+  I.bb = A.take<double>(S);
+  I.a2 = A.take<double>(S);
+  I.da2 = A.take<double>(S);
+  I.g0 = A.take<double>(S);
+  I.g1 = A.take<double>(S);
   for (int b = 0; b < 2; ++b) {
-    I.skey_r[b] = A.take<double>(N);
-    I.skey_i[b] = A.take<int32_t>(N);
-    I.skey_p[b] = A.take<int32_t>(N);
+    I.sk_r[b] = A.take<double>(N);
+    I.sk_i[b] = A.take<int32_t>(N);
+    I.sk_s[b] = A.take<int32_t>(N);
   }
+  I.free_slot = A.take<int32_t>(N);
+  I.flag = A.take<int32_t>(S);
   I.axis = A.take<double>(2 * (size_t)I.n_xi);
   I.snap = n_rec ? A.take<double>(n_rec * OUT_N * N) : nullptr;
   I.last = A.take<double>((size_t)OUT_N * N);
@@ -356,7 +351,7 @@ extern "C" int wake_prepare(wake_ctx* c) {
   std::vector<double>().swap(c->pxi);
   std::vector<double>().swap(c->pw);
   std::vector<double>().swap(c->pq);
-  HIP_TRY(march_prepare(g_nt, g_k));
+  HIP_TRY(march_prepare(I.nt));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->prepared = true;
   return WAKE_OK;
@@ -383,7 +378,7 @@ static int launch_one(wake_ctx* c, int first, int count) {
   I.first = first;
   I.count = count;
   HIP_TRY(hipMemcpyAsync(c->d_inst, &I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_march(g_nt, g_k, c->d_inst, 1, c->d_counter, 1, c->stream));
+  HIP_TRY(launch_march(I.nt, c->d_inst, 1, c->d_counter, 1, c->stream));
   return WAKE_OK;
 }
 
@@ -528,46 +523,50 @@ extern "C" int wake_reset(wake_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// tiling
+// tiling: workgroup threads (fixed per context at creation) and workgroups
+// per compute unit of persistent launches
 // ---------------------------------------------------------------------------
-extern "C" int wake_tiling_count(void) { return march_config_count(); }
+static const int kThreads[] = {256, 512, 1024};
 
-extern "C" int wake_tiling_get(int32_t idx, int32_t* nt, int32_t* k) {
-  int a, b;
-  if (!nt || !k || march_config(idx, &a, &b) != 0) return WAKE_EINVAL;
-  *nt = a;
-  *k = b;
+extern "C" int wake_tiling_count(void) { return 3; }
+
+extern "C" int wake_tiling_get(int32_t idx, int32_t* nt, int32_t* wpc) {
+  if (!nt || !wpc || idx < 0 || idx >= 3) return WAKE_EINVAL;
+  *nt = kThreads[idx];
+  *wpc = march_occupancy(kThreads[idx]);
   return WAKE_OK;
 }
 
-static bool tiling_ok(int nt, int k) {
-  for (int i = 0; i < march_config_count(); ++i) {
-    int a, b;
-    march_config(i, &a, &b);
-    if (a == nt && b == k) return true;
-  }
-  return false;
-}
-
-extern "C" int wake_set_tiling(int32_t nt, int32_t k) {
-  if (!tiling_ok(nt, k)) return WAKE_EINVAL;
-  HIP_TRY(march_prepare(nt, k));
+extern "C" int wake_set_tiling(int32_t nt, int32_t wpc) {
+  if (!march_threads_ok(nt) || wpc < 0 || wpc > 32) return WAKE_EINVAL;
+  HIP_TRY(march_prepare(nt));
   g_nt = nt;
-  g_k = k;
+  g_wpc = wpc;
   return WAKE_OK;
 }
 
-extern "C" int wake_get_tiling(int32_t* nt, int32_t* k) {
-  if (!nt || !k) return WAKE_EINVAL;
+extern "C" int wake_get_tiling(int32_t* nt, int32_t* wpc) {
+  if (!nt || !wpc) return WAKE_EINVAL;
   *nt = g_nt;
-  *k = g_k;
+  *wpc = g_wpc;
   return WAKE_OK;
 }
 
-extern "C" int wake_tiling_occupancy(int32_t nt, int32_t k) {
-  if (!tiling_ok(nt, k)) return WAKE_EINVAL;
-  if (march_prepare(nt, k) != hipSuccess) return WAKE_EDEVICE;
-  return march_occupancy(nt, k);
+extern "C" int wake_tiling_occupancy(int32_t nt, int32_t wpc) {
+  (void)wpc;
+  if (!march_threads_ok(nt)) return WAKE_EINVAL;
+  if (march_prepare(nt) != hipSuccess) return WAKE_EDEVICE;
+  return march_occupancy(nt);
+}
+
+// persistent grid for nt-thread workgroups
+static int march_grid(int nt, int n_insts, int dev) {
+  const int occ = std::max(1, march_occupancy(nt));
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+    cu = 1;
+  const int wpc = g_wpc > 0 ? std::min(g_wpc, occ) : occ;
+  return std::max(1, std::min(n_insts, wpc * cu));
 }
 
 // ---------------------------------------------------------------------------
@@ -621,12 +620,6 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
   return WAKE_OK;
 }
 
-static int device_cus(int dev) {
-  int cu = 0;
-  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  return cu > 0 ? cu : 1;
-}
-
 // Fill the device descriptor array with (first, count) per instance, longest
 // first.  Returns the number of instances with work.
 static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vector<WakeInst>& v) {
@@ -647,6 +640,22 @@ static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vec
   return (int)v.size();
 }
 
+// one persistent launch per distinct workgroup size present in v (v is
+// sorted longest-first; each launch takes the instances of its size)
+static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v, int grid_override) {
+  int off = 0;
+  for (int nt : kThreads) {
+    int n = 0;
+    for (const WakeInst& I : v) n += I.nt == nt;
+    if (n == 0) continue;
+    (void)off;
+    const int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, b->device);
+    hipError_t e = launch_march(nt, b->d_insts, (int)v.size(), b->d_counter, g, b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
   if (!b) return WAKE_EINVAL;
   HIP_TRY(hipSetDevice(b->device));
@@ -658,9 +667,7 @@ extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
   const int n = batch_stage(b, n_slices, false, v);
   if (n == 0) return WAKE_OK;
   HIP_TRY(hipMemcpyAsync(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice, b->stream));
-  const int occ = std::max(1, march_occupancy(g_nt, g_k));
-  const int grid = std::min(n, occ * device_cus(b->device));
-  HIP_TRY(launch_march(g_nt, g_k, b->d_insts, n, b->d_counter, grid, b->stream));
+  HIP_TRY(batch_launch(b, v, 0));
   for (wake_ctx* c : b->ctxs) {
     int count = c->I.n_xi - c->next;
     if (n_slices >= 0) count = std::min(count, (int)n_slices);
@@ -683,13 +690,10 @@ extern "C" int wake_batch_capture(wake_batch* b, int32_t grid) {
   HIP_TRY(hipMemcpy(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice));
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-  const int occ = std::max(1, march_occupancy(g_nt, g_k));
-  int g = grid > 0 ? grid : occ * device_cus(b->device);
-  g = std::min(g, n);
   HIP_TRY(hipStreamSynchronize(b->stream));
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = launch_reset(b->d_insts, n, b->stream);
-  if (e == hipSuccess) e = launch_march(g_nt, g_k, b->d_insts, n, b->d_counter, g, b->stream);
+  if (e == hipSuccess) e = batch_launch(b, v, grid);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {

@@ -5,13 +5,16 @@
 
 #define WAKE_MAX_ANALYTIC 8   // analytic beams + lasers per instance
 #define WAKE_BCAP 2048        // beam-table entries staged in LDS per chunk
-#define WAKE_NSCR 9           // per-ring scratch arrays of the multi-tile path
-
-// Scratch array slots (multi-tile path), each [N] doubles by sorted position.
-enum { SC_PSI = 0, SC_DPSI, SC_BB, SC_G0, SC_G1, SC_E0, SC_E1, SC_A2, SC_DA2 };
+#define WAKE_SORTCAP 2048     // out-of-place rings sorted in LDS in one piece
+#define WAKE_ION_REC 8        // doubles per ion interval record
 
 // Control words of one instance (device memory, int32).
 enum { CTL_CUR = 0, CTL_BREAK = 1, CTL_NEXT = 2, CTL_NWORDS = 4 };
+
+// Ion interval record j (j = 0..N), nodes 0 = axis, j = r0[j-1], N+1 = R_p:
+// [node_j, node_{j+1}), psi-psi(0) at node j (dd), its step to node j+1,
+// d_rho psi at node j (dd), its step.
+enum { IR_LO = 0, IR_HI, IR_PSH, IR_PSL, IR_DPS, IR_DPH, IR_DPL, IR_DDP };
 
 struct WakeAnalytic {
   int32_t kind;     // 2 = bi-Gaussian beam, 3 = Gaussian laser envelope
@@ -21,6 +24,10 @@ struct WakeAnalytic {
 };
 
 // One instance as the kernels see it.  All pointers are device pointers.
+// Per-ring arrays in "slot" order: the ring at sorted position p sits in slot
+// (p % C) * nt + p / C, so that thread t of an nt-thread workgroup, which
+// owns positions [t*C, t*C + C), reads its k-th ring at slot k*nt + t and a
+// wavefront's accesses are contiguous.
 struct WakeInst {
   int32_t N;          // rings
   int32_t n_xi;       // slices of the window
@@ -29,35 +36,35 @@ struct WakeInst {
   int32_t stride;     // snapshot every `stride` slices (0: none)
   int32_t n_an;       // analytic sources
   int32_t has_laser;  // any laser among the analytic sources
-  int32_t lut_n;      // buckets of the ion-node lookup table
+  int32_t nt;         // workgroup threads of the slot layout
+  int32_t C;          // rings per thread, ceil(N / nt)
   int32_t nb;         // beam-table entries
-  int32_t pad;
-  double dxi, Rp, Q, lut_scale;   // lut_scale = lut_n / Rp
-  double inv2pidxi;               // 1 / (2 pi dxi)
+  double dxi, Rp, inv2pidxi;
   WakeAnalytic an[WAKE_MAX_ANALYTIC];
-  // constants by ring id: weight, modified weight, ln r0 (double-double)
-  const double *w, *wh;
-  const double *L0_hi, *L0_lo;
-  // ion nodes (N+2): radius, d_rho psi (dd), psi - psi(0) (dd)
-  const double *ion_r, *ion_dp_hi, *ion_dp_lo, *ion_ps_hi, *ion_ps_lo;
-  const double *tot0;             // [2]: sum_j w_j ln r0_j (dd)
-  const int32_t *ion_lut;         // [lut_n + 1]
+  // per-ring constants by ring id: weight, modified weight, r0, 1/r0,
+  // ln r0 (double-double)
+  const double *w, *wh, *r0, *ir0, *L0h, *L0l;
+  const double *ion;          // [N+1][WAKE_ION_REC]
+  const double *tot0;         // [4]: sum_j w_j ln r0_j (dd), total weight Q (dd)
   // beam table (CSR over slices)
-  const int32_t *boff;            // [n_xi + 1]
-  const double *br, *bcum;        // [nb]
-  // ring state, two buffers, by sorted position
+  const int32_t *boff;        // [n_xi + 1]
+  const double *br, *bcum;    // [nb]
+  // ring state, two buffers, slot order
   double *rho[2], *u[2], *fr[2], *fu[2];
-  int32_t *id[2];
-  // multi-tile scratch
-  double *scr;                    // [WAKE_NSCR][N]
-  double *tscr;                   // [tiles][threads][5]
-  double *skey_r[2];              // [N] global merge buffers (multi-tile sort)
-  int32_t *skey_i[2], *skey_p[2];
+  int32_t *id[2], *hint[2];
+  // scratch, slot order: ln rho (dd), psi, d_rho psi, B^(b), laser |a|^2
+  // and d_rho|a|^2, growing mode g_{i-1} (2)
+  double *lnh, *lnl, *psi, *dpsi, *bb, *a2, *da2, *g0, *g1;
+  // sort scratch: out-of-place keys (two ping-pong buffers), free slots,
+  // per-slot flags
+  double *sk_r[2];
+  int32_t *sk_i[2], *sk_s[2];
+  int32_t *free_slot, *flag;
   // outputs
-  double *axis;                   // [n_xi][2]: psi(0), E_z(0)
-  double *snap;                   // [n_rec][6][N] by ring id
-  double *last;                   // [6][N] by ring id: last marched slice
-  int32_t *ctl;                   // [CTL_NWORDS]
+  double *axis;               // [n_xi][2]: psi(0), E_z(0)
+  double *snap;               // [n_rec][6][N] by ring id
+  double *last;               // [6][N] by ring id: last marched slice
+  int32_t *ctl;               // [CTL_NWORDS]
 };
 
 // Quantities of a snapshot, in this order: psi, E_r - B_theta, E_z,

@@ -157,6 +157,7 @@ __device__ __forceinline__ Pack<NF> block_prefix(const Pack<NF>& x, const Pack<N
   }
   __syncthreads();
   Pack<NF> pre = ident, tot;
+  #pragma unroll 1
   for (int w = 0; w < NW; ++w) {
     Pack<NF> s;
 #pragma unroll
@@ -191,6 +192,7 @@ __device__ __forceinline__ Pack<NF> block_suffix(const Pack<NF>& x, const Pack<N
   }
   __syncthreads();
   Pack<NF> suf = ident, tot;
+  #pragma unroll 1
   for (int w = NW - 1; w >= 0; --w) {
     Pack<NF> s;
 #pragma unroll
@@ -201,6 +203,65 @@ __device__ __forceinline__ Pack<NF> block_suffix(const Pack<NF>& x, const Pack<N
   __syncthreads();
   total = tot;
   return op(ex, suf);
+}
+
+// A prefix (in thread order, opP(earlier, later)) of xp and a suffix
+// (opS(lower, higher)) of xs in one pass: one pair of barriers for both.
+// `lds` holds NT/64 * (NP + NS) doubles.
+template <int NT, int NP, int NS, class OpP, class OpS>
+__device__ __forceinline__ void block_prefix_suffix(const Pack<NP>& xp, const Pack<NP>& idP, OpP opP,
+                                                    const Pack<NS>& xs, const Pack<NS>& idS, OpS opS,
+                                                    double* lds, Pack<NP>& exP, Pack<NP>& totP,
+                                                    Pack<NS>& exS, Pack<NS>& totS) {
+  constexpr int NW = NT / 64;
+  constexpr int NF = NP + NS;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  Pack<NP> ip = xp;
+  Pack<NS> is = xs;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    Pack<NP> o = shfl_up_pack(ip, d);
+    Pack<NS> q = shfl_down_pack(is, d);
+    if (lane >= d) ip = opP(o, ip);
+    if (lane + d < 64) is = opS(is, q);
+  }
+  Pack<NP> ep = shfl_up_pack(ip, 1);
+  Pack<NS> es = shfl_down_pack(is, 1);
+  if (lane == 0) ep = idP;
+  if (lane == 63) es = idS;
+  if (lane == 63) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) lds[wv * NF + i] = ip.v[i];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) lds[wv * NF + NP + i] = is.v[i];
+  }
+  __syncthreads();
+  Pack<NP> pre = idP, tp;
+  Pack<NS> suf = idS, ts;
+  #pragma unroll 1
+  for (int w = 0; w < NW; ++w) {
+    Pack<NP> a;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) a.v[i] = lds[w * NF + i];
+    if (w < wv) pre = opP(pre, a);
+    tp = (w == 0) ? a : opP(tp, a);
+  }
+  #pragma unroll 1
+  for (int w = NW - 1; w >= 0; --w) {
+    Pack<NS> a;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) a.v[i] = lds[w * NF + NP + i];
+    if (w > wv) suf = opS(a, suf);
+    ts = (w == NW - 1) ? a : opS(a, ts);
+  }
+  __syncthreads();
+  exP = opP(pre, ep);
+  totP = tp;
+  exS = opS(es, suf);
+  totS = ts;
 }
 
 // sums of packs (commutative), used with the scans above

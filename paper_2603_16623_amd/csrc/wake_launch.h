@@ -1,6 +1,7 @@
-// Host-callable kernel launchers (defined in wake_kernels.hip).
+// Host-callable kernel launchers (defined in wake_march.hip, wake_beam.hip).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include "wake_common.h"
 
 hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, const double* dens,
@@ -16,9 +17,10 @@ hipError_t launch_state_set(const WakeInst& I, const double* rho, const double* 
                             const double* fu, int slice, hipStream_t s);
 hipError_t launch_reset(const WakeInst* d_insts, int n_insts, hipStream_t s);
 
-int march_config_count();
-int march_config(int idx, int* nt, int* k);
-hipError_t launch_march(int nt, int k, const WakeInst* d_insts, int n_insts, int32_t* counter,
-                        int grid, hipStream_t s);
-int march_occupancy(int nt, int k);
-hipError_t march_prepare(int nt, int k);
+// marcher: workgroups of nt threads (256, 512 or 1024)
+bool march_threads_ok(int nt);
+size_t march_lds_bytes(int nt);
+hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int32_t* counter, int grid,
+                        hipStream_t s);
+int march_occupancy(int nt);
+hipError_t march_prepare(int nt);

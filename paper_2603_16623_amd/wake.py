@@ -154,8 +154,10 @@ def wake_tiling_get(i: int):
     return a.value, b.value
 
 
-def wake_set_tiling(threads: int, rings_per_thread: int):
-    _check(load().wake_set_tiling(threads, rings_per_thread), "wake_set_tiling")
+def wake_set_tiling(threads: int, wgs_per_cu: int = 0):
+    """Workgroup threads for contexts created from now on, and workgroups per
+    compute unit of persistent launches (0: as many as fit)."""
+    _check(load().wake_set_tiling(threads, wgs_per_cu), "wake_set_tiling")
 
 
 def wake_get_tiling():
@@ -164,8 +166,8 @@ def wake_get_tiling():
     return a.value, b.value
 
 
-def wake_tiling_occupancy(threads: int, rings_per_thread: int) -> int:
-    r = int(load().wake_tiling_occupancy(threads, rings_per_thread))
+def wake_tiling_occupancy(threads: int, wgs_per_cu: int = 0) -> int:
+    r = int(load().wake_tiling_occupancy(threads, wgs_per_cu))
     if r < 0:
         raise WakeError(r, "wake_tiling_occupancy")
     return r

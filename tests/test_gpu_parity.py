@@ -32,7 +32,7 @@ def wk():
     from paper_2603_16623_amd import wake
     wake.load()
     yield wake
-    wake.wake_set_tiling(256, 4)
+    wake.wake_set_tiling(512, 0)
 
 
 def _say(*a):
@@ -82,16 +82,17 @@ def _case(name):
     raise KeyError(name)
 
 
+# tiling = (threads per workgroup, workgroups per compute unit); each thread
+# owns ceil(N / threads) consecutive rings
 SLICE_CASES = [
-    ("blowout-geometric", (256, 4), (0, 1, 60, 130, 199)),
-    ("blowout-geometric", (256, 2), (0, 90, 150)),      # 300 rings, tile 512 (ragged)
-    ("laser-beam", (256, 4), (0, 40, 100, 170)),
-    ("uniform-linear", (256, 4), (0, 250, 700)),
-    ("multitile-1200", (256, 2), (0, 70, 120)),         # 3 tiles, ragged tail
-    ("multitile-1200", (512, 2), (100,)),
-    ("multitile-1200", (256, 8), (110,)),
+    ("blowout-geometric", (256, 0), (0, 1, 60, 130, 199)),   # 300 rings: 2 per thread, ragged
+    ("blowout-geometric", (1024, 0), (0, 90, 150)),          # 1 ring per thread, idle threads
+    ("laser-beam", (512, 0), (0, 40, 100, 170)),
+    ("uniform-linear", (512, 0), (0, 250, 700)),
+    ("multitile-1200", (256, 0), (0, 70, 120)),              # 5 rings per thread
+    ("multitile-1200", (512, 0), (100,)),
+    ("multitile-1200", (1024, 0), (110,)),
 ]
-
 
 @pytest.mark.parametrize("case,tiling,slices", SLICE_CASES)
 def test_slice_parity_on_identical_state(wk, case, tiling, slices):
@@ -128,7 +129,7 @@ def test_slice_parity_on_identical_state(wk, case, tiling, slices):
 
 def test_linear_end_to_end(wk):
     """Linear-regime driver (1000 rings x 1200 slices, 10^4 particles)."""
-    wk.wake_set_tiling(256, 4)
+    wk.wake_set_tiling(512, 0)
     inst = W.config1()
     _say("e2e linear 1000x1200")
     ref = _oracle(inst).run(record_stride=100)
@@ -188,7 +189,7 @@ def test_unsorted_injected_state_is_sorted_first(wk):
     state["u"] = rng.normal(0, 0.1, inst.n_rings)
     state["fr"] = rng.normal(0, 0.1, inst.n_rings)
     state["fu"] = rng.normal(0, 0.1, inst.n_rings)
-    for tiling in ((256, 4), (256, 2)):
+    for tiling in ((512, 0), (256, 0)):
         wk.wake_set_tiling(*tiling)
         _say(f"unsorted state tiling={tiling}")
         ref, new = o.slice(20, state, keep=True)
@@ -213,7 +214,7 @@ def test_breakdown_is_reported_at_the_same_slice(wk):
     ref, _ = o.slice(5, state)
     assert ref["status"] == O_BREAKDOWN
     _say("breakdown case")
-    wk.wake_set_tiling(256, 4)
+    wk.wake_set_tiling(512, 0)
     s = wk.WakeSolver.from_instance(inst, record_stride=1)
     s.wake_set_state(5, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(5, 3)
@@ -231,7 +232,7 @@ O_BREAKDOWN = -5
 
 def test_edge_sizes(wk):
     """One ring; one slice; ragged first tile; no particles in the window."""
-    wk.wake_set_tiling(256, 4)
+    wk.wake_set_tiling(512, 0)
     cases = []
     r0, dr = W.uniform_rings(1, 2.0)
     cases.append(("one ring", r0, dr, 0.05, 20, [W.GaussianBeam(-1.0, 0.5, 0.5, 0.3, 0.6)]))
@@ -272,7 +273,7 @@ def test_particle_radius_rounding_matches_numpy(wk):
 
 
 def test_batched_equals_alone_bitwise(wk):
-    wk.wake_set_tiling(256, 4)
+    wk.wake_set_tiling(512, 0)
     rng = np.random.default_rng(44)
     insts = [W.batched_instance(rng, n, 120, n_drv=3000, n_wit=1000, r_max=4.0)
              for n in (300, 1500, 777, 64, 2100)]
@@ -302,7 +303,7 @@ def test_batched_equals_alone_bitwise(wk):
 
 
 def test_graph_replays_match_eager(wk):
-    wk.wake_set_tiling(256, 4)
+    wk.wake_set_tiling(512, 0)
     rng = np.random.default_rng(45)
     insts = [W.batched_instance(rng, n, 80, n_drv=2000, n_wit=500, r_max=4.0) for n in (200, 900, 450)]
     _say("graph replay")
