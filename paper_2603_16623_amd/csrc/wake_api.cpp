@@ -36,14 +36,16 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
   const size_t S = C * nt;
   const size_t n_rec = stride > 0 ? (size_t)(n_xi + stride - 1) / stride : 0;
   size_t d = 0, i = 0;
-  d += 6 * (size_t)N;                       // w, wh, r0, 1/r0, ln r0 (dd)
+  d += 6 * S;                               // w, wh, r0, 1/r0, ln r0 (dd) by home slot
   d += WAKE_ION_REC * (size_t)(N + 1);      // ion interval records
   d += 4;                                   // tot0, Q
-  d += 8 * S;                               // rho, u, fr, fu x2
-  i += 4 * S;                               // id, hint x2
-  d += 9 * S;                               // scratch
+  d += 12 * S;                              // rho, u, fr, fu, ln rho (dd) x2
+  i += 4 * S;                               // home slot, hint x2
+  d += 5 * S;                               // slice scratch
+  d += 1 * S;                               // fix-up: suffix minimum
+  i += 3 * S;                               // fix-up: suffix min id, flags, classes
   d += 2 * (size_t)N;                       // sort keys x2
-  i += 4 * (size_t)N + (size_t)N + S;       // sort ids/slots x2, free slots, flags
+  i += 4 * (size_t)N + (size_t)N;           // sort ids/slots x2, free slots
   d += 2 * (size_t)n_xi;                    // axis
   d += n_rec * OUT_N * (size_t)N;           // snapshots
   d += OUT_N * (size_t)N;                   // last
@@ -182,12 +184,12 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
   c->arena.size = bytes;
   Arena& A = c->arena;
   const size_t n_rec = I.stride > 0 ? (size_t)(I.n_xi + I.stride - 1) / I.stride : 0;
-  I.w = A.take<double>(N);
-  I.wh = A.take<double>(N);
-  I.r0 = A.take<double>(N);
-  I.ir0 = A.take<double>(N);
-  I.L0h = A.take<double>(N);
-  I.L0l = A.take<double>(N);
+  I.w = A.take<double>(S);
+  I.wh = A.take<double>(S);
+  I.r0 = A.take<double>(S);
+  I.ir0 = A.take<double>(S);
+  I.L0h = A.take<double>(S);
+  I.L0l = A.take<double>(S);
   I.ion = A.take<double>((size_t)WAKE_ION_REC * (N + 1));
   I.tot0 = A.take<double>(4);
   for (int b = 0; b < 2; ++b) {
@@ -195,25 +197,26 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
     I.u[b] = A.take<double>(S);
     I.fr[b] = A.take<double>(S);
     I.fu[b] = A.take<double>(S);
-    I.id[b] = A.take<int32_t>(S);
+    I.hs[b] = A.take<int32_t>(S);
     I.hint[b] = A.take<int32_t>(S);
+    I.lnh[b] = A.take<double>(S);
+    I.lnl[b] = A.take<double>(S);
   }
-  I.lnh = A.take<double>(S);
-  I.lnl = A.take<double>(S);
   I.psi = A.take<double>(S);
   I.dpsi = A.take<double>(S);
   I.bb = A.take<double>(S);
   I.a2 = A.take<double>(S);
   I.da2 = A.take<double>(S);
-  I.g0 = A.take<double>(S);
-  I.g1 = A.take<double>(S);
+  I.sm_r = A.take<double>(S);
+  I.sm_i = A.take<int32_t>(S);
+  I.flag = A.take<int32_t>(S);
+  I.cls = A.take<int32_t>(S);
   for (int b = 0; b < 2; ++b) {
     I.sk_r[b] = A.take<double>(N);
     I.sk_i[b] = A.take<int32_t>(N);
     I.sk_s[b] = A.take<int32_t>(N);
   }
   I.free_slot = A.take<int32_t>(N);
-  I.flag = A.take<int32_t>(S);
   I.axis = A.take<double>(2 * (size_t)I.n_xi);
   I.snap = n_rec ? A.take<double>(n_rec * OUT_N * N) : nullptr;
   I.last = A.take<double>((size_t)OUT_N * N);

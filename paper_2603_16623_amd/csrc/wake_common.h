@@ -4,8 +4,9 @@
 #include <stdint.h>
 
 #define WAKE_MAX_ANALYTIC 8   // analytic beams + lasers per instance
-#define WAKE_BCAP 2048        // beam-table entries staged in LDS per chunk
-#define WAKE_SORTCAP 2048     // out-of-place rings sorted in LDS in one piece
+#define WAKE_BCAP 2048        // beam-table entries staged in LDS per slice
+#define WAKE_SORTCAP 2048     // rings of long disordered runs sorted in LDS in one piece
+#define WAKE_SEGMAX 64        // disordered runs up to this length are ranked in place
 #define WAKE_ION_REC 8        // doubles per ion interval record
 
 // Control words of one instance (device memory, int32).
@@ -24,10 +25,24 @@ struct WakeAnalytic {
 };
 
 // One instance as the kernels see it.  All pointers are device pointers.
-// Per-ring arrays in "slot" order: the ring at sorted position p sits in slot
-// (p % C) * nt + p / C, so that thread t of an nt-thread workgroup, which
-// owns positions [t*C, t*C + C), reads its k-th ring at slot k*nt + t and a
-// wavefront's accesses are contiguous.
+//
+// Slot layout.  A workgroup of nt threads owns the instance; thread t owns
+// the C = ceil(N / nt) consecutive sorted positions [t*C, t*C + C).  Per-ring
+// arrays are stored by slot: position p sits in slot (p % C) * nt + p / C,
+// so that thread t reads its k-th ring at slot k*nt + t and the lanes of a
+// wavefront touch consecutive addresses.
+//
+// Home slot.  Ring id i has home slot hs(i) = (i % C) * nt + i / C, the slot
+// of position i; its constants (weights, r0, ln r0) are stored at hs(i).
+// The state stores hs instead of the id (id = (hs % nt) * C + hs / nt), so
+// that while rings stay near their initial order the constant gathers of a
+// wavefront stay contiguous.
+//
+// Order.  Rings are kept in (rho, id) order.  When the keys of every
+// position fit in LDS, a slice whose pushed radii come out of order only
+// computes the new order as a permutation (sorted position -> slot) in LDS;
+// the next slice reads through it and writes its pushed rings in the new
+// order.  Otherwise the buffer itself is reordered in global memory.
 struct WakeInst {
   int32_t N;          // rings
   int32_t n_xi;       // slices of the window
@@ -41,7 +56,7 @@ struct WakeInst {
   int32_t nb;         // beam-table entries
   double dxi, Rp, inv2pidxi;
   WakeAnalytic an[WAKE_MAX_ANALYTIC];
-  // per-ring constants by ring id: weight, modified weight, r0, 1/r0,
+  // per-ring constants by home slot: weight, modified weight, r0, 1/r0,
   // ln r0 (double-double)
   const double *w, *wh, *r0, *ir0, *L0h, *L0l;
   const double *ion;          // [N+1][WAKE_ION_REC]
@@ -49,17 +64,23 @@ struct WakeInst {
   // beam table (CSR over slices)
   const int32_t *boff;        // [n_xi + 1]
   const double *br, *bcum;    // [nb]
-  // ring state, two buffers, slot order
+  // ring state by slot, two buffers: rho, u_r, AB2 history, home slot,
+  // ion-interval search hint, ln rho (dd).  A slice reads the rings of its
+  // sorted positions from the current buffer (through the order permutation)
+  // and writes them to the slots of those positions in the other buffer.
   double *rho[2], *u[2], *fr[2], *fu[2];
-  int32_t *id[2], *hint[2];
-  // scratch, slot order: ln rho (dd), psi, d_rho psi, B^(b), laser |a|^2
-  // and d_rho|a|^2, growing mode g_{i-1} (2)
-  double *lnh, *lnl, *psi, *dpsi, *bb, *a2, *da2, *g0, *g1;
-  // sort scratch: out-of-place keys (two ping-pong buffers), free slots,
-  // per-slot flags
+  int32_t *hs[2], *hint[2];
+  double *lnh[2], *lnl[2];
+  // slice scratch by position slot: psi, d_rho psi, B^(b), laser |a|^2 and
+  // d_rho |a|^2
+  double *psi, *dpsi, *bb, *a2, *da2;
+  // order fix-up scratch in global memory: running suffix minimum key, run
+  // boundaries and classes, long-run sort keys
+  double *sm_r;
+  int32_t *sm_i, *flag, *cls;
   double *sk_r[2];
   int32_t *sk_i[2], *sk_s[2];
-  int32_t *free_slot, *flag;
+  int32_t *free_slot;
   // outputs
   double *axis;               // [n_xi][2]: psi(0), E_z(0)
   double *snap;               // [n_rec][6][N] by ring id

@@ -136,8 +136,10 @@ __device__ __forceinline__ Pack<NF> shfl_down_pack(const Pack<NF>& p, int d) {
 
 // Exclusive prefix over the workgroup in thread order.  op(earlier, later)
 // must be associative; ident must satisfy op(ident, x) == x exactly.
-// `lds` holds NT/64 packs.  Every thread also receives the total.
-template <int NT, int NF, class Op>
+// `lds` holds NT/64 packs.  Every thread also receives the total.  With
+// TAIL = false the closing barrier is left out: the caller must not write
+// `lds` again before another barrier has been passed by every thread.
+template <int NT, int NF, class Op, bool TAIL = true>
 __device__ __forceinline__ Pack<NF> block_prefix(const Pack<NF>& x, const Pack<NF>& ident, Op op,
                                                  double* lds, Pack<NF>& total) {
   constexpr int NW = NT / 64;
@@ -165,7 +167,7 @@ __device__ __forceinline__ Pack<NF> block_prefix(const Pack<NF>& x, const Pack<N
     if (w < wv) pre = op(pre, s);
     tot = (w == 0) ? s : op(tot, s);
   }
-  __syncthreads();
+  if (TAIL) __syncthreads();
   total = tot;
   return op(pre, ex);
 }
@@ -207,8 +209,8 @@ __device__ __forceinline__ Pack<NF> block_suffix(const Pack<NF>& x, const Pack<N
 
 // A prefix (in thread order, opP(earlier, later)) of xp and a suffix
 // (opS(lower, higher)) of xs in one pass: one pair of barriers for both.
-// `lds` holds NT/64 * (NP + NS) doubles.
-template <int NT, int NP, int NS, class OpP, class OpS>
+// `lds` holds NT/64 * (NP + NS) doubles.  TAIL as for block_prefix.
+template <int NT, int NP, int NS, class OpP, class OpS, bool TAIL = true>
 __device__ __forceinline__ void block_prefix_suffix(const Pack<NP>& xp, const Pack<NP>& idP, OpP opP,
                                                     const Pack<NS>& xs, const Pack<NS>& idS, OpS opS,
                                                     double* lds, Pack<NP>& exP, Pack<NP>& totP,
@@ -257,7 +259,7 @@ __device__ __forceinline__ void block_prefix_suffix(const Pack<NP>& xp, const Pa
     if (w > wv) suf = opS(a, suf);
     ts = (w == NW - 1) ? a : opS(a, ts);
   }
-  __syncthreads();
+  if (TAIL) __syncthreads();
   exP = opP(pre, ep);
   totP = tp;
   exS = opS(es, suf);

@@ -10,27 +10,38 @@
 // B_theta^(p) (eq. ai_bi, b_0 = 0, a_N = 0) and the Adams-Bashforth-2 push
 // (eqs. motion_1-2).
 //
+// The recursion x_i = M_i x_{i-1} + s_i (x = (a, b), det M_i = 1) is solved
+// in Green's-function form: with the growing mode g (g_0 = (1, 0),
+// g_i = M_i g_{i-1}), the decaying mode h (h_N = (0, 1), h_{i-1} = M_i^-1
+// h_i) and W = det[g, h] = a-part of g_N,
+//   x_i = (h_i E_i - g_i D_i) / W,  E_i = sum_{j<=i} det[g_j, s_j],
+//                                    D_i = sum_{j>i}  det[s_j, h_j].
+// It solves the same linear system as the paper's shooting (Appendix "Solve
+// recursive system") without its exponential loss of digits.
+//
 // One workgroup owns one instance and marches its slices; thread t owns the
 // C = ceil(N / NT) consecutive sorted positions [t*C, t*C + C), stored in
-// slots k*NT + t (coalesced).  Per slice:
-//   loop B (forward)  psi, d_rho psi from a double-double prefix of
-//                     (w, w ln rho); sources; psibar, gamma, A_i, transfer
-//                     matrix M_i; per-thread product of M_i and sum of v_i
-//   scan              prefix of the products (growing mode g, g_0 = (1,0))
-//                     and of v; suffix of the inverse products (decaying
-//                     mode h, h_N = (0,1)) and of v
-//   loop C (forward)  g_{i-1} stored; sums of det[g_i, s_i], with s_i affine
-//                     in the total V = sum v (s = s0 + V s1)
-//   loop D (backward) d_zeta psi, B_i, s_i, sum of det[s_i, h_i]
-//   scan              prefix of the det[g, s] sums, suffix of det[s, h]
-//   loop E (backward) x_{i-1} = (h_{i-1} E_{i-1} - g_{i-1} D_{i-1}) / W,
-//                     W = det[g, h] = a-part of g_N; B^(p), outputs, AB2
-//                     push, ln rho of the pushed radius for the next slice.
-// This variation-of-parameters form solves the same linear system as the
-// paper's shooting (Appendix "Solve recursive system") without its
-// exponential loss of digits.  If the pushed radii are out of order, the
-// rings that are not already in their final place are compacted, sorted
-// and dropped into the freed positions (every other ring keeps its slot).
+// slots k*NT + t (coalesced).  Two passes over the rings per slice:
+//   pass B (forward)  psi, d_rho psi from a double-double prefix of
+//                     (w, w ln rho); sources; psibar, gamma, A_i, M_i; the
+//                     chunk product G of the M_i and the chunk sum of v_i;
+//                     lambda = sum_i G_i^T J s_i with G_i the product up to
+//                     ring i and J s = (s_b, -s_a), split as lambda0 +
+//                     c lambda1 because s_i is affine in the one unknown
+//                     c = -(v of this chunk and every later one).
+//   scan              prefix of (G, v) (g at the chunk start), suffix of
+//                     (G^-1, v) (h at the chunk end).  The chunk's sums are
+//                     then det-sums without another pass:
+//                     sum det[g_i, s_i] = g_start . lambda,
+//                     sum det[s_i, h_i] = -(G^-1 h_end) . lambda.
+//   scan              prefix of the det[g, s] sums, suffix of det[s, h].
+//   pass E (backward) s_i again, g and h stepped back by M_i^-1, x_{i-1},
+//                     B^(p), outputs, AB2 push, ln rho of the pushed radius.
+// If the pushed radii are out of order, runs of positions that must be
+// permuted among themselves are found (a run boundary sits where every key
+// before is below every key after); short runs are ranked in place, the
+// rings of long runs are compacted, sorted and dropped into their freed
+// positions.
 #include "wake_common.h"
 #include "wake_device.h"
 #include "wake_launch.h"
@@ -79,6 +90,10 @@ __device__ __forceinline__ Pack<4> rec_matrix(double A, double rho, double irho)
   return {{1.0 + h, 0.5 * A * irho, -h * rho * rho, 1.0 - h}};
 }
 
+__device__ __forceinline__ Pack<4> mat_adj(const Pack<4>& m) {
+  return {{m.v[3], -m.v[1], -m.v[2], m.v[0]}};
+}
+
 // a / b for double-double a with a precomputed reciprocal ib = 1/b
 __device__ __forceinline__ dd dd_div_rcp(dd a, double b, double ib) {
   _Pragma("clang fp contract(off)")
@@ -88,12 +103,21 @@ __device__ __forceinline__ dd dd_div_rcp(dd a, double b, double ib) {
   return fast_two_sum(q1, q2);
 }
 
-// ln(rho) of ring `id` as ln r0 + log1p((rho - r0)/r0): its rounding scales
-// with the ring's displacement, not with |ln rho| (the psi sums multiply
-// ln rho by the enclosed charge).
-__device__ __forceinline__ dd ring_log(const WakeInst& I, int id, double rho) {
-  const double l1 = log1p((rho - I.r0[id]) * I.ir0[id]);
-  return dd_add_d({I.L0h[id], I.L0l[id]}, l1);
+// ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
+// rounding scales with the ring's displacement, not with |ln rho| (the psi
+// sums multiply ln rho by the enclosed charge).
+__device__ __forceinline__ dd ring_log(const WakeInst& I, unsigned hs, double rho) {
+  const double l1 = log1p((rho - I.r0[hs]) * I.ir0[hs]);
+  return dd_add_d({I.L0h[hs], I.L0l[hs]}, l1);
+}
+
+template <int NT>
+__device__ __forceinline__ int32_t id_of(int32_t hs, int C) {
+  return (hs & (NT - 1)) * C + (hs >> __builtin_ctz(NT));
+}
+
+__device__ __forceinline__ unsigned slot_of(int p, int C, int nt) {
+  return (unsigned)((p % C) * nt + p / C);
 }
 
 // Ion psi - psi(0) and d_rho psi at radius r: linear interpolation inside
@@ -148,6 +172,34 @@ __device__ __forceinline__ void ion_fields(const WakeInst& I, double r, dd lnr, 
   dp = dd_add_d({rec[IR_DPH], rec[IR_DPL]}, t * rec[IR_DDP]);
 }
 
+// Number of entries of the ascending table br[0..m) below r, given that
+// the first lo entries are below r: galloping from lo (gallop) or a plain
+// binary search of [lo, m).
+__device__ __forceinline__ int count_below(const double* br, int lo, int m, double r, bool gallop) {
+  int a, b;
+  if (gallop) {
+    if (lo >= m || !(br[lo] < r)) return lo;
+    a = lo;                            // br[a] < r
+    int step = 1;
+    for (;;) {
+      b = a + step;
+      if (b >= m) { b = m; break; }
+      if (!(br[b] < r)) break;
+      a = b;
+      step <<= 1;
+    }
+    a += 1;                            // answer in [a, b]
+  } else {
+    a = lo;
+    b = m;
+  }
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (br[mid] < r) a = mid + 1; else b = mid;
+  }
+  return a;
+}
+
 // ---------------------------------------------------------------------------
 // ring-set initialisation: weights, ln r0, ion interval records, state
 // ---------------------------------------------------------------------------
@@ -180,8 +232,9 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
       w = nd * r * d;                              // eq. macroparticle_weight
       wh = w / 2.0 - nd * d * d / 8.0;             // modified weight
       lr = dd_log(r);
-      w_out[j] = w; wh_out[j] = wh; r0_out[j] = r; ir0_out[j] = 1.0 / r;
-      l0h[j] = lr.hi; l0l[j] = lr.lo;
+      const unsigned hs = slot_of(j, I.C, I.nt);   // home slot of ring j
+      w_out[hs] = w; wh_out[hs] = wh; r0_out[hs] = r; ir0_out[hs] = 1.0 / r;
+      l0h[hs] = lr.hi; l0l[hs] = lr.lo;
     }
     const dd wl = dd_mul_d(lr, w);
     Pack<4> tot;
@@ -198,9 +251,9 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
       rec[IR_PSH] = ps.hi; rec[IR_PSL] = ps.lo;
       rec[IR_DPH] = dp.hi; rec[IR_DPL] = dp.lo;
       // initial state: position j holds ring j; its interval starts at its node
-      const int sl = (j % I.C) * I.nt + j / I.C;
+      const unsigned sl = slot_of(j, I.C, I.nt);
       I.rho[0][sl] = r; I.u[0][sl] = 0.0; I.fr[0][sl] = 0.0; I.fu[0][sl] = 0.0;
-      I.id[0][sl] = j; I.hint[0][sl] = j + 1;
+      I.hs[0][sl] = (int32_t)sl; I.hint[0][sl] = j + 1;
     }
     cS = dd_add(cS, {tot.v[0], tot.v[1]});
     cPT = dd_add(cPT, {tot.v[2], tot.v[3]});
@@ -235,7 +288,7 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
 }
 
 // ---------------------------------------------------------------------------
-// ring order fix-up
+// ring order
 // ---------------------------------------------------------------------------
 struct MaxKeyOp {   // (rho, id) maximum
   __device__ __forceinline__ Pack<2> operator()(const Pack<2>& a, const Pack<2>& b) const {
@@ -318,24 +371,44 @@ __device__ int sort_keys_global(const WakeInst& I, int M, double* kr, int32_t* k
   return src;
 }
 
-// Put buffer `buf` in (rho, id) order.  Rings that are already in their
-// final position (key above every key before and below every key after)
-// keep their slot; the others are compacted in position order, sorted, and
-// written into the freed positions.  Moves the state and the ln rho scratch;
-// `tmp` is the other state buffer (free at this point).  Uniform result:
-// true if any ring moved.
+// Runs.  A run boundary sits before position p when every key before p is
+// below every key from p on; the rings between consecutive boundaries are
+// permuted among themselves.  Runs of one ring stay; runs of up to
+// WAKE_SEGMAX rings are ranked by counting; the rings of longer runs are
+// compacted, sorted together and placed into their freed positions in order
+// (each long run keeps its position range, so the j-th smallest goes to the
+// j-th freed position).
+
+// Copy the ring at slot `src` of buffer `buf` into slot `dst` of buffer tmp.
+__device__ __forceinline__ void stage_move(const WakeInst& I, int buf, int tmp, unsigned src,
+                                           unsigned dst) {
+  I.rho[tmp][dst] = I.rho[buf][src];
+  I.u[tmp][dst] = I.u[buf][src];
+  I.fr[tmp][dst] = I.fr[buf][src];
+  I.fu[tmp][dst] = I.fu[buf][src];
+  I.hs[tmp][dst] = I.hs[buf][src];
+  I.hint[tmp][dst] = I.hint[buf][src];
+  I.lnh[tmp][dst] = I.lnh[buf][src];
+  I.lnl[tmp][dst] = I.lnl[buf][src];
+}
+
+// Order fix-up in global memory (instances whose keys do not fit in LDS):
+// puts buffer `buf` itself in (rho, id) order, moving the rings through the
+// other buffer `tmp`.
 template <int NT>
-__device__ __noinline__ bool fix_order(const WakeInst& I, int buf, int tmp, double* s_scan,
-                                       unsigned char* region) {
+__device__ __noinline__ void fix_order_global(const WakeInst& I, int buf, int tmp, double* s_scan,
+                                              unsigned char* region) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C;
   const int cnt = max(0, min(C, N - tid * C));
+  const double* R = I.rho[buf];
+  const int32_t* HS = I.hs[buf];
   // chunk extremes
   Pack<2> mx = {{-INFINITY, -2147483648.0}}, mn = {{INFINITY, 2147483647.0}};
   #pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
-    const int sl = k * NT + tid;
-    const Pack<2> key = {{I.rho[buf][sl], (double)I.id[buf][sl]}};
+    const unsigned sl = k * NT + tid;
+    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
     mx = MaxKeyOp()(mx, key);
     mn = MinKeyOp()(mn, key);
   }
@@ -343,79 +416,244 @@ __device__ __noinline__ bool fix_order(const WakeInst& I, int buf, int tmp, doub
   block_prefix_suffix<NT, 2, 2>(mx, Pack<2>{{-INFINITY, -2147483648.0}}, MaxKeyOp(), mn,
                                 Pack<2>{{INFINITY, 2147483647.0}}, MinKeyOp(), s_scan, before, tb,
                                 after, ta);
-  // below every later key (backward), above every earlier key (forward)
+  // minimum key from each position on
   Pack<2> sm = after;
   #pragma unroll 1
   for (int k = cnt - 1; k >= 0; --k) {
-    const int sl = k * NT + tid;
-    const Pack<2> key = {{I.rho[buf][sl], (double)I.id[buf][sl]}};
-    I.flag[sl] = key_lt(key.v[0], (int32_t)key.v[1], sm.v[0], (int32_t)sm.v[1]) ? 1 : 0;
+    const unsigned sl = k * NT + tid;
+    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
     sm = MinKeyOp()(sm, key);
+    I.sm_r[sl] = sm.v[0];
+    I.sm_i[sl] = (int32_t)sm.v[1];
   }
+  // run boundaries
   Pack<2> pm = before;
-  double oop = 0.0;
   #pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
-    const int sl = k * NT + tid;
-    const Pack<2> key = {{I.rho[buf][sl], (double)I.id[buf][sl]}};
-    const bool ok = I.flag[sl] && key_lt(pm.v[0], (int32_t)pm.v[1], key.v[0], (int32_t)key.v[1]);
-    I.flag[sl] = ok ? 1 : 0;
-    if (!ok) oop += 1.0;
+    const unsigned sl = k * NT + tid;
+    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
+    const bool bnd = (tid == 0 && k == 0) ||
+                     key_lt(pm.v[0], (int32_t)pm.v[1], I.sm_r[sl], I.sm_i[sl]);
+    I.flag[sl] = bnd ? 1 : 0;
     pm = MaxKeyOp()(pm, key);
   }
-  Pack<1> tot;
-  const Pack<1> j0p = block_prefix<NT, 1>(Pack<1>{{oop}}, Pack<1>{{0.0}}, SumOp<1>(), s_scan, tot);
-  const int M = (int)tot.v[0];
-  if (M == 0) return false;
-  const bool in_lds = M <= WAKE_SORTCAP;
-  double* kr = reinterpret_cast<double*>(region);
-  int32_t* ki = reinterpret_cast<int32_t*>(kr + WAKE_SORTCAP);
-  int32_t* ks = ki + WAKE_SORTCAP;
-  int j = (int)j0p.v[0];
+  __syncthreads();
+  // classify: 0 = in place, 1 = short run (ranked here), 2 = long run
+  double nlong = 0.0;
   #pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
-    const int sl = k * NT + tid;
-    if (I.flag[sl]) continue;
-    I.free_slot[j] = sl;
-    const double r = I.rho[buf][sl];
-    const int32_t id = I.id[buf][sl];
-    if (in_lds) { kr[j] = r; ki[j] = id; ks[j] = sl; }
-    else { I.sk_r[0][j] = r; I.sk_i[0][j] = id; I.sk_s[0][j] = sl; }
-    ++j;
+    const int p = tid * C + k;
+    const unsigned sl = k * NT + tid;
+    const bool b0 = I.flag[sl] != 0;
+    const bool b1 = p + 1 >= N || I.flag[slot_of(p + 1, C, NT)] != 0;
+    int cls = 0;
+    if (!(b0 && b1)) {
+      int a = p;
+      while (p - a < WAKE_SEGMAX && I.flag[slot_of(a, C, NT)] == 0) --a;
+      int e = p + 1;
+      while (e - p <= WAKE_SEGMAX && e < N && I.flag[slot_of(e, C, NT)] == 0) ++e;
+      const bool closed = I.flag[slot_of(a, C, NT)] != 0 && (e >= N || I.flag[slot_of(e, C, NT)] != 0);
+      if (closed && e - a <= WAKE_SEGMAX) {
+        cls = 1;
+        const double r = R[sl];
+        const int32_t id = id_of<NT>(HS[sl], C);
+        int rank = 0;
+        #pragma unroll 1
+        for (int q = a; q < e; ++q) {
+          const unsigned sq = slot_of(q, C, NT);
+          if (key_lt(R[sq], id_of<NT>(HS[sq], C), r, id)) ++rank;
+        }
+        stage_move(I, buf, tmp, sl, slot_of(a + rank, C, NT));
+      } else {
+        cls = 2;
+        nlong += 1.0;
+      }
+    }
+    I.cls[sl] = cls;
   }
-  __syncthreads();
-  const double* Kr;
-  const int32_t* Ki;
-  const int32_t* Ks;
-  if (in_lds) {
-    int P = 1;
-    while (P < M) P <<= 1;
-    for (int i = M + tid; i < P; i += NT) { kr[i] = INFINITY; ki[i] = 0x7fffffff - i; ks[i] = -1; }
+  Pack<1> tot;
+  const Pack<1> j0p = block_prefix<NT, 1>(Pack<1>{{nlong}}, Pack<1>{{0.0}}, SumOp<1>(), s_scan, tot);
+  const int M = (int)tot.v[0];
+  if (M > 0) {
+    const bool in_lds = M <= WAKE_SORTCAP;
+    double* kr = reinterpret_cast<double*>(region);
+    int32_t* ki = reinterpret_cast<int32_t*>(kr + WAKE_SORTCAP);
+    int32_t* ks = ki + WAKE_SORTCAP;
+    int j = (int)j0p.v[0];
+    #pragma unroll 1
+    for (int k = 0; k < cnt; ++k) {
+      const unsigned sl = k * NT + tid;
+      if (I.cls[sl] != 2) continue;
+      I.free_slot[j] = (int32_t)sl;
+      const double r = R[sl];
+      const int32_t id = id_of<NT>(HS[sl], C);
+      if (in_lds) { kr[j] = r; ki[j] = id; ks[j] = (int32_t)sl; }
+      else { I.sk_r[0][j] = r; I.sk_i[0][j] = id; I.sk_s[0][j] = (int32_t)sl; }
+      ++j;
+    }
     __syncthreads();
-    bitonic_keys<NT>(kr, ki, ks, P);
-    Kr = kr; Ki = ki; Ks = ks;
-  } else {
-    const int b = sort_keys_global<NT>(I, M, kr, ki, ks);
-    Kr = I.sk_r[b]; Ki = I.sk_i[b]; Ks = I.sk_s[b];
-  }
-  // j-th smallest out-of-place ring -> j-th freed position (via tmp)
-  for (int q = tid; q < M; q += NT) {
-    const int src = Ks[q], dst = I.free_slot[q];
-    I.rho[tmp][dst] = Kr[q]; I.id[tmp][dst] = Ki[q];
-    I.u[tmp][dst] = I.u[buf][src]; I.fr[tmp][dst] = I.fr[buf][src]; I.fu[tmp][dst] = I.fu[buf][src];
-    I.hint[tmp][dst] = I.hint[buf][src];
-    I.g0[dst] = I.lnh[src]; I.g1[dst] = I.lnl[src];
-  }
-  __syncthreads();
-  for (int q = tid; q < M; q += NT) {
-    const int dst = I.free_slot[q];
-    I.rho[buf][dst] = I.rho[tmp][dst]; I.id[buf][dst] = I.id[tmp][dst];
-    I.u[buf][dst] = I.u[tmp][dst]; I.fr[buf][dst] = I.fr[tmp][dst]; I.fu[buf][dst] = I.fu[tmp][dst];
-    I.hint[buf][dst] = I.hint[tmp][dst];
-    I.lnh[dst] = I.g0[dst]; I.lnl[dst] = I.g1[dst];
+    const int32_t* Ks;
+    if (in_lds) {
+      int P = 1;
+      while (P < M) P <<= 1;
+      for (int i = M + tid; i < P; i += NT) { kr[i] = INFINITY; ki[i] = 0x7fffffff - i; ks[i] = -1; }
+      __syncthreads();
+      bitonic_keys<NT>(kr, ki, ks, P);
+      Ks = ks;
+    } else {
+      const int b = sort_keys_global<NT>(I, M, kr, ki, ks);
+      Ks = I.sk_s[b];
+    }
+    // j-th smallest ring of the long runs -> j-th freed position
+    for (int q = tid; q < M; q += NT) stage_move(I, buf, tmp, (unsigned)Ks[q], (unsigned)I.free_slot[q]);
   }
   __syncthreads();
-  return true;
+  #pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const unsigned sl = k * NT + tid;
+    if (I.cls[sl] == 0) continue;
+    stage_move(I, tmp, buf, sl, sl);
+  }
+  __syncthreads();
+}
+
+// LDS index (slot form) of position p: (p % C) * NT + p / C, with p / C from
+// a float estimate corrected to the exact quotient (p < 2^24).
+template <int NT>
+__device__ __forceinline__ int pos_index(int p, int C, float iC) {
+  int q = (int)((float)p * iC);
+  if (q * C > p) --q;
+  else if ((q + 1) * C <= p) ++q;
+  return (p - q * C) * NT + q;
+}
+
+struct MaxIntOp {
+  __device__ __forceinline__ Pack<1> operator()(const Pack<1>& a, const Pack<1>& b) const {
+    return a.v[0] < b.v[0] ? b : a;
+  }
+};
+struct MinIntOp {
+  __device__ __forceinline__ Pack<1> operator()(const Pack<1>& a, const Pack<1>& b) const {
+    return b.v[0] < a.v[0] ? b : a;
+  }
+};
+
+// Order fix-up in LDS (C <= CMAX).  The keys of the rings at every position
+// are in LDS in slot form (position (t, k) of thread t at index k*NT + t):
+// kr (radius), ki (id).  Builds perm[k*NT + t] = slot, in the current buffer,
+// of the ring at sorted position (t, k).  Nothing in global memory moves.
+// Run boundaries come from register prefix maxima, run extents from a scan
+// of the first and last boundary of each chunk; short runs are ranked by
+// counting, long runs sorted together.
+template <int NT, int CMAX>
+__device__ __noinline__ void fix_order_lds(const WakeInst& I, double* s_scan, double* s_scan2,
+                                           unsigned char* region, const double* kr,
+                                           const uint16_t* ki, uint16_t* zf, uint16_t* perm) {
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C;
+  const float iC = 1.0f / (float)C;
+  const int p0 = tid * C;
+  const int cnt = max(0, min(C, N - p0));
+  Pack<2> mx = {{-INFINITY, -2147483648.0}}, mn = {{INFINITY, 2147483647.0}};
+  double pr[CMAX];
+  int32_t pi[CMAX];      // maximum key before each position of the chunk
+#pragma unroll
+  for (int k = 0; k < CMAX; ++k) {
+    if (k < cnt) {
+      pr[k] = mx.v[0];
+      pi[k] = (int32_t)mx.v[1];
+      const Pack<2> key = {{kr[k * NT + tid], (double)ki[k * NT + tid]}};
+      mx = MaxKeyOp()(mx, key);
+      mn = MinKeyOp()(mn, key);
+    }
+  }
+  Pack<2> before, tb, after, ta;
+  block_prefix_suffix<NT, 2, 2, MaxKeyOp, MinKeyOp, false>(
+      mx, Pack<2>{{-INFINITY, -2147483648.0}}, MaxKeyOp(), mn, Pack<2>{{INFINITY, 2147483647.0}},
+      MinKeyOp(), s_scan, before, tb, after, ta);
+  // run boundaries of the chunk (bit k: boundary before position p0 + k)
+  Pack<2> sm = after;
+  unsigned bits = 0;
+#pragma unroll
+  for (int k = CMAX - 1; k >= 0; --k) {
+    if (k < cnt) {
+      const Pack<2> key = {{kr[k * NT + tid], (double)ki[k * NT + tid]}};
+      sm = MinKeyOp()(sm, key);
+      const Pack<2> pm = MaxKeyOp()(before, Pack<2>{{pr[k], (double)pi[k]}});
+      const bool b = (p0 + k == 0) || key_lt(pm.v[0], (int32_t)pm.v[1], sm.v[0], (int32_t)sm.v[1]);
+      bits |= (unsigned)b << k;
+    }
+  }
+  // last boundary at or before each chunk, first one after it
+  const double lb = bits ? (double)(p0 + 31 - __builtin_clz(bits)) : -1.0;
+  const double fb = bits ? (double)(p0 + __builtin_ctz(bits)) : (double)N;
+  Pack<1> ain, at_, ein, et_;
+  block_prefix_suffix<NT, 1, 1, MaxIntOp, MinIntOp, false>(
+      Pack<1>{{lb}}, Pack<1>{{-1.0}}, MaxIntOp(), Pack<1>{{fb}}, Pack<1>{{(double)N}}, MinIntOp(),
+      s_scan2, ain, at_, ein, et_);
+  // classify; rings of short runs placed here
+  unsigned lng = 0;
+  double nlong = 0.0;
+  #pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const int p = p0 + k;
+    const unsigned own = (unsigned)(k * NT + tid);
+    const unsigned below = bits & ((2u << k) - 1u);           // boundaries at or before p
+    const unsigned above = bits & ~((2u << k) - 1u);          // boundaries after p
+    const int a = below ? p0 + 31 - __builtin_clz(below) : (int)ain.v[0];
+    const int e = above ? p0 + __builtin_ctz(above) : (int)ein.v[0];
+    if (e - a == 1) { perm[own] = (uint16_t)own; continue; }
+    if (e - a <= WAKE_SEGMAX) {
+      const double r = kr[own];
+      const int32_t id = ki[own];
+      int qi = pos_index<NT>(a, C, iC);
+      int qk = qi / NT, qt = qi % NT;                          // NT is a power of two
+      int rank = 0;
+      #pragma unroll 1
+      for (int q = a; q < e; ++q) {
+        const int x = qk * NT + qt;
+        rank += key_lt(kr[x], ki[x], r, id) ? 1 : 0;
+        if (++qk == C) { qk = 0; ++qt; }
+      }
+      perm[pos_index<NT>(a + rank, C, iC)] = (uint16_t)own;
+    } else {
+      lng |= 1u << k;
+      nlong += 1.0;
+    }
+  }
+  Pack<1> tot;
+  const Pack<1> j0p = block_prefix<NT, 1>(Pack<1>{{nlong}}, Pack<1>{{0.0}}, SumOp<1>(), s_scan, tot);
+  const int M = (int)tot.v[0];
+  if (M > 0) {
+    // rings of the long runs, compacted in position order; sorted keys in
+    // zr/zi/zs (slots), their freed positions in zf (LDS index form)
+    double* zr = reinterpret_cast<double*>(region);
+    int32_t* zi = reinterpret_cast<int32_t*>(zr + WAKE_SORTCAP);
+    int32_t* zs = zi + WAKE_SORTCAP;
+    const bool in_lds = M <= WAKE_SORTCAP;
+    int j = (int)j0p.v[0];
+    #pragma unroll 1
+    for (int k = 0; k < cnt; ++k) {
+      if (!((lng >> k) & 1u)) continue;
+      const int own = k * NT + tid;
+      if (in_lds) { zf[j] = (uint16_t)own; zr[j] = kr[own]; zi[j] = ki[own]; zs[j] = own; }
+      else { I.free_slot[j] = own; I.sk_r[0][j] = kr[own]; I.sk_i[0][j] = ki[own]; I.sk_s[0][j] = own; }
+      ++j;
+    }
+    __syncthreads();
+    if (in_lds) {
+      int P = 1;
+      while (P < M) P <<= 1;
+      for (int i = M + tid; i < P; i += NT) { zr[i] = INFINITY; zi[i] = 0x7fffffff - i; zs[i] = -1; }
+      __syncthreads();
+      bitonic_keys<NT>(zr, zi, zs, P);
+      for (int q = tid; q < M; q += NT) perm[zf[q]] = (uint16_t)zs[q];
+    } else {
+      const int b = sort_keys_global<NT>(I, M, zr, zi, zs);
+      for (int q = tid; q < M; q += NT) perm[I.free_slot[q]] = (uint16_t)I.sk_s[b][q];
+    }
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -433,129 +671,215 @@ struct BwdMatSumOp {  // (index-order product of inverse transfers, running sum)
     return {{m.v[0], m.v[1], m.v[2], m.v[3], lo.v[4] + hi.v[4]}};
   }
 };
-struct DDSumOp {      // one double-double sum
-  __device__ __forceinline__ Pack<2> operator()(const Pack<2>& a, const Pack<2>& b) const {
-    const dd s = dd_add({a.v[0], a.v[1]}, {b.v[0], b.v[1]});
-    return {{s.hi, s.lo}};
+struct SliceHeadOp {  // (w, w ln rho) as double-doubles, then two flag counts
+  __device__ __forceinline__ Pack<6> operator()(const Pack<6>& a, const Pack<6>& b) const {
+    const dd x = dd_add({a.v[0], a.v[1]}, {b.v[0], b.v[1]});
+    const dd y = dd_add({a.v[2], a.v[3]}, {b.v[2], b.v[3]});
+    return {{x.hi, x.lo, y.hi, y.lo, a.v[4] + b.v[4], a.v[5] + b.v[5]}};
   }
 };
 
 template <int NT>
 struct MarchLds {
   static constexpr int NW = NT / 64;
+  // rings per thread up to which the keys of every position live in LDS
+  static constexpr int CMAX = NT >= 1024 ? 8 : 16;
+  static constexpr int KCAP = NT * CMAX;
   static constexpr size_t region_bytes() {
     const size_t beam = 2 * WAKE_BCAP * sizeof(double);
     const size_t sort = WAKE_SORTCAP * (sizeof(double) + 2 * sizeof(int32_t));
-    const size_t nb = NT * (sizeof(double) + sizeof(int32_t));
-    size_t m = beam > sort ? beam : sort;
-    return m > nb ? m : nb;
+    return beam > sort ? beam : sort;
   }
-  static constexpr size_t bytes() { return sizeof(double) * (NW * 16 + 64) + region_bytes(); }
+  // two scan areas, analytic constants, first keys of the chunks
+  static constexpr size_t head_bytes() {
+    return sizeof(double) * (2 * NW * 16 + 64 + NT) + sizeof(int32_t) * NT;
+  }
+  // per position (slot form): key radius, key id, slot of the ring
+  // (permutation); freed positions of long runs
+  static constexpr size_t key_bytes() {
+    return (size_t)KCAP * (sizeof(double) + 2 * sizeof(uint16_t)) +
+           (size_t)WAKE_SORTCAP * sizeof(uint16_t);
+  }
+  static constexpr size_t bytes() { return head_bytes() + key_bytes() + region_bytes(); }
 };
+
+// This slice's analytic source factors (beams: lam += c0 (1 - exp(-rho^2 c1));
+// lasers: |a|^2 = c0 exp(-rho^2 c1)) and beam-table entries into LDS.
+template <int NT>
+__device__ __forceinline__ void stage_slice(const WakeInst& I, int n, double* s_misc, double* s_br,
+                                            double* s_bc) {
+  const int tid = threadIdx.x;
+  const double xi = n * I.dxi;
+  if (tid < I.n_an) {
+    const WakeAnalytic& A = I.an[tid];
+    if (A.kind == 2) {
+      const double s2 = A.sigma_r * A.sigma_r;
+      const double dl = xi - A.xi_c;
+      const double lon = exp(-(dl * dl) / (2.0 * A.sigma_xi * A.sigma_xi));
+      s_misc[3 * tid] = 2.0;
+      s_misc[3 * tid + 1] = A.q * A.n_peak * lon * s2;
+      s_misc[3 * tid + 2] = 1.0 / (2.0 * s2);
+    } else {
+      const double dl = xi - A.xi_l;
+      const double lon = exp(-2.0 * dl * dl / (A.L * A.L));
+      s_misc[3 * tid] = 3.0;
+      s_misc[3 * tid + 1] = A.a0 * A.a0 * lon;
+      s_misc[3 * tid + 2] = 2.0 / (A.w0 * A.w0);
+    }
+  }
+  if (I.nb) {
+    const int bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
+    const int bm = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
+    if (bm <= WAKE_BCAP)
+      for (int i = tid; i < bm; i += NT) { s_br[i] = I.br[bt0 + i]; s_bc[i] = I.bcum[bt0 + i]; }
+  }
+}
+
+// Per-thread sums of (w, w ln rho) over the rings at this thread's
+// positions (ln rho of each ring taken from its slot).
+template <int NT>
+__device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, bool ident,
+                                           const uint16_t* perm, dd& sw, dd& swl) {
+  const int tid = threadIdx.x;
+  const unsigned smax = (unsigned)(I.C * NT - 1);
+  sw = {0.0, 0.0};
+  swl = {0.0, 0.0};
+  #pragma unroll 4
+  for (int k = 0; k < cnt; ++k) {
+    const unsigned s = ident ? (unsigned)(k * NT + tid) : min((unsigned)perm[k * NT + tid], smax);
+    const double w = I.w[I.hs[cur][s]];
+    sw = dd_add_d(sw, w);
+    swl = dd_add(swl, dd_mul_d(dd{I.lnh[cur][s], I.lnl[cur][s]}, w));
+  }
+}
 
 template <int NT>
 __device__ void march(const WakeInst& I, unsigned char* smem) {
   constexpr int NW = NT / 64;
+  constexpr int CMAX = MarchLds<NT>::CMAX;
+  constexpr int KCAP = MarchLds<NT>::KCAP;
   const int tid = threadIdx.x;
   const int N = I.N;
   const int C = I.C;
-  const int cnt = max(0, min(C, N - tid * C));   // rings owned by this thread
+  const int p0 = tid * C;
+  const int cnt = max(0, min(C, N - p0));   // rings owned by this thread
 
-  double* s_scan = reinterpret_cast<double*>(smem);       // NW * 16
-  double* s_misc = s_scan + NW * 16;                       // 64
-  unsigned char* region = reinterpret_cast<unsigned char*>(s_misc + 64);
+  double* s_scanA = reinterpret_cast<double*>(smem);      // NW * 16
+  double* s_scanB = s_scanA + NW * 16;                     // NW * 16
+  double* s_misc = s_scanB + NW * 16;                      // 64
+  double* s_fr = s_misc + 64;                              // NT: first pushed key of each chunk
+  int32_t* s_fi = reinterpret_cast<int32_t*>(s_fr + NT);  // NT
+  double* s_kr = reinterpret_cast<double*>(smem + MarchLds<NT>::head_bytes());
+  uint16_t* s_ki = reinterpret_cast<uint16_t*>(s_kr + KCAP);
+  uint16_t* s_perm = s_ki + KCAP;
+  uint16_t* s_zf = s_perm + KCAP;
+  unsigned char* region = smem + MarchLds<NT>::head_bytes() + MarchLds<NT>::key_bytes();
   double* s_br = reinterpret_cast<double*>(region);        // beam radii
   double* s_bc = s_br + WAKE_BCAP;                         // beam cumulative charge
+  // keys and ring order in LDS (else the order is fixed in global memory)
+  const bool lds_keys = C <= CMAX;
+  const unsigned smax = (unsigned)(C * NT - 1);    // last slot
 
-  if (I.ctl[CTL_BREAK] >= 0) return;
-  int cur = I.ctl[CTL_CUR];
+  if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
+  int cur = __builtin_amdgcn_readfirstlane(I.ctl[CTL_CUR]);
   __syncthreads();
-  fix_order<NT>(I, cur, 1 - cur, s_scan, region);   // injected states may be unsorted
-  const dd tot0 = {I.tot0[0], I.tot0[1]};
-  const double dxi = I.dxi;
-
-  // per-thread sums of (w, w ln rho) for the next slice's prefix
-  dd sw = {0.0, 0.0}, swl = {0.0, 0.0};
-  bool have_ln = false;
-
-  for (int step = 0; step < I.count; ++step) {
-    const int n = I.first + step;
-    const double xi = n * dxi;
-    const bool do_push = n < I.n_xi - 1;
-    const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
-    const bool rec_last = step == I.count - 1;
-    const int nb = 1 - cur;
-    double* const rho_c = I.rho[cur];
-    double* const u_c = I.u[cur];
-    const int32_t* const id_c = I.id[cur];
-    int32_t* const hint_c = I.hint[cur];
-
-    // ---- loop A: ln rho of every ring (only when not carried over) ----
-    if (!have_ln) {
-      sw = {0.0, 0.0};
-      swl = {0.0, 0.0};
-      #pragma unroll 1
-      for (int k = 0; k < cnt; ++k) {
-        const int sl = k * NT + tid;
-        const int id = id_c[sl];
-        const double w = I.w[id];
-        const dd lr = ring_log(I, id, rho_c[sl]);
-        I.lnh[sl] = lr.hi;
-        I.lnl[sl] = lr.lo;
-        sw = dd_add_d(sw, w);
-        swl = dd_add(swl, dd_mul_d(lr, w));
-      }
-    }
-    // ---- Gauss/log prefix: sum_{k<i} w_k, sum_{k<i} w_k ln rho_k ----
-    Pack<4> t4;
-    const Pack<4> pre = block_prefix<NT, 4>(Pack<4>{{sw.hi, sw.lo, swl.hi, swl.lo}},
-                                            Pack<4>{{0, 0, 0, 0}}, DD2Op(), s_scan, t4);
-    const dd totl = {t4.v[2], t4.v[3]};
-    const double psi_axis = dd_round(dd_sub(totl, tot0));
-
-    // ---- this slice's analytic source constants (slice-dependent factors) ----
-    // beams: lam += c0 * (-expm1(-rho^2 * c1)); lasers: |a|^2 = c0 exp(-rho^2 c1)
-    if (tid < I.n_an) {
-      const WakeAnalytic& A = I.an[tid];
-      if (A.kind == 2) {
-        const double s2 = A.sigma_r * A.sigma_r;
-        const double dl = xi - A.xi_c;
-        const double lon = exp(-(dl * dl) / (2.0 * A.sigma_xi * A.sigma_xi));
-        s_misc[3 * tid] = 2.0;
-        s_misc[3 * tid + 1] = A.q * A.n_peak * lon * s2;
-        s_misc[3 * tid + 2] = 1.0 / (2.0 * s2);
-      } else {
-        const double dl = xi - A.xi_l;
-        const double lon = exp(-2.0 * dl * dl / (A.L * A.L));
-        s_misc[3 * tid] = 3.0;
-        s_misc[3 * tid + 1] = A.a0 * A.a0 * lon;
-        s_misc[3 * tid + 2] = 2.0 / (A.w0 * A.w0);
-      }
-    }
-    const int n_an = I.n_an;
-
-    // ---- stage this slice's beam table ----
-    const int bt0 = I.nb ? I.boff[n] : 0;
-    const int bm = I.nb ? I.boff[n + 1] - bt0 : 0;
-    const bool staged = bm <= WAKE_BCAP;
-    if (bm > 0 && staged) {
-      for (int i = tid; i < bm; i += NT) { s_br[i] = I.br[bt0 + i]; s_bc[i] = I.bcum[bt0 + i]; }
+  // injected states may be unsorted
+  bool ident = true;
+  if (lds_keys) {
+    #pragma unroll 1
+    for (int k = 0; k < cnt; ++k) {
+      const unsigned sl = k * NT + tid;
+      s_kr[sl] = I.rho[cur][sl];
+      s_ki[sl] = (uint16_t)id_of<NT>(I.hs[cur][sl], C);
     }
     __syncthreads();
+    fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
+    ident = false;
+  } else {
+    fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
+  }
+  const dd tot0 = {I.tot0[0], I.tot0[1]};
+  const double dxi = I.dxi;
+  const int n_an = I.n_an;
+  const bool has_laser = I.has_laser != 0;
 
-    // ---- loop B: psi family, sources, local quantities, transfer product ----
+  // ln rho of every ring and the per-thread sums of (w, w ln rho)
+  #pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const unsigned sl = k * NT + tid;
+    const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+    const dd lr = ring_log(I, I.hs[cur][s], I.rho[cur][s]);
+    I.lnh[cur][s] = lr.hi;
+    I.lnl[cur][s] = lr.lo;
+  }
+  dd sw, swl;
+  chunk_sums<NT>(I, cur, cnt, ident, s_perm, sw, swl);
+  int n = I.first;
+  const int end = I.first + I.count;
+  if (n < end) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
+  double bad = 0.0, dis = 0.0;
+  int unpushed = cur;          // buffer with the unpushed state of slice n-1
+
+  for (;;) {
+    // ---- Gauss/log prefix sum_{k<i} (w_k, w_k ln rho_k); flags of slice n-1 ----
+    Pack<6> t6;
+    const Pack<6> pre = block_prefix<NT, 6, SliceHeadOp, false>(
+        Pack<6>{{sw.hi, sw.lo, swl.hi, swl.lo, bad, dis}}, Pack<6>{{0, 0, 0, 0, 0, 0}},
+        SliceHeadOp(), s_scanA, t6);
+    if (t6.v[4] != 0.0) {     // slice n-1 broke down: stop there
+      if (tid == 0) { I.ctl[CTL_BREAK] = n - 1; I.ctl[CTL_CUR] = unpushed; I.ctl[CTL_NEXT] = n - 1; }
+      return;
+    }
+    if (n == end) break;
+    if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
+      if (lds_keys) {
+        fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
+        ident = false;
+        // chunks that took a ring from another chunk sum again
+        bool changed = false;
+        for (int k = 0; k < cnt; ++k) changed |= (s_perm[k * NT + tid] & (NT - 1)) != (unsigned)tid;
+        if (changed) chunk_sums<NT>(I, cur, cnt, ident, s_perm, sw, swl);
+      } else {
+        fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
+        chunk_sums<NT>(I, cur, cnt, true, s_perm, sw, swl);
+      }
+      stage_slice<NT>(I, n, s_misc, s_br, s_bc);
+      dis = 0.0;
+      continue;
+    }
+    const double psi_axis = dd_round(dd_sub({t6.v[2], t6.v[3]}, tot0));
+    const bool do_push = n < I.n_xi - 1;
+    const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
+    const bool rec_last = n == end - 1;
+    const int nb = 1 - cur;
+    const double* const rho_c = I.rho[cur];
+    const double* const u_c = I.u[cur];
+    const int32_t* const hs_c = I.hs[cur];
+    int bt0 = 0, bm = 0;
+    if (I.nb) {
+      bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
+      bm = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
+    }
+    const bool staged = bm <= WAKE_BCAP;
+    const double* const bR = staged ? s_br : I.br + bt0;
+    const double* const bQ = staged ? s_bc : I.bcum + bt0;
+
+    // ---- pass B: psi family, sources, local quantities, chunk sums ----
     dd S = {pre.v[0], pre.v[1]}, PT = {pre.v[2], pre.v[3]};
-    Pack<4> P = mat_ident();
-    double vs = 0.0, bad = 0.0;
+    Pack<4> G = mat_ident();
+    double Vw = 0.0;
+    double l0a = 0.0, l0b = 0.0, l1a = 0.0, l1b = 0.0;
+    bad = 0.0;
     int blo = 0;
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
-      const int sl = k * NT + tid;
-      const double rho = rho_c[sl], u = u_c[sl];
-      const int id = id_c[sl];
-      int h = hint_c[sl];
-      const double w = I.w[id], wh = I.wh[id];
-      const dd lnr = {I.lnh[sl], I.lnl[sl]};
+      const unsigned sl = k * NT + tid;
+      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+      const double rho = rho_c[s], u = u_c[s];
+      const int32_t hs = hs_c[s];
+      int h = I.hint[cur][s];
+      const dd lnr = {I.lnh[cur][s], I.lnl[cur][s]};
+      const double w = I.w[hs], wh = I.wh[hs];
       const double irho = 1.0 / rho;
       const dd PTi = dd_add(PT, dd_mul_d(lnr, w));
       const dd pe = dd_sub(dd_mul(dd_add_d(S, w), lnr), PTi);    // psi_e - sum w ln rho
@@ -569,30 +893,13 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       // beam charge inside rho (strictly below), analytic beams, lasers
       double lam = 0.0;
       if (bm > 0) {
-        int c = 0;
-        if (staged) {
-          int lo = blo, hi = bm;
-          while (lo < hi) {
-            const int m = (lo + hi) >> 1;
-            if (s_br[m] < rho) lo = m + 1; else hi = m;
-          }
-          c = lo;
-          blo = lo;
-          if (c > 0) lam = s_bc[c - 1];
-        } else {
-          int lo = 0, hi = bm;
-          while (lo < hi) {
-            const int m = (lo + hi) >> 1;
-            if (I.br[bt0 + m] < rho) lo = m + 1; else hi = m;
-          }
-          c = lo;
-          if (c > 0) lam = I.bcum[bt0 + c - 1];
-        }
+        blo = count_below(bR, blo, bm, rho, k > 0);
+        if (blo > 0) lam = bQ[blo - 1];
       }
       double aa = 0.0, dda = 0.0;
-#pragma unroll 1
-      for (int s = 0; s < n_an; ++s) {
-        const double kind = s_misc[3 * s], c0 = s_misc[3 * s + 1], c1 = s_misc[3 * s + 2];
+      #pragma unroll 1
+      for (int si = 0; si < n_an; ++si) {
+        const double kind = s_misc[3 * si], c0 = s_misc[3 * si + 1], c1 = s_misc[3 * si + 2];
         if (kind == 2.0) {
           lam += c0 * (-expm1(-rho * rho * c1));
         } else {
@@ -604,136 +911,94 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const double bb = lam * irho;
       const Local L = local_of(irho, u, w, psi, aa);
       if (!(L.pb > 0.0)) bad = 1.0;
-      P = mat_mul(rec_matrix(L.A, rho, irho), P);
-      vs += L.v;
+      G = mat_mul(rec_matrix(L.A, rho, irho), G);
+      Vw += L.v;
+      // s_i with d_zeta psi = (Vw - own) + c: s = s0 + c s1
+      const double dz0 = Vw - (w - wh) * u * irho * L.ipb;
+      double B0, Cc;
+      ring_BC(irho, u, w, L, dpsi, dz0, bb, dda, B0, Cc);
+      const double beta = w * irho * u * L.ipb * L.ipb;     // -dB/d(d_zeta psi)
+      double s0a, s0b;
+      rec_offset(L.A, B0, Cc, rho, s0a, s0b);
+      const double s1a = -0.5 * beta, s1b = 0.5 * rho * rho * beta;
+      l0a += G.v[0] * s0b - G.v[2] * s0a;
+      l0b += G.v[1] * s0b - G.v[3] * s0a;
+      l1a += G.v[0] * s1b - G.v[2] * s1a;
+      l1b += G.v[1] * s1b - G.v[3] * s1a;
       I.psi[sl] = psi;
       I.dpsi[sl] = dpsi;
       I.bb[sl] = bb;
-      if (I.has_laser) { I.a2[sl] = aa; I.da2[sl] = dda; }
-      hint_c[sl] = h;
+      if (has_laser) { I.a2[sl] = aa; I.da2[sl] = dda; }
+      // the ring's home slot and hint move to its position slot in the next buffer
+      I.hs[nb][sl] = hs;
+      I.hint[nb][sl] = h;
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
-    Pack<5> gp, gt, hs, ht;
-    block_prefix_suffix<NT, 5, 5>(Pack<5>{{P.v[0], P.v[1], P.v[2], P.v[3], vs}},
-                                  Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, FwdMatSumOp(),
-                                  Pack<5>{{P.v[3], -P.v[1], -P.v[2], P.v[0], vs}},   // adj(P)
-                                  Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, BwdMatSumOp(), s_scan, gp, gt,
-                                  hs, ht);
+    Pack<5> gp, gt, hx, ht;
+    block_prefix_suffix<NT, 5, 5, FwdMatSumOp, BwdMatSumOp, false>(
+        Pack<5>{{G.v[0], G.v[1], G.v[2], G.v[3], Vw}}, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}},
+        FwdMatSumOp(), Pack<5>{{G.v[3], -G.v[1], -G.v[2], G.v[0], Vw}},
+        Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, BwdMatSumOp(), s_scanB, gp, gt, hx, ht);
     const double W = gt.v[0];                 // det[g_N, (0,1)]
     const double iW = 1.0 / W;
     const double Vtot = gt.v[4];
-    const double hea = hs.v[1], heb = hs.v[3];   // h at the end of this chunk
-    const double Vafter = hs.v[4];
+    const double Vafter = hx.v[4];
+    const double gsa = gp.v[0], gsb = gp.v[2];    // g at the chunk start
+    const double hea = hx.v[1], heb = hx.v[3];    // h at the chunk end
+    const double c = -(Vw + Vafter);
+    const double la = l0a + c * l1a, lb = l0b + c * l1b;
+    const double le = gsa * la + gsb * lb;        // sum of det[g_i, s_i] over the chunk
+    const double hsa = G.v[3] * hea - G.v[1] * heb;   // h at the chunk start
+    const double hsb = -G.v[2] * hea + G.v[0] * heb;
+    const double lds = -(hsa * la + hsb * lb);     // sum of det[s_i, h_i] over the chunk
+    Pack<1> ep, et, dsf, dt;
+    block_prefix_suffix<NT, 1, 1, SumOp<1>, SumOp<1>, false>(
+        Pack<1>{{le}}, Pack<1>{{0.0}}, SumOp<1>(), Pack<1>{{lds}}, Pack<1>{{0.0}}, SumOp<1>(),
+        s_scanA, ep, et, dsf, dt);
 
-    // ---- loop C: store g_{i-1}; sums of det[g_i, s0_i], det[g_i, s1_i] ----
-    double ga = gp.v[0], gb = gp.v[2];
-    double V = gp.v[4];
-    double le0 = 0.0, le1 = 0.0;
-    #pragma unroll 1
-    for (int k = 0; k < cnt; ++k) {
-      const int sl = k * NT + tid;
-      const double rho = rho_c[sl], u = u_c[sl];
-      const int id = id_c[sl];
-      const double w = I.w[id], wh = I.wh[id];
-      const double psi = I.psi[sl], dpsi = I.dpsi[sl], bb = I.bb[sl];
-      const double a2 = I.has_laser ? I.a2[sl] : 0.0, da2 = I.has_laser ? I.da2[sl] : 0.0;
-      const double irho = 1.0 / rho;
-      const Local L = local_of(irho, u, w, psi, a2);
-      I.g0[sl] = ga;
-      I.g1[sl] = gb;
-      const Pack<4> M = rec_matrix(L.A, rho, irho);
-      const double na = M.v[0] * ga + M.v[1] * gb;
-      const double nbg = M.v[2] * ga + M.v[3] * gb;
-      ga = na;
-      gb = nbg;
-      V += L.v;
-      const double dz0 = V - (w - wh) * u * irho * L.ipb;    // d_zeta psi + V_total
-      double B0, C;
-      ring_BC(irho, u, w, L, dpsi, dz0, bb, da2, B0, C);
-      const double B1 = w * irho * u * L.ipb * L.ipb;         // dB/dV_total
-      double s0a, s0b;
-      rec_offset(L.A, B0, C, rho, s0a, s0b);
-      const double s1a = 0.5 * B1, s1b = -0.5 * rho * rho * B1;
-      le0 += ga * s0b - gb * s0a;
-      le1 += ga * s1b - gb * s1a;
-    }
-
-    // ---- loop D: sum of det[s_i, h_i] ----
+    // ---- pass E: B^(p), outputs, push ----
+    double ga = G.v[0] * gsa + G.v[1] * gsb;      // g at the chunk end
+    double gb = G.v[2] * gsa + G.v[3] * gsb;
     double ha = hea, hb = heb;
     double Vgt = Vafter;
-    double lds = 0.0;
-    #pragma unroll 1
-    for (int k = cnt - 1; k >= 0; --k) {
-      const int sl = k * NT + tid;
-      const double rho = rho_c[sl], u = u_c[sl];
-      const int id = id_c[sl];
-      const double w = I.w[id], wh = I.wh[id];
-      const double psi = I.psi[sl], dpsi = I.dpsi[sl], bb = I.bb[sl];
-      const double a2 = I.has_laser ? I.a2[sl] : 0.0, da2 = I.has_laser ? I.da2[sl] : 0.0;
-      const double irho = 1.0 / rho;
-      const Local L = local_of(irho, u, w, psi, a2);
-      const double dz = -(Vgt + (w - wh) * u * irho * L.ipb);
-      double B, C;
-      ring_BC(irho, u, w, L, dpsi, dz, bb, da2, B, C);
-      double sa, sb;
-      rec_offset(L.A, B, C, rho, sa, sb);
-      lds += sa * hb - sb * ha;
-      const double hh = 0.5 * L.A * rho;
-      const double na = (1.0 - hh) * ha - (0.5 * L.A * irho) * hb;
-      const double nbh = (hh * rho * rho) * ha + (1.0 + hh) * hb;
-      ha = na;
-      hb = nbh;
-      Vgt += L.v;
-    }
-    Pack<2> ep, et;
-    Pack<1> dsf, dt;
-    block_prefix_suffix<NT, 2, 1>(Pack<2>{{le0, le1}}, Pack<2>{{0.0, 0.0}}, SumOp<2>(),
-                                  Pack<1>{{lds}}, Pack<1>{{0.0}}, SumOp<1>(), s_scan, ep, et, dsf, dt);
-
-    // ---- loop E: B^(p), outputs, push ----
-    ha = hea; hb = heb;
-    Vgt = Vafter;
+    double E = ep.v[0] + le;
     double D = dsf.v[0];
-    double E = (ep.v[0] + le0) + Vtot * (ep.v[1] + le1);
-    double disorder = 0.0;
-    double nxt_r = INFINITY;
-    int32_t nxt_i = 0x7fffffff;
+    double nxt_r = INFINITY, last_r = INFINITY;
+    int32_t nxt_i = 0x7fffffff, last_i = 0x7fffffff;
     dd sw2 = {0.0, 0.0}, swl2 = {0.0, 0.0};
+    double dis_l = 0.0;
     double* const rho_n = I.rho[nb];
     double* const u_n = I.u[nb];
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
-      const int sl = k * NT + tid;
-      const double rho = rho_c[sl], u = u_c[sl];
-      const int id = id_c[sl];
-      const double w = I.w[id], wh = I.wh[id];
+      const unsigned sl = k * NT + tid;
+      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+      const double rho = rho_c[s], u = u_c[s];
+      const int32_t hs = I.hs[nb][sl];
+      const double w = I.w[hs], wh = I.wh[hs];
       const double psi = I.psi[sl], dpsi = I.dpsi[sl], bb = I.bb[sl];
-      const double a2 = I.has_laser ? I.a2[sl] : 0.0, da2 = I.has_laser ? I.da2[sl] : 0.0;
-      const double ga0 = I.g0[sl], gb0 = I.g1[sl];
+      const double a2 = has_laser ? I.a2[sl] : 0.0, da2 = has_laser ? I.da2[sl] : 0.0;
       const double irho = 1.0 / rho;
       const Local L = local_of(irho, u, w, psi, a2);
       const double dz = -(Vgt + (w - wh) * u * irho * L.ipb);
-      double B, C;
-      ring_BC(irho, u, w, L, dpsi, dz, bb, da2, B, C);
+      double B, Cc;
+      ring_BC(irho, u, w, L, dpsi, dz, bb, da2, B, Cc);
       double sa, sb;
-      rec_offset(L.A, B, C, rho, sa, sb);
-      const double ds = sa * hb - sb * ha;                 // det[s_i, h_i]
-      const Pack<4> M = rec_matrix(L.A, rho, irho);
-      const double gia = M.v[0] * ga0 + M.v[1] * gb0;
-      const double gib = M.v[2] * ga0 + M.v[3] * gb0;
-      const double e = gia * sb - gib * sa;                // det[g_i, s_i]
-      D += ds;                                             // D_{i-1}
-      E -= e;                                              // E_{i-1}
-      const double hh = 0.5 * L.A * rho;
-      const double hpa = (1.0 - hh) * ha - (0.5 * L.A * irho) * hb;   // h_{i-1}
-      const double hpb = (hh * rho * rho) * ha + (1.0 + hh) * hb;
-      const double a = (hpa * E - ga0 * D) * iW;
-      const double b = (hpb * E - gb0 * D) * iW;
-      const double bp = a * rho + b * irho + (wh / w) * C;
+      rec_offset(L.A, B, Cc, rho, sa, sb);
+      D += sa * hb - sb * ha;                              // D_{i-1} (det[s_i, h_i])
+      E -= ga * sb - gb * sa;                              // E_{i-1} (det[g_i, s_i])
+      const double hh = 0.5 * L.A * rho, q = 0.5 * L.A * irho, pp = hh * rho * rho;
+      const double nga = (1.0 - hh) * ga - q * gb, ngb = pp * ga + (1.0 + hh) * gb;   // M_i^-1 g_i
+      const double nha = (1.0 - hh) * ha - q * hb, nhb = pp * ha + (1.0 + hh) * hb;   // M_i^-1 h_i
+      ga = nga; gb = ngb; ha = nha; hb = nhb;
+      const double a = (ha * E - ga * D) * iW;
+      const double b = (hb * E - gb * D) * iW;
+      const double bp = a * rho + b * irho + (wh / w) * Cc;
       const double bt = bb + bp;
       const double ez = -dz;
       if (!(isfinite(psi) && isfinite(dpsi) && isfinite(ez) && isfinite(bt))) bad = 1.0;
+      const int32_t id = id_of<NT>(hs, C);
       if (rec_snap) {
         double* sp = I.snap + (size_t)(n / I.stride) * OUT_N * N;
         sp[OUT_PSI * N + id] = psi; sp[OUT_ERBT * N + id] = -dpsi;
@@ -750,87 +1015,66 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const double f_r = u * L.ipb;
         const double f_u = L.gm * dpsi * L.ipb - bt - 0.25 * da2 * L.ipb;
         double pr = f_r, pu = f_u;
-        if (n > 0) { pr = I.fr[cur][sl]; pu = I.fu[cur][sl]; }
+        if (n > 0) { pr = I.fr[cur][s]; pu = I.fu[cur][s]; }
         double rn = rho + dxi * (1.5 * f_r - 0.5 * pr);
         double un = u + dxi * (1.5 * f_u - 0.5 * pu);
         double sr = f_r, su = f_u;
         if (rn < 0.0) { rn = -rn; un = -un; sr = -sr; su = -su; }
         if (!(isfinite(rn) && isfinite(un))) bad = 1.0;
         rho_n[sl] = rn; u_n[sl] = un; I.fr[nb][sl] = sr; I.fu[nb][sl] = su;
-        I.id[nb][sl] = id; I.hint[nb][sl] = hint_c[sl];
-        const dd lr = ring_log(I, id, rn);
-        I.lnh[sl] = lr.hi;
-        I.lnl[sl] = lr.lo;
+        const dd lr = ring_log(I, hs, rn);
+        I.lnh[nb][sl] = lr.hi;
+        I.lnl[nb][sl] = lr.lo;
         sw2 = dd_add_d(sw2, w);
         swl2 = dd_add(swl2, dd_mul_d(lr, w));
-        if (!key_lt(rn, id, nxt_r, nxt_i)) disorder = 1.0;
+        if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
+        if (!key_lt(rn, id, nxt_r, nxt_i)) dis_l = 1.0;
+        if (k == cnt - 1) { last_r = rn; last_i = id; }
         nxt_r = rn;
         nxt_i = id;
       }
-      ha = hpa;
-      hb = hpb;
       Vgt += L.v;
     }
-    // order across chunk boundaries
-    double* s_fr = reinterpret_cast<double*>(region);
-    int32_t* s_fi = reinterpret_cast<int32_t*>(s_fr + NT);
-    if (do_push) {
-      __syncthreads();
-      s_fr[tid] = nxt_r;      // this chunk's first pushed key (+inf if empty)
-      s_fi[tid] = nxt_i;
-      __syncthreads();
-      if (cnt > 0 && tid + 1 < NT && (tid + 1) * C < N) {
-        const int sl_last = (cnt - 1) * NT + tid;
-        const double lr = rho_n[sl_last];
-        const int32_t li = I.id[nb][sl_last];
-        if (!key_lt(lr, li, s_fr[tid + 1], s_fi[tid + 1])) disorder = 1.0;
-      }
-    }
-    Pack<2> red;
-    block_prefix<NT, 2>(Pack<2>{{bad, disorder}}, Pack<2>{{0.0, 0.0}}, SumOp<2>(), s_scan, red);
     if (tid == 0) { I.axis[2 * n] = psi_axis; I.axis[2 * n + 1] = Vtot; }
-    if (red.v[0] != 0.0) {
-      if (tid == 0) { I.ctl[CTL_BREAK] = n; I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = n; }
-      return;
-    }
-    if (!do_push) {
-      if (tid == 0) { I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = n + 1; }
-      return;
-    }
-    cur = nb;
-    sw = sw2;
-    swl = swl2;
-    have_ln = true;
-    if (red.v[1] != 0.0 && fix_order<NT>(I, cur, 1 - cur, s_scan, region)) {
-      // the chunks changed: rebuild the per-thread sums from the moved ln rho
-      sw = {0.0, 0.0};
-      swl = {0.0, 0.0};
-      #pragma unroll 1
-      for (int k = 0; k < cnt; ++k) {
-        const int sl = k * NT + tid;
-        const double w = I.w[I.id[cur][sl]];
-        sw = dd_add_d(sw, w);
-        swl = dd_add(swl, dd_mul_d(dd{I.lnh[sl], I.lnl[sl]}, w));
-      }
-    }
+    // order across chunk boundaries: this chunk's first pushed key (+inf if
+    // empty) against the previous chunk's last one
+    s_fr[tid] = nxt_r;
+    s_fi[tid] = nxt_i;
+    if (do_push && n + 1 < end) stage_slice<NT>(I, n + 1, s_misc, s_br, s_bc);
     __syncthreads();
+    if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))
+      dis_l = 1.0;
+    dis = dis_l;
+    unpushed = cur;
+    if (do_push) {
+      // the pushed rings sit at the slots of this slice's positions
+      cur = nb;
+      ident = true;
+      sw = sw2;
+      swl = swl2;
+    }
+    ++n;
   }
-  if (tid == 0) { I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = I.first + I.count; }
+  if (tid == 0) { I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = end; }
 }
 
-// 2 waves per SIMD: up to 256 VGPRs per lane, no spills
+#ifndef WAKE_WAVES_PER_EU
+#define WAKE_WAVES_PER_EU 2
+#endif
+// WAKE_WAVES_PER_EU waves per SIMD (2: up to 256 VGPRs per lane)
 template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAKE_WAVES_PER_EU)))
 void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int32_t* counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_idx;
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
     __syncthreads();
-    const int idx = s_idx;
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     __syncthreads();
     if (idx >= n_insts) return;   // every workgroup leaves once the queue is empty
-    if (insts[idx].nt == NT) march<NT>(insts[idx], smem);
+    const WakeInst& I = insts[idx];
+    if (I.nt == NT) march<NT>(I, smem);
     __syncthreads();
   }
 }
@@ -846,8 +1090,9 @@ __global__ void state_by_id_kernel(WakeInst I, double* rho, double* u, double* f
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= I.N) return;
   const int c = I.ctl[CTL_CUR];
-  const int sl = (p % I.C) * I.nt + p / I.C;
-  const int i = I.id[c][sl];
+  const unsigned sl = slot_of(p, I.C, I.nt);
+  const int hs = I.hs[c][sl];
+  const int i = (hs % I.nt) * I.C + hs / I.nt;
   if (rho) rho[i] = I.rho[c][sl];
   if (u) u[i] = I.u[c][sl];
   if (fr) fr[i] = I.fr[c][sl];
@@ -861,12 +1106,12 @@ __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = slice; }
   if (i >= I.N) return;
-  const int sl = (i % I.C) * I.nt + i / I.C;
+  const unsigned sl = slot_of(i, I.C, I.nt);
   I.rho[0][sl] = rho[i];
   I.u[0][sl] = u[i];
   I.fr[0][sl] = fr ? fr[i] : 0.0;
   I.fu[0][sl] = fu ? fu[i] : 0.0;
-  I.id[0][sl] = i;
+  I.hs[0][sl] = (int32_t)sl;
   I.hint[0][sl] = i + 1;
 }
 
@@ -875,12 +1120,12 @@ __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u,
 __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_insts) {
   const WakeInst& I = insts[blockIdx.x];
   for (int j = threadIdx.x; j < I.N; j += blockDim.x) {
-    const int sl = (j % I.C) * I.nt + j / I.C;
-    I.rho[0][sl] = I.r0[j];
+    const unsigned sl = slot_of(j, I.C, I.nt);
+    I.rho[0][sl] = I.r0[sl];
     I.u[0][sl] = 0.0;
     I.fr[0][sl] = 0.0;
     I.fu[0][sl] = 0.0;
-    I.id[0][sl] = j;
+    I.hs[0][sl] = (int32_t)sl;
     I.hint[0][sl] = j + 1;
   }
   if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; }
