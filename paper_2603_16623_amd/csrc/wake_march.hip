@@ -134,8 +134,11 @@ __device__ __forceinline__ void ion_fields(const WakeInst& I, double r, dd lnr, 
   const double* R = I.ion;
   const int N = I.N;
   int j = h < 0 ? 0 : (h > N ? N : h);
-  if (R[j * WAKE_ION_REC + IR_LO] <= r) {
-    if (j < N && !(r < R[(j + 1) * WAKE_ION_REC + IR_LO])) {
+  // the whole record of the hinted interval in one go (64 B, 16-B aligned)
+  const double2* rv = reinterpret_cast<const double2*>(R + (size_t)j * WAKE_ION_REC);
+  double2 r0 = rv[0], r1 = rv[1], r2 = rv[2], r3 = rv[3];
+  if (!(r0.x <= r && r < r0.y)) {
+    if (r0.x <= r) {
       int a = j + 1, b, step = 1;     // lo(a) <= r
       for (;;) {
         b = a + step;
@@ -149,27 +152,29 @@ __device__ __forceinline__ void ion_fields(const WakeInst& I, double r, dd lnr, 
         if (R[m * WAKE_ION_REC + IR_LO] <= r) a = m; else b = m;
       }
       j = a;
+    } else {
+      int b = j, a, step = 1;           // lo(b) > r
+      for (;;) {
+        a = b - step;
+        if (a <= 0) { a = 0; break; }
+        if (R[a * WAKE_ION_REC + IR_LO] <= r) break;
+        b = a;
+        step <<= 1;
+      }
+      while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (R[m * WAKE_ION_REC + IR_LO] <= r) a = m; else b = m;
+      }
+      j = a;
     }
-  } else {
-    int b = j, a, step = 1;           // lo(b) > r
-    for (;;) {
-      a = b - step;
-      if (a <= 0) { a = 0; break; }
-      if (R[a * WAKE_ION_REC + IR_LO] <= r) break;
-      b = a;
-      step <<= 1;
-    }
-    while (b - a > 1) {
-      const int m = (a + b) >> 1;
-      if (R[m * WAKE_ION_REC + IR_LO] <= r) a = m; else b = m;
-    }
-    j = a;
+    rv = reinterpret_cast<const double2*>(R + (size_t)j * WAKE_ION_REC);
+    r0 = rv[0]; r1 = rv[1]; r2 = rv[2]; r3 = rv[3];
   }
   h = j;
-  const double* rec = R + j * WAKE_ION_REC;
-  const double t = (r - rec[IR_LO]) / (rec[IR_HI] - rec[IR_LO]);
-  ps = dd_add_d({rec[IR_PSH], rec[IR_PSL]}, t * rec[IR_DPS]);
-  dp = dd_add_d({rec[IR_DPH], rec[IR_DPL]}, t * rec[IR_DDP]);
+  // record layout: LO, HI | PSH, PSL | DPS, DPH | DPL, DDP
+  const double t = (r - r0.x) / (r0.y - r0.x);
+  ps = dd_add_d({r1.x, r1.y}, t * r2.x);
+  dp = dd_add_d({r2.y, r3.x}, t * r3.y);
 }
 
 // Number of entries of the ascending table br[0..m) below r, given that
@@ -610,10 +615,19 @@ __device__ __noinline__ void fix_order_lds(const WakeInst& I, double* s_scan, do
       int qk = qi / NT, qt = qi % NT;                          // NT is a power of two
       int rank = 0;
       #pragma unroll 1
-      for (int q = a; q < e; ++q) {
-        const int x = qk * NT + qt;
-        rank += key_lt(kr[x], ki[x], r, id) ? 1 : 0;
-        if (++qk == C) { qk = 0; ++qt; }
+      for (int q = a; q < e; q += 4) {
+        int x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {       // past the run end: compare with itself
+          x[i] = q + i < e ? qk * NT + qt : (int)own;
+          if (++qk == C) { qk = 0; ++qt; }
+        }
+        double xr[4];
+        int32_t xi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { xr[i] = kr[x[i]]; xi[i] = ki[x[i]]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rank += key_lt(xr[i], xi[i], r, id) ? 1 : 0;
       }
       perm[pos_index<NT>(a + rank, C, iC)] = (uint16_t)own;
     } else {
@@ -871,14 +885,28 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     double l0a = 0.0, l0b = 0.0, l1a = 0.0, l1b = 0.0;
     bad = 0.0;
     int blo = 0;
+    // the next ring's state is loaded one ring ahead
+    const int32_t* const hint_c = I.hint[cur];
+    const double* const lnh_c = I.lnh[cur];
+    const double* const lnl_c = I.lnl[cur];
+    double x_rho = 1.0, x_u = 0.0, x_lh = 0.0, x_ll = 0.0;
+    int32_t x_hs = 0, x_h = 0;
+    if (cnt > 0) {
+      const unsigned s = ident ? (unsigned)tid : min((unsigned)s_perm[tid], smax);
+      x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
+    }
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
-      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
-      const double rho = rho_c[s], u = u_c[s];
-      const int32_t hs = hs_c[s];
-      int h = I.hint[cur][s];
-      const dd lnr = {I.lnh[cur][s], I.lnl[cur][s]};
+      const double rho = x_rho, u = x_u;
+      const int32_t hs = x_hs;
+      int h = x_h;
+      const dd lnr = {x_lh, x_ll};
+      if (k + 1 < cnt) {
+        const unsigned sn = sl + NT;
+        const unsigned s = ident ? sn : min((unsigned)s_perm[sn], smax);
+        x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
+      }
       const double w = I.w[hs], wh = I.wh[hs];
       const double irho = 1.0 / rho;
       const dd PTi = dd_add(PT, dd_mul_d(lnr, w));
@@ -970,14 +998,31 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     double dis_l = 0.0;
     double* const rho_n = I.rho[nb];
     double* const u_n = I.u[nb];
+    // the next ring (one position back) is loaded one ring ahead
+    const int32_t* const hs_n = I.hs[nb];
+    const double* const fr_c = I.fr[cur];
+    const double* const fu_c = I.fu[cur];
+    double y_rho = 1.0, y_u = 0.0, y_fr = 0.0, y_fu = 0.0, y_psi = 0.0, y_dpsi = 0.0, y_bb = 0.0;
+    int32_t y_hs = 0;
+    if (cnt > 0) {
+      const unsigned sl = (cnt - 1) * NT + tid;
+      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+      y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
+      y_hs = hs_n[sl]; y_psi = I.psi[sl]; y_dpsi = I.dpsi[sl]; y_bb = I.bb[sl];
+    }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
-      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
-      const double rho = rho_c[s], u = u_c[s];
-      const int32_t hs = I.hs[nb][sl];
+      const double rho = y_rho, u = y_u, fr_p = y_fr, fu_p = y_fu;
+      const int32_t hs = y_hs;
+      const double psi = y_psi, dpsi = y_dpsi, bb = y_bb;
+      if (k > 0) {
+        const unsigned sp = sl - NT;
+        const unsigned s = ident ? sp : min((unsigned)s_perm[sp], smax);
+        y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
+        y_hs = hs_n[sp]; y_psi = I.psi[sp]; y_dpsi = I.dpsi[sp]; y_bb = I.bb[sp];
+      }
       const double w = I.w[hs], wh = I.wh[hs];
-      const double psi = I.psi[sl], dpsi = I.dpsi[sl], bb = I.bb[sl];
       const double a2 = has_laser ? I.a2[sl] : 0.0, da2 = has_laser ? I.da2[sl] : 0.0;
       const double irho = 1.0 / rho;
       const Local L = local_of(irho, u, w, psi, a2);
@@ -1015,7 +1060,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const double f_r = u * L.ipb;
         const double f_u = L.gm * dpsi * L.ipb - bt - 0.25 * da2 * L.ipb;
         double pr = f_r, pu = f_u;
-        if (n > 0) { pr = I.fr[cur][s]; pu = I.fu[cur][s]; }
+        if (n > 0) { pr = fr_p; pu = fu_p; }
         double rn = rho + dxi * (1.5 * f_r - 0.5 * pr);
         double un = u + dxi * (1.5 * f_u - 0.5 * pu);
         double sr = f_r, su = f_u;
