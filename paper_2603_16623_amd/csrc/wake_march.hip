@@ -105,10 +105,50 @@ __device__ __forceinline__ dd dd_div_rcp(dd a, double b, double ib) {
 
 // ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
 // rounding scales with the ring's displacement, not with |ln rho| (the psi
+// A per-instance array seen as uniform: its base in scalar registers and in
+// the global address space, indexed with 32-bit element offsets (loads and
+// stores then take the scalar-base + vector-offset form).
+#define WAKE_GLOBAL __attribute__((address_space(1)))
+template <class T>
+struct GA {
+  WAKE_GLOBAL T* p;
+  __device__ __forceinline__ T operator[](uint32_t i) const {
+    return *reinterpret_cast<WAKE_GLOBAL T*>(reinterpret_cast<WAKE_GLOBAL char*>(p) +
+                                            i * (uint32_t)sizeof(T));
+  }
+  __device__ __forceinline__ void st(uint32_t i, T v) const {
+    *reinterpret_cast<WAKE_GLOBAL T*>(reinterpret_cast<WAKE_GLOBAL char*>(p) +
+                                     i * (uint32_t)sizeof(T)) = v;
+  }
+};
+template <class T>
+__device__ __forceinline__ GA<T> uview(const T* q) {
+  const uint64_t v = reinterpret_cast<uint64_t>(q);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  GA<T> g;
+  g.p = reinterpret_cast<WAKE_GLOBAL T*>(((uint64_t)hi << 32) | lo);
+  return g;
+}
+__device__ __forceinline__ double uni(double x) {
+  const uint64_t v = __double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
+// rounding scales with the ring's displacement, not with |ln rho| (the psi
 // sums multiply ln rho by the enclosed charge).
-__device__ __forceinline__ dd ring_log(const WakeInst& I, unsigned hs, double rho) {
-  const double l1 = log1p((rho - I.r0[hs]) * I.ir0[hs]);
-  return dd_add_d({I.L0h[hs], I.L0l[hs]}, l1);
+struct LogView {
+  GA<double> r0, ir0, L0h, L0l;
+};
+__device__ __forceinline__ LogView log_view(const WakeInst& I) {
+  return {uview(I.r0), uview(I.ir0), uview(I.L0h), uview(I.L0l)};
+}
+__device__ __forceinline__ dd ring_log(const LogView& V, unsigned hs, double rho) {
+  const double l1 = log1p((rho - V.r0[hs]) * V.ir0[hs]);
+  return dd_add_d({V.L0h[hs], V.L0l[hs]}, l1);
 }
 
 template <int NT>
@@ -124,21 +164,30 @@ __device__ __forceinline__ unsigned slot_of(int p, int C, int nt) {
 // the node interval containing r (Sec. "Key algorithmic adjustments"),
 // searched from the ring's previous interval h; exact exterior field at and
 // beyond the plasma edge.
-__device__ __forceinline__ void ion_fields(const WakeInst& I, double r, dd lnr, int& h, dd& ps, dd& dp) {
-  if (!(r < I.Rp)) {
-    const dd Q = {I.tot0[2], I.tot0[3]};
-    ps = dd_sub({I.tot0[0], I.tot0[1]}, dd_mul(Q, lnr));
-    dp = dd_neg(dd_div_d(Q, r));
+// Ion fields need: the records R, their count N, the plasma edge Rp and the
+// exterior constants (sum w ln r0 as dd, Q as dd).
+struct IonView {
+  GA<double> R;
+  int N;
+  double Rp;
+  dd T0, Q;
+};
+
+__device__ __forceinline__ void ion_fields(const IonView& V, double r, dd lnr, int& h, dd& ps, dd& dp) {
+  if (!(r < V.Rp)) {
+    ps = dd_sub(V.T0, dd_mul(V.Q, lnr));
+    dp = dd_neg(dd_div_d(V.Q, r));
     return;
   }
-  const double* R = I.ion;
-  const int N = I.N;
+  const GA<double>& R = V.R;
+  const int N = V.N;
   int j = h < 0 ? 0 : (h > N ? N : h);
   // the whole record of the hinted interval in one go (64 B, 16-B aligned)
-  const double2* rv = reinterpret_cast<const double2*>(R + (size_t)j * WAKE_ION_REC);
-  double2 r0 = rv[0], r1 = rv[1], r2 = rv[2], r3 = rv[3];
-  if (!(r0.x <= r && r < r0.y)) {
-    if (r0.x <= r) {
+  double q[WAKE_ION_REC];
+#pragma unroll
+  for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = R[j * WAKE_ION_REC + i];
+  if (!(q[IR_LO] <= r && r < q[IR_HI])) {
+    if (q[IR_LO] <= r) {
       int a = j + 1, b, step = 1;     // lo(a) <= r
       for (;;) {
         b = a + step;
@@ -167,14 +216,13 @@ __device__ __forceinline__ void ion_fields(const WakeInst& I, double r, dd lnr, 
       }
       j = a;
     }
-    rv = reinterpret_cast<const double2*>(R + (size_t)j * WAKE_ION_REC);
-    r0 = rv[0]; r1 = rv[1]; r2 = rv[2]; r3 = rv[3];
+#pragma unroll
+    for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = R[j * WAKE_ION_REC + i];
   }
   h = j;
-  // record layout: LO, HI | PSH, PSL | DPS, DPH | DPL, DDP
-  const double t = (r - r0.x) / (r0.y - r0.x);
-  ps = dd_add_d({r1.x, r1.y}, t * r2.x);
-  dp = dd_add_d({r2.y, r3.x}, t * r3.y);
+  const double t = (r - q[IR_LO]) / (q[IR_HI] - q[IR_LO]);
+  ps = dd_add_d({q[IR_PSH], q[IR_PSL]}, t * q[IR_DPS]);
+  dp = dd_add_d({q[IR_DPH], q[IR_DPL]}, t * q[IR_DDP]);
 }
 
 // Number of entries of the ascending table br[0..m) below r, given that
@@ -756,14 +804,16 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
                                            const uint16_t* perm, dd& sw, dd& swl) {
   const int tid = threadIdx.x;
   const unsigned smax = (unsigned)(I.C * NT - 1);
+  const GA<double> Wv = uview(I.w), LH = uview(I.lnh[cur]), LL = uview(I.lnl[cur]);
+  const GA<int32_t> HS = uview(I.hs[cur]);
   sw = {0.0, 0.0};
   swl = {0.0, 0.0};
   #pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
     const unsigned s = ident ? (unsigned)(k * NT + tid) : min((unsigned)perm[k * NT + tid], smax);
-    const double w = I.w[I.hs[cur][s]];
+    const double w = Wv[HS[s]];
     sw = dd_add_d(sw, w);
-    swl = dd_add(swl, dd_mul_d(dd{I.lnh[cur][s], I.lnl[cur][s]}, w));
+    swl = dd_add(swl, dd_mul_d(dd{LH[s], LL[s]}, w));
   }
 }
 
@@ -812,8 +862,17 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   } else {
     fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
   }
-  const dd tot0 = {I.tot0[0], I.tot0[1]};
+  const dd tot0 = {uni(I.tot0[0]), uni(I.tot0[1])};
   const double dxi = I.dxi;
+  const LogView LV = log_view(I);
+  IonView IV;
+  IV.R = uview(I.ion);
+  IV.N = N;
+  IV.Rp = I.Rp;
+  IV.T0 = tot0;
+  IV.Q = {uni(I.tot0[2]), uni(I.tot0[3])};
+  const GA<double> Wc = uview(I.w), WHc = uview(I.wh);
+  const GA<double> PSI = uview(I.psi), DPSI = uview(I.dpsi), BB = uview(I.bb), A2 = uview(I.a2), DA2 = uview(I.da2);
   const int n_an = I.n_an;
   const bool has_laser = I.has_laser != 0;
 
@@ -822,7 +881,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
     const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
-    const dd lr = ring_log(I, I.hs[cur][s], I.rho[cur][s]);
+    const dd lr = ring_log(LV, I.hs[cur][s], I.rho[cur][s]);
     I.lnh[cur][s] = lr.hi;
     I.lnl[cur][s] = lr.lo;
   }
@@ -866,9 +925,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
     const bool rec_last = n == end - 1;
     const int nb = 1 - cur;
-    const double* const rho_c = I.rho[cur];
-    const double* const u_c = I.u[cur];
-    const int32_t* const hs_c = I.hs[cur];
+    const GA<double> rho_c = uview(I.rho[cur]), u_c = uview(I.u[cur]);
+    const GA<int32_t> hs_c = uview(I.hs[cur]);
     int bt0 = 0, bm = 0;
     if (I.nb) {
       bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
@@ -886,9 +944,9 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     bad = 0.0;
     int blo = 0;
     // the next ring's state is loaded one ring ahead
-    const int32_t* const hint_c = I.hint[cur];
-    const double* const lnh_c = I.lnh[cur];
-    const double* const lnl_c = I.lnl[cur];
+    const GA<int32_t> hint_c = uview(I.hint[cur]);
+    const GA<double> lnh_c = uview(I.lnh[cur]), lnl_c = uview(I.lnl[cur]);
+    const GA<int32_t> hs_nb = uview(I.hs[nb]), hint_nb = uview(I.hint[nb]);
     double x_rho = 1.0, x_u = 0.0, x_lh = 0.0, x_ll = 0.0;
     int32_t x_hs = 0, x_h = 0;
     if (cnt > 0) {
@@ -907,13 +965,13 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const unsigned s = ident ? sn : min((unsigned)s_perm[sn], smax);
         x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
       }
-      const double w = I.w[hs], wh = I.wh[hs];
+      const double w = Wc[hs], wh = WHc[hs];
       const double irho = 1.0 / rho;
       const dd PTi = dd_add(PT, dd_mul_d(lnr, w));
       const dd pe = dd_sub(dd_mul(dd_add_d(S, w), lnr), PTi);    // psi_e - sum w ln rho
       const dd de = dd_div_rcp(dd_add_d(S, wh), rho, irho);         // d_rho psi_e (self w^)
       dd ips, idp;
-      ion_fields(I, rho, lnr, h, ips, idp);
+      ion_fields(IV, rho, lnr, h, ips, idp);
       const double psi = dd_round(dd_add(pe, ips)) + psi_axis;
       const double dpsi = dd_round(dd_add(de, idp));
       S = dd_add_d(S, w);
@@ -953,13 +1011,13 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       l0b += G.v[1] * s0b - G.v[3] * s0a;
       l1a += G.v[0] * s1b - G.v[2] * s1a;
       l1b += G.v[1] * s1b - G.v[3] * s1a;
-      I.psi[sl] = psi;
-      I.dpsi[sl] = dpsi;
-      I.bb[sl] = bb;
-      if (has_laser) { I.a2[sl] = aa; I.da2[sl] = dda; }
+      PSI.st(sl, psi);
+      DPSI.st(sl, dpsi);
+      BB.st(sl, bb);
+      if (has_laser) { A2.st(sl, aa); DA2.st(sl, dda); }
       // the ring's home slot and hint move to its position slot in the next buffer
-      I.hs[nb][sl] = hs;
-      I.hint[nb][sl] = h;
+      hs_nb.st(sl, hs);
+      hint_nb.st(sl, h);
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -996,19 +1054,18 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     int32_t nxt_i = 0x7fffffff, last_i = 0x7fffffff;
     dd sw2 = {0.0, 0.0}, swl2 = {0.0, 0.0};
     double dis_l = 0.0;
-    double* const rho_n = I.rho[nb];
-    double* const u_n = I.u[nb];
+    const GA<double> rho_n = uview(I.rho[nb]), u_n = uview(I.u[nb]), fr_n = uview(I.fr[nb]), fu_n = uview(I.fu[nb]);
+    const GA<double> lnh_n = uview(I.lnh[nb]), lnl_n = uview(I.lnl[nb]);
     // the next ring (one position back) is loaded one ring ahead
-    const int32_t* const hs_n = I.hs[nb];
-    const double* const fr_c = I.fr[cur];
-    const double* const fu_c = I.fu[cur];
+    const GA<int32_t> hs_n = uview(I.hs[nb]);
+    const GA<double> fr_c = uview(I.fr[cur]), fu_c = uview(I.fu[cur]);
     double y_rho = 1.0, y_u = 0.0, y_fr = 0.0, y_fu = 0.0, y_psi = 0.0, y_dpsi = 0.0, y_bb = 0.0;
     int32_t y_hs = 0;
     if (cnt > 0) {
       const unsigned sl = (cnt - 1) * NT + tid;
       const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
       y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
-      y_hs = hs_n[sl]; y_psi = I.psi[sl]; y_dpsi = I.dpsi[sl]; y_bb = I.bb[sl];
+      y_hs = hs_n[sl]; y_psi = PSI[sl]; y_dpsi = DPSI[sl]; y_bb = BB[sl];
     }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
@@ -1020,10 +1077,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const unsigned sp = sl - NT;
         const unsigned s = ident ? sp : min((unsigned)s_perm[sp], smax);
         y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
-        y_hs = hs_n[sp]; y_psi = I.psi[sp]; y_dpsi = I.dpsi[sp]; y_bb = I.bb[sp];
+        y_hs = hs_n[sp]; y_psi = PSI[sp]; y_dpsi = DPSI[sp]; y_bb = BB[sp];
       }
-      const double w = I.w[hs], wh = I.wh[hs];
-      const double a2 = has_laser ? I.a2[sl] : 0.0, da2 = has_laser ? I.da2[sl] : 0.0;
+      const double w = Wc[hs], wh = WHc[hs];
+      const double a2 = has_laser ? A2[sl] : 0.0, da2 = has_laser ? DA2[sl] : 0.0;
       const double irho = 1.0 / rho;
       const Local L = local_of(irho, u, w, psi, a2);
       const double dz = -(Vgt + (w - wh) * u * irho * L.ipb);
@@ -1066,10 +1123,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         double sr = f_r, su = f_u;
         if (rn < 0.0) { rn = -rn; un = -un; sr = -sr; su = -su; }
         if (!(isfinite(rn) && isfinite(un))) bad = 1.0;
-        rho_n[sl] = rn; u_n[sl] = un; I.fr[nb][sl] = sr; I.fu[nb][sl] = su;
-        const dd lr = ring_log(I, hs, rn);
-        I.lnh[nb][sl] = lr.hi;
-        I.lnl[nb][sl] = lr.lo;
+        rho_n.st(sl, rn); u_n.st(sl, un); fr_n.st(sl, sr); fu_n.st(sl, su);
+        const dd lr = ring_log(LV, hs, rn);
+        lnh_n.st(sl, lr.hi);
+        lnl_n.st(sl, lr.lo);
         sw2 = dd_add_d(sw2, w);
         swl2 = dd_add(swl2, dd_mul_d(lr, w));
         if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
