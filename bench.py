@@ -170,11 +170,21 @@ def main():
 
     flops = ALG_FLOPS_PER_RING_SLICE * work
     achieved = flops / avg_kernel_s
+    # measured HBM traffic of one march dispatch of this workload, if the
+    # counters were taken on the current marcher sources
+    from paper_2603_16623_amd.profile_summary import read_traffic
+    workload = f"batched-{args.n_inst}x[1000,8000]rings-x{args.n_xi}slices"
+    tr = read_traffic(os.path.join(ROOT, "profiles", "wake_march_kernel_traffic.txt"))
+    traffic = None
+    if tr is not None and tr.get("workload") == workload:
+        traffic = float(tr["fetch_bytes_per_dispatch"]) + float(tr["write_bytes_per_dispatch"])
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_VECTOR / 1e12,
-                unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR, traffic=None,
+                unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR, traffic=traffic,
                 kernel="wake_march_kernel", kernel_ms=float(np.mean(kernel_ms)),
                 alg_flops_per_ring_slice=ALG_FLOPS_PER_RING_SLICE,
-                hbm_alg_GBps=ALG_BYTES_PER_RING_SLICE * work / avg_kernel_s / 1e9)
+                hbm_alg_GBps=ALG_BYTES_PER_RING_SLICE * work / avg_kernel_s / 1e9,
+                hbm_measured_GBps=None if traffic is None else traffic / avg_kernel_s / 1e9,
+                traffic_B_per_ring_slice=None if traffic is None else traffic / work)
 
     out = {
         "metric": METRIC,
@@ -189,7 +199,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"batched-{args.n_inst}x[1000,8000]rings-x{args.n_xi}slices",
+        "config": {"workload": workload,
                    "instances": args.n_inst, "ring_slices_per_step": work,
                    "tiling": {"threads": nt, "wgs_per_cu": wpc}, "breakdowns": breakdowns},
         "plain_single_instance": {"value": plain_value, "unit": "ring-slice updates/s",

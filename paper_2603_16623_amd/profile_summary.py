@@ -1,0 +1,112 @@
+"""Summaries of rocprofv3 output for the march kernel (markdown, a few KB).
+
+    python -m paper_2603_16623_amd.profile_summary trace DIR TITLE COMMAND > summary.md
+    python -m paper_2603_16623_amd.profile_summary traffic MARCH_DIR COPY_DIR COPY_MIB WORKLOAD > traffic.txt
+
+`trace`: DIR holds the CSV files of `rocprofv3 --kernel-trace --stats --output-format csv`;
+prints the march dispatches and the top kernels.
+`traffic`: MARCH_DIR / COPY_DIR hold `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs
+(subfolders FETCH_SIZE/ and WRITE_SIZE/) of the profiling driver and of a plain copy of COPY_MIB
+MiB; prints HBM bytes per march dispatch, each counter scaled by copy bytes / counter reading
+of the copy, and the digest of the marcher sources the counters belong to.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MARCH_SOURCES = ["wake_march.hip", "wake_device.h", "wake_common.h"]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in MARCH_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(pattern):
+    out = []
+    for f in sorted(glob.glob(pattern, recursive=True)):
+        with open(f) as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def trace(d, title, command):
+    trace_rows = _rows(os.path.join(d, "**", "*kernel_trace.csv"))
+    stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
+    print(f"# {title}\n\nCommand (GPU box, repository root as $R):\n\n    {command}\n")
+    march = [r for r in trace_rows if "wake_march_kernel" in r.get("Kernel_Name", "")]
+    if march:
+        print("March dispatches in order:\n")
+        print("| dispatch | duration ms | grid threads | workgroup | arch VGPR | acc VGPR | SGPR | LDS B | scratch B |")
+        print("|---|---|---|---|---|---|---|---|---|")
+        for r in march:
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            print(f"| {r.get('Dispatch_Id', '')} | {dur:.3f} | {r.get('Grid_Size_X', r.get('Grid_Size', ''))} | "
+                  f"{r.get('Workgroup_Size_X', r.get('Workgroup_Size', ''))} | {r.get('VGPR_Count', '')} | "
+                  f"{r.get('Accum_VGPR_Count', '')} | {r.get('SGPR_Count', '')} | {r.get('LDS_Block_Size', '')} | "
+                  f"{r.get('Scratch_Size', '')} |")
+        print()
+    if stats:
+        print("Kernels by total time:\n")
+        print("| kernel | calls | avg ms | min ms | max ms | total ms |")
+        print("|---|---|---|---|---|---|")
+        stats.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+        for r in stats[:12]:
+            name = r["Name"][:90]
+            print(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                  f"{float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} | "
+                  f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+
+
+def _counter(d, name, kernel_sub):
+    vals = []
+    for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+        if r["Counter_Name"] == name and kernel_sub in r["Kernel_Name"]:
+            vals.append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic(march_dir, copy_dir, copy_mib, workload):
+    copy_bytes = float(copy_mib) * (1 << 20)
+    out = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = _counter(os.path.join(copy_dir, c), c, "copyBuffer")
+        m = _counter(os.path.join(march_dir, c), c, "wake_march_kernel")
+        scale = copy_bytes / (cal[-1] * 1024.0)
+        out[c] = (m[-1] * 1024.0 * scale, scale, m[-1])
+    print(f"workload: {workload}")
+    print(f"source_digest: {source_digest()}")
+    print(f"fetch_bytes_per_dispatch: {out['FETCH_SIZE'][0]:.6e}")
+    print(f"write_bytes_per_dispatch: {out['WRITE_SIZE'][0]:.6e}")
+    print(f"fetch_counter_KiB: {out['FETCH_SIZE'][2]:.6e}  (copy calibration x{out['FETCH_SIZE'][1]:.4f})")
+    print(f"write_counter_KiB: {out['WRITE_SIZE'][2]:.6e}  (copy calibration x{out['WRITE_SIZE'][1]:.4f})")
+
+
+def read_traffic(path):
+    """Traffic figures of a summary file, if it belongs to the current sources."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if kv.get("source_digest") != source_digest():
+        return None
+    return kv
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
