@@ -195,6 +195,48 @@ int wake_batch_replay(wake_batch *b);
 int wake_batch_sync(wake_batch *b);
 void wake_batch_destroy(wake_batch *b);
 
+/* ---------------------------------------------------------------------
+ * Served form: continuous batching of independent solves (a parameter scan
+ * issuing requests of different ring counts and window lengths).  Requests
+ * are queued with their inputs copied; each wake_server_step admits queued
+ * requests in arrival order while their device footprint (wake_footprint at
+ * the server's tiling) fits device_bytes (a request larger than the whole
+ * budget is admitted alone when nothing else is resident), marches every
+ * resident request by up to slices_per_step slices in one persistent launch,
+ * and retires those that reached their window end or broke down (on-axis
+ * lineout and final fields copied to the host, device memory released).
+ * Ring state stays on the device between steps.  A request's result is
+ * bitwise the result of solving it alone with wake_solve.  One host thread
+ * at a time per server.
+ * --------------------------------------------------------------------- */
+typedef struct wake_server wake_server;
+
+typedef struct {
+  int32_t threads;          /* workgroup threads of the server's contexts (0: current tiling) */
+  int32_t slices_per_step;  /* slices each resident request advances per step (> 0) */
+  int32_t max_active;       /* cap on resident requests (0: none) */
+  int64_t device_bytes;     /* device-memory budget of the resident requests (> 0) */
+} wake_server_config;
+
+int wake_server_create(wake_server **out, const wake_server_config *cfg, void *hip_stream);
+/* Queue one solve (sources as for wake_add_beam).  *ticket names it. */
+int wake_server_submit(wake_server *s, const wake_plasma *plasma, const wake_domain *domain,
+                       const wake_source *sources, int32_t n_sources, int64_t *ticket);
+/* Admit, march one step, retire (synchronous).  Counts after the step:
+ * resident, still queued, retired by this step. */
+int wake_server_step(wake_server *s, int32_t *n_active, int32_t *n_queued, int32_t *n_done);
+/* Result of a retired request, then released: returns WAKE_OK, WAKE_EBREAKDOWN
+ * (lineout up to the breakdown slice, no final fields), another negative
+ * status if it could not run, or WAKE_ESTATE if not retired yet.  Lineout
+ * [n_xi] each; final fields at the last slice by ring id [n_rings] each;
+ * NULL skips. */
+int wake_server_result(wake_server *s, int64_t ticket, int32_t *breakdown_slice, double *psi_axis,
+                       double *ez_axis, double *psi, double *er_minus_bt, double *ez, double *bt,
+                       double *rho, double *ur);
+int wake_server_stats(wake_server *s, int64_t *bytes_in_use, int32_t *n_active, int32_t *n_queued,
+                      int32_t *n_results);
+void wake_server_destroy(wake_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,23 +11,13 @@
 #include "../../include/wake.h"
 #include "wake_common.h"
 #include "wake_launch.h"
+#include "wake_runtime.h"
 
 namespace {
 
 int g_nt = 512;      // workgroup threads of new contexts (slot layout)
 int g_wpc = 0;       // workgroups per compute unit of persistent launches (0: occupancy)
 
-struct Arena {
-  char* base = nullptr;
-  size_t size = 0, used = 0;
-  template <class T>
-  T* take(size_t n) {
-    used = (used + 255) & ~size_t(255);
-    T* p = reinterpret_cast<T*>(base + used);
-    used += n * sizeof(T);
-    return p;
-  }
-};
 
 // Bytes of the per-context arena (mirrors the carving in wake_create).
 // S = slots of the per-ring arrays (C * nt >= N).
@@ -56,24 +46,6 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
 
 }  // namespace
 
-struct wake_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  WakeInst I;
-  WakeInst* d_inst = nullptr;
-  int32_t* d_counter = nullptr;
-  Arena arena;
-  double* staging = nullptr;   // 4N doubles
-  // beam table (persistent part)
-  char* beam_mem = nullptr;
-  // pending particle sources (host copies until the table is built)
-  std::vector<double> px, py, pxi, pw, pq;
-  bool prepared = false;
-  int next = 0;
-  hipStream_t pending = nullptr;   // batch stream that last marched this context
-};
-
 struct wake_batch {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -86,13 +58,7 @@ struct wake_batch {
   hipGraphExec_t exec = nullptr;
 };
 
-static int dev_err(hipError_t e) { return e == hipErrorOutOfMemory ? WAKE_ENOMEM : WAKE_EDEVICE; }
-
-#define HIP_TRY(x)                              \
-  do {                                          \
-    hipError_t e_ = (x);                        \
-    if (e_ != hipSuccess) return dev_err(e_);   \
-  } while (0)
+int dev_err(hipError_t e) { return e == hipErrorOutOfMemory ? WAKE_ENOMEM : WAKE_EDEVICE; }
 
 extern "C" const char* wake_strerror(int code) {
   switch (code) {
@@ -107,16 +73,21 @@ extern "C" const char* wake_strerror(int code) {
   }
 }
 
-extern "C" int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles,
-                                  int32_t record_stride) {
+int64_t ctx_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_t record_stride,
+                      int nt) {
   if (n_rings <= 0 || n_xi <= 0 || n_particles < 0 || record_stride < 0) return -1;
-  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, g_nt);
+  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, nt);
   // persistent beam table: offsets + (r, cumulative charge) per entry
   b += 4 * (int64_t)(n_xi + 1) + 16 * 2 * n_particles + 1024;
   // transient build buffers (particles, counts, padded entries)
   b += 40 * n_particles + 20 * (int64_t)(n_xi + 1) + 24 * 4 * n_particles + 2048;
   b += sizeof(WakeInst) + 512;
   return b;
+}
+
+extern "C" int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles,
+                                  int32_t record_stride) {
+  return ctx_footprint(n_rings, n_xi, n_particles, record_stride, g_nt);
 }
 
 static void release(wake_ctx* c) {
@@ -135,9 +106,10 @@ extern "C" void wake_destroy(wake_ctx* ctx) { release(ctx); }
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom,
-                           void* hip_stream) {
+int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
+               int nt) {
   if (!out) return WAKE_EINVAL;
+  if (!march_threads_ok(nt)) return WAKE_EINVAL;
   *out = nullptr;
   if (!plasma || !dom || plasma->n_rings <= 0 || !plasma->r0 || !plasma->dr) return WAKE_EINVAL;
   const int N = plasma->n_rings;
@@ -175,8 +147,8 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
   I.dxi = dom->dxi;
   I.Rp = plasma->r0[N - 1] + plasma->dr[N - 1] / 2.0;
   I.inv2pidxi = 1.0 / (2.0 * M_PI * I.dxi);
-  I.nt = g_nt;
-  I.C = (N + g_nt - 1) / g_nt;
+  I.nt = nt;
+  I.C = (N + nt - 1) / nt;
   const size_t S = (size_t)I.C * I.nt;
   const size_t bytes = arena_bytes(N, I.n_xi, I.stride, I.nt);
   hipError_t e = hipMalloc(&c->arena.base, bytes);
@@ -241,6 +213,11 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
   if (e != hipSuccess) { release(c); return dev_err(e); }
   *out = c;
   return WAKE_OK;
+}
+
+extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom,
+                           void* hip_stream) {
+  return ctx_create(out, plasma, dom, hip_stream, g_nt);
 }
 
 extern "C" int wake_add_beam(wake_ctx* c, const wake_source* s) {
@@ -360,7 +337,7 @@ extern "C" int wake_prepare(wake_ctx* c) {
   return WAKE_OK;
 }
 
-static int drain(wake_ctx* c) {
+int drain(wake_ctx* c) {
   if (c->pending) {
     HIP_TRY(hipStreamSynchronize(c->pending));
     c->pending = nullptr;
@@ -563,7 +540,7 @@ extern "C" int wake_tiling_occupancy(int32_t nt, int32_t wpc) {
 }
 
 // persistent grid for nt-thread workgroups
-static int march_grid(int nt, int n_insts, int dev) {
+int march_grid(int nt, int n_insts, int dev) {
   const int occ = std::max(1, march_occupancy(nt));
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
@@ -643,20 +620,24 @@ static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vec
   return (int)v.size();
 }
 
-// one persistent launch per distinct workgroup size present in v (v is
-// sorted longest-first; each launch takes the instances of its size)
-static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v, int grid_override) {
-  int off = 0;
+// one persistent launch per distinct workgroup size present in v (the
+// descriptors are already at d_insts; each launch takes the instances of its
+// size from the shared queue)
+hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts, int32_t* d_counter,
+                        int dev, int grid_override, hipStream_t s) {
   for (int nt : kThreads) {
     int n = 0;
     for (const WakeInst& I : v) n += I.nt == nt;
     if (n == 0) continue;
-    (void)off;
-    const int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, b->device);
-    hipError_t e = launch_march(nt, b->d_insts, (int)v.size(), b->d_counter, g, b->stream);
+    const int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, dev);
+    hipError_t e = launch_march(nt, d_insts, (int)v.size(), d_counter, g, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v, int grid_override) {
+  return launch_insts(v, b->d_insts, b->d_counter, b->device, grid_override, b->stream);
 }
 
 extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {

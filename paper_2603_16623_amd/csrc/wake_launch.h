@@ -16,6 +16,7 @@ hipError_t launch_state_by_id(const WakeInst& I, double* rho, double* u, double*
 hipError_t launch_state_set(const WakeInst& I, const double* rho, const double* u, const double* fr,
                             const double* fu, int slice, hipStream_t s);
 hipError_t launch_reset(const WakeInst* d_insts, int n_insts, hipStream_t s);
+hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipStream_t s);
 
 // marcher: workgroups of nt threads (256, 512 or 1024)
 bool march_threads_ok(int nt);

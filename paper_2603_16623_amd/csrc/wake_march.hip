@@ -449,7 +449,7 @@ __device__ __forceinline__ void stage_move(const WakeInst& I, int buf, int tmp, 
 // puts buffer `buf` itself in (rho, id) order, moving the rings through the
 // other buffer `tmp`.
 template <int NT>
-__device__ __noinline__ void fix_order_global(const WakeInst& I, int buf, int tmp, double* s_scan,
+__device__ __noinline__ bool fix_order_global(const WakeInst& I, int buf, int tmp, double* s_scan,
                                               unsigned char* region) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C;
@@ -492,7 +492,7 @@ __device__ __noinline__ void fix_order_global(const WakeInst& I, int buf, int tm
   }
   __syncthreads();
   // classify: 0 = in place, 1 = short run (ranked here), 2 = long run
-  double nlong = 0.0;
+  double nlong = 0.0, nmoved = 0.0;
   #pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
     const int p = tid * C + k;
@@ -521,11 +521,13 @@ __device__ __noinline__ void fix_order_global(const WakeInst& I, int buf, int tm
         cls = 2;
         nlong += 1.0;
       }
+      nmoved += 1.0;
     }
     I.cls[sl] = cls;
   }
-  Pack<1> tot;
-  const Pack<1> j0p = block_prefix<NT, 1>(Pack<1>{{nlong}}, Pack<1>{{0.0}}, SumOp<1>(), s_scan, tot);
+  Pack<2> tot;
+  const Pack<2> j0p = block_prefix<NT, 2>(Pack<2>{{nlong, nmoved}}, Pack<2>{{0.0, 0.0}}, SumOp<2>(),
+                                          s_scan, tot);
   const int M = (int)tot.v[0];
   if (M > 0) {
     const bool in_lds = M <= WAKE_SORTCAP;
@@ -568,6 +570,7 @@ __device__ __noinline__ void fix_order_global(const WakeInst& I, int buf, int tm
     stage_move(I, tmp, buf, sl, sl);
   }
   __syncthreads();
+  return tot.v[1] != 0.0;
 }
 
 // LDS index (slot form) of position p: (p % C) * NT + p / C, with p / C from
@@ -849,6 +852,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   __syncthreads();
   // injected states may be unsorted
   bool ident = true;
+  bool moved = false;       // a chunk holds rings of another chunk after the fix-up
   if (lds_keys) {
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
@@ -859,8 +863,9 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     __syncthreads();
     fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
     ident = false;
+    for (int k = 0; k < cnt; ++k) moved |= (s_perm[k * NT + tid] & (NT - 1)) != (unsigned)tid;
   } else {
-    fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
+    moved = fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
   }
   const dd tot0 = {uni(I.tot0[0]), uni(I.tot0[1])};
   const double dxi = I.dxi;
@@ -885,8 +890,23 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     I.lnh[cur][s] = lr.hi;
     I.lnl[cur][s] = lr.lo;
   }
-  dd sw, swl;
-  chunk_sums<NT>(I, cur, cnt, ident, s_perm, sw, swl);
+  // The sums in the order the march itself would have left them in (so that
+  // a solve split over several launches is bitwise the one-launch solve):
+  // chunks that took rings of another chunk in the fix-up sum forward, the
+  // others backward as the push does.
+  dd sw = {0.0, 0.0}, swl = {0.0, 0.0};
+  if (moved) {
+    chunk_sums<NT>(I, cur, cnt, ident, s_perm, sw, swl);
+  } else {
+    #pragma unroll 1
+    for (int k = cnt - 1; k >= 0; --k) {
+      const unsigned sl = k * NT + tid;
+      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+      const double w = Wc[I.hs[cur][s]];
+      sw = dd_add_d(sw, w);
+      swl = dd_add(swl, dd_mul_d(dd{I.lnh[cur][s], I.lnl[cur][s]}, w));
+    }
+  }
   int n = I.first;
   const int end = I.first + I.count;
   if (n < end) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
@@ -1233,9 +1253,22 @@ __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_ins
   if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; }
 }
 
+// Control words of a list of instances into one buffer (4 words each).
+__global__ void ctl_gather_kernel(const WakeInst* __restrict__ insts, int n, int32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int w = 0; w < CTL_NWORDS; ++w) out[i * CTL_NWORDS + w] = insts[i].ctl[w];
+}
+
 // ---------------------------------------------------------------------------
 // host-callable launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ctl_gather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_insts, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, const double* dens,
                        hipStream_t s) {
   hipLaunchKernelGGL((wake_init_kernel<256>), dim3(1), dim3(256), 0, s, I, r0, dr, dens);

@@ -1,0 +1,63 @@
+// Host runtime internals shared by the C ABI (wake_api.cpp) and the
+// request server (wake_serve.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/wake.h"
+#include "wake_common.h"
+
+// bump allocation of one context's device arena (256-B aligned pieces)
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  template <class T>
+  T* take(size_t n) {
+    used = (used + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + used);
+    used += n * sizeof(T);
+    return p;
+  }
+};
+
+struct wake_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  WakeInst I;
+  WakeInst* d_inst = nullptr;
+  int32_t* d_counter = nullptr;
+  Arena arena;
+  double* staging = nullptr;   // 4N doubles
+  // beam table (persistent part)
+  char* beam_mem = nullptr;
+  // pending particle sources (host copies until the table is built)
+  std::vector<double> px, py, pxi, pw, pq;
+  bool prepared = false;
+  int next = 0;
+  hipStream_t pending = nullptr;   // batch stream that last marched this context
+};
+
+
+int dev_err(hipError_t e);
+
+#define HIP_TRY(x)                              \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return dev_err(e_);   \
+  } while (0)
+
+// wait for every stream that may still work on the context
+int drain(wake_ctx* c);
+// persistent grid for nt-thread workgroups over n instances
+int march_grid(int nt, int n_insts, int dev);
+// one persistent launch per distinct workgroup size over the descriptors v
+// (already copied to d_insts)
+hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts, int32_t* d_counter,
+                        int dev, int grid_override, hipStream_t s);
+// context creation / footprint with an explicit workgroup size
+int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
+               int nt);
+int64_t ctx_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_t record_stride,
+                      int nt);

@@ -45,6 +45,11 @@ class _Source(C.Structure):
                 ("xi_l", C.c_double)]
 
 
+class _ServerConfig(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("slices_per_step", C.c_int32), ("max_active", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+
 _I, _P, _D, _I64 = C.c_int32, C.c_void_p, C.c_double, C.c_int64
 _SIGS = {
     "wake_create": (_I, [C.POINTER(_P), C.POINTER(_Plasma), C.POINTER(_Domain), _P]),
@@ -72,6 +77,13 @@ _SIGS = {
     "wake_batch_replay": (_I, [_P]),
     "wake_batch_sync": (_I, [_P]),
     "wake_batch_destroy": (None, [_P]),
+    "wake_server_create": (_I, [C.POINTER(_P), C.POINTER(_ServerConfig), _P]),
+    "wake_server_submit": (_I, [_P, C.POINTER(_Plasma), C.POINTER(_Domain), C.POINTER(_Source), _I,
+                                C.POINTER(_I64)]),
+    "wake_server_step": (_I, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    "wake_server_result": (_I, [_P, _I64, C.POINTER(_I), _P, _P, _P, _P, _P, _P, _P, _P]),
+    "wake_server_stats": (_I, [_P, C.POINTER(_I64), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    "wake_server_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -289,3 +301,74 @@ class WakeBatch:
 
     def wake_batch_sync(self):
         _check(self._lib.wake_batch_sync(self.h), "wake_batch_sync")
+
+
+class WakeServer:
+    """Continuous batching of independent solves (wake_server_*)."""
+
+    def __init__(self, device_bytes: int, slices_per_step: int = 100, threads: int = 0,
+                 max_active: int = 0, stream: Optional[int] = None):
+        lib = load()
+        self._lib = lib
+        cfg = _ServerConfig(int(threads), int(slices_per_step), int(max_active), int(device_bytes))
+        h = _P()
+        _check(lib.wake_server_create(C.byref(h), C.byref(cfg), stream), "wake_server_create")
+        self.h = h
+        self.meta = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._lib.wake_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def submit(self, r0, dr, dxi: float, n_xi: int, sources: Sequence = (), dens=None) -> int:
+        r0, dr = _host(r0), _host(dr)
+        dens = None if dens is None else _host(dens)
+        pl = _Plasma(len(r0), r0.ctypes.data, dr.ctypes.data, None if dens is None else dens.ctypes.data)
+        dm = _Domain(float(dxi), int(n_xi), 0)
+        structs, keep = [], []
+        for src in sources:
+            st, k = _source_struct(src)
+            structs.append(st)
+            keep.append(k)
+        arr = (_Source * max(1, len(structs)))(*structs)
+        t = _I64()
+        _check(self._lib.wake_server_submit(self.h, C.byref(pl), C.byref(dm), arr, len(structs),
+                                            C.byref(t)), "wake_server_submit")
+        del keep
+        self.meta[t.value] = (len(r0), int(n_xi))
+        return t.value
+
+    def submit_instance(self, inst) -> int:
+        return self.submit(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+
+    def step(self):
+        a, q, d = _I(), _I(), _I()
+        _check(self._lib.wake_server_step(self.h, C.byref(a), C.byref(q), C.byref(d)), "wake_server_step")
+        return a.value, q.value, d.value
+
+    def result(self, ticket: int):
+        """dict with status, breakdown, psi_axis, ez_axis and the final fields (or
+        None while the request is not finished)."""
+        N, n_xi = self.meta[ticket]
+        out = {k: np.empty(n_xi) for k in ("psi_axis", "ez_axis")}
+        out.update({k: np.empty(N) for k in ("psi", "er_bt", "ez", "bt", "rho", "ur")})
+        brk = _I()
+        r = self._lib.wake_server_result(self.h, ticket, C.byref(brk),
+                                         *[out[k].ctypes.data for k in ("psi_axis", "ez_axis", "psi",
+                                                                        "er_bt", "ez", "bt", "rho",
+                                                                        "ur")])
+        if r == WAKE_ESTATE:
+            return None
+        del self.meta[ticket]
+        out["status"] = r
+        out["breakdown"] = brk.value
+        return out
+
+    def stats(self):
+        b, a, q, n = _I64(), _I(), _I(), _I()
+        _check(self._lib.wake_server_stats(self.h, C.byref(b), C.byref(a), C.byref(q), C.byref(n)),
+               "wake_server_stats")
+        return dict(bytes_in_use=b.value, active=a.value, queued=q.value, results=n.value)

@@ -1,0 +1,122 @@
+"""Served form and chunked marching: results do not depend on the mix.
+
+A solve split over several launches must be bitwise the one-launch solve
+(the march restarts from the stored state and rebuilds its sums in the same
+order), so a request served in a mix of others, stepped a few slices at a
+time, returns exactly what solving it alone returns.
+"""
+import numpy as np
+import pytest
+
+from paper_2603_16623_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("psi", "er_bt", "ez", "bt", "rho", "ur")
+
+
+@pytest.fixture(scope="module")
+def wk():
+    from paper_2603_16623_amd import wake
+    wake.load()
+    wake.wake_set_tiling(512, 0)
+    yield wake
+    wake.wake_set_tiling(512, 0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _alone(wk, inst):
+    s = wk.WakeSolver.from_instance(inst)
+    s.wake_solve(0, inst.n_xi)
+    out = dict(s.wake_fields(-1))
+    out["psi_axis"], out["ez_axis"] = s.wake_lineout()
+    s.close()
+    return out
+
+
+def _mix(seed, sizes):
+    rng = np.random.default_rng(seed)
+    return [W.batched_instance(rng, n, n_xi, n_drv=2500, n_wit=800, r_max=4.0) for n, n_xi in sizes]
+
+
+def test_chunked_solve_is_bitwise_one_solve(wk):
+    # 9000 rings: keys beyond LDS (global order fix-up); 700: LDS permutation path
+    for n, n_xi in ((700, 140), (9000, 60)):
+        inst = _mix(51 + n, [(n, n_xi)])[0]
+        _say("chunked", n)
+        ref = _alone(wk, inst)
+        s = wk.WakeSolver.from_instance(inst)
+        cuts = sorted({0, 7, 8, 31, n_xi // 2, n_xi})
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            s.wake_solve(a, b - a)
+        got = s.wake_fields(-1)
+        lp, le = s.wake_lineout()
+        for q in FIELDS:
+            assert np.array_equal(got[q], ref[q]), (n, q)
+        assert np.array_equal(lp, ref["psi_axis"]) and np.array_equal(le, ref["ez_axis"]), n
+        s.close()
+
+
+def test_served_results_equal_alone(wk):
+    sizes = [(300, 90), (1500, 60), (777, 130), (64, 40), (2100, 75), (9000, 30), (1200, 110)]
+    insts = _mix(61, sizes)
+    _say("served mix")
+    ref = [_alone(wk, inst) for inst in insts]
+    srv = wk.WakeServer(device_bytes=8 << 30, slices_per_step=17)
+    tickets = {}
+    # requests arrive while others are resident
+    for i in range(3):
+        tickets[srv.submit_instance(insts[i])] = i
+    results = {}
+    pending = list(range(3, len(insts)))
+    steps = 0
+    while len(results) < len(insts):
+        if pending and steps % 2 == 1:
+            i = pending.pop(0)
+            tickets[srv.submit_instance(insts[i])] = i
+        srv.step()
+        steps += 1
+        assert steps < 200
+        for t, i in list(tickets.items()):
+            r = srv.result(t)
+            if r is not None:
+                results[i] = r
+                del tickets[t]
+    for i, r in results.items():
+        assert r["status"] == 0, i
+        for q in FIELDS:
+            assert np.array_equal(r[q], ref[i][q]), (i, q)
+        assert np.array_equal(r["psi_axis"], ref[i]["psi_axis"]), i
+        assert np.array_equal(r["ez_axis"], ref[i]["ez_axis"]), i
+    st = srv.stats()
+    assert st["active"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_served_admission_respects_the_footprint_budget(wk):
+    sizes = [(1000, 50), (1400, 40), (900, 60), (1100, 30), (1300, 45)]
+    insts = _mix(71, sizes)
+    fps = [wk.wake_footprint(i.n_rings, i.n_xi, sum(len(s.x) for s in i.sources)) for i in insts]
+    budget = max(fps) + min(fps)          # never more than two resident at once
+    _say("admission budget", budget)
+    srv = wk.WakeServer(device_bytes=budget, slices_per_step=20)
+    tickets = [srv.submit_instance(i) for i in insts]
+    done = 0
+    steps = 0
+    while done < len(insts):
+        srv.step()
+        steps += 1
+        st = srv.stats()
+        assert st["bytes_in_use"] <= budget
+        assert st["active"] <= 2
+        for t in tickets:
+            if t in srv.meta:
+                r = srv.result(t)
+                if r is not None:
+                    assert r["status"] == 0
+                    done += 1
+        assert steps < 200
+    srv.close()
