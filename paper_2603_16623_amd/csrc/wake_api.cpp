@@ -33,7 +33,7 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
   i += 4 * S;                               // home slot, hint x2
   d += 5 * S;                               // slice scratch
   d += 1 * S;                               // fix-up: suffix minimum
-  i += 3 * S;                               // fix-up: suffix min id, flags, classes
+  i += 4 * S;                               // fix-up: order, prefix max id, flags, run starts
   d += 2 * (size_t)N;                       // sort keys x2
   i += 4 * (size_t)N + (size_t)N;           // sort ids/slots x2, free slots
   d += 2 * (size_t)n_xi;                    // axis
@@ -179,6 +179,7 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   I.bb = A.take<double>(S);
   I.a2 = A.take<double>(S);
   I.da2 = A.take<double>(S);
+  I.perm = A.take<int32_t>(S);
   I.sm_r = A.take<double>(S);
   I.sm_i = A.take<int32_t>(S);
   I.flag = A.take<int32_t>(S);

@@ -38,11 +38,11 @@ struct WakeAnalytic {
 // that while rings stay near their initial order the constant gathers of a
 // wavefront stay contiguous.
 //
-// Order.  Rings are kept in (rho, id) order.  When the keys of every
-// position fit in LDS, a slice whose pushed radii come out of order only
-// computes the new order as a permutation (sorted position -> slot) in LDS;
-// the next slice reads through it and writes its pushed rings in the new
-// order.  Otherwise the buffer itself is reordered in global memory.
+// Order.  Rings are kept in (rho, id) order.  A slice whose pushed radii come
+// out of order only computes the new order as a permutation (sorted position
+// -> slot), in LDS when the keys of every position fit there, else in global
+// memory; the next slice reads through it and writes its pushed rings at the
+// slots of the new positions.
 struct WakeInst {
   int32_t N;          // rings
   int32_t n_xi;       // slices of the window
@@ -74,8 +74,10 @@ struct WakeInst {
   // slice scratch by position slot: psi, d_rho psi, B^(b), laser |a|^2 and
   // d_rho |a|^2
   double *psi, *dpsi, *bb, *a2, *da2;
-  // order fix-up scratch in global memory: running suffix minimum key, run
-  // boundaries and classes, long-run sort keys
+  // order fix-up with global keys: ring order (sorted position, slot form ->
+  // slot), prefix maximum keys, run boundaries, run starts / long-run marks,
+  // long-run sort keys
+  int32_t *perm;
   double *sm_r;
   int32_t *sm_i, *flag, *cls;
   double *sk_r[2];

@@ -432,152 +432,11 @@ __device__ int sort_keys_global(const WakeInst& I, int M, double* kr, int32_t* k
 // (each long run keeps its position range, so the j-th smallest goes to the
 // j-th freed position).
 
-// Copy the ring at slot `src` of buffer `buf` into slot `dst` of buffer tmp.
-__device__ __forceinline__ void stage_move(const WakeInst& I, int buf, int tmp, unsigned src,
-                                           unsigned dst) {
-  I.rho[tmp][dst] = I.rho[buf][src];
-  I.u[tmp][dst] = I.u[buf][src];
-  I.fr[tmp][dst] = I.fr[buf][src];
-  I.fu[tmp][dst] = I.fu[buf][src];
-  I.hs[tmp][dst] = I.hs[buf][src];
-  I.hint[tmp][dst] = I.hint[buf][src];
-  I.lnh[tmp][dst] = I.lnh[buf][src];
-  I.lnl[tmp][dst] = I.lnl[buf][src];
-}
-
-// Order fix-up in global memory (instances whose keys do not fit in LDS):
-// puts buffer `buf` itself in (rho, id) order, moving the rings through the
-// other buffer `tmp`.
+// Slot form of position p: (p % C) * NT + p / C, with p / C from a
+// reciprocal estimate corrected to the exact quotient.
 template <int NT>
-__device__ __noinline__ bool fix_order_global(const WakeInst& I, int buf, int tmp, double* s_scan,
-                                              unsigned char* region) {
-  const int tid = threadIdx.x;
-  const int N = I.N, C = I.C;
-  const int cnt = max(0, min(C, N - tid * C));
-  const double* R = I.rho[buf];
-  const int32_t* HS = I.hs[buf];
-  // chunk extremes
-  Pack<2> mx = {{-INFINITY, -2147483648.0}}, mn = {{INFINITY, 2147483647.0}};
-  #pragma unroll 1
-  for (int k = 0; k < cnt; ++k) {
-    const unsigned sl = k * NT + tid;
-    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
-    mx = MaxKeyOp()(mx, key);
-    mn = MinKeyOp()(mn, key);
-  }
-  Pack<2> before, tb, after, ta;
-  block_prefix_suffix<NT, 2, 2>(mx, Pack<2>{{-INFINITY, -2147483648.0}}, MaxKeyOp(), mn,
-                                Pack<2>{{INFINITY, 2147483647.0}}, MinKeyOp(), s_scan, before, tb,
-                                after, ta);
-  // minimum key from each position on
-  Pack<2> sm = after;
-  #pragma unroll 1
-  for (int k = cnt - 1; k >= 0; --k) {
-    const unsigned sl = k * NT + tid;
-    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
-    sm = MinKeyOp()(sm, key);
-    I.sm_r[sl] = sm.v[0];
-    I.sm_i[sl] = (int32_t)sm.v[1];
-  }
-  // run boundaries
-  Pack<2> pm = before;
-  #pragma unroll 1
-  for (int k = 0; k < cnt; ++k) {
-    const unsigned sl = k * NT + tid;
-    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
-    const bool bnd = (tid == 0 && k == 0) ||
-                     key_lt(pm.v[0], (int32_t)pm.v[1], I.sm_r[sl], I.sm_i[sl]);
-    I.flag[sl] = bnd ? 1 : 0;
-    pm = MaxKeyOp()(pm, key);
-  }
-  __syncthreads();
-  // classify: 0 = in place, 1 = short run (ranked here), 2 = long run
-  double nlong = 0.0, nmoved = 0.0;
-  #pragma unroll 1
-  for (int k = 0; k < cnt; ++k) {
-    const int p = tid * C + k;
-    const unsigned sl = k * NT + tid;
-    const bool b0 = I.flag[sl] != 0;
-    const bool b1 = p + 1 >= N || I.flag[slot_of(p + 1, C, NT)] != 0;
-    int cls = 0;
-    if (!(b0 && b1)) {
-      int a = p;
-      while (p - a < WAKE_SEGMAX && I.flag[slot_of(a, C, NT)] == 0) --a;
-      int e = p + 1;
-      while (e - p <= WAKE_SEGMAX && e < N && I.flag[slot_of(e, C, NT)] == 0) ++e;
-      const bool closed = I.flag[slot_of(a, C, NT)] != 0 && (e >= N || I.flag[slot_of(e, C, NT)] != 0);
-      if (closed && e - a <= WAKE_SEGMAX) {
-        cls = 1;
-        const double r = R[sl];
-        const int32_t id = id_of<NT>(HS[sl], C);
-        int rank = 0;
-        #pragma unroll 1
-        for (int q = a; q < e; ++q) {
-          const unsigned sq = slot_of(q, C, NT);
-          if (key_lt(R[sq], id_of<NT>(HS[sq], C), r, id)) ++rank;
-        }
-        stage_move(I, buf, tmp, sl, slot_of(a + rank, C, NT));
-      } else {
-        cls = 2;
-        nlong += 1.0;
-      }
-      nmoved += 1.0;
-    }
-    I.cls[sl] = cls;
-  }
-  Pack<2> tot;
-  const Pack<2> j0p = block_prefix<NT, 2>(Pack<2>{{nlong, nmoved}}, Pack<2>{{0.0, 0.0}}, SumOp<2>(),
-                                          s_scan, tot);
-  const int M = (int)tot.v[0];
-  if (M > 0) {
-    const bool in_lds = M <= WAKE_SORTCAP;
-    double* kr = reinterpret_cast<double*>(region);
-    int32_t* ki = reinterpret_cast<int32_t*>(kr + WAKE_SORTCAP);
-    int32_t* ks = ki + WAKE_SORTCAP;
-    int j = (int)j0p.v[0];
-    #pragma unroll 1
-    for (int k = 0; k < cnt; ++k) {
-      const unsigned sl = k * NT + tid;
-      if (I.cls[sl] != 2) continue;
-      I.free_slot[j] = (int32_t)sl;
-      const double r = R[sl];
-      const int32_t id = id_of<NT>(HS[sl], C);
-      if (in_lds) { kr[j] = r; ki[j] = id; ks[j] = (int32_t)sl; }
-      else { I.sk_r[0][j] = r; I.sk_i[0][j] = id; I.sk_s[0][j] = (int32_t)sl; }
-      ++j;
-    }
-    __syncthreads();
-    const int32_t* Ks;
-    if (in_lds) {
-      int P = 1;
-      while (P < M) P <<= 1;
-      for (int i = M + tid; i < P; i += NT) { kr[i] = INFINITY; ki[i] = 0x7fffffff - i; ks[i] = -1; }
-      __syncthreads();
-      bitonic_keys<NT>(kr, ki, ks, P);
-      Ks = ks;
-    } else {
-      const int b = sort_keys_global<NT>(I, M, kr, ki, ks);
-      Ks = I.sk_s[b];
-    }
-    // j-th smallest ring of the long runs -> j-th freed position
-    for (int q = tid; q < M; q += NT) stage_move(I, buf, tmp, (unsigned)Ks[q], (unsigned)I.free_slot[q]);
-  }
-  __syncthreads();
-  #pragma unroll 1
-  for (int k = 0; k < cnt; ++k) {
-    const unsigned sl = k * NT + tid;
-    if (I.cls[sl] == 0) continue;
-    stage_move(I, tmp, buf, sl, sl);
-  }
-  __syncthreads();
-  return tot.v[1] != 0.0;
-}
-
-// LDS index (slot form) of position p: (p % C) * NT + p / C, with p / C from
-// a float estimate corrected to the exact quotient (p < 2^24).
-template <int NT>
-__device__ __forceinline__ int pos_index(int p, int C, float iC) {
-  int q = (int)((float)p * iC);
+__device__ __forceinline__ int pos_index(int p, int C, double iC) {
+  int q = (int)((double)p * iC);
   if (q * C > p) --q;
   else if ((q + 1) * C <= p) ++q;
   return (p - q * C) * NT + q;
@@ -594,6 +453,145 @@ struct MinIntOp {
   }
 };
 
+// Order fix-up with the keys in global memory (instances with C > CMAX).
+// The keys of the ring at position (t, k) are the current buffer's rho and
+// id at slot k*NT + t.  Same runs, ranks and long-run sort as the LDS
+// version; prefix maxima, boundaries and run starts go through global
+// scratch (sm_r/sm_i, flag, cls); the permutation (slot form) is written to
+// the global array perm.
+template <int NT>
+__device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s_scan,
+                                           double* s_scan2, unsigned char* region) {
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C;
+  const double iC = 1.0 / (double)C;
+  const int p0 = tid * C;
+  const int cnt = max(0, min(C, N - p0));
+  const GA<double> R = uview(I.rho[buf]);
+  const GA<int32_t> HS = uview(I.hs[buf]);
+  const GA<double> PMR = uview(I.sm_r);
+  const GA<int32_t> PMI = uview(I.sm_i), FL = uview(I.flag), CL = uview(I.cls), PERM = uview(I.perm);
+  // chunk extremes; maximum key before each position of the chunk
+  Pack<2> mx = {{-INFINITY, -2147483648.0}}, mn = {{INFINITY, 2147483647.0}};
+  #pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const unsigned sl = k * NT + tid;
+    PMR.st(sl, mx.v[0]);
+    PMI.st(sl, (int32_t)mx.v[1]);
+    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
+    mx = MaxKeyOp()(mx, key);
+    mn = MinKeyOp()(mn, key);
+  }
+  Pack<2> before, tb, after, ta;
+  block_prefix_suffix<NT, 2, 2, MaxKeyOp, MinKeyOp, false>(
+      mx, Pack<2>{{-INFINITY, -2147483648.0}}, MaxKeyOp(), mn, Pack<2>{{INFINITY, 2147483647.0}},
+      MinKeyOp(), s_scan, before, tb, after, ta);
+  // run boundaries, first and last of the chunk
+  Pack<2> sm = after;
+  int lb = -1, fb = N;
+  #pragma unroll 1
+  for (int k = cnt - 1; k >= 0; --k) {
+    const unsigned sl = k * NT + tid;
+    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
+    sm = MinKeyOp()(sm, key);
+    const Pack<2> pm = MaxKeyOp()(before, Pack<2>{{PMR[sl], (double)PMI[sl]}});
+    const bool b = (p0 + k == 0) || key_lt(pm.v[0], (int32_t)pm.v[1], sm.v[0], (int32_t)sm.v[1]);
+    FL.st(sl, b ? 1 : 0);
+    if (b) {
+      if (lb < 0) lb = p0 + k;
+      fb = p0 + k;
+    }
+  }
+  Pack<1> ain, at_, ein, et_;
+  block_prefix_suffix<NT, 1, 1, MaxIntOp, MinIntOp, false>(
+      Pack<1>{{(double)lb}}, Pack<1>{{-1.0}}, MaxIntOp(), Pack<1>{{(double)fb}}, Pack<1>{{(double)N}},
+      MinIntOp(), s_scan2, ain, at_, ein, et_);
+  // run start of each position
+  int a = (int)ain.v[0];
+  #pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const unsigned sl = k * NT + tid;
+    if (FL[sl]) a = p0 + k;
+    CL.st(sl, a);
+  }
+  // classify backward (run end = first boundary after the position); short
+  // runs ranked here; long-run positions marked -1
+  int e = (int)ein.v[0];
+  double nlong = 0.0;
+  #pragma unroll 1
+  for (int k = cnt - 1; k >= 0; --k) {
+    const int p = p0 + k;
+    const unsigned sl = k * NT + tid;
+    const int ra = CL[sl];
+    if (e - ra == 1) {
+      PERM.st(sl, (int32_t)sl);
+    } else if (e - ra <= WAKE_SEGMAX) {
+      const double r = R[sl];
+      const int32_t id = id_of<NT>(HS[sl], C);
+      const int qi = pos_index<NT>(ra, C, iC);
+      int qk = qi / NT, qt = qi % NT;
+      int rank = 0;
+      #pragma unroll 1
+      for (int q = ra; q < e; q += 4) {
+        unsigned x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {      // past the run end: compare with itself
+          x[i] = q + i < e ? (unsigned)(qk * NT + qt) : sl;
+          if (++qk == C) { qk = 0; ++qt; }
+        }
+        double xr[4];
+        int32_t xh[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { xr[i] = R[x[i]]; xh[i] = HS[x[i]]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rank += key_lt(xr[i], id_of<NT>(xh[i], C), r, id) ? 1 : 0;
+      }
+      PERM.st((unsigned)pos_index<NT>(ra + rank, C, iC), (int32_t)sl);
+    } else {
+      CL.st(sl, -1);
+      nlong += 1.0;
+    }
+    if (FL[sl]) e = p;
+  }
+  Pack<1> tot;
+  const Pack<1> j0p = block_prefix<NT, 1>(Pack<1>{{nlong}}, Pack<1>{{0.0}}, SumOp<1>(), s_scan, tot);
+  const int M = (int)tot.v[0];
+  if (M > 0) {
+    // rings of the long runs, compacted in position order; their freed
+    // positions (slot form) in free_slot
+    double* zr = reinterpret_cast<double*>(region);
+    int32_t* zi = reinterpret_cast<int32_t*>(zr + WAKE_SORTCAP);
+    int32_t* zs = zi + WAKE_SORTCAP;
+    const bool in_lds = M <= WAKE_SORTCAP;
+    int j = (int)j0p.v[0];
+    #pragma unroll 1
+    for (int k = 0; k < cnt; ++k) {
+      const unsigned sl = k * NT + tid;
+      if (CL[sl] != -1) continue;
+      I.free_slot[j] = (int32_t)sl;
+      const double r = R[sl];
+      const int32_t id = id_of<NT>(HS[sl], C);
+      if (in_lds) { zr[j] = r; zi[j] = id; zs[j] = (int32_t)sl; }
+      else { I.sk_r[0][j] = r; I.sk_i[0][j] = id; I.sk_s[0][j] = (int32_t)sl; }
+      ++j;
+    }
+    __syncthreads();
+    if (in_lds) {
+      int P = 1;
+      while (P < M) P <<= 1;
+      for (int i = M + tid; i < P; i += NT) { zr[i] = INFINITY; zi[i] = 0x7fffffff - i; zs[i] = -1; }
+      __syncthreads();
+      bitonic_keys<NT>(zr, zi, zs, P);
+      for (int q = tid; q < M; q += NT) PERM.st((unsigned)I.free_slot[q], zs[q]);
+    } else {
+      const int b = sort_keys_global<NT>(I, M, zr, zi, zs);
+      for (int q = tid; q < M; q += NT) PERM.st((unsigned)I.free_slot[q], I.sk_s[b][q]);
+    }
+  }
+  __syncthreads();
+}
+
+
 // Order fix-up in LDS (C <= CMAX).  The keys of the rings at every position
 // are in LDS in slot form (position (t, k) of thread t at index k*NT + t):
 // kr (radius), ki (id).  Builds perm[k*NT + t] = slot, in the current buffer,
@@ -607,7 +605,7 @@ __device__ __noinline__ void fix_order_lds(const WakeInst& I, double* s_scan, do
                                            const uint16_t* ki, uint16_t* zf, uint16_t* perm) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C;
-  const float iC = 1.0f / (float)C;
+  const double iC = 1.0 / (double)C;
   const int p0 = tid * C;
   const int cnt = max(0, min(C, N - p0));
   Pack<2> mx = {{-INFINITY, -2147483648.0}}, mn = {{INFINITY, 2147483647.0}};
@@ -804,7 +802,7 @@ __device__ __forceinline__ void stage_slice(const WakeInst& I, int n, double* s_
 // positions (ln rho of each ring taken from its slot).
 template <int NT>
 __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, bool ident,
-                                           const uint16_t* perm, dd& sw, dd& swl) {
+                                           bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
   const int tid = threadIdx.x;
   const unsigned smax = (unsigned)(I.C * NT - 1);
   const GA<double> Wv = uview(I.w), LH = uview(I.lnh[cur]), LL = uview(I.lnl[cur]);
@@ -813,7 +811,8 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
   swl = {0.0, 0.0};
   #pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
-    const unsigned s = ident ? (unsigned)(k * NT + tid) : min((unsigned)perm[k * NT + tid], smax);
+    const unsigned sl = k * NT + tid;
+    const unsigned s = ident ? sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[sl], smax);
     const double w = Wv[HS[s]];
     sw = dd_add_d(sw, w);
     swl = dd_add(swl, dd_mul_d(dd{LH[s], LL[s]}, w));
@@ -846,6 +845,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   // keys and ring order in LDS (else the order is fixed in global memory)
   const bool lds_keys = C <= CMAX;
   const unsigned smax = (unsigned)(C * NT - 1);    // last slot
+  const GA<int32_t> gperm = uview(I.perm);
+  // slot, in the current buffer, of the ring at the position of slot-form index sl
+#define WAKE_SLOT(sl) (ident ? (unsigned)(sl) \
+                             : min(lds_keys ? (unsigned)s_perm[sl] : (unsigned)gperm[sl], smax))
 
   if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
   int cur = __builtin_amdgcn_readfirstlane(I.ctl[CTL_CUR]);
@@ -865,7 +868,9 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     ident = false;
     for (int k = 0; k < cnt; ++k) moved |= (s_perm[k * NT + tid] & (NT - 1)) != (unsigned)tid;
   } else {
-    moved = fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
+    fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
+    ident = false;
+    for (int k = 0; k < cnt; ++k) moved |= (gperm[k * NT + tid] & (NT - 1)) != tid;
   }
   const dd tot0 = {uni(I.tot0[0]), uni(I.tot0[1])};
   const double dxi = I.dxi;
@@ -885,7 +890,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   #pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
-    const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+    const unsigned s = WAKE_SLOT(sl);
     const dd lr = ring_log(LV, I.hs[cur][s], I.rho[cur][s]);
     I.lnh[cur][s] = lr.hi;
     I.lnl[cur][s] = lr.lo;
@@ -896,12 +901,12 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   // others backward as the push does.
   dd sw = {0.0, 0.0}, swl = {0.0, 0.0};
   if (moved) {
-    chunk_sums<NT>(I, cur, cnt, ident, s_perm, sw, swl);
+    chunk_sums<NT>(I, cur, cnt, ident, lds_keys, s_perm, sw, swl);
   } else {
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
-      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+      const unsigned s = WAKE_SLOT(sl);
       const double w = Wc[I.hs[cur][s]];
       sw = dd_add_d(sw, w);
       swl = dd_add(swl, dd_mul_d(dd{I.lnh[cur][s], I.lnl[cur][s]}, w));
@@ -927,15 +932,15 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
       if (lds_keys) {
         fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
-        ident = false;
-        // chunks that took a ring from another chunk sum again
-        bool changed = false;
-        for (int k = 0; k < cnt; ++k) changed |= (s_perm[k * NT + tid] & (NT - 1)) != (unsigned)tid;
-        if (changed) chunk_sums<NT>(I, cur, cnt, ident, s_perm, sw, swl);
       } else {
-        fix_order_global<NT>(I, cur, 1 - cur, s_scanB, region);
-        chunk_sums<NT>(I, cur, cnt, true, s_perm, sw, swl);
+        fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
       }
+      ident = false;
+      // chunks that took a ring from another chunk sum again
+      bool changed = false;
+      for (int k = 0; k < cnt; ++k)
+        changed |= ((lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[k * NT + tid]) & (NT - 1)) != tid;
+      if (changed) chunk_sums<NT>(I, cur, cnt, ident, lds_keys, s_perm, sw, swl);
       stage_slice<NT>(I, n, s_misc, s_br, s_bc);
       dis = 0.0;
       continue;
@@ -970,7 +975,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     double x_rho = 1.0, x_u = 0.0, x_lh = 0.0, x_ll = 0.0;
     int32_t x_hs = 0, x_h = 0;
     if (cnt > 0) {
-      const unsigned s = ident ? (unsigned)tid : min((unsigned)s_perm[tid], smax);
+      const unsigned s = WAKE_SLOT(tid);
       x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
     }
     #pragma unroll 1
@@ -982,7 +987,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const dd lnr = {x_lh, x_ll};
       if (k + 1 < cnt) {
         const unsigned sn = sl + NT;
-        const unsigned s = ident ? sn : min((unsigned)s_perm[sn], smax);
+        const unsigned s = WAKE_SLOT(sn);
         x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
       }
       const double w = Wc[hs], wh = WHc[hs];
@@ -1083,7 +1088,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     int32_t y_hs = 0;
     if (cnt > 0) {
       const unsigned sl = (cnt - 1) * NT + tid;
-      const unsigned s = ident ? sl : min((unsigned)s_perm[sl], smax);
+      const unsigned s = WAKE_SLOT(sl);
       y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
       y_hs = hs_n[sl]; y_psi = PSI[sl]; y_dpsi = DPSI[sl]; y_bb = BB[sl];
     }
@@ -1095,7 +1100,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const double psi = y_psi, dpsi = y_dpsi, bb = y_bb;
       if (k > 0) {
         const unsigned sp = sl - NT;
-        const unsigned s = ident ? sp : min((unsigned)s_perm[sp], smax);
+        const unsigned s = WAKE_SLOT(sp);
         y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
         y_hs = hs_n[sp]; y_psi = PSI[sp]; y_dpsi = DPSI[sp]; y_bb = BB[sp];
       }
