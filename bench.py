@@ -94,6 +94,60 @@ def cpu_baseline(insts, budget_s: float = 15.0):
                        + "; ".join(sample) + f"; {done} ring-slices in {dt:.1f} s")
 
 
+C4_MEAN_WORK = (50_000 - 500) / math.log(100.0) * (500 + 8000) / 2.0   # E[N] E[N_xi]
+
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def served_run(wake, W, stream, rate, seconds, budget_bytes, step_us, seed=4, max_wall=150.0):
+    """Real-time Poisson stream of served-form requests (ring counts log-uniform
+    in [500, 50000], window lengths uniform in [500, 8000], beams as the batched
+    workload).  Instances are built before the clock starts; each arrives at its
+    scheduled time.  Latency = result ready - scheduled arrival."""
+    specs, build = W.config4_stream(seed=seed, rate=rate, duration=seconds)
+    reqs = [(t, build(k)) for t, k in specs]
+    srv = wake.WakeServer(device_bytes=budget_bytes, slices_per_step=100_000, step_us=step_us,
+                          stream=stream)
+    arrival, work, lat = {}, {}, []
+    done_work, i, steps, max_queue = 0, 0, 0, 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i][0] <= now:
+            t = srv.submit_instance(reqs[i][1])
+            arrival[t] = reqs[i][0]
+            work[t] = reqs[i][1].ring_slices
+            i += 1
+        st = srv.stats()
+        max_queue = max(max_queue, st["queued"])
+        if st["active"] + st["queued"] == 0:
+            if i >= len(reqs):
+                break
+            time.sleep(max(0.0, min(0.002, reqs[i][0] - now)))
+            continue
+        srv.step()
+        steps += 1
+        tnow = time.perf_counter() - t0
+        for t in srv.ready():
+            r = srv.result(t)
+            lat.append(tnow - arrival.pop(t))
+            done_work += work.pop(t)
+            if r["status"] not in (0, wake.WAKE_EBREAKDOWN):
+                raise RuntimeError(f"request {t} failed: {r['status']}")
+        if tnow > max_wall:
+            break
+    wall = time.perf_counter() - t0
+    marched = srv.stats()["ring_slices"]
+    srv.close()
+    return dict(rate=rate, arrival_seconds=seconds, requests=len(reqs), completed=len(lat),
+                unfinished=len(arrival), wall_s=wall, steps=steps, max_queue=max_queue,
+                ring_slices_marched=marched, throughput=marched / wall,
+                p50_latency_s=_pct(lat, 50), p99_latency_s=_pct(lat, 99),
+                mean_latency_s=float(np.mean(lat)) if lat else None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +159,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tiling", type=str, default="")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=20.0,
+                    help="arrival window of the served run (0: skip)")
+    ap.add_argument("--served-rate", type=float, default=0.0,
+                    help="request rate of the served run (0: 70%% of the measured capacity)")
+    ap.add_argument("--served-budget-gib", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the "
@@ -207,6 +266,36 @@ def main():
         "batched_vs_plain": value / plain_value,
         "roofline": roof,
     }
+    if args.served_seconds > 0:
+        # capacity: sustained ring-slice rate of the server on the request mix
+        # while it is saturated (a backlog of requests submitted at once)
+        budget = int(args.served_budget_gib * (1 << 30))
+        step_us = 20_000
+        log("served: capacity")
+        specs, build = W.config4_stream(seed=40, rate=1000.0, duration=0.3)
+        srv = wake.WakeServer(device_bytes=budget, slices_per_step=100_000, step_us=step_us,
+                              stream=stream)
+        for t, k in specs:
+            srv.submit_instance(build(k))
+        t0 = time.perf_counter()
+        srv.step()                                   # first admissions
+        w0, c0 = srv.stats()["ring_slices"], time.perf_counter()
+        while time.perf_counter() - c0 < 8.0 and srv.stats()["active"] > 0:
+            srv.step()
+            for t in srv.ready():
+                srv.result(t)
+        capacity = (srv.stats()["ring_slices"] - w0) / (time.perf_counter() - c0)
+        srv.close()
+        rate = args.served_rate or 0.7 * capacity / C4_MEAN_WORK
+        log(f"served: capacity {capacity:.3e} ring-slices/s -> run at {rate:.1f} requests/s")
+        run = served_run(wake, W, stream, rate, args.served_seconds, budget, step_us)
+        offered = 2000.0 * C4_MEAN_WORK
+        out["served"] = dict(
+            workload="served Poisson stream, ring counts logU[500,50000], slices U[500,8000]",
+            step_ms=step_us / 1e3,
+            capacity_ring_slices_per_s=capacity,
+            offered_at_2000_per_s=offered, stable_at_2000_per_s=bool(offered < capacity),
+            max_sustainable_rate_per_s=capacity / C4_MEAN_WORK, **run)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_budget)

@@ -213,9 +213,16 @@ typedef struct wake_server wake_server;
 
 typedef struct {
   int32_t threads;          /* workgroup threads of the server's contexts (0: current tiling) */
-  int32_t slices_per_step;  /* slices each resident request advances per step (> 0) */
+  int32_t slices_per_step;  /* most slices a resident request advances per step (> 0) */
   int32_t max_active;       /* cap on resident requests (0: none) */
   int64_t device_bytes;     /* device-memory budget of the resident requests (> 0) */
+  int64_t ring_slices_per_step; /* per-request work per step: a request of N rings advances
+                                   max(1, ring_slices_per_step / N) slices (at most
+                                   slices_per_step), so that small requests are not held to
+                                   the pace of large ones; 0: slices_per_step for all */
+  int32_t step_us;          /* wall-clock length of a step (0: none): each request stops after
+                               the slice that exhausts its share of it (the step length, shared
+                               when more requests are resident than workgroups fit) */
 } wake_server_config;
 
 int wake_server_create(wake_server **out, const wake_server_config *cfg, void *hip_stream);
@@ -233,8 +240,13 @@ int wake_server_step(wake_server *s, int32_t *n_active, int32_t *n_queued, int32
 int wake_server_result(wake_server *s, int64_t ticket, int32_t *breakdown_slice, double *psi_axis,
                        double *ez_axis, double *psi, double *er_minus_bt, double *ez, double *bt,
                        double *rho, double *ur);
+/* Device bytes held by resident requests, resident / queued requests,
+ * results waiting to be fetched, ring-slice updates marched so far. */
 int wake_server_stats(wake_server *s, int64_t *bytes_in_use, int32_t *n_active, int32_t *n_queued,
-                      int32_t *n_results);
+                      int32_t *n_results, int64_t *ring_slices);
+/* Tickets whose results are ready (not yet fetched), up to cap of them;
+ * *n receives how many were written. */
+int wake_server_ready(wake_server *s, int64_t *tickets, int32_t cap, int32_t *n);
 void wake_server_destroy(wake_server *s);
 
 #ifdef __cplusplus

@@ -55,6 +55,8 @@ struct WakeInst {
   int32_t C;          // rings per thread, ceil(N / nt)
   int32_t nb;         // beam-table entries
   double dxi, Rp, inv2pidxi;
+  int64_t budget;     // wall-clock budget of this launch in 100 MHz ticks (0: none):
+                      // the march stops after the slice that exhausts it
   WakeAnalytic an[WAKE_MAX_ANALYTIC];
   // per-ring constants by home slot: weight, modified weight, r0, 1/r0,
   // ln r0 (double-double)

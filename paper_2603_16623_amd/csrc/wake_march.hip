@@ -851,6 +851,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
                              : min(lds_keys ? (unsigned)s_perm[sl] : (unsigned)gperm[sl], smax))
 
   if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  const int64_t budget = I.budget;
   int cur = __builtin_amdgcn_readfirstlane(I.ctl[CTL_CUR]);
   __syncthreads();
   // injected states may be unsorted
@@ -913,7 +915,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     }
   }
   int n = I.first;
-  const int end = I.first + I.count;
+  int end = I.first + I.count;
   if (n < end) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
   double bad = 0.0, dis = 0.0;
   int unpushed = cur;          // buffer with the unpushed state of slice n-1
@@ -1168,7 +1170,11 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     s_fr[tid] = nxt_r;
     s_fi[tid] = nxt_i;
     if (do_push && n + 1 < end) stage_slice<NT>(I, n + 1, s_misc, s_br, s_bc);
+    // out of time: this slice is the launch's last (one clock read, broadcast)
+    if (tid == 0)
+      s_misc[63] = budget > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget ? 1.0 : 0.0;
     __syncthreads();
+    if (s_misc[63] != 0.0) end = n + 1;
     if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))
       dis_l = 1.0;
     dis = dis_l;

@@ -60,6 +60,7 @@ struct wake_server {
   wake_server_config cfg{};
   int64_t next_ticket = 1;
   int64_t in_use = 0;
+  int64_t marched = 0;        // ring-slice updates marched so far
   std::deque<Request> queue;
   std::vector<Active> active;
   std::unordered_map<int64_t, Result> done;
@@ -87,7 +88,8 @@ extern "C" void wake_server_destroy(wake_server* s) { server_release(s); }
 extern "C" int wake_server_create(wake_server** out, const wake_server_config* cfg, void* hip_stream) {
   if (!out) return WAKE_EINVAL;
   *out = nullptr;
-  if (!cfg || cfg->slices_per_step <= 0 || cfg->device_bytes <= 0 || cfg->max_active < 0)
+  if (!cfg || cfg->slices_per_step <= 0 || cfg->device_bytes <= 0 || cfg->max_active < 0 ||
+      cfg->ring_slices_per_step < 0 || cfg->step_us < 0)
     return WAKE_EINVAL;
   int cur_nt = 0, cur_wpc = 0;
   (void)wake_get_tiling(&cur_nt, &cur_wpc);
@@ -225,16 +227,27 @@ extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_qu
   }
   int32_t retired = 0;
   if (!s->active.empty()) {
-    // one persistent launch over every resident request
+    // one persistent launch over every resident request; with a step length,
+    // each request's share of it (workgroups that fit / resident requests)
+    int64_t budget = 0;
+    if (s->cfg.step_us > 0) {
+      const int grid = march_grid(s->cfg.threads, (int)s->active.size(), s->device);
+      const double share = std::min(1.0, (double)grid / (double)s->active.size());
+      budget = std::max<int64_t>(1, (int64_t)(s->cfg.step_us * 100.0 * share));   // 100 MHz ticks
+    }
     std::vector<WakeInst> v;
     std::vector<int> count(s->active.size(), 0);
     for (size_t i = 0; i < s->active.size(); ++i) {
       wake_ctx* c = s->active[i].ctx;
-      const int cnt = std::min(s->cfg.slices_per_step, c->I.n_xi - c->next);
+      int k = s->cfg.slices_per_step;
+      if (s->cfg.ring_slices_per_step > 0)
+        k = (int)std::min<int64_t>(k, std::max<int64_t>(1, s->cfg.ring_slices_per_step / c->I.N));
+      const int cnt = std::min(k, c->I.n_xi - c->next);
       count[i] = cnt;
       WakeInst I = c->I;
       I.first = c->next;
       I.count = cnt;
+      I.budget = budget;
       v.push_back(I);
     }
     const int n = (int)v.size();
@@ -271,7 +284,9 @@ extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_qu
       const int32_t* w = &s->h_ctl[(size_t)CTL_NWORDS * j];
       wake_ctx* c = s->active[i].ctx;
       brk[i] = w[CTL_BREAK];
-      c->next = brk[i] >= 0 ? w[CTL_NEXT] : c->next + count[i];
+      const int nx = w[CTL_NEXT];
+      s->marched += (int64_t)std::max(0, nx - c->next) * c->I.N;
+      c->next = nx;
     }
     for (size_t i = s->active.size(); i-- > 0;) {
       wake_ctx* c = s->active[i].ctx;
@@ -313,11 +328,23 @@ extern "C" int wake_server_result(wake_server* s, int64_t ticket, int32_t* break
 }
 
 extern "C" int wake_server_stats(wake_server* s, int64_t* bytes_in_use, int32_t* n_active,
-                                 int32_t* n_queued, int32_t* n_results) {
+                                 int32_t* n_queued, int32_t* n_results, int64_t* ring_slices) {
   if (!s) return WAKE_EINVAL;
+  if (ring_slices) *ring_slices = s->marched;
   if (bytes_in_use) *bytes_in_use = s->in_use;
   if (n_active) *n_active = (int32_t)s->active.size();
   if (n_queued) *n_queued = (int32_t)s->queue.size();
   if (n_results) *n_results = (int32_t)s->done.size();
+  return WAKE_OK;
+}
+
+extern "C" int wake_server_ready(wake_server* s, int64_t* tickets, int32_t cap, int32_t* n) {
+  if (!s || !n || cap < 0 || (cap > 0 && !tickets)) return WAKE_EINVAL;
+  int32_t k = 0;
+  for (const auto& kv : s->done) {
+    if (k >= cap) break;
+    tickets[k++] = kv.first;
+  }
+  *n = k;
   return WAKE_OK;
 }

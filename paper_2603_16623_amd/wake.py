@@ -47,7 +47,8 @@ class _Source(C.Structure):
 
 class _ServerConfig(C.Structure):
     _fields_ = [("threads", C.c_int32), ("slices_per_step", C.c_int32), ("max_active", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("ring_slices_per_step", C.c_int64),
+                ("step_us", C.c_int32)]
 
 
 _I, _P, _D, _I64 = C.c_int32, C.c_void_p, C.c_double, C.c_int64
@@ -82,7 +83,9 @@ _SIGS = {
                                 C.POINTER(_I64)]),
     "wake_server_step": (_I, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
     "wake_server_result": (_I, [_P, _I64, C.POINTER(_I), _P, _P, _P, _P, _P, _P, _P, _P]),
-    "wake_server_stats": (_I, [_P, C.POINTER(_I64), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    "wake_server_stats": (_I, [_P, C.POINTER(_I64), C.POINTER(_I), C.POINTER(_I), C.POINTER(_I),
+                               C.POINTER(_I64)]),
+    "wake_server_ready": (_I, [_P, C.POINTER(_I64), _I, C.POINTER(_I)]),
     "wake_server_destroy": (None, [_P]),
 }
 
@@ -307,10 +310,12 @@ class WakeServer:
     """Continuous batching of independent solves (wake_server_*)."""
 
     def __init__(self, device_bytes: int, slices_per_step: int = 100, threads: int = 0,
-                 max_active: int = 0, stream: Optional[int] = None):
+                 max_active: int = 0, ring_slices_per_step: int = 0, step_us: int = 0,
+                 stream: Optional[int] = None):
         lib = load()
         self._lib = lib
-        cfg = _ServerConfig(int(threads), int(slices_per_step), int(max_active), int(device_bytes))
+        cfg = _ServerConfig(int(threads), int(slices_per_step), int(max_active), int(device_bytes),
+                            int(ring_slices_per_step), int(step_us))
         h = _P()
         _check(lib.wake_server_create(C.byref(h), C.byref(cfg), stream), "wake_server_create")
         self.h = h
@@ -367,8 +372,16 @@ class WakeServer:
         out["breakdown"] = brk.value
         return out
 
+    def ready(self, cap: int = 4096):
+        """Tickets whose results are waiting to be fetched."""
+        buf = (_I64 * cap)()
+        n = _I()
+        _check(self._lib.wake_server_ready(self.h, buf, cap, C.byref(n)), "wake_server_ready")
+        return [buf[i] for i in range(n.value)]
+
     def stats(self):
-        b, a, q, n = _I64(), _I(), _I(), _I()
-        _check(self._lib.wake_server_stats(self.h, C.byref(b), C.byref(a), C.byref(q), C.byref(n)),
-               "wake_server_stats")
-        return dict(bytes_in_use=b.value, active=a.value, queued=q.value, results=n.value)
+        b, a, q, n, w = _I64(), _I(), _I(), _I(), _I64()
+        _check(self._lib.wake_server_stats(self.h, C.byref(b), C.byref(a), C.byref(q), C.byref(n),
+                                           C.byref(w)), "wake_server_stats")
+        return dict(bytes_in_use=b.value, active=a.value, queued=q.value, results=n.value,
+                    ring_slices=w.value)

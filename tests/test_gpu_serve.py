@@ -60,12 +60,16 @@ def test_chunked_solve_is_bitwise_one_solve(wk):
         s.close()
 
 
-def test_served_results_equal_alone(wk):
+@pytest.mark.parametrize("budget,step_us", [(0, 0), (40_000, 0), (0, 300)])
+def test_served_results_equal_alone(wk, budget, step_us):
+    """Fixed slices per step, a work budget per step, and time-sliced steps
+    (chunk lengths then depend on timing) all give the alone results."""
     sizes = [(300, 90), (1500, 60), (777, 130), (64, 40), (2100, 75), (9000, 30), (1200, 110)]
     insts = _mix(61, sizes)
-    _say("served mix")
+    _say("served mix, work budget per step", budget, "step us", step_us)
     ref = [_alone(wk, inst) for inst in insts]
-    srv = wk.WakeServer(device_bytes=8 << 30, slices_per_step=17)
+    srv = wk.WakeServer(device_bytes=8 << 30, slices_per_step=17 if step_us == 0 else 100000,
+                        ring_slices_per_step=budget, step_us=step_us)
     tickets = {}
     # requests arrive while others are resident
     for i in range(3):
@@ -79,7 +83,7 @@ def test_served_results_equal_alone(wk):
             tickets[srv.submit_instance(insts[i])] = i
         srv.step()
         steps += 1
-        assert steps < 200
+        assert steps < 5000
         for t, i in list(tickets.items()):
             r = srv.result(t)
             if r is not None:
@@ -93,6 +97,8 @@ def test_served_results_equal_alone(wk):
         assert np.array_equal(r["ez_axis"], ref[i]["ez_axis"]), i
     st = srv.stats()
     assert st["active"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+    assert st["ring_slices"] == sum(i.ring_slices for i in insts)
+    assert srv.ready() == []
     srv.close()
 
 
