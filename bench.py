@@ -30,26 +30,15 @@ METRIC = "ring-slice updates/s batched+served vs plain (FP64, 1e-8 rel); p50/p99
 PEAK_FP64_VECTOR = 78.6e12       # FP64 vector FLOP/s of MI355X (256 CU x 2.4 GHz x 128)
 PEAK_HBM = 8.0e12                 # HBM3E bytes/s
 
-# Algorithmic work per ring-slice of the method (one ring, one slice), counted
-# from the sequential algorithm with double-double sums as their binary64
-# operations (two_sum 6, two_prod 2 with fma, dd add 20, dd mul-by-double 10,
-# dd divide-by-double 12); fma counts 2, divide and log1p/exp count 1.
-#   psi family  : w ln(rho) (log1p + dd add + dd mul 32), prefix dd sums (40),
-#                 psi_e (dd mul + dd add 30), d_rho psi_e (dd add + dd div 32),
-#                 ion interpolation (2 x (dd sub + dd mul + dd add) 100),
-#                 two roundings (2)                                       236
-#   local       : psibar, gamma, v, A                                     14
-#   d_zeta psi  : suffix sum and own term                                  4
-#   A, B, C, s  : coefficients and offset vector                          40
-#   recursion   : growing mode (M g, 8 with the matrix), decaying mode (8),
-#                 det[g,s], det[s,h] (6), prefix/suffix sums (2), x (10),
-#                 B^(p) (6)                                               40
-#   push        : forces (8), AB2 (8), next-slice ln rho (dd mul + add 31) 47
-ALG_FLOPS_PER_RING_SLICE = 236 + 14 + 4 + 40 + 40 + 47
-# Ring state that must be read and written once per slice (rho, u_r and the
-# two AB2 history terms, 8 B each, in and out) plus the per-ring constants
-# read (w, w^, ln r0 as double-double, r0: 40 B) and the id (4 B in, 4 B out).
-ALG_BYTES_PER_RING_SLICE = 32 + 32 + 40 + 8
+# Algorithmic work per ring-slice of the method (one ring, one slice), the
+# per-unit figures of the measurement plan: 150-200 FP64 flops, one log and
+# about eight divides counted as one flop each, and about four double-double
+# additions of about 20 flops each.
+ALG_FLOPS_PER_RING_SLICE = 280
+# Bytes the method must move per ring-slice: read rho, u_r, the two AB2
+# history terms, w and w^ (48 B); write rho, u_r and the history (32 B); the
+# ion-table interpolation (32 B, cache resident).
+ALG_BYTES_PER_RING_SLICE = 48 + 32 + 32
 
 
 def log(*a):
