@@ -280,10 +280,8 @@ def transfer(A, B, C, rho):
     return M, s
 
 
-def solve_recursion(M, s):
-    """Solve x_i = M_i x_{i-1} + s_i (i=1..N) with b_0 = 0 and a_N = 0
-    (eq. ai_bi) as one banded linear system in (a_0, b_0, ..., a_N, b_N).
-    Returns arrays a, b of length N+1."""
+def _recursion_banded(M, s):
+    """Banded storage and right-hand side of eq. ai_bi with b_0 = 0, a_N = 0."""
     n = M.shape[0]
     nu = 2 * n + 2
     # banded storage with 2 lower and 1 upper diagonals: entry (row r,
@@ -303,8 +301,41 @@ def solve_recursion(M, s):
     rhs[ra] = s[:, 0]
     rhs[rb] = s[:, 1]
     ab[1 + (nu - 1) - 2 * n, 2 * n] = 1.0                    # a_N = 0
+    return ab, rhs
+
+
+def _recursion_residual(M, s, a, b):
+    """Residual of eq. ai_bi and the boundary rows in 80-bit arithmetic."""
+    L = np.longdouble
+    a, b = a.astype(L), b.astype(L)
+    Ml, sl = M.astype(L), s.astype(L)
+    r = np.zeros(2 * M.shape[0] + 2, dtype=L)
+    r[0] = -b[0]
+    r[1:-1:2] = sl[:, 0] - (a[1:] - Ml[:, 0, 0] * a[:-1] - Ml[:, 0, 1] * b[:-1])
+    r[2:-1:2] = sl[:, 1] - (b[1:] - Ml[:, 1, 0] * a[:-1] - Ml[:, 1, 1] * b[:-1])
+    r[-1] = -a[-1]
+    return r
+
+
+def solve_recursion(M, s, refine: int = 2):
+    """Solve x_i = M_i x_{i-1} + s_i (i=1..N) with b_0 = 0 and a_N = 0
+    (eq. ai_bi) as one banded linear system in (a_0, b_0, ..., a_N, b_N),
+    by banded LU, then `refine` steps of iterative refinement with residuals
+    accumulated in 80-bit arithmetic (the binary64 LU alone loses digits with
+    the system's conditioning at large N; R15).  Returns arrays a, b of
+    length N+1."""
+    ab, rhs = _recursion_banded(M, s)
     z = solve_banded((2, 1), ab, rhs)
-    return z[0::2].copy(), z[1::2].copy()
+    a, b = z[0::2].copy(), z[1::2].copy()
+    if refine:
+        az, bz = a.astype(np.longdouble), b.astype(np.longdouble)
+        for _ in range(refine):
+            r = _recursion_residual(M, s, a, b)
+            d = solve_banded((2, 1), ab, r.astype(np.float64))
+            az += d[0::2]
+            bz += d[1::2]
+            a, b = az.astype(np.float64), bz.astype(np.float64)
+    return a, b
 
 
 def solve_shooting(M, s):

@@ -1,0 +1,83 @@
+"""Parity at the configurations' full sizes, in the launch configuration the
+benchmark times (512-thread workgroups).
+
+Per-slice parity on identical state: a seeded perturbed state (radii jittered
+across their neighbours, random momenta and Adams-Bashforth history), not the
+product of either march, is given to both sides at a slice inside the driver,
+witness or laser; the fields at that slice and the pushed state must agree to
+the per-slice tolerance (tolerance reading in test_gpu_parity).  The jitter
+crosses hundreds of rings, so the device's first order fix-up runs its long-run
+sort at these sizes.
+"""
+import numpy as np
+import pytest
+
+from oracle.wake_oracle import RingOracle
+from paper_2603_16623_amd import workloads as W
+from test_gpu_parity import FIELDS, TOL_SLICE, _field_scale, _field_tol, _rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wk():
+    from paper_2603_16623_amd import wake
+    wake.load()
+    wake.wake_set_tiling(512, 0)
+    yield wake
+    wake.wake_set_tiling(512, 0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _perturbed(inst, seed, jitter):
+    rng = np.random.default_rng(seed)
+    N = inst.n_rings
+    return dict(rho=inst.r0 * (1.0 + jitter * rng.standard_normal(N)).clip(0.5, 1.5),
+                u=0.02 * rng.standard_normal(N), fr=0.02 * rng.standard_normal(N),
+                fu=0.02 * rng.standard_normal(N))
+
+
+def _check_slice(wk, inst, n, state, label):
+    o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+    ref, new = o.slice(n, state, push=True, keep=True)
+    assert ref["status"] == 0, label
+    F = _field_scale(ref)
+    _say(f"full-size slice parity {label}: N={inst.n_rings} slice={n} F={F:.3e}")
+    s = wk.WakeSolver.from_instance(inst, record_stride=n)
+    s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(n, 1)
+    got = s.wake_fields(n)
+    for q in FIELDS:
+        e = float(np.max(np.abs(got[q] - ref[q])))
+        assert e <= _field_tol(F), (label, q, e, F)
+    st = s.wake_get_state()
+    assert st["slice"] == n + 1
+    for a, b in (("rho", "rho"), ("ur", "u"), ("f_rho", "fr"), ("f_u", "fu")):
+        assert _rel(st[a], new[b]) <= TOL_SLICE, (label, a, _rel(st[a], new[b]))
+    lp, le = s.wake_lineout()
+    assert abs(lp[n] - ref["psi_axis"]) <= _field_tol(F)
+    assert abs(le[n] - ref["ez_axis"]) <= _field_tol(F)
+    s.close()
+
+
+def test_blowout_20000_rings_full_size(wk):
+    inst = W.config2()                     # 20000 rings, 4000 slices, driver + witness
+    for n, seed in ((int(2.8 / inst.dxi), 1), (int(7.3 / inst.dxi), 2)):   # driver, witness centres
+        _check_slice(wk, inst, n, _perturbed(inst, seed, 0.01), "blowout-20000x4000")
+
+
+def test_laser_200000_rings_full_size(wk):
+    inst = W.config5()                     # 2e5 rings, 8000 slices, laser + witness
+    n = int(2.0 / inst.dxi)                # laser centre
+    _check_slice(wk, inst, n, _perturbed(inst, 3, 0.002), "laser-200000x8000")
+
+
+def test_batched_instances_full_size(wk):
+    insts = W.config3(n_inst=512, n_xi=2000)
+    picks = sorted(range(len(insts)), key=lambda i: insts[i].n_rings)
+    for i in (picks[0], picks[len(picks) // 2], picks[-1]):   # smallest, median, largest
+        inst = insts[i]
+        _check_slice(wk, inst, 800, _perturbed(inst, 10 + i, 0.01), f"batched[{i}]")
