@@ -26,12 +26,11 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
   const size_t S = C * nt;
   const size_t n_rec = stride > 0 ? (size_t)(n_xi + stride - 1) / stride : 0;
   size_t d = 0, i = 0;
-  d += 6 * S;                               // w, wh, r0, 1/r0, ln r0 (dd) by home slot
+  d += 2 * RC_CHUNKS * S;                   // constants by home slot
   d += WAKE_ION_REC * (size_t)(N + 1);      // ion interval records
   d += 4;                                   // tot0, Q
-  d += 12 * S;                              // rho, u, fr, fu, ln rho (dd) x2
-  i += 4 * S;                               // home slot, hint x2
-  d += 5 * S;                               // slice scratch
+  d += 4 * RS_CHUNKS * S;                   // state, two buffers
+  d += (2 * SC_CHUNKS + 2) * S;             // slice scratch, laser terms
   d += 1 * S;                               // fix-up: suffix minimum
   i += 4 * S;                               // fix-up: order, prefix max id, flags, run starts
   d += 2 * (size_t)N;                       // sort keys x2
@@ -156,27 +155,11 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   c->arena.size = bytes;
   Arena& A = c->arena;
   const size_t n_rec = I.stride > 0 ? (size_t)(I.n_xi + I.stride - 1) / I.stride : 0;
-  I.w = A.take<double>(S);
-  I.wh = A.take<double>(S);
-  I.r0 = A.take<double>(S);
-  I.ir0 = A.take<double>(S);
-  I.L0h = A.take<double>(S);
-  I.L0l = A.take<double>(S);
+  I.cst = A.take<double>((size_t)2 * RC_CHUNKS * S);
   I.ion = A.take<double>((size_t)WAKE_ION_REC * (N + 1));
   I.tot0 = A.take<double>(4);
-  for (int b = 0; b < 2; ++b) {
-    I.rho[b] = A.take<double>(S);
-    I.u[b] = A.take<double>(S);
-    I.fr[b] = A.take<double>(S);
-    I.fu[b] = A.take<double>(S);
-    I.hs[b] = A.take<int32_t>(S);
-    I.hint[b] = A.take<int32_t>(S);
-    I.lnh[b] = A.take<double>(S);
-    I.lnl[b] = A.take<double>(S);
-  }
-  I.psi = A.take<double>(S);
-  I.dpsi = A.take<double>(S);
-  I.bb = A.take<double>(S);
+  for (int b = 0; b < 2; ++b) I.st[b] = A.take<double>((size_t)2 * RS_CHUNKS * S);
+  I.sc = A.take<double>((size_t)2 * SC_CHUNKS * S);
   I.a2 = A.take<double>(S);
   I.da2 = A.take<double>(S);
   I.perm = A.take<int32_t>(S);

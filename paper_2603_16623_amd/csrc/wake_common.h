@@ -58,24 +58,22 @@ struct WakeInst {
   int64_t budget;     // wall-clock budget of this launch in 100 MHz ticks (0: none):
                       // the march stops after the slice that exhausts it
   WakeAnalytic an[WAKE_MAX_ANALYTIC];
-  // per-ring constants by home slot: weight, modified weight, r0, 1/r0,
-  // ln r0 (double-double)
-  const double *w, *wh, *r0, *ir0, *L0h, *L0l;
+  // per-ring constants by home slot (RC_* chunks)
+  const double *cst;
   const double *ion;          // [N+1][WAKE_ION_REC]
   const double *tot0;         // [4]: sum_j w_j ln r0_j (dd), total weight Q (dd)
   // beam table (CSR over slices)
   const int32_t *boff;        // [n_xi + 1]
   const double *br, *bcum;    // [nb]
-  // ring state by slot, two buffers: rho, u_r, AB2 history, home slot,
-  // ion-interval search hint, ln rho (dd).  A slice reads the rings of its
-  // sorted positions from the current buffer (through the order permutation)
-  // and writes them to the slots of those positions in the other buffer.
-  double *rho[2], *u[2], *fr[2], *fu[2];
-  int32_t *hs[2], *hint[2];
-  double *lnh[2], *lnl[2];
-  // slice scratch by position slot: psi, d_rho psi, B^(b), laser |a|^2 and
-  // d_rho |a|^2
-  double *psi, *dpsi, *bb, *a2, *da2;
+  // ring state by slot, two buffers (RS_* chunks): rho, u_r, AB2 history,
+  // ln rho (dd), home slot, ion-interval search hint.  A slice reads
+  // the rings of its sorted positions from the current buffer (through the
+  // order permutation) and writes them to the slots of those positions in
+  // the other buffer.
+  double *st[2];
+  // slice scratch by position slot (SC_* chunks): psi, d_rho psi, B^(b);
+  // laser |a|^2 and d_rho |a|^2
+  double *sc, *a2, *da2;
   // order fix-up with global keys: ring order (sorted position, slot form ->
   // slot), prefix maximum keys, run boundaries, run starts / long-run marks,
   // long-run sort keys
@@ -91,6 +89,14 @@ struct WakeInst {
   double *last;               // [6][N] by ring id: last marched slice
   int32_t *ctl;               // [CTL_NWORDS]
 };
+
+// Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c
+// of slot i at element c * S + i of the array (S = C * nt slots), so that a
+// wave reads one chunk of 64 consecutive slots as contiguous 16-B lanes.
+// The home slot and hint share one double's bits (home slot in the low word).
+enum { RS_RU = 0, RS_F, RS_LN, RS_HH, RS_CHUNKS };      // (rho, u_r) (f_rho, f_u) (ln rho) (hs|hint, -)
+enum { RC_W = 0, RC_R0, RC_LN, RC_CHUNKS };             // (w, w^) (r0, 1/r0) (ln r0)
+enum { SC_PSI = 0, SC_BB, SC_CHUNKS };                  // (psi, d_rho psi) (B^(b), -)
 
 // Quantities of a snapshot, in this order: psi, E_r - B_theta, E_z,
 // B_theta, rho, u_r.

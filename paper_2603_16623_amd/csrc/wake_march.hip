@@ -103,8 +103,6 @@ __device__ __forceinline__ dd dd_div_rcp(dd a, double b, double ib) {
   return fast_two_sum(q1, q2);
 }
 
-// ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
-// rounding scales with the ring's displacement, not with |ln rho| (the psi
 // A per-instance array seen as uniform: its base in scalar registers and in
 // the global address space, indexed with 32-bit element offsets (loads and
 // stores then take the scalar-base + vector-offset form).
@@ -137,18 +135,58 @@ __device__ __forceinline__ double uni(double x) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// 16-B chunk of a record (two doubles), moved by one 16-B load or store.
+typedef double D2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ D2 d2(double x, double y) {
+  D2 r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+// home slot (low word) and ion-interval hint (high word) in one double's bits
+__device__ __forceinline__ double hh_pack(int32_t hs, int32_t hint) {
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hint << 32) | (uint32_t)hs));
+}
+__device__ __forceinline__ int32_t hh_hs(double v) {
+  return (int32_t)(uint32_t)(uint64_t)__double_as_longlong(v);
+}
+__device__ __forceinline__ int32_t hh_hint(double v) {
+  return (int32_t)((uint64_t)__double_as_longlong(v) >> 32);
+}
+// A record array kept as planes of 16-B chunks: chunk c of record i sits at
+// c * ps + i (ps = slots per plane), so a wave's accesses to one chunk are
+// contiguous 16-B lanes.  One uniform base per array.
+struct PV {
+  GA<D2> g;
+  uint32_t ps;
+  __device__ __forceinline__ D2 ld(uint32_t c, uint32_t i) const { return g[c * ps + i]; }
+  __device__ __forceinline__ void st(uint32_t c, uint32_t i, D2 v) const { g.st(c * ps + i, v); }
+  // one double of a chunk (half 0: x, 1: y), an 8-B access
+  __device__ __forceinline__ double ldh(uint32_t c, uint32_t i, int half) const {
+    return *reinterpret_cast<WAKE_GLOBAL double*>(reinterpret_cast<WAKE_GLOBAL char*>(g.p) +
+                                                 (c * ps + i) * 16u + half * 8u);
+  }
+  __device__ __forceinline__ void sth(uint32_t c, uint32_t i, int half, double v) const {
+    *reinterpret_cast<WAKE_GLOBAL double*>(reinterpret_cast<WAKE_GLOBAL char*>(g.p) + (c * ps + i) * 16u +
+                                          half * 8u) = v;
+  }
+};
+__device__ __forceinline__ PV pview(const double* p, uint32_t ps) {
+  PV v;
+  v.g = uview(reinterpret_cast<const D2*>(p));
+  v.ps = __builtin_amdgcn_readfirstlane(ps);
+  return v;
+}
+// sort keys of the ring at slot sl of a state buffer
+__device__ __forceinline__ double st_rho(const PV& S, unsigned sl) { return S.ldh(RS_RU, sl, 0); }
+__device__ __forceinline__ int32_t st_hs(const PV& S, unsigned sl) { return hh_hs(S.ldh(RS_HH, sl, 0)); }
+
 // ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
 // rounding scales with the ring's displacement, not with |ln rho| (the psi
-// sums multiply ln rho by the enclosed charge).
-struct LogView {
-  GA<double> r0, ir0, L0h, L0l;
-};
-__device__ __forceinline__ LogView log_view(const WakeInst& I) {
-  return {uview(I.r0), uview(I.ir0), uview(I.L0h), uview(I.L0l)};
-}
-__device__ __forceinline__ dd ring_log(const LogView& V, unsigned hs, double rho) {
-  const double l1 = log1p((rho - V.r0[hs]) * V.ir0[hs]);
-  return dd_add_d({V.L0h[hs], V.L0l[hs]}, l1);
+// sums multiply ln rho by the enclosed charge).  r: (r0, 1/r0), l: ln r0.
+__device__ __forceinline__ dd ring_log(D2 r, D2 l, double rho) {
+  const double l1 = log1p((rho - r.x) * r.y);
+  return dd_add_d({l.x, l.y}, l1);
 }
 
 template <int NT>
@@ -173,7 +211,16 @@ struct IonView {
   dd T0, Q;
 };
 
-__device__ __forceinline__ void ion_fields(const IonView& V, double r, dd lnr, int& h, dd& ps, dd& dp) {
+// The record of the interval a hint points at (loaded ahead of its use).
+__device__ __forceinline__ void ion_load(const IonView& V, int h, double* q) {
+  const int j = h < 0 ? 0 : (h > V.N ? V.N : h);
+#pragma unroll
+  for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = V.R[j * WAKE_ION_REC + i];
+}
+
+// q: the record ion_load gave for the same hint h.
+__device__ __forceinline__ void ion_fields(const IonView& V, double r, dd lnr, int& h, double* q, dd& ps,
+                                           dd& dp) {
   if (!(r < V.Rp)) {
     ps = dd_sub(V.T0, dd_mul(V.Q, lnr));
     dp = dd_neg(dd_div_d(V.Q, r));
@@ -182,10 +229,6 @@ __device__ __forceinline__ void ion_fields(const IonView& V, double r, dd lnr, i
   const GA<double>& R = V.R;
   const int N = V.N;
   int j = h < 0 ? 0 : (h > N ? N : h);
-  // the whole record of the hinted interval in one go (64 B, 16-B aligned)
-  double q[WAKE_ION_REC];
-#pragma unroll
-  for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = R[j * WAKE_ION_REC + i];
   if (!(q[IR_LO] <= r && r < q[IR_HI])) {
     if (q[IR_LO] <= r) {
       int a = j + 1, b, step = 1;     // lo(a) <= r
@@ -263,12 +306,9 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
   __shared__ double s_scan[(NT / 64) * 8];
   const int N = I.N;
   const int tid = threadIdx.x;
-  double* w_out = const_cast<double*>(I.w);
-  double* wh_out = const_cast<double*>(I.wh);
-  double* r0_out = const_cast<double*>(I.r0);
-  double* ir0_out = const_cast<double*>(I.ir0);
-  double* l0h = const_cast<double*>(I.L0h);
-  double* l0l = const_cast<double*>(I.L0l);
+  D2* cst = reinterpret_cast<D2*>(const_cast<double*>(I.cst));
+  D2* st = reinterpret_cast<D2*>(I.st[0]);
+  const size_t PS = (size_t)I.C * I.nt;      // slots per plane
   double* R = const_cast<double*>(I.ion);
   double* consts = const_cast<double*>(I.tot0);
   dd cS = {0.0, 0.0}, cPT = {0.0, 0.0};
@@ -286,8 +326,9 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
       wh = w / 2.0 - nd * d * d / 8.0;             // modified weight
       lr = dd_log(r);
       const unsigned hs = slot_of(j, I.C, I.nt);   // home slot of ring j
-      w_out[hs] = w; wh_out[hs] = wh; r0_out[hs] = r; ir0_out[hs] = 1.0 / r;
-      l0h[hs] = lr.hi; l0l[hs] = lr.lo;
+      cst[RC_W * PS + hs] = d2(w, wh);
+      cst[RC_R0 * PS + hs] = d2(r, 1.0 / r);
+      cst[RC_LN * PS + hs] = d2(lr.hi, lr.lo);
     }
     const dd wl = dd_mul_d(lr, w);
     Pack<4> tot;
@@ -305,8 +346,10 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
       rec[IR_DPH] = dp.hi; rec[IR_DPL] = dp.lo;
       // initial state: position j holds ring j; its interval starts at its node
       const unsigned sl = slot_of(j, I.C, I.nt);
-      I.rho[0][sl] = r; I.u[0][sl] = 0.0; I.fr[0][sl] = 0.0; I.fu[0][sl] = 0.0;
-      I.hs[0][sl] = (int32_t)sl; I.hint[0][sl] = j + 1;
+      st[RS_RU * PS + sl] = d2(r, 0.0);
+      st[RS_F * PS + sl] = d2(0.0, 0.0);
+      st[RS_LN * PS + sl] = d2(0.0, 0.0);
+      st[RS_HH * PS + sl] = d2(hh_pack((int32_t)sl, j + 1), 0.0);
     }
     cS = dd_add(cS, {tot.v[0], tot.v[1]});
     cPT = dd_add(cPT, {tot.v[2], tot.v[3]});
@@ -467,8 +510,7 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
   const double iC = 1.0 / (double)C;
   const int p0 = tid * C;
   const int cnt = max(0, min(C, N - p0));
-  const GA<double> R = uview(I.rho[buf]);
-  const GA<int32_t> HS = uview(I.hs[buf]);
+  const PV SB = pview(I.st[buf], (uint32_t)(C * NT));
   const GA<double> PMR = uview(I.sm_r);
   const GA<int32_t> PMI = uview(I.sm_i), FL = uview(I.flag), CL = uview(I.cls), PERM = uview(I.perm);
   // chunk extremes; maximum key before each position of the chunk
@@ -478,7 +520,7 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
     const unsigned sl = k * NT + tid;
     PMR.st(sl, mx.v[0]);
     PMI.st(sl, (int32_t)mx.v[1]);
-    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
+    const Pack<2> key = {{st_rho(SB, sl), (double)id_of<NT>(st_hs(SB, sl), C)}};
     mx = MaxKeyOp()(mx, key);
     mn = MinKeyOp()(mn, key);
   }
@@ -492,7 +534,7 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
   #pragma unroll 1
   for (int k = cnt - 1; k >= 0; --k) {
     const unsigned sl = k * NT + tid;
-    const Pack<2> key = {{R[sl], (double)id_of<NT>(HS[sl], C)}};
+    const Pack<2> key = {{st_rho(SB, sl), (double)id_of<NT>(st_hs(SB, sl), C)}};
     sm = MinKeyOp()(sm, key);
     const Pack<2> pm = MaxKeyOp()(before, Pack<2>{{PMR[sl], (double)PMI[sl]}});
     const bool b = (p0 + k == 0) || key_lt(pm.v[0], (int32_t)pm.v[1], sm.v[0], (int32_t)sm.v[1]);
@@ -526,8 +568,8 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
     if (e - ra == 1) {
       PERM.st(sl, (int32_t)sl);
     } else if (e - ra <= WAKE_SEGMAX) {
-      const double r = R[sl];
-      const int32_t id = id_of<NT>(HS[sl], C);
+      const double r = st_rho(SB, sl);
+      const int32_t id = id_of<NT>(st_hs(SB, sl), C);
       const int qi = pos_index<NT>(ra, C, iC);
       int qk = qi / NT, qt = qi % NT;
       int rank = 0;
@@ -542,7 +584,7 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
         double xr[4];
         int32_t xh[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { xr[i] = R[x[i]]; xh[i] = HS[x[i]]; }
+        for (int i = 0; i < 4; ++i) { xr[i] = st_rho(SB, x[i]); xh[i] = st_hs(SB, x[i]); }
 #pragma unroll
         for (int i = 0; i < 4; ++i) rank += key_lt(xr[i], id_of<NT>(xh[i], C), r, id) ? 1 : 0;
       }
@@ -569,8 +611,8 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
       const unsigned sl = k * NT + tid;
       if (CL[sl] != -1) continue;
       I.free_slot[j] = (int32_t)sl;
-      const double r = R[sl];
-      const int32_t id = id_of<NT>(HS[sl], C);
+      const double r = st_rho(SB, sl);
+      const int32_t id = id_of<NT>(st_hs(SB, sl), C);
       if (in_lds) { zr[j] = r; zi[j] = id; zs[j] = (int32_t)sl; }
       else { I.sk_r[0][j] = r; I.sk_i[0][j] = id; I.sk_s[0][j] = (int32_t)sl; }
       ++j;
@@ -609,8 +651,8 @@ __device__ __noinline__ void fix_order_lds(const WakeInst& I, double* s_scan, do
   const int p0 = tid * C;
   const int cnt = max(0, min(C, N - p0));
   Pack<2> mx = {{-INFINITY, -2147483648.0}}, mn = {{INFINITY, 2147483647.0}};
-  double pr[CMAX];
-  int32_t pi[CMAX];      // maximum key before each position of the chunk
+  double pr[CMAX > 0 ? CMAX : 1];
+  int32_t pi[CMAX > 0 ? CMAX : 1];      // maximum key before each position of the chunk
 #pragma unroll
   for (int k = 0; k < CMAX; ++k) {
     if (k < cnt) {
@@ -805,17 +847,18 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
                                            bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
   const int tid = threadIdx.x;
   const unsigned smax = (unsigned)(I.C * NT - 1);
-  const GA<double> Wv = uview(I.w), LH = uview(I.lnh[cur]), LL = uview(I.lnl[cur]);
-  const GA<int32_t> HS = uview(I.hs[cur]);
+  const uint32_t ps = (uint32_t)(I.C * NT);
+  const PV SC = pview(I.st[cur], ps), K = pview(I.cst, ps);
   sw = {0.0, 0.0};
   swl = {0.0, 0.0};
   #pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
     const unsigned s = ident ? sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[sl], smax);
-    const double w = Wv[HS[s]];
+    const double w = K.ldh(RC_W, (unsigned)st_hs(SC, s), 0);
+    const D2 l = SC.ld(RS_LN, s);
     sw = dd_add_d(sw, w);
-    swl = dd_add(swl, dd_mul_d(dd{LH[s], LL[s]}, w));
+    swl = dd_add(swl, dd_mul_d(dd{l.x, l.y}, w));
   }
 }
 
@@ -862,8 +905,9 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
-      s_kr[sl] = I.rho[cur][sl];
-      s_ki[sl] = (uint16_t)id_of<NT>(I.hs[cur][sl], C);
+      const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
+      s_kr[sl] = st_rho(SB, sl);
+      s_ki[sl] = (uint16_t)id_of<NT>(st_hs(SB, sl), C);
     }
     __syncthreads();
     fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
@@ -876,15 +920,15 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   }
   const dd tot0 = {uni(I.tot0[0]), uni(I.tot0[1])};
   const double dxi = I.dxi;
-  const LogView LV = log_view(I);
   IonView IV;
   IV.R = uview(I.ion);
   IV.N = N;
   IV.Rp = I.Rp;
   IV.T0 = tot0;
   IV.Q = {uni(I.tot0[2]), uni(I.tot0[3])};
-  const GA<double> Wc = uview(I.w), WHc = uview(I.wh);
-  const GA<double> PSI = uview(I.psi), DPSI = uview(I.dpsi), BB = uview(I.bb), A2 = uview(I.a2), DA2 = uview(I.da2);
+  const uint32_t ps = (uint32_t)(C * NT);
+  const PV KC = pview(I.cst, ps), SCR = pview(I.sc, ps);
+  const GA<double> A2 = uview(I.a2), DA2 = uview(I.da2);
   const int n_an = I.n_an;
   const bool has_laser = I.has_laser != 0;
 
@@ -893,9 +937,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
     const unsigned s = WAKE_SLOT(sl);
-    const dd lr = ring_log(LV, I.hs[cur][s], I.rho[cur][s]);
-    I.lnh[cur][s] = lr.hi;
-    I.lnl[cur][s] = lr.lo;
+    const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
+    const unsigned hs = (unsigned)st_hs(SB, s);
+    const dd lr = ring_log(KC.ld(RC_R0, hs), KC.ld(RC_LN, hs), st_rho(SB, s));
+    SB.st(RS_LN, s, d2(lr.hi, lr.lo));
   }
   // The sums in the order the march itself would have left them in (so that
   // a solve split over several launches is bitwise the one-launch solve):
@@ -909,9 +954,11 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
-      const double w = Wc[I.hs[cur][s]];
+      const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
+      const double w = KC.ldh(RC_W, (unsigned)st_hs(SB, s), 0);
+      const D2 l = SB.ld(RS_LN, s);
       sw = dd_add_d(sw, w);
-      swl = dd_add(swl, dd_mul_d(dd{I.lnh[cur][s], I.lnl[cur][s]}, w));
+      swl = dd_add(swl, dd_mul_d(dd{l.x, l.y}, w));
     }
   }
   int n = I.first;
@@ -952,8 +999,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
     const bool rec_last = n == end - 1;
     const int nb = 1 - cur;
-    const GA<double> rho_c = uview(I.rho[cur]), u_c = uview(I.u[cur]);
-    const GA<int32_t> hs_c = uview(I.hs[cur]);
+    const PV Sc = pview(I.st[cur], ps), Sn = pview(I.st[nb], ps);
     int bt0 = 0, bm = 0;
     if (I.nb) {
       bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
@@ -970,35 +1016,53 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     double l0a = 0.0, l0b = 0.0, l1a = 0.0, l1b = 0.0;
     bad = 0.0;
     int blo = 0;
-    // the next ring's state is loaded one ring ahead
-    const GA<int32_t> hint_c = uview(I.hint[cur]);
-    const GA<double> lnh_c = uview(I.lnh[cur]), lnl_c = uview(I.lnl[cur]);
-    const GA<int32_t> hs_nb = uview(I.hs[nb]), hint_nb = uview(I.hint[nb]);
-    double x_rho = 1.0, x_u = 0.0, x_lh = 0.0, x_ll = 0.0;
-    int32_t x_hs = 0, x_h = 0;
+    // loads run ahead: the state of ring k+2 and the constants and ion
+    // record of ring k+1 are requested while ring k is computed
+    D2 x_ru = d2(1.0, 0.0), x_ln = d2(0.0, 0.0), z_ru = d2(1.0, 0.0), z_ln = d2(0.0, 0.0);
+    double x_hh = 0.0, z_hh = 0.0;                   // (home slot, hint) bits
+    D2 x_wc = d2(0.0, 0.0);                          // (w, w^) of ring k+1
+    double x_q[WAKE_ION_REC];
     if (cnt > 0) {
       const unsigned s = WAKE_SLOT(tid);
-      x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
+      x_ru = Sc.ld(RS_RU, s); x_ln = Sc.ld(RS_LN, s);
+      x_hh = Sc.ldh(RS_HH, s, 0);
+    }
+    if (cnt > 1) {
+      const unsigned s = WAKE_SLOT(NT + tid);
+      z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
+      z_hh = Sc.ldh(RS_HH, s, 0);
+    }
+    if (cnt > 0) {
+      x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
+      ion_load(IV, hh_hint(x_hh), x_q);
     }
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
-      const double rho = x_rho, u = x_u;
-      const int32_t hs = x_hs;
-      int h = x_h;
-      const dd lnr = {x_lh, x_ll};
-      if (k + 1 < cnt) {
-        const unsigned sn = sl + NT;
-        const unsigned s = WAKE_SLOT(sn);
-        x_rho = rho_c[s]; x_u = u_c[s]; x_hs = hs_c[s]; x_h = hint_c[s]; x_lh = lnh_c[s]; x_ll = lnl_c[s];
+      const double rho = x_ru.x, u = x_ru.y;
+      const int32_t hs = hh_hs(x_hh);
+      int h = hh_hint(x_hh);
+      const dd lnr = {x_ln.x, x_ln.y};
+      const double w = x_wc.x, wh = x_wc.y;
+      double q[WAKE_ION_REC];
+#pragma unroll
+      for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = x_q[i];
+      x_ru = z_ru; x_ln = z_ln; x_hh = z_hh;
+      if (k + 2 < cnt) {
+        const unsigned s = WAKE_SLOT(sl + 2 * NT);
+        z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
+        z_hh = Sc.ldh(RS_HH, s, 0);
       }
-      const double w = Wc[hs], wh = WHc[hs];
+      if (k + 1 < cnt) {
+        x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
+        ion_load(IV, hh_hint(x_hh), x_q);
+      }
       const double irho = 1.0 / rho;
       const dd PTi = dd_add(PT, dd_mul_d(lnr, w));
       const dd pe = dd_sub(dd_mul(dd_add_d(S, w), lnr), PTi);    // psi_e - sum w ln rho
       const dd de = dd_div_rcp(dd_add_d(S, wh), rho, irho);         // d_rho psi_e (self w^)
       dd ips, idp;
-      ion_fields(IV, rho, lnr, h, ips, idp);
+      ion_fields(IV, rho, lnr, h, q, ips, idp);
       const double psi = dd_round(dd_add(pe, ips)) + psi_axis;
       const double dpsi = dd_round(dd_add(de, idp));
       S = dd_add_d(S, w);
@@ -1038,13 +1102,11 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       l0b += G.v[1] * s0b - G.v[3] * s0a;
       l1a += G.v[0] * s1b - G.v[2] * s1a;
       l1b += G.v[1] * s1b - G.v[3] * s1a;
-      PSI.st(sl, psi);
-      DPSI.st(sl, dpsi);
-      BB.st(sl, bb);
+      SCR.st(SC_PSI, sl, d2(psi, dpsi));
+      SCR.sth(SC_BB, sl, 0, bb);
       if (has_laser) { A2.st(sl, aa); DA2.st(sl, dda); }
       // the ring's home slot and hint move to its position slot in the next buffer
-      hs_nb.st(sl, hs);
-      hint_nb.st(sl, h);
+      Sn.sth(RS_HH, sl, 0, hh_pack(hs, h));
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1081,32 +1143,52 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     int32_t nxt_i = 0x7fffffff, last_i = 0x7fffffff;
     dd sw2 = {0.0, 0.0}, swl2 = {0.0, 0.0};
     double dis_l = 0.0;
-    const GA<double> rho_n = uview(I.rho[nb]), u_n = uview(I.u[nb]), fr_n = uview(I.fr[nb]), fu_n = uview(I.fu[nb]);
-    const GA<double> lnh_n = uview(I.lnh[nb]), lnl_n = uview(I.lnl[nb]);
-    // the next ring (one position back) is loaded one ring ahead
-    const GA<int32_t> hs_n = uview(I.hs[nb]);
-    const GA<double> fr_c = uview(I.fr[cur]), fu_c = uview(I.fu[cur]);
-    double y_rho = 1.0, y_u = 0.0, y_fr = 0.0, y_fu = 0.0, y_psi = 0.0, y_dpsi = 0.0, y_bb = 0.0;
+    // loads run ahead (the march goes backward): the state of ring k-2 and
+    // the constants of ring k-1 are requested while ring k is computed
+    D2 y_ru = d2(1.0, 0.0), y_f = d2(0.0, 0.0), y_ps = d2(0.0, 0.0);    // ring k-1
+    double y_bb = 0.0;
     int32_t y_hs = 0;
+    D2 v_ru = d2(1.0, 0.0), v_f = d2(0.0, 0.0), v_ps = d2(0.0, 0.0);    // ring k-2
+    double v_bb = 0.0;
+    int32_t v_hs = 0;
+    D2 c_w = d2(1.0, 0.0), c_r = d2(1.0, 1.0), c_l = d2(0.0, 0.0);      // ring k-1
     if (cnt > 0) {
       const unsigned sl = (cnt - 1) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
-      y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
-      y_hs = hs_n[sl]; y_psi = PSI[sl]; y_dpsi = DPSI[sl]; y_bb = BB[sl];
+      y_ru = Sc.ld(RS_RU, s); y_f = Sc.ld(RS_F, s);
+      y_hs = hh_hs(Sn.ldh(RS_HH, sl, 0));
+      y_ps = SCR.ld(SC_PSI, sl); y_bb = SCR.ldh(SC_BB, sl, 0);
+    }
+    if (cnt > 1) {
+      const unsigned sl = (cnt - 2) * NT + tid;
+      const unsigned s = WAKE_SLOT(sl);
+      v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
+      v_hs = hh_hs(Sn.ldh(RS_HH, sl, 0));
+      v_ps = SCR.ld(SC_PSI, sl); v_bb = SCR.ldh(SC_BB, sl, 0);
+    }
+    if (cnt > 0) {
+      const unsigned kc = (unsigned)y_hs;
+      c_w = KC.ld(RC_W, kc); c_r = KC.ld(RC_R0, kc); c_l = KC.ld(RC_LN, kc);
     }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
-      const double rho = y_rho, u = y_u, fr_p = y_fr, fu_p = y_fu;
+      const double rho = y_ru.x, u = y_ru.y, fr_p = y_f.x, fu_p = y_f.y;
       const int32_t hs = y_hs;
-      const double psi = y_psi, dpsi = y_dpsi, bb = y_bb;
-      if (k > 0) {
-        const unsigned sp = sl - NT;
+      const double psi = y_ps.x, dpsi = y_ps.y, bb = y_bb;
+      const double w = c_w.x, wh = c_w.y, k_r0 = c_r.x, k_ir0 = c_r.y, k_lh = c_l.x, k_ll = c_l.y;
+      y_ru = v_ru; y_f = v_f; y_hs = v_hs; y_ps = v_ps; y_bb = v_bb;
+      if (k > 1) {
+        const unsigned sp = sl - 2 * NT;
         const unsigned s = WAKE_SLOT(sp);
-        y_rho = rho_c[s]; y_u = u_c[s]; y_fr = fr_c[s]; y_fu = fu_c[s];
-        y_hs = hs_n[sp]; y_psi = PSI[sp]; y_dpsi = DPSI[sp]; y_bb = BB[sp];
+        v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
+        v_hs = hh_hs(Sn.ldh(RS_HH, sp, 0));
+        v_ps = SCR.ld(SC_PSI, sp); v_bb = SCR.ldh(SC_BB, sp, 0);
       }
-      const double w = Wc[hs], wh = WHc[hs];
+      if (k > 0) {
+        const unsigned kc = (unsigned)y_hs;
+        c_w = KC.ld(RC_W, kc); c_r = KC.ld(RC_R0, kc); c_l = KC.ld(RC_LN, kc);
+      }
       const double a2 = has_laser ? A2[sl] : 0.0, da2 = has_laser ? DA2[sl] : 0.0;
       const double irho = 1.0 / rho;
       const Local L = local_of(irho, u, w, psi, a2);
@@ -1150,10 +1232,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         double sr = f_r, su = f_u;
         if (rn < 0.0) { rn = -rn; un = -un; sr = -sr; su = -su; }
         if (!(isfinite(rn) && isfinite(un))) bad = 1.0;
-        rho_n.st(sl, rn); u_n.st(sl, un); fr_n.st(sl, sr); fu_n.st(sl, su);
-        const dd lr = ring_log(LV, hs, rn);
-        lnh_n.st(sl, lr.hi);
-        lnl_n.st(sl, lr.lo);
+        const dd lr = dd_add_d({k_lh, k_ll}, log1p((rn - k_r0) * k_ir0));   // as ring_log
+        Sn.st(RS_RU, sl, d2(rn, un));
+        Sn.st(RS_F, sl, d2(sr, su));
+        Sn.st(RS_LN, sl, d2(lr.hi, lr.lo));
         sw2 = dd_add_d(sw2, w);
         swl2 = dd_add(swl2, dd_mul_d(lr, w));
         if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
@@ -1224,12 +1306,14 @@ __global__ void state_by_id_kernel(WakeInst I, double* rho, double* u, double* f
   if (p >= I.N) return;
   const int c = I.ctl[CTL_CUR];
   const unsigned sl = slot_of(p, I.C, I.nt);
-  const int hs = I.hs[c][sl];
+  const size_t PS = (size_t)I.C * I.nt;
+  const D2* r = reinterpret_cast<const D2*>(I.st[c]) + sl;
+  const int hs = hh_hs(r[RS_HH * PS].x);
   const int i = (hs % I.nt) * I.C + hs / I.nt;
-  if (rho) rho[i] = I.rho[c][sl];
-  if (u) u[i] = I.u[c][sl];
-  if (fr) fr[i] = I.fr[c][sl];
-  if (fu) fu[i] = I.fu[c][sl];
+  if (rho) rho[i] = r[RS_RU * PS].x;
+  if (u) u[i] = r[RS_RU * PS].y;
+  if (fr) fr[i] = r[RS_F * PS].x;
+  if (fu) fu[i] = r[RS_F * PS].y;
 }
 
 // Injected state (by id) at position = id in buffer 0; the marcher orders
@@ -1240,12 +1324,12 @@ __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u,
   if (i == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = slice; }
   if (i >= I.N) return;
   const unsigned sl = slot_of(i, I.C, I.nt);
-  I.rho[0][sl] = rho[i];
-  I.u[0][sl] = u[i];
-  I.fr[0][sl] = fr ? fr[i] : 0.0;
-  I.fu[0][sl] = fu ? fu[i] : 0.0;
-  I.hs[0][sl] = (int32_t)sl;
-  I.hint[0][sl] = i + 1;
+  const size_t PS = (size_t)I.C * I.nt;
+  D2* r = reinterpret_cast<D2*>(I.st[0]) + sl;
+  r[RS_RU * PS] = d2(rho[i], u[i]);
+  r[RS_F * PS] = d2(fr ? fr[i] : 0.0, fu ? fu[i] : 0.0);
+  r[RS_LN * PS] = d2(0.0, 0.0);
+  r[RS_HH * PS] = d2(hh_pack((int32_t)sl, i + 1), 0.0);
 }
 
 // Back to the state at slice 0 (rings at rest at their initial radii);
@@ -1254,12 +1338,12 @@ __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_ins
   const WakeInst& I = insts[blockIdx.x];
   for (int j = threadIdx.x; j < I.N; j += blockDim.x) {
     const unsigned sl = slot_of(j, I.C, I.nt);
-    I.rho[0][sl] = I.r0[sl];
-    I.u[0][sl] = 0.0;
-    I.fr[0][sl] = 0.0;
-    I.fu[0][sl] = 0.0;
-    I.hs[0][sl] = (int32_t)sl;
-    I.hint[0][sl] = j + 1;
+    const size_t PS = (size_t)I.C * I.nt;
+    D2* r = reinterpret_cast<D2*>(I.st[0]) + sl;
+    r[RS_RU * PS] = d2(reinterpret_cast<const D2*>(I.cst)[RC_R0 * PS + sl].x, 0.0);
+    r[RS_F * PS] = d2(0.0, 0.0);
+    r[RS_LN * PS] = d2(0.0, 0.0);
+    r[RS_HH * PS] = d2(hh_pack((int32_t)sl, j + 1), 0.0);
   }
   if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; }
 }
