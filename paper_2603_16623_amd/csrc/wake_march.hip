@@ -641,6 +641,155 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
 // Run boundaries come from register prefix maxima, run extents from a scan
 // of the first and last boundary of each chunk; short runs are ranked by
 // counting, long runs sorted together.
+// (rho, id) order of packed keys: k = id << 16 | slot, so that equal radii
+// fall back to the ring id.
+__device__ __forceinline__ bool pk_lt(double ra, uint32_t ka, double rb, uint32_t kb) {
+  return (ra < rb) | ((ra == rb) & (ka < kb));     // no short-circuit: straight-line selects
+}
+
+// Value of lane (lane ^ lm) of the wave, lm in {1, 2, 4, 8, 16, 32}, by
+// register-level moves (DPP within rows of 16 lanes, lane-swap instructions
+// across rows and halves) rather than through the LDS crossbar.
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lm) {
+  const int lane = threadIdx.x & 63;
+  switch (lm) {
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
+    case 4: {
+      const uint32_t up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, true);   // from lane + 4
+      const uint32_t dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);   // from lane - 4
+      return (lane & 4) ? dn : up;
+    }
+    case 8: return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, true);  // rotate row by 8
+    case 16: {
+      const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+      return (lane & 16) ? r[0] : r[1];
+    }
+    default: {
+      const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+      return (lane & 32) ? r[0] : r[1];
+    }
+  }
+}
+__device__ __forceinline__ double lane_xor(double x, int lm) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_xor((uint32_t)v, lm), hi = lane_xor((uint32_t)(v >> 32), lm);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One wave puts the positions [b0, b0 + 256) (clipped at N) in (rho, id)
+// order: four keys per lane, read through the current order perm, sorted by
+// a bitonic network over registers and lane exchanges, written back as the
+// new order of these positions.  A block already in order is left alone.
+template <int NT>
+__device__ __forceinline__ void sort_block_wave(int b0, int N, int C, double iC, const double* kr,
+                                                const uint16_t* ki, uint16_t* perm) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint32_t k[4];
+  int sl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    sl[j] = -1;
+    r[j] = INFINITY;
+    k[j] = 0xffffffffu;
+    if (p < N) {
+      sl[j] = pos_index<NT>(p, C, iC);
+      const unsigned src = perm[sl[j]];
+      r[j] = kr[src];
+      k[j] = ((uint32_t)ki[src] << 16) | src;
+    }
+  }
+  bool ok = !pk_lt(r[1], k[1], r[0], k[0]) && !pk_lt(r[2], k[2], r[1], k[1]) &&
+            !pk_lt(r[3], k[3], r[2], k[2]);
+  const double nr = __shfl_down(r[0], 1, 64);
+  const uint32_t nk = __shfl_down(k[0], 1, 64);
+  if (lane < 63) ok = ok && !pk_lt(nr, nk, r[3], k[3]);
+  if (__all(ok)) return;
+#pragma unroll
+  for (int kk = 2; kk <= 256; kk <<= 1) {
+#pragma unroll
+    for (int d = kk >> 1; d > 0; d >>= 1) {
+      if (d >= 4) {                 // partner in lane ^ (d / 4), same register
+        const int lm = d >> 2;
+        const bool lower = (lane & lm) == 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double pr = lane_xor(r[j], lm);
+          const uint32_t pq = lane_xor(k[j], lm);
+          const bool up = ((4 * lane + j) & kk) == 0;
+          if (pk_lt(pr, pq, r[j], k[j]) == (lower == up)) { r[j] = pr; k[j] = pq; }
+        }
+      } else {                      // partner in this lane
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j & d) continue;
+          const int jj = j | d;
+          const bool up = ((4 * lane + j) & kk) == 0;
+          if (pk_lt(r[jj], k[jj], r[j], k[j]) == up) {
+            const double tr = r[j]; r[j] = r[jj]; r[jj] = tr;
+            const uint32_t tk = k[j]; k[j] = k[jj]; k[jj] = tk;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (sl[j] >= 0) perm[sl[j]] = (uint16_t)(k[j] & 0xffffu);
+}
+
+// Order fix-up for nearly sorted keys in LDS: blocks of 256 positions sorted
+// by single waves, first at offsets 0, 256, 512, ... and then at 128, 384,
+// ...  If no ring is more than 128 positions from its place in the order,
+// the two phases leave the whole sequence sorted (with the keys cut at any
+// threshold, the mixed zone left by the first phase lies inside one block
+// of the second).  Up to two such rounds; returns whether the order is
+// complete (else the caller runs the general fix-up).
+template <int NT>
+__device__ __noinline__ bool fix_order_blocks(const WakeInst& I, const double* kr, const uint16_t* ki,
+                                              uint16_t* perm) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int N = I.N, C = I.C;
+  const double iC = 1.0 / (double)C;
+  const int p0 = tid * C;
+  const int cnt = max(0, min(C, N - p0));
+  for (int k = 0; k < cnt; ++k) perm[k * NT + tid] = (uint16_t)(k * NT + tid);
+  __syncthreads();
+  #pragma unroll 1
+  for (int round = 0; round < 2; ++round) {
+    #pragma unroll 1
+    for (int b = wave; b * 256 < N; b += NW) sort_block_wave<NT>(b * 256, N, C, iC, kr, ki, perm);
+    __syncthreads();
+    #pragma unroll 1
+    for (int b = wave; 128 + b * 256 < N; b += NW) sort_block_wave<NT>(128 + b * 256, N, C, iC, kr, ki, perm);
+    __syncthreads();
+    // in order? (this chunk, and its last position against the next chunk's first)
+    int bad = 0;
+    if (cnt > 0) {
+      unsigned src = perm[tid];
+      double pr = kr[src];
+      uint32_t pq = ((uint32_t)ki[src] << 16) | src;
+      const int m = p0 + cnt < N ? cnt + 1 : cnt;
+      #pragma unroll 1
+      for (int k = 1; k < m; ++k) {
+        const unsigned sl = k < cnt ? k * NT + tid : tid + 1;
+        src = perm[sl];
+        const double r = kr[src];
+        const uint32_t q = ((uint32_t)ki[src] << 16) | src;
+        if (pk_lt(r, q, pr, pq)) bad = 1;
+        pr = r;
+        pq = q;
+      }
+    }
+    if (!__syncthreads_or(bad)) return true;
+  }
+  return false;
+}
+
 template <int NT, int CMAX>
 __device__ __noinline__ void fix_order_lds(const WakeInst& I, double* s_scan, double* s_scan2,
                                            unsigned char* region, const double* kr,
@@ -980,7 +1129,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     if (n == end) break;
     if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
       if (lds_keys) {
-        fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
+        if (!fix_order_blocks<NT>(I, s_kr, s_ki, s_perm))
+          fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
       } else {
         fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
       }

@@ -206,6 +206,35 @@ def test_unsorted_injected_state_is_sorted_first(wk):
         s.close()
 
 
+@pytest.mark.parametrize("u_amp", [0.05, 2.0, 40.0])
+def test_reorder_after_push(wk, u_amp):
+    """Rings pushed past many neighbours in one step (from a few positions up
+    to thousands) come out in the same order as the oracle's sort: the slice
+    after the push matches."""
+    rng = np.random.default_rng(31)
+    inst = W.small_instance(5, n_rings=3000, n_xi=40, n_peak=2.0, geometric=False)
+    o = _oracle(inst)
+    state = o.initial_state()
+    state["u"] = rng.normal(0, u_amp, inst.n_rings)
+    n = 10
+    _, mid = o.slice(n, state, keep=True)
+    ref, _ = o.slice(n + 1, mid, keep=True)
+    F = _field_scale(ref)
+    order = np.lexsort((np.arange(inst.n_rings), mid["rho"]))
+    disp = int(np.abs(np.argsort(order) - np.arange(inst.n_rings)).max())
+    for tiling in ((512, 0), (256, 0)):
+        wk.wake_set_tiling(*tiling)
+        _say(f"reorder after push u_amp={u_amp} tiling={tiling} max displacement {disp}")
+        s = wk.WakeSolver.from_instance(inst, record_stride=1)
+        s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(n, 2)
+        got = s.wake_fields(n + 1)
+        for q in FIELDS:
+            assert float(np.max(np.abs(got[q] - ref[q]))) <= _field_tol(F), (tiling, q)
+        assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
+        s.close()
+
+
 def test_breakdown_is_reported_at_the_same_slice(wk):
     inst = W.small_instance(4, n_rings=200, n_xi=30, n_peak=1.0)
     o = _oracle(inst)
