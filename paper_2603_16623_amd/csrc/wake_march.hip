@@ -671,6 +671,20 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lm) {
     }
   }
 }
+// Value of the next (lane + 1) or previous (lane - 1) lane of the wave (a
+// whole-wave DPP shift; the last / first lane reads 0).
+__device__ __forceinline__ uint32_t lane_next(uint32_t x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ uint32_t lane_prev(uint32_t x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ double lane_next(double x) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_next((uint32_t)v), hi = lane_next((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_prev(double x) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_prev((uint32_t)v), hi = lane_prev((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 __device__ __forceinline__ double lane_xor(double x, int lm) {
   const uint64_t v = (uint64_t)__double_as_longlong(x);
   const uint32_t lo = lane_xor((uint32_t)v, lm), hi = lane_xor((uint32_t)(v >> 32), lm);
@@ -707,6 +721,46 @@ __device__ __forceinline__ void sort_block_wave(int b0, int N, int C, double iC,
   const uint32_t nk = __shfl_down(k[0], 1, 64);
   if (lane < 63) ok = ok && !pk_lt(nr, nk, r[3], k[3]);
   if (__all(ok)) return;
+  // Odd-even transposition first: the rings of a run of length L reach
+  // their places within L phases and never cross a run boundary, so blocks
+  // with short runs (the common case) are done after a few phases.  Order
+  // checked every four phases; a block still out of order after 32 phases
+  // goes through the full bitonic network.
+  #pragma unroll 1
+  for (int it = 0; it < 8; ++it) {
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+      // even phase: (0,1) (2,3); odd phase: (1,2) and (3 | next lane's 0)
+#pragma unroll
+      for (int j = 0; j < 4; j += 2) {
+        if (pk_lt(r[j + 1], k[j + 1], r[j], k[j])) {
+          const double tr = r[j]; r[j] = r[j + 1]; r[j + 1] = tr;
+          const uint32_t tk = k[j]; k[j] = k[j + 1]; k[j + 1] = tk;
+        }
+      }
+      if (pk_lt(r[2], k[2], r[1], k[1])) {
+        const double tr = r[1]; r[1] = r[2]; r[2] = tr;
+        const uint32_t tk = k[1]; k[1] = k[2]; k[2] = tk;
+      }
+      const double nr = lane_next(r[0]), pr = lane_prev(r[3]);
+      const uint32_t nq = lane_next(k[0]), pq = lane_prev(k[3]);
+      const bool take_next = lane < 63 && pk_lt(nr, nq, r[3], k[3]);    // keep the smaller
+      const bool take_prev = lane > 0 && pk_lt(r[0], k[0], pr, pq);     // keep the larger
+      if (take_next) { r[3] = nr; k[3] = nq; }
+      if (take_prev) { r[0] = pr; k[0] = pq; }
+    }
+    bool in_order = !pk_lt(r[1], k[1], r[0], k[0]) && !pk_lt(r[2], k[2], r[1], k[1]) &&
+                    !pk_lt(r[3], k[3], r[2], k[2]);
+    const double xr = lane_next(r[0]);
+    const uint32_t xq = lane_next(k[0]);
+    if (lane < 63) in_order = in_order && !pk_lt(xr, xq, r[3], k[3]);
+    if (__all(in_order)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (sl[j] >= 0) perm[sl[j]] = (uint16_t)(k[j] & 0xffffu);
+      return;
+    }
+  }
 #pragma unroll
   for (int kk = 2; kk <= 256; kk <<= 1) {
 #pragma unroll
