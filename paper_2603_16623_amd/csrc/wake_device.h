@@ -118,20 +118,126 @@ struct Pack {
   double v[NF];
 };
 
-template <int NF>
-__device__ __forceinline__ Pack<NF> shfl_up_pack(const Pack<NF>& p, int d) {
+// ---------------------------------------------------------------------------
+// Wave-level scans on DPP row shifts (lanes of a 16-lane row) and lane reads
+// (across rows), then one LDS exchange of the wave totals per workgroup.
+// ---------------------------------------------------------------------------
+// DPP move of each double of a pack (two 32-bit halves).  CTRL 0x110 + d:
+// lane i reads lane i - d of its row; 0x100 + d: lane i + d; 0x138 / 0x130:
+// the previous / next lane of the wave.  Lanes with no source read 0.  A
+// DPP read from a lane that is switched off reads 0 too, so these moves are
+// always evaluated with the whole wave active, never as one operand of ?:
+// or && (which evaluates it under a partial mask).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int NF>
+__device__ __forceinline__ Pack<NF> dpp_pack(const Pack<NF>& p) {
   Pack<NF> r;
 #pragma unroll
-  for (int i = 0; i < NF; ++i) r.v[i] = __shfl_up(p.v[i], d, 64);
+  for (int i = 0; i < NF; ++i) r.v[i] = dpp_d<CTRL>(p.v[i]);
+  return r;
+}
+// the pack of lane l (l uniform over the wave)
+template <int NF>
+__device__ __forceinline__ Pack<NF> lane_pack(const Pack<NF>& p, int l) {
+  Pack<NF> r;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    const long long v = __double_as_longlong(p.v[i]);
+    const int lo = __builtin_amdgcn_readlane((int)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    r.v[i] = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+  return r;
+}
+template <int NF>
+__device__ __forceinline__ Pack<NF> pick(bool c, const Pack<NF>& a, const Pack<NF>& b) {
+  Pack<NF> r;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) r.v[i] = c ? a.v[i] : b.v[i];
   return r;
 }
 
-template <int NF>
-__device__ __forceinline__ Pack<NF> shfl_down_pack(const Pack<NF>& p, int d) {
-  Pack<NF> r;
+// Inclusive prefix within each 16-lane row over the first M lanes of the
+// row (M <= 16), op(earlier, later).
+template <int M, int NF, class Op>
+__device__ __forceinline__ Pack<NF> row_prefix_incl(Pack<NF> inc, Op op) {
+  const int lr = threadIdx.x & 15;
+  if (M > 1) { const Pack<NF> o = dpp_pack<0x111>(inc); if (lr >= 1) inc = op(o, inc); }
+  if (M > 2) { const Pack<NF> o = dpp_pack<0x112>(inc); if (lr >= 2) inc = op(o, inc); }
+  if (M > 4) { const Pack<NF> o = dpp_pack<0x114>(inc); if (lr >= 4) inc = op(o, inc); }
+  if (M > 8) { const Pack<NF> o = dpp_pack<0x118>(inc); if (lr >= 8) inc = op(o, inc); }
+  return inc;
+}
+// Inclusive suffix within each row over its first M lanes, op(lower, higher).
+template <int M, int NF, class Op>
+__device__ __forceinline__ Pack<NF> row_suffix_incl(Pack<NF> inc, Op op) {
+  const int lr = threadIdx.x & 15;
+  if (M > 1) { const Pack<NF> o = dpp_pack<0x101>(inc); if (lr + 1 < M) inc = op(inc, o); }
+  if (M > 2) { const Pack<NF> o = dpp_pack<0x102>(inc); if (lr + 2 < M) inc = op(inc, o); }
+  if (M > 4) { const Pack<NF> o = dpp_pack<0x104>(inc); if (lr + 4 < M) inc = op(inc, o); }
+  if (M > 8) { const Pack<NF> o = dpp_pack<0x108>(inc); if (lr + 8 < M) inc = op(inc, o); }
+  return inc;
+}
+// Inclusive prefix over the 64 lanes of the wave.
+template <int NF, class Op>
+__device__ __forceinline__ Pack<NF> wave_prefix_incl(const Pack<NF>& x, Op op) {
+  Pack<NF> inc = row_prefix_incl<16>(x, op);
+  const int row = (threadIdx.x & 63) >> 4;
+  const Pack<NF> t0 = lane_pack(inc, 15), t1 = lane_pack(inc, 31), t2 = lane_pack(inc, 47);
+  const Pack<NF> t01 = op(t0, t1);
+  const Pack<NF> t012 = op(t01, t2);
+  const Pack<NF> pre = pick(row == 1, t0, pick(row == 2, t01, t012));
+  if (row > 0) inc = op(pre, inc);
+  return inc;
+}
+// Inclusive suffix over the 64 lanes of the wave.
+template <int NF, class Op>
+__device__ __forceinline__ Pack<NF> wave_suffix_incl(const Pack<NF>& x, Op op) {
+  Pack<NF> inc = row_suffix_incl<16>(x, op);
+  const int row = (threadIdx.x & 63) >> 4;
+  const Pack<NF> t1 = lane_pack(inc, 16), t2 = lane_pack(inc, 32), t3 = lane_pack(inc, 48);
+  const Pack<NF> t23 = op(t2, t3);
+  const Pack<NF> t123 = op(t1, t23);
+  const Pack<NF> post = pick(row == 0, t123, pick(row == 1, t23, t3));
+  if (row < 3) inc = op(inc, post);
+  return inc;
+}
+// Combined wave totals, read by every lane from `lds` (NW packs of NF,
+// starting at lds + off, stride S): exclusive prefix for this wave and the
+// total.  NW <= 16.
+template <int NW, int NF, class Op>
+__device__ __forceinline__ void waves_prefix(const double* lds, int off, int S, const Pack<NF>& ident, Op op,
+                                             Pack<NF>& pre, Pack<NF>& total) {
+  const int lane = threadIdx.x & 63;
+  Pack<NF> a = ident;
+  if (lane < NW) {
 #pragma unroll
-  for (int i = 0; i < NF; ++i) r.v[i] = __shfl_down(p.v[i], d, 64);
-  return r;
+    for (int i = 0; i < NF; ++i) a.v[i] = lds[lane * S + off + i];
+  }
+  a = row_prefix_incl<NW>(a, op);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  pre = wv > 0 ? lane_pack(a, wv - 1) : ident;
+  total = lane_pack(a, NW - 1);
+}
+template <int NW, int NF, class Op>
+__device__ __forceinline__ void waves_suffix(const double* lds, int off, int S, const Pack<NF>& ident, Op op,
+                                             Pack<NF>& suf, Pack<NF>& total) {
+  const int lane = threadIdx.x & 63;
+  Pack<NF> a = ident;
+  if (lane < NW) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) a.v[i] = lds[lane * S + off + i];
+  }
+  a = row_suffix_incl<NW>(a, op);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  suf = wv < NW - 1 ? lane_pack(a, wv + 1) : ident;
+  total = lane_pack(a, 0);
 }
 
 // Exclusive prefix over the workgroup in thread order.  op(earlier, later)
@@ -145,30 +251,17 @@ __device__ __forceinline__ Pack<NF> block_prefix(const Pack<NF>& x, const Pack<N
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  Pack<NF> inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    Pack<NF> o = shfl_up_pack(inc, d);
-    if (lane >= d) inc = op(o, inc);
-  }
-  Pack<NF> ex = shfl_up_pack(inc, 1);
-  if (lane == 0) ex = ident;
+  const Pack<NF> inc = wave_prefix_incl(x, op);
+  const Pack<NF> sh = dpp_pack<0x138>(inc);       // outside any condition: every lane active
+  const Pack<NF> ex = pick(lane == 0, ident, sh);
   if (lane == 63) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) lds[wv * NF + i] = inc.v[i];
   }
   __syncthreads();
-  Pack<NF> pre = ident, tot;
-  #pragma unroll 1
-  for (int w = 0; w < NW; ++w) {
-    Pack<NF> s;
-#pragma unroll
-    for (int i = 0; i < NF; ++i) s.v[i] = lds[w * NF + i];
-    if (w < wv) pre = op(pre, s);
-    tot = (w == 0) ? s : op(tot, s);
-  }
+  Pack<NF> pre;
+  waves_prefix<NW, NF>(lds, 0, NF, ident, op, pre, total);
   if (TAIL) __syncthreads();
-  total = tot;
   return op(pre, ex);
 }
 
@@ -180,30 +273,17 @@ __device__ __forceinline__ Pack<NF> block_suffix(const Pack<NF>& x, const Pack<N
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  Pack<NF> inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    Pack<NF> o = shfl_down_pack(inc, d);
-    if (lane + d < 64) inc = op(inc, o);
-  }
-  Pack<NF> ex = shfl_down_pack(inc, 1);
-  if (lane == 63) ex = ident;
+  const Pack<NF> inc = wave_suffix_incl(x, op);
+  const Pack<NF> sh = dpp_pack<0x130>(inc);
+  const Pack<NF> ex = pick(lane == 63, ident, sh);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) lds[wv * NF + i] = inc.v[i];
   }
   __syncthreads();
-  Pack<NF> suf = ident, tot;
-  #pragma unroll 1
-  for (int w = NW - 1; w >= 0; --w) {
-    Pack<NF> s;
-#pragma unroll
-    for (int i = 0; i < NF; ++i) s.v[i] = lds[w * NF + i];
-    if (w > wv) suf = op(s, suf);
-    tot = (w == NW - 1) ? s : op(s, tot);
-  }
+  Pack<NF> suf;
+  waves_suffix<NW, NF>(lds, 0, NF, ident, op, suf, total);
   __syncthreads();
-  total = tot;
   return op(ex, suf);
 }
 
@@ -219,19 +299,12 @@ __device__ __forceinline__ void block_prefix_suffix(const Pack<NP>& xp, const Pa
   constexpr int NF = NP + NS;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  Pack<NP> ip = xp;
-  Pack<NS> is = xs;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    Pack<NP> o = shfl_up_pack(ip, d);
-    Pack<NS> q = shfl_down_pack(is, d);
-    if (lane >= d) ip = opP(o, ip);
-    if (lane + d < 64) is = opS(is, q);
-  }
-  Pack<NP> ep = shfl_up_pack(ip, 1);
-  Pack<NS> es = shfl_down_pack(is, 1);
-  if (lane == 0) ep = idP;
-  if (lane == 63) es = idS;
+  const Pack<NP> ip = wave_prefix_incl(xp, opP);
+  const Pack<NS> is = wave_suffix_incl(xs, opS);
+  const Pack<NP> shp = dpp_pack<0x138>(ip);
+  const Pack<NS> shs = dpp_pack<0x130>(is);
+  const Pack<NP> ep = pick(lane == 0, idP, shp);
+  const Pack<NS> es = pick(lane == 63, idS, shs);
   if (lane == 63) {
 #pragma unroll
     for (int i = 0; i < NP; ++i) lds[wv * NF + i] = ip.v[i];
@@ -241,29 +314,13 @@ __device__ __forceinline__ void block_prefix_suffix(const Pack<NP>& xp, const Pa
     for (int i = 0; i < NS; ++i) lds[wv * NF + NP + i] = is.v[i];
   }
   __syncthreads();
-  Pack<NP> pre = idP, tp;
-  Pack<NS> suf = idS, ts;
-  #pragma unroll 1
-  for (int w = 0; w < NW; ++w) {
-    Pack<NP> a;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) a.v[i] = lds[w * NF + i];
-    if (w < wv) pre = opP(pre, a);
-    tp = (w == 0) ? a : opP(tp, a);
-  }
-  #pragma unroll 1
-  for (int w = NW - 1; w >= 0; --w) {
-    Pack<NS> a;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) a.v[i] = lds[w * NF + NP + i];
-    if (w > wv) suf = opS(a, suf);
-    ts = (w == NW - 1) ? a : opS(a, ts);
-  }
+  Pack<NP> pre;
+  Pack<NS> suf;
+  waves_prefix<NW, NP>(lds, 0, NF, idP, opP, pre, totP);
+  waves_suffix<NW, NS>(lds, NP, NF, idS, opS, suf, totS);
   if (TAIL) __syncthreads();
   exP = opP(pre, ep);
-  totP = tp;
   exS = opS(es, suf);
-  totS = ts;
 }
 
 // sums of packs (commutative), used with the scans above
