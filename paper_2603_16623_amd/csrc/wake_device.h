@@ -49,6 +49,27 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
   return fast_two_sum(s.hi, s.lo);
 }
 
+// Sum with one two_sum of the high parts and the low parts added in
+// double: the error stays within a few units of 2^-104 (|a| + |b|), which
+// is all the field sums need (they end rounded to double).
+__device__ __forceinline__ dd dd_add_fast(dd a, dd b) {
+  _Pragma("clang fp contract(off)")
+  dd s = two_sum(a.hi, b.hi);
+  s.lo += a.lo + b.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (e = 1 - x r, r += r e): within about an ulp of the rounded quotient,
+// without the IEEE division sequence.  x = 0 or +-inf give NaN.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 __device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
 __device__ __forceinline__ dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
 

@@ -59,7 +59,7 @@ struct Local {
 __device__ __forceinline__ Local local_of(double irho, double u, double w, double psi, double a2) {
   Local L;
   L.pb = 1.0 + psi;
-  L.ipb = 1.0 / L.pb;
+  L.ipb = rcp_nr(L.pb);
   L.gm = (1.0 + u * u + L.pb * L.pb + 0.5 * a2) * (0.5 * L.ipb);
   L.v = w * u * irho * L.ipb;
   L.A = w * irho * L.ipb;
@@ -263,7 +263,7 @@ __device__ __forceinline__ void ion_fields(const IonView& V, double r, dd lnr, i
     for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = R[j * WAKE_ION_REC + i];
   }
   h = j;
-  const double t = (r - q[IR_LO]) / (q[IR_HI] - q[IR_LO]);
+  const double t = (r - q[IR_LO]) * rcp_nr(q[IR_HI] - q[IR_LO]);
   ps = dd_add_d({q[IR_PSH], q[IR_PSL]}, t * q[IR_DPS]);
   dp = dd_add_d({q[IR_DPH], q[IR_DPL]}, t * q[IR_DDP]);
 }
@@ -981,8 +981,8 @@ struct BwdMatSumOp {  // (index-order product of inverse transfers, running sum)
 };
 struct SliceHeadOp {  // (w, w ln rho) as double-doubles, then two flag counts
   __device__ __forceinline__ Pack<6> operator()(const Pack<6>& a, const Pack<6>& b) const {
-    const dd x = dd_add({a.v[0], a.v[1]}, {b.v[0], b.v[1]});
-    const dd y = dd_add({a.v[2], a.v[3]}, {b.v[2], b.v[3]});
+    const dd x = dd_add_fast({a.v[0], a.v[1]}, {b.v[0], b.v[1]});
+    const dd y = dd_add_fast({a.v[2], a.v[3]}, {b.v[2], b.v[3]});
     return {{x.hi, x.lo, y.hi, y.lo, a.v[4] + b.v[4], a.v[5] + b.v[5]}};
   }
 };
@@ -1061,7 +1061,7 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
     const double w = K.ldh(RC_W, (unsigned)st_hs(SC, s), 0);
     const D2 l = SC.ld(RS_LN, s);
     sw = dd_add_d(sw, w);
-    swl = dd_add(swl, dd_mul_d(dd{l.x, l.y}, w));
+    swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
   }
 }
 
@@ -1161,7 +1161,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const double w = KC.ldh(RC_W, (unsigned)st_hs(SB, s), 0);
       const D2 l = SB.ld(RS_LN, s);
       sw = dd_add_d(sw, w);
-      swl = dd_add(swl, dd_mul_d(dd{l.x, l.y}, w));
+      swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
     }
   }
   int n = I.first;
@@ -1261,14 +1261,14 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
         ion_load(IV, hh_hint(x_hh), x_q);
       }
-      const double irho = 1.0 / rho;
-      const dd PTi = dd_add(PT, dd_mul_d(lnr, w));
-      const dd pe = dd_sub(dd_mul(dd_add_d(S, w), lnr), PTi);    // psi_e - sum w ln rho
+      const double irho = rcp_nr(rho);
+      const dd PTi = dd_add_fast(PT, dd_mul_d(lnr, w));
+      const dd pe = dd_add_fast(dd_mul(dd_add_d(S, w), lnr), dd_neg(PTi));    // psi_e - sum w ln rho
       const dd de = dd_div_rcp(dd_add_d(S, wh), rho, irho);         // d_rho psi_e (self w^)
       dd ips, idp;
       ion_fields(IV, rho, lnr, h, q, ips, idp);
-      const double psi = dd_round(dd_add(pe, ips)) + psi_axis;
-      const double dpsi = dd_round(dd_add(de, idp));
+      const double psi = dd_round(dd_add_fast(pe, ips)) + psi_axis;
+      const double dpsi = dd_round(dd_add_fast(de, idp));
       S = dd_add_d(S, w);
       PT = PTi;
       // beam charge inside rho (strictly below), analytic beams, lasers
@@ -1394,7 +1394,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         c_w = KC.ld(RC_W, kc); c_r = KC.ld(RC_R0, kc); c_l = KC.ld(RC_LN, kc);
       }
       const double a2 = has_laser ? A2[sl] : 0.0, da2 = has_laser ? DA2[sl] : 0.0;
-      const double irho = 1.0 / rho;
+      const double irho = rcp_nr(rho);
       const Local L = local_of(irho, u, w, psi, a2);
       const double dz = -(Vgt + (w - wh) * u * irho * L.ipb);
       double B, Cc;
@@ -1409,7 +1409,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       ga = nga; gb = ngb; ha = nha; hb = nhb;
       const double a = (ha * E - ga * D) * iW;
       const double b = (hb * E - gb * D) * iW;
-      const double bp = a * rho + b * irho + (wh / w) * Cc;
+      const double bp = a * rho + b * irho + wh * rcp_nr(w) * Cc;
       const double bt = bb + bp;
       const double ez = -dz;
       if (!(isfinite(psi) && isfinite(dpsi) && isfinite(ez) && isfinite(bt))) bad = 1.0;
@@ -1441,7 +1441,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         Sn.st(RS_F, sl, d2(sr, su));
         Sn.st(RS_LN, sl, d2(lr.hi, lr.lo));
         sw2 = dd_add_d(sw2, w);
-        swl2 = dd_add(swl2, dd_mul_d(lr, w));
+        swl2 = dd_add_fast(swl2, dd_mul_d(lr, w));
         if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
         if (!key_lt(rn, id, nxt_r, nxt_i)) dis_l = 1.0;
         if (k == cnt - 1) { last_r = rn; last_i = id; }
