@@ -4,8 +4,8 @@
 #include <stdint.h>
 
 #define WAKE_MAX_ANALYTIC 8   // analytic beams + lasers per instance
-#define WAKE_BCAP 2048        // beam-table entries staged in LDS per slice
-#define WAKE_SORTCAP 2048     // rings of long disordered runs sorted in LDS in one piece
+#define WAKE_BCAP 1024        // beam-table entries staged in LDS per slice
+#define WAKE_SORTCAP 1024     // rings of long disordered runs sorted in LDS in one piece
 #define WAKE_SEGMAX 64        // disordered runs up to this length are ranked in place
 #define WAKE_ION_REC 8        // doubles per ion interval record
 

@@ -271,6 +271,43 @@ __device__ __forceinline__ void ion_fields(const IonView& V, double r, dd lnr, i
 // Number of entries of the ascending table br[0..m) below r, given that
 // the first lo entries are below r: galloping from lo (gallop) or a plain
 // binary search of [lo, m).
+// Ion interval of radius r from the interval nodes kept in LDS as floats
+// (node j = lower end of record j, j = 0..N): the largest j with
+// node_j <= r in float, by a gallop from the guess j then bisection.  The
+// record's exact double bounds confirm it when it is used (a radius within
+// a float ulp of a node can land one interval off; the exact search in
+// ion_fields then corrects it).
+__device__ __forceinline__ int ion_find(const float* nodes, int N, double r, int j) {
+  const float x = (float)r;
+  j = j < 0 ? 0 : (j > N ? N : j);
+  int a, b;
+  if (nodes[j] <= x) {
+    a = j;                                   // nodes[a] <= x
+    int step = 1;
+    for (;;) {
+      b = a + step;
+      if (b > N) { b = N + 1; break; }
+      if (x < nodes[b]) break;
+      a = b;
+      step <<= 1;
+    }
+  } else {
+    b = j;                                   // nodes[b] > x
+    int step = 1;
+    for (;;) {
+      a = b - step;
+      if (a <= 0) { a = 0; break; }
+      if (nodes[a] <= x) break;
+      b = a;
+      step <<= 1;
+    }
+  }
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if (nodes[m] <= x) a = m; else b = m;
+  }
+  return a;
+}
 __device__ __forceinline__ int count_below(const double* br, int lo, int m, double r, bool gallop) {
   int a, b;
   if (gallop) {
@@ -991,7 +1028,7 @@ template <int NT>
 struct MarchLds {
   static constexpr int NW = NT / 64;
   // rings per thread up to which the keys of every position live in LDS
-  static constexpr int CMAX = NT >= 1024 ? 8 : 16;
+  static constexpr int CMAX = NT >= 1024 ? 7 : 16;
   static constexpr int KCAP = NT * CMAX;
   static constexpr size_t region_bytes() {
     const size_t beam = 2 * WAKE_BCAP * sizeof(double);
@@ -1008,8 +1045,14 @@ struct MarchLds {
     return (size_t)KCAP * (sizeof(double) + 2 * sizeof(uint16_t)) +
            (size_t)WAKE_SORTCAP * sizeof(uint16_t);
   }
-  static constexpr size_t bytes() { return head_bytes() + key_bytes() + region_bytes(); }
+  // ion interval nodes as floats (instances with keys in LDS: N <= KCAP)
+  static constexpr size_t ion_bytes() { return ((size_t)(KCAP + 1) * sizeof(float) + 15) & ~(size_t)15; }
+  static constexpr size_t bytes() { return head_bytes() + key_bytes() + region_bytes() + ion_bytes(); }
 };
+// one workgroup's LDS must fit the 160 KiB of a compute unit
+static_assert(MarchLds<256>::bytes() <= 160 * 1024, "LDS layout too large");
+static_assert(MarchLds<512>::bytes() <= 160 * 1024, "LDS layout too large");
+static_assert(MarchLds<1024>::bytes() <= 160 * 1024, "LDS layout too large");
 
 // This slice's analytic source factors (beams: lam += c0 (1 - exp(-rho^2 c1));
 // lasers: |a|^2 = c0 exp(-rho^2 c1)) and beam-table entries into LDS.
@@ -1088,6 +1131,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   unsigned char* region = smem + MarchLds<NT>::head_bytes() + MarchLds<NT>::key_bytes();
   double* s_br = reinterpret_cast<double*>(region);        // beam radii
   double* s_bc = s_br + WAKE_BCAP;                         // beam cumulative charge
+  float* s_ion = reinterpret_cast<float*>(region + MarchLds<NT>::region_bytes());   // ion nodes
   // keys and ring order in LDS (else the order is fixed in global memory)
   const bool lds_keys = C <= CMAX;
   const unsigned smax = (unsigned)(C * NT - 1);    // last slot
@@ -1134,6 +1178,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   const GA<double> A2 = uview(I.a2), DA2 = uview(I.da2);
   const int n_an = I.n_an;
   const bool has_laser = I.has_laser != 0;
+  // ion interval nodes in LDS (float) for the interval search of pass B;
+  // read there after the slice-head scan's barriers
+  if (lds_keys)
+    for (int j = tid; j <= N; j += NT) s_ion[j] = (float)IV.R[j * WAKE_ION_REC + IR_LO];
 
   // ln rho of every ring and the per-thread sums of (w, w ln rho)
   #pragma unroll 1
@@ -1236,16 +1284,20 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
       z_hh = Sc.ldh(RS_HH, s, 0);
     }
+    // ion interval of the next ring: searched in LDS from the interval of
+    // the ring before it (sorted order), its record requested one ring ahead
+    int jn = 0;
     if (cnt > 0) {
       x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
-      ion_load(IV, hh_hint(x_hh), x_q);
+      jn = lds_keys ? ion_find(s_ion, N, x_ru.x, hh_hint(x_hh)) : hh_hint(x_hh);
+      ion_load(IV, jn, x_q);
     }
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
       const double rho = x_ru.x, u = x_ru.y;
       const int32_t hs = hh_hs(x_hh);
-      int h = hh_hint(x_hh);
+      int h = jn;
       const dd lnr = {x_ln.x, x_ln.y};
       const double w = x_wc.x, wh = x_wc.y;
       double q[WAKE_ION_REC];
@@ -1259,7 +1311,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       }
       if (k + 1 < cnt) {
         x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
-        ion_load(IV, hh_hint(x_hh), x_q);
+        jn = lds_keys ? ion_find(s_ion, N, x_ru.x, h) : hh_hint(x_hh);
+        ion_load(IV, jn, x_q);
       }
       const double irho = rcp_nr(rho);
       const dd PTi = dd_add_fast(PT, dd_mul_d(lnr, w));
