@@ -386,7 +386,7 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
       st[RS_RU * PS + sl] = d2(r, 0.0);
       st[RS_F * PS + sl] = d2(0.0, 0.0);
       st[RS_LN * PS + sl] = d2(0.0, 0.0);
-      st[RS_HH * PS + sl] = d2(hh_pack((int32_t)sl, j + 1), 0.0);
+      st[RS_HH * PS + sl] = d2(hh_pack((int32_t)sl, j + 1), w);
     }
     cS = dd_add(cS, {tot.v[0], tot.v[1]});
     cPT = dd_add(cPT, {tot.v[2], tot.v[3]});
@@ -1057,8 +1057,7 @@ static_assert(MarchLds<1024>::bytes() <= 160 * 1024, "LDS layout too large");
 // This slice's analytic source factors (beams: lam += c0 (1 - exp(-rho^2 c1));
 // lasers: |a|^2 = c0 exp(-rho^2 c1)) and beam-table entries into LDS.
 template <int NT>
-__device__ __forceinline__ void stage_slice(const WakeInst& I, int n, double* s_misc, double* s_br,
-                                            double* s_bc) {
+__device__ __forceinline__ void stage_analytic(const WakeInst& I, int n, double* s_misc) {
   const int tid = threadIdx.x;
   const double xi = n * I.dxi;
   if (tid < I.n_an) {
@@ -1078,11 +1077,51 @@ __device__ __forceinline__ void stage_slice(const WakeInst& I, int n, double* s_
       s_misc[3 * tid + 2] = 2.0 / (A.w0 * A.w0);
     }
   }
+}
+template <int NT>
+__device__ __forceinline__ void stage_slice(const WakeInst& I, int n, double* s_misc, double* s_br,
+                                            double* s_bc) {
+  const int tid = threadIdx.x;
+  stage_analytic<NT>(I, n, s_misc);
   if (I.nb) {
     const int bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
     const int bm = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
     if (bm <= WAKE_BCAP)
       for (int i = tid; i < bm; i += NT) { s_br[i] = I.br[bt0 + i]; s_bc[i] = I.bcum[bt0 + i]; }
+  }
+}
+
+// The beam-table entries of a slice that one thread stages in LDS, fetched
+// into registers ahead of the store (the fetch for slice n+1 is issued when
+// pass E of slice n starts, the store follows the pass).
+template <int NT>
+struct BeamStage {
+  static constexpr int BPT = (WAKE_BCAP + NT - 1) / NT;
+  double r[BPT], c[BPT];
+  int m;                 // entries of the slice; more than WAKE_BCAP: read from global memory
+};
+template <int NT>
+__device__ __forceinline__ void beam_fetch(const WakeInst& I, int n, BeamStage<NT>& b) {
+  b.m = 0;
+  if (!I.nb) return;
+  const int bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
+  b.m = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
+  if (b.m > WAKE_BCAP) return;
+#pragma unroll
+  for (int q = 0; q < BeamStage<NT>::BPT; ++q) {
+    const int i = threadIdx.x + q * NT;
+    b.r[q] = 0.0;
+    b.c[q] = 0.0;
+    if (i < b.m) { b.r[q] = I.br[bt0 + i]; b.c[q] = I.bcum[bt0 + i]; }
+  }
+}
+template <int NT>
+__device__ __forceinline__ void beam_store(const BeamStage<NT>& b, double* s_br, double* s_bc) {
+  if (b.m > WAKE_BCAP) return;
+#pragma unroll
+  for (int q = 0; q < BeamStage<NT>::BPT; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < b.m) { s_br[i] = b.r[q]; s_bc[i] = b.c[q]; }
   }
 }
 
@@ -1094,14 +1133,14 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
   const int tid = threadIdx.x;
   const unsigned smax = (unsigned)(I.C * NT - 1);
   const uint32_t ps = (uint32_t)(I.C * NT);
-  const PV SC = pview(I.st[cur], ps), K = pview(I.cst, ps);
+  const PV SC = pview(I.st[cur], ps);
   sw = {0.0, 0.0};
   swl = {0.0, 0.0};
   #pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
     const unsigned s = ident ? sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[sl], smax);
-    const double w = K.ldh(RC_W, (unsigned)st_hs(SC, s), 0);
+    const double w = SC.ldh(RS_HH, s, 1);
     const D2 l = SC.ld(RS_LN, s);
     sw = dd_add_d(sw, w);
     swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
@@ -1206,7 +1245,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const unsigned sl = k * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
-      const double w = KC.ldh(RC_W, (unsigned)st_hs(SB, s), 0);
+      const double w = SB.ldh(RS_HH, s, 1);
       const D2 l = SB.ld(RS_LN, s);
       sw = dd_add_d(sw, w);
       swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
@@ -1230,9 +1269,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     }
     if (n == end) break;
     if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
+      bool restage = true;    // the general fix-ups use the beam-table area of LDS
       if (lds_keys) {
-        if (!fix_order_blocks<NT>(I, s_kr, s_ki, s_perm))
-          fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
+        restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm);
+        if (restage) fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
       } else {
         fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
       }
@@ -1242,7 +1282,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       for (int k = 0; k < cnt; ++k)
         changed |= ((lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[k * NT + tid]) & (NT - 1)) != tid;
       if (changed) chunk_sums<NT>(I, cur, cnt, ident, lds_keys, s_perm, sw, swl);
-      stage_slice<NT>(I, n, s_misc, s_br, s_bc);
+      if (restage) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
       dis = 0.0;
       continue;
     }
@@ -1363,7 +1403,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       SCR.sth(SC_BB, sl, 0, bb);
       if (has_laser) { A2.st(sl, aa); DA2.st(sl, dda); }
       // the ring's home slot and hint move to its position slot in the next buffer
-      Sn.sth(RS_HH, sl, 0, hh_pack(hs, h));
+      Sn.st(RS_HH, sl, d2(hh_pack(hs, h), w));
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1390,6 +1430,11 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         s_scanA, ep, et, dsf, dt);
 
     // ---- pass E: B^(p), outputs, push ----
+    // the next slice's beam-table entries, fetched now and stored after the pass
+    const bool stage_next = do_push && n + 1 < end;
+    BeamStage<NT> nbs;
+    nbs.m = 0;
+    if (stage_next) beam_fetch<NT>(I, n + 1, nbs);
     double ga = G.v[0] * gsa + G.v[1] * gsb;      // g at the chunk end
     double gb = G.v[2] * gsa + G.v[3] * gsb;
     double ha = hea, hb = heb;
@@ -1508,7 +1553,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     // empty) against the previous chunk's last one
     s_fr[tid] = nxt_r;
     s_fi[tid] = nxt_i;
-    if (do_push && n + 1 < end) stage_slice<NT>(I, n + 1, s_misc, s_br, s_bc);
+    if (stage_next) {
+      stage_analytic<NT>(I, n + 1, s_misc);
+      beam_store<NT>(nbs, s_br, s_bc);
+    }
     // out of time: this slice is the launch's last (one clock read, broadcast)
     if (tid == 0)
       s_misc[63] = budget > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget ? 1.0 : 0.0;
@@ -1586,7 +1634,7 @@ __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u,
   r[RS_RU * PS] = d2(rho[i], u[i]);
   r[RS_F * PS] = d2(fr ? fr[i] : 0.0, fu ? fu[i] : 0.0);
   r[RS_LN * PS] = d2(0.0, 0.0);
-  r[RS_HH * PS] = d2(hh_pack((int32_t)sl, i + 1), 0.0);
+  r[RS_HH * PS] = d2(hh_pack((int32_t)sl, i + 1), reinterpret_cast<const D2*>(I.cst)[RC_W * PS + sl].x);
 }
 
 // Back to the state at slice 0 (rings at rest at their initial radii);
@@ -1600,7 +1648,7 @@ __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_ins
     r[RS_RU * PS] = d2(reinterpret_cast<const D2*>(I.cst)[RC_R0 * PS + sl].x, 0.0);
     r[RS_F * PS] = d2(0.0, 0.0);
     r[RS_LN * PS] = d2(0.0, 0.0);
-    r[RS_HH * PS] = d2(hh_pack((int32_t)sl, j + 1), 0.0);
+    r[RS_HH * PS] = d2(hh_pack((int32_t)sl, j + 1), reinterpret_cast<const D2*>(I.cst)[RC_W * PS + sl].x);
   }
   if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; }
 }
