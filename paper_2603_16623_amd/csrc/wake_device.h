@@ -105,6 +105,41 @@ __device__ __forceinline__ dd dd_mul(dd a, dd b) {
   return fast_two_sum(p.hi, p.lo);
 }
 
+// ln(1 + d) for d > -1 in a few dozen operations, to a few ulp:
+// 1 + d = m + c exactly (two_sum), m = 2^k f with f in [sqrt(1/2), sqrt(2)),
+// ln f = 2 atanh(s) with s = (f - 1) / (f + 1) (|s| < 0.172) summed by its
+// Taylor series through s^25 (the next term is below 2^-64 of the sum), and
+// ln(1 + d) = k ln 2 + ln f + c / m.  m <= 0 gives NaN.
+__device__ __forceinline__ double log1p_fast(double d) {
+  _Pragma("clang fp contract(off)")
+  const dd mc = two_sum(1.0, d);
+  const double m = mc.hi;
+  int k = __builtin_amdgcn_frexp_exp(m);
+  double f = __builtin_amdgcn_frexp_mant(m);            // [0.5, 1)
+  if (f < 0.70710678118654752440) { f = f + f; k -= 1; }
+  const double s = (f - 1.0) * rcp_nr(f + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 25.0;
+  p = __builtin_fma(p, z, 1.0 / 23.0);
+  p = __builtin_fma(p, z, 1.0 / 21.0);
+  p = __builtin_fma(p, z, 1.0 / 19.0);
+  p = __builtin_fma(p, z, 1.0 / 17.0);
+  p = __builtin_fma(p, z, 1.0 / 15.0);
+  p = __builtin_fma(p, z, 1.0 / 13.0);
+  p = __builtin_fma(p, z, 1.0 / 11.0);
+  p = __builtin_fma(p, z, 1.0 / 9.0);
+  p = __builtin_fma(p, z, 1.0 / 7.0);
+  p = __builtin_fma(p, z, 1.0 / 5.0);
+  p = __builtin_fma(p, z, 1.0 / 3.0);
+  const double two_s = s + s;
+  const double lf = __builtin_fma(two_s * z, p, two_s);     // 2 s (1 + z p)
+  const double LN2_HI = 6.93147180559945286227e-01, LN2_LO = 2.31904681384629955842e-17;
+  const double kd = (double)k;
+  const double tail = __builtin_fma(kd, LN2_LO, lf + mc.lo * rcp_nr(m));
+  const double r = __builtin_fma(kd, LN2_HI, tail);
+  return m > 0.0 ? r : __builtin_nan("");
+}
+
 // exp(x) to double-double accuracy (|x| < 700): x = k ln2 + t with
 // |t| <= ln2/2, Taylor series of e^t in double-double, scaled by 2^k.
 __device__ inline dd dd_exp(double x) {

@@ -185,7 +185,7 @@ __device__ __forceinline__ int32_t st_hs(const PV& S, unsigned sl) { return hh_h
 // rounding scales with the ring's displacement, not with |ln rho| (the psi
 // sums multiply ln rho by the enclosed charge).  r: (r0, 1/r0), l: ln r0.
 __device__ __forceinline__ dd ring_log(D2 r, D2 l, double rho) {
-  const double l1 = log1p((rho - r.x) * r.y);
+  const double l1 = log1p_fast((rho - r.x) * r.y);
   return dd_add_d({l.x, l.y}, l1);
 }
 
@@ -1534,7 +1534,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         double sr = f_r, su = f_u;
         if (rn < 0.0) { rn = -rn; un = -un; sr = -sr; su = -su; }
         if (!(isfinite(rn) && isfinite(un))) bad = 1.0;
-        const dd lr = dd_add_d({k_lh, k_ll}, log1p((rn - k_r0) * k_ir0));   // as ring_log
+        const dd lr = dd_add_d({k_lh, k_ll}, log1p_fast((rn - k_r0) * k_ir0));   // as ring_log
         Sn.st(RS_RU, sl, d2(rn, un));
         Sn.st(RS_F, sl, d2(sr, su));
         Sn.st(RS_LN, sl, d2(lr.hi, lr.lo));
