@@ -96,7 +96,7 @@ struct WakeInst {
 // The home slot and hint share one double's bits (home slot in the low word).
 enum { RS_RU = 0, RS_F, RS_LN, RS_HH, RS_CHUNKS };      // (rho, u_r) (f_rho, f_u) (ln rho) (hs|hint, w)
 enum { RC_W = 0, RC_R0, RC_LN, RC_CHUNKS };             // (w, w^) (r0, 1/r0) (ln r0)
-enum { SC_PSI = 0, SC_BB, SC_CHUNKS };                  // (psi, d_rho psi) (B^(b), -)
+enum { SC_PSI = 0, SC_BB, SC_CHUNKS };                  // (psi, d_rho psi) (B^(b), home slot bits)
 
 // Quantities of a snapshot, in this order: psi, E_r - B_theta, E_z,
 // B_theta, rho, u_r.

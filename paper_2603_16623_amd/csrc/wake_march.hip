@@ -1400,7 +1400,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       l1a += G.v[0] * s1b - G.v[2] * s1a;
       l1b += G.v[1] * s1b - G.v[3] * s1a;
       SCR.st(SC_PSI, sl, d2(psi, dpsi));
-      SCR.sth(SC_BB, sl, 0, bb);
+      SCR.st(SC_BB, sl, d2(bb, hh_pack(hs, 0)));      // pass E takes the home slot from here
       if (has_laser) { A2.st(sl, aa); DA2.st(sl, dda); }
       // the ring's home slot and hint move to its position slot in the next buffer
       Sn.st(RS_HH, sl, d2(hh_pack(hs, h), w));
@@ -1458,15 +1458,19 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const unsigned sl = (cnt - 1) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       y_ru = Sc.ld(RS_RU, s); y_f = Sc.ld(RS_F, s);
-      y_hs = hh_hs(Sn.ldh(RS_HH, sl, 0));
-      y_ps = SCR.ld(SC_PSI, sl); y_bb = SCR.ldh(SC_BB, sl, 0);
+      y_ps = SCR.ld(SC_PSI, sl);
+      const D2 b = SCR.ld(SC_BB, sl);
+      y_bb = b.x;
+      y_hs = hh_hs(b.y);
     }
     if (cnt > 1) {
       const unsigned sl = (cnt - 2) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
-      v_hs = hh_hs(Sn.ldh(RS_HH, sl, 0));
-      v_ps = SCR.ld(SC_PSI, sl); v_bb = SCR.ldh(SC_BB, sl, 0);
+      v_ps = SCR.ld(SC_PSI, sl);
+      const D2 b = SCR.ld(SC_BB, sl);
+      v_bb = b.x;
+      v_hs = hh_hs(b.y);
     }
     if (cnt > 0) {
       const unsigned kc = (unsigned)y_hs;
@@ -1484,8 +1488,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const unsigned sp = sl - 2 * NT;
         const unsigned s = WAKE_SLOT(sp);
         v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
-        v_hs = hh_hs(Sn.ldh(RS_HH, sp, 0));
-        v_ps = SCR.ld(SC_PSI, sp); v_bb = SCR.ldh(SC_BB, sp, 0);
+        v_ps = SCR.ld(SC_PSI, sp);
+        const D2 b = SCR.ld(SC_BB, sp);
+        v_bb = b.x;
+        v_hs = hh_hs(b.y);
       }
       if (k > 0) {
         const unsigned kc = (unsigned)y_hs;
