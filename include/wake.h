@@ -178,6 +178,27 @@ int wake_get_tiling(int32_t *threads, int32_t *wgs_per_cu);
 int wake_tiling_occupancy(int32_t threads, int32_t wgs_per_cu);
 
 /* ---------------------------------------------------------------------
+ * Cooperative instances (the large-ring-count path).  A context with more
+ * rings than one workgroup can keep ordered in LDS (more than 16 * threads
+ * at 256 or 512 threads, 7 * 1024 at 1024) is marched by G workgroups
+ * together, member g owning the sorted positions [g P, g P + P), P = C *
+ * threads, with C = max(rings_per_thread, ceil(n_rings / (64 threads)))
+ * and G = ceil(n_rings / P) <= 64.  Per slice the members exchange their
+ * scan totals through device memory (three all-gathers) and fix the ring
+ * order on keys in device memory; the order is the same and the fields
+ * agree with a single workgroup's to rounding.  The members of one instance
+ * must be resident together: launches always place at least G workgroups.
+ * wake_set_cluster(rings_per_thread, min_rings) applies to contexts
+ * created from now on: rings_per_thread 0 = 8; min_rings 0 = the LDS limit
+ * above, otherwise contexts of at least min_rings rings are cooperative
+ * (when that gives G >= 2).  A member that waits more than 2 s at a barrier
+ * stops the instance, which then reports WAKE_EDEVICE.
+ * --------------------------------------------------------------------- */
+int wake_set_cluster(int32_t rings_per_thread, int32_t min_rings);
+/* workgroups (G) and rings per thread (C) of a context */
+int wake_get_layout(wake_ctx *ctx, int32_t *workgroups, int32_t *rings_per_thread);
+
+/* ---------------------------------------------------------------------
  * Batched form: many independent contexts (same device) marched by one
  * persistent launch; workgroups take instances longest-first from a device
  * counter.  Per-instance results equal those of solving alone with the same

@@ -17,13 +17,38 @@ namespace {
 
 int g_nt = 512;      // workgroup threads of new contexts (slot layout)
 int g_wpc = 0;       // workgroups per compute unit of persistent launches (0: occupancy)
+int g_cl_rings = 0;  // rings per thread of cooperative instances (0: 8)
+int g_cl_min = 0;    // ring count from which instances are cooperative (0: beyond one workgroup's LDS keys)
 
+
+// Layout of an instance of N rings on nt-thread workgroups: one workgroup
+// with C = ceil(N / nt) rings per thread while the keys of every position
+// fit its LDS (and N is at most the cooperative threshold), else G members
+// of C rings per thread (G <= 64).
+void layout_of(int N, int nt, int* C, int* G) {
+  const int kcap = march_cmax(nt) * nt;
+  const int min_n = g_cl_min > 0 ? g_cl_min : kcap + 1;
+  if (N >= min_n && N > nt) {
+    int c = std::max(g_cl_rings > 0 ? g_cl_rings : 8, (N + 64 * nt - 1) / (64 * nt));
+    const int g = (N + c * nt - 1) / (c * nt);
+    if (g > 1) { *C = c; *G = g; return; }
+  }
+  *C = (N + nt - 1) / nt;
+  *G = 1;
+}
+
+static size_t pow2_at_least(size_t n) {
+  size_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
 
 // Bytes of the per-context arena (mirrors the carving in wake_create).
-// S = slots of the per-ring arrays (C * nt >= N).
+// S = slots of the per-ring arrays (G * C * nt >= N).
 size_t arena_bytes(int N, int n_xi, int stride, int nt) {
-  const size_t C = (size_t)(N + nt - 1) / nt;
-  const size_t S = C * nt;
+  int Ci = 0, Gi = 1;
+  layout_of(N, nt, &Ci, &Gi);
+  const size_t S = (size_t)Gi * Ci * nt;
   const size_t n_rec = stride > 0 ? (size_t)(n_xi + stride - 1) / stride : 0;
   size_t d = 0, i = 0;
   d += 2 * RC_CHUNKS * S;                   // constants by home slot
@@ -40,6 +65,11 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
   d += OUT_N * (size_t)N;                   // last
   i += CTL_NWORDS;                          // ctl
   d += 4 * (size_t)N;                       // staging
+  if (Gi > 1) {                             // cooperative: exchange, keys, fallback sort
+    const size_t P2 = pow2_at_least((size_t)N);
+    d += 2 * (size_t)Gi * 16 + S + P2;
+    i += 4 + S + 2 * P2;
+  }
   return d * 8 + i * 4 + 64 * 256;          // + alignment slack
 }
 
@@ -147,8 +177,8 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   I.Rp = plasma->r0[N - 1] + plasma->dr[N - 1] / 2.0;
   I.inv2pidxi = 1.0 / (2.0 * M_PI * I.dxi);
   I.nt = nt;
-  I.C = (N + nt - 1) / nt;
-  const size_t S = (size_t)I.C * I.nt;
+  layout_of(N, nt, &I.C, &I.G);
+  const size_t S = (size_t)I.G * I.C * I.nt;
   const size_t bytes = arena_bytes(N, I.n_xi, I.stride, I.nt);
   hipError_t e = hipMalloc(&c->arena.base, bytes);
   if (e != hipSuccess) { c->arena.base = nullptr; release(c); return dev_err(e); }
@@ -178,6 +208,16 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   I.last = A.take<double>((size_t)OUT_N * N);
   I.ctl = A.take<int32_t>(CTL_NWORDS);
   c->staging = A.take<double>(4 * (size_t)N);
+  if (I.G > 1) {
+    const size_t P2 = pow2_at_least((size_t)N);
+    I.xd = A.take<double>((size_t)2 * I.G * 16);
+    I.xc = A.take<int32_t>(4);
+    I.gk_r = A.take<double>(S);
+    I.gk_i = A.take<int32_t>(S);
+    I.bt_r = A.take<double>(P2);
+    I.bt_i = A.take<int32_t>(P2);
+    I.bt_s = A.take<int32_t>(P2);
+  }
   if (A.used > A.size) { release(c); return WAKE_ENOMEM; }
   e = hipMalloc(&c->d_inst, sizeof(WakeInst));
   if (e == hipSuccess) e = hipMalloc(&c->d_counter, 64);
@@ -334,15 +374,16 @@ static int read_ctl(wake_ctx* c, int32_t ctl[CTL_NWORDS]) {
   int r = drain(c);
   if (r != WAKE_OK) return r;
   HIP_TRY(hipMemcpy(ctl, c->I.ctl, sizeof(int32_t) * CTL_NWORDS, hipMemcpyDeviceToHost));
-  return WAKE_OK;
+  return ctl[CTL_FAULT] ? WAKE_EDEVICE : WAKE_OK;
 }
 
 static int launch_one(wake_ctx* c, int first, int count) {
   WakeInst& I = c->I;
   I.first = first;
   I.count = count;
+  I.task0 = 0;
   HIP_TRY(hipMemcpyAsync(c->d_inst, &I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_march(I.nt, c->d_inst, 1, c->d_counter, 1, c->stream));
+  HIP_TRY(launch_march(I.nt, c->d_inst, 1, I.G, c->d_counter, I.G, c->stream));
   return WAKE_OK;
 }
 
@@ -509,6 +550,20 @@ extern "C" int wake_set_tiling(int32_t nt, int32_t wpc) {
   return WAKE_OK;
 }
 
+extern "C" int wake_set_cluster(int32_t rings_per_thread, int32_t min_rings) {
+  if (rings_per_thread < 0 || rings_per_thread > 4096 || min_rings < 0) return WAKE_EINVAL;
+  g_cl_rings = rings_per_thread;
+  g_cl_min = min_rings;
+  return WAKE_OK;
+}
+
+extern "C" int wake_get_layout(wake_ctx* c, int32_t* workgroups, int32_t* rings_per_thread) {
+  if (!c) return WAKE_EINVAL;
+  if (workgroups) *workgroups = c->I.G;
+  if (rings_per_thread) *rings_per_thread = c->I.C;
+  return WAKE_OK;
+}
+
 extern "C" int wake_get_tiling(int32_t* nt, int32_t* wpc) {
   if (!nt || !wpc) return WAKE_EINVAL;
   *nt = g_nt;
@@ -601,20 +656,36 @@ static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vec
   std::stable_sort(v.begin(), v.end(), [](const WakeInst& a, const WakeInst& c) {
     return (int64_t)a.N * a.count > (int64_t)c.N * c.count;
   });
+  assign_tasks(v);
   return (int)v.size();
 }
 
 // one persistent launch per distinct workgroup size present in v (the
 // descriptors are already at d_insts; each launch takes the instances of its
 // size from the shared queue)
+int assign_tasks(std::vector<WakeInst>& v) {
+  int t = 0;
+  for (WakeInst& I : v) {
+    I.task0 = t;
+    t += I.G;
+  }
+  return t;
+}
+
+// (task0 already assigned; a cooperative instance's members need their G
+// workgroups resident together, so the grid never drops below the largest G)
 hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts, int32_t* d_counter,
                         int dev, int grid_override, hipStream_t s) {
+  int n_tasks = 0;
+  for (const WakeInst& I : v) n_tasks += I.G;
   for (int nt : kThreads) {
-    int n = 0;
-    for (const WakeInst& I : v) n += I.nt == nt;
+    int n = 0, gmax = 1;
+    for (const WakeInst& I : v)
+      if (I.nt == nt) { n += I.G; gmax = std::max(gmax, (int)I.G); }
     if (n == 0) continue;
-    const int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, dev);
-    hipError_t e = launch_march(nt, d_insts, (int)v.size(), d_counter, g, s);
+    int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, dev);
+    g = std::max(g, gmax);
+    hipError_t e = launch_march(nt, d_insts, (int)v.size(), n_tasks, d_counter, g, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -1,0 +1,336 @@
+// Cooperative instances (device side): G workgroups march one instance that
+// is too large for one workgroup's LDS.  Member g owns the sorted positions
+// [g*P, g*P + P) (P = C * NT).  Per slice the members meet three times
+// (slice head, transfer-matrix scan, source-sum scan) to exchange their scan
+// totals, and a few more times when the order needs fixing; the order
+// fix-up works on keys and permutation in device memory.
+//
+// Barrier.  Each member publishes a pack (agent-scope stores), releases
+// (agent-scope fence: the XCD's L2 writes back what this workgroup wrote),
+// counts itself in, waits until every member of this round has, acquires
+// (fence), and reads all packs.  Packs alternate between two buffers by
+// round; a member writes buffer b again only two rounds later, when every
+// member has finished reading it.  A wait that exceeds its time bound sets
+// the give-up word, and every member then leaves the instance (reported as
+// a device error), so no wave can wait forever.
+#pragma once
+#include "wake_common.h"
+#include "wake_device.h"
+
+#define WAKE_CL_WAIT_TICKS 200000000ll    // 2 s of the 100 MHz clock
+
+struct Cluster {
+  int g, G;      // this member, members
+  int round;     // barriers passed in this launch
+  double* xd;    // [2][G][16]
+  int32_t* xc;   // [0] arrivals, [1] give-up
+};
+
+// All-gather of NF doubles per member; member m's pack lands at s_x[m * NF].
+// Every thread of every member calls it at the same point of the march.
+// Returns false when a member gave up.
+template <int NF>
+__device__ __noinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, double* s_x, int* s_ok) {
+  static_assert(NF <= 16, "exchange packs hold 16 doubles");
+  const int buf = cl.round & 1;
+  __syncthreads();                                   // this member's writes of the round are issued
+  if (threadIdx.x == 0) {
+    double* slot = cl.xd + ((size_t)buf * cl.G + cl.g) * 16;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) __hip_atomic_store(slot + i, mine.v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    atomicAdd(cl.xc, 1);
+    const int target = cl.G * (cl.round + 1);
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    int ok = 0;
+    for (;;) {
+      if (__hip_atomic_load(cl.xc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (__hip_atomic_load(cl.xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) { ok = 1; break; }
+      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > WAKE_CL_WAIT_TICKS) {
+        __hip_atomic_store(cl.xc + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    *s_ok = ok;
+  }
+  __syncthreads();
+  const int ok = *s_ok;
+  if (ok)
+    for (int i = threadIdx.x; i < cl.G * NF; i += blockDim.x) {
+      const int m = i / NF, f = i - m * NF;
+      s_x[i] = __hip_atomic_load(cl.xd + ((size_t)buf * cl.G + m) * 16 + f, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    }
+  __syncthreads();
+  ++cl.round;
+  return ok != 0;
+}
+
+// Exclusive prefix over members (op(earlier, later)) of the packs gathered at
+// s_x (field offset off, NFT doubles per member) for member g, and the total.
+// G <= 64: lane m of each wave holds member m's pack.
+template <int NF, int NFT, class Op>
+__device__ __forceinline__ void cl_prefix(const double* s_x, int off, int g, int G, const Pack<NF>& ident,
+                                          Op op, Pack<NF>& pre, Pack<NF>& tot) {
+  const int lane = threadIdx.x & 63;
+  Pack<NF> a = ident;
+  if (lane < G) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) a.v[i] = s_x[lane * NFT + off + i];
+  }
+  const Pack<NF> inc = wave_prefix_incl(a, op);
+  const Pack<NF> pg = lane_pack(inc, g > 0 ? g - 1 : 0);
+  pre = g > 0 ? pg : ident;
+  tot = lane_pack(inc, G - 1);
+}
+// Exclusive suffix over members (op(lower, higher)) and the total.  Lanes
+// past the last member hold ident, which op absorbs exactly.
+template <int NF, int NFT, class Op>
+__device__ __forceinline__ void cl_suffix(const double* s_x, int off, int g, int G, const Pack<NF>& ident,
+                                          Op op, Pack<NF>& suf, Pack<NF>& tot) {
+  const int lane = threadIdx.x & 63;
+  Pack<NF> a = ident;
+  if (lane < G) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) a.v[i] = s_x[lane * NFT + off + i];
+  }
+  const Pack<NF> inc = wave_suffix_incl(a, op);
+  const Pack<NF> sg = lane_pack(inc, g < G - 1 ? g + 1 : 0);
+  suf = g < G - 1 ? sg : ident;
+  tot = lane_pack(inc, 0);
+}
+
+// Slot of position p in the cooperative layout (P = C * NT), quotients from
+// reciprocal estimates corrected to the exact ones.
+__device__ __forceinline__ int cl_div(int a, int b, double ib) {
+  int q = (int)((double)a * ib);
+  if (q * b > a) --q;
+  else if ((q + 1) * b <= a) ++q;
+  return q;
+}
+template <int NT>
+__device__ __forceinline__ int cl_slot(int p, int C, int P, double iC, double iP) {
+  const int g = cl_div(p, P, iP);
+  const int q = p - g * P;
+  const int t = cl_div(q, C, iC);
+  return g * P + (q - t * C) * NT + t;
+}
+// Ring id of home slot hs (the inverse of cl_slot).
+template <int NT>
+__device__ __forceinline__ int32_t cl_id(int32_t hs, int C, int P, double iP) {
+  const int g = cl_div(hs, P, iP);
+  const int r = hs - g * P;
+  return g * P + (r & (NT - 1)) * C + (r >> __builtin_ctz(NT));
+}
+
+// (rho, id) order with the slot carried in the low word: k = id << 32 | slot.
+__device__ __forceinline__ bool k64_lt(double ra, uint64_t ka, double rb, uint64_t kb) {
+  return (ra < rb) | ((ra == rb) & (ka < kb));
+}
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t x, int lm) {
+  return ((uint64_t)lane_xor((uint32_t)(x >> 32), lm) << 32) | lane_xor((uint32_t)x, lm);
+}
+__device__ __forceinline__ uint64_t lane_next64(uint64_t x) {
+  return ((uint64_t)lane_next((uint32_t)(x >> 32)) << 32) | lane_next((uint32_t)x);
+}
+__device__ __forceinline__ uint64_t lane_prev64(uint64_t x) {
+  return ((uint64_t)lane_prev((uint32_t)(x >> 32)) << 32) | lane_prev((uint32_t)x);
+}
+
+// One wave puts the positions [b0, b0 + 256) of a cooperative instance in
+// order: keys by slot in device memory (gk_r, gk_i), order perm by position
+// slot.  Same scheme as the LDS block sort: odd-even transposition for up to
+// 32 phases, then a bitonic network.
+template <int NT>
+__device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double iC, double iP,
+                                           const double* gk_r, const int32_t* gk_i, int32_t* perm) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint64_t k[4];
+  int sl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    sl[j] = -1;
+    r[j] = INFINITY;
+    k[j] = ~0ull;
+    if (p < N) {
+      sl[j] = cl_slot<NT>(p, C, P, iC, iP);
+      const int src = perm[sl[j]];
+      r[j] = gk_r[src];
+      k[j] = ((uint64_t)(uint32_t)gk_i[src] << 32) | (uint32_t)src;
+    }
+  }
+  bool ok = !k64_lt(r[1], k[1], r[0], k[0]) && !k64_lt(r[2], k[2], r[1], k[1]) &&
+            !k64_lt(r[3], k[3], r[2], k[2]);
+  {
+    const double nr = lane_next(r[0]);
+    const uint64_t nk = lane_next64(k[0]);
+    if (lane < 63) ok = ok && !k64_lt(nr, nk, r[3], k[3]);
+  }
+  if (__all(ok)) return;
+  bool done = false;
+  #pragma unroll 1
+  for (int it = 0; it < 8 && !done; ++it) {
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll
+      for (int j = 0; j < 4; j += 2) {
+        if (k64_lt(r[j + 1], k[j + 1], r[j], k[j])) {
+          const double tr = r[j]; r[j] = r[j + 1]; r[j + 1] = tr;
+          const uint64_t tk = k[j]; k[j] = k[j + 1]; k[j + 1] = tk;
+        }
+      }
+      if (k64_lt(r[2], k[2], r[1], k[1])) {
+        const double tr = r[1]; r[1] = r[2]; r[2] = tr;
+        const uint64_t tk = k[1]; k[1] = k[2]; k[2] = tk;
+      }
+      const double nr = lane_next(r[0]), pr = lane_prev(r[3]);
+      const uint64_t nq = lane_next64(k[0]), pq = lane_prev64(k[3]);
+      const bool take_next = lane < 63 && k64_lt(nr, nq, r[3], k[3]);
+      const bool take_prev = lane > 0 && k64_lt(r[0], k[0], pr, pq);
+      if (take_next) { r[3] = nr; k[3] = nq; }
+      if (take_prev) { r[0] = pr; k[0] = pq; }
+    }
+    bool in_order = !k64_lt(r[1], k[1], r[0], k[0]) && !k64_lt(r[2], k[2], r[1], k[1]) &&
+                    !k64_lt(r[3], k[3], r[2], k[2]);
+    const double xr = lane_next(r[0]);
+    const uint64_t xq = lane_next64(k[0]);
+    if (lane < 63) in_order = in_order && !k64_lt(xr, xq, r[3], k[3]);
+    done = __all(in_order);
+  }
+  if (!done) {
+#pragma unroll
+    for (int kk = 2; kk <= 256; kk <<= 1) {
+#pragma unroll
+      for (int d = kk >> 1; d > 0; d >>= 1) {
+        if (d >= 4) {
+          const int lm = d >> 2;
+          const bool lower = (lane & lm) == 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double pr = lane_xor(r[j], lm);
+            const uint64_t pq = lane_xor64(k[j], lm);
+            const bool up = ((4 * lane + j) & kk) == 0;
+            if (k64_lt(pr, pq, r[j], k[j]) == (lower == up)) { r[j] = pr; k[j] = pq; }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j & d) continue;
+            const int jj = j | d;
+            const bool up = ((4 * lane + j) & kk) == 0;
+            if (k64_lt(r[jj], k[jj], r[j], k[j]) == up) {
+              const double tr = r[j]; r[j] = r[jj]; r[jj] = tr;
+              const uint64_t tk = k[j]; k[j] = k[jj]; k[jj] = tk;
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (sl[j] >= 0) perm[sl[j]] = (int32_t)(uint32_t)(k[j] & 0xffffffffull);
+}
+
+// Fallback order of a cooperative instance: a bitonic sort of every position
+// in device memory (keys copied out in position order, padded to the next
+// power of two with keys above every ring), one barrier per network stage.
+template <int NT>
+__device__ __noinline__ bool cl_bitonic(const WakeInst& I, Cluster& cl, double* s_x, int* s_ok) {
+  const int N = I.N, C = I.C, P = C * NT;
+  const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
+  const int P2 = N <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)(N - 1)));
+  const int gt = cl.g * NT + threadIdx.x, nth = cl.G * NT;
+  for (int p = gt; p < P2; p += nth) {
+    if (p < N) {
+      const int src = I.perm[cl_slot<NT>(p, C, P, iC, iP)];
+      I.bt_r[p] = I.gk_r[src];
+      I.bt_i[p] = I.gk_i[src];
+      I.bt_s[p] = src;
+    } else {
+      I.bt_r[p] = INFINITY;
+      I.bt_i[p] = 0x7fffffff;
+      I.bt_s[p] = -1;
+    }
+  }
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  for (int kk = 2; kk <= P2; kk <<= 1) {
+    for (int d = kk >> 1; d > 0; d >>= 1) {
+      const int ld = __builtin_ctz((unsigned)d);
+      for (int i = gt; i < P2 / 2; i += nth) {
+        const int a = ((i >> ld) << (ld + 1)) | (i & (d - 1)), b = a | d;
+        const bool up = (a & kk) == 0;
+        const double ra = I.bt_r[a], rb = I.bt_r[b];
+        const int32_t ia = I.bt_i[a], ib = I.bt_i[b];
+        if (key_lt(rb, ib, ra, ia) == up) {
+          const int32_t sa = I.bt_s[a], sb = I.bt_s[b];
+          I.bt_r[a] = rb; I.bt_r[b] = ra;
+          I.bt_i[a] = ib; I.bt_i[b] = ia;
+          I.bt_s[a] = sb; I.bt_s[b] = sa;
+        }
+      }
+      if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+    }
+  }
+  for (int p = gt; p < N; p += nth) I.perm[cl_slot<NT>(p, C, P, iC, iP)] = I.bt_s[p];
+  return cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok);
+}
+
+// Order fix-up of a cooperative instance from its keys by slot (gk_r, gk_i):
+// writes perm (position slot -> slot).  Blocks of 256 positions sorted by
+// single waves of all members at offsets 0, 256, ... and then 128, 384, ...
+// (the two phases order every ring within 128 positions of its place), the
+// order checked across all positions, at most two such rounds, then the
+// bitonic fallback.  Returns false when a member gave up.
+template <int NT>
+__device__ __noinline__ bool cl_fix(const WakeInst& I, Cluster& cl, double* s_x, int* s_ok) {
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C, P = C * NT;
+  const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
+  const int goff = cl.g * P;
+  const int Ng = min(P, N - goff);
+  const int cnt = max(0, min(C, Ng - tid * C));
+  for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  constexpr int NW = NT / 64;
+  const int gw = cl.g * NW + (tid >> 6), nw = cl.G * NW;
+  #pragma unroll 1
+  for (int round = 0; round < 2; ++round) {
+    #pragma unroll 1
+    for (int b = gw; b * 256 < N; b += nw) cl_sort_block<NT>(b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+    #pragma unroll 1
+    for (int b = gw; 128 + b * 256 < N; b += nw)
+      cl_sort_block<NT>(128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+    // in order? this thread's positions and the position after them
+    int bad = 0;
+    if (cnt > 0) {
+      const int p0 = goff + tid * C;
+      int src = I.perm[goff + tid];
+      double pr = I.gk_r[src];
+      int32_t pi = I.gk_i[src];
+      const int m = p0 + cnt < N ? cnt + 1 : cnt;
+      #pragma unroll 1
+      for (int k = 1; k < m; ++k) {
+        const int sl = k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP);
+        src = I.perm[sl];
+        const double r = I.gk_r[src];
+        const int32_t id = I.gk_i[src];
+        if (key_lt(r, id, pr, pi)) bad = 1;
+        pr = r;
+        pi = id;
+      }
+    }
+    bad = __syncthreads_or(bad);
+    if (!cl_gather<1>(cl, Pack<1>{{(double)bad}}, s_x, s_ok)) return false;
+    double any = 0.0;
+    for (int m = 0; m < cl.G; ++m) any += s_x[m];
+    if (any == 0.0) return true;
+  }
+  return cl_bitonic<NT>(I, cl, s_x, s_ok);
+}

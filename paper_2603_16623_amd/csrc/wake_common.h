@@ -10,7 +10,7 @@
 #define WAKE_ION_REC 8        // doubles per ion interval record
 
 // Control words of one instance (device memory, int32).
-enum { CTL_CUR = 0, CTL_BREAK = 1, CTL_NEXT = 2, CTL_NWORDS = 4 };
+enum { CTL_CUR = 0, CTL_BREAK = 1, CTL_NEXT = 2, CTL_FAULT = 3, CTL_NWORDS = 4 };
 
 // Ion interval record j (j = 0..N), nodes 0 = axis, j = r0[j-1], N+1 = R_p:
 // [node_j, node_{j+1}), psi-psi(0) at node j (dd), its step to node j+1,
@@ -38,6 +38,13 @@ struct WakeAnalytic {
 // that while rings stay near their initial order the constant gathers of a
 // wavefront stay contiguous.
 //
+// Cooperative instances.  An instance too large for one workgroup's LDS is
+// marched by G workgroups (members) together; member g owns the positions
+// [g*P, g*P + P), P = C * nt, and inside that range uses the layout above
+// shifted by g*P (slot g*P + (q % C) * nt + q / C for q = p - g*P).  With
+// G = 1 this is the layout above.  Members exchange their scan totals and
+// meet at barriers through device memory.
+//
 // Order.  Rings are kept in (rho, id) order.  A slice whose pushed radii come
 // out of order only computes the new order as a permutation (sorted position
 // -> slot), in LDS when the keys of every position fit there, else in global
@@ -52,7 +59,9 @@ struct WakeInst {
   int32_t n_an;       // analytic sources
   int32_t has_laser;  // any laser among the analytic sources
   int32_t nt;         // workgroup threads of the slot layout
-  int32_t C;          // rings per thread, ceil(N / nt)
+  int32_t C;          // rings per thread (ceil(N / nt) for a single workgroup)
+  int32_t G;          // workgroups per instance (1, or a cooperative cluster)
+  int32_t task0;      // first task of this instance in its launch queue
   int32_t nb;         // beam-table entries
   double dxi, Rp, inv2pidxi;
   int64_t budget;     // wall-clock budget of this launch in 100 MHz ticks (0: none):
@@ -83,6 +92,15 @@ struct WakeInst {
   double *sk_r[2];
   int32_t *sk_i[2], *sk_s[2];
   int32_t *free_slot;
+  // cooperative instances: exchange packs [2][G][16], control words
+  // (barrier arrivals, give-up flag), sort keys by slot, fallback sort arrays
+  // of the next power of two >= N
+  double *xd;
+  int32_t *xc;
+  double *gk_r;
+  int32_t *gk_i;
+  double *bt_r;
+  int32_t *bt_i, *bt_s;
   // outputs
   double *axis;               // [n_xi][2]: psi(0), E_z(0)
   double *snap;               // [n_rec][6][N] by ring id

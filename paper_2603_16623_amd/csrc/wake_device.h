@@ -167,6 +167,53 @@ __device__ inline dd dd_log(double r) {
 }
 
 // ---------------------------------------------------------------------------
+// single values moved between lanes of a wave
+// ---------------------------------------------------------------------------
+// Value of lane (lane ^ lm) of the wave, lm in {1, 2, 4, 8, 16, 32}, by
+// register-level moves (DPP within rows of 16 lanes, lane-swap instructions
+// across rows and halves) rather than through the LDS crossbar.
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lm) {
+  const int lane = threadIdx.x & 63;
+  switch (lm) {
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
+    case 4: {
+      const uint32_t up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, true);   // from lane + 4
+      const uint32_t dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);   // from lane - 4
+      return (lane & 4) ? dn : up;
+    }
+    case 8: return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, true);  // rotate row by 8
+    case 16: {
+      const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+      return (lane & 16) ? r[0] : r[1];
+    }
+    default: {
+      const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+      return (lane & 32) ? r[0] : r[1];
+    }
+  }
+}
+// Value of the next (lane + 1) or previous (lane - 1) lane of the wave (a
+// whole-wave DPP shift; the last / first lane reads 0).
+__device__ __forceinline__ uint32_t lane_next(uint32_t x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ uint32_t lane_prev(uint32_t x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ double lane_next(double x) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_next((uint32_t)v), hi = lane_next((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_prev(double x) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_prev((uint32_t)v), hi = lane_prev((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_xor(double x, int lm) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_xor((uint32_t)v, lm), hi = lane_xor((uint32_t)(v >> 32), lm);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// ---------------------------------------------------------------------------
 // packs of doubles moved through cross-lane shuffles and LDS
 // ---------------------------------------------------------------------------
 template <int NF>

@@ -21,7 +21,8 @@ hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipSt
 // marcher: workgroups of nt threads (256, 512 or 1024)
 bool march_threads_ok(int nt);
 size_t march_lds_bytes(int nt);
-hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int32_t* counter, int grid,
-                        hipStream_t s);
+hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
+                        int grid, hipStream_t s);
 int march_occupancy(int nt);
+int march_cmax(int nt);     // rings per thread up to which the keys of every position fit LDS
 hipError_t march_prepare(int nt);

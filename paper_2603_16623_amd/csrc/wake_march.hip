@@ -44,6 +44,7 @@
 // positions.
 #include "wake_common.h"
 #include "wake_device.h"
+#include "wake_cluster.h"
 #include "wake_launch.h"
 
 #include <math.h>
@@ -194,8 +195,16 @@ __device__ __forceinline__ int32_t id_of(int32_t hs, int C) {
   return (hs & (NT - 1)) * C + (hs >> __builtin_ctz(NT));
 }
 
+// slot of position p (member g = p / (C nt) of a cooperative instance uses
+// the single-workgroup layout shifted by g C nt; g = 0 otherwise)
 __device__ __forceinline__ unsigned slot_of(int p, int C, int nt) {
-  return (unsigned)((p % C) * nt + p / C);
+  const int P = C * nt, g = p / P, q = p - g * P;
+  return (unsigned)(g * P + (q % C) * nt + q / C);
+}
+// position of slot s (the ring id of home slot s)
+__device__ __forceinline__ int pos_of_slot(int s, int C, int nt) {
+  const int P = C * nt, g = s / P, r = s - g * P;
+  return g * P + (r % nt) * C + r / nt;
 }
 
 // Ion psi - psi(0) and d_rho psi at radius r: linear interpolation inside
@@ -345,7 +354,7 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
   const int tid = threadIdx.x;
   D2* cst = reinterpret_cast<D2*>(const_cast<double*>(I.cst));
   D2* st = reinterpret_cast<D2*>(I.st[0]);
-  const size_t PS = (size_t)I.C * I.nt;      // slots per plane
+  const size_t PS = (size_t)I.G * I.C * I.nt;      // slots per plane
   double* R = const_cast<double*>(I.ion);
   double* consts = const_cast<double*>(I.tot0);
   dd cS = {0.0, 0.0}, cPT = {0.0, 0.0};
@@ -399,6 +408,7 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
     I.ctl[CTL_CUR] = 0;
     I.ctl[CTL_BREAK] = -1;
     I.ctl[CTL_NEXT] = 0;
+    I.ctl[CTL_FAULT] = 0;
   }
   __syncthreads();
   // phase 2: interval ends and steps; the last node is the plasma edge
@@ -682,50 +692,6 @@ __device__ __noinline__ void fix_order_big(const WakeInst& I, int buf, double* s
 // fall back to the ring id.
 __device__ __forceinline__ bool pk_lt(double ra, uint32_t ka, double rb, uint32_t kb) {
   return (ra < rb) | ((ra == rb) & (ka < kb));     // no short-circuit: straight-line selects
-}
-
-// Value of lane (lane ^ lm) of the wave, lm in {1, 2, 4, 8, 16, 32}, by
-// register-level moves (DPP within rows of 16 lanes, lane-swap instructions
-// across rows and halves) rather than through the LDS crossbar.
-__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lm) {
-  const int lane = threadIdx.x & 63;
-  switch (lm) {
-    case 1: return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
-    case 2: return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
-    case 4: {
-      const uint32_t up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, true);   // from lane + 4
-      const uint32_t dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);   // from lane - 4
-      return (lane & 4) ? dn : up;
-    }
-    case 8: return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, true);  // rotate row by 8
-    case 16: {
-      const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-      return (lane & 16) ? r[0] : r[1];
-    }
-    default: {
-      const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-      return (lane & 32) ? r[0] : r[1];
-    }
-  }
-}
-// Value of the next (lane + 1) or previous (lane - 1) lane of the wave (a
-// whole-wave DPP shift; the last / first lane reads 0).
-__device__ __forceinline__ uint32_t lane_next(uint32_t x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true); }
-__device__ __forceinline__ uint32_t lane_prev(uint32_t x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true); }
-__device__ __forceinline__ double lane_next(double x) {
-  const uint64_t v = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = lane_next((uint32_t)v), hi = lane_next((uint32_t)(v >> 32));
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-__device__ __forceinline__ double lane_prev(double x) {
-  const uint64_t v = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = lane_prev((uint32_t)v), hi = lane_prev((uint32_t)(v >> 32));
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-__device__ __forceinline__ double lane_xor(double x, int lm) {
-  const uint64_t v = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = lane_xor((uint32_t)v, lm), hi = lane_xor((uint32_t)(v >> 32), lm);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // One wave puts the positions [b0, b0 + 256) (clipped at N) in (rho, id)
@@ -1128,18 +1094,17 @@ __device__ __forceinline__ void beam_store(const BeamStage<NT>& b, double* s_br,
 // Per-thread sums of (w, w ln rho) over the rings at this thread's
 // positions (ln rho of each ring taken from its slot).
 template <int NT>
-__device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, bool ident,
-                                           bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
+__device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, int goff, uint32_t ps,
+                                           bool ident, bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
   const int tid = threadIdx.x;
-  const unsigned smax = (unsigned)(I.C * NT - 1);
-  const uint32_t ps = (uint32_t)(I.C * NT);
+  const unsigned smax = ps - 1;
   const PV SC = pview(I.st[cur], ps);
   sw = {0.0, 0.0};
   swl = {0.0, 0.0};
   #pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
-    const unsigned s = ident ? sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[sl], smax);
+    const unsigned s = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[goff + sl], smax);
     const double w = SC.ldh(RS_HH, s, 1);
     const D2 l = SC.ld(RS_LN, s);
     sw = dd_add_d(sw, w);
@@ -1147,16 +1112,25 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
   }
 }
 
-template <int NT>
-__device__ void march(const WakeInst& I, unsigned char* smem) {
+// CL: member `member` of a cooperative instance (I.G workgroups); its
+// positions and slots start at goff = member * C * NT, and the slice scans
+// and the order fix-up span all members.
+template <int NT, bool CL>
+__device__ __forceinline__ void march(const WakeInst& I, int member, unsigned char* smem) {
   constexpr int NW = NT / 64;
   constexpr int CMAX = MarchLds<NT>::CMAX;
   constexpr int KCAP = MarchLds<NT>::KCAP;
   const int tid = threadIdx.x;
   const int N = I.N;
   const int C = I.C;
+  const int P = C * NT;                          // positions per member
+  const int goff = CL ? member * P : 0;          // this member's first position / slot
+  const int Ng = CL ? min(P, N - goff) : N;      // positions of this member
   const int p0 = tid * C;
-  const int cnt = max(0, min(C, N - p0));   // rings owned by this thread
+  const int cnt = max(0, min(C, Ng - p0));   // rings owned by this thread
+  const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
+  // ring id of home slot hs
+#define WAKE_ID(hs) (CL ? cl_id<NT>((hs), C, P, iP) : id_of<NT>((hs), C))
 
   double* s_scanA = reinterpret_cast<double*>(smem);      // NW * 16
   double* s_scanB = s_scanA + NW * 16;                     // NW * 16
@@ -1172,37 +1146,63 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   double* s_bc = s_br + WAKE_BCAP;                         // beam cumulative charge
   float* s_ion = reinterpret_cast<float*>(region + MarchLds<NT>::region_bytes());   // ion nodes
   // keys and ring order in LDS (else the order is fixed in global memory)
-  const bool lds_keys = C <= CMAX;
-  const unsigned smax = (unsigned)(C * NT - 1);    // last slot
+  const bool lds_keys = !CL && C <= CMAX;
+  const uint32_t ps = (uint32_t)(CL ? I.G * P : P);   // slots of the instance
+  const unsigned smax = ps - 1;                        // last slot
   const GA<int32_t> gperm = uview(I.perm);
-  // slot, in the current buffer, of the ring at the position of slot-form index sl
-#define WAKE_SLOT(sl) (ident ? (unsigned)(sl) \
-                             : min(lds_keys ? (unsigned)s_perm[sl] : (unsigned)gperm[sl], smax))
+  // slot, in the current buffer, of the ring at this member's position of
+  // slot-form index sl
+#define WAKE_SLOT(sl) (ident ? (unsigned)(goff + (sl)) \
+                             : min(lds_keys ? (unsigned)s_perm[sl] : (unsigned)gperm[goff + (sl)], smax))
+  Cluster cl;
+  cl.g = member;
+  cl.G = CL ? I.G : 1;
+  cl.round = 0;
+  cl.xd = I.xd;
+  cl.xc = I.xc;
+  double* const s_x = s_kr;                                   // gathered packs (cooperative)
+  int* const s_ok = reinterpret_cast<int*>(s_misc + 62);
 
   if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
   const int64_t budget = I.budget;
   int cur = __builtin_amdgcn_readfirstlane(I.ctl[CTL_CUR]);
   __syncthreads();
+  // a ring at slot s came from another thread's chunk (or member)
+#define WAKE_FOREIGN(s) ((unsigned)((int)(s) - goff) >= (unsigned)P || (((int)(s) - goff) & (NT - 1)) != tid)
   // injected states may be unsorted
   bool ident = true;
   bool moved = false;       // a chunk holds rings of another chunk after the fix-up
-  if (lds_keys) {
+  if (CL) {
+    #pragma unroll 1
+    for (int k = 0; k < cnt; ++k) {
+      const unsigned sl = goff + k * NT + tid;
+      const PV SB = pview(I.st[cur], ps);
+      I.gk_r[sl] = st_rho(SB, sl);
+      I.gk_i[sl] = WAKE_ID(st_hs(SB, sl));
+    }
+    if (!cl_fix<NT>(I, cl, s_x, s_ok)) {
+      if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+      return;
+    }
+    ident = false;
+    for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(gperm[goff + k * NT + tid]);
+  } else if (lds_keys) {
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
-      const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
+      const PV SB = pview(I.st[cur], ps);
       s_kr[sl] = st_rho(SB, sl);
       s_ki[sl] = (uint16_t)id_of<NT>(st_hs(SB, sl), C);
     }
     __syncthreads();
     fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
     ident = false;
-    for (int k = 0; k < cnt; ++k) moved |= (s_perm[k * NT + tid] & (NT - 1)) != (unsigned)tid;
+    for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(s_perm[k * NT + tid]);
   } else {
     fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
     ident = false;
-    for (int k = 0; k < cnt; ++k) moved |= (gperm[k * NT + tid] & (NT - 1)) != tid;
+    for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(gperm[k * NT + tid]);
   }
   const dd tot0 = {uni(I.tot0[0]), uni(I.tot0[1])};
   const double dxi = I.dxi;
@@ -1212,7 +1212,6 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   IV.Rp = I.Rp;
   IV.T0 = tot0;
   IV.Q = {uni(I.tot0[2]), uni(I.tot0[3])};
-  const uint32_t ps = (uint32_t)(C * NT);
   const PV KC = pview(I.cst, ps), SCR = pview(I.sc, ps);
   const GA<double> A2 = uview(I.a2), DA2 = uview(I.da2);
   const int n_an = I.n_an;
@@ -1227,7 +1226,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
     const unsigned s = WAKE_SLOT(sl);
-    const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
+    const PV SB = pview(I.st[cur], ps);
     const unsigned hs = (unsigned)st_hs(SB, s);
     const dd lr = ring_log(KC.ld(RC_R0, hs), KC.ld(RC_LN, hs), st_rho(SB, s));
     SB.st(RS_LN, s, d2(lr.hi, lr.lo));
@@ -1238,13 +1237,13 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   // others backward as the push does.
   dd sw = {0.0, 0.0}, swl = {0.0, 0.0};
   if (moved) {
-    chunk_sums<NT>(I, cur, cnt, ident, lds_keys, s_perm, sw, swl);
+    chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
   } else {
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
-      const PV SB = pview(I.st[cur], (uint32_t)(C * NT));
+      const PV SB = pview(I.st[cur], ps);
       const double w = SB.ldh(RS_HH, s, 1);
       const D2 l = SB.ld(RS_LN, s);
       sw = dd_add_d(sw, w);
@@ -1260,17 +1259,56 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
   for (;;) {
     // ---- Gauss/log prefix sum_{k<i} (w_k, w_k ln rho_k); flags of slice n-1 ----
     Pack<6> t6;
-    const Pack<6> pre = block_prefix<NT, 6, SliceHeadOp, false>(
+    Pack<6> pre = block_prefix<NT, 6, SliceHeadOp, false>(
         Pack<6>{{sw.hi, sw.lo, swl.hi, swl.lo, bad, dis}}, Pack<6>{{0, 0, 0, 0, 0, 0}},
         SliceHeadOp(), s_scanA, t6);
+    if (CL) {
+      // members' totals, their first and last keys in the current order (run
+      // boundaries between members) and the time budget
+      Pack<11> mine;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) mine.v[i] = t6.v[i];
+      if (tid == 0) {
+        const int ql = Ng - 1;
+        const unsigned sf = WAKE_SLOT(0u), sL = WAKE_SLOT((unsigned)((ql % C) * NT + ql / C));
+        mine.v[6] = I.gk_r[sf];
+        mine.v[7] = (double)I.gk_i[sf];
+        mine.v[8] = I.gk_r[sL];
+        mine.v[9] = (double)I.gk_i[sL];
+        mine.v[10] = (budget > 0 && n > I.first &&
+                      (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget) ? 1.0 : 0.0;
+      }
+      if (!cl_gather<11>(cl, mine, s_x, s_ok)) {
+        if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+        return;
+      }
+      Pack<6> pg;
+      cl_prefix<6, 11>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
+      pre = SliceHeadOp()(pg, pre);
+      double bnd = 0.0, stop = 0.0;
+      for (int m = 0; m < cl.G; ++m) {
+        stop += s_x[m * 11 + 10];
+        if (m + 1 < cl.G &&
+            key_lt(s_x[(m + 1) * 11 + 6], (int32_t)s_x[(m + 1) * 11 + 7], s_x[m * 11 + 8], (int32_t)s_x[m * 11 + 9]))
+          bnd += 1.0;
+      }
+      t6.v[5] += bnd;
+      if (stop != 0.0 && t6.v[4] == 0.0) end = n;
+    }
     if (t6.v[4] != 0.0) {     // slice n-1 broke down: stop there
-      if (tid == 0) { I.ctl[CTL_BREAK] = n - 1; I.ctl[CTL_CUR] = unpushed; I.ctl[CTL_NEXT] = n - 1; }
+      if (tid == 0 && member == 0) { I.ctl[CTL_BREAK] = n - 1; I.ctl[CTL_CUR] = unpushed; I.ctl[CTL_NEXT] = n - 1; }
       return;
     }
     if (n == end) break;
     if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
       bool restage = true;    // the general fix-ups use the beam-table area of LDS
-      if (lds_keys) {
+      if (CL) {
+        if (!cl_fix<NT>(I, cl, s_x, s_ok)) {
+          if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+          return;
+        }
+        restage = false;
+      } else if (lds_keys) {
         restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm);
         if (restage) fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
       } else {
@@ -1280,8 +1318,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       // chunks that took a ring from another chunk sum again
       bool changed = false;
       for (int k = 0; k < cnt; ++k)
-        changed |= ((lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[k * NT + tid]) & (NT - 1)) != tid;
-      if (changed) chunk_sums<NT>(I, cur, cnt, ident, lds_keys, s_perm, sw, swl);
+        changed |= WAKE_FOREIGN(lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[goff + k * NT + tid]);
+      if (changed) chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
       if (restage) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
       dis = 0.0;
       continue;
@@ -1399,11 +1437,11 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       l0b += G.v[1] * s0b - G.v[3] * s0a;
       l1a += G.v[0] * s1b - G.v[2] * s1a;
       l1b += G.v[1] * s1b - G.v[3] * s1a;
-      SCR.st(SC_PSI, sl, d2(psi, dpsi));
-      SCR.st(SC_BB, sl, d2(bb, hh_pack(hs, 0)));      // pass E takes the home slot from here
-      if (has_laser) { A2.st(sl, aa); DA2.st(sl, dda); }
+      SCR.st(SC_PSI, goff + sl, d2(psi, dpsi));
+      SCR.st(SC_BB, goff + sl, d2(bb, hh_pack(hs, 0)));      // pass E takes the home slot from here
+      if (has_laser) { A2.st(goff + sl, aa); DA2.st(goff + sl, dda); }
       // the ring's home slot and hint move to its position slot in the next buffer
-      Sn.st(RS_HH, sl, d2(hh_pack(hs, h), w));
+      Sn.st(RS_HH, goff + sl, d2(hh_pack(hs, h), w));
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1412,6 +1450,20 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         Pack<5>{{G.v[0], G.v[1], G.v[2], G.v[3], Vw}}, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}},
         FwdMatSumOp(), Pack<5>{{G.v[3], -G.v[1], -G.v[2], G.v[0], Vw}},
         Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, BwdMatSumOp(), s_scanB, gp, gt, hx, ht);
+    if (CL) {                // the other members' chunk products before / after this one
+      Pack<10> mine;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) { mine.v[i] = gt.v[i]; mine.v[5 + i] = ht.v[i]; }
+      if (!cl_gather<10>(cl, mine, s_x, s_ok)) {
+        if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+        return;
+      }
+      Pack<5> pg, sg;
+      cl_prefix<5, 10>(s_x, 0, member, cl.G, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, FwdMatSumOp(), pg, gt);
+      cl_suffix<5, 10>(s_x, 5, member, cl.G, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, BwdMatSumOp(), sg, ht);
+      gp = FwdMatSumOp()(pg, gp);
+      hx = BwdMatSumOp()(hx, sg);
+    }
     const double W = gt.v[0];                 // det[g_N, (0,1)]
     const double iW = 1.0 / W;
     const double Vtot = gt.v[4];
@@ -1428,6 +1480,17 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     block_prefix_suffix<NT, 1, 1, SumOp<1>, SumOp<1>, false>(
         Pack<1>{{le}}, Pack<1>{{0.0}}, SumOp<1>(), Pack<1>{{lds}}, Pack<1>{{0.0}}, SumOp<1>(),
         s_scanA, ep, et, dsf, dt);
+    if (CL) {
+      if (!cl_gather<2>(cl, Pack<2>{{et.v[0], dt.v[0]}}, s_x, s_ok)) {
+        if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+        return;
+      }
+      Pack<1> pg, sg;
+      cl_prefix<1, 2>(s_x, 0, member, cl.G, Pack<1>{{0.0}}, SumOp<1>(), pg, et);
+      cl_suffix<1, 2>(s_x, 1, member, cl.G, Pack<1>{{0.0}}, SumOp<1>(), sg, dt);
+      ep = SumOp<1>()(pg, ep);
+      dsf = SumOp<1>()(dsf, sg);
+    }
 
     // ---- pass E: B^(p), outputs, push ----
     // the next slice's beam-table entries, fetched now and stored after the pass
@@ -1458,8 +1521,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const unsigned sl = (cnt - 1) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       y_ru = Sc.ld(RS_RU, s); y_f = Sc.ld(RS_F, s);
-      y_ps = SCR.ld(SC_PSI, sl);
-      const D2 b = SCR.ld(SC_BB, sl);
+      y_ps = SCR.ld(SC_PSI, goff + sl);
+      const D2 b = SCR.ld(SC_BB, goff + sl);
       y_bb = b.x;
       y_hs = hh_hs(b.y);
     }
@@ -1467,8 +1530,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const unsigned sl = (cnt - 2) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
-      v_ps = SCR.ld(SC_PSI, sl);
-      const D2 b = SCR.ld(SC_BB, sl);
+      v_ps = SCR.ld(SC_PSI, goff + sl);
+      const D2 b = SCR.ld(SC_BB, goff + sl);
       v_bb = b.x;
       v_hs = hh_hs(b.y);
     }
@@ -1488,8 +1551,8 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const unsigned sp = sl - 2 * NT;
         const unsigned s = WAKE_SLOT(sp);
         v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
-        v_ps = SCR.ld(SC_PSI, sp);
-        const D2 b = SCR.ld(SC_BB, sp);
+        v_ps = SCR.ld(SC_PSI, goff + sp);
+        const D2 b = SCR.ld(SC_BB, goff + sp);
         v_bb = b.x;
         v_hs = hh_hs(b.y);
       }
@@ -1497,7 +1560,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         const unsigned kc = (unsigned)y_hs;
         c_w = KC.ld(RC_W, kc); c_r = KC.ld(RC_R0, kc); c_l = KC.ld(RC_LN, kc);
       }
-      const double a2 = has_laser ? A2[sl] : 0.0, da2 = has_laser ? DA2[sl] : 0.0;
+      const double a2 = has_laser ? A2[goff + sl] : 0.0, da2 = has_laser ? DA2[goff + sl] : 0.0;
       const double irho = rcp_nr(rho);
       const Local L = local_of(irho, u, w, psi, a2);
       const double dz = -(Vgt + (w - wh) * u * irho * L.ipb);
@@ -1517,7 +1580,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       const double bt = bb + bp;
       const double ez = -dz;
       if (!(isfinite(psi) && isfinite(dpsi) && isfinite(ez) && isfinite(bt))) bad = 1.0;
-      const int32_t id = id_of<NT>(hs, C);
+      const int32_t id = WAKE_ID(hs);
       if (rec_snap) {
         double* sp = I.snap + (size_t)(n / I.stride) * OUT_N * N;
         sp[OUT_PSI * N + id] = psi; sp[OUT_ERBT * N + id] = -dpsi;
@@ -1541,12 +1604,13 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
         if (rn < 0.0) { rn = -rn; un = -un; sr = -sr; su = -su; }
         if (!(isfinite(rn) && isfinite(un))) bad = 1.0;
         const dd lr = dd_add_d({k_lh, k_ll}, log1p_fast((rn - k_r0) * k_ir0));   // as ring_log
-        Sn.st(RS_RU, sl, d2(rn, un));
-        Sn.st(RS_F, sl, d2(sr, su));
-        Sn.st(RS_LN, sl, d2(lr.hi, lr.lo));
+        Sn.st(RS_RU, goff + sl, d2(rn, un));
+        Sn.st(RS_F, goff + sl, d2(sr, su));
+        Sn.st(RS_LN, goff + sl, d2(lr.hi, lr.lo));
         sw2 = dd_add_d(sw2, w);
         swl2 = dd_add_fast(swl2, dd_mul_d(lr, w));
         if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
+        if (CL) { I.gk_r[goff + sl] = rn; I.gk_i[goff + sl] = id; }
         if (!key_lt(rn, id, nxt_r, nxt_i)) dis_l = 1.0;
         if (k == cnt - 1) { last_r = rn; last_i = id; }
         nxt_r = rn;
@@ -1554,7 +1618,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       }
       Vgt += L.v;
     }
-    if (tid == 0) { I.axis[2 * n] = psi_axis; I.axis[2 * n + 1] = Vtot; }
+    if (tid == 0 && member == 0) { I.axis[2 * n] = psi_axis; I.axis[2 * n + 1] = Vtot; }
     // order across chunk boundaries: this chunk's first pushed key (+inf if
     // empty) against the previous chunk's last one
     s_fr[tid] = nxt_r;
@@ -1563,9 +1627,10 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
       stage_analytic<NT>(I, n + 1, s_misc);
       beam_store<NT>(nbs, s_br, s_bc);
     }
-    // out of time: this slice is the launch's last (one clock read, broadcast)
+    // out of time: this slice is the launch's last (one clock read, broadcast;
+    // cooperative members decide together at the next slice head)
     if (tid == 0)
-      s_misc[63] = budget > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget ? 1.0 : 0.0;
+      s_misc[63] = !CL && budget > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget ? 1.0 : 0.0;
     __syncthreads();
     if (s_misc[63] != 0.0) end = n + 1;
     if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))
@@ -1581,7 +1646,17 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
     }
     ++n;
   }
-  if (tid == 0) { I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = end; }
+  if (tid == 0 && member == 0) { I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = end; }
+#undef WAKE_SLOT
+#undef WAKE_ID
+#undef WAKE_FOREIGN
+}
+
+// the cooperative march as a function of its own (its registers stay out of
+// the single-workgroup march, which is inlined into the kernel)
+template <int NT>
+__device__ __noinline__ void march_member(const WakeInst& I, int member, unsigned char* smem) {
+  march<NT, true>(I, member, smem);
 }
 
 #ifndef WAKE_WAVES_PER_EU
@@ -1590,7 +1665,7 @@ __device__ void march(const WakeInst& I, unsigned char* smem) {
 // WAKE_WAVES_PER_EU waves per SIMD (2: up to 256 VGPRs per lane)
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAKE_WAVES_PER_EU)))
-void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int32_t* counter) {
+void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_tasks, int32_t* counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_idx;
   for (;;) {
@@ -1598,15 +1673,30 @@ void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int32_t*
     __syncthreads();
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     __syncthreads();
-    if (idx >= n_insts) return;   // every workgroup leaves once the queue is empty
-    const WakeInst& I = insts[idx];
-    if (I.nt == NT) march<NT>(I, smem);
+    if (idx >= n_tasks) return;   // every workgroup leaves once the queue is empty
+    // task idx: member idx - task0 of the last instance with task0 <= idx
+    int lo = 0, hi = n_insts;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (__builtin_amdgcn_readfirstlane(insts[mid].task0) <= idx) lo = mid; else hi = mid;
+    }
+    const WakeInst& I = insts[lo];
+    if (I.nt == NT) {
+      if (I.G > 1) march_member<NT>(I, idx - I.task0, smem);
+      else march<NT, false>(I, 0, smem);
+    }
     __syncthreads();
   }
 }
 
 __global__ void counter_zero_kernel(int32_t* p) {
   if (threadIdx.x == 0) p[0] = 0;
+}
+
+// barrier words of the cooperative instances of a launch start at zero
+__global__ void cluster_reset_kernel(const WakeInst* __restrict__ insts, int n_insts) {
+  for (int i = threadIdx.x; i < n_insts; i += blockDim.x)
+    if (insts[i].G > 1) { insts[i].xc[0] = 0; insts[i].xc[1] = 0; }
 }
 
 // ---------------------------------------------------------------------------
@@ -1617,10 +1707,10 @@ __global__ void state_by_id_kernel(WakeInst I, double* rho, double* u, double* f
   if (p >= I.N) return;
   const int c = I.ctl[CTL_CUR];
   const unsigned sl = slot_of(p, I.C, I.nt);
-  const size_t PS = (size_t)I.C * I.nt;
+  const size_t PS = (size_t)I.G * I.C * I.nt;
   const D2* r = reinterpret_cast<const D2*>(I.st[c]) + sl;
   const int hs = hh_hs(r[RS_HH * PS].x);
-  const int i = (hs % I.nt) * I.C + hs / I.nt;
+  const int i = pos_of_slot(hs, I.C, I.nt);
   if (rho) rho[i] = r[RS_RU * PS].x;
   if (u) u[i] = r[RS_RU * PS].y;
   if (fr) fr[i] = r[RS_F * PS].x;
@@ -1632,10 +1722,10 @@ __global__ void state_by_id_kernel(WakeInst I, double* rho, double* u, double* f
 __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u, const double* fr,
                                  const double* fu, int slice) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = slice; }
+  if (i == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = slice; I.ctl[CTL_FAULT] = 0; }
   if (i >= I.N) return;
   const unsigned sl = slot_of(i, I.C, I.nt);
-  const size_t PS = (size_t)I.C * I.nt;
+  const size_t PS = (size_t)I.G * I.C * I.nt;
   D2* r = reinterpret_cast<D2*>(I.st[0]) + sl;
   r[RS_RU * PS] = d2(rho[i], u[i]);
   r[RS_F * PS] = d2(fr ? fr[i] : 0.0, fu ? fu[i] : 0.0);
@@ -1649,14 +1739,14 @@ __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_ins
   const WakeInst& I = insts[blockIdx.x];
   for (int j = threadIdx.x; j < I.N; j += blockDim.x) {
     const unsigned sl = slot_of(j, I.C, I.nt);
-    const size_t PS = (size_t)I.C * I.nt;
+    const size_t PS = (size_t)I.G * I.C * I.nt;
     D2* r = reinterpret_cast<D2*>(I.st[0]) + sl;
     r[RS_RU * PS] = d2(reinterpret_cast<const D2*>(I.cst)[RC_R0 * PS + sl].x, 0.0);
     r[RS_F * PS] = d2(0.0, 0.0);
     r[RS_LN * PS] = d2(0.0, 0.0);
     r[RS_HH * PS] = d2(hh_pack((int32_t)sl, j + 1), reinterpret_cast<const D2*>(I.cst)[RC_W * PS + sl].x);
   }
-  if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; }
+  if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; I.ctl[CTL_FAULT] = 0; }
 }
 
 // Control words of a list of instances into one buffer (4 words each).
@@ -1710,18 +1800,27 @@ size_t march_lds_bytes(int nt) {
   return 0;
 }
 
-hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int32_t* counter, int grid,
-                        hipStream_t s) {
+hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
+                        int grid, hipStream_t s) {
 #define X(a)                                                                                      \
   if (nt == a) {                                                                                  \
     hipLaunchKernelGGL(counter_zero_kernel, dim3(1), dim3(64), 0, s, counter);                     \
+    hipLaunchKernelGGL(cluster_reset_kernel, dim3(1), dim3(256), 0, s, d_insts, n_insts);          \
     hipLaunchKernelGGL((wake_march_kernel<a>), dim3(grid), dim3(a), MarchLds<a>::bytes(), s,       \
-                       d_insts, n_insts, counter);                                                 \
+                       d_insts, n_insts, n_tasks, counter);                                        \
     return hipGetLastError();                                                                     \
   }
   WAKE_THREADS(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+int march_cmax(int nt) {
+#define X(a) \
+  if (nt == a) return MarchLds<a>::CMAX;
+  WAKE_THREADS(X)
+#undef X
+  return 0;
 }
 
 int march_occupancy(int nt) {

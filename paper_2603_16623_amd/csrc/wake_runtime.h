@@ -52,8 +52,11 @@ int dev_err(hipError_t e);
 int drain(wake_ctx* c);
 // persistent grid for nt-thread workgroups over n instances
 int march_grid(int nt, int n_insts, int dev);
+// first task of each descriptor (members of a cooperative instance are G
+// consecutive tasks); returns the number of tasks
+int assign_tasks(std::vector<WakeInst>& v);
 // one persistent launch per distinct workgroup size over the descriptors v
-// (already copied to d_insts)
+// (already copied to d_insts, tasks assigned)
 hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts, int32_t* d_counter,
                         int dev, int grid_override, hipStream_t s);
 // context creation / footprint with an explicit workgroup size

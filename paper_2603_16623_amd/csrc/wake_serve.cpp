@@ -270,6 +270,7 @@ extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_qu
     });
     std::vector<WakeInst> vs(n);
     for (int i = 0; i < n; ++i) vs[i] = v[order[i]];
+    assign_tasks(vs);
     HIP_TRY(hipMemcpyAsync(s->d_insts, vs.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice,
                            s->stream));
     HIP_TRY(launch_insts(vs, s->d_insts, s->d_counter, s->device, 0, s->stream));

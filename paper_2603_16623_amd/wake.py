@@ -70,6 +70,8 @@ _SIGS = {
     "wake_tiling_count": (_I, []),
     "wake_tiling_get": (_I, [_I, C.POINTER(_I), C.POINTER(_I)]),
     "wake_set_tiling": (_I, [_I, _I]),
+    "wake_set_cluster": (_I, [_I, _I]),
+    "wake_get_layout": (_I, [C.c_void_p, C.POINTER(_I), C.POINTER(_I)]),
     "wake_get_tiling": (_I, [C.POINTER(_I), C.POINTER(_I)]),
     "wake_tiling_occupancy": (_I, [_I, _I]),
     "wake_batch_create": (_I, [C.POINTER(_P), C.POINTER(_P), _I, _P]),
@@ -175,6 +177,13 @@ def wake_set_tiling(threads: int, wgs_per_cu: int = 0):
     _check(load().wake_set_tiling(threads, wgs_per_cu), "wake_set_tiling")
 
 
+def wake_set_cluster(rings_per_thread: int = 0, min_rings: int = 0):
+    """Cooperative (multi-workgroup) layout for contexts created from now on:
+    rings per thread of their members (0: 8) and the ring count from which
+    contexts are cooperative (0: beyond one workgroup's LDS)."""
+    _check(load().wake_set_cluster(rings_per_thread, min_rings), "wake_set_cluster")
+
+
 def wake_get_tiling():
     a, b = _I(), _I()
     _check(load().wake_get_tiling(C.byref(a), C.byref(b)), "wake_get_tiling")
@@ -212,6 +221,12 @@ class WakeSolver:
     def from_instance(cls, inst, record_stride: int = 0, stream=None):
         return cls(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens,
                    record_stride, stream)
+
+    def layout(self):
+        """(workgroups, rings per thread) of this context's layout."""
+        g, c = _I(), _I()
+        _check(self._lib.wake_get_layout(self.h, C.byref(g), C.byref(c)), "wake_get_layout")
+        return g.value, c.value
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -1,0 +1,180 @@
+"""GPU parity of cooperative instances: several workgroups march one instance
+(the large-ring-count path), here forced onto small instances so the oracle
+stays fast.  Same tolerances as the single-workgroup parity tests; the
+cooperative march must also be bitwise reproducible across launch splits and
+inside a batch."""
+import numpy as np
+import pytest
+
+from oracle.wake_oracle import RingOracle
+from paper_2603_16623_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("psi", "er_bt", "ez", "bt")
+TOL_SLICE = 1e-12
+
+
+@pytest.fixture(scope="module")
+def wk():
+    from paper_2603_16623_amd import wake
+    wake.load()
+    yield wake
+    wake.wake_set_cluster(0, 0)
+    wake.wake_set_tiling(512, 0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _oracle(inst):
+    return RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+
+
+def _field_scale(ref):
+    parts = [np.abs(ref[q]).max() for q in FIELDS]
+    parts += [np.abs(ref["C"]).max(), np.abs(ref["bb"]).max(), abs(ref["psi_axis"]), abs(ref["ez_axis"])]
+    return float(max(parts))
+
+
+def _tol(F):
+    return TOL_SLICE * F if F > 0 else 1e-15
+
+
+def _rel(a, b):
+    s = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b))) / (s if s > 0 else 1.0)
+
+
+def _inst(n=3000, n_xi=60):
+    return W.small_instance(5, n_rings=n, n_xi=n_xi, n_peak=3.0, sigma_r=0.2, geometric=False, dxi=0.02)
+
+
+# (threads, rings per thread): members = ceil(3000 / (threads * rings))
+LAYOUTS = [((256, 0), 2, 6), ((512, 0), 1, 6), ((512, 0), 4, 2)]
+
+
+@pytest.mark.parametrize("tiling,rings,members", LAYOUTS)
+def test_cluster_slice_parity(wk, tiling, rings, members):
+    inst = _inst()
+    o = _oracle(inst)
+    wk.wake_set_tiling(*tiling)
+    wk.wake_set_cluster(rings, 500)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    assert s.layout() == (members, rings)
+    state = o.initial_state()
+    at = 0
+    for n in (0, 25, 50):
+        for m in range(at, n):
+            _, state = o.slice(m, state)
+        at = n
+        ref, new = o.slice(n, state, keep=True)
+        F = _field_scale(ref)
+        _say(f"cluster slice parity tiling={tiling} rings={rings} members={members} slice={n} F={F:.3e}")
+        s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(n, 1)
+        got = s.wake_fields(n)
+        for q in FIELDS:
+            e = float(np.max(np.abs(got[q] - ref[q])))
+            assert e <= _tol(F), (n, q, e, F)
+        st = s.wake_get_state()
+        assert st["slice"] == n + 1
+        for a, b in (("rho", "rho"), ("ur", "u"), ("f_rho", "fr"), ("f_u", "fu")):
+            assert _rel(st[a], new[b]) <= TOL_SLICE, (n, a)
+        lp, le = s.wake_lineout()
+        assert abs(lp[n] - ref["psi_axis"]) <= _tol(F)
+        assert abs(le[n] - ref["ez_axis"]) <= _tol(F)
+    s.close()
+
+
+@pytest.mark.parametrize("u_amp", [0.05, 2.0, 40.0])
+def test_cluster_reorder_after_push(wk, u_amp):
+    """Pushed rings crossing a few to thousands of neighbours, across member
+    boundaries: block rounds, and the bitonic fallback for the far moves."""
+    rng = np.random.default_rng(31)
+    inst = _inst(n_xi=40)
+    o = _oracle(inst)
+    state = o.initial_state()
+    state["u"] = rng.normal(0, u_amp, inst.n_rings)
+    n = 10
+    _, mid = o.slice(n, state, keep=True)
+    ref, _ = o.slice(n + 1, mid, keep=True)
+    F = _field_scale(ref)
+    wk.wake_set_tiling(256, 0)
+    wk.wake_set_cluster(2, 500)
+    _say(f"cluster reorder u_amp={u_amp}")
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    assert s.layout()[0] == 6
+    s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(n, 2)
+    got = s.wake_fields(n + 1)
+    for q in FIELDS:
+        assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
+    assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
+    s.close()
+
+
+def test_cluster_unsorted_injected_state(wk):
+    """A random (heavily crossed) injected state is ordered before the first
+    slice (the bitonic fallback over all members)."""
+    rng = np.random.default_rng(21)
+    inst = _inst(n_xi=40)
+    o = _oracle(inst)
+    state = o.initial_state()
+    state["rho"] = inst.r0 * np.exp(rng.normal(0, 0.2, inst.n_rings))
+    state["u"] = rng.normal(0, 0.1, inst.n_rings)
+    ref, new = o.slice(20, state, keep=True)
+    F = _field_scale(ref)
+    wk.wake_set_tiling(256, 0)
+    wk.wake_set_cluster(2, 500)
+    _say("cluster unsorted injected state")
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    s.wake_set_state(20, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(20, 1)
+    got = s.wake_fields(20)
+    for q in FIELDS:
+        assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
+    st = s.wake_get_state()
+    assert _rel(st["rho"], new["rho"]) <= TOL_SLICE
+    s.close()
+
+
+def test_cluster_split_and_batch_bitwise(wk):
+    """A cooperative march split over launches, and inside a batch with
+    single-workgroup instances, is bitwise the one-launch march."""
+    wk.wake_set_tiling(256, 0)
+    wk.wake_set_cluster(2, 2000)
+    big = _inst(n_xi=60)
+    rng = np.random.default_rng(44)
+    small = [W.batched_instance(rng, n, 60, n_drv=2000, n_wit=500, r_max=4.0) for n in (300, 1500)]
+    _say("cluster split / batch")
+    ref = wk.WakeSolver.from_instance(big, record_stride=20)
+    assert ref.layout()[0] > 1
+    ref.wake_solve(0, 60)
+    f_ref = ref.wake_fields(40)
+    st_ref = ref.wake_get_state()
+    lp_ref, le_ref = ref.wake_lineout()
+    ref.close()
+    s = wk.WakeSolver.from_instance(big, record_stride=20)
+    for a, b in ((0, 7), (7, 30), (37, 23)):
+        s.wake_solve(a, b)
+    g = s.wake_fields(40)
+    for q in FIELDS:
+        assert np.array_equal(g[q], f_ref[q]), q
+    assert np.array_equal(s.wake_get_state()["rho"], st_ref["rho"])
+    s.close()
+    solvers = [wk.WakeSolver.from_instance(i, record_stride=20) for i in [big] + small]
+    assert solvers[1].layout()[0] == 1
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_solve(25)
+    b.wake_batch_solve(-1)
+    b.wake_batch_sync()
+    g = solvers[0].wake_fields(40)
+    for q in FIELDS:
+        assert np.array_equal(g[q], f_ref[q]), q
+    lp, le = solvers[0].wake_lineout()
+    assert np.array_equal(lp, lp_ref) and np.array_equal(le, le_ref)
+    b.close()
+    for x in solvers:
+        x.close()
