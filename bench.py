@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--served-rate", type=float, default=0.0,
                     help="request rate of the served run (0: 70%% of the measured capacity)")
     ap.add_argument("--served-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-large", dest="large", action="store_false",
+                    help="skip the large single instances (cooperative path)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the "
@@ -285,6 +287,27 @@ def main():
             capacity_ring_slices_per_s=capacity,
             offered_at_2000_per_s=offered, stable_at_2000_per_s=bool(offered < capacity),
             max_sustainable_rate_per_s=capacity / C4_MEAN_WORK, **run)
+    if args.large:
+        # the large single instances on the cooperative (multi-workgroup) path
+        log("large instances")
+        big = {}
+        for name, mk in (("blowout 20000 rings x 4000 slices", W.config2),
+                         ("laser 200000 rings x 8000 slices", W.config5)):
+            inst = mk()
+            s = wake.WakeSolver.from_instance(inst, stream=stream)
+            s.wake_prepare()
+            g, c = s.layout()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s.wake_solve(0, inst.n_xi)
+            s.wake_sync()
+            dt = time.perf_counter() - t1
+            brk = s.wake_status()[0]
+            s.close()
+            big[name] = dict(workgroups=g, rings_per_thread=c, seconds=dt, breakdown_slice=brk,
+                             ring_slice_updates_per_s=inst.ring_slices / dt,
+                             us_per_slice=dt / inst.n_xi * 1e6)
+        out["large_instances"] = big
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_budget)

@@ -334,3 +334,54 @@ __device__ __noinline__ bool cl_fix(const WakeInst& I, Cluster& cl, double* s_x,
   }
   return cl_bitonic<NT>(I, cl, s_x, s_ok);
 }
+
+// One in-loop round of the cooperative fix-up (the first from the identity
+// order of the pushed rings): the blocks at offsets 0, 256,
+// ... lie inside one member's range (member ranges are multiples of 256
+// positions), so each member sorts its own after a local barrier; the
+// blocks at 128, 384, ... straddle members and go between two barriers.
+// *bad reports whether this member's positions (and the first of the next
+// member) are still out of order; the next slice-head exchange sums it.
+template <int NT>
+__device__ __noinline__ bool cl_fix_round(const WakeInst& I, Cluster& cl, double* s_x, int* s_ok, bool first,
+                                          int* bad) {
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C, P = C * NT;
+  const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
+  const int goff = cl.g * P;
+  const int Ng = min(P, N - goff);
+  const int cnt = max(0, min(C, Ng - tid * C));
+  constexpr int NW = NT / 64;
+  if (first)           // later rounds continue from the order the previous one left
+    for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
+  __syncthreads();
+  #pragma unroll 1
+  for (int b = (tid >> 6); b * 256 < Ng; b += NW)
+    cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  const int gw = cl.g * NW + (tid >> 6), nw = cl.G * NW;
+  #pragma unroll 1
+  for (int b = gw; 128 + b * 256 < N; b += nw)
+    cl_sort_block<NT>(128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  int b_ = 0;
+  if (cnt > 0) {
+    const int p0 = goff + tid * C;
+    int src = I.perm[goff + tid];
+    double pr = I.gk_r[src];
+    int32_t pi = I.gk_i[src];
+    const int m = p0 + cnt < N ? cnt + 1 : cnt;
+    #pragma unroll 1
+    for (int k = 1; k < m; ++k) {
+      const int sl = k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP);
+      src = I.perm[sl];
+      const double r = I.gk_r[src];
+      const int32_t id = I.gk_i[src];
+      if (key_lt(r, id, pr, pi)) b_ = 1;
+      pr = r;
+      pi = id;
+    }
+  }
+  *bad = __syncthreads_or(b_);
+  return true;
+}

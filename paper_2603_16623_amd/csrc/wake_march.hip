@@ -1254,6 +1254,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
   int end = I.first + I.count;
   if (n < end) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
   double bad = 0.0, dis = 0.0;
+  int fix_rounds = 0;          // consecutive fix-up rounds at this slice head
   int unpushed = cur;          // buffer with the unpushed state of slice n-1
 
   for (;;) {
@@ -1302,11 +1303,17 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
     if (n == end) break;
     if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
       bool restage = true;    // the general fix-ups use the beam-table area of LDS
+      double still = 0.0;      // cooperative: this member still out of order after the round
       if (CL) {
-        if (!cl_fix<NT>(I, cl, s_x, s_ok)) {
+        // block rounds; after two that leave disorder, the full sort
+        int b = 0;
+        const bool ok = fix_rounds < 2 ? cl_fix_round<NT>(I, cl, s_x, s_ok, fix_rounds == 0, &b) : cl_bitonic<NT>(I, cl, s_x, s_ok);
+        if (!ok) {
           if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
           return;
         }
+        ++fix_rounds;
+        still = b ? 1.0 : 0.0;
         restage = false;
       } else if (lds_keys) {
         restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm);
@@ -1321,9 +1328,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
         changed |= WAKE_FOREIGN(lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[goff + k * NT + tid]);
       if (changed) chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
       if (restage) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
-      dis = 0.0;
+      dis = still;
       continue;
     }
+    fix_rounds = 0;
     const double psi_axis = dd_round(dd_sub({t6.v[2], t6.v[3]}, tot0));
     const bool do_push = n < I.n_xi - 1;
     const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
