@@ -288,8 +288,12 @@ def main():
             offered_at_2000_per_s=offered, stable_at_2000_per_s=bool(offered < capacity),
             max_sustainable_rate_per_s=capacity / C4_MEAN_WORK, **run)
     if args.large:
-        # the large single instances on the cooperative (multi-workgroup) path
+        # the large single instances on the cooperative (multi-workgroup) path,
+        # four rings per member thread (more members per instance: lower
+        # latency of one solve; the served form keeps the default eight,
+        # which gives it more throughput)
         log("large instances")
+        wake.wake_set_cluster(4, 0)
         big = {}
         for name, mk in (("blowout 20000 rings x 4000 slices", W.config2),
                          ("laser 200000 rings x 8000 slices", W.config5)):
@@ -307,6 +311,7 @@ def main():
             big[name] = dict(workgroups=g, rings_per_thread=c, seconds=dt, breakdown_slice=brk,
                              ring_slice_updates_per_s=inst.ring_slices / dt,
                              us_per_slice=dt / inst.n_xi * 1e6)
+        wake.wake_set_cluster(0, 0)
         out["large_instances"] = big
     if not args.no_cpu:
         log("cpu baseline")
