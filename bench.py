@@ -218,8 +218,6 @@ def main():
     tplain = time.perf_counter() - tp
     plain_value = sum(i.ring_slices for i in sample) / tplain
 
-    flops = ALG_FLOPS_PER_RING_SLICE * work
-    achieved = flops / avg_kernel_s
     # measured HBM traffic of one march dispatch of this workload, if the
     # counters were taken on the current marcher sources
     from paper_2603_16623_amd.profile_summary import read_traffic
@@ -228,14 +226,23 @@ def main():
     traffic = None
     if tr is not None and tr.get("workload") == workload:
         traffic = float(tr["fetch_bytes_per_dispatch"]) + float(tr["write_bytes_per_dispatch"])
-    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP64_VECTOR / 1e12,
-                unit="TFLOP/s", frac=achieved / PEAK_FP64_VECTOR, traffic=traffic,
+    # The march moves several times its algorithmic bytes (two passes over
+    # the rings, the slice scratch and the ion records) and its measured HBM
+    # traffic runs at the larger part of the HBM peak, so the HBM roof is the
+    # one that bounds it; the FP64 figure is reported beside it.
+    alg_bytes = ALG_BYTES_PER_RING_SLICE * work
+    achieved = alg_bytes / avg_kernel_s
+    flops = ALG_FLOPS_PER_RING_SLICE * work
+    roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                frac=achieved / PEAK_HBM, traffic=traffic,
                 kernel="wake_march_kernel", kernel_ms=float(np.mean(kernel_ms)),
-                alg_flops_per_ring_slice=ALG_FLOPS_PER_RING_SLICE,
-                hbm_alg_GBps=ALG_BYTES_PER_RING_SLICE * work / avg_kernel_s / 1e9,
+                alg_bytes_per_ring_slice=ALG_BYTES_PER_RING_SLICE,
+                traffic_B_per_ring_slice=None if traffic is None else traffic / work,
                 hbm_measured_GBps=None if traffic is None else traffic / avg_kernel_s / 1e9,
-                traffic_B_per_ring_slice=None if traffic is None else traffic / work)
-
+                hbm_measured_frac=None if traffic is None else traffic / avg_kernel_s / PEAK_HBM,
+                alg_flops_per_ring_slice=ALG_FLOPS_PER_RING_SLICE,
+                fp64_TFLOPs=flops / avg_kernel_s / 1e12,
+                fp64_frac=flops / avg_kernel_s / PEAK_FP64_VECTOR)
     out = {
         "metric": METRIC,
         "value": value,
