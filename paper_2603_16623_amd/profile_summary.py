@@ -19,7 +19,7 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MARCH_SOURCES = ["wake_march.hip", "wake_device.h", "wake_common.h"]
+MARCH_SOURCES = ["wake_march.hip", "wake_device.h", "wake_common.h", "wake_cluster.h"]
 
 
 def source_digest() -> str:
