@@ -1218,7 +1218,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
   const bool has_laser = I.has_laser != 0;
   // ion interval nodes in LDS (float) for the interval search of pass B;
   // read there after the slice-head scan's barriers
-  if (lds_keys)
+  const bool lds_ion = N <= KCAP;      // the interval nodes fit the LDS table
+  if (lds_ion)
     for (int j = tid; j <= N; j += NT) s_ion[j] = (float)IV.R[j * WAKE_ION_REC + IR_LO];
 
   // ln rho of every ring and the per-thread sums of (w, w ln rho)
@@ -1375,7 +1376,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
     int jn = 0;
     if (cnt > 0) {
       x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
-      jn = lds_keys ? ion_find(s_ion, N, x_ru.x, hh_hint(x_hh)) : hh_hint(x_hh);
+      jn = lds_ion ? ion_find(s_ion, N, x_ru.x, hh_hint(x_hh)) : hh_hint(x_hh);
       ion_load(IV, jn, x_q);
     }
     #pragma unroll 1
@@ -1397,7 +1398,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       }
       if (k + 1 < cnt) {
         x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
-        jn = lds_keys ? ion_find(s_ion, N, x_ru.x, h) : hh_hint(x_hh);
+        jn = lds_ion ? ion_find(s_ion, N, x_ru.x, h) : hh_hint(x_hh);
         ion_load(IV, jn, x_q);
       }
       const double irho = rcp_nr(rho);
