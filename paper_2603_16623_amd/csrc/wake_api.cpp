@@ -21,6 +21,8 @@ int g_cl_rings = 0;  // rings per thread of cooperative instances (0: 8)
 int g_cl_min = 0;    // ring count from which instances are cooperative (0: beyond one workgroup's LDS keys)
 
 
+}  // namespace
+
 // Layout of an instance of N rings on nt-thread workgroups: one workgroup
 // with C = ceil(N / nt) rings per thread while the keys of every position
 // fit its LDS (and N is at most the cooperative threshold), else G members
@@ -36,6 +38,8 @@ void layout_of(int N, int nt, int* C, int* G) {
   *C = (N + nt - 1) / nt;
   *G = 1;
 }
+
+namespace {
 
 static size_t pow2_at_least(size_t n) {
   size_t p = 1;

@@ -1251,6 +1251,9 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
     }
   }
+  // sums of the thread's own rings in the push's order (what a fix-up that
+  // leaves the chunk with its own rings falls back to)
+  dd sw_push = sw, swl_push = swl;
   int n = I.first;
   int end = I.first + I.count;
   if (n < end) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
@@ -1327,7 +1330,13 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       bool changed = false;
       for (int k = 0; k < cnt; ++k)
         changed |= WAKE_FOREIGN(lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[goff + k * NT + tid]);
-      if (changed) chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
+      // (a chunk back to its own rings after a later round takes the push's sums again)
+      if (changed) {
+        chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
+      } else {
+        sw = sw_push;
+        swl = swl_push;
+      }
       if (restage) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
       dis = still;
       continue;
@@ -1652,6 +1661,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       ident = true;
       sw = sw2;
       swl = swl2;
+      sw_push = sw2;
+      swl_push = swl2;
     }
     ++n;
   }

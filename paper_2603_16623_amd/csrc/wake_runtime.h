@@ -52,6 +52,8 @@ int dev_err(hipError_t e);
 int drain(wake_ctx* c);
 // persistent grid for nt-thread workgroups over n instances
 int march_grid(int nt, int n_insts, int dev);
+// layout of an instance (rings per thread C, workgroups G) on nt threads
+void layout_of(int N, int nt, int* C, int* G);
 // first task of each descriptor (members of a cooperative instance are G
 // consecutive tasks); returns the number of tasks
 int assign_tasks(std::vector<WakeInst>& v);

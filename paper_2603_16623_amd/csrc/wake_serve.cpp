@@ -204,10 +204,18 @@ static int retire(wake_server* s, size_t i, int32_t brk) {
 extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_queued, int32_t* n_done) {
   if (!s) return WAKE_EINVAL;
   HIP_TRY(hipSetDevice(s->device));
-  // admission, in arrival order, by device footprint
+  // admission, in arrival order, by device footprint and by workgroups: the
+  // resident requests' workgroups (G each) must fit one persistent launch,
+  // so that every request marches for the whole step
+  const int slots = march_grid(s->cfg.threads, 1 << 30, s->device);
+  int used = 0;
+  for (const Active& a : s->active) used += a.ctx->I.G;
   while (!s->queue.empty()) {
     if (s->cfg.max_active > 0 && (int)s->active.size() >= s->cfg.max_active) break;
     Request& q = s->queue.front();
+    int qc = 0, qg = 1;
+    layout_of((int)q.r0.size(), s->cfg.threads, &qc, &qg);
+    if (used + qg > slots && !s->active.empty()) break;
     const bool fits = s->in_use + q.footprint <= s->cfg.device_bytes;
     if (!fits && !s->active.empty()) break;
     wake_ctx* c = nullptr;
@@ -223,6 +231,7 @@ extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_qu
     }
     s->active.push_back({q.ticket, c, q.footprint});
     s->in_use += q.footprint;
+    used += c->I.G;
     s->queue.pop_front();
   }
   int32_t retired = 0;
@@ -231,8 +240,9 @@ extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_qu
     // each request's share of it (workgroups that fit / resident requests)
     int64_t budget = 0;
     if (s->cfg.step_us > 0) {
-      const int grid = march_grid(s->cfg.threads, (int)s->active.size(), s->device);
-      const double share = std::min(1.0, (double)grid / (double)s->active.size());
+      int tasks = 0;
+      for (const Active& a : s->active) tasks += a.ctx->I.G;
+      const double share = std::min(1.0, (double)slots / (double)tasks);
       budget = std::max<int64_t>(1, (int64_t)(s->cfg.step_us * 100.0 * share));   // 100 MHz ticks
     }
     std::vector<WakeInst> v;

@@ -178,3 +178,29 @@ def test_cluster_split_and_batch_bitwise(wk):
     b.close()
     for x in solvers:
         x.close()
+
+
+def test_cluster_multi_round_fixups_match_split_launches(wk):
+    """A 9000-ring instance whose order fix-ups at some slices take more than
+    one block round (rings that return to their own chunk after a later
+    round must get their own sums back): the one-launch march is bitwise the
+    march split into launches of four slices, whose prologues order from
+    scratch."""
+    wk.wake_set_tiling(512, 0)
+    wk.wake_set_cluster(0, 0)
+    rng = np.random.default_rng(61)
+    sizes = [(300, 90), (1500, 60), (777, 130), (64, 40), (2100, 75), (9000, 30)]
+    inst = [W.batched_instance(rng, n, n_xi, n_drv=2500, n_wit=800, r_max=4.0) for n, n_xi in sizes][-1]
+    _say("cooperative multi-round fix-ups, 9000 rings")
+    a = wk.WakeSolver.from_instance(inst, record_stride=1)
+    assert a.layout()[0] == 3
+    a.wake_solve(0, inst.n_xi)
+    b = wk.WakeSolver.from_instance(inst, record_stride=1)
+    for n in range(0, inst.n_xi, 4):
+        b.wake_solve(n, min(4, inst.n_xi - n))
+    for n in range(inst.n_xi):
+        fa, fb = a.wake_fields(n), b.wake_fields(n)
+        for q in FIELDS + ("rho",):
+            assert np.array_equal(fa[q], fb[q]), (n, q)
+    a.close()
+    b.close()
