@@ -236,6 +236,42 @@ __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double i
     if (sl[j] >= 0) perm[sl[j]] = (int32_t)(uint32_t)(k[j] & 0xffffffffull);
 }
 
+// Whether this thread's positions (and the position after them) are out of
+// order in the cooperative order perm.  Slots are read eight at a time, then
+// their keys, so each batch costs two rounds of independent loads.
+template <int NT>
+__device__ __forceinline__ int cl_chunk_disordered(const WakeInst& I, int goff, int cnt, int C, int P,
+                                                   double iC, double iP) {
+  const int tid = threadIdx.x;
+  const int N = I.N;
+  if (cnt <= 0) return 0;
+  const int p0 = goff + tid * C;
+  const int m = p0 + cnt < N ? cnt + 1 : cnt;
+  int bad = 0;
+  double pr = -INFINITY;
+  int32_t pi = -1;
+  #pragma unroll 1
+  for (int k0 = 0; k0 < m; k0 += 8) {
+    int src[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + j;
+      src[j] = -1;
+      if (k < m) src[j] = I.perm[k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP)];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (src[j] < 0) continue;
+      const double r = I.gk_r[src[j]];
+      const int32_t id = I.gk_i[src[j]];
+      if (k0 + j > 0 && key_lt(r, id, pr, pi)) bad = 1;
+      pr = r;
+      pi = id;
+    }
+  }
+  return bad;
+}
+
 // Fallback order of a cooperative instance: a bitonic sort of every position
 // in device memory (keys copied out in position order, padded to the next
 // power of two with keys above every ring), one barrier per network stage.
@@ -308,24 +344,7 @@ __device__ __noinline__ bool cl_fix(const WakeInst& I, Cluster& cl, double* s_x,
       cl_sort_block<NT>(128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
     if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
     // in order? this thread's positions and the position after them
-    int bad = 0;
-    if (cnt > 0) {
-      const int p0 = goff + tid * C;
-      int src = I.perm[goff + tid];
-      double pr = I.gk_r[src];
-      int32_t pi = I.gk_i[src];
-      const int m = p0 + cnt < N ? cnt + 1 : cnt;
-      #pragma unroll 1
-      for (int k = 1; k < m; ++k) {
-        const int sl = k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP);
-        src = I.perm[sl];
-        const double r = I.gk_r[src];
-        const int32_t id = I.gk_i[src];
-        if (key_lt(r, id, pr, pi)) bad = 1;
-        pr = r;
-        pi = id;
-      }
-    }
+    int bad = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
     bad = __syncthreads_or(bad);
     if (!cl_gather<1>(cl, Pack<1>{{(double)bad}}, s_x, s_ok)) return false;
     double any = 0.0;
@@ -364,24 +383,7 @@ __device__ __noinline__ bool cl_fix_round(const WakeInst& I, Cluster& cl, double
   for (int b = gw; 128 + b * 256 < N; b += nw)
     cl_sort_block<NT>(128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
   if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
-  int b_ = 0;
-  if (cnt > 0) {
-    const int p0 = goff + tid * C;
-    int src = I.perm[goff + tid];
-    double pr = I.gk_r[src];
-    int32_t pi = I.gk_i[src];
-    const int m = p0 + cnt < N ? cnt + 1 : cnt;
-    #pragma unroll 1
-    for (int k = 1; k < m; ++k) {
-      const int sl = k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP);
-      src = I.perm[sl];
-      const double r = I.gk_r[src];
-      const int32_t id = I.gk_i[src];
-      if (key_lt(r, id, pr, pi)) b_ = 1;
-      pr = r;
-      pi = id;
-    }
-  }
+  const int b_ = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
   *bad = __syncthreads_or(b_);
   return true;
 }
