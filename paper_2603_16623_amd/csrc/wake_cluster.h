@@ -5,32 +5,77 @@
 // totals, and a few more times when the order needs fixing; the order
 // fix-up works on keys and permutation in device memory.
 //
-// Barrier.  Each member publishes a pack (agent-scope stores), releases
-// (agent-scope fence: the XCD's L2 writes back what this workgroup wrote),
-// counts itself in, waits until every member of this round has, acquires
-// (fence), and reads all packs.  Packs alternate between two buffers by
-// round; a member writes buffer b again only two rounds later, when every
-// member has finished reading it.  A wait that exceeds its time bound sets
-// the give-up word, and every member then leaves the instance (reported as
-// a device error), so no wave can wait forever.
+// Barrier.  Each member publishes a pack (agent-scope atomic stores, which
+// write through to the point where all XCDs meet), waits for those stores to
+// complete, counts itself in, waits until every member of this round has, and
+// reads all packs with agent-scope atomic loads.  Packs alternate between two
+// buffers by round; a member writes buffer b again only two rounds later,
+// when every member has finished reading it.  The per-slice exchanges carry
+// nothing but their packs and take no cache maintenance.  The fenced form,
+// used by the order fix-up, also hands over plain device-memory data (keys,
+// permutation, ring state that changes member): a release fence before the
+// arrival writes the XCD's L2 back, an acquire fence after the wait drops
+// its stale lines; both act on the whole L2 of the XCD, so they are kept off
+// the every-slice path.
+//
+// Wait bounds.  Once every member of the instance has started, a wait longer
+// than WAKE_CL_WAIT_TICKS sets the give-up word, and every member then leaves
+// the instance (reported as a device error).  Before that, a member waits for
+// workgroups of the launch to finish earlier tasks and take up the missing
+// members (the queue hands out tasks in order, so they come): the bound then
+// counts from the last task taken from the queue and is WAKE_CL_START_TICKS.
+// No wave can wait forever.
 #pragma once
 #include "wake_common.h"
 #include "wake_device.h"
 
-#define WAKE_CL_WAIT_TICKS 200000000ll    // 2 s of the 100 MHz clock
+#define WAKE_CL_WAIT_TICKS 200000000ll     // 2 s of the 100 MHz clock
+#define WAKE_CL_START_TICKS 3000000000ll   // 30 s without a task taken
 
 struct Cluster {
   int g, G;      // this member, members
   int round;     // barriers passed in this launch
   double* xd;    // [2][G][16]
-  int32_t* xc;   // [0] arrivals, [1] give-up
+  int32_t* xc;   // [0] arrivals, [1] give-up, [2] members started
+  const int32_t* queue;   // task queue counter of the launch
 };
+
+// Counts the member in as started (once per launch, before its first
+// exchange).
+__device__ __forceinline__ void cl_start(Cluster& cl) {
+  if (threadIdx.x == 0) atomicAdd(cl.xc + 2, 1);
+}
+
+// Thread 0 of a member: counts the member in and waits (bounded) until the
+// round's arrivals reach target.  1 when they did, 0 when a member gave up.
+__device__ __noinline__ int cl_wait(int32_t* xc, const int32_t* queue, int target, int G) {
+  atomicAdd(xc, 1);
+  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  bool all_in = false;
+  int q_last = -1;
+  for (;;) {
+    if (__hip_atomic_load(xc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
+    if (__hip_atomic_load(xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return 1;
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    if (!all_in) {
+      all_in = __hip_atomic_load(xc + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G;
+      const int q = __hip_atomic_load(queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (all_in || q != q_last) { q_last = q; t0 = now; }
+    }
+    if ((int64_t)(now - t0) > (all_in ? WAKE_CL_WAIT_TICKS : WAKE_CL_START_TICKS)) {
+      __hip_atomic_store(xc + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
 
 // All-gather of NF doubles per member; member m's pack lands at s_x[m * NF].
 // Every thread of every member calls it at the same point of the march.
-// Returns false when a member gave up.
-template <int NF>
-__device__ __noinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, double* s_x, int* s_ok) {
+// FENCED also publishes the plain device-memory writes before it and makes
+// the others' visible after it.  Returns false when a member gave up.
+template <int NF, bool FENCED = true>
+__device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, double* s_x, int* s_ok) {
   static_assert(NF <= 16, "exchange packs hold 16 doubles");
   const int buf = cl.round & 1;
   __syncthreads();                                   // this member's writes of the round are issued
@@ -38,21 +83,16 @@ __device__ __noinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, double
     double* slot = cl.xd + ((size_t)buf * cl.G + cl.g) * 16;
 #pragma unroll
     for (int i = 0; i < NF; ++i) __hip_atomic_store(slot + i, mine.v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    atomicAdd(cl.xc, 1);
-    const int target = cl.G * (cl.round + 1);
-    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    int ok = 0;
-    for (;;) {
-      if (__hip_atomic_load(cl.xc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      if (__hip_atomic_load(cl.xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) { ok = 1; break; }
-      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > WAKE_CL_WAIT_TICKS) {
-        __hip_atomic_store(cl.xc + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
+    if (FENCED) {
+      __threadfence();
+    } else {
+      // the pack's write-through stores complete before the arrival
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    __threadfence();
+    const int ok = cl_wait(cl.xc, cl.queue, cl.G * (cl.round + 1), cl.G);
+    if (FENCED) __threadfence();
     *s_ok = ok;
   }
   __syncthreads();
@@ -237,16 +277,18 @@ __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double i
 }
 
 // Whether this thread's positions (and the position after them) are out of
-// order in the cooperative order perm.  Slots are read eight at a time, then
-// their keys, so each batch costs two rounds of independent loads.
+// order in the cooperative order perm; with within, the position after the
+// member's last one (the next member's first) is left out.  Slots are read
+// eight at a time, then their keys, so each batch costs two rounds of
+// independent loads.
 template <int NT>
 __device__ __forceinline__ int cl_chunk_disordered(const WakeInst& I, int goff, int cnt, int C, int P,
-                                                   double iC, double iP) {
+                                                   double iC, double iP, bool within = false) {
   const int tid = threadIdx.x;
   const int N = I.N;
   if (cnt <= 0) return 0;
   const int p0 = goff + tid * C;
-  const int m = p0 + cnt < N ? cnt + 1 : cnt;
+  const int m = p0 + cnt < (within ? min(N, goff + P) : N) ? cnt + 1 : cnt;
   int bad = 0;
   double pr = -INFINITY;
   int32_t pi = -1;
@@ -276,7 +318,7 @@ __device__ __forceinline__ int cl_chunk_disordered(const WakeInst& I, int goff, 
 // in device memory (keys copied out in position order, padded to the next
 // power of two with keys above every ring), one barrier per network stage.
 template <int NT>
-__device__ __noinline__ bool cl_bitonic(const WakeInst& I, Cluster& cl, double* s_x, int* s_ok) {
+__device__ __noinline__ int cl_bitonic(const WakeInst& I, Cluster cl, double* s_x, int* s_ok) {
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
   const int P2 = N <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)(N - 1)));
@@ -293,7 +335,7 @@ __device__ __noinline__ bool cl_bitonic(const WakeInst& I, Cluster& cl, double* 
       I.bt_s[p] = -1;
     }
   }
-  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   for (int kk = 2; kk <= P2; kk <<= 1) {
     for (int d = kk >> 1; d > 0; d >>= 1) {
       const int ld = __builtin_ctz((unsigned)d);
@@ -309,11 +351,11 @@ __device__ __noinline__ bool cl_bitonic(const WakeInst& I, Cluster& cl, double* 
           I.bt_s[a] = sb; I.bt_s[b] = sa;
         }
       }
-      if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+      if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
     }
   }
   for (int p = gt; p < N; p += nth) I.perm[cl_slot<NT>(p, C, P, iC, iP)] = I.bt_s[p];
-  return cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok);
+  return cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok) ? cl.round : -1;
 }
 
 // Order fix-up of a cooperative instance from its keys by slot (gk_r, gk_i):
@@ -323,7 +365,7 @@ __device__ __noinline__ bool cl_bitonic(const WakeInst& I, Cluster& cl, double* 
 // order checked across all positions, at most two such rounds, then the
 // bitonic fallback.  Returns false when a member gave up.
 template <int NT>
-__device__ __noinline__ bool cl_fix(const WakeInst& I, Cluster& cl, double* s_x, int* s_ok) {
+__device__ __noinline__ int cl_fix(const WakeInst& I, Cluster cl, double* s_x, int* s_ok) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
@@ -331,39 +373,40 @@ __device__ __noinline__ bool cl_fix(const WakeInst& I, Cluster& cl, double* s_x,
   const int Ng = min(P, N - goff);
   const int cnt = max(0, min(C, Ng - tid * C));
   for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
-  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   constexpr int NW = NT / 64;
-  const int gw = cl.g * NW + (tid >> 6), nw = cl.G * NW;
+  const int wave = tid >> 6;
   #pragma unroll 1
   for (int round = 0; round < 2; ++round) {
     #pragma unroll 1
-    for (int b = gw; b * 256 < N; b += nw) cl_sort_block<NT>(b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
-    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+    for (int b = wave; b * 256 < Ng; b += NW) cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
     #pragma unroll 1
-    for (int b = gw; 128 + b * 256 < N; b += nw)
-      cl_sort_block<NT>(128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
-    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+    for (int b = wave; 128 + b * 256 < Ng; b += NW)
+      cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
     // in order? this thread's positions and the position after them
     int bad = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
     bad = __syncthreads_or(bad);
-    if (!cl_gather<1>(cl, Pack<1>{{(double)bad}}, s_x, s_ok)) return false;
+    if (!cl_gather<1>(cl, Pack<1>{{(double)bad}}, s_x, s_ok)) return -1;
     double any = 0.0;
     for (int m = 0; m < cl.G; ++m) any += s_x[m];
-    if (any == 0.0) return true;
+    if (any == 0.0) return cl.round;
   }
   return cl_bitonic<NT>(I, cl, s_x, s_ok);
 }
 
-// One in-loop round of the cooperative fix-up (the first from the identity
-// order of the pushed rings): the blocks at offsets 0, 256,
-// ... lie inside one member's range (member ranges are multiples of 256
-// positions), so each member sorts its own after a local barrier; the
-// blocks at 128, 384, ... straddle members and go between two barriers.
-// *bad reports whether this member's positions (and the first of the next
-// member) are still out of order; the next slice-head exchange sums it.
+// One in-loop round of the cooperative fix-up over all members (first: this
+// member's order starts from the identity of the pushed rings).  Each member
+// sorts the blocks at offsets 0, 256, ... of its own range (member ranges are
+// multiples of 256 positions) after a local barrier, then, between two
+// barriers of all members, the blocks at 128, 384, ... that start in its
+// range; the last of these straddles the next member.  Returns -1 when a
+// member gave up, else twice the barrier count plus whether this member's
+// positions (and the first of the next member) are still out of order; the
+// next slice-head exchange sums that flag.
 template <int NT>
-__device__ __noinline__ bool cl_fix_round(const WakeInst& I, Cluster& cl, double* s_x, int* s_ok, bool first,
-                                          int* bad) {
+__device__ __noinline__ int cl_fix_round(const WakeInst& I, Cluster cl, double* s_x, int* s_ok, bool first) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
@@ -371,19 +414,50 @@ __device__ __noinline__ bool cl_fix_round(const WakeInst& I, Cluster& cl, double
   const int Ng = min(P, N - goff);
   const int cnt = max(0, min(C, Ng - tid * C));
   constexpr int NW = NT / 64;
+  const int wave = tid >> 6;
   if (first)           // later rounds continue from the order the previous one left
     for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
   __syncthreads();
   #pragma unroll 1
-  for (int b = (tid >> 6); b * 256 < Ng; b += NW)
+  for (int b = wave; b * 256 < Ng; b += NW)
     cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
-  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
-  const int gw = cl.g * NW + (tid >> 6), nw = cl.G * NW;
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   #pragma unroll 1
-  for (int b = gw; 128 + b * 256 < N; b += nw)
-    cl_sort_block<NT>(128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
-  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return false;
+  for (int b = wave; 128 + b * 256 < Ng; b += NW)
+    cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   const int b_ = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
-  *bad = __syncthreads_or(b_);
-  return true;
+  return 2 * cl.round + (__syncthreads_or(b_) ? 1 : 0);
+}
+
+// One member-local round of the in-loop fix-up, for disorder inside this
+// member's range while the order across member boundaries holds: the blocks
+// at offsets 0, 256, ... and then 128, 384, ... of the member's own range,
+// less the one that straddles the next member, between the member's own
+// barriers; the member's keys and order are its own writes, so no exchange
+// is needed.  Returns whether the member's positions are still out of order.
+template <int NT>
+__device__ __noinline__ int cl_fix_local(const WakeInst& I, int g, bool first) {
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C, P = C * NT;
+  const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
+  const int goff = g * P;
+  const int Ng = min(P, N - goff);
+  const int cnt = max(0, min(C, Ng - tid * C));
+  const int lim = goff + Ng == N ? Ng : Ng - 256;   // phase-two blocks starting below lim lie inside
+  constexpr int NW = NT / 64;
+  const int wave = tid >> 6;
+  if (first)
+    for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
+  __syncthreads();
+  #pragma unroll 1
+  for (int b = wave; b * 256 < Ng; b += NW)
+    cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+  __syncthreads();
+  #pragma unroll 1
+  for (int b = wave; 128 + b * 256 < lim; b += NW)
+    cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+  __syncthreads();
+  const int b_ = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP, true);
+  return __syncthreads_or(b_);
 }

@@ -1116,7 +1116,7 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
 // positions and slots start at goff = member * C * NT, and the slice scans
 // and the order fix-up span all members.
 template <int NT, bool CL>
-__device__ __forceinline__ void march(const WakeInst& I, int member, unsigned char* smem) {
+__device__ __forceinline__ void march(const WakeInst& I, int member, const int32_t* queue, unsigned char* smem) {
   constexpr int NW = NT / 64;
   constexpr int CMAX = MarchLds<NT>::CMAX;
   constexpr int KCAP = MarchLds<NT>::KCAP;
@@ -1160,6 +1160,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
   cl.round = 0;
   cl.xd = I.xd;
   cl.xc = I.xc;
+  cl.queue = queue;
+  if (CL) cl_start(cl);
   double* const s_x = s_kr;                                   // gathered packs (cooperative)
   int* const s_ok = reinterpret_cast<int*>(s_misc + 62);
 
@@ -1181,10 +1183,12 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       I.gk_r[sl] = st_rho(SB, sl);
       I.gk_i[sl] = WAKE_ID(st_hs(SB, sl));
     }
-    if (!cl_fix<NT>(I, cl, s_x, s_ok)) {
+    const int r = cl_fix<NT>(I, cl, s_x, s_ok);
+    if (r < 0) {
       if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
       return;
     }
+    cl.round = r;
     ident = false;
     for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(gperm[goff + k * NT + tid]);
   } else if (lds_keys) {
@@ -1259,11 +1263,13 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
   if (n < end) stage_slice<NT>(I, n, s_misc, s_br, s_bc);
   double bad = 0.0, dis = 0.0;
   int fix_rounds = 0;          // consecutive fix-up rounds at this slice head
+  int cl_rounds = 0;           // of which over all members (cooperative)
   int unpushed = cur;          // buffer with the unpushed state of slice n-1
 
   for (;;) {
     // ---- Gauss/log prefix sum_{k<i} (w_k, w_k ln rho_k); flags of slice n-1 ----
     Pack<6> t6;
+    double my_dis = 0.0, bnd = 0.0;   // cooperative: this member's disorder, member boundaries out of order
     Pack<6> pre = block_prefix<NT, 6, SliceHeadOp, false>(
         Pack<6>{{sw.hi, sw.lo, swl.hi, swl.lo, bad, dis}}, Pack<6>{{0, 0, 0, 0, 0, 0}},
         SliceHeadOp(), s_scanA, t6);
@@ -1283,14 +1289,15 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
         mine.v[10] = (budget > 0 && n > I.first &&
                       (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget) ? 1.0 : 0.0;
       }
-      if (!cl_gather<11>(cl, mine, s_x, s_ok)) {
+      if (!cl_gather<11, false>(cl, mine, s_x, s_ok)) {
         if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
         return;
       }
       Pack<6> pg;
+      my_dis = t6.v[5];
       cl_prefix<6, 11>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
       pre = SliceHeadOp()(pg, pre);
-      double bnd = 0.0, stop = 0.0;
+      double stop = 0.0;
       for (int m = 0; m < cl.G; ++m) {
         stop += s_x[m * 11 + 10];
         if (m + 1 < cl.G &&
@@ -1309,16 +1316,37 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       bool restage = true;    // the general fix-ups use the beam-table area of LDS
       double still = 0.0;      // cooperative: this member still out of order after the round
       if (CL) {
-        // block rounds; after two that leave disorder, the full sort
-        int b = 0;
-        const bool ok = fix_rounds < 2 ? cl_fix_round<NT>(I, cl, s_x, s_ok, fix_rounds == 0, &b) : cl_bitonic<NT>(I, cl, s_x, s_ok);
-        if (!ok) {
-          if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
-          return;
+        // disorder inside members only: up to two member-local block rounds
+        // (members in order skip them); across member boundaries, or left
+        // over, block rounds over all members; after two of these that leave
+        // disorder, the full sort
+        restage = false;
+        if (bnd == 0.0 && fix_rounds < 2 && cl_rounds == 0) {
+          if (my_dis == 0.0) {
+            ++fix_rounds;
+            dis = 0.0;
+            continue;
+          }
+          still = cl_fix_local<NT>(I, member, ident) ? 1.0 : 0.0;
+        } else {
+          int r = -1;
+          if (cl_rounds < 2) {
+            r = cl_fix_round<NT>(I, cl, s_x, s_ok, ident);
+            if (r >= 0) {
+              still = (r & 1) ? 1.0 : 0.0;
+              r >>= 1;
+            }
+          } else {
+            r = cl_bitonic<NT>(I, cl, s_x, s_ok);
+          }
+          if (r < 0) {
+            if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+            return;
+          }
+          cl.round = r;
+          ++cl_rounds;
         }
         ++fix_rounds;
-        still = b ? 1.0 : 0.0;
-        restage = false;
       } else if (lds_keys) {
         restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm);
         if (restage) fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
@@ -1342,6 +1370,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       continue;
     }
     fix_rounds = 0;
+    cl_rounds = 0;
     const double psi_axis = dd_round(dd_sub({t6.v[2], t6.v[3]}, tot0));
     const bool do_push = n < I.n_xi - 1;
     const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
@@ -1472,7 +1501,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
       Pack<10> mine;
 #pragma unroll
       for (int i = 0; i < 5; ++i) { mine.v[i] = gt.v[i]; mine.v[5 + i] = ht.v[i]; }
-      if (!cl_gather<10>(cl, mine, s_x, s_ok)) {
+      if (!cl_gather<10, false>(cl, mine, s_x, s_ok)) {
         if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
         return;
       }
@@ -1499,7 +1528,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
         Pack<1>{{le}}, Pack<1>{{0.0}}, SumOp<1>(), Pack<1>{{lds}}, Pack<1>{{0.0}}, SumOp<1>(),
         s_scanA, ep, et, dsf, dt);
     if (CL) {
-      if (!cl_gather<2>(cl, Pack<2>{{et.v[0], dt.v[0]}}, s_x, s_ok)) {
+      if (!cl_gather<2, false>(cl, Pack<2>{{et.v[0], dt.v[0]}}, s_x, s_ok)) {
         if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
         return;
       }
@@ -1675,8 +1704,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, unsigned ch
 // the cooperative march as a function of its own (its registers stay out of
 // the single-workgroup march, which is inlined into the kernel)
 template <int NT>
-__device__ __noinline__ void march_member(const WakeInst& I, int member, unsigned char* smem) {
-  march<NT, true>(I, member, smem);
+__device__ __noinline__ void march_member(const WakeInst& I, int member, const int32_t* queue, unsigned char* smem) {
+  march<NT, true>(I, member, queue, smem);
 }
 
 #ifndef WAKE_WAVES_PER_EU
@@ -1702,8 +1731,8 @@ void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_ta
     }
     const WakeInst& I = insts[lo];
     if (I.nt == NT) {
-      if (I.G > 1) march_member<NT>(I, idx - I.task0, smem);
-      else march<NT, false>(I, 0, smem);
+      if (I.G > 1) march_member<NT>(I, idx - I.task0, counter, smem);
+      else march<NT, false>(I, 0, counter, smem);
     }
     __syncthreads();
   }
@@ -1716,7 +1745,7 @@ __global__ void counter_zero_kernel(int32_t* p) {
 // barrier words of the cooperative instances of a launch start at zero
 __global__ void cluster_reset_kernel(const WakeInst* __restrict__ insts, int n_insts) {
   for (int i = threadIdx.x; i < n_insts; i += blockDim.x)
-    if (insts[i].G > 1) { insts[i].xc[0] = 0; insts[i].xc[1] = 0; }
+    if (insts[i].G > 1) { insts[i].xc[0] = 0; insts[i].xc[1] = 0; insts[i].xc[2] = 0; }
 }
 
 // ---------------------------------------------------------------------------
