@@ -58,7 +58,7 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
   d += 2 * RC_CHUNKS * S;                   // constants by home slot
   d += WAKE_ION_REC * (size_t)(N + 1);      // ion interval records
   d += 4;                                   // tot0, Q
-  d += 4 * RS_CHUNKS * S;                   // state, two buffers
+  d += 2 * RS_DOUBLES * S;                  // state, two buffers
   d += (2 * SC_CHUNKS + 2) * S;             // slice scratch, laser terms
   d += 1 * S;                               // fix-up: suffix minimum
   i += 4 * S;                               // fix-up: order, prefix max id, flags, run starts
@@ -192,7 +192,7 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   I.cst = A.take<double>((size_t)2 * RC_CHUNKS * S);
   I.ion = A.take<double>((size_t)WAKE_ION_REC * (N + 1));
   I.tot0 = A.take<double>(4);
-  for (int b = 0; b < 2; ++b) I.st[b] = A.take<double>((size_t)2 * RS_CHUNKS * S);
+  for (int b = 0; b < 2; ++b) I.st[b] = A.take<double>((size_t)RS_DOUBLES * S);
   I.sc = A.take<double>((size_t)2 * SC_CHUNKS * S);
   I.a2 = A.take<double>(S);
   I.da2 = A.take<double>(S);

@@ -171,6 +171,13 @@ struct PV {
     *reinterpret_cast<WAKE_GLOBAL double*>(reinterpret_cast<WAKE_GLOBAL char*>(g.p) + (c * ps + i) * 16u +
                                           half * 8u) = v;
   }
+  // word i of the plane of 8-B words that starts where chunk c would
+  __device__ __forceinline__ double ldw(uint32_t c, uint32_t i) const {
+    return reinterpret_cast<WAKE_GLOBAL const double*>(g.p)[2u * c * ps + i];
+  }
+  __device__ __forceinline__ void stw(uint32_t c, uint32_t i, double v) const {
+    reinterpret_cast<WAKE_GLOBAL double*>(g.p)[2u * c * ps + i] = v;
+  }
 };
 __device__ __forceinline__ PV pview(const double* p, uint32_t ps) {
   PV v;
@@ -180,7 +187,7 @@ __device__ __forceinline__ PV pview(const double* p, uint32_t ps) {
 }
 // sort keys of the ring at slot sl of a state buffer
 __device__ __forceinline__ double st_rho(const PV& S, unsigned sl) { return S.ldh(RS_RU, sl, 0); }
-__device__ __forceinline__ int32_t st_hs(const PV& S, unsigned sl) { return hh_hs(S.ldh(RS_HH, sl, 0)); }
+__device__ __forceinline__ int32_t st_hs(const PV& S, unsigned sl) { return hh_hs(S.ldw(RS_HH, sl)); }
 
 // ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
 // rounding scales with the ring's displacement, not with |ln rho| (the psi
@@ -341,6 +348,31 @@ __device__ __forceinline__ int count_below(const double* br, int lo, int m, doub
   }
   return a;
 }
+// The same count for radii met in descending order: hi is the count of the
+// previous (larger) radius when gallop is set.
+__device__ __forceinline__ int count_below_down(const double* br, int hi, int m, double r, bool gallop) {
+  int a, b;
+  if (gallop) {
+    if (hi <= 0 || br[hi - 1] < r) return hi;
+    b = hi - 1;                        // br[b] >= r: the answer is at most b
+    int step = 1;
+    for (;;) {
+      a = b - step;
+      if (a < 0) { a = 0; break; }
+      if (br[a] < r) { a += 1; break; }
+      b = a;
+      step <<= 1;
+    }
+  } else {
+    a = 0;
+    b = m;
+  }
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (br[mid] < r) a = mid + 1; else b = mid;
+  }
+  return a;
+}
 
 // ---------------------------------------------------------------------------
 // ring-set initialisation: weights, ln r0, ion interval records, state
@@ -354,6 +386,7 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
   const int tid = threadIdx.x;
   D2* cst = reinterpret_cast<D2*>(const_cast<double*>(I.cst));
   D2* st = reinterpret_cast<D2*>(I.st[0]);
+  double* st_w = I.st[0];
   const size_t PS = (size_t)I.G * I.C * I.nt;      // slots per plane
   double* R = const_cast<double*>(I.ion);
   double* consts = const_cast<double*>(I.tot0);
@@ -394,8 +427,8 @@ __global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double*
       const unsigned sl = slot_of(j, I.C, I.nt);
       st[RS_RU * PS + sl] = d2(r, 0.0);
       st[RS_F * PS + sl] = d2(0.0, 0.0);
-      st[RS_LN * PS + sl] = d2(0.0, 0.0);
-      st[RS_HH * PS + sl] = d2(hh_pack((int32_t)sl, j + 1), w);
+      st[RS_LN * PS + sl] = d2(lr.hi, lr.lo);
+      st_w[2 * RS_HH * PS + sl] = hh_pack((int32_t)sl, j + 1);
     }
     cS = dd_add(cS, {tot.v[0], tot.v[1]});
     cPT = dd_add(cPT, {tot.v[2], tot.v[3]});
@@ -1098,14 +1131,14 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
                                            bool ident, bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
   const int tid = threadIdx.x;
   const unsigned smax = ps - 1;
-  const PV SC = pview(I.st[cur], ps);
+  const PV SC = pview(I.st[cur], ps), KC = pview(I.cst, ps);
   sw = {0.0, 0.0};
   swl = {0.0, 0.0};
   #pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
     const unsigned sl = k * NT + tid;
     const unsigned s = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[goff + sl], smax);
-    const double w = SC.ldh(RS_HH, s, 1);
+    const double w = KC.ldh(RC_W, (unsigned)hh_hs(SC.ldw(RS_HH, s)), 0);
     const D2 l = SC.ld(RS_LN, s);
     sw = dd_add_d(sw, w);
     swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
@@ -1226,16 +1259,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   if (lds_ion)
     for (int j = tid; j <= N; j += NT) s_ion[j] = (float)IV.R[j * WAKE_ION_REC + IR_LO];
 
-  // ln rho of every ring and the per-thread sums of (w, w ln rho)
-  #pragma unroll 1
-  for (int k = 0; k < cnt; ++k) {
-    const unsigned sl = k * NT + tid;
-    const unsigned s = WAKE_SLOT(sl);
-    const PV SB = pview(I.st[cur], ps);
-    const unsigned hs = (unsigned)st_hs(SB, s);
-    const dd lr = ring_log(KC.ld(RC_R0, hs), KC.ld(RC_LN, hs), st_rho(SB, s));
-    SB.st(RS_LN, s, d2(lr.hi, lr.lo));
-  }
+  // The per-thread sums of (w, w ln rho), ln rho as the state carries it.
   // The sums in the order the march itself would have left them in (so that
   // a solve split over several launches is bitwise the one-launch solve):
   // chunks that took rings of another chunk in the fix-up sum forward, the
@@ -1249,7 +1273,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       const unsigned sl = k * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       const PV SB = pview(I.st[cur], ps);
-      const double w = SB.ldh(RS_HH, s, 1);
+      const double w = KC.ldh(RC_W, (unsigned)st_hs(SB, s), 0);
       const D2 l = SB.ld(RS_LN, s);
       sw = dd_add_d(sw, w);
       swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
@@ -1402,12 +1426,12 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (cnt > 0) {
       const unsigned s = WAKE_SLOT(tid);
       x_ru = Sc.ld(RS_RU, s); x_ln = Sc.ld(RS_LN, s);
-      x_hh = Sc.ldh(RS_HH, s, 0);
+      x_hh = Sc.ldw(RS_HH, s);
     }
     if (cnt > 1) {
       const unsigned s = WAKE_SLOT(NT + tid);
       z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
-      z_hh = Sc.ldh(RS_HH, s, 0);
+      z_hh = Sc.ldw(RS_HH, s);
     }
     // ion interval of the next ring: searched in LDS from the interval of
     // the ring before it (sorted order), its record requested one ring ahead
@@ -1432,7 +1456,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       if (k + 2 < cnt) {
         const unsigned s = WAKE_SLOT(sl + 2 * NT);
         z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
-        z_hh = Sc.ldh(RS_HH, s, 0);
+        z_hh = Sc.ldw(RS_HH, s);
       }
       if (k + 1 < cnt) {
         x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
@@ -1485,10 +1509,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       l1a += G.v[0] * s1b - G.v[2] * s1a;
       l1b += G.v[1] * s1b - G.v[3] * s1a;
       SCR.st(SC_PSI, goff + sl, d2(psi, dpsi));
-      SCR.st(SC_BB, goff + sl, d2(bb, hh_pack(hs, 0)));      // pass E takes the home slot from here
       if (has_laser) { A2.st(goff + sl, aa); DA2.st(goff + sl, dda); }
-      // the ring's home slot and hint move to its position slot in the next buffer
-      Sn.st(RS_HH, goff + sl, d2(hh_pack(hs, h), w));
+      // the ring's home slot and hint move to its position slot in the next
+      // buffer (pass E takes the home slot from there)
+      Sn.stw(RS_HH, goff + sl, hh_pack(hs, h));
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1557,58 +1581,56 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     double dis_l = 0.0;
     // loads run ahead (the march goes backward): the state of ring k-2 and
     // the constants of ring k-1 are requested while ring k is computed
-    D2 y_ru = d2(1.0, 0.0), y_f = d2(0.0, 0.0), y_ps = d2(0.0, 0.0);    // ring k-1
-    double y_bb = 0.0;
+    D2 y_ru = d2(1.0, 0.0), y_f = d2(0.0, 0.0), y_ps = d2(0.0, 0.0), y_ln = d2(0.0, 0.0);   // ring k-1
     int32_t y_hs = 0;
-    D2 v_ru = d2(1.0, 0.0), v_f = d2(0.0, 0.0), v_ps = d2(0.0, 0.0);    // ring k-2
-    double v_bb = 0.0;
+    D2 v_ru = d2(1.0, 0.0), v_f = d2(0.0, 0.0), v_ps = d2(0.0, 0.0), v_ln = d2(0.0, 0.0);   // ring k-2
     int32_t v_hs = 0;
-    D2 c_w = d2(1.0, 0.0), c_r = d2(1.0, 1.0), c_l = d2(0.0, 0.0);      // ring k-1
+    int bhi = 0;                // beam-table entries below the ring (pass B's count, met downward)
+    D2 c_w = d2(1.0, 0.0);      // ring k-1
     if (cnt > 0) {
       const unsigned sl = (cnt - 1) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
-      y_ru = Sc.ld(RS_RU, s); y_f = Sc.ld(RS_F, s);
+      y_ru = Sc.ld(RS_RU, s); y_f = Sc.ld(RS_F, s); y_ln = Sc.ld(RS_LN, s);
       y_ps = SCR.ld(SC_PSI, goff + sl);
-      const D2 b = SCR.ld(SC_BB, goff + sl);
-      y_bb = b.x;
-      y_hs = hh_hs(b.y);
+      y_hs = hh_hs(Sn.ldw(RS_HH, goff + sl));
     }
     if (cnt > 1) {
       const unsigned sl = (cnt - 2) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
-      v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
+      v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s); v_ln = Sc.ld(RS_LN, s);
       v_ps = SCR.ld(SC_PSI, goff + sl);
-      const D2 b = SCR.ld(SC_BB, goff + sl);
-      v_bb = b.x;
-      v_hs = hh_hs(b.y);
+      v_hs = hh_hs(Sn.ldw(RS_HH, goff + sl));
     }
-    if (cnt > 0) {
-      const unsigned kc = (unsigned)y_hs;
-      c_w = KC.ld(RC_W, kc); c_r = KC.ld(RC_R0, kc); c_l = KC.ld(RC_LN, kc);
-    }
+    if (cnt > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
       const double rho = y_ru.x, u = y_ru.y, fr_p = y_f.x, fu_p = y_f.y;
       const int32_t hs = y_hs;
-      const double psi = y_ps.x, dpsi = y_ps.y, bb = y_bb;
-      const double w = c_w.x, wh = c_w.y, k_r0 = c_r.x, k_ir0 = c_r.y, k_lh = c_l.x, k_ll = c_l.y;
-      y_ru = v_ru; y_f = v_f; y_hs = v_hs; y_ps = v_ps; y_bb = v_bb;
+      const double psi = y_ps.x, dpsi = y_ps.y;
+      const double w = c_w.x, wh = c_w.y;
+      const dd lr0 = {y_ln.x, y_ln.y};
+      y_ru = v_ru; y_f = v_f; y_hs = v_hs; y_ps = v_ps; y_ln = v_ln;
       if (k > 1) {
         const unsigned sp = sl - 2 * NT;
         const unsigned s = WAKE_SLOT(sp);
-        v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s);
+        v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s); v_ln = Sc.ld(RS_LN, s);
         v_ps = SCR.ld(SC_PSI, goff + sp);
-        const D2 b = SCR.ld(SC_BB, goff + sp);
-        v_bb = b.x;
-        v_hs = hh_hs(b.y);
+        v_hs = hh_hs(Sn.ldw(RS_HH, goff + sp));
       }
-      if (k > 0) {
-        const unsigned kc = (unsigned)y_hs;
-        c_w = KC.ld(RC_W, kc); c_r = KC.ld(RC_R0, kc); c_l = KC.ld(RC_LN, kc);
-      }
+      if (k > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
       const double a2 = has_laser ? A2[goff + sl] : 0.0, da2 = has_laser ? DA2[goff + sl] : 0.0;
       const double irho = rcp_nr(rho);
+      // B^(b) as pass B formed it: the table count, then the analytic beams
+      double lam = 0.0;
+      if (bm > 0) {
+        bhi = count_below_down(bR, bhi, bm, rho, k < cnt - 1);
+        if (bhi > 0) lam = bQ[bhi - 1];
+      }
+      #pragma unroll 1
+      for (int si = 0; si < n_an; ++si)
+        if (s_misc[3 * si] == 2.0) lam += s_misc[3 * si + 1] * (-expm1(-rho * rho * s_misc[3 * si + 2]));
+      const double bb = lam * irho;
       const Local L = local_of(irho, u, w, psi, a2);
       const double dz = -(Vgt + (w - wh) * u * irho * L.ipb);
       double B, Cc;
@@ -1650,7 +1672,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         double sr = f_r, su = f_u;
         if (rn < 0.0) { rn = -rn; un = -un; sr = -sr; su = -su; }
         if (!(isfinite(rn) && isfinite(un))) bad = 1.0;
-        const dd lr = dd_add_d({k_lh, k_ll}, log1p_fast((rn - k_r0) * k_ir0));   // as ring_log
+        // ln rho moves with the ring: the old value plus log1p of the step
+        const dd lr = dd_add_d(lr0, log1p_fast((rn - rho) * irho));
         Sn.st(RS_RU, goff + sl, d2(rn, un));
         Sn.st(RS_F, goff + sl, d2(sr, su));
         Sn.st(RS_LN, goff + sl, d2(lr.hi, lr.lo));
@@ -1671,6 +1694,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     s_fr[tid] = nxt_r;
     s_fi[tid] = nxt_i;
     if (stage_next) {
+      __syncthreads();        // every wave is done with this slice's table and constants
       stage_analytic<NT>(I, n + 1, s_misc);
       beam_store<NT>(nbs, s_br, s_bc);
     }
@@ -1758,7 +1782,7 @@ __global__ void state_by_id_kernel(WakeInst I, double* rho, double* u, double* f
   const unsigned sl = slot_of(p, I.C, I.nt);
   const size_t PS = (size_t)I.G * I.C * I.nt;
   const D2* r = reinterpret_cast<const D2*>(I.st[c]) + sl;
-  const int hs = hh_hs(r[RS_HH * PS].x);
+  const int hs = hh_hs(I.st[c][2 * RS_HH * PS + sl]);
   const int i = pos_of_slot(hs, I.C, I.nt);
   if (rho) rho[i] = r[RS_RU * PS].x;
   if (u) u[i] = r[RS_RU * PS].y;
@@ -1776,10 +1800,12 @@ __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u,
   const unsigned sl = slot_of(i, I.C, I.nt);
   const size_t PS = (size_t)I.G * I.C * I.nt;
   D2* r = reinterpret_cast<D2*>(I.st[0]) + sl;
+  const D2* k = reinterpret_cast<const D2*>(I.cst) + sl;
+  const dd lr = ring_log(k[RC_R0 * PS], k[RC_LN * PS], rho[i]);
   r[RS_RU * PS] = d2(rho[i], u[i]);
   r[RS_F * PS] = d2(fr ? fr[i] : 0.0, fu ? fu[i] : 0.0);
-  r[RS_LN * PS] = d2(0.0, 0.0);
-  r[RS_HH * PS] = d2(hh_pack((int32_t)sl, i + 1), reinterpret_cast<const D2*>(I.cst)[RC_W * PS + sl].x);
+  r[RS_LN * PS] = d2(lr.hi, lr.lo);
+  I.st[0][2 * RS_HH * PS + sl] = hh_pack((int32_t)sl, i + 1);
 }
 
 // Back to the state at slice 0 (rings at rest at their initial radii);
@@ -1790,10 +1816,11 @@ __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_ins
     const unsigned sl = slot_of(j, I.C, I.nt);
     const size_t PS = (size_t)I.G * I.C * I.nt;
     D2* r = reinterpret_cast<D2*>(I.st[0]) + sl;
-    r[RS_RU * PS] = d2(reinterpret_cast<const D2*>(I.cst)[RC_R0 * PS + sl].x, 0.0);
+    const D2* k = reinterpret_cast<const D2*>(I.cst) + sl;
+    r[RS_RU * PS] = d2(k[RC_R0 * PS].x, 0.0);
     r[RS_F * PS] = d2(0.0, 0.0);
-    r[RS_LN * PS] = d2(0.0, 0.0);
-    r[RS_HH * PS] = d2(hh_pack((int32_t)sl, j + 1), reinterpret_cast<const D2*>(I.cst)[RC_W * PS + sl].x);
+    r[RS_LN * PS] = k[RC_LN * PS];
+    I.st[0][2 * RS_HH * PS + sl] = hh_pack((int32_t)sl, j + 1);
   }
   if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; I.ctl[CTL_FAULT] = 0; }
 }
