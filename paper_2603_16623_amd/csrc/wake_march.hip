@@ -1125,7 +1125,9 @@ __device__ __forceinline__ void beam_store(const BeamStage<NT>& b, double* s_br,
 }
 
 // Per-thread sums of (w, w ln rho) over the rings at this thread's
-// positions (ln rho of each ring taken from its slot).
+// positions (ln rho of each ring taken from its slot).  Eight rings at a
+// time: their slots and home-slot words, then (w, w^) and ln rho, so each
+// batch costs two rounds of independent loads.
 template <int NT>
 __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, int goff, uint32_t ps,
                                            bool ident, bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
@@ -1134,14 +1136,33 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
   const PV SC = pview(I.st[cur], ps), KC = pview(I.cst, ps);
   sw = {0.0, 0.0};
   swl = {0.0, 0.0};
-  #pragma unroll 4
-  for (int k = 0; k < cnt; ++k) {
-    const unsigned sl = k * NT + tid;
-    const unsigned s = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[goff + sl], smax);
-    const double w = KC.ldh(RC_W, (unsigned)hh_hs(SC.ldw(RS_HH, s)), 0);
-    const D2 l = SC.ld(RS_LN, s);
-    sw = dd_add_d(sw, w);
-    swl = dd_add_fast(swl, dd_mul_d(dd{l.x, l.y}, w));
+  #pragma unroll 1
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    unsigned s[8], hs[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const unsigned sl = (k0 + j) * NT + tid;
+      s[j] = 0;
+      hs[j] = 0;
+      if (k0 + j < cnt) {
+        s[j] = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[goff + sl], smax);
+        hs[j] = (unsigned)hh_hs(SC.ldw(RS_HH, s[j]));
+      }
+    }
+    double w[8];
+    D2 l[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      w[j] = k0 + j < cnt ? KC.ldh(RC_W, hs[j], 0) : 0.0;
+      l[j] = k0 + j < cnt ? SC.ld(RS_LN, s[j]) : d2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (k0 + j < cnt) {
+        sw = dd_add_d(sw, w[j]);
+        swl = dd_add_fast(swl, dd_mul_d(dd{l[j].x, l[j].y}, w[j]));
+      }
+    }
   }
 }
 
