@@ -2,6 +2,7 @@
 
     python -m paper_2603_16623_amd.profile_summary trace DIR TITLE COMMAND > summary.md
     python -m paper_2603_16623_amd.profile_summary traffic MARCH_DIR COPY_DIR COPY_MIB WORKLOAD > traffic.txt
+    python -m paper_2603_16623_amd.profile_summary sq DIR RING_SLICES > sq.txt
 
 `trace`: DIR holds the CSV files of `rocprofv3 --kernel-trace --stats --output-format csv`;
 prints the march dispatches and the top kernels.
@@ -9,6 +10,10 @@ prints the march dispatches and the top kernels.
 (subfolders FETCH_SIZE/ and WRITE_SIZE/) of the profiling driver and of a plain copy of COPY_MIB
 MiB; prints HBM bytes per march dispatch, each counter scaled by copy bytes / counter reading
 of the copy, and the digest of the marcher sources the counters belong to.
+`sq`: DIR holds `--pmc` runs of SQ counters (any subfolders) over march dispatches covering
+RING_SLICES ring-slices in all; prints the counters summed over those dispatches, per
+ring-slice, and the occupancy / issue ratios (SQ_WAVE_CYCLES and SQ_ACTIVE_INST_* count
+four-cycle units, SQ_BUSY_CYCLES single cycles).
 """
 from __future__ import annotations
 
@@ -90,6 +95,33 @@ def traffic(march_dir, copy_dir, copy_mib, workload):
     print(f"write_counter_KiB: {out['WRITE_SIZE'][2]:.6e}  (copy calibration x{out['WRITE_SIZE'][1]:.4f})")
 
 
+def sq(d, ring_slices):
+    rs = float(ring_slices)
+    tot, disp = {}, set()
+    for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+        if "wake_march_kernel" not in r["Kernel_Name"]:
+            continue
+        tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp.add((r["Counter_Name"], r["Dispatch_Id"]))
+    print(f"source_digest: {source_digest()}")
+    print(f"ring_slices: {rs:.6e}")
+    print("| counter | sum | per ring-slice |")
+    print("|---|---|---|")
+    for k in sorted(tot):
+        print(f"| {k} | {tot[k]:.4e} | {tot[k] / rs:.3f} |")
+    w = tot.get("SQ_WAVE_CYCLES")
+    if w:
+        print()
+        for k in ("SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA",
+                  "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS"):
+            if k in tot:
+                print(f"{k} / SQ_WAVE_CYCLES: {tot[k] / w:.3f}")
+    if "SQ_INSTS_VALU" in tot:
+        print(f"VALU lane-instructions per ring-slice (64 lanes): {tot['SQ_INSTS_VALU'] * 64 / rs:.0f}")
+    if "SQ_INSTS_LDS" in tot:
+        print(f"LDS instructions per ring-slice: {tot['SQ_INSTS_LDS'] / rs:.3f}")
+
+
 def read_traffic(path):
     """Traffic figures of a summary file, if it belongs to the current sources."""
     if not os.path.exists(path):
@@ -110,3 +142,5 @@ if __name__ == "__main__":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    elif sys.argv[1] == "sq":
+        sq(sys.argv[2], sys.argv[3])
