@@ -129,6 +129,13 @@ __device__ __forceinline__ GA<T> uview(const T* q) {
   g.p = reinterpret_cast<WAKE_GLOBAL T*>(((uint64_t)hi << 32) | lo);
   return g;
 }
+// A device array's pointer in the global address space (64-bit indexing), so
+// that its accesses take global rather than flat instructions (a flat access
+// waits for both the memory and the LDS counters).
+template <class T>
+__device__ __forceinline__ WAKE_GLOBAL T* gptr(T* q) {
+  return reinterpret_cast<WAKE_GLOBAL T*>(reinterpret_cast<uint64_t>(q));
+}
 __device__ __forceinline__ double uni(double x) {
   const uint64_t v = __double_as_longlong(x);
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -324,7 +331,8 @@ __device__ __forceinline__ int ion_find(const float* nodes, int N, double r, int
   }
   return a;
 }
-__device__ __forceinline__ int count_below(const double* br, int lo, int m, double r, bool gallop) {
+template <class P>
+__device__ __forceinline__ int count_below(P br, int lo, int m, double r, bool gallop) {
   int a, b;
   if (gallop) {
     if (lo >= m || !(br[lo] < r)) return lo;
@@ -350,7 +358,8 @@ __device__ __forceinline__ int count_below(const double* br, int lo, int m, doub
 }
 // The same count for radii met in descending order: hi is the count of the
 // previous (larger) radius when gallop is set.
-__device__ __forceinline__ int count_below_down(const double* br, int hi, int m, double r, bool gallop) {
+template <class P>
+__device__ __forceinline__ int count_below_down(P br, int hi, int m, double r, bool gallop) {
   int a, b;
   if (gallop) {
     if (hi <= 0 || br[hi - 1] < r) return hi;
@@ -1060,7 +1069,7 @@ __device__ __forceinline__ void stage_analytic(const WakeInst& I, int n, double*
   const int tid = threadIdx.x;
   const double xi = n * I.dxi;
   if (tid < I.n_an) {
-    const WakeAnalytic& A = I.an[tid];
+    const WAKE_GLOBAL WakeAnalytic& A = gptr(I.an)[tid];
     if (A.kind == 2) {
       const double s2 = A.sigma_r * A.sigma_r;
       const double dl = xi - A.xi_c;
@@ -1083,10 +1092,12 @@ __device__ __forceinline__ void stage_slice(const WakeInst& I, int n, double* s_
   const int tid = threadIdx.x;
   stage_analytic<NT>(I, n, s_misc);
   if (I.nb) {
-    const int bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
-    const int bm = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
+    const int bt0 = __builtin_amdgcn_readfirstlane(gptr(I.boff)[n]);
+    const int bm = __builtin_amdgcn_readfirstlane(gptr(I.boff)[n + 1]) - bt0;
+    const WAKE_GLOBAL double* br = gptr(I.br) + bt0;
+    const WAKE_GLOBAL double* bc = gptr(I.bcum) + bt0;
     if (bm <= WAKE_BCAP)
-      for (int i = tid; i < bm; i += NT) { s_br[i] = I.br[bt0 + i]; s_bc[i] = I.bcum[bt0 + i]; }
+      for (int i = tid; i < bm; i += NT) { s_br[i] = br[i]; s_bc[i] = bc[i]; }
   }
 }
 
@@ -1103,15 +1114,17 @@ template <int NT>
 __device__ __forceinline__ void beam_fetch(const WakeInst& I, int n, BeamStage<NT>& b) {
   b.m = 0;
   if (!I.nb) return;
-  const int bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
-  b.m = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
+  const int bt0 = __builtin_amdgcn_readfirstlane(gptr(I.boff)[n]);
+  b.m = __builtin_amdgcn_readfirstlane(gptr(I.boff)[n + 1]) - bt0;
   if (b.m > WAKE_BCAP) return;
+  const WAKE_GLOBAL double* br = gptr(I.br) + bt0;
+  const WAKE_GLOBAL double* bc = gptr(I.bcum) + bt0;
 #pragma unroll
   for (int q = 0; q < BeamStage<NT>::BPT; ++q) {
     const int i = threadIdx.x + q * NT;
     b.r[q] = 0.0;
     b.c[q] = 0.0;
-    if (i < b.m) { b.r[q] = I.br[bt0 + i]; b.c[q] = I.bcum[bt0 + i]; }
+    if (i < b.m) { b.r[q] = br[i]; b.c[q] = bc[i]; }
   }
 }
 template <int NT>
@@ -1145,7 +1158,7 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
       s[j] = 0;
       hs[j] = 0;
       if (k0 + j < cnt) {
-        s[j] = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)I.perm[goff + sl], smax);
+        s[j] = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)gptr(I.perm)[goff + sl], smax);
         hs[j] = (unsigned)hh_hs(SC.ldw(RS_HH, s[j]));
       }
     }
@@ -1234,8 +1247,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = goff + k * NT + tid;
       const PV SB = pview(I.st[cur], ps);
-      I.gk_r[sl] = st_rho(SB, sl);
-      I.gk_i[sl] = WAKE_ID(st_hs(SB, sl));
+      gptr(I.gk_r)[sl] = st_rho(SB, sl);
+      gptr(I.gk_i)[sl] = WAKE_ID(st_hs(SB, sl));
     }
     const int r = cl_fix<NT>(I, cl, s_x, s_ok);
     if (r < 0) {
@@ -1327,10 +1340,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       if (tid == 0) {
         const int ql = Ng - 1;
         const unsigned sf = WAKE_SLOT(0u), sL = WAKE_SLOT((unsigned)((ql % C) * NT + ql / C));
-        mine.v[6] = I.gk_r[sf];
-        mine.v[7] = (double)I.gk_i[sf];
-        mine.v[8] = I.gk_r[sL];
-        mine.v[9] = (double)I.gk_i[sL];
+        mine.v[6] = gptr(I.gk_r)[sf];
+        mine.v[7] = (double)gptr(I.gk_i)[sf];
+        mine.v[8] = gptr(I.gk_r)[sL];
+        mine.v[9] = (double)gptr(I.gk_i)[sL];
         mine.v[10] = (budget > 0 && n > I.first &&
                       (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget) ? 1.0 : 0.0;
       }
@@ -1424,12 +1437,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     const PV Sc = pview(I.st[cur], ps), Sn = pview(I.st[nb], ps);
     int bt0 = 0, bm = 0;
     if (I.nb) {
-      bt0 = __builtin_amdgcn_readfirstlane(I.boff[n]);
-      bm = __builtin_amdgcn_readfirstlane(I.boff[n + 1]) - bt0;
+      bt0 = __builtin_amdgcn_readfirstlane(gptr(I.boff)[n]);
+      bm = __builtin_amdgcn_readfirstlane(gptr(I.boff)[n + 1]) - bt0;
     }
     const bool staged = bm <= WAKE_BCAP;
-    const double* const bR = staged ? s_br : I.br + bt0;
-    const double* const bQ = staged ? s_bc : I.bcum + bt0;
+    // the slice's table: staged in LDS, or (too long) in device memory; the
+    // two are searched by separate code so each takes its own instructions
+    const WAKE_GLOBAL double* const gR = gptr(I.br) + bt0;
+    const WAKE_GLOBAL double* const gQ = gptr(I.bcum) + bt0;
 
     // ---- pass B: psi family, sources, local quantities, chunk sums ----
     dd S = {pre.v[0], pre.v[1]}, PT = {pre.v[2], pre.v[3]};
@@ -1497,8 +1512,13 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       // beam charge inside rho (strictly below), analytic beams, lasers
       double lam = 0.0;
       if (bm > 0) {
-        blo = count_below(bR, blo, bm, rho, k > 0);
-        if (blo > 0) lam = bQ[blo - 1];
+        if (staged) {
+          blo = count_below(s_br, blo, bm, rho, k > 0);
+          if (blo > 0) lam = s_bc[blo - 1];
+        } else {
+          blo = count_below(gR, blo, bm, rho, k > 0);
+          if (blo > 0) lam = gQ[blo - 1];
+        }
       }
       double aa = 0.0, dda = 0.0;
       #pragma unroll 1
@@ -1645,8 +1665,13 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       // B^(b) as pass B formed it: the table count, then the analytic beams
       double lam = 0.0;
       if (bm > 0) {
-        bhi = count_below_down(bR, bhi, bm, rho, k < cnt - 1);
-        if (bhi > 0) lam = bQ[bhi - 1];
+        if (staged) {
+          bhi = count_below_down(s_br, bhi, bm, rho, k < cnt - 1);
+          if (bhi > 0) lam = s_bc[bhi - 1];
+        } else {
+          bhi = count_below_down(gR, bhi, bm, rho, k < cnt - 1);
+          if (bhi > 0) lam = gQ[bhi - 1];
+        }
       }
       #pragma unroll 1
       for (int si = 0; si < n_an; ++si)
@@ -1672,13 +1697,13 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       if (!(isfinite(psi) && isfinite(dpsi) && isfinite(ez) && isfinite(bt))) bad = 1.0;
       const int32_t id = WAKE_ID(hs);
       if (rec_snap) {
-        double* sp = I.snap + (size_t)(n / I.stride) * OUT_N * N;
+        WAKE_GLOBAL double* sp = gptr(I.snap) + (size_t)(n / I.stride) * OUT_N * N;
         sp[OUT_PSI * N + id] = psi; sp[OUT_ERBT * N + id] = -dpsi;
         sp[OUT_EZ * N + id] = ez; sp[OUT_BT * N + id] = bt;
         sp[OUT_RHO * N + id] = rho; sp[OUT_UR * N + id] = u;
       }
       if (rec_last) {
-        double* sp = I.last;
+        WAKE_GLOBAL double* sp = gptr(I.last);
         sp[OUT_PSI * N + id] = psi; sp[OUT_ERBT * N + id] = -dpsi;
         sp[OUT_EZ * N + id] = ez; sp[OUT_BT * N + id] = bt;
         sp[OUT_RHO * N + id] = rho; sp[OUT_UR * N + id] = u;
@@ -1701,7 +1726,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         sw2 = dd_add_d(sw2, w);
         swl2 = dd_add_fast(swl2, dd_mul_d(lr, w));
         if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
-        if (CL) { I.gk_r[goff + sl] = rn; I.gk_i[goff + sl] = id; }
+        if (CL) { gptr(I.gk_r)[goff + sl] = rn; gptr(I.gk_i)[goff + sl] = id; }
         if (!key_lt(rn, id, nxt_r, nxt_i)) dis_l = 1.0;
         if (k == cnt - 1) { last_r = rn; last_i = id; }
         nxt_r = rn;
@@ -1709,7 +1734,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       }
       Vgt += L.v;
     }
-    if (tid == 0 && member == 0) { I.axis[2 * n] = psi_axis; I.axis[2 * n + 1] = Vtot; }
+    if (tid == 0 && member == 0) { gptr(I.axis)[2 * n] = psi_axis; gptr(I.axis)[2 * n + 1] = Vtot; }
     // order across chunk boundaries: this chunk's first pushed key (+inf if
     // empty) against the previous chunk's last one
     s_fr[tid] = nxt_r;
