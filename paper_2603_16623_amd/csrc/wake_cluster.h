@@ -48,8 +48,8 @@ __device__ __forceinline__ void cl_start(Cluster& cl) {
 
 // Thread 0 of a member: counts the member in and waits (bounded) until the
 // round's arrivals reach target.  1 when they did, 0 when a member gave up.
-__device__ __noinline__ int cl_wait(int32_t* xc, const int32_t* queue, int target, int G) {
-  atomicAdd(xc, 1);
+__device__ __noinline__ int cl_wait(WAKE_GLOBAL int32_t* xc, const WAKE_GLOBAL int32_t* queue, int target, int G) {
+  __hip_atomic_fetch_add(xc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   bool all_in = false;
   int q_last = -1;
@@ -78,9 +78,10 @@ template <int NF, bool FENCED = true>
 __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, double* s_x, int* s_ok) {
   static_assert(NF <= 16, "exchange packs hold 16 doubles");
   const int buf = cl.round & 1;
+  WAKE_GLOBAL double* const xd = gptr(cl.xd);
   __syncthreads();                                   // this member's writes of the round are issued
   if (threadIdx.x == 0) {
-    double* slot = cl.xd + ((size_t)buf * cl.G + cl.g) * 16;
+    WAKE_GLOBAL double* slot = xd + ((size_t)buf * cl.G + cl.g) * 16;
 #pragma unroll
     for (int i = 0; i < NF; ++i) __hip_atomic_store(slot + i, mine.v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (FENCED) {
@@ -91,7 +92,7 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
       __builtin_amdgcn_s_waitcnt(0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    const int ok = cl_wait(cl.xc, cl.queue, cl.G * (cl.round + 1), cl.G);
+    const int ok = cl_wait(gptr(cl.xc), gptr(cl.queue), cl.G * (cl.round + 1), cl.G);
     if (FENCED) __threadfence();
     *s_ok = ok;
   }
@@ -100,7 +101,7 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
   if (ok)
     for (int i = threadIdx.x; i < cl.G * NF; i += blockDim.x) {
       const int m = i / NF, f = i - m * NF;
-      s_x[i] = __hip_atomic_load(cl.xd + ((size_t)buf * cl.G + m) * 16 + f, __ATOMIC_RELAXED,
+      s_x[i] = __hip_atomic_load(xd + ((size_t)buf * cl.G + m) * 16 + f, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
     }
   __syncthreads();
@@ -185,7 +186,8 @@ __device__ __forceinline__ uint64_t lane_prev64(uint64_t x) {
 // 32 phases, then a bitonic network.
 template <int NT>
 __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double iC, double iP,
-                                           const double* gk_r, const int32_t* gk_i, int32_t* perm) {
+                                           const WAKE_GLOBAL double* gk_r, const WAKE_GLOBAL int32_t* gk_i,
+                                           WAKE_GLOBAL int32_t* perm) {
   const int lane = threadIdx.x & 63;
   double r[4];
   uint64_t k[4];
@@ -299,13 +301,13 @@ __device__ __forceinline__ int cl_chunk_disordered(const WakeInst& I, int goff, 
     for (int j = 0; j < 8; ++j) {
       const int k = k0 + j;
       src[j] = -1;
-      if (k < m) src[j] = I.perm[k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP)];
+      if (k < m) src[j] = gptr(I.perm)[k < cnt ? goff + k * NT + tid : cl_slot<NT>(p0 + k, C, P, iC, iP)];
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       if (src[j] < 0) continue;
-      const double r = I.gk_r[src[j]];
-      const int32_t id = I.gk_i[src[j]];
+      const double r = gptr(I.gk_r)[src[j]];
+      const int32_t id = gptr(I.gk_i)[src[j]];
       if (k0 + j > 0 && key_lt(r, id, pr, pi)) bad = 1;
       pr = r;
       pi = id;
@@ -318,21 +320,24 @@ __device__ __forceinline__ int cl_chunk_disordered(const WakeInst& I, int goff, 
 // in device memory (keys copied out in position order, padded to the next
 // power of two with keys above every ring), one barrier per network stage.
 template <int NT>
-__device__ __noinline__ int cl_bitonic(const WakeInst& I, Cluster cl, double* s_x, int* s_ok) {
+__device__ __noinline__ int cl_bitonic(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko) {
+  const WakeInst& I = *(const WakeInst*)Ig;
+  double* const s_x = reinterpret_cast<double*>(wake_lds + xo);
+  int* const s_ok = reinterpret_cast<int*>(wake_lds + oko);
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
   const int P2 = N <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)(N - 1)));
   const int gt = cl.g * NT + threadIdx.x, nth = cl.G * NT;
   for (int p = gt; p < P2; p += nth) {
     if (p < N) {
-      const int src = I.perm[cl_slot<NT>(p, C, P, iC, iP)];
-      I.bt_r[p] = I.gk_r[src];
-      I.bt_i[p] = I.gk_i[src];
-      I.bt_s[p] = src;
+      const int src = gptr(I.perm)[cl_slot<NT>(p, C, P, iC, iP)];
+      gptr(I.bt_r)[p] = gptr(I.gk_r)[src];
+      gptr(I.bt_i)[p] = gptr(I.gk_i)[src];
+      gptr(I.bt_s)[p] = src;
     } else {
-      I.bt_r[p] = INFINITY;
-      I.bt_i[p] = 0x7fffffff;
-      I.bt_s[p] = -1;
+      gptr(I.bt_r)[p] = INFINITY;
+      gptr(I.bt_i)[p] = 0x7fffffff;
+      gptr(I.bt_s)[p] = -1;
     }
   }
   if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
@@ -342,19 +347,19 @@ __device__ __noinline__ int cl_bitonic(const WakeInst& I, Cluster cl, double* s_
       for (int i = gt; i < P2 / 2; i += nth) {
         const int a = ((i >> ld) << (ld + 1)) | (i & (d - 1)), b = a | d;
         const bool up = (a & kk) == 0;
-        const double ra = I.bt_r[a], rb = I.bt_r[b];
-        const int32_t ia = I.bt_i[a], ib = I.bt_i[b];
+        const double ra = gptr(I.bt_r)[a], rb = gptr(I.bt_r)[b];
+        const int32_t ia = gptr(I.bt_i)[a], ib = gptr(I.bt_i)[b];
         if (key_lt(rb, ib, ra, ia) == up) {
-          const int32_t sa = I.bt_s[a], sb = I.bt_s[b];
-          I.bt_r[a] = rb; I.bt_r[b] = ra;
-          I.bt_i[a] = ib; I.bt_i[b] = ia;
-          I.bt_s[a] = sb; I.bt_s[b] = sa;
+          const int32_t sa = gptr(I.bt_s)[a], sb = gptr(I.bt_s)[b];
+          gptr(I.bt_r)[a] = rb; gptr(I.bt_r)[b] = ra;
+          gptr(I.bt_i)[a] = ib; gptr(I.bt_i)[b] = ia;
+          gptr(I.bt_s)[a] = sb; gptr(I.bt_s)[b] = sa;
         }
       }
       if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
     }
   }
-  for (int p = gt; p < N; p += nth) I.perm[cl_slot<NT>(p, C, P, iC, iP)] = I.bt_s[p];
+  for (int p = gt; p < N; p += nth) gptr(I.perm)[cl_slot<NT>(p, C, P, iC, iP)] = gptr(I.bt_s)[p];
   return cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok) ? cl.round : -1;
 }
 
@@ -365,25 +370,28 @@ __device__ __noinline__ int cl_bitonic(const WakeInst& I, Cluster cl, double* s_
 // order checked across all positions, at most two such rounds, then the
 // bitonic fallback.  Returns false when a member gave up.
 template <int NT>
-__device__ __noinline__ int cl_fix(const WakeInst& I, Cluster cl, double* s_x, int* s_ok) {
+__device__ __noinline__ int cl_fix(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko) {
+  const WakeInst& I = *(const WakeInst*)Ig;
+  double* const s_x = reinterpret_cast<double*>(wake_lds + xo);
+  int* const s_ok = reinterpret_cast<int*>(wake_lds + oko);
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
   const int goff = cl.g * P;
   const int Ng = min(P, N - goff);
   const int cnt = max(0, min(C, Ng - tid * C));
-  for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
+  for (int k = 0; k < cnt; ++k) gptr(I.perm)[goff + k * NT + tid] = goff + k * NT + tid;
   if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   constexpr int NW = NT / 64;
   const int wave = tid >> 6;
   #pragma unroll 1
   for (int round = 0; round < 2; ++round) {
     #pragma unroll 1
-    for (int b = wave; b * 256 < Ng; b += NW) cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    for (int b = wave; b * 256 < Ng; b += NW) cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
     if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
     #pragma unroll 1
     for (int b = wave; 128 + b * 256 < Ng; b += NW)
-      cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+      cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
     if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
     // in order? this thread's positions and the position after them
     int bad = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
@@ -393,7 +401,7 @@ __device__ __noinline__ int cl_fix(const WakeInst& I, Cluster cl, double* s_x, i
     for (int m = 0; m < cl.G; ++m) any += s_x[m];
     if (any == 0.0) return cl.round;
   }
-  return cl_bitonic<NT>(I, cl, s_x, s_ok);
+  return cl_bitonic<NT>(Ig, cl, xo, oko);
 }
 
 // One in-loop round of the cooperative fix-up over all members (first: this
@@ -406,7 +414,10 @@ __device__ __noinline__ int cl_fix(const WakeInst& I, Cluster cl, double* s_x, i
 // positions (and the first of the next member) are still out of order; the
 // next slice-head exchange sums that flag.
 template <int NT>
-__device__ __noinline__ int cl_fix_round(const WakeInst& I, Cluster cl, double* s_x, int* s_ok, bool first) {
+__device__ __noinline__ int cl_fix_round(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko, bool first) {
+  const WakeInst& I = *(const WakeInst*)Ig;
+  double* const s_x = reinterpret_cast<double*>(wake_lds + xo);
+  int* const s_ok = reinterpret_cast<int*>(wake_lds + oko);
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
@@ -416,15 +427,15 @@ __device__ __noinline__ int cl_fix_round(const WakeInst& I, Cluster cl, double* 
   constexpr int NW = NT / 64;
   const int wave = tid >> 6;
   if (first)           // later rounds continue from the order the previous one left
-    for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
+    for (int k = 0; k < cnt; ++k) gptr(I.perm)[goff + k * NT + tid] = goff + k * NT + tid;
   __syncthreads();
   #pragma unroll 1
   for (int b = wave; b * 256 < Ng; b += NW)
-    cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
   if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   #pragma unroll 1
   for (int b = wave; 128 + b * 256 < Ng; b += NW)
-    cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
   if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
   const int b_ = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
   return 2 * cl.round + (__syncthreads_or(b_) ? 1 : 0);
@@ -437,7 +448,8 @@ __device__ __noinline__ int cl_fix_round(const WakeInst& I, Cluster cl, double* 
 // barriers; the member's keys and order are its own writes, so no exchange
 // is needed.  Returns whether the member's positions are still out of order.
 template <int NT>
-__device__ __noinline__ int cl_fix_local(const WakeInst& I, int g, bool first) {
+__device__ __noinline__ int cl_fix_local(const WAKE_GLOBAL WakeInst* Ig, int g, bool first) {
+  const WakeInst& I = *(const WakeInst*)Ig;
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
@@ -448,15 +460,15 @@ __device__ __noinline__ int cl_fix_local(const WakeInst& I, int g, bool first) {
   constexpr int NW = NT / 64;
   const int wave = tid >> 6;
   if (first)
-    for (int k = 0; k < cnt; ++k) I.perm[goff + k * NT + tid] = goff + k * NT + tid;
+    for (int k = 0; k < cnt; ++k) gptr(I.perm)[goff + k * NT + tid] = goff + k * NT + tid;
   __syncthreads();
   #pragma unroll 1
   for (int b = wave; b * 256 < Ng; b += NW)
-    cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    cl_sort_block<NT>(goff + b * 256, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
   __syncthreads();
   #pragma unroll 1
   for (int b = wave; 128 + b * 256 < lim; b += NW)
-    cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, I.gk_r, I.gk_i, I.perm);
+    cl_sort_block<NT>(goff + 128 + b * 256, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
   __syncthreads();
   const int b_ = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP, true);
   return __syncthreads_or(b_);

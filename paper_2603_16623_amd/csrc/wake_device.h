@@ -4,6 +4,26 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// The workgroup's dynamic LDS, named once so that code reached through a
+// call (not only the kernel itself) addresses it as LDS rather than through
+// flat pointers.
+extern __shared__ __align__(16) unsigned char wake_lds[];
+
+#define WAKE_GLOBAL __attribute__((address_space(1)))
+// A device array's pointer in the global address space (64-bit indexing), so
+// that its accesses take global rather than flat instructions (a flat access
+// waits for both the memory and the LDS counters).
+template <class T>
+__device__ __forceinline__ WAKE_GLOBAL T* gptr(T* q) {
+  return reinterpret_cast<WAKE_GLOBAL T*>(reinterpret_cast<uint64_t>(q));
+}
+// An object in device memory handed to a function that is not inlined, typed
+// so that the callee reads it with global instructions.
+template <class T>
+__device__ __forceinline__ const WAKE_GLOBAL T* as_global(const T& x) {
+  return (const WAKE_GLOBAL T*)&x;
+}
+
 // ---------------------------------------------------------------------------
 // double-double (unevaluated sum hi + lo) arithmetic.  Contraction of a
 // multiply into an addition is forbidden inside every helper: after

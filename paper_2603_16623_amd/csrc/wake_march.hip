@@ -107,7 +107,6 @@ __device__ __forceinline__ dd dd_div_rcp(dd a, double b, double ib) {
 // A per-instance array seen as uniform: its base in scalar registers and in
 // the global address space, indexed with 32-bit element offsets (loads and
 // stores then take the scalar-base + vector-offset form).
-#define WAKE_GLOBAL __attribute__((address_space(1)))
 template <class T>
 struct GA {
   WAKE_GLOBAL T* p;
@@ -128,13 +127,6 @@ __device__ __forceinline__ GA<T> uview(const T* q) {
   GA<T> g;
   g.p = reinterpret_cast<WAKE_GLOBAL T*>(((uint64_t)hi << 32) | lo);
   return g;
-}
-// A device array's pointer in the global address space (64-bit indexing), so
-// that its accesses take global rather than flat instructions (a flat access
-// waits for both the memory and the LDS counters).
-template <class T>
-__device__ __forceinline__ WAKE_GLOBAL T* gptr(T* q) {
-  return reinterpret_cast<WAKE_GLOBAL T*>(reinterpret_cast<uint64_t>(q));
 }
 __device__ __forceinline__ double uni(double x) {
   const uint64_t v = __double_as_longlong(x);
@@ -1231,6 +1223,9 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   if (CL) cl_start(cl);
   double* const s_x = s_kr;                                   // gathered packs (cooperative)
   int* const s_ok = reinterpret_cast<int*>(s_misc + 62);
+  // the same two as byte offsets into the LDS, for the cooperative fix-ups
+  const int xo = (int)MarchLds<NT>::head_bytes();
+  const int oko = (int)(reinterpret_cast<unsigned char*>(s_ok) - smem);
 
   if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
@@ -1250,7 +1245,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       gptr(I.gk_r)[sl] = st_rho(SB, sl);
       gptr(I.gk_i)[sl] = WAKE_ID(st_hs(SB, sl));
     }
-    const int r = cl_fix<NT>(I, cl, s_x, s_ok);
+    const int r = cl_fix<NT>(as_global(I), cl, xo, oko);
     if (r < 0) {
       if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
       return;
@@ -1385,17 +1380,17 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
             dis = 0.0;
             continue;
           }
-          still = cl_fix_local<NT>(I, member, ident) ? 1.0 : 0.0;
+          still = cl_fix_local<NT>(as_global(I), member, ident) ? 1.0 : 0.0;
         } else {
           int r = -1;
           if (cl_rounds < 2) {
-            r = cl_fix_round<NT>(I, cl, s_x, s_ok, ident);
+            r = cl_fix_round<NT>(as_global(I), cl, xo, oko, ident);
             if (r >= 0) {
               still = (r & 1) ? 1.0 : 0.0;
               r >>= 1;
             }
           } else {
-            r = cl_bitonic<NT>(I, cl, s_x, s_ok);
+            r = cl_bitonic<NT>(as_global(I), cl, xo, oko);
           }
           if (r < 0) {
             if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
@@ -1774,8 +1769,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
 // the cooperative march as a function of its own (its registers stay out of
 // the single-workgroup march, which is inlined into the kernel)
 template <int NT>
-__device__ __noinline__ void march_member(const WakeInst& I, int member, const int32_t* queue, unsigned char* smem) {
-  march<NT, true>(I, member, queue, smem);
+__device__ __noinline__ void march_member(const WAKE_GLOBAL WakeInst* I, int member, const int32_t* queue) {
+  march<NT, true>(*(const WakeInst*)I, member, queue, wake_lds);
 }
 
 #ifndef WAKE_WAVES_PER_EU
@@ -1785,7 +1780,7 @@ __device__ __noinline__ void march_member(const WakeInst& I, int member, const i
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAKE_WAVES_PER_EU)))
 void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_tasks, int32_t* counter) {
-  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char* const smem = wake_lds;
   __shared__ int s_idx;
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
@@ -1801,7 +1796,7 @@ void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_ta
     }
     const WakeInst& I = insts[lo];
     if (I.nt == NT) {
-      if (I.G > 1) march_member<NT>(I, idx - I.task0, counter, smem);
+      if (I.G > 1) march_member<NT>(as_global(I), idx - I.task0, counter);
       else march<NT, false>(I, 0, counter, smem);
     }
     __syncthreads();
