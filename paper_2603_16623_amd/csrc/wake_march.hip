@@ -1131,12 +1131,16 @@ __device__ __forceinline__ void beam_store(const BeamStage<NT>& b, double* s_br,
 
 // Per-thread sums of (w, w ln rho) over the rings at this thread's
 // positions (ln rho of each ring taken from its slot).  Eight rings at a
-// time: their slots and home-slot words, then (w, w^) and ln rho, so each
-// batch costs two rounds of independent loads.
+// time: their slots and home slots (from the ring ids in LDS when the order
+// is there, else from the home-slot words), then (w, w^) and ln rho, so each
+// batch costs one round of independent loads (two without the LDS ids).
 template <int NT>
 __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, int goff, uint32_t ps,
-                                           bool ident, bool lds_perm, const uint16_t* perm, dd& sw, dd& swl) {
+                                           bool ident, bool lds_perm, const uint16_t* perm,
+                                           const uint16_t* ki, dd& sw, dd& swl) {
   const int tid = threadIdx.x;
+  const int C = I.C;
+  const double iC = 1.0 / (double)C;
   const unsigned smax = ps - 1;
   const PV SC = pview(I.st[cur], ps), KC = pview(I.cst, ps);
   sw = {0.0, 0.0};
@@ -1151,7 +1155,7 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
       hs[j] = 0;
       if (k0 + j < cnt) {
         s[j] = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)gptr(I.perm)[goff + sl], smax);
-        hs[j] = (unsigned)hh_hs(SC.ldw(RS_HH, s[j]));
+        hs[j] = lds_perm ? (unsigned)pos_index<NT>(ki[s[j]], C, iC) : (unsigned)hh_hs(SC.ldw(RS_HH, s[j]));
       }
     }
     double w[8];
@@ -1295,7 +1299,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   // others backward as the push does.
   dd sw = {0.0, 0.0}, swl = {0.0, 0.0};
   if (moved) {
-    chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
+    chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, s_ki, sw, swl);
   } else {
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
@@ -1413,7 +1417,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         changed |= WAKE_FOREIGN(lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[goff + k * NT + tid]);
       // (a chunk back to its own rings after a later round takes the push's sums again)
       if (changed) {
-        chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, sw, swl);
+        chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, s_ki, sw, swl);
       } else {
         sw = sw_push;
         swl = swl_push;
