@@ -180,31 +180,12 @@ __device__ __forceinline__ uint64_t lane_prev64(uint64_t x) {
   return ((uint64_t)lane_prev((uint32_t)(x >> 32)) << 32) | lane_prev((uint32_t)x);
 }
 
-// One wave puts the positions [b0, b0 + 256) of a cooperative instance in
-// order: keys by slot in device memory (gk_r, gk_i), order perm by position
-// slot.  Same scheme as the LDS block sort: odd-even transposition for up to
-// 32 phases, then a bitonic network.
-template <int NT>
-__device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double iC, double iP,
-                                           const WAKE_GLOBAL double* gk_r, const WAKE_GLOBAL int32_t* gk_i,
-                                           WAKE_GLOBAL int32_t* perm) {
+// One wave sorts 256 keys held four per lane (lane l: keys 4l..4l+3) by
+// (radius, 64-bit word with the id in the high half): odd-even
+// transposition for up to 32 phases, then a bitonic network.  Returns false
+// when they were in order already (nothing moved).
+__device__ __forceinline__ bool sort_regs256(double* r, uint64_t* k) {
   const int lane = threadIdx.x & 63;
-  double r[4];
-  uint64_t k[4];
-  int sl[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int p = b0 + 4 * lane + j;
-    sl[j] = -1;
-    r[j] = INFINITY;
-    k[j] = ~0ull;
-    if (p < N) {
-      sl[j] = cl_slot<NT>(p, C, P, iC, iP);
-      const int src = perm[sl[j]];
-      r[j] = gk_r[src];
-      k[j] = ((uint64_t)(uint32_t)gk_i[src] << 32) | (uint32_t)src;
-    }
-  }
   bool ok = !k64_lt(r[1], k[1], r[0], k[0]) && !k64_lt(r[2], k[2], r[1], k[1]) &&
             !k64_lt(r[3], k[3], r[2], k[2]);
   {
@@ -212,7 +193,7 @@ __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double i
     const uint64_t nk = lane_next64(k[0]);
     if (lane < 63) ok = ok && !k64_lt(nr, nk, r[3], k[3]);
   }
-  if (__all(ok)) return;
+  if (__all(ok)) return false;
   bool done = false;
   #pragma unroll 1
   for (int it = 0; it < 8 && !done; ++it) {
@@ -273,9 +254,56 @@ __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double i
       }
     }
   }
+  return true;
+}
+
+// One wave puts the positions [b0, b0 + 256) of a cooperative instance in
+// order: keys by slot in device memory (gk_r, gk_i), order perm by position
+// slot.
+template <int NT>
+__device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double iC, double iP,
+                                           const WAKE_GLOBAL double* gk_r, const WAKE_GLOBAL int32_t* gk_i,
+                                           WAKE_GLOBAL int32_t* perm) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint64_t k[4];
+  int sl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    sl[j] = -1;
+    r[j] = INFINITY;
+    k[j] = ~0ull;
+    if (p < N) {
+      sl[j] = cl_slot<NT>(p, C, P, iC, iP);
+      const int src = perm[sl[j]];
+      r[j] = gk_r[src];
+      k[j] = ((uint64_t)(uint32_t)gk_i[src] << 32) | (uint32_t)src;
+    }
+  }
+  if (!sort_regs256(r, k)) return;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     if (sl[j] >= 0) perm[sl[j]] = (int32_t)(uint32_t)(k[j] & 0xffffffffull);
+}
+
+// The same for keys held by position in LDS (L_r, L_k, positions [0, n)).
+__device__ __noinline__ void lds_sort_block(int b0, int n, double* L_r, uint64_t* L_k) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint64_t k[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    r[j] = p < n ? L_r[p] : INFINITY;
+    k[j] = p < n ? L_k[p] : ~0ull;
+  }
+  if (!sort_regs256(r, k)) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    if (p < n) { L_r[p] = r[j]; L_k[p] = k[j]; }
+  }
 }
 
 // Whether this thread's positions (and the position after them) are out of
@@ -472,4 +500,60 @@ __device__ __noinline__ int cl_fix_local(const WAKE_GLOBAL WakeInst* Ig, int g, 
   __syncthreads();
   const int b_ = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP, true);
   return __syncthreads_or(b_);
+}
+
+// The member-local round with the member's keys copied into LDS by position
+// (radius; id and slot in one 64-bit word) at byte offset lo of the dynamic
+// LDS (16 bytes per position): the same blocks sorted there, then the order
+// written back to perm.  Loads batched: slots, then keys.
+template <int NT>
+__device__ __noinline__ int cl_fix_local_lds(const WAKE_GLOBAL WakeInst* Ig, int g, bool first, int lo) {
+  const WakeInst& I = *(const WakeInst*)Ig;
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C, P = C * NT;
+  const int goff = g * P;
+  const int Ng = min(P, N - goff);
+  const int cnt = max(0, min(C, Ng - tid * C));
+  const int lim = goff + Ng == N ? Ng : Ng - 256;   // phase-two blocks starting below lim lie inside
+  constexpr int NW = NT / 64;
+  const int wave = tid >> 6;
+  double* const L_r = reinterpret_cast<double*>(wake_lds + lo);
+  uint64_t* const L_k = reinterpret_cast<uint64_t*>(wake_lds + lo + 8 * P);
+  WAKE_GLOBAL int32_t* const perm = gptr(I.perm);
+  const WAKE_GLOBAL double* const gr = gptr(I.gk_r);
+  const WAKE_GLOBAL int32_t* const gi = gptr(I.gk_i);
+  #pragma unroll 1
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    int src[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int sl = goff + (k0 + j) * NT + tid;
+      src[j] = -1;
+      if (k0 + j < cnt) src[j] = first ? sl : perm[sl];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (src[j] < 0) continue;
+      const int q = tid * C + k0 + j;
+      L_r[q] = gr[src[j]];
+      L_k[q] = ((uint64_t)(uint32_t)gi[src[j]] << 32) | (uint32_t)src[j];
+    }
+  }
+  __syncthreads();
+  #pragma unroll 1
+  for (int b = wave; b * 256 < Ng; b += NW) lds_sort_block(b * 256, Ng, L_r, L_k);
+  __syncthreads();
+  #pragma unroll 1
+  for (int b = wave; 128 + b * 256 < lim; b += NW) lds_sort_block(128 + b * 256, Ng, L_r, L_k);
+  __syncthreads();
+  // order inside the member (the position after its last is the next
+  // member's, checked at the slice head) and the order back to perm
+  int bad = 0;
+  #pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const int q = tid * C + k;
+    if (q + 1 < Ng && k64_lt(L_r[q + 1], L_k[q + 1], L_r[q], L_k[q])) bad = 1;
+    perm[goff + k * NT + tid] = (int32_t)(uint32_t)(L_k[q] & 0xffffffffull);
+  }
+  return __syncthreads_or(bad);
 }

@@ -1230,6 +1230,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   // the same two as byte offsets into the LDS, for the cooperative fix-ups
   const int xo = (int)MarchLds<NT>::head_bytes();
   const int oko = (int)(reinterpret_cast<unsigned char*>(s_ok) - smem);
+  // cooperative member-local fix-up rounds in LDS: the key area after the
+  // gathered packs (64 members x 16 doubles)
+  const int lo = xo + 64 * 16 * (int)sizeof(double);
+  const int lo_cap = (int)MarchLds<NT>::key_bytes() - 64 * 16 * (int)sizeof(double);
 
   if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
@@ -1384,7 +1388,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
             dis = 0.0;
             continue;
           }
-          still = cl_fix_local<NT>(as_global(I), member, ident) ? 1.0 : 0.0;
+          still = (16 * P <= lo_cap ? cl_fix_local_lds<NT>(as_global(I), member, ident, lo)
+                                    : cl_fix_local<NT>(as_global(I), member, ident)) ? 1.0 : 0.0;
         } else {
           int r = -1;
           if (cl_rounds < 2) {
