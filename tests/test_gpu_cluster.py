@@ -204,3 +204,42 @@ def test_cluster_multi_round_fixups_match_split_launches(wk):
             assert np.array_equal(fa[q], fb[q]), (n, q)
     a.close()
     b.close()
+
+
+def test_cluster_members_wait_for_busy_workgroups(wk):
+    """A batch launched on fewer workgroups than it has tasks: an instance's
+    first member starts while the rest of its members still wait for
+    workgroups busy with an earlier instance, and waits for them (the wait
+    bound counts from the last task taken).  Every instance ends bitwise as
+    when solved alone."""
+    wk.wake_set_tiling(256, 0)
+    wk.wake_set_cluster(2, 500)
+    insts = [W.small_instance(seed, n_rings=3000, n_xi=30, n_peak=3.0, sigma_r=0.2, geometric=False,
+                              dxi=0.02) for seed in (5, 6, 7)]
+    rng = np.random.default_rng(48)
+    insts += [W.batched_instance(rng, n, 30, n_drv=2000, n_wit=500, r_max=4.0) for n in (300, 450)]
+    _say("cluster batch on a 7-workgroup grid")
+    alone = []
+    for inst in insts:
+        s = wk.WakeSolver.from_instance(inst, record_stride=10)
+        s.wake_solve(0, inst.n_xi)
+        alone.append(([s.wake_fields(n) for n in (10, 20)], s.wake_lineout(), s.wake_get_state()["rho"]))
+        s.close()
+    solvers = [wk.WakeSolver.from_instance(inst, record_stride=10) for inst in insts]
+    assert [s.layout()[0] for s in solvers] == [6, 6, 6, 1, 1]
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_capture(7)
+    b.wake_batch_replay()
+    b.wake_batch_sync()
+    for s, (fields, (lp, le), rho) in zip(solvers, alone):
+        assert s.wake_status()[0] == -1
+        for n, f in zip((10, 20), fields):
+            g = s.wake_fields(n)
+            for q in FIELDS:
+                assert np.array_equal(g[q], f[q]), (n, q)
+        glp, gle = s.wake_lineout()
+        assert np.array_equal(glp, lp) and np.array_equal(gle, le)
+        assert np.array_equal(s.wake_get_state()["rho"], rho)
+    b.close()
+    for s in solvers:
+        s.close()
