@@ -378,90 +378,126 @@ __device__ __forceinline__ int count_below_down(P br, int hi, int m, double r, b
 // ---------------------------------------------------------------------------
 // ring-set initialisation: weights, ln r0, ion interval records, state
 // ---------------------------------------------------------------------------
+// Three kernels over the rings' blocks of NT (in ring order), then one
+// over the intervals.  Block b's (w, w ln r0) totals go to tmp[4b..4b+3];
+// the serial pass turns them into exclusive offsets, in the order a single
+// workgroup marching block by block would have summed them.
 template <int NT>
-__global__ __launch_bounds__(NT) void wake_init_kernel(WakeInst I, const double* __restrict__ r0,
-                                                       const double* __restrict__ dr,
-                                                       const double* __restrict__ dens) {
+__global__ __launch_bounds__(NT) void init_rings_kernel(WakeInst I, const double* __restrict__ r0,
+                                                        const double* __restrict__ dr,
+                                                        const double* __restrict__ dens, double* tmp) {
   __shared__ double s_scan[(NT / 64) * 8];
   const int N = I.N;
-  const int tid = threadIdx.x;
+  const int j = blockIdx.x * NT + threadIdx.x;
   D2* cst = reinterpret_cast<D2*>(const_cast<double*>(I.cst));
   D2* st = reinterpret_cast<D2*>(I.st[0]);
   double* st_w = I.st[0];
   const size_t PS = (size_t)I.G * I.C * I.nt;      // slots per plane
+  const bool ok = j < N;
+  double w = 0.0, wh = 0.0, r = 1.0;
+  dd lr = {0.0, 0.0};
+  if (ok) {
+    r = r0[j];
+    const double d = dr[j];
+    const double nd = dens ? dens[j] : 1.0;
+    w = nd * r * d;                              // eq. macroparticle_weight
+    wh = w / 2.0 - nd * d * d / 8.0;             // modified weight
+    lr = dd_log(r);
+    const unsigned hs = slot_of(j, I.C, I.nt);   // home slot of ring j
+    cst[RC_W * PS + hs] = d2(w, wh);
+    cst[RC_R0 * PS + hs] = d2(r, 1.0 / r);
+    cst[RC_LN * PS + hs] = d2(lr.hi, lr.lo);
+    // initial state: position j holds ring j; its interval starts at its node
+    st[RS_RU * PS + hs] = d2(r, 0.0);
+    st[RS_F * PS + hs] = d2(0.0, 0.0);
+    st[RS_LN * PS + hs] = d2(lr.hi, lr.lo);
+    st_w[2 * RS_HH * PS + hs] = hh_pack((int32_t)hs, j + 1);
+  }
+  const dd wl = dd_mul_d(lr, w);
+  Pack<4> tot;
+  block_prefix<NT, 4>(Pack<4>{{w, 0.0, wl.hi, wl.lo}}, Pack<4>{{0, 0, 0, 0}}, DD2Op(), s_scan, tot);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 4; ++i) tmp[4 * blockIdx.x + i] = tot.v[i];
+}
+
+// One thread: block totals to exclusive offsets, the totals, record 0, control.
+__global__ void init_offsets_kernel(WakeInst I, double* tmp, int n_blocks) {
+  if (threadIdx.x != 0) return;
+  dd cS = {0.0, 0.0}, cPT = {0.0, 0.0};
+  for (int b = 0; b < n_blocks; ++b) {
+    const dd tS = {tmp[4 * b], tmp[4 * b + 1]}, tPT = {tmp[4 * b + 2], tmp[4 * b + 3]};
+    tmp[4 * b] = cS.hi; tmp[4 * b + 1] = cS.lo; tmp[4 * b + 2] = cPT.hi; tmp[4 * b + 3] = cPT.lo;
+    cS = dd_add(cS, tS);
+    cPT = dd_add(cPT, tPT);
+  }
   double* R = const_cast<double*>(I.ion);
   double* consts = const_cast<double*>(I.tot0);
-  dd cS = {0.0, 0.0}, cPT = {0.0, 0.0};
-  // phase 1: node values (node j+1 is ring j) into records j+1
-  for (int base = 0; base < N; base += NT) {
-    const int j = base + tid;
-    const bool ok = j < N;
-    double w = 0.0, wh = 0.0, r = 1.0;
-    dd lr = {0.0, 0.0};
-    if (ok) {
-      r = r0[j];
-      const double d = dr[j];
-      const double nd = dens ? dens[j] : 1.0;
-      w = nd * r * d;                              // eq. macroparticle_weight
-      wh = w / 2.0 - nd * d * d / 8.0;             // modified weight
-      lr = dd_log(r);
-      const unsigned hs = slot_of(j, I.C, I.nt);   // home slot of ring j
-      cst[RC_W * PS + hs] = d2(w, wh);
-      cst[RC_R0 * PS + hs] = d2(r, 1.0 / r);
-      cst[RC_LN * PS + hs] = d2(lr.hi, lr.lo);
-    }
-    const dd wl = dd_mul_d(lr, w);
-    Pack<4> tot;
-    Pack<4> pre = block_prefix<NT, 4>(Pack<4>{{w, 0.0, wl.hi, wl.lo}}, Pack<4>{{0, 0, 0, 0}},
-                                      DD2Op(), s_scan, tot);
-    const dd S = dd_add(cS, {pre.v[0], pre.v[1]});
-    const dd PTi = dd_add(dd_add(cPT, {pre.v[2], pre.v[3]}), wl);
-    if (ok) {
-      // ion ring j (q=+1) at its own radius with self weight w^
-      const dd dp = dd_neg(dd_div_d(dd_add_d(S, wh), r));
-      const dd ps = dd_neg(dd_sub(dd_mul(dd_add_d(S, w), lr), PTi));
-      double* rec = R + (size_t)(j + 1) * WAKE_ION_REC;
-      rec[IR_LO] = r;
-      rec[IR_PSH] = ps.hi; rec[IR_PSL] = ps.lo;
-      rec[IR_DPH] = dp.hi; rec[IR_DPL] = dp.lo;
-      // initial state: position j holds ring j; its interval starts at its node
-      const unsigned sl = slot_of(j, I.C, I.nt);
-      st[RS_RU * PS + sl] = d2(r, 0.0);
-      st[RS_F * PS + sl] = d2(0.0, 0.0);
-      st[RS_LN * PS + sl] = d2(lr.hi, lr.lo);
-      st_w[2 * RS_HH * PS + sl] = hh_pack((int32_t)sl, j + 1);
-    }
-    cS = dd_add(cS, {tot.v[0], tot.v[1]});
-    cPT = dd_add(cPT, {tot.v[2], tot.v[3]});
+  R[IR_LO] = 0.0;
+  R[IR_PSH] = 0.0; R[IR_PSL] = 0.0; R[IR_DPH] = 0.0; R[IR_DPL] = 0.0;
+  consts[0] = cPT.hi; consts[1] = cPT.lo;   // sum_j w_j ln r0_j
+  consts[2] = cS.hi; consts[3] = cS.lo;     // total weight Q
+  I.ctl[CTL_CUR] = 0;
+  I.ctl[CTL_BREAK] = -1;
+  I.ctl[CTL_NEXT] = 0;
+  I.ctl[CTL_FAULT] = 0;
+}
+
+// Node values of the ion rings (node j+1 is ring j) into records j+1.
+template <int NT>
+__global__ __launch_bounds__(NT) void init_nodes_kernel(WakeInst I, const double* __restrict__ tmp) {
+  __shared__ double s_scan[(NT / 64) * 8];
+  const int N = I.N;
+  const int j = blockIdx.x * NT + threadIdx.x;
+  const D2* cst = reinterpret_cast<const D2*>(I.cst);
+  const size_t PS = (size_t)I.G * I.C * I.nt;
+  const bool ok = j < N;
+  double w = 0.0, wh = 0.0, r = 1.0;
+  dd lr = {0.0, 0.0};
+  if (ok) {
+    const unsigned hs = slot_of(j, I.C, I.nt);
+    const D2 kw = cst[RC_W * PS + hs], kr = cst[RC_R0 * PS + hs], kl = cst[RC_LN * PS + hs];
+    w = kw.x; wh = kw.y; r = kr.x; lr = {kl.x, kl.y};
   }
-  if (tid == 0) {
-    R[IR_LO] = 0.0;
-    R[IR_PSH] = 0.0; R[IR_PSL] = 0.0; R[IR_DPH] = 0.0; R[IR_DPL] = 0.0;
-    consts[0] = cPT.hi; consts[1] = cPT.lo;   // sum_j w_j ln r0_j
-    consts[2] = cS.hi; consts[3] = cS.lo;     // total weight Q
-    I.ctl[CTL_CUR] = 0;
-    I.ctl[CTL_BREAK] = -1;
-    I.ctl[CTL_NEXT] = 0;
-    I.ctl[CTL_FAULT] = 0;
+  const dd wl = dd_mul_d(lr, w);
+  Pack<4> tot;
+  const Pack<4> pre = block_prefix<NT, 4>(Pack<4>{{w, 0.0, wl.hi, wl.lo}}, Pack<4>{{0, 0, 0, 0}},
+                                          DD2Op(), s_scan, tot);
+  const dd cS = {tmp[4 * blockIdx.x], tmp[4 * blockIdx.x + 1]};
+  const dd cPT = {tmp[4 * blockIdx.x + 2], tmp[4 * blockIdx.x + 3]};
+  const dd S = dd_add(cS, {pre.v[0], pre.v[1]});
+  const dd PTi = dd_add(dd_add(cPT, {pre.v[2], pre.v[3]}), wl);
+  if (ok) {
+    // ion ring j (q=+1) at its own radius with self weight w^
+    const dd dp = dd_neg(dd_div_d(dd_add_d(S, wh), r));
+    const dd ps = dd_neg(dd_sub(dd_mul(dd_add_d(S, w), lr), PTi));
+    double* rec = const_cast<double*>(I.ion) + (size_t)(j + 1) * WAKE_ION_REC;
+    rec[IR_LO] = r;
+    rec[IR_PSH] = ps.hi; rec[IR_PSL] = ps.lo;
+    rec[IR_DPH] = dp.hi; rec[IR_DPL] = dp.lo;
   }
-  __syncthreads();
-  // phase 2: interval ends and steps; the last node is the plasma edge
-  const double Rp = I.Rp;
-  const dd eps = dd_sub(cPT, dd_mul(cS, dd_log(Rp)));
-  const dd edp = dd_neg(dd_div_d(cS, Rp));
-  for (int j = tid; j <= N; j += NT) {
-    double* rec = R + (size_t)j * WAKE_ION_REC;
-    double hi, nps_h, nps_l, ndp_h, ndp_l;
-    if (j < N) {
-      const double* nx = rec + WAKE_ION_REC;
-      hi = nx[IR_LO]; nps_h = nx[IR_PSH]; nps_l = nx[IR_PSL]; ndp_h = nx[IR_DPH]; ndp_l = nx[IR_DPL];
-    } else {
-      hi = Rp; nps_h = eps.hi; nps_l = eps.lo; ndp_h = edp.hi; ndp_l = edp.lo;
-    }
-    rec[IR_HI] = hi;
-    rec[IR_DPS] = dd_round(dd_sub({nps_h, nps_l}, {rec[IR_PSH], rec[IR_PSL]}));
-    rec[IR_DDP] = dd_round(dd_sub({ndp_h, ndp_l}, {rec[IR_DPH], rec[IR_DPL]}));
+}
+
+// Interval ends and steps; the last node is the plasma edge.
+__global__ void init_intervals_kernel(WakeInst I) {
+  const int N = I.N;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > N) return;
+  double* R = const_cast<double*>(I.ion);
+  const dd cPT = {I.tot0[0], I.tot0[1]}, cS = {I.tot0[2], I.tot0[3]};
+  double* rec = R + (size_t)j * WAKE_ION_REC;
+  double hi, nps_h, nps_l, ndp_h, ndp_l;
+  if (j < N) {
+    const double* nx = rec + WAKE_ION_REC;
+    hi = nx[IR_LO]; nps_h = nx[IR_PSH]; nps_l = nx[IR_PSL]; ndp_h = nx[IR_DPH]; ndp_l = nx[IR_DPL];
+  } else {
+    const double Rp = I.Rp;
+    const dd eps = dd_sub(cPT, dd_mul(cS, dd_log(Rp)));
+    const dd edp = dd_neg(dd_div_d(cS, Rp));
+    hi = Rp; nps_h = eps.hi; nps_l = eps.lo; ndp_h = edp.hi; ndp_l = edp.lo;
   }
+  rec[IR_HI] = hi;
+  rec[IR_DPS] = dd_round(dd_sub({nps_h, nps_l}, {rec[IR_PSH], rec[IR_PSL]}));
+  rec[IR_DDP] = dd_round(dd_sub({ndp_h, ndp_l}, {rec[IR_DPH], rec[IR_DPL]}));
 }
 
 // ---------------------------------------------------------------------------
@@ -1893,7 +1929,13 @@ hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipSt
 
 hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, const double* dens,
                        hipStream_t s) {
-  hipLaunchKernelGGL((wake_init_kernel<256>), dim3(1), dim3(256), 0, s, I, r0, dr, dens);
+  // block totals / offsets in the fix-up's scratch (4 doubles per block of 256 rings)
+  const int nb = (I.N + 255) / 256;
+  double* tmp = I.sm_r;
+  hipLaunchKernelGGL((init_rings_kernel<256>), dim3(nb), dim3(256), 0, s, I, r0, dr, dens, tmp);
+  hipLaunchKernelGGL(init_offsets_kernel, dim3(1), dim3(64), 0, s, I, tmp, nb);
+  hipLaunchKernelGGL((init_nodes_kernel<256>), dim3(nb), dim3(256), 0, s, I, (const double*)tmp);
+  hipLaunchKernelGGL(init_intervals_kernel, dim3((I.N + 1 + 255) / 256), dim3(256), 0, s, I);
   return hipGetLastError();
 }
 
