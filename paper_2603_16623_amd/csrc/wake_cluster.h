@@ -442,7 +442,8 @@ __device__ __noinline__ int cl_fix(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, i
 // positions (and the first of the next member) are still out of order; the
 // next slice-head exchange sums that flag.
 template <int NT>
-__device__ __noinline__ int cl_fix_round(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko, bool first) {
+__device__ __noinline__ int cl_fix_round(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko, bool first,
+                                         int lo) {
   const WakeInst& I = *(const WakeInst*)Ig;
   double* const s_x = reinterpret_cast<double*>(wake_lds + xo);
   int* const s_ok = reinterpret_cast<int*>(wake_lds + oko);
@@ -454,6 +455,16 @@ __device__ __noinline__ int cl_fix_round(const WAKE_GLOBAL WakeInst* Ig, Cluster
   const int cnt = max(0, min(C, Ng - tid * C));
   constexpr int NW = NT / 64;
   const int wave = tid >> 6;
+  if (lo >= 0) {
+    // the same blocks with the interior ones sorted in LDS first: only the
+    // block straddling the next member is sorted between the two meetings
+    cl_lds_blocks<NT>(I, cl.g, first, lo, false);
+    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
+    if (wave == 0 && goff + Ng < N) cl_sort_block<NT>(goff + Ng - 128, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
+    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
+    const int bl = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
+    return 2 * cl.round + (__syncthreads_or(bl) ? 1 : 0);
+  }
   if (first)           // later rounds continue from the order the previous one left
     for (int k = 0; k < cnt; ++k) gptr(I.perm)[goff + k * NT + tid] = goff + k * NT + tid;
   __syncthreads();
@@ -502,13 +513,16 @@ __device__ __noinline__ int cl_fix_local(const WAKE_GLOBAL WakeInst* Ig, int g, 
   return __syncthreads_or(b_);
 }
 
-// The member-local round with the member's keys copied into LDS by position
-// (radius; id and slot in one 64-bit word) at byte offset lo of the dynamic
-// LDS (16 bytes per position): the same blocks sorted there, then the order
-// written back to perm.  Loads batched: slots, then keys.
+// Block phases over this member's own positions with its keys copied into
+// LDS by position (radius; id and slot in one 64-bit word) at byte offset lo
+// of the dynamic LDS (16 bytes per position): the blocks at offsets 0, 256,
+// ... and then 128, 384, ... of the member's range, less the one that
+// straddles the next member, sorted there, and the order written back to
+// perm.  Loads batched: slots, then keys.  With check, returns whether the
+// member's positions are still out of order (the position after its last is
+// the next member's, checked elsewhere).
 template <int NT>
-__device__ __noinline__ int cl_fix_local_lds(const WAKE_GLOBAL WakeInst* Ig, int g, bool first, int lo) {
-  const WakeInst& I = *(const WakeInst*)Ig;
+__device__ __forceinline__ int cl_lds_blocks(const WakeInst& I, int g, bool first, int lo, bool check) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const int goff = g * P;
@@ -546,14 +560,18 @@ __device__ __noinline__ int cl_fix_local_lds(const WAKE_GLOBAL WakeInst* Ig, int
   #pragma unroll 1
   for (int b = wave; 128 + b * 256 < lim; b += NW) lds_sort_block(128 + b * 256, Ng, L_r, L_k);
   __syncthreads();
-  // order inside the member (the position after its last is the next
-  // member's, checked at the slice head) and the order back to perm
   int bad = 0;
   #pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
     const int q = tid * C + k;
-    if (q + 1 < Ng && k64_lt(L_r[q + 1], L_k[q + 1], L_r[q], L_k[q])) bad = 1;
+    if (check && q + 1 < Ng && k64_lt(L_r[q + 1], L_k[q + 1], L_r[q], L_k[q])) bad = 1;
     perm[goff + k * NT + tid] = (int32_t)(uint32_t)(L_k[q] & 0xffffffffull);
   }
   return __syncthreads_or(bad);
+}
+
+// The member-local round in LDS (cl_fix_local's blocks).
+template <int NT>
+__device__ __noinline__ int cl_fix_local_lds(const WAKE_GLOBAL WakeInst* Ig, int g, bool first, int lo) {
+  return cl_lds_blocks<NT>(*(const WakeInst*)Ig, g, first, lo, true);
 }

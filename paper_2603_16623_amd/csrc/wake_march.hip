@@ -537,6 +537,138 @@ __device__ void bitonic_keys(double* kr, int32_t* ki, int32_t* ks, int P) {
   }
 }
 
+// Fallback order of a cooperative instance, by segments.  A segment
+// boundary sits before position p when every key before p is below every
+// key from p on; the rings between consecutive boundaries are permuted
+// among themselves.  Rings alone in their segment keep their positions; the
+// others (M of them) are compacted in position order, sorted together by
+// member 0 in LDS, and put back into the positions they left, in order (the
+// segments follow each other in key order, so the j-th smallest goes to the
+// j-th freed position).  Two exchanges of totals and three fenced ones, in
+// place of the bitonic network's one per stage, which remains for M beyond
+// the LDS sort (cap bytes at byte offset lo, 16 per key).  Returns the
+// barrier count, -1 when a member gave up.
+template <int NT>
+__device__ __noinline__ int cl_segments(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko, int lo,
+                                        int cap) {
+  const WakeInst& I = *(const WakeInst*)Ig;
+  double* const s_x = reinterpret_cast<double*>(wake_lds + xo);
+  int* const s_ok = reinterpret_cast<int*>(wake_lds + oko);
+  constexpr int NW = NT / 64;
+  double* const s_scanA = reinterpret_cast<double*>(wake_lds);          // the slice scans' areas
+  double* const s_scanB = s_scanA + NW * 16;
+  const int tid = threadIdx.x;
+  const int N = I.N, C = I.C, P = C * NT;
+  const double iC = 1.0 / (double)C, iP = 1.0 / (double)P;
+  const int goff = cl.g * P;
+  const int Ng = min(P, N - goff);
+  const int q0 = tid * C;
+  const int cnt = max(0, min(C, Ng - q0));
+  double* const L_r = reinterpret_cast<double*>(wake_lds + lo);
+  uint64_t* const L_k = reinterpret_cast<uint64_t*>(wake_lds + lo + 8 * P);
+  WAKE_GLOBAL int32_t* const perm = gptr(I.perm);
+  // this member's keys by position, in the current order
+  #pragma unroll 1
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    int src[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) src[j] = k0 + j < cnt ? perm[goff + (k0 + j) * NT + tid] : -1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (src[j] < 0) continue;
+      L_r[q0 + k0 + j] = gptr(I.gk_r)[src[j]];
+      L_k[q0 + k0 + j] = ((uint64_t)(uint32_t)gptr(I.gk_i)[src[j]] << 32) | (uint32_t)src[j];
+    }
+  }
+  __syncthreads();
+  const Pack<2> k_lo = {{-INFINITY, -2147483648.0}}, k_hi = {{INFINITY, 2147483647.0}};
+  // suffix minima inside the chunk, its maximum and minimum
+  double sr[16];
+  int32_t si[16];
+  Pack<2> mx = k_lo, mn = k_hi;
+#pragma unroll
+  for (int k = 15; k >= 0; --k) {
+    if (k < cnt) {
+      const Pack<2> x = {{L_r[q0 + k], (double)(int32_t)(L_k[q0 + k] >> 32)}};
+      mx = MaxKeyOp()(mx, x);
+      mn = MinKeyOp()(mn, x);
+    }
+    sr[k] = mn.v[0];
+    si[k] = (int32_t)mn.v[1];
+  }
+  Pack<2> tmx, tmn;
+  const Pack<2> bmx = block_prefix<NT, 2>(mx, k_lo, MaxKeyOp(), s_scanA, tmx);   // before the chunk
+  const Pack<2> bmn = block_suffix<NT, 2>(mn, k_hi, MinKeyOp(), s_scanB, tmn);   // after the chunk
+  if (!cl_gather<4, false>(cl, Pack<4>{{tmx.v[0], tmx.v[1], tmn.v[0], tmn.v[1]}}, s_x, s_ok)) return -1;
+  Pack<2> gmx, gtot, gmn, gtot2;
+  cl_prefix<2, 4>(s_x, 0, cl.g, cl.G, k_lo, MaxKeyOp(), gmx, gtot);    // earlier members
+  cl_suffix<2, 4>(s_x, 2, cl.g, cl.G, k_hi, MinKeyOp(), gmn, gtot2);   // later members
+  // boundary before position q0 + k: max of every key before it below min
+  // of every key from it on; a ring is alone in its segment when there are
+  // boundaries before it and after it
+  const Pack<2> after = MinKeyOp()(bmn, gmn);
+  Pack<2> pm = MaxKeyOp()(gmx, bmx);
+  const Pack<2> from0 = MinKeyOp()(Pack<2>{{sr[0], (double)si[0]}}, after);   // every key from q0 on
+  bool bnd = key_lt(pm.v[0], (int32_t)pm.v[1], from0.v[0], (int32_t)from0.v[1]);
+  uint32_t bad = 0;             // bit k: ring at q0 + k moves
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < cnt) {
+      pm = MaxKeyOp()(pm, Pack<2>{{L_r[q0 + k], (double)(int32_t)(L_k[q0 + k] >> 32)}});
+      const Pack<2> m = k + 1 < cnt ? Pack<2>{{sr[k + 1], (double)si[k + 1]}} : after;
+      const Pack<2> sm = MinKeyOp()(m, after);
+      const bool nb = key_lt(pm.v[0], (int32_t)pm.v[1], sm.v[0], (int32_t)sm.v[1]);
+      if (!(bnd && nb)) bad |= 1u << k;
+      bnd = nb;
+    }
+  }
+  const double nbad = (double)__builtin_popcount(bad);
+  Pack<1> tb;
+  const Pack<1> ob = block_prefix<NT, 1>(Pack<1>{{nbad}}, Pack<1>{{0.0}}, SumOp<1>(), s_scanA, tb);
+  if (!cl_gather<1, false>(cl, tb, s_x, s_ok)) return -1;
+  Pack<1> om, mt;
+  cl_prefix<1, 1>(s_x, 0, cl.g, cl.G, Pack<1>{{0.0}}, SumOp<1>(), om, mt);
+  const int M = (int)mt.v[0];
+  int P2 = 1;
+  while (P2 < M) P2 <<= 1;
+  if (16 * P2 > cap) return cl_bitonic<NT>(Ig, cl, xo, oko);     // every member takes the same branch
+  // compaction in position order: key, slot, and the position it leaves
+  WAKE_GLOBAL double* const br = gptr(I.bt_r);
+  WAKE_GLOBAL int32_t* const bi = gptr(I.bt_i);
+  WAKE_GLOBAL int32_t* const bs = gptr(I.bt_s);
+  WAKE_GLOBAL int32_t* const fp = gptr(I.sm_i);
+  int j = (int)om.v[0] + (int)ob.v[0];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (bad & (1u << k)) {
+      br[j] = L_r[q0 + k];
+      bi[j] = (int32_t)(L_k[q0 + k] >> 32);
+      bs[j] = (int32_t)(uint32_t)L_k[q0 + k];
+      fp[j] = goff + q0 + k;
+      ++j;
+    }
+  }
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
+  if (cl.g == 0) {
+    double* const K_r = L_r;
+    int32_t* const K_i = reinterpret_cast<int32_t*>(K_r + P2);
+    int32_t* const K_s = K_i + P2;
+    for (int i = tid; i < P2; i += NT) {
+      K_r[i] = i < M ? br[i] : INFINITY;
+      K_i[i] = i < M ? bi[i] : 0x7fffffff;
+      K_s[i] = i < M ? bs[i] : -1;
+    }
+    __syncthreads();
+    bitonic_keys<NT>(K_r, K_i, K_s, P2);
+    for (int i = tid; i < M; i += NT) bs[i] = K_s[i];
+  }
+  if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
+  // the j-th smallest moving ring to the j-th freed position (this member's)
+  const int m0 = (int)om.v[0], m1 = m0 + (int)tb.v[0];
+  for (int i = m0 + tid; i < m1; i += NT) perm[cl_slot<NT>(fp[i], C, P, iC, iP)] = bs[i];
+  return cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok) ? cl.round : -1;
+}
+
 // Sort the M compacted keys in sk[0]: pieces of WAKE_SORTCAP sorted in LDS,
 // then pairwise merges by rank (each key's place in the other run found by
 // binary search).  Returns the buffer index holding the result.
@@ -1416,7 +1548,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         // disorder inside members only: up to two member-local block rounds
         // (members in order skip them); across member boundaries, or left
         // over, block rounds over all members; after two of these that leave
-        // disorder, the full sort
+        // disorder the sort by segments, then the bitonic network
         restage = false;
         if (bnd == 0.0 && fix_rounds < 2 && cl_rounds == 0) {
           if (my_dis == 0.0) {
@@ -1429,12 +1561,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         } else {
           int r = -1;
           if (cl_rounds < 2) {
-            r = cl_fix_round<NT>(as_global(I), cl, xo, oko, ident);
+            r = cl_fix_round<NT>(as_global(I), cl, xo, oko, ident, 16 * P <= lo_cap ? lo : -1);
             if (r >= 0) {
               still = (r & 1) ? 1.0 : 0.0;
               r >>= 1;
             }
-          } else {
+          } else if (cl_rounds == 2 && C <= 16 && 16 * P <= lo_cap) {
+            r = cl_segments<NT>(as_global(I), cl, xo, oko, lo, lo_cap);
+          } else {             // exact in any case: the round after it finds the order complete
             r = cl_bitonic<NT>(as_global(I), cl, xo, oko);
           }
           if (r < 0) {

@@ -81,3 +81,30 @@ def test_batched_instances_full_size(wk):
     for i in (picks[0], picks[len(picks) // 2], picks[-1]):   # smallest, median, largest
         inst = insts[i]
         _check_slice(wk, inst, 800, _perturbed(inst, 10 + i, 0.01), f"batched[{i}]")
+
+
+def test_laser_witness_region_matches_split_launches(wk):
+    """The 200000-ring laser case through the start of its witness region
+    (slices 4000-4100 of 8000), where pushed rings cross hundreds of
+    neighbours and the march's order fix-up goes past its block rounds to the
+    sort by segments: one launch is bitwise the march split into launches of
+    ten slices, whose prologues order each launch's start from scratch."""
+    inst = W.config5()
+    _say("laser 200000 rings: one launch vs launches of 10 slices through slice 4100")
+    a = wk.WakeSolver.from_instance(inst)
+    a.wake_solve(0, 4100)
+    b = wk.WakeSolver.from_instance(inst)
+    b.wake_solve(0, 4000)
+    for n in range(4000, 4100, 10):
+        b.wake_solve(n, 10)
+    assert a.wake_status()[0] == -1 and b.wake_status()[0] == -1
+    la, lb = a.wake_lineout(), b.wake_lineout()
+    assert np.array_equal(la[0][:4100], lb[0][:4100]) and np.array_equal(la[1][:4100], lb[1][:4100])
+    fa, fb = a.wake_fields(-1), b.wake_fields(-1)
+    for q in FIELDS + ("rho",):
+        assert np.array_equal(fa[q], fb[q]), q
+    sa, sb = a.wake_get_state(), b.wake_get_state()
+    for q in ("rho", "ur", "f_rho", "f_u"):
+        assert np.array_equal(sa[q], sb[q]), q
+    a.close()
+    b.close()
