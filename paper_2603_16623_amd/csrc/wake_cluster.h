@@ -395,8 +395,9 @@ __device__ __noinline__ int cl_bitonic(const WAKE_GLOBAL WakeInst* Ig, Cluster c
 // writes perm (position slot -> slot).  Blocks of 256 positions sorted by
 // single waves of all members at offsets 0, 256, ... and then 128, 384, ...
 // (the two phases order every ring within 128 positions of its place), the
-// order checked across all positions, at most two such rounds, then the
-// bitonic fallback.  Returns false when a member gave up.
+// order checked across all positions, at most two such rounds.  Returns -1
+// when a member gave up, else twice the barrier count plus whether disorder
+// remains (the caller then runs a fallback sort).
 template <int NT>
 __device__ __noinline__ int cl_fix(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, int xo, int oko) {
   const WakeInst& I = *(const WakeInst*)Ig;
@@ -427,9 +428,9 @@ __device__ __noinline__ int cl_fix(const WAKE_GLOBAL WakeInst* Ig, Cluster cl, i
     if (!cl_gather<1>(cl, Pack<1>{{(double)bad}}, s_x, s_ok)) return -1;
     double any = 0.0;
     for (int m = 0; m < cl.G; ++m) any += s_x[m];
-    if (any == 0.0) return cl.round;
+    if (any == 0.0) return 2 * cl.round;
   }
-  return cl_bitonic<NT>(Ig, cl, xo, oko);
+  return 2 * cl.round + 1;
 }
 
 // One in-loop round of the cooperative fix-up over all members (first: this

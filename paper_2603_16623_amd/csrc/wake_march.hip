@@ -1421,12 +1421,18 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       gptr(I.gk_r)[sl] = st_rho(SB, sl);
       gptr(I.gk_i)[sl] = WAKE_ID(st_hs(SB, sl));
     }
-    const int r = cl_fix<NT>(as_global(I), cl, xo, oko);
+    int r = cl_fix<NT>(as_global(I), cl, xo, oko);
+    if (r >= 0 && (r & 1)) {      // the block rounds left disorder
+      cl.round = r >> 1;
+      r = C <= 16 && 16 * P <= lo_cap ? cl_segments<NT>(as_global(I), cl, xo, oko, lo, lo_cap)
+                                      : cl_bitonic<NT>(as_global(I), cl, xo, oko);
+      if (r >= 0) r <<= 1;
+    }
     if (r < 0) {
       if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
       return;
     }
-    cl.round = r;
+    cl.round = r >> 1;
     ident = false;
     for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(gperm[goff + k * NT + tid]);
   } else if (lds_keys) {
