@@ -296,11 +296,13 @@ def main():
             max_sustainable_rate_per_s=capacity / C4_MEAN_WORK, **run)
     if args.large:
         # the large single instances on the cooperative (multi-workgroup) path,
-        # four rings per member thread (more members per instance: lower
-        # latency of one solve; the served form keeps the default eight,
-        # which gives it more throughput)
+        # two rings per member thread (more members per instance: lower
+        # latency of one solve, 20000 rings: 57 us per slice against 61 with
+        # four and 78 with eight; the served form keeps the default eight,
+        # which gives it more throughput; 200000 rings need seven, the
+        # fewest that keep within 64 members)
         log("large instances")
-        wake.wake_set_cluster(4, 0)
+        wake.wake_set_cluster(2, 0)
         big = {}
         for name, mk in (("blowout 20000 rings x 4000 slices", W.config2),
                          ("laser 200000 rings x 8000 slices", W.config5)):
