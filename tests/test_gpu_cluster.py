@@ -243,3 +243,32 @@ def test_cluster_members_wait_for_busy_workgroups(wk):
     b.close()
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("u_amp", [0.5, 40.0])
+def test_cluster_fixups_in_device_memory(wk, u_amp):
+    """Members whose keys exceed the LDS area (1024-thread workgroups, eight
+    rings per thread: 8192 positions per member) fix their order in device
+    memory: member-local rounds, rounds over all members and the bitonic
+    network, after pushes that move rings a few to thousands of places."""
+    rng = np.random.default_rng(37)
+    inst = W.small_instance(8, n_rings=17000, n_xi=20, n_peak=3.0, sigma_r=0.2, geometric=False, dxi=0.02)
+    o = _oracle(inst)
+    state = o.initial_state()
+    state["u"] = rng.normal(0, u_amp, inst.n_rings)
+    n = 8
+    _, mid = o.slice(n, state, keep=True)
+    ref, _ = o.slice(n + 1, mid, keep=True)
+    F = _field_scale(ref)
+    wk.wake_set_tiling(1024, 0)
+    wk.wake_set_cluster(8, 500)
+    _say(f"cluster fix-ups in device memory u_amp={u_amp}")
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    assert s.layout() == (3, 8)
+    s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(n, 2)
+    got = s.wake_fields(n + 1)
+    for q in FIELDS:
+        assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
+    assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
+    s.close()
