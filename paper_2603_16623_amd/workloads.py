@@ -94,6 +94,13 @@ class GaussianLaser:
     kind: str = "laser"
 
 
+def channel_density(r0: np.ndarray, w0: float) -> np.ndarray:
+    """Parabolic channel n(r)/n0 = 1 + 4 r^2 / w0^4 (lengths in k_p^-1), the
+    radial profile of the paper's laser-driven benchmark (Sec. "Validation
+    benchmarks"), sampled at the rings' initial radii."""
+    return 1.0 + 4.0 * np.asarray(r0, dtype=np.float64) ** 2 / w0 ** 4
+
+
 def beam_number(n_peak: float, sigma_r: float, sigma_xi: float) -> float:
     """Physical particle count (units n0 k_p^-3) of a bi-Gaussian of peak n_peak."""
     return n_peak * (2.0 * math.pi) ** 1.5 * sigma_r ** 2 * sigma_xi
@@ -140,8 +147,9 @@ class Instance:
 
 
 def config1(seed: int = 1, n_part: int = 10_000, analytic: bool = False,
-            n_peak: float = 0.05) -> Instance:
-    """Linear regime: 1000 uniform rings to r=5, weak bi-Gaussian driver."""
+            n_peak: float = 0.05, channel_w0: Optional[float] = None) -> Instance:
+    """Linear regime: 1000 uniform rings to r=5, weak bi-Gaussian driver
+    (in a parabolic channel with channel_w0)."""
     r0, dr = uniform_rings(1000, 5.0)
     sr, sx, xc = 0.1, 0.5, 2.0
     if analytic:
@@ -149,7 +157,8 @@ def config1(seed: int = 1, n_part: int = 10_000, analytic: bool = False,
     else:
         rng = np.random.default_rng(seed)
         src = [gaussian_particles(rng, n_part, n_peak, sr, sx, xc)]
-    return Instance("linear-1000x1200", r0, dr, 0.01, 1200, src)
+    dens = None if channel_w0 is None else channel_density(r0, channel_w0)
+    return Instance("linear-1000x1200", r0, dr, 0.01, 1200, src, dens)
 
 
 def config2(seed: int = 2) -> Instance:
@@ -238,8 +247,10 @@ def config5(seed: int = 5) -> Instance:
 def small_instance(seed: int, n_rings: int = 96, n_xi: int = 60,
                    n_peak: float = 2.0, sigma_r: float = 0.15,
                    geometric: bool = True, laser: bool = False,
-                   n_part: int = 3000, dxi: float = 0.02) -> Instance:
-    """Small nonlinear instance for parity tests (several tiles, ragged tail)."""
+                   n_part: int = 3000, dxi: float = 0.02,
+                   channel_w0: Optional[float] = None) -> Instance:
+    """Small nonlinear instance for parity tests (several tiles, ragged tail);
+    with channel_w0, a parabolic channel instead of uniform density."""
     rng = np.random.default_rng(seed)
     if geometric:
         r0, dr = geometric_rings(n_rings, 2e-3, 3.0)
@@ -250,4 +261,5 @@ def small_instance(seed: int, n_rings: int = 96, n_xi: int = 60,
     src: List[object] = [gaussian_particles(rng, n_part, n_peak, sigma_r, sx, xc)]
     if laser:
         src.append(GaussianLaser(1.0, 1.0, 0.6, 0.8))
-    return Instance(f"small-{n_rings}x{n_xi}", r0, dr, dxi, n_xi, src)
+    dens = None if channel_w0 is None else channel_density(r0, channel_w0)
+    return Instance(f"small-{n_rings}x{n_xi}", r0, dr, dxi, n_xi, src, dens)

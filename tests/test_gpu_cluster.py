@@ -47,17 +47,21 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b))) / (s if s > 0 else 1.0)
 
 
-def _inst(n=3000, n_xi=60):
-    return W.small_instance(5, n_rings=n, n_xi=n_xi, n_peak=3.0, sigma_r=0.2, geometric=False, dxi=0.02)
+def _inst(n=3000, n_xi=60, channel_w0=None):
+    return W.small_instance(5, n_rings=n, n_xi=n_xi, n_peak=3.0, sigma_r=0.2, geometric=False, dxi=0.02,
+                            channel_w0=channel_w0)
 
 
-# (threads, rings per thread): members = ceil(3000 / (threads * rings))
-LAYOUTS = [((256, 0), 2, 6), ((512, 0), 1, 6), ((512, 0), 4, 2)]
+# (threads, rings per thread): members = ceil(3000 / (threads * rings)); the
+# last case in a parabolic channel (n = 1 + 4 r^2/w0^4, w0 = 2)
+LAYOUTS = [((256, 0), 2, 6, None), ((512, 0), 1, 6, None), ((512, 0), 4, 2, None),
+           ((256, 0), 2, 6, 2.0)]
 
 
-@pytest.mark.parametrize("tiling,rings,members", LAYOUTS)
-def test_cluster_slice_parity(wk, tiling, rings, members):
-    inst = _inst()
+@pytest.mark.parametrize("tiling,rings,members,channel_w0", LAYOUTS,
+                         ids=["256x2", "512x1", "512x4", "256x2-channel"])
+def test_cluster_slice_parity(wk, tiling, rings, members, channel_w0):
+    inst = _inst(channel_w0=channel_w0)
     o = _oracle(inst)
     wk.wake_set_tiling(*tiling)
     wk.wake_set_cluster(rings, 500)
@@ -71,7 +75,8 @@ def test_cluster_slice_parity(wk, tiling, rings, members):
         at = n
         ref, new = o.slice(n, state, keep=True)
         F = _field_scale(ref)
-        _say(f"cluster slice parity tiling={tiling} rings={rings} members={members} slice={n} F={F:.3e}")
+        _say(f"cluster slice parity tiling={tiling} rings={rings} members={members} "
+             f"channel={channel_w0} slice={n} F={F:.3e}")
         s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
         s.wake_solve(n, 1)
         got = s.wake_fields(n)
@@ -272,3 +277,4 @@ def test_cluster_fixups_in_device_memory(wk, u_amp):
         assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
     assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
     s.close()
+

@@ -77,6 +77,9 @@ def _case(name):
         return W.small_instance(8, n_rings=257, n_xi=200, n_peak=1.0, laser=True, dxi=0.01)
     if name == "uniform-linear":
         return W.config1(analytic=False, n_part=4000)
+    if name == "laser-channel":   # parabolic channel, three times the axis density at the edge
+        return W.small_instance(10, n_rings=700, n_xi=200, n_peak=1.0, laser=True, dxi=0.01,
+                                channel_w0=2.0)
     if name == "multitile-1200":
         return W.small_instance(9, n_rings=1200, n_xi=150, n_peak=3.0, sigma_r=0.2, dxi=0.01)
     raise KeyError(name)
@@ -89,6 +92,7 @@ SLICE_CASES = [
     ("blowout-geometric", (1024, 0), (0, 90, 150)),          # 1 ring per thread, idle threads
     ("laser-beam", (512, 0), (0, 40, 100, 170)),
     ("uniform-linear", (512, 0), (0, 250, 700)),
+    ("laser-channel", (256, 0), (0, 50, 120, 190)),          # 3 rings per thread, ragged
     ("multitile-1200", (256, 0), (0, 70, 120)),              # 5 rings per thread
     ("multitile-1200", (512, 0), (100,)),
     ("multitile-1200", (1024, 0), (110,)),
@@ -148,6 +152,27 @@ def test_linear_end_to_end(wk):
     last = s.wake_fields(-1)
     for q in FIELDS:
         assert _rel(last[q], ref["snap"][inst.n_xi - 1][q]) <= TOL_E2E
+    s.close()
+
+
+def test_linear_channel_end_to_end(wk):
+    """Linear driver in a parabolic channel (n = 1 + 4 r^2/w0^4, k_p w0 = 3.4,
+    the laser benchmark's profile): density-scaled weights and ion tables."""
+    wk.wake_set_tiling(512, 0)
+    inst = W.config1(channel_w0=3.4)
+    _say("e2e linear channel 1000x1200")
+    ref = _oracle(inst).run(record_stride=300)
+    s = wk.WakeSolver.from_instance(inst, record_stride=300)
+    s.wake_solve(0, inst.n_xi)
+    assert s.wake_status() == (-1, inst.n_xi)
+    lp, le = s.wake_lineout()
+    assert _rel(lp, ref["axis"][:, 0]) <= TOL_E2E
+    assert _rel(le, ref["axis"][:, 1]) <= TOL_E2E
+    for n in range(0, inst.n_xi, 300):
+        got = s.wake_fields(n)
+        for q in FIELDS:
+            assert _rel(got[q], ref["snap"][n][q]) <= TOL_E2E, (n, q)
+        assert _rel(got["ur"], ref["snap"][n]["u"]) <= TOL_E2E
     s.close()
 
 

@@ -122,9 +122,13 @@ def test_dzeta_psi_matches_pairwise_sum():
 
 
 def test_unperturbed_plasma_has_zero_fields():
-    """No sources: the electron and ion sums cancel exactly and rings stay."""
+    """No sources: the electron and ion sums cancel exactly and rings stay,
+    for uniform density and in a parabolic channel (weights scaled by n(r0))."""
+    cases = []
     for r0, dr in (W.uniform_rings(300, 5.0), W.geometric_rings(300, 1e-3, 6.0)):
-        o = O.RingOracle(r0, dr, 0.01, 25, [])
+        cases += [(r0, dr, None), (r0, dr, W.channel_density(r0, 2.0))]
+    for r0, dr, dens in cases:
+        o = O.RingOracle(r0, dr, 0.01, 25, [], dens)
         res = o.run(record_stride=1)
         assert res["breakdown"] == -1
         for n, snap in res["snap"].items():
@@ -336,13 +340,14 @@ def test_linear_laser_wake_closed_form():
 # ---------------------------------------------------------------------------
 # convergence and Maxwell consistency in the nonlinear regime
 # ---------------------------------------------------------------------------
-def _nonlinear(n_rings=60, dxi=0.01, xi_end=3.0, n_peak=1.5, laser=False):
+def _nonlinear(n_rings=60, dxi=0.01, xi_end=3.0, n_peak=1.5, laser=False, channel_w0=None):
     r0, dr = W.geometric_rings(n_rings, 0.01, 3.0)
     src = [W.GaussianBeam(-1.0, n_peak, 0.3, 0.4, 1.2)]
     if laser:
         src.append(W.GaussianLaser(1.2, 1.0, 0.5, 0.8))
     n_xi = int(round(xi_end / dxi)) + 1
-    return O.RingOracle(r0, dr, dxi, n_xi, src)
+    dens = None if channel_w0 is None else W.channel_density(r0, channel_w0)
+    return O.RingOracle(r0, dr, dxi, n_xi, src, dens)
 
 
 def test_ab2_is_second_order():
@@ -458,6 +463,24 @@ def _ampere_error(o, slices):
 def test_bp_matches_integrated_ampere_law(laser):
     o = _nonlinear(dxi=0.002, xi_end=2.0, laser=laser, n_rings=40)
     assert _ampere_error(o, [300, 500, 700]) < 1.5e-3
+
+
+def test_channel_wake_keeps_the_axis_and_ampere_pins():
+    """Parabolic channel (n = 1 + 4 r^2/w0^4, w0 = 2, three times the axis
+    density at the edge): E_z = d_xi psi on the axis and the integrated
+    Ampere law hold with the density-scaled weights, and the wake differs
+    from the uniform plasma's (the profile reaches the fields)."""
+    o = _nonlinear(dxi=0.002, xi_end=2.0, laser=True, n_rings=40, channel_w0=2.0)
+    assert o.w[-1] / _nonlinear(n_rings=40).w[-1] > 3.0
+    assert _ampere_error(o, [300, 500, 700]) < 1.5e-3
+    o = _nonlinear(dxi=0.002, xi_end=2.5, laser=True, channel_w0=2.0)
+    ax = o.run(record_stride=0)["axis"]
+    fd = (ax[2:, 0] - ax[:-2, 0]) / (2 * o.dxi)
+    scale = np.abs(ax[:, 1]).max()
+    assert scale > 0.05
+    assert np.max(np.abs(fd - ax[1:-1, 1])) < 2e-4 * scale
+    flat = _nonlinear(dxi=0.002, xi_end=2.5, laser=True).run(record_stride=0)["axis"]
+    assert np.max(np.abs(flat[:, 1] - ax[:, 1])) > 0.05 * scale
 
 
 # ---------------------------------------------------------------------------
