@@ -50,6 +50,11 @@ Readings taken where the paper is silent, garbled or self-inconsistent
   R14 (numerics, not model) ln rho is evaluated as ln r0 + log1p((rho-r0)/r0)
       so that its rounding, multiplied by the enclosed charge in eq. psi,
       stays proportional to the ring displacement.
+  R16 fields at radii off the rings (Fig. 2, external grid): the same sums
+      with no ring at the radius (no w^ term, no own-ring share), B^(p) from
+      the interval's (a, b); a ring at exactly that radius counts as
+      outside.  The field grid is uniform with nodes at cell centres
+      (g + 1/2) r_max / n_r.
 """
 from __future__ import annotations
 
@@ -366,6 +371,13 @@ def forces(u, psibar, gamma, dpsi, bt, da2, q=Q_E, m=M_E):
     return f_rho, f_u
 
 
+def grid_radii(n_r, r_max):
+    """Nodes of a uniform radial field grid: cell centres (g + 1/2) dr_g,
+    dr_g = r_max / n_r (reading R16)."""
+    dg = float(r_max) / int(n_r)
+    return (np.arange(int(n_r), dtype=np.float64) + 0.5) * dg
+
+
 # ---------------------------------------------------------------------------
 # driver (Fig. 2 right column)
 # ---------------------------------------------------------------------------
@@ -465,26 +477,69 @@ class RingOracle:
                        dpsi_sorted=dpsi, dzpsi_sorted=dzpsi, bp=bp)
         return out, new
 
-    def run(self, first=0, count=None, state=None, record_stride=1):
+    def fields_at(self, n, out, radii):
+        """psi, E_r - B_theta, E_z and B_theta of slice n at arbitrary radii
+        r > 0 (Sec. "Numerical integration of wakefields": eqs. psi, dpsi_dr,
+        dpsi_dzeta and b_theta_plasma hold at any radius of the column once
+        the rings are known; Fig. 2, fields on an external grid).  ``out``
+        is the slice's result with keep=True.  A radius with k rings
+        strictly inside it lies in interval k of the recursion: a ring at
+        exactly r counts as outside (reading R16).  Returns a dict of
+        binary64 arrays."""
+        ids = out["order"]
+        rho = out["rho"][ids]
+        u = out["u"][ids]
+        w = self.w[ids]
+        r = np.asarray(radii, np.float64)
+        k = np.searchsorted(rho, r, side="left")
+        w_l = w.astype(LD)
+        lnr_k = ring_log(rho, self.r0[ids])                          # R14
+        S = np.concatenate([np.zeros(1, LD), np.cumsum(w_l)])          # sum_{j<k} w_j
+        wl = w_l * lnr_k
+        T = np.concatenate([np.cumsum(wl[::-1])[::-1], np.zeros(1, LD)])   # sum_{j>=k} w ln rho
+        r_l = r.astype(LD)
+        psi_e = -Q_E * (S[k] * np.log(r_l) + T[k])                     # eq. psi
+        dpsi_e = -Q_E * S[k] / r_l                                     # eq. dpsi_dr
+        psi_i, dpsi_i = self.ions.at(r_l)                              # R11
+        c = w_l * (Q_E * u / (rho * out["psibar"])).astype(LD)
+        V = np.concatenate([np.cumsum(c[::-1])[::-1], np.zeros(1, LD)])   # eq. dpsi_dzeta, R2
+        bb, _, _ = self.sources_at(n, r)
+        bt = bb + out["a"][k] * r + out["b"][k] / r                   # eq. b_theta_plasma
+        return dict(psi=(psi_e + psi_i).astype(np.float64),
+                    er_bt=(-(dpsi_e + dpsi_i)).astype(np.float64),
+                    ez=(-V[k]).astype(np.float64), bt=bt)
+
+    def run(self, first=0, count=None, state=None, record_stride=1, grid=None):
         """March slices [first, first+count).  Returns a dict with per-slice
         on-axis lineouts, snapshots every ``record_stride`` slices (by ring
-        id), the final state and the breakdown slice (-1 if none)."""
+        id), the final state and the breakdown slice (-1 if none); with
+        ``grid = (n_r, r_max)`` also the fields at the grid_radii nodes of
+        every slice, 'grid' of shape [count][4][n_r] (psi, E_r - B_theta,
+        E_z, B_theta)."""
         if count is None:
             count = self.n_xi - first
         if state is None:
             state = self.initial_state()
         rec = {}
         axis = np.full((count, 2), np.nan)
+        gr = None if grid is None else grid_radii(*grid)
+        gfield = None if grid is None else np.full((count, 4, len(gr)), np.nan)
         breakdown = -1
         for k in range(count):
             n = first + k
-            out, new = self.slice(n, state, push=(n < self.n_xi - 1))
+            out, new = self.slice(n, state, push=(n < self.n_xi - 1), keep=grid is not None)
             if out["status"] != 0:
                 breakdown = n
                 break
             axis[k] = (out["psi_axis"], out["ez_axis"])
+            if grid is not None:
+                f = self.fields_at(n, out, gr)
+                gfield[k] = [f["psi"], f["er_bt"], f["ez"], f["bt"]]
             if record_stride and (n % record_stride == 0 or k == count - 1):
                 rec[n] = {q: out[q] for q in ("psi", "er_bt", "ez", "bt", "rho", "u")}
             if new is not None:
                 state = new
-        return dict(axis=axis, snap=rec, state=state, breakdown=breakdown)
+        res = dict(axis=axis, snap=rec, state=state, breakdown=breakdown)
+        if grid is not None:
+            res["grid"] = gfield
+        return res
