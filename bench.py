@@ -45,9 +45,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_batch(wake, insts, stream):
+def build_batch(wake, insts, stream, grid=None):
     solvers = [wake.WakeSolver.from_instance(inst, stream=stream) for inst in insts]
     for s in solvers:
+        if grid is not None:
+            s.wake_set_grid(*grid)
         s.wake_prepare()
     batch = wake.WakeBatch(solvers, stream=stream)
     return solvers, batch
@@ -147,6 +149,10 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tiling", type=str, default="")
+    ap.add_argument("--grid-nodes", type=int, default=64,
+                    help="field-grid nodes per instance for the grid measurement (0: skip it)")
+    ap.add_argument("--grid-r", type=float, default=1.0, help="field-grid radius")
+    ap.add_argument("--grid-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="arrival window of the served run (0: skip)")
@@ -264,6 +270,28 @@ def main():
         "batched_vs_plain": value / plain_value,
         "roofline": roof,
     }
+    if args.grid_nodes > 0:
+        # the same batch with a radial field grid on every instance: the
+        # fields at grid_nodes cell-centred nodes to r = grid_r, every slice
+        log("field grid")
+        gsolvers, gbatch = build_batch(wake, insts, stream, grid=(args.grid_nodes, args.grid_r))
+        gbatch.wake_batch_capture()
+        gbatch.wake_batch_replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.grid_steps):
+            gbatch.wake_batch_replay()
+            torch.cuda.synchronize()
+            log("grid step done")
+        gstep = (time.perf_counter() - tg) / args.grid_steps
+        out["field_grid"] = dict(
+            nodes=args.grid_nodes, r_max=args.grid_r, steps=args.grid_steps,
+            value=work / gstep, unit="ring-slice updates/s", ms_per_step=gstep * 1e3,
+            vs_without_grid=(work / gstep) / value,
+            node_updates_per_s=args.n_inst * args.n_xi * args.grid_nodes / gstep)
+        gbatch.close()
+        for s in gsolvers:
+            s.close()
     if args.served_seconds > 0:
         # capacity: sustained ring-slice rate of the server on the request mix
         # while it is saturated (a backlog of requests submitted at once)

@@ -128,6 +128,26 @@ int wake_solve(wake_ctx *ctx, int32_t first_slice, int32_t n_slices);
 int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, double *ez,
                 double *bt, double *rho, double *ur, int32_t dst_is_device);
 
+/* Radial field grid (Fig. 2 of the paper, the fields on an external grid
+ * that couples the plasma to the beams; eqs. psi, dpsi_dr, dpsi_dzeta and
+ * b_theta_plasma hold at any radius once the rings of a slice are known).
+ * n_r uniform nodes at cell centres r_g = (g + 1/2) r_max / n_r,
+ * g = 0..n_r-1; every marched slice also writes psi, E_r - B_theta, E_z
+ * and B_theta at them (4 n_r doubles per slice, n_xi slices, held on the
+ * device by the context; not counted by wake_footprint).  A node with k
+ * rings strictly inside it takes the sums of the rings below and above,
+ * with no ring at the node; a ring exactly at a node counts as outside it.
+ * Only before the first solve (WAKE_ESTATE after); n_r = 0 removes the
+ * grid.  n_r <= 2^20, r_max > 0 finite (WAKE_EINVAL).  Synchronous. */
+int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
+
+/* Grid fields of one solved slice [n_r each] (slice = -1: the last slice
+ * of the most recent solve): WAKE_ESTATE without a grid or for a slice not
+ * solved yet, WAKE_EBREAKDOWN at or after a breakdown.  NULL outputs are
+ * skipped.  Synchronizes the context's stream. */
+int wake_grid_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, double *ez,
+                     double *bt, int32_t dst_is_device);
+
 /* psi(0) and E_z(0) of every slice [n_xi each]; slices not solved yet hold
  * stale values.  Synchronizes. */
 int wake_lineout(wake_ctx *ctx, double *psi_axis, double *ez_axis, int32_t dst_is_device);

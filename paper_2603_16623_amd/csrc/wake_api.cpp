@@ -129,6 +129,7 @@ static void release(wake_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->arena.base) (void)hipFree(c->arena.base);
   if (c->beam_mem) (void)hipFree(c->beam_mem);
+  if (c->grid_mem) (void)hipFree(c->grid_mem);
   if (c->d_inst) (void)hipFree(c->d_inst);
   if (c->d_counter) (void)hipFree(c->d_counter);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -387,7 +388,7 @@ static int launch_one(wake_ctx* c, int first, int count) {
   I.count = count;
   I.task0 = 0;
   HIP_TRY(hipMemcpyAsync(c->d_inst, &I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_march(I.nt, c->d_inst, 1, I.G, c->d_counter, I.G, c->stream));
+  HIP_TRY(launch_march(I.nt, c->d_inst, 1, I.G, c->d_counter, I.G, I.grid_n > 0, c->stream));
   return WAKE_OK;
 }
 
@@ -454,6 +455,62 @@ extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt
   double* outs[OUT_N] = {psi, erbt, ez, bt, rho, ur};
   for (int q = 0; q < OUT_N; ++q) {
     r = copy_out(outs[q], base + q * N, N, dev, c->stream);
+    if (r != WAKE_OK) return r;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
+  if (!c) return WAKE_EINVAL;
+  if (n_r < 0 || n_r > (1 << 20) || (n_r > 0 && !finite_pos(r_max))) return WAKE_EINVAL;
+  if (c->next != 0) return WAKE_ESTATE;
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  WakeInst& I = c->I;
+  if (c->grid_mem) {
+    HIP_TRY(hipFree(c->grid_mem));
+    c->grid_mem = nullptr;
+  }
+  I.grid_n = 0;
+  I.grid_dr = 0.0;
+  I.grid = nullptr;
+  I.grid_tab = nullptr;
+  if (n_r == 0) return WAKE_OK;
+  const size_t nf = (size_t)4 * n_r * (size_t)I.n_xi;
+  HIP_TRY(hipMalloc(&c->grid_mem, sizeof(double) * (nf + WAKE_GRID_TAB * (size_t)n_r)));
+  I.grid_n = n_r;
+  I.grid_dr = r_max / (double)n_r;
+  I.grid = c->grid_mem;
+  I.grid_tab = c->grid_mem + nf;
+  HIP_TRY(launch_grid_init(I, c->grid_mem + nf, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+extern "C" int wake_grid_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt, double* ez,
+                                double* bt, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  const WakeInst& I = c->I;
+  if (I.grid_n <= 0) return WAKE_ESTATE;
+  int32_t ctl[CTL_NWORDS];
+  int r = read_ctl(c, ctl);
+  if (r != WAKE_OK) return r;
+  const int brk = ctl[CTL_BREAK];
+  if (slice == -1) {
+    if (brk >= 0) return WAKE_EBREAKDOWN;
+    if (c->next == 0) return WAKE_ESTATE;
+    slice = c->next - 1;
+  }
+  if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
+  if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
+  if (slice >= c->next) return WAKE_ESTATE;
+  const size_t ng = I.grid_n;
+  const double* base = I.grid + (size_t)slice * 4 * ng;
+  double* outs[4] = {psi, erbt, ez, bt};
+  for (int q = 0; q < 4; ++q) {
+    r = copy_out(outs[q], base + q * ng, ng, dev, c->stream);
     if (r != WAKE_OK) return r;
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -684,12 +741,13 @@ hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts,
   for (const WakeInst& I : v) n_tasks += I.G;
   for (int nt : kThreads) {
     int n = 0, gmax = 1;
+    bool with_grid = false;
     for (const WakeInst& I : v)
-      if (I.nt == nt) { n += I.G; gmax = std::max(gmax, (int)I.G); }
+      if (I.nt == nt) { n += I.G; gmax = std::max(gmax, (int)I.G); with_grid |= I.grid_n > 0; }
     if (n == 0) continue;
     int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, dev);
     g = std::max(g, gmax);
-    hipError_t e = launch_march(nt, d_insts, (int)v.size(), n_tasks, d_counter, g, s);
+    hipError_t e = launch_march(nt, d_insts, (int)v.size(), n_tasks, d_counter, g, with_grid, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

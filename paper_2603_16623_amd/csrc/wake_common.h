@@ -8,6 +8,7 @@
 #define WAKE_SORTCAP 1024     // rings of long disordered runs sorted in LDS in one piece
 #define WAKE_SEGMAX 64        // disordered runs up to this length are ranked in place
 #define WAKE_ION_REC 8        // doubles per ion interval record
+#define WAKE_GRID_TAB 6       // doubles per field-grid node record
 
 // Control words of one instance (device memory, int32).
 enum { CTL_CUR = 0, CTL_BREAK = 1, CTL_NEXT = 2, CTL_FAULT = 3, CTL_NWORDS = 4 };
@@ -106,6 +107,14 @@ struct WakeInst {
   double *snap;               // [n_rec][6][N] by ring id
   double *last;               // [6][N] by ring id: last marched slice
   int32_t *ctl;               // [CTL_NWORDS]
+  // radial field grid (none while grid_n is 0): nodes r_g = (g + 1/2)
+  // grid_dr, g < grid_n; fields of every slice [n_xi][4][grid_n] (psi,
+  // E_r - B_theta, E_z, B_theta); per node [grid_n][WAKE_GRID_TAB]: ln r_g,
+  // the ions' psi - psi(0) and d_rho psi at r_g, as dd pairs
+  int32_t grid_n;
+  double grid_dr;
+  double *grid;
+  const double *grid_tab;
 };
 
 // Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c

@@ -21,8 +21,12 @@ hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipSt
 // marcher: workgroups of nt threads (256, 512 or 1024)
 bool march_threads_ok(int nt);
 size_t march_lds_bytes(int nt);
+// with_grid: the variant that also evaluates the fields at the instances'
+// grid nodes (instances without a grid march as in the plain variant)
 hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
-                        int grid, hipStream_t s);
+                        int grid, bool with_grid, hipStream_t s);
+// field-grid node table of I's grid (ln r_g, ion fields at r_g)
+hipError_t launch_grid_init(const WakeInst& I, double* tab, hipStream_t s);
 int march_occupancy(int nt);
 int march_cmax(int nt);     // rings per thread up to which the keys of every position fit LDS
 hipError_t march_prepare(int nt);

@@ -1346,7 +1346,59 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
 // CL: member `member` of a cooperative instance (I.G workgroups); its
 // positions and slots start at goff = member * C * NT, and the slice scans
 // and the order fix-up span all members.
-template <int NT, bool CL>
+// ---------------------------------------------------------------------------
+// radial field grid (Fig. 2: fields on an external grid): the ring solve's
+// sums evaluated at the uniform nodes r_g = (g + 1/2) dg, g < ng.  A node in
+// (rho_{p-1}, rho_p] lies in interval p of the recursion: below it the
+// rings before position p, at and above it the rest.
+// ---------------------------------------------------------------------------
+// The largest node g with r_g <= x (-1 if none), decided on the node radii
+// themselves so that neighbouring intervals split the nodes exactly.
+__device__ __forceinline__ int grid_last_below(double x, double dg, double idg, int ng) {
+  if (!(x >= 0.5 * dg)) return -1;
+  const double t = floor(x * idg - 0.5);      // a guess; the node radii decide
+  int g = t >= (double)(ng - 1) ? ng - 1 : (int)t;
+  if (g < -1) g = -1;
+  while (g + 1 < ng && ((double)(g + 1) + 0.5) * dg <= x) ++g;
+  while (g >= 0 && ((double)g + 0.5) * dg > x) --g;
+  return g;
+}
+
+// psi (eq. psi) and E_r - B_theta = -d_rho psi (eq. dpsi_dr, no ring at r)
+// at node g (radius r) of an interval with the sums S, P of weight and
+// w ln rho below it.  tab: the node's ln r and the immobile ions' fields
+// there (dd pairs, fixed for the solve); out: the slice's [4][ng] block.
+__device__ __forceinline__ void grid_node_psi(WAKE_GLOBAL double* out, int ng, int g, double r,
+                                              const WAKE_GLOBAL double* tab, dd S, dd P,
+                                              double psi_axis) {
+  const D2 t0 = *reinterpret_cast<const WAKE_GLOBAL D2*>(tab + WAKE_GRID_TAB * g);
+  const D2 t1 = *reinterpret_cast<const WAKE_GLOBAL D2*>(tab + WAKE_GRID_TAB * g + 2);
+  const D2 t2 = *reinterpret_cast<const WAKE_GLOBAL D2*>(tab + WAKE_GRID_TAB * g + 4);
+  const dd pe = dd_add_fast(dd_mul(S, dd{t0.x, t0.y}), dd_neg(P));
+  const dd de = dd_div_rcp(S, r, rcp_nr(r));
+  out[g] = dd_round(dd_add_fast(pe, dd{t1.x, t1.y})) + psi_axis;
+  out[ng + g] = -dd_round(dd_add_fast(de, dd{t2.x, t2.y}));
+}
+
+// E_z (eq. dpsi_dzeta: the rings at and above the interval) and
+// B_theta = Lambda/r + a r + b/r (eq. b_theta_plasma) at node g.
+__device__ __forceinline__ void grid_node_b(WAKE_GLOBAL double* out, int ng, int g, double r, double ez,
+                                            double a, double b, double lam) {
+  const double ir = rcp_nr(r);
+  out[2 * ng + g] = ez;
+  out[3 * ng + g] = lam * ir + (a * r + b * ir);
+}
+
+// charge of the analytic beams inside r (staged constants of the slice)
+__device__ __forceinline__ double analytic_lam(const double* s_misc, int n_an, double r) {
+  double lam = 0.0;
+  #pragma unroll 1
+  for (int si = 0; si < n_an; ++si)
+    if (s_misc[3 * si] == 2.0) lam += s_misc[3 * si + 1] * (-expm1(-r * r * s_misc[3 * si + 2]));
+  return lam;
+}
+
+template <int NT, bool CL, bool GRID>
 __device__ __forceinline__ void march(const WakeInst& I, int member, const int32_t* queue, unsigned char* smem) {
   constexpr int NW = NT / 64;
   constexpr int CMAX = MarchLds<NT>::CMAX;
@@ -1407,6 +1459,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
   const int64_t budget = I.budget;
   int cur = __builtin_amdgcn_readfirstlane(I.ctl[CTL_CUR]);
+  double rho_mprev = -1.0;   // field grid, cooperative: radius at the previous member's last position
   __syncthreads();
   // a ring at slot s came from another thread's chunk (or member)
 #define WAKE_FOREIGN(s) ((unsigned)((int)(s) - goff) >= (unsigned)P || (((int)(s) - goff) & (NT - 1)) != tid)
@@ -1532,6 +1585,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       my_dis = t6.v[5];
       cl_prefix<6, 11>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
       pre = SliceHeadOp()(pg, pre);
+      if constexpr (GRID) rho_mprev = member > 0 ? s_x[(member - 1) * 11 + 8] : -1.0;
       double stop = 0.0;
       for (int m = 0; m < cl.G; ++m) {
         stop += s_x[m * 11 + 10];
@@ -1657,6 +1711,19 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       jn = lds_ion ? ion_find(s_ion, N, x_ru.x, hh_hint(x_hh)) : hh_hint(x_hh);
       ion_load(IV, jn, x_q);
     }
+    // field grid, psi and E_r - B_theta: the last node at or below the
+    // position before this thread's first
+    const int ngB = GRID ? I.grid_n : 0;
+    const double dgB = I.grid_dr, idgB = 1.0 / dgB;
+    WAKE_GLOBAL double* const goutB = gptr(I.grid) + (size_t)n * 4 * (size_t)ngB;
+    const WAKE_GLOBAL double* const gtab = gptr(I.grid_tab);
+    int gb_lo = -1;
+    if (GRID && ngB > 0 && cnt > 0) {
+      double rb = -1.0;
+      if (tid > 0) rb = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
+      else if (CL) rb = rho_mprev;
+      gb_lo = grid_last_below(rb, dgB, idgB, ngB);
+    }
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
@@ -1687,6 +1754,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       ion_fields(IV, rho, lnr, h, q, ips, idp);
       const double psi = dd_round(dd_add_fast(pe, ips)) + psi_axis;
       const double dpsi = dd_round(dd_add_fast(de, idp));
+      if (GRID && ngB > 0) {
+        // nodes of interval p = (rho_{p-1}, rho_p]: the sums below position p
+        const int glo = gb_lo + 1;
+        gb_lo = grid_last_below(rho, dgB, idgB, ngB);
+        #pragma unroll 1
+        for (int g = glo; g <= gb_lo; ++g)
+          grid_node_psi(goutB, ngB, g, ((double)g + 0.5) * dgB, gtab, S, PT, psi_axis);
+      }
       S = dd_add_d(S, w);
       PT = PTi;
       // beam charge inside rho (strictly below), analytic beams, lasers
@@ -1734,6 +1809,12 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       // the ring's home slot and hint move to its position slot in the next
       // buffer (pass E takes the home slot from there)
       Sn.stw(RS_HH, goff + sl, hh_pack(hs, h));
+    }
+    if (GRID && ngB > 0 && cnt > 0 && p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
+      // nodes beyond the last ring: every ring below them
+      #pragma unroll 1
+      for (int g = gb_lo + 1; g < ngB; ++g)
+        grid_node_psi(goutB, ngB, g, ((double)g + 0.5) * dgB, gtab, S, PT, psi_axis);
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1823,6 +1904,41 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       v_hs = hh_hs(Sn.ldw(RS_HH, goff + sl));
     }
     if (cnt > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
+    // field grid, E_z and B_theta: the radius before this thread's first
+    // position and the last node at or below its last ring
+    const int ng = GRID ? I.grid_n : 0;
+    const double dg = I.grid_dr, idg = 1.0 / dg;
+    WAKE_GLOBAL double* const gout = gptr(I.grid) + (size_t)n * 4 * (size_t)ng;
+    int ge_hi = -1;
+    double g_lo_r = -1.0;
+    if (GRID && ng > 0 && cnt > 0) {
+      if (tid > 0) g_lo_r = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
+      else if (CL) g_lo_r = rho_mprev;
+      ge_hi = grid_last_below(y_ru.x, dg, idg, ng);
+      // nodes beyond the last ring: interval N (a_N = 0, no ring outside)
+      if (p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
+        const double a = (ha * E - ga * D) * iW, b = (hb * E - gb * D) * iW;
+        int cb = 0;
+        bool gal = false;
+        #pragma unroll 1
+        for (int g = ge_hi + 1; g < ng; ++g) {
+          const double r = ((double)g + 0.5) * dg;
+          double lam = 0.0;
+          if (bm > 0) {
+            if (staged) {
+              cb = count_below(s_br, cb, bm, r, gal);
+              if (cb > 0) lam = s_bc[cb - 1];
+            } else {
+              cb = count_below(gR, cb, bm, r, gal);
+              if (cb > 0) lam = gQ[cb - 1];
+            }
+            gal = true;
+          }
+          lam += analytic_lam(s_misc, n_an, r);
+          grid_node_b(gout, ng, g, r, Vgt, a, b, lam);
+        }
+      }
+    }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
       const unsigned sl = k * NT + tid;
@@ -1913,6 +2029,28 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         nxt_i = id;
       }
       Vgt += L.v;
+      if (GRID && ng > 0) {
+        // nodes of interval p = (rho_{p-1}, rho_p], downward
+        const int ghi = ge_hi;
+        ge_hi = grid_last_below(k > 0 ? y_ru.x : g_lo_r, dg, idg, ng);
+        int cb = bhi;
+        #pragma unroll 1
+        for (int g = ghi; g > ge_hi; --g) {
+          const double r = ((double)g + 0.5) * dg;
+          double lam = 0.0;
+          if (bm > 0) {
+            if (staged) {
+              cb = count_below_down(s_br, cb, bm, r, true);
+              if (cb > 0) lam = s_bc[cb - 1];
+            } else {
+              cb = count_below_down(gR, cb, bm, r, true);
+              if (cb > 0) lam = gQ[cb - 1];
+            }
+          }
+          lam += analytic_lam(s_misc, n_an, r);
+          grid_node_b(gout, ng, g, r, Vgt, a, b, lam);
+        }
+      }
     }
     if (tid == 0 && member == 0) { gptr(I.axis)[2 * n] = psi_axis; gptr(I.axis)[2 * n + 1] = Vtot; }
     // order across chunk boundaries: this chunk's first pushed key (+inf if
@@ -1953,16 +2091,16 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
 
 // the cooperative march as a function of its own (its registers stay out of
 // the single-workgroup march, which is inlined into the kernel)
-template <int NT>
+template <int NT, bool GRID>
 __device__ __noinline__ void march_member(const WAKE_GLOBAL WakeInst* I, int member, const int32_t* queue) {
-  march<NT, true>(*(const WakeInst*)I, member, queue, wake_lds);
+  march<NT, true, GRID>(*(const WakeInst*)I, member, queue, wake_lds);
 }
 
 #ifndef WAKE_WAVES_PER_EU
 #define WAKE_WAVES_PER_EU 2
 #endif
 // WAKE_WAVES_PER_EU waves per SIMD (2: up to 256 VGPRs per lane)
-template <int NT>
+template <int NT, bool GRID>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAKE_WAVES_PER_EU)))
 void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_tasks, int32_t* counter) {
   unsigned char* const smem = wake_lds;
@@ -1981,8 +2119,8 @@ void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_ta
     }
     const WakeInst& I = insts[lo];
     if (I.nt == NT) {
-      if (I.G > 1) march_member<NT>(as_global(I), idx - I.task0, counter);
-      else march<NT, false>(I, 0, counter, smem);
+      if (I.G > 1) march_member<NT, GRID>(as_global(I), idx - I.task0, counter);
+      else march<NT, false, GRID>(I, 0, counter, smem);
     }
     __syncthreads();
   }
@@ -2079,6 +2217,36 @@ hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, co
   return hipGetLastError();
 }
 
+// Field-grid node table: ln r_g and the immobile ions' psi - psi(0) and
+// d_rho psi at r_g (the same interpolation as at the rings), dd pairs.
+__global__ void grid_init_kernel(WakeInst I, double* tab) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.grid_n) return;
+  const double r = ((double)g + 0.5) * I.grid_dr;
+  const dd l = dd_log(r);
+  IonView IV;
+  IV.R = uview(I.ion);
+  IV.N = I.N;
+  IV.Rp = I.Rp;
+  IV.T0 = {I.tot0[0], I.tot0[1]};
+  IV.Q = {I.tot0[2], I.tot0[3]};
+  int h = 0;
+  double q[WAKE_ION_REC];
+  ion_load(IV, h, q);
+  dd ps, dp;
+  ion_fields(IV, r, l, h, q, ps, dp);
+  double* t = tab + (size_t)WAKE_GRID_TAB * g;
+  t[0] = l.hi; t[1] = l.lo;
+  t[2] = ps.hi; t[3] = ps.lo;
+  t[4] = dp.hi; t[5] = dp.lo;
+}
+
+hipError_t launch_grid_init(const WakeInst& I, double* tab, hipStream_t s) {
+  if (I.grid_n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grid_init_kernel, dim3((I.grid_n + 255) / 256), dim3(256), 0, s, I, tab);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(const WakeInst* d_insts, int n_insts, hipStream_t s) {
   if (n_insts <= 0) return hipSuccess;
   hipLaunchKernelGGL(state_reset_kernel, dim3(n_insts), dim3(256), 0, s, d_insts, n_insts);
@@ -2109,13 +2277,17 @@ size_t march_lds_bytes(int nt) {
 }
 
 hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
-                        int grid, hipStream_t s) {
+                        int grid, bool with_grid, hipStream_t s) {
 #define X(a)                                                                                      \
   if (nt == a) {                                                                                  \
     hipLaunchKernelGGL(counter_zero_kernel, dim3(1), dim3(64), 0, s, counter);                     \
     hipLaunchKernelGGL(cluster_reset_kernel, dim3(1), dim3(256), 0, s, d_insts, n_insts);          \
-    hipLaunchKernelGGL((wake_march_kernel<a>), dim3(grid), dim3(a), MarchLds<a>::bytes(), s,       \
-                       d_insts, n_insts, n_tasks, counter);                                        \
+    if (with_grid)                                                                                \
+      hipLaunchKernelGGL((wake_march_kernel<a, true>), dim3(grid), dim3(a), MarchLds<a>::bytes(), \
+                         s, d_insts, n_insts, n_tasks, counter);                                  \
+    else                                                                                          \
+      hipLaunchKernelGGL((wake_march_kernel<a, false>), dim3(grid), dim3(a), MarchLds<a>::bytes(),\
+                         s, d_insts, n_insts, n_tasks, counter);                                  \
     return hipGetLastError();                                                                     \
   }
   WAKE_THREADS(X)
@@ -2135,7 +2307,7 @@ int march_occupancy(int nt) {
   int nb = 0;
 #define X(a)                                                                                      \
   if (nt == a) {                                                                                  \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wake_march_kernel<a>, a,                \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wake_march_kernel<a, false>, a,         \
                                                      MarchLds<a>::bytes()) != hipSuccess)         \
       return 0;                                                                                   \
     return nb;                                                                                    \
@@ -2147,10 +2319,15 @@ int march_occupancy(int nt) {
 
 hipError_t march_prepare(int nt) {
 #define X(a)                                                                                      \
-  if (nt == a)                                                                                    \
-    return hipFuncSetAttribute((const void*)wake_march_kernel<a>,                                 \
+  if (nt == a) {                                                                                  \
+    hipError_t e = hipFuncSetAttribute((const void*)wake_march_kernel<a, false>,                  \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,                \
+                                       (int)MarchLds<a>::bytes());                                \
+    if (e != hipSuccess) return e;                                                                \
+    return hipFuncSetAttribute((const void*)wake_march_kernel<a, true>,                           \
                                hipFuncAttributeMaxDynamicSharedMemorySize,                        \
-                               (int)MarchLds<a>::bytes());
+                               (int)MarchLds<a>::bytes());                                        \
+  }
   WAKE_THREADS(X)
 #undef X
   return hipErrorInvalidValue;

@@ -34,6 +34,7 @@ struct wake_ctx {
   char* beam_mem = nullptr;
   // pending particle sources (host copies until the table is built)
   std::vector<double> px, py, pxi, pw, pq;
+  double* grid_mem = nullptr;  // field grid: fields [n_xi][4][n_r], then the node table
   bool prepared = false;
   int next = 0;
   hipStream_t pending = nullptr;   // batch stream that last marched this context

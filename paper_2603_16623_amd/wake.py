@@ -59,6 +59,8 @@ _SIGS = {
     "wake_solve": (_I, [_P, _I, _I]),
     "wake_fields": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _I]),
     "wake_lineout": (_I, [_P, _P, _P, _I]),
+    "wake_set_grid": (_I, [_P, _I, C.c_double]),
+    "wake_grid_fields": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "wake_get_state": (_I, [_P, C.POINTER(_I), _P, _P, _P, _P, _I]),
     "wake_set_state": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "wake_reset": (_I, [_P]),
@@ -266,6 +268,26 @@ class WakeSolver:
             out = {k: np.empty(self.N) for k in names}
         ptrs = [_ptr(out.get(k)) for k in names]
         _check(self._lib.wake_fields(self.h, slice_, *ptrs, int(device)), "wake_fields")
+        return out
+
+    def wake_set_grid(self, n_r: int, r_max: float = 0.0):
+        """Uniform radial field grid of n_r cell-centred nodes to r_max."""
+        _check(self._lib.wake_set_grid(self.h, int(n_r), float(r_max)), "wake_set_grid")
+        self.grid_n = int(n_r)
+        self.grid_r_max = float(r_max)
+
+    def grid_radii(self):
+        """The grid's node radii (g + 1/2) r_max / n_r."""
+        dg = self.grid_r_max / self.grid_n
+        return (np.arange(self.grid_n, dtype=np.float64) + 0.5) * dg
+
+    def wake_grid_fields(self, slice_: int = -1, out=None, device: bool = False):
+        """dict of psi, er_bt, ez, bt at the grid nodes of a slice."""
+        names = ("psi", "er_bt", "ez", "bt")
+        if out is None:
+            out = {k: np.empty(self.grid_n) for k in names}
+        ptrs = [_ptr(out.get(k)) for k in names]
+        _check(self._lib.wake_grid_fields(self.h, slice_, *ptrs, int(device)), "wake_grid_fields")
         return out
 
     def wake_lineout(self):

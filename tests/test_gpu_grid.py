@@ -1,0 +1,213 @@
+"""GPU parity of the radial field grid (the ring solve's sums at the nodes
+of a uniform cell-centred grid, every slice) against the oracle's
+fields_at, through the C ABI.
+
+Tolerances as for the ring fields: per slice 1e-12 of the slice's field
+scale F_n (psi, E_r - B_theta, E_z, B_theta, B^(b) and the B_theta jumps at
+the rings); end to end 1e-8 of each quantity's largest magnitude.
+"""
+import numpy as np
+import pytest
+
+from oracle.wake_oracle import RingOracle, grid_radii
+from paper_2603_16623_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("psi", "er_bt", "ez", "bt")
+TOL_SLICE = 1e-12
+TOL_E2E = 1e-8
+WAKE_ESTATE = -4
+WAKE_EINVAL = -1
+
+
+@pytest.fixture(scope="module")
+def wk():
+    from paper_2603_16623_amd import wake
+    wake.load()
+    yield wake
+    wake.wake_set_cluster(0, 0)
+    wake.wake_set_tiling(512, 0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _oracle(inst):
+    return RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+
+
+def _scale(ref):
+    parts = [np.abs(ref[q]).max() for q in FIELDS]
+    parts += [np.abs(ref["C"]).max(), np.abs(ref["bb"]).max(), abs(ref["psi_axis"])]
+    return float(max(parts))
+
+
+def _rel(gpu, ref):
+    s = float(np.max(np.abs(ref)))
+    return float(np.max(np.abs(gpu - ref))) / (s if s > 0 else 1.0)
+
+
+def _check_slices(wk, inst, tiling, cluster, n_r, r_max, slices, layout=None):
+    """Inject the oracle's state at each slice, march one slice, compare the
+    grid fields with the oracle's fields at the same nodes."""
+    o = _oracle(inst)
+    wk.wake_set_tiling(*tiling)
+    wk.wake_set_cluster(*cluster)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    if layout is not None:
+        assert s.layout() == layout
+    s.wake_set_grid(n_r, r_max)
+    gr = grid_radii(n_r, r_max)
+    assert np.array_equal(s.grid_radii(), gr)
+    state = o.initial_state()
+    at = 0
+    for n in slices:
+        for m in range(at, n):
+            _, state = o.slice(m, state)
+        at = n
+        ref, _ = o.slice(n, state, keep=True)
+        assert ref["status"] == 0
+        want = o.fields_at(n, ref, gr)
+        F = _scale(ref)
+        rho = np.sort(state["rho"])
+        _say(f"grid slice {inst.name} tiling={tiling} cluster={cluster} n_r={n_r} slice={n} "
+             f"F={F:.3e} nodes inside first ring={int(np.sum(gr <= rho[0]))} "
+             f"beyond last={int(np.sum(gr > rho[-1]))}")
+        s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(n, 1)
+        got = s.wake_grid_fields(n)
+        for q in FIELDS:
+            e = float(np.max(np.abs(got[q] - want[q])))
+            assert e <= (TOL_SLICE * F if F > 0 else 1e-15), (n, q, e, F)
+        last = s.wake_grid_fields(-1)
+        for q in FIELDS:
+            assert np.array_equal(last[q], got[q])
+    s.close()
+
+
+def test_grid_slice_parity_small_tilings(wk):
+    """300 geometric rings, 2 per thread (256) and one per thread with idle
+    threads (1024); nodes inside the first ring, between rings, beyond the
+    last ring and beyond the plasma edge (r_max = 1.5 R_p)."""
+    inst = W.small_instance(7, n_rings=300, n_xi=200, n_peak=4.0, sigma_r=0.1, dxi=0.01)
+    for tiling in ((256, 0), (1024, 0)):
+        _check_slices(wk, inst, tiling, (0, 0), 97, 4.5, (0, 60, 130, 199))
+
+
+def test_grid_slice_parity_laser_channel_fine_grid(wk):
+    """700 rings in a parabolic channel with a laser; a grid finer than the
+    rings near the axis (many nodes per interval) and coarser outside."""
+    inst = W.small_instance(10, n_rings=700, n_xi=200, n_peak=1.0, laser=True, dxi=0.01,
+                            channel_w0=2.0)
+    _check_slices(wk, inst, (512, 0), (0, 0), 3000, 3.3, (0, 50, 120, 190))
+
+
+def test_grid_slice_parity_blowout_cavity(wk):
+    """A driver that clears the axis (150 uniform rings, peak density 60):
+    up to ~120 nodes inside the first ring, all in interval 0 of one
+    thread, no ring below them."""
+    inst = W.small_instance(11, n_rings=150, n_xi=300, n_peak=60.0, sigma_r=0.1, geometric=False,
+                            dxi=0.01)
+    _check_slices(wk, inst, (256, 0), (0, 0), 400, 3.3, (150, 225, 290))
+
+
+def test_grid_slice_parity_unstaged_beam_table(wk):
+    """A slice table longer than the LDS stage (20000 particles over a short
+    beam): node charges searched in device memory."""
+    rng = np.random.default_rng(5)
+    r0, dr = W.uniform_rings(400, 2.0)
+    p = W.gaussian_particles(rng, 20000, 1.0, 0.4, 0.05, 0.5)
+    inst = W.Instance("dense-beam-400x60", r0, dr, 0.01, 60, [p])
+    _check_slices(wk, inst, (512, 0), (0, 0), 160, 2.4, (45, 50, 55))
+
+
+def test_grid_slice_parity_cooperative(wk):
+    """A 3000-ring instance over six cooperative members (256 threads, two
+    rings per thread): member boundaries inside the grid."""
+    inst = W.small_instance(5, n_rings=3000, n_xi=60, n_peak=3.0, sigma_r=0.2, geometric=False,
+                            dxi=0.02)
+    _check_slices(wk, inst, (256, 0), (2, 500), 1201, 3.6, (0, 25, 50), layout=(6, 2))
+
+
+def test_grid_linear_end_to_end(wk):
+    """Linear driver, 1000 rings x 1200 slices, 64 nodes to r = 6 (beyond
+    the plasma at r = 5): every slice's grid fields within 1e-8."""
+    wk.wake_set_tiling(512, 0)
+    inst = W.config1()
+    _say("grid e2e linear 1000x1200")
+    ref = _oracle(inst).run(record_stride=0, grid=(64, 6.0))
+    s = wk.WakeSolver.from_instance(inst)
+    s.wake_set_grid(64, 6.0)
+    s.wake_solve(0, inst.n_xi)
+    assert s.wake_status() == (-1, inst.n_xi)
+    got = np.stack([[s.wake_grid_fields(n)[q] for q in FIELDS] for n in range(inst.n_xi)])
+    for qi, q in enumerate(FIELDS):
+        assert _rel(got[:, qi], ref["grid"][:, qi]) <= TOL_E2E, q
+    s.close()
+
+
+def test_grid_batched_equals_alone(wk):
+    """Instances with and without grids in one persistent launch: the grid
+    fields and the ring fields equal those of each instance marched alone."""
+    wk.wake_set_tiling(512, 0)
+    wk.wake_set_cluster(0, 0)
+    rng = np.random.default_rng(45)
+    insts = [W.batched_instance(rng, n, 90, n_drv=3000, n_wit=1000, r_max=4.0)
+             for n in (300, 1500, 777)]
+    grids = [(50, 4.5), None, (500, 2.0)]
+    _say("grid batched vs alone")
+    alone = []
+    for inst, g in zip(insts, grids):
+        s = wk.WakeSolver.from_instance(inst, record_stride=30)
+        if g:
+            s.wake_set_grid(*g)
+        s.wake_solve(0, inst.n_xi)
+        alone.append((s.wake_fields(60), [s.wake_grid_fields(n) for n in (0, 45, 89)] if g else None))
+        s.close()
+    solvers = []
+    for inst, g in zip(insts, grids):
+        s = wk.WakeSolver.from_instance(inst, record_stride=30)
+        if g:
+            s.wake_set_grid(*g)
+        solvers.append(s)
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_solve(40)
+    b.wake_batch_solve(-1)
+    b.wake_batch_sync()
+    for s, g, (f, gf) in zip(solvers, grids, alone):
+        got = s.wake_fields(60)
+        for q in FIELDS:
+            if g:
+                assert np.array_equal(got[q], f[q]), q
+            else:     # marched by the grid variant of the kernel here
+                assert _rel(got[q], f[q]) <= 1e-13, q
+        if g:
+            for n, want in zip((0, 45, 89), gf):
+                have = s.wake_grid_fields(n)
+                for q in FIELDS:
+                    assert np.array_equal(have[q], want[q]), (n, q)
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_grid_call_order_and_arguments(wk):
+    wk.wake_set_tiling(512, 0)
+    inst = W.small_instance(3, n_rings=100, n_xi=20)
+    s = wk.WakeSolver.from_instance(inst)
+    lib = wk.load()
+    assert lib.wake_grid_fields(s.h, 0, None, None, None, None, 0) == WAKE_ESTATE   # no grid
+    assert lib.wake_set_grid(s.h, -1, 1.0) == WAKE_EINVAL
+    assert lib.wake_set_grid(s.h, 10, 0.0) == WAKE_EINVAL
+    assert lib.wake_set_grid(s.h, 10, float("nan")) == WAKE_EINVAL
+    assert lib.wake_set_grid(s.h, (1 << 20) + 1, 1.0) == WAKE_EINVAL
+    s.wake_set_grid(10, 1.0)
+    assert lib.wake_grid_fields(s.h, 0, None, None, None, None, 0) == WAKE_ESTATE   # not solved
+    s.wake_solve(0, 5)
+    s.wake_grid_fields(4)
+    assert lib.wake_grid_fields(s.h, 5, None, None, None, None, 0) == WAKE_ESTATE
+    assert lib.wake_grid_fields(s.h, 20, None, None, None, None, 0) == WAKE_EINVAL
+    assert lib.wake_set_grid(s.h, 12, 1.0) == WAKE_ESTATE                         # after a solve
+    s.close()
