@@ -50,7 +50,7 @@ Readings taken where the paper is silent, garbled or self-inconsistent
   R14 (numerics, not model) ln rho is evaluated as ln r0 + log1p((rho-r0)/r0)
       so that its rounding, multiplied by the enclosed charge in eq. psi,
       stays proportional to the ring displacement.
-  R16 fields at radii off the rings (Fig. 2, external grid): the same sums
+  R17 fields at radii off the rings (Fig. 2, external grid): the same sums
       with no ring at the radius (no w^ term, no own-ring share), B^(p) from
       the interval's (a, b); a ring at exactly that radius counts as
       outside.  The field grid is uniform with nodes at cell centres
@@ -373,7 +373,7 @@ def forces(u, psibar, gamma, dpsi, bt, da2, q=Q_E, m=M_E):
 
 def grid_radii(n_r, r_max):
     """Nodes of a uniform radial field grid: cell centres (g + 1/2) dr_g,
-    dr_g = r_max / n_r (reading R16)."""
+    dr_g = r_max / n_r (reading R17)."""
     dg = float(r_max) / int(n_r)
     return (np.arange(int(n_r), dtype=np.float64) + 0.5) * dg
 
@@ -484,7 +484,7 @@ class RingOracle:
         the rings are known; Fig. 2, fields on an external grid).  ``out``
         is the slice's result with keep=True.  A radius with k rings
         strictly inside it lies in interval k of the recursion: a ring at
-        exactly r counts as outside (reading R16).  Returns a dict of
+        exactly r counts as outside (reading R17).  Returns a dict of
         binary64 arrays."""
         ids = out["order"]
         rho = out["rho"][ids]
