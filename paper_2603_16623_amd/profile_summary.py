@@ -50,11 +50,13 @@ def trace(d, title, command):
     march = [r for r in trace_rows if "wake_march_kernel" in r.get("Kernel_Name", "")]
     if march:
         print("March dispatches in order:\n")
-        print("| dispatch | duration ms | grid threads | workgroup | arch VGPR | acc VGPR | SGPR | LDS B | scratch B |")
-        print("|---|---|---|---|---|---|---|---|---|")
+        print("| dispatch | variant | duration ms | grid threads | workgroup | arch VGPR | acc VGPR | SGPR | LDS B | scratch B |")
+        print("|---|---|---|---|---|---|---|---|---|---|")
         for r in march:
             dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
-            print(f"| {r.get('Dispatch_Id', '')} | {dur:.3f} | {r.get('Grid_Size_X', r.get('Grid_Size', ''))} | "
+            name = r.get("Kernel_Name", "")
+            var = name[name.find("<") + 1:name.find(">")] if "<" in name else ""
+            print(f"| {r.get('Dispatch_Id', '')} | {var} | {dur:.3f} | {r.get('Grid_Size_X', r.get('Grid_Size', ''))} | "
                   f"{r.get('Workgroup_Size_X', r.get('Workgroup_Size', ''))} | {r.get('VGPR_Count', '')} | "
                   f"{r.get('Accum_VGPR_Count', '')} | {r.get('SGPR_Count', '')} | {r.get('LDS_Block_Size', '')} | "
                   f"{r.get('Scratch_Size', '')} |")
