@@ -477,13 +477,15 @@ extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
   I.grid_dr = 0.0;
   I.grid = nullptr;
   I.grid_tab = nullptr;
+  I.grid_scr = nullptr;
   if (n_r == 0) return WAKE_OK;
   const size_t nf = (size_t)4 * n_r * (size_t)I.n_xi;
-  HIP_TRY(hipMalloc(&c->grid_mem, sizeof(double) * (nf + WAKE_GRID_TAB * (size_t)n_r)));
+  HIP_TRY(hipMalloc(&c->grid_mem, sizeof(double) * (nf + (WAKE_GRID_TAB + 8) * (size_t)n_r)));
   I.grid_n = n_r;
   I.grid_dr = r_max / (double)n_r;
   I.grid = c->grid_mem;
   I.grid_tab = c->grid_mem + nf;
+  I.grid_scr = c->grid_mem + nf + WAKE_GRID_TAB * (size_t)n_r;
   HIP_TRY(launch_grid_init(I, c->grid_mem + nf, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return WAKE_OK;

@@ -115,6 +115,7 @@ struct WakeInst {
   double grid_dr;
   double *grid;
   const double *grid_tab;
+  double *grid_scr;           // [grid_n][8]: the owning interval's sums handed to each node
 };
 
 // Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c

@@ -1221,6 +1221,16 @@ struct MarchLds {
 static_assert(MarchLds<256>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<512>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<1024>::bytes() <= 160 * 1024, "LDS layout too large");
+// field-grid variant: the LDS left beside the layout holds the node records
+// of grids up to grid_lds_nodes nodes (else they are read from device memory)
+template <int NT>
+constexpr int grid_lds_nodes() {
+  return (int)((160 * 1024 - MarchLds<NT>::bytes() - 512) / (WAKE_GRID_TAB * sizeof(double)));
+}
+template <int NT>
+constexpr size_t grid_lds_bytes() {
+  return (size_t)grid_lds_nodes<NT>() * WAKE_GRID_TAB * sizeof(double);
+}
 
 // This slice's analytic source factors (beams: lam += c0 (1 - exp(-rho^2 c1));
 // lasers: |a|^2 = c0 exp(-rho^2 c1)) and beam-table entries into LDS.
@@ -1366,14 +1376,11 @@ __device__ __forceinline__ int grid_last_below(double x, double dg, double idg, 
 
 // psi (eq. psi) and E_r - B_theta = -d_rho psi (eq. dpsi_dr, no ring at r)
 // at node g (radius r) of an interval with the sums S, P of weight and
-// w ln rho below it.  tab: the node's ln r and the immobile ions' fields
-// there (dd pairs, fixed for the solve); out: the slice's [4][ng] block.
-__device__ __forceinline__ void grid_node_psi(WAKE_GLOBAL double* out, int ng, int g, double r,
-                                              const WAKE_GLOBAL double* tab, dd S, dd P,
-                                              double psi_axis) {
-  const D2 t0 = *reinterpret_cast<const WAKE_GLOBAL D2*>(tab + WAKE_GRID_TAB * g);
-  const D2 t1 = *reinterpret_cast<const WAKE_GLOBAL D2*>(tab + WAKE_GRID_TAB * g + 2);
-  const D2 t2 = *reinterpret_cast<const WAKE_GLOBAL D2*>(tab + WAKE_GRID_TAB * g + 4);
+// w ln rho below it.  t0, t1, t2: the node's record (ln r and the immobile
+// ions' psi - psi(0) and d_rho psi there, dd pairs, fixed for the solve);
+// out: the slice's [4][ng] block.
+__device__ __forceinline__ void grid_node_psi(WAKE_GLOBAL double* out, int ng, int g, double r, D2 t0,
+                                              D2 t1, D2 t2, dd S, dd P, double psi_axis) {
   const dd pe = dd_add_fast(dd_mul(S, dd{t0.x, t0.y}), dd_neg(P));
   const dd de = dd_div_rcp(S, r, rcp_nr(r));
   out[g] = dd_round(dd_add_fast(pe, dd{t1.x, t1.y})) + psi_axis;
@@ -1381,12 +1388,12 @@ __device__ __forceinline__ void grid_node_psi(WAKE_GLOBAL double* out, int ng, i
 }
 
 // E_z (eq. dpsi_dzeta: the rings at and above the interval) and
-// B_theta = Lambda/r + a r + b/r (eq. b_theta_plasma) at node g.
+// B_theta = B^(b) + a r + b/r (eq. b_theta_plasma) at node g.
 __device__ __forceinline__ void grid_node_b(WAKE_GLOBAL double* out, int ng, int g, double r, double ez,
-                                            double a, double b, double lam) {
+                                            double a, double b, double bb) {
   const double ir = rcp_nr(r);
   out[2 * ng + g] = ez;
-  out[3 * ng + g] = lam * ir + (a * r + b * ir);
+  out[3 * ng + g] = bb + (a * r + b * ir);
 }
 
 // charge of the analytic beams inside r (staged constants of the slice)
@@ -1460,6 +1467,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   const int64_t budget = I.budget;
   int cur = __builtin_amdgcn_readfirstlane(I.ctl[CTL_CUR]);
   double rho_mprev = -1.0;   // field grid, cooperative: radius at the previous member's last position
+  double rho_mlast = -1.0;   // field grid, cooperative: radius at this member's last position
   __syncthreads();
   // a ring at slot s came from another thread's chunk (or member)
 #define WAKE_FOREIGN(s) ((unsigned)((int)(s) - goff) >= (unsigned)P || (((int)(s) - goff) & (NT - 1)) != tid)
@@ -1520,6 +1528,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   // ion interval nodes in LDS (float) for the interval search of pass B;
   // read there after the slice-head scan's barriers
   const bool lds_ion = N <= KCAP;      // the interval nodes fit the LDS table
+  // field-grid node records in the LDS beyond the layout (read after the
+  // slice-head scan's barriers)
+  const bool grid_lds = GRID && I.grid_n > 0 && I.grid_n <= grid_lds_nodes<NT>();
+  D2* const s_gt = reinterpret_cast<D2*>(smem + MarchLds<NT>::bytes());
+  if (grid_lds) {
+    const WAKE_GLOBAL D2* const t = reinterpret_cast<const WAKE_GLOBAL D2*>(gptr(I.grid_tab));
+    for (int i = tid; i < 3 * I.grid_n; i += NT) s_gt[i] = t[i];
+  }
   if (lds_ion)
     for (int j = tid; j <= N; j += NT) s_ion[j] = (float)IV.R[j * WAKE_ION_REC + IR_LO];
 
@@ -1585,7 +1601,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       my_dis = t6.v[5];
       cl_prefix<6, 11>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
       pre = SliceHeadOp()(pg, pre);
-      if constexpr (GRID) rho_mprev = member > 0 ? s_x[(member - 1) * 11 + 8] : -1.0;
+      if constexpr (GRID) {
+        rho_mprev = member > 0 ? s_x[(member - 1) * 11 + 8] : -1.0;
+        rho_mlast = s_x[member * 11 + 8];
+      }
       double stop = 0.0;
       for (int m = 0; m < cl.G; ++m) {
         stop += s_x[m * 11 + 10];
@@ -1711,18 +1730,22 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       jn = lds_ion ? ion_find(s_ion, N, x_ru.x, hh_hint(x_hh)) : hh_hint(x_hh);
       ion_load(IV, jn, x_q);
     }
-    // field grid, psi and E_r - B_theta: the last node at or below the
-    // position before this thread's first
+    // field grid: the interval owning each node hands the node its sums
+    // (pass B: weight and w ln rho below it; pass E: the E_z sum and the
+    // B^(p) coefficients); every thread then evaluates nodes.  gb_lo: the
+    // last node at or below the previous position, gb_next its successor's
+    // radius (a ring at or above it owns nodes)
     const int ngB = GRID ? I.grid_n : 0;
     const double dgB = I.grid_dr, idgB = 1.0 / dgB;
-    WAKE_GLOBAL double* const goutB = gptr(I.grid) + (size_t)n * 4 * (size_t)ngB;
-    const WAKE_GLOBAL double* const gtab = gptr(I.grid_tab);
+    WAKE_GLOBAL D2* const gscr = reinterpret_cast<WAKE_GLOBAL D2*>(gptr(I.grid_scr));
     int gb_lo = -1;
+    double gb_next = INFINITY;
     if (GRID && ngB > 0 && cnt > 0) {
       double rb = -1.0;
       if (tid > 0) rb = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
       else if (CL) rb = rho_mprev;
       gb_lo = grid_last_below(rb, dgB, idgB, ngB);
+      gb_next = gb_lo + 1 < ngB ? ((double)(gb_lo + 1) + 0.5) * dgB : INFINITY;
     }
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
@@ -1754,13 +1777,16 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       ion_fields(IV, rho, lnr, h, q, ips, idp);
       const double psi = dd_round(dd_add_fast(pe, ips)) + psi_axis;
       const double dpsi = dd_round(dd_add_fast(de, idp));
-      if (GRID && ngB > 0) {
+      if (GRID && rho >= gb_next) {
         // nodes of interval p = (rho_{p-1}, rho_p]: the sums below position p
-        const int glo = gb_lo + 1;
-        gb_lo = grid_last_below(rho, dgB, idgB, ngB);
+        const int ghi = grid_last_below(rho, dgB, idgB, ngB);
         #pragma unroll 1
-        for (int g = glo; g <= gb_lo; ++g)
-          grid_node_psi(goutB, ngB, g, ((double)g + 0.5) * dgB, gtab, S, PT, psi_axis);
+        for (int g = gb_lo + 1; g <= ghi; ++g) {
+          gscr[4 * g] = d2(S.hi, S.lo);
+          gscr[4 * g + 1] = d2(PT.hi, PT.lo);
+        }
+        gb_lo = ghi;
+        gb_next = gb_lo + 1 < ngB ? ((double)(gb_lo + 1) + 0.5) * dgB : INFINITY;
       }
       S = dd_add_d(S, w);
       PT = PTi;
@@ -1813,8 +1839,16 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (GRID && ngB > 0 && cnt > 0 && p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
       // nodes beyond the last ring: every ring below them
       #pragma unroll 1
-      for (int g = gb_lo + 1; g < ngB; ++g)
-        grid_node_psi(goutB, ngB, g, ((double)g + 0.5) * dgB, gtab, S, PT, psi_axis);
+      for (int g = gb_lo + 1; g < ngB; ++g) {
+        gscr[4 * g] = d2(S.hi, S.lo);
+        gscr[4 * g + 1] = d2(PT.hi, PT.lo);
+      }
+    }
+    // this member's nodes (all of them for a single workgroup)
+    int g_begin = 0, g_end = ngB;
+    if (GRID && CL && ngB > 0) {
+      g_begin = grid_last_below(rho_mprev, dgB, idgB, ngB) + 1;
+      if (member < cl.G - 1) g_end = grid_last_below(rho_mlast, dgB, idgB, ngB) + 1;
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1823,6 +1857,37 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         Pack<5>{{G.v[0], G.v[1], G.v[2], G.v[3], Vw}}, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}},
         FwdMatSumOp(), Pack<5>{{G.v[3], -G.v[1], -G.v[2], G.v[0], Vw}},
         Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, BwdMatSumOp(), s_scanB, gp, gt, hx, ht);
+    if (GRID && ngB > 0) {
+      // psi, E_r - B_theta and the beam field at this member's nodes (the
+      // scans' barriers order the sums written in pass B before these reads)
+      const WAKE_GLOBAL D2* const gtab = reinterpret_cast<const WAKE_GLOBAL D2*>(gptr(I.grid_tab));
+      WAKE_GLOBAL double* const gout = gptr(I.grid) + (size_t)n * 4 * (size_t)ngB;
+      #pragma unroll 1
+      for (int g = g_begin + tid; g < g_end; g += NT) {
+        const double r = ((double)g + 0.5) * dgB;
+        D2 t0, t1, t2;
+        if (grid_lds) {
+          t0 = s_gt[3 * g]; t1 = s_gt[3 * g + 1]; t2 = s_gt[3 * g + 2];
+        } else {
+          t0 = gtab[3 * g]; t1 = gtab[3 * g + 1]; t2 = gtab[3 * g + 2];
+        }
+        const D2 sS = gscr[4 * g], sP = gscr[4 * g + 1];
+        grid_node_psi(gout, ngB, g, r, t0, t1, t2, dd{sS.x, sS.y}, dd{sP.x, sP.y}, psi_axis);
+        double lam = 0.0;
+        if (bm > 0) {
+          int cb;
+          if (staged) {
+            cb = count_below(s_br, 0, bm, r, false);
+            if (cb > 0) lam = s_bc[cb - 1];
+          } else {
+            cb = count_below(gR, 0, bm, r, false);
+            if (cb > 0) lam = gQ[cb - 1];
+          }
+        }
+        lam += analytic_lam(s_misc, n_an, r);
+        gout[3 * ngB + g] = lam * rcp_nr(r);     // B^(b); pass E adds B^(p)
+      }
+    }
     if (CL) {                // the other members' chunk products before / after this one
       Pack<10> mine;
 #pragma unroll
@@ -1904,40 +1969,24 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       v_hs = hh_hs(Sn.ldw(RS_HH, goff + sl));
     }
     if (cnt > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
-    // field grid, E_z and B_theta: the radius before this thread's first
-    // position and the last node at or below its last ring
-    const int ng = GRID ? I.grid_n : 0;
-    const double dg = I.grid_dr, idg = 1.0 / dg;
-    WAKE_GLOBAL double* const gout = gptr(I.grid) + (size_t)n * 4 * (size_t)ng;
+    // field grid: ge_hi the last node at or below the current ring, ge_top
+    // its radius (a previous ring below it means the interval owns nodes)
     int ge_hi = -1;
-    double g_lo_r = -1.0;
-    if (GRID && ng > 0 && cnt > 0) {
+    double ge_top = -INFINITY, g_lo_r = -1.0;
+    if (GRID && ngB > 0 && cnt > 0) {
       if (tid > 0) g_lo_r = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
       else if (CL) g_lo_r = rho_mprev;
-      ge_hi = grid_last_below(y_ru.x, dg, idg, ng);
-      // nodes beyond the last ring: interval N (a_N = 0, no ring outside)
+      ge_hi = grid_last_below(y_ru.x, dgB, idgB, ngB);
       if (p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
+        // nodes beyond the last ring: interval N (a_N = 0, no ring outside)
         const double a = (ha * E - ga * D) * iW, b = (hb * E - gb * D) * iW;
-        int cb = 0;
-        bool gal = false;
         #pragma unroll 1
-        for (int g = ge_hi + 1; g < ng; ++g) {
-          const double r = ((double)g + 0.5) * dg;
-          double lam = 0.0;
-          if (bm > 0) {
-            if (staged) {
-              cb = count_below(s_br, cb, bm, r, gal);
-              if (cb > 0) lam = s_bc[cb - 1];
-            } else {
-              cb = count_below(gR, cb, bm, r, gal);
-              if (cb > 0) lam = gQ[cb - 1];
-            }
-            gal = true;
-          }
-          lam += analytic_lam(s_misc, n_an, r);
-          grid_node_b(gout, ng, g, r, Vgt, a, b, lam);
+        for (int g = ge_hi + 1; g < ngB; ++g) {
+          gscr[4 * g + 2] = d2(Vgt, a);
+          gscr[4 * g + 3] = d2(b, 0.0);
         }
       }
+      ge_top = ge_hi >= 0 ? ((double)ge_hi + 0.5) * dgB : -INFINITY;
     }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
@@ -2029,26 +2078,18 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         nxt_i = id;
       }
       Vgt += L.v;
-      if (GRID && ng > 0) {
-        // nodes of interval p = (rho_{p-1}, rho_p], downward
-        const int ghi = ge_hi;
-        ge_hi = grid_last_below(k > 0 ? y_ru.x : g_lo_r, dg, idg, ng);
-        int cb = bhi;
-        #pragma unroll 1
-        for (int g = ghi; g > ge_hi; --g) {
-          const double r = ((double)g + 0.5) * dg;
-          double lam = 0.0;
-          if (bm > 0) {
-            if (staged) {
-              cb = count_below_down(s_br, cb, bm, r, true);
-              if (cb > 0) lam = s_bc[cb - 1];
-            } else {
-              cb = count_below_down(gR, cb, bm, r, true);
-              if (cb > 0) lam = gQ[cb - 1];
-            }
+      if (GRID) {
+        const double rlo = k > 0 ? y_ru.x : g_lo_r;
+        if (rlo < ge_top) {
+          // nodes of interval p = (rho_{p-1}, rho_p]
+          const int glo = grid_last_below(rlo, dgB, idgB, ngB) + 1;
+          #pragma unroll 1
+          for (int g = glo; g <= ge_hi; ++g) {
+            gscr[4 * g + 2] = d2(Vgt, a);
+            gscr[4 * g + 3] = d2(b, 0.0);
           }
-          lam += analytic_lam(s_misc, n_an, r);
-          grid_node_b(gout, ng, g, r, Vgt, a, b, lam);
+          ge_hi = glo - 1;
+          ge_top = ge_hi >= 0 ? ((double)ge_hi + 0.5) * dgB : -INFINITY;
         }
       }
     }
@@ -2068,6 +2109,16 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       s_misc[63] = !CL && budget > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget ? 1.0 : 0.0;
     __syncthreads();
     if (s_misc[63] != 0.0) end = n + 1;
+    if (GRID && ngB > 0) {
+      // E_z and B_theta at this member's nodes (after the barrier above)
+      WAKE_GLOBAL double* const gout = gptr(I.grid) + (size_t)n * 4 * (size_t)ngB;
+      #pragma unroll 1
+      for (int g = g_begin + tid; g < g_end; g += NT) {
+        const double r = ((double)g + 0.5) * dgB;
+        const D2 e0 = gscr[4 * g + 2], e1 = gscr[4 * g + 3];
+        grid_node_b(gout, ngB, g, r, e0.x, e0.y, e1.x, gout[3 * ngB + g]);
+      }
+    }
     if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))
       dis_l = 1.0;
     dis = dis_l;
@@ -2283,8 +2334,9 @@ hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_task
     hipLaunchKernelGGL(counter_zero_kernel, dim3(1), dim3(64), 0, s, counter);                     \
     hipLaunchKernelGGL(cluster_reset_kernel, dim3(1), dim3(256), 0, s, d_insts, n_insts);          \
     if (with_grid)                                                                                \
-      hipLaunchKernelGGL((wake_march_kernel<a, true>), dim3(grid), dim3(a), MarchLds<a>::bytes(), \
-                         s, d_insts, n_insts, n_tasks, counter);                                  \
+      hipLaunchKernelGGL((wake_march_kernel<a, true>), dim3(grid), dim3(a),                       \
+                         MarchLds<a>::bytes() + grid_lds_bytes<a>(), s, d_insts, n_insts, n_tasks, \
+                         counter);                                                                \
     else                                                                                          \
       hipLaunchKernelGGL((wake_march_kernel<a, false>), dim3(grid), dim3(a), MarchLds<a>::bytes(),\
                          s, d_insts, n_insts, n_tasks, counter);                                  \
@@ -2326,7 +2378,7 @@ hipError_t march_prepare(int nt) {
     if (e != hipSuccess) return e;                                                                \
     return hipFuncSetAttribute((const void*)wake_march_kernel<a, true>,                           \
                                hipFuncAttributeMaxDynamicSharedMemorySize,                        \
-                               (int)MarchLds<a>::bytes());                                        \
+                               (int)(MarchLds<a>::bytes() + grid_lds_bytes<a>()));                \
   }
   WAKE_THREADS(X)
 #undef X
