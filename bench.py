@@ -106,11 +106,15 @@ def cpu_baseline(insts, budget_s: float = 15.0, cores: int = 0):
         res = pool.map(_oracle_worker, jobs, chunksize=1)
     done = sum(r[0] for r in res)
     span = max(r[3] for r in res) - min(r[2] for r in res)
-    sample = "; ".join(f"{nr} rings x {ns} slices" for r in res for nr, ns in r[1])
+    parts = [p for r in res for p in r[1]]
+    whole = sum(1 for nr, ns in parts if ns == max(ns for _, ns in parts))
+    rings = [nr for nr, _ in parts]
     return dict(value=done / span, unit="ring-slice updates/s", cores=cores, kind="oracle",
                 sample=f"oracle (numpy, one thread per process) in {cores} host processes, each "
-                       f"marching instances of the batch (process i takes instances i, i + {cores}, "
-                       f"...) from slice 0: {sample}; {done} ring-slices in {span:.1f} s")
+                       f"marching instances of the batch from slice 0 (process i takes instances "
+                       f"i, i + {cores}, ...): {len(parts)} instances of {min(rings)}-{max(rings)} "
+                       f"rings, {whole} of them through the whole window; {done} ring-slices in "
+                       f"{span:.1f} s")
 
 
 C4_MEAN_WORK = (50_000 - 500) / math.log(100.0) * (500 + 8000) / 2.0   # E[N] E[N_xi]
