@@ -58,8 +58,8 @@ def build_batch(wake, insts, stream, grid=None):
 def _oracle_worker(job):
     """One host process: the oracle on its instances in turn, each from
     slice 0, for about budget_s seconds in all (numpy on one thread).
-    Returns (ring-slices, per-instance (rings, slices), start, end) with
-    wall-clock times."""
+    Returns (ring-slices, per-instance (rings, slices, slices of the
+    window), start, end) with wall-clock times."""
     insts, budget_s = job
     from oracle.wake_oracle import RingOracle
     try:
@@ -77,7 +77,7 @@ def _oracle_worker(job):
             _, state = o.slice(n, state)
             n += 1
         done += inst.n_rings * n
-        parts.append((inst.n_rings, n))
+        parts.append((inst.n_rings, n, inst.n_xi - 1))
         if time.time() - t0 >= budget_s:
             break
     return done, parts, t0, time.time()
@@ -107,8 +107,8 @@ def cpu_baseline(insts, budget_s: float = 15.0, cores: int = 0):
     done = sum(r[0] for r in res)
     span = max(r[3] for r in res) - min(r[2] for r in res)
     parts = [p for r in res for p in r[1]]
-    whole = sum(1 for nr, ns in parts if ns == max(ns for _, ns in parts))
-    rings = [nr for nr, _ in parts]
+    whole = sum(1 for _, ns, nw in parts if ns == nw)
+    rings = [p[0] for p in parts]
     return dict(value=done / span, unit="ring-slice updates/s", cores=cores, kind="oracle",
                 sample=f"oracle (numpy, one thread per process) in {cores} host processes, each "
                        f"marching instances of the batch from slice 0 (process i takes instances "
