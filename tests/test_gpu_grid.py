@@ -113,6 +113,37 @@ def test_grid_slice_parity_blowout_cavity(wk):
     _check_slices(wk, inst, (256, 0), (0, 0), 400, 3.3, (150, 225, 290))
 
 
+def test_grid_rings_exactly_at_nodes(wk):
+    """An injected state whose radii are node radii (every third node, so
+    the nodes between rings and on rings alternate): a ring exactly at a
+    node counts as outside it on both sides."""
+    wk.wake_set_tiling(256, 0)
+    wk.wake_set_cluster(0, 0)
+    inst = W.small_instance(13, n_rings=200, n_xi=40, n_peak=2.0, sigma_r=0.3, geometric=False,
+                            dxi=0.02)
+    o = _oracle(inst)
+    n_r, r_max = 600, 3.0
+    gr = grid_radii(n_r, r_max)
+    rng = np.random.default_rng(8)
+    state = o.initial_state()
+    state["rho"] = gr[1::3][: inst.n_rings].copy()
+    state["u"] = rng.normal(0.0, 0.05, inst.n_rings)
+    n = 20
+    ref, _ = o.slice(n, state, keep=True)
+    want = o.fields_at(n, ref, gr)
+    F = _scale(ref)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    s.wake_set_grid(n_r, r_max)
+    s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(n, 1)
+    got = s.wake_grid_fields(n)
+    _say(f"grid rings at nodes F={F:.3e}")
+    for q in FIELDS:
+        e = float(np.max(np.abs(got[q] - want[q])))
+        assert e <= TOL_SLICE * F, (q, e, F)
+    s.close()
+
+
 def test_grid_slice_parity_unstaged_beam_table(wk):
     """A slice table longer than the LDS stage (20000 particles over a short
     beam): node charges searched in device memory."""
