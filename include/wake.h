@@ -137,8 +137,9 @@ int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, 
  * device by the context; not counted by wake_footprint).  A node with k
  * rings strictly inside it takes the sums of the rings below and above,
  * with no ring at the node; a ring exactly at a node counts as outside it.
- * Only before the first solve (WAKE_ESTATE after); n_r = 0 removes the
- * grid.  n_r <= 2^20, r_max > 0 finite (WAKE_EINVAL).  Synchronous. */
+ * Only before the first solve and while no batch holds the context
+ * (WAKE_ESTATE otherwise); n_r = 0 removes the grid.  n_r <= 2^20,
+ * r_max > 0 finite (WAKE_EINVAL).  Synchronous. */
 int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 
 /* Grid fields of one solved slice [n_r each] (slice = -1: the last slice

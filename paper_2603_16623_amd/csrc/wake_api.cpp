@@ -89,6 +89,7 @@ struct wake_batch {
   int cap = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool holds = false;      // the contexts count this batch
 };
 
 int dev_err(hipError_t e) { return e == hipErrorOutOfMemory ? WAKE_ENOMEM : WAKE_EDEVICE; }
@@ -464,7 +465,7 @@ extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt
 extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
   if (!c) return WAKE_EINVAL;
   if (n_r < 0 || n_r > (1 << 20) || (n_r > 0 && !finite_pos(r_max))) return WAKE_EINVAL;
-  if (c->next != 0) return WAKE_ESTATE;
+  if (c->next != 0 || c->batches > 0) return WAKE_ESTATE;
   HIP_TRY(hipSetDevice(c->device));
   int r = drain(c);
   if (r != WAKE_OK) return r;
@@ -663,6 +664,8 @@ static void batch_release(wake_batch* b) {
   if (b->d_insts) (void)hipFree(b->d_insts);
   if (b->d_counter) (void)hipFree(b->d_counter);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->holds)
+    for (wake_ctx* c : b->ctxs) --c->batches;
   delete b;
 }
 
@@ -698,6 +701,8 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
     batch_release(b);
     return WAKE_ENOMEM;
   }
+  for (wake_ctx* c : b->ctxs) ++c->batches;
+  b->holds = true;
   *out = b;
   return WAKE_OK;
 }

@@ -36,6 +36,7 @@ struct wake_ctx {
   std::vector<double> px, py, pxi, pw, pq;
   double* grid_mem = nullptr;  // field grid: fields [n_xi][4][n_r], then the node table
   bool prepared = false;
+  int batches = 0;                 // batches that hold this context
   int next = 0;
   hipStream_t pending = nullptr;   // batch stream that last marched this context
 };

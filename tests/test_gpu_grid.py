@@ -242,3 +242,9 @@ def test_grid_call_order_and_arguments(wk):
     assert lib.wake_grid_fields(s.h, 20, None, None, None, None, 0) == WAKE_EINVAL
     assert lib.wake_set_grid(s.h, 12, 1.0) == WAKE_ESTATE                         # after a solve
     s.close()
+    s = wk.WakeSolver.from_instance(inst)
+    b = wk.WakeBatch([s])
+    assert lib.wake_set_grid(s.h, 12, 1.0) == WAKE_ESTATE                         # held by a batch
+    b.close()
+    s.wake_set_grid(12, 1.0)                                                      # released
+    s.close()
