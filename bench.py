@@ -326,11 +326,13 @@ def main():
             s.close()
     if args.served_seconds > 0:
         # capacity: sustained ring-slice rate of the server on the request mix
-        # while it is saturated (a backlog of requests submitted at once)
+        # while it is saturated: a backlog of about 1000 requests submitted at
+        # once, measured while some still wait for admission (the drain at
+        # the end, when the last large requests run alone, is not capacity)
         budget = int(args.served_budget_gib * (1 << 30))
         step_us = 20_000
         log("served: capacity")
-        specs, build = W.config4_stream(seed=40, rate=1000.0, duration=0.3)
+        specs, build = W.config4_stream(seed=40, rate=1000.0, duration=1.0)
         srv = wake.WakeServer(device_bytes=budget, slices_per_step=100_000, step_us=step_us,
                               stream=stream)
         for t, k in specs:
@@ -338,7 +340,7 @@ def main():
         t0 = time.perf_counter()
         srv.step()                                   # first admissions
         w0, c0 = srv.stats()["ring_slices"], time.perf_counter()
-        while time.perf_counter() - c0 < 8.0 and srv.stats()["active"] > 0:
+        while time.perf_counter() - c0 < 8.0 and srv.stats()["queued"] > 0:
             srv.step()
             for t in srv.ready():
                 srv.result(t)
