@@ -46,7 +46,7 @@ def _rows(pattern):
 def trace(d, title, command):
     trace_rows = _rows(os.path.join(d, "**", "*kernel_trace.csv"))
     stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
-    print(f"# {title}\n\nCommand (GPU box, repository root as $R):\n\n    {command}\n")
+    print(f"# {title}\n\nCommand (repository root as $R):\n\n    {command}\n")
     march = [r for r in trace_rows if "wake_march_kernel" in r.get("Kernel_Name", "")]
     if march:
         print("March dispatches in order:\n")

@@ -16,7 +16,7 @@ def _declared():
     return sorted(set(re.findall(r"\b(wake_[a-z_]+)\s*\(", src)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_core_calls():
     names = _declared()
     for n in ("wake_create", "wake_add_beam", "wake_solve", "wake_fields"):
         assert n in names
