@@ -12,7 +12,7 @@ sort at these sizes.
 import numpy as np
 import pytest
 
-from oracle.wake_oracle import RingOracle
+from oracle.wake_oracle import RingOracle, grid_radii
 from paper_2603_16623_amd import workloads as W
 from test_gpu_parity import FIELDS, TOL_SLICE, _field_scale, _field_tol, _rel
 
@@ -40,13 +40,16 @@ def _perturbed(inst, seed, jitter):
                 fu=0.02 * rng.standard_normal(N))
 
 
-def _check_slice(wk, inst, n, state, label):
+def _check_slice(wk, inst, n, state, label, grid=None):
+    """grid = (n_r, r_max): also the radial field grid of that slice."""
     o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
     ref, new = o.slice(n, state, push=True, keep=True)
     assert ref["status"] == 0, label
     F = _field_scale(ref)
-    _say(f"full-size slice parity {label}: N={inst.n_rings} slice={n} F={F:.3e}")
+    _say(f"full-size slice parity {label}: N={inst.n_rings} slice={n} F={F:.3e} grid={grid}")
     s = wk.WakeSolver.from_instance(inst, record_stride=n)
+    if grid is not None:
+        s.wake_set_grid(*grid)
     s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(n, 1)
     got = s.wake_fields(n)
@@ -60,19 +63,25 @@ def _check_slice(wk, inst, n, state, label):
     lp, le = s.wake_lineout()
     assert abs(lp[n] - ref["psi_axis"]) <= _field_tol(F)
     assert abs(le[n] - ref["ez_axis"]) <= _field_tol(F)
+    if grid is not None:
+        want = o.fields_at(n, ref, grid_radii(*grid))
+        got = s.wake_grid_fields(n)
+        for q in FIELDS:
+            e = float(np.max(np.abs(got[q] - want[q])))
+            assert e <= _field_tol(F), (label, "grid", q, e, F)
     s.close()
 
 
 def test_blowout_20000_rings_full_size(wk):
     inst = W.config2()                     # 20000 rings, 4000 slices, driver + witness
     for n, seed in ((int(2.8 / inst.dxi), 1), (int(7.3 / inst.dxi), 2)):   # driver, witness centres
-        _check_slice(wk, inst, n, _perturbed(inst, seed, 0.01), "blowout-20000x4000")
+        _check_slice(wk, inst, n, _perturbed(inst, seed, 0.01), "blowout-20000x4000", grid=(400, 2.0))
 
 
 def test_laser_200000_rings_full_size(wk):
     inst = W.config5()                     # 2e5 rings, 8000 slices, laser + witness
     n = int(2.0 / inst.dxi)                # laser centre
-    _check_slice(wk, inst, n, _perturbed(inst, 3, 0.002), "laser-200000x8000")
+    _check_slice(wk, inst, n, _perturbed(inst, 3, 0.002), "laser-200000x8000", grid=(600, 18.0))
 
 
 def test_batched_instances_full_size(wk):
@@ -80,7 +89,7 @@ def test_batched_instances_full_size(wk):
     picks = sorted(range(len(insts)), key=lambda i: insts[i].n_rings)
     for i in (picks[0], picks[len(picks) // 2], picks[-1]):   # smallest, median, largest
         inst = insts[i]
-        _check_slice(wk, inst, 800, _perturbed(inst, 10 + i, 0.01), f"batched[{i}]")
+        _check_slice(wk, inst, 800, _perturbed(inst, 10 + i, 0.01), f"batched[{i}]", grid=(64, 1.0))
 
 
 def test_laser_witness_region_matches_split_launches(wk):
