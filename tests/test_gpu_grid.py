@@ -248,3 +248,44 @@ def test_grid_call_order_and_arguments(wk):
     b.close()
     s.wake_set_grid(12, 1.0)                                                      # released
     s.close()
+
+
+def test_grid_graph_replays_match_eager(wk):
+    """A captured batch with field grids: every replay (with eager work of
+    the program in between) gives the eager solve's grid fields bitwise."""
+    wk.wake_set_tiling(512, 0)
+    wk.wake_set_cluster(0, 0)
+    rng = np.random.default_rng(46)
+    insts = [W.batched_instance(rng, n, 70, n_drv=2000, n_wit=500, r_max=4.0) for n in (250, 800)]
+    grids = [(40, 2.0), (120, 4.5)]
+    _say("grid graph replay")
+    eager = []
+    for inst, g in zip(insts, grids):
+        s = wk.WakeSolver.from_instance(inst)
+        s.wake_set_grid(*g)
+        s.wake_solve(0, inst.n_xi)
+        eager.append([s.wake_grid_fields(n) for n in (0, 35, 69)])
+        s.close()
+    solvers = []
+    for inst, g in zip(insts, grids):
+        s = wk.WakeSolver.from_instance(inst)
+        s.wake_set_grid(*g)
+        solvers.append(s)
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_capture()
+    for rep in range(3):
+        b.wake_batch_replay()
+        b.wake_batch_sync()
+        for s, want in zip(solvers, eager):
+            for n, w in zip((0, 35, 69), want):
+                have = s.wake_grid_fields(n)
+                for q in FIELDS:
+                    assert np.array_equal(have[q], w[q]), (rep, n, q)
+        x = wk.WakeSolver.from_instance(insts[0])
+        x.wake_set_grid(16, 1.0)
+        x.wake_solve(0, 10)
+        x.wake_sync()
+        x.close()
+    b.close()
+    for s in solvers:
+        s.close()
