@@ -289,3 +289,58 @@ def test_grid_graph_replays_match_eager(wk):
     b.close()
     for s in solvers:
         s.close()
+
+
+def _hip_runtime():
+    """The HIP runtime the library itself loaded (the same process-wide one)."""
+    import ctypes
+    with open("/proc/self/maps") as fh:
+        paths = {ln.split()[-1] for ln in fh if "libamdhip64" in ln}
+    assert paths, "HIP runtime not loaded"
+    hip = ctypes.CDLL(sorted(paths)[0])
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    return hip
+
+
+def test_device_destinations_match_host(wk):
+    """wake_fields and wake_grid_fields with device destinations (dst_is_device
+    = 1, buffers from hipMalloc) copy what the host destinations receive."""
+    import ctypes
+    wk.wake_set_tiling(512, 0)
+    wk.wake_set_cluster(0, 0)
+    inst = W.small_instance(14, n_rings=333, n_xi=50, n_peak=2.0)
+    s = wk.WakeSolver.from_instance(inst, record_stride=10)
+    s.wake_set_grid(77, 3.0)
+    s.wake_solve(0, inst.n_xi)
+    lib, hip = wk.load(), _hip_runtime()
+
+    def through_device(call, count, n_out):
+        bufs = []
+        for _ in range(n_out):
+            p = ctypes.c_void_p()
+            assert hip.hipMalloc(ctypes.byref(p), 8 * count) == 0
+            bufs.append(p)
+        try:
+            assert call(*[b.value for b in bufs]) == 0
+            out = []
+            for b in bufs:
+                a = np.empty(count)
+                assert hip.hipMemcpy(a.ctypes.data, b.value, 8 * count, 2) == 0   # device to host
+                out.append(a)
+            return out
+        finally:
+            for b in bufs:
+                hip.hipFree(b.value)
+
+    for n in (20, -1):
+        host = s.wake_fields(n)
+        dev = through_device(lambda *p: lib.wake_fields(s.h, n, *p, 1), inst.n_rings, 6)
+        for k, a in zip(("psi", "er_bt", "ez", "bt", "rho", "ur"), dev):
+            assert np.array_equal(a, host[k]), (n, k)
+        ghost = s.wake_grid_fields(n)
+        gdev = through_device(lambda *p: lib.wake_grid_fields(s.h, n, *p, 1), 77, 4)
+        for k, a in zip(FIELDS, gdev):
+            assert np.array_equal(a, ghost[k]), (n, k)
+    s.close()
