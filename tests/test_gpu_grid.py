@@ -305,8 +305,10 @@ def _hip_runtime():
 
 
 def test_device_destinations_match_host(wk):
-    """wake_fields and wake_grid_fields with device destinations (dst_is_device
-    = 1, buffers from hipMalloc) copy what the host destinations receive."""
+    """Device destinations (wake_fields, wake_grid_fields, wake_lineout,
+    wake_get_state with dst_is_device = 1, buffers from hipMalloc) receive
+    what host destinations do, and a state injected from device sources
+    marches like the same state from host arrays."""
     import ctypes
     wk.wake_set_tiling(512, 0)
     wk.wake_set_cluster(0, 0)
@@ -343,4 +345,35 @@ def test_device_destinations_match_host(wk):
         gdev = through_device(lambda *p: lib.wake_grid_fields(s.h, n, *p, 1), 77, 4)
         for k, a in zip(FIELDS, gdev):
             assert np.array_equal(a, ghost[k]), (n, k)
+    lp, le = s.wake_lineout()
+    dl = through_device(lambda *p: lib.wake_lineout(s.h, *p, 1), inst.n_xi, 2)
+    assert np.array_equal(dl[0], lp) and np.array_equal(dl[1], le)
+    st = s.wake_get_state()
+    sl = wk._I()
+    ds = through_device(lambda *p: lib.wake_get_state(s.h, ctypes.byref(sl), *p, 1), inst.n_rings, 4)
+    assert sl.value == st["slice"]
+    for k, a in zip(("rho", "ur", "f_rho", "f_u"), ds):
+        assert np.array_equal(a, st[k]), k
+    # an injected state from device sources marches like the same host state
+    rng = np.random.default_rng(3)
+    new = [st["rho"] * (1.0 + 0.01 * rng.standard_normal(inst.n_rings)).clip(0.9, 1.1),
+           st["ur"], st["f_rho"], st["f_u"]]
+    s.wake_set_state(30, *new)
+    s.wake_solve(30, 5)
+    want = s.wake_fields(-1)
+    bufs = []
+    for a in new:
+        p = ctypes.c_void_p()
+        assert hip.hipMalloc(ctypes.byref(p), 8 * inst.n_rings) == 0
+        assert hip.hipMemcpy(p.value, np.ascontiguousarray(a).ctypes.data, 8 * inst.n_rings, 1) == 0
+        bufs.append(p)
+    try:
+        assert lib.wake_set_state(s.h, 30, *[b.value for b in bufs], 1) == 0
+    finally:
+        for b in bufs:
+            hip.hipFree(b.value)
+    s.wake_solve(30, 5)
+    have = s.wake_fields(-1)
+    for k in want:
+        assert np.array_equal(have[k], want[k]), k
     s.close()
