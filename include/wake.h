@@ -142,10 +142,13 @@ int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, 
  * r_max > 0 finite (WAKE_EINVAL).  Synchronous. */
 int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 
-/* Grid fields of one solved slice [n_r each] (slice = -1: the last slice
- * of the most recent solve): WAKE_ESTATE without a grid or for a slice not
- * solved yet, WAKE_EBREAKDOWN at or after a breakdown.  NULL outputs are
- * skipped.  Synchronizes the context's stream. */
+/* Grid fields of one solved slice [n_r each], slice-major storage read out
+ * per slice (slice = -1: the slice before the context's next slice, i.e.
+ * the last slice of the most recent solve; after wake_set_state without a
+ * solve it names a slice this state has not marched).  WAKE_ESTATE without
+ * a grid or for a slice at or after the next slice, WAKE_EBREAKDOWN at or
+ * after a breakdown.  NULL outputs are skipped.  Synchronizes the
+ * context's stream. */
 int wake_grid_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, double *ez,
                      double *bt, int32_t dst_is_device);
 
