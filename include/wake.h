@@ -145,7 +145,8 @@ int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 /* Grid fields of one solved slice [n_r each], slice-major storage read out
  * per slice (slice = -1: the slice before the context's next slice, i.e.
  * the last slice of the most recent solve; after wake_set_state without a
- * solve it names a slice this state has not marched).  WAKE_ESTATE without
+ * solve it names a slice this state has not marched; slices never marched
+ * since wake_set_grid read as NaN).  WAKE_ESTATE without
  * a grid or for a slice at or after the next slice, WAKE_EBREAKDOWN at or
  * after a breakdown.  NULL outputs are skipped.  Synchronizes the
  * context's stream. */

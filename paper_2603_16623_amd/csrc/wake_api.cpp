@@ -487,6 +487,8 @@ extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
   I.grid = c->grid_mem;
   I.grid_tab = c->grid_mem + nf;
   I.grid_scr = c->grid_mem + nf + WAKE_GRID_TAB * (size_t)n_r;
+  // slices not marched read as NaN (all-ones bytes)
+  HIP_TRY(hipMemsetAsync(c->grid_mem, 0xFF, sizeof(double) * nf, c->stream));
   HIP_TRY(launch_grid_init(I, c->grid_mem + nf, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return WAKE_OK;

@@ -236,6 +236,14 @@ def test_grid_call_order_and_arguments(wk):
     assert lib.wake_set_grid(s.h, (1 << 20) + 1, 1.0) == WAKE_EINVAL
     s.wake_set_grid(10, 1.0)
     assert lib.wake_grid_fields(s.h, 0, None, None, None, None, 0) == WAKE_ESTATE   # not solved
+    st = s.wake_get_state()
+    s.wake_set_state(3, st["rho"], st["ur"])
+    s.wake_solve(3, 2)
+    assert np.all(np.isnan(s.wake_grid_fields(1)["psi"]))                         # never marched
+    assert np.all(np.isfinite(s.wake_grid_fields(4)["psi"]))
+    s.close()
+    s = wk.WakeSolver.from_instance(inst)
+    s.wake_set_grid(10, 1.0)
     s.wake_solve(0, 5)
     s.wake_grid_fields(4)
     assert lib.wake_grid_fields(s.h, 5, None, None, None, None, 0) == WAKE_ESTATE
