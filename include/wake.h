@@ -139,7 +139,9 @@ int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, 
  * with no ring at the node; a ring exactly at a node counts as outside it.
  * Only before the first solve and while no batch holds the context
  * (WAKE_ESTATE otherwise); n_r = 0 removes the grid.  n_r <= 2^20,
- * r_max > 0 finite (WAKE_EINVAL).  Synchronous. */
+ * r_max > 0 finite (WAKE_EINVAL); WAKE_ENOMEM if the device memory is not
+ * there.  A batch marches contexts with and without grids together.  The
+ * served form (wake_server_*) has no grid.  Synchronous. */
 int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 
 /* Grid fields of one solved slice [n_r each], slice-major storage read out
