@@ -43,8 +43,8 @@ def _rows(pattern):
     return out
 
 
-def trace(d, title, command):
-    trace_rows = _rows(os.path.join(d, "**", "*kernel_trace.csv"))
+def trace(d, title, command, per_dispatch=True):
+    trace_rows = _rows(os.path.join(d, "**", "*kernel_trace.csv")) if per_dispatch else []
     stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
     print(f"# {title}\n\nCommand (repository root as $R):\n\n    {command}\n")
     march = [r for r in trace_rows if "wake_march_kernel" in r.get("Kernel_Name", "")]
@@ -142,6 +142,8 @@ def read_traffic(path):
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "stats":       # kernels by total time only (many dispatches)
+        trace(sys.argv[2], sys.argv[3], sys.argv[4], per_dispatch=False)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     elif sys.argv[1] == "sq":
