@@ -15,14 +15,17 @@ time:
   -> Adams-Bashforth-2 push.
 
 Every floating-point quantity is IEEE binary64 except the sums that cancel
-(the Gauss/log sums of the psi family, eqs. dpsi_dr and psi, and the ion
-node fields), which are accumulated in 80-bit extended precision and rounded
-to binary64 once.  The two-point recursion (eq. ai_bi with b_0=0, a_N=0) is
+(the Gauss/log sums of the psi family, eqs. dpsi_dr and psi, the ion node
+fields and the d_zeta psi sum), which are formed in 80-bit extended
+precision from prefix sums accumulated in double-double (about 106 bits,
+``prefix_sum``) and rounded to binary64 once.  The two-point recursion
+(eq. ai_bi with b_0=0, a_N=0) is
 solved as the linear system it defines, with LAPACK's banded LU (partial
 pivoting); the paper's shooting procedure is kept as ``solve_shooting``.
 
 Readings taken where the paper is silent, garbled or self-inconsistent
-(numbered as in the design notes, R1..R13):
+(numbered as in the design notes; R16, the parity norm, concerns the tests
+only):
   R1  electrons carry q=-1, m=1; psibar = 1 + psi = gamma - u_z.
   R2  d_zeta psi = +sum_{rho_k>rho} q w u/(rho psibar)   (the printed sum is
       its negative; derived by differentiating eq. psi with eq. motion_2).
@@ -50,6 +53,13 @@ Readings taken where the paper is silent, garbled or self-inconsistent
   R14 (numerics, not model) ln rho is evaluated as ln r0 + log1p((rho-r0)/r0)
       so that its rounding, multiplied by the enclosed charge in eq. psi,
       stays proportional to the ring displacement.
+  R15 (numerics) the B^(p) recursion is solved as the linear system it
+      defines (eq. ai_bi with b_0 = 0, a_N = 0) by banded LU, followed by
+      two steps of iterative refinement whose residuals are accumulated in
+      80-bit arithmetic: the binary64 LU alone loses digits with the
+      system's conditioning at 10^5 rings.  The paper's shooting procedure
+      (Appendix "Solve recursive system") reaches the same solution with a
+      loss of about log10(I1(R_p)^2) digits and is kept as solve_shooting.
   R17 fields at radii off the rings (Fig. 2, external grid): the same sums
       with no ring at the radius (no w^ term, no own-ring share), B^(p) from
       the interval's (a, b); a ring at exactly that radius counts as
@@ -72,6 +82,145 @@ BREAKDOWN = -5
 
 
 # ---------------------------------------------------------------------------
+# double-double arithmetic (for psi, whose terms cancel) and accurate sums
+# ---------------------------------------------------------------------------
+def _two_sum(a, b):
+    """a + b = s + e exactly (binary64 arrays; numpy does not contract)."""
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def _quick_two_sum(a, b):
+    """a + b = s + e exactly when |a| >= |b|."""
+    s = a + b
+    return s, b - (s - a)
+
+
+def _split(a):
+    """Dekker's split: a = h + l with h, l of at most 26 significand bits."""
+    c = 134217729.0 * a
+    h = c - (c - a)
+    return h, a - h
+
+
+def _two_prod(a, b):
+    """a * b = p + e exactly (Dekker's product, no fused multiply-add)."""
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    return p, ((ah * bh - p) + ah * bl + al * bh) + al * bl
+
+
+class DD:
+    """Double-double numbers: unevaluated sums hi + lo of binary64 arrays
+    (about 106 significand bits), for the psi sums, whose terms cancel."""
+
+    def __init__(self, hi, lo=None):
+        self.hi = np.asarray(hi, np.float64)
+        self.lo = np.zeros_like(self.hi) if lo is None else np.asarray(lo, np.float64)
+
+    @staticmethod
+    def of(x):
+        """Exact conversion of a DD, binary64 or 80-bit array (an 80-bit
+        value is the sum of two binary64 numbers: 64 significand bits)."""
+        if isinstance(x, DD):
+            return x
+        x = np.asarray(x)
+        if x.dtype == LD:
+            hi = x.astype(np.float64)
+            return DD(hi, (x - hi.astype(LD)).astype(np.float64))
+        return DD(x.astype(np.float64))
+
+    def __add__(self, o):
+        o = DD.of(o)
+        s, e = _two_sum(self.hi, o.hi)
+        t, f = _two_sum(self.lo, o.lo)
+        s, e = _quick_two_sum(s, e + t)
+        return DD(*_quick_two_sum(s, e + f))
+
+    __radd__ = __add__
+
+    def __neg__(self):
+        return DD(-self.hi, -self.lo)
+
+    def __sub__(self, o):
+        return self + (-DD.of(o))
+
+    def __rsub__(self, o):
+        return DD.of(o) + (-self)
+
+    def __mul__(self, o):
+        o = DD.of(o)
+        p, e = _two_prod(self.hi, o.hi)
+        e = e + (self.hi * o.lo + self.lo * o.hi)
+        return DD(*_quick_two_sum(p, e))
+
+    __rmul__ = __mul__
+
+    def __getitem__(self, k):
+        return DD(self.hi[k], self.lo[k])
+
+    def __len__(self):
+        return len(self.hi)
+
+    def ld(self):
+        """Rounded to 80-bit extended precision."""
+        return self.hi.astype(LD) + self.lo.astype(LD)
+
+    def f64(self):
+        """Rounded to binary64."""
+        return self.hi + self.lo
+
+
+def dd_cat(parts):
+    parts = [DD.of(p) for p in parts]
+    return DD(np.concatenate([np.atleast_1d(p.hi) for p in parts]),
+              np.concatenate([np.atleast_1d(p.lo) for p in parts]))
+
+
+def dd_log(x):
+    """ln x of positive binary64 values as double-doubles, from 40-digit
+    logarithms (mpmath)."""
+    import mpmath
+    out_h = np.empty(len(x))
+    out_l = np.empty(len(x))
+    with mpmath.workdps(40):
+        for i, v in enumerate(np.asarray(x, np.float64)):
+            l = mpmath.log(mpmath.mpf(float(v)))
+            h = float(l)
+            out_h[i] = h
+            out_l[i] = float(l - h)
+    return DD(out_h, out_l)
+
+
+def prefix_sum(x):
+    """Inclusive prefix sums x_0 + ... + x_i (a DD array; x: DD, binary64 or
+    80-bit), each the exact sum to about 2^-100 of the magnitudes involved.
+    The terms are added in double-double arithmetic over the log2(n) steps
+    of a scan (step d adds the running sum d places back): at this
+    precision the order of the additions does not show in the result.  (A
+    plain 80-bit running sum over 2e5 terms of the psi sums errs by a few
+    1e-15, more than 1e-12 of a psi of order 1e-3.)"""
+    x = DD.of(x)
+    hi, lo = x.hi.copy(), x.lo.copy()
+    d = 1
+    while d < len(hi):
+        t = DD(hi[d:], lo[d:]) + DD(hi[:-d], lo[:-d])
+        hi = np.concatenate([hi[:d], t.hi])
+        lo = np.concatenate([lo[:d], t.lo])
+        d *= 2
+    return DD(hi, lo)
+
+
+def suffix_sum(x):
+    """Inclusive suffix sums x_i + ... + x_{n-1}, as prefix_sum."""
+    x = DD.of(x)
+    r = prefix_sum(DD(x.hi[::-1], x.lo[::-1]))
+    return DD(r.hi[::-1], r.lo[::-1])
+
+
+# ---------------------------------------------------------------------------
 # set-up (Sec. "Discretization of plasma species into macroparticles")
 # ---------------------------------------------------------------------------
 def ring_weights(r0, dr, dens=None):
@@ -84,33 +233,33 @@ def ring_weights(r0, dr, dens=None):
     return w, wh
 
 
-def _gauss_log_sums(rho_l, w_l, wh_l, q, lnr):
-    """Fields of one species at its own sorted ring radii, extended precision.
+def _gauss_log_sums(rho_l, w, wh, q, lnr):
+    """Fields of one species at its own sorted ring radii.
 
     eq. dpsi_dr : d_rho psi(rho) = -(1/rho) sum_{rho_k<rho} q w_k
     eq. psi     : psi(rho) = -sum_k q w_k ln max(rho, rho_k)
     At the ring itself the ring contributes w^ to the Gauss sum (R6); psi is
-    continuous there.  lnr = ln(rho_l).  Returns (psi, d_rho psi, psi on the
-    axis).
+    continuous there.  w, wh: binary64 weights; lnr = ln(rho_l) as DD.
+    Returns (psi as DD, d_rho psi in 80-bit, psi on the axis as DD).
     """
-    csum = np.cumsum(w_l)
-    below = np.concatenate([np.zeros(1, LD), csum[:-1]])        # sum_{k<i} w_k
-    wl = w_l * lnr
-    rsum = np.cumsum(wl[::-1])[::-1]                              # sum_{k>=i}
-    above = np.concatenate([rsum[1:], np.zeros(1, LD)])          # sum_{k>i}
-    dpsi = -q * (below + wh_l) / rho_l
-    psi = -q * ((below + w_l) * lnr + above)
-    psi_axis = -q * rsum[0]
+    csum = prefix_sum(w)
+    below = dd_cat([DD(0.0), csum[:-1]])                          # sum_{k<i} w_k
+    wl = lnr * np.asarray(w, np.float64)
+    rsum = suffix_sum(wl)                                         # sum_{k>=i}
+    above = dd_cat([rsum[1:], DD(0.0)])                           # sum_{k>i}
+    dpsi = -q * (below.ld() + np.asarray(wh, LD)) / rho_l
+    psi = ((below + np.asarray(w, np.float64)) * lnr + above) * (-q)
+    psi_axis = rsum[0:1] * (-q)
     return psi, dpsi, psi_axis
 
 
 class IonNodes:
     """Immobile ion rings at the initial radii (reading R11)."""
 
-    def __init__(self, r0, w, wh):
-        r0_l, w_l, wh_l = r0.astype(LD), w.astype(LD), wh.astype(LD)
-        psi, dpsi, psi_axis = _gauss_log_sums(r0_l, w_l, wh_l, Q_ION, np.log(r0_l))
-        self.Q = np.cumsum(w_l)[-1]
+    def __init__(self, r0, w, wh, lnr0):
+        """lnr0: ln r0 as DD."""
+        psi, dpsi, psi_axis = _gauss_log_sums(r0.astype(LD), w, wh, Q_ION, lnr0)
+        self.Q = prefix_sum(w)[len(w) - 1:]
         self.Rp = None
         self.r = None
         self._psi = psi
@@ -118,31 +267,34 @@ class IonNodes:
         self._psi_axis = psi_axis
         self._r0 = r0
 
-    def finish(self, Rp):
+    def finish(self, Rp, lnRp):
+        """Rp: the plasma edge; lnRp: its logarithm as DD."""
         self.Rp = LD(Rp)
         self.r = np.concatenate([[LD(0)], self._r0.astype(LD), [self.Rp]])
-        self.psi = np.concatenate([[self._psi_axis], self._psi,
-                                   [-Q_ION * self.Q * np.log(self.Rp)]])
+        self.psi = dd_cat([self._psi_axis, self._psi, self.Q * DD.of(lnRp) * (-Q_ION)])
         self.dpsi = np.concatenate([[LD(0)], self._dpsi,
-                                    [-Q_ION * self.Q / self.Rp]])
+                                    [-Q_ION * self.Q.ld()[0] / self.Rp]])
         return self
 
-    def at(self, rho):
-        """Ion psi and d_rho psi at radii rho: linear interpolation between the
-        bracketing nodes, j = last node with r_j < rho (Key algorithmic
-        adjustments); exact exterior field beyond the plasma edge."""
+    def at(self, rho, lnrho):
+        """Ion psi (DD) and d_rho psi (80-bit) at radii rho (lnrho: their
+        logarithms as DD): linear interpolation between the bracketing
+        nodes, j = last node with r_j < rho (Key algorithmic adjustments),
+        psi as the lower node's value plus t times the step; exact exterior
+        field beyond the plasma edge."""
         rho_l = np.asarray(rho).astype(LD)
         j = np.searchsorted(self.r, rho_l, side="left") - 1
         outside = j >= len(self.r) - 1
         jj = np.clip(j, 0, len(self.r) - 2)
         r_lo, r_hi = self.r[jj], self.r[jj + 1]
         t = (rho_l - r_lo) / (r_hi - r_lo)
-        psi = (1 - t) * self.psi[jj] + t * self.psi[jj + 1]
+        psi = self.psi[jj] + (self.psi[jj + 1] - self.psi[jj]) * DD.of(t)
         dpsi = (1 - t) * self.dpsi[jj] + t * self.dpsi[jj + 1]
         if np.any(outside):
-            ro = rho_l[outside]
-            psi[outside] = -Q_ION * self.Q * np.log(ro)
-            dpsi[outside] = -Q_ION * self.Q / ro
+            ext = DD.of(lnrho)[outside] * self.Q * (-Q_ION)
+            psi.hi[outside] = ext.hi
+            psi.lo[outside] = ext.lo
+            dpsi[outside] = -Q_ION * self.Q.ld()[0] / rho_l[outside]
         return psi, dpsi
 
 
@@ -215,26 +367,28 @@ def laser_terms(src, xi, rho):
 # ---------------------------------------------------------------------------
 # the per-slice steps
 # ---------------------------------------------------------------------------
-def ring_log(rho, r0):
-    """ln(rho) of rings whose initial radius is r0, evaluated as
-    ln r0 + log1p((rho - r0)/r0) in extended precision (reading R14): the
-    psi sums multiply ln rho by the enclosed charge, so its rounding must
-    scale with the ring's displacement, not with |ln rho|."""
+def ring_log(rho, r0, lnr0):
+    """ln(rho) of rings whose initial radius is r0 (lnr0 = ln r0 as DD),
+    evaluated as ln r0 + log1p((rho - r0)/r0) with the log1p in 80-bit
+    arithmetic (reading R14): the psi sums multiply ln rho by the enclosed
+    charge, so its rounding must scale with the ring's displacement, not
+    with |ln rho|.  Returns DD."""
     r0_l = np.asarray(r0).astype(LD)
-    return np.log(r0_l) + np.log1p((np.asarray(rho).astype(LD) - r0_l) / r0_l)
+    return DD.of(lnr0) + np.log1p((np.asarray(rho).astype(LD) - r0_l) / r0_l)
 
 
-def psi_family(rho, w, wh, ions, r0):
+def psi_family(rho, w, wh, ions, r0, lnr0):
     """psi and d_rho psi at sorted electron rings plus the ion species
     (eqs. dpsi_dr, psi; species summed after interpolation, R11).  r0 are
-    the rings' initial radii.  Returns binary64 (psi, dpsi, psi_axis)."""
+    the rings' initial radii, lnr0 their logarithms (DD).  Returns binary64
+    (psi, dpsi, psi_axis)."""
     rho_l = rho.astype(LD)
-    psi_e, dpsi_e, axis_e = _gauss_log_sums(rho_l, w.astype(LD), wh.astype(LD), Q_E,
-                                            ring_log(rho, r0))
-    psi_i, dpsi_i = ions.at(rho_l)
-    psi = (psi_e + psi_i).astype(np.float64)
+    lnr = ring_log(rho, r0, lnr0)
+    psi_e, dpsi_e, axis_e = _gauss_log_sums(rho_l, w, wh, Q_E, lnr)
+    psi_i, dpsi_i = ions.at(rho_l, lnr)
+    psi = (psi_e + psi_i).f64()
     dpsi = (dpsi_e + dpsi_i).astype(np.float64)
-    axis = float(axis_e + ions.psi[0])
+    axis = float((axis_e + ions.psi[0:1]).f64()[0])
     return psi, dpsi, axis
 
 
@@ -252,7 +406,7 @@ def dzeta_psi(rho, u, w, wh, psibar):
     weight w - w^.  Returns (dzpsi at rings, dzpsi on the axis)."""
     c = (Q_E * u / (rho * psibar)).astype(LD)
     term = w.astype(LD) * c
-    rsum = np.cumsum(term[::-1])[::-1]
+    rsum = suffix_sum(term).ld()
     above = np.concatenate([rsum[1:], np.zeros(1, LD)])
     own = (w - wh).astype(LD) * c
     return (above + own).astype(np.float64), float(rsum[0]) if len(rsum) else 0.0
@@ -371,6 +525,24 @@ def forces(u, psibar, gamma, dpsi, bt, da2, q=Q_E, m=M_E):
     return f_rho, f_u
 
 
+def push_ab2(rho, u, fr, fu, fr_p, fu_p, dxi):
+    """One second-order Adams-Bashforth step of (rho, u_r) in xi
+    (eqs. plasma_particle_motion_1-2; Sec. "Integration into Wake-T"): x +=
+    dxi (3/2 f - 1/2 f_prev).  A ring pushed to a negative radius is
+    reflected through the axis (reading R9): rho, u_r and the derivatives
+    kept as the next step's history change sign.  Returns (rho, u, f_rho,
+    f_u) after the step, the last two being the history to keep."""
+    rho_n = rho + dxi * (1.5 * fr - 0.5 * fr_p)
+    u_n = u + dxi * (1.5 * fu - 0.5 * fu_p)
+    frs, fus = np.array(fr, np.float64), np.array(fu, np.float64)
+    neg = rho_n < 0                                                   # R9
+    rho_n[neg] = -rho_n[neg]
+    u_n[neg] = -u_n[neg]
+    frs[neg] = -frs[neg]
+    fus[neg] = -fus[neg]
+    return rho_n, u_n, frs, fus
+
+
 def grid_radii(n_r, r_max):
     """Nodes of a uniform radial field grid: cell centres (g + 1/2) dr_g,
     dr_g = r_max / n_r (reading R17)."""
@@ -392,7 +564,9 @@ class RingOracle:
         self.n_xi = int(n_xi)
         self.w, self.wh = ring_weights(self.r0, self.dr, dens)
         self.Rp = float(self.r0[-1] + self.dr[-1] / 2.0)
-        self.ions = IonNodes(self.r0, self.w, self.wh).finish(self.Rp)
+        self.lnr0 = dd_log(self.r0)
+        self.ions = IonNodes(self.r0, self.w, self.wh, self.lnr0).finish(self.Rp, dd_log([self.Rp]))
+        self._grid_logs = {}
         beams = [s for s in sources if getattr(s, "kind", "") == "particles"]
         self.analytic = [s for s in sources if getattr(s, "kind", "") == "gaussian"]
         self.lasers = [s for s in sources if getattr(s, "kind", "") == "laser"]
@@ -425,7 +599,7 @@ class RingOracle:
         u = state["u"][ids]
         w, wh = self.w[ids], self.wh[ids]
         bb, a2, da2 = self.sources_at(n, rho)
-        psi, dpsi, psi_axis = psi_family(rho, w, wh, self.ions, self.r0[ids])
+        psi, dpsi, psi_axis = psi_family(rho, w, wh, self.ions, self.r0[ids], self.lnr0[ids])
         psibar, gamma = local_quantities(psi, u, a2)
         out = dict(status=0)
         if not np.all(psibar > 0) or not np.all(np.isfinite(psibar)):  # R10
@@ -445,14 +619,7 @@ class RingOracle:
                 fr_p, fu_p = fr, fu
             else:
                 fr_p, fu_p = state["fr"][ids], state["fu"][ids]
-            rho_n = rho + self.dxi * (1.5 * fr - 0.5 * fr_p)
-            u_n = u + self.dxi * (1.5 * fu - 0.5 * fu_p)
-            frs, fus = fr.copy(), fu.copy()
-            neg = rho_n < 0                                           # R9
-            rho_n[neg] = -rho_n[neg]
-            u_n[neg] = -u_n[neg]
-            frs[neg] = -frs[neg]
-            fus[neg] = -fus[neg]
+            rho_n, u_n, frs, fus = push_ab2(rho, u, fr, fu, fr_p, fu_p, self.dxi)
             new = {k: np.empty(self.N) for k in ("rho", "u", "fr", "fu")}
             new["rho"][ids], new["u"][ids] = rho_n, u_n
             new["fr"][ids], new["fu"][ids] = frs, fus
@@ -492,20 +659,22 @@ class RingOracle:
         w = self.w[ids]
         r = np.asarray(radii, np.float64)
         k = np.searchsorted(rho, r, side="left")
-        w_l = w.astype(LD)
-        lnr_k = ring_log(rho, self.r0[ids])                          # R14
-        S = np.concatenate([np.zeros(1, LD), np.cumsum(w_l)])          # sum_{j<k} w_j
-        wl = w_l * lnr_k
-        T = np.concatenate([np.cumsum(wl[::-1])[::-1], np.zeros(1, LD)])   # sum_{j>=k} w ln rho
+        key = r.tobytes()
+        if key not in self._grid_logs:
+            self._grid_logs = {key: dd_log(r)}
+        lnr_g = self._grid_logs[key]
+        lnr_k = ring_log(rho, self.r0[ids], self.lnr0[ids])           # R14
+        S = dd_cat([DD(0.0), prefix_sum(w)])                          # sum_{j<k} w_j
+        T = dd_cat([suffix_sum(lnr_k * w), DD(0.0)])                  # sum_{j>=k} w ln rho
         r_l = r.astype(LD)
-        psi_e = -Q_E * (S[k] * np.log(r_l) + T[k])                     # eq. psi
-        dpsi_e = -Q_E * S[k] / r_l                                     # eq. dpsi_dr
-        psi_i, dpsi_i = self.ions.at(r_l)                              # R11
-        c = w_l * (Q_E * u / (rho * out["psibar"])).astype(LD)
-        V = np.concatenate([np.cumsum(c[::-1])[::-1], np.zeros(1, LD)])   # eq. dpsi_dzeta, R2
+        psi_e = (S[k] * lnr_g + T[k]) * (-Q_E)                        # eq. psi
+        dpsi_e = -Q_E * S[k].ld() / r_l                               # eq. dpsi_dr
+        psi_i, dpsi_i = self.ions.at(r_l, lnr_g)                      # R11
+        c = w.astype(LD) * (Q_E * u / (rho * out["psibar"])).astype(LD)
+        V = np.concatenate([suffix_sum(c).ld(), np.zeros(1, LD)])     # eq. dpsi_dzeta, R2
         bb, _, _ = self.sources_at(n, r)
         bt = bb + out["a"][k] * r + out["b"][k] / r                   # eq. b_theta_plasma
-        return dict(psi=(psi_e + psi_i).astype(np.float64),
+        return dict(psi=(psi_e + psi_i).f64(),
                     er_bt=(-(dpsi_e + dpsi_i)).astype(np.float64),
                     ez=(-V[k]).astype(np.float64), bt=bt)
 

@@ -79,8 +79,10 @@ def test_psi_family_matches_pairwise_sums():
     ion_psi.append(-Q * mpmath.log(mpmath.mpf(Rp)))
     ion_dpsi.append(-Q / mpmath.mpf(Rp))
     ids = np.lexsort((np.arange(n), rho))
+    lnr0 = O.dd_log(r0)
     psi, dpsi, axis = O.psi_family(rho[ids], w[ids], wh[ids],
-                                   O.IonNodes(r0, w, wh).finish(Rp), r0[ids])
+                                   O.IonNodes(r0, w, wh, lnr0).finish(Rp, O.dd_log([Rp])), r0[ids],
+                                   lnr0[ids])
     mp = mpmath.mpf
     scale = 0.0
     errs = []
