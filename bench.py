@@ -39,6 +39,10 @@ ALG_FLOPS_PER_RING_SLICE = 280
 # history terms, w and w^ (48 B); write rho, u_r and the history (32 B); the
 # ion-table interpolation (32 B, cache resident).
 ALG_BYTES_PER_RING_SLICE = 48 + 32 + 32
+# Cooperative layout of the large single solves (wake_set_cluster arguments):
+# two rings per member thread, cooperative from the LDS limit on.  The
+# full-size parity tests run this same layout.
+LARGE_CLUSTER = (2, 0)
 
 
 def log(*a):
@@ -364,7 +368,7 @@ def main():
         # which gives it more throughput; 200000 rings need seven, the
         # fewest that keep within 64 members)
         log("large instances")
-        wake.wake_set_cluster(2, 0)
+        wake.wake_set_cluster(*LARGE_CLUSTER)
         big = {}
         for name, mk in (("blowout 20000 rings x 4000 slices", W.config2),
                          ("laser 200000 rings x 8000 slices", W.config5)):

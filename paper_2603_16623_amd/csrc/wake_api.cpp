@@ -84,8 +84,10 @@ struct wake_batch {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<wake_ctx*> ctxs;
-  WakeInst* d_insts = nullptr;
+  WakeInst* d_insts = nullptr;     // descriptors of eager solves
   int32_t* d_counter = nullptr;
+  WakeInst* d_ginsts = nullptr;    // descriptors the captured graph reads (written by capture only)
+  int32_t* d_gcounter = nullptr;
   int cap = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -448,7 +450,7 @@ extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt
   } else {
     if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
     if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
-    if (slice >= c->next) return WAKE_ESTATE;
+    if (slice >= c->next || slice < c->valid_from) return WAKE_ESTATE;
     if (I.stride <= 0 || slice % I.stride != 0) return WAKE_ENOTREC;
     base = I.snap + (size_t)(slice / I.stride) * OUT_N * I.N;
   }
@@ -510,7 +512,7 @@ extern "C" int wake_grid_fields(wake_ctx* c, int32_t slice, double* psi, double*
   }
   if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
   if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
-  if (slice >= c->next) return WAKE_ESTATE;
+  if (slice >= c->next || slice < c->valid_from) return WAKE_ESTATE;
   const size_t ng = I.grid_n;
   const double* base = I.grid + (size_t)slice * 4 * ng;
   double* outs[4] = {psi, erbt, ez, bt};
@@ -579,6 +581,7 @@ extern "C" int wake_set_state(wake_ctx* c, int32_t slice, const double* rho, con
                            f_u ? st + 3 * N : nullptr, slice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->next = slice;
+  c->valid_from = slice;
   return WAKE_OK;
 }
 
@@ -590,6 +593,7 @@ extern "C" int wake_reset(wake_ctx* c) {
   HIP_TRY(hipMemcpyAsync(c->d_inst, &c->I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(launch_reset(c->d_inst, 1, c->stream));
   c->next = 0;
+  c->valid_from = 0;
   return WAKE_OK;
 }
 
@@ -665,6 +669,8 @@ static void batch_release(wake_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_insts) (void)hipFree(b->d_insts);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->d_ginsts) (void)hipFree(b->d_ginsts);
+  if (b->d_gcounter) (void)hipFree(b->d_gcounter);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   if (b->holds)
     for (wake_ctx* c : b->ctxs) --c->batches;
@@ -699,7 +705,9 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
   }
   b->cap = n;
   if (hipMalloc(&b->d_insts, sizeof(WakeInst) * n) != hipSuccess ||
-      hipMalloc(&b->d_counter, 64) != hipSuccess) {
+      hipMalloc(&b->d_counter, 64) != hipSuccess ||
+      hipMalloc(&b->d_ginsts, sizeof(WakeInst) * n) != hipSuccess ||
+      hipMalloc(&b->d_gcounter, 64) != hipSuccess) {
     batch_release(b);
     return WAKE_ENOMEM;
   }
@@ -762,8 +770,10 @@ hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts,
   return hipSuccess;
 }
 
-static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v, int grid_override) {
-  return launch_insts(v, b->d_insts, b->d_counter, b->device, grid_override, b->stream);
+static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v, int grid_override,
+                               bool graph) {
+  return launch_insts(v, graph ? b->d_ginsts : b->d_insts, graph ? b->d_gcounter : b->d_counter,
+                      b->device, grid_override, b->stream);
 }
 
 extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
@@ -777,7 +787,7 @@ extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
   const int n = batch_stage(b, n_slices, false, v);
   if (n == 0) return WAKE_OK;
   HIP_TRY(hipMemcpyAsync(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(batch_launch(b, v, 0));
+  HIP_TRY(batch_launch(b, v, 0, false));
   for (wake_ctx* c : b->ctxs) {
     int count = c->I.n_xi - c->next;
     if (n_slices >= 0) count = std::min(count, (int)n_slices);
@@ -797,13 +807,15 @@ extern "C" int wake_batch_capture(wake_batch* b, int32_t grid) {
   std::vector<WakeInst> v;
   const int n = batch_stage(b, -1, true, v);
   if (n == 0) return WAKE_EINVAL;
-  HIP_TRY(hipMemcpy(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice));
+  // the graph reads descriptors of its own: eager solves of the batch
+  // between a capture and its replays rewrite only d_insts
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemcpy(b->d_ginsts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice));
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-  HIP_TRY(hipStreamSynchronize(b->stream));
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = launch_reset(b->d_insts, n, b->stream);
-  if (e == hipSuccess) e = batch_launch(b, v, grid);
+  hipError_t e = launch_reset(b->d_ginsts, n, b->stream);
+  if (e == hipSuccess) e = batch_launch(b, v, grid, true);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -812,7 +824,10 @@ extern "C" int wake_batch_capture(wake_batch* b, int32_t grid) {
   }
   b->graph = graph;
   HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-  for (wake_ctx* c : b->ctxs) c->next = 0;
+  for (wake_ctx* c : b->ctxs) {
+    c->next = 0;
+    c->valid_from = 0;
+  }
   return WAKE_OK;
 }
 
@@ -822,6 +837,7 @@ extern "C" int wake_batch_replay(wake_batch* b) {
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   for (wake_ctx* c : b->ctxs) {
     c->next = c->I.n_xi;
+    c->valid_from = 0;
     c->pending = b->stream;
   }
   return WAKE_OK;

@@ -2269,7 +2269,12 @@ hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, co
 }
 
 // Field-grid node table: ln r_g and the immobile ions' psi - psi(0) and
-// d_rho psi at r_g (the same interpolation as at the rings), dd pairs.
+// d_rho psi at r_g (the same interpolation as at the rings), dd pairs.  The
+// table is made once per grid, so psi's interpolation is carried out in
+// double-double throughout: the weight t = (r - lo)/(hi - lo) from exact
+// differences and the step between the nodes' double-double values (at the
+// rings the step is rounded to double, which resolves psi to ~1e-16 of the
+// step; nodes between rings at rest see psi of order w dr^2 only).
 __global__ void grid_init_kernel(WakeInst I, double* tab) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= I.grid_n) return;
@@ -2286,6 +2291,20 @@ __global__ void grid_init_kernel(WakeInst I, double* tab) {
   ion_load(IV, h, q);
   dd ps, dp;
   ion_fields(IV, r, l, h, q, ps, dp);
+  if (r < I.Rp) {
+    const dd a = two_sum(r, -q[IR_LO]);            // r - lo, exact
+    const dd b = two_sum(q[IR_HI], -q[IR_LO]);     // hi - lo, exact
+    dd t = dd_div_d(a, b.hi);
+    t = dd_add_d(t, -t.hi * b.lo / b.hi);          // a / (b.hi + b.lo) to second order
+    dd nxt;                                         // psi - psi(0) at the upper node
+    if (h < I.N) {
+      nxt = {I.ion[(size_t)(h + 1) * WAKE_ION_REC + IR_PSH], I.ion[(size_t)(h + 1) * WAKE_ION_REC + IR_PSL]};
+    } else {                                        // the plasma edge: exterior value there
+      nxt = dd_sub(IV.T0, dd_mul(IV.Q, dd_log(I.Rp)));
+    }
+    const dd lo_ps = {q[IR_PSH], q[IR_PSL]};
+    ps = dd_add(lo_ps, dd_mul(dd_sub(nxt, lo_ps), t));
+  }
   double* t = tab + (size_t)WAKE_GRID_TAB * g;
   t[0] = l.hi; t[1] = l.lo;
   t[2] = ps.hi; t[3] = ps.lo;

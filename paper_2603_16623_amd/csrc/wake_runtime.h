@@ -38,6 +38,7 @@ struct wake_ctx {
   bool prepared = false;
   int batches = 0;                 // batches that hold this context
   int next = 0;
+  int valid_from = 0;              // first slice whose records belong to the current state's march
   hipStream_t pending = nullptr;   // batch stream that last marched this context
 };
 

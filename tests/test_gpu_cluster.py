@@ -11,8 +11,8 @@ from paper_2603_16623_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ("psi", "er_bt", "ez", "bt")
-TOL_SLICE = 1e-12
+from parity import (FIELDS, TOL_SLICE, check_axis, check_fields, check_state, field_scales,
+                    pushed_by_device, rel as _rel)
 
 
 @pytest.fixture(scope="module")
@@ -30,21 +30,6 @@ def _say(*a):
 
 def _oracle(inst):
     return RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
-
-
-def _field_scale(ref):
-    parts = [np.abs(ref[q]).max() for q in FIELDS]
-    parts += [np.abs(ref["C"]).max(), np.abs(ref["bb"]).max(), abs(ref["psi_axis"]), abs(ref["ez_axis"])]
-    return float(max(parts))
-
-
-def _tol(F):
-    return TOL_SLICE * F if F > 0 else 1e-15
-
-
-def _rel(a, b):
-    s = float(np.max(np.abs(b))) if b.size else 0.0
-    return float(np.max(np.abs(a - b))) / (s if s > 0 else 1.0)
 
 
 def _inst(n=3000, n_xi=60, channel_w0=None):
@@ -74,29 +59,28 @@ def test_cluster_slice_parity(wk, tiling, rings, members, channel_w0):
             _, state = o.slice(m, state)
         at = n
         ref, new = o.slice(n, state, keep=True)
-        F = _field_scale(ref)
-        _say(f"cluster slice parity tiling={tiling} rings={rings} members={members} "
-             f"channel={channel_w0} slice={n} F={F:.3e}")
+        sc = field_scales(ref)
+        label = (f"cluster tiling={tiling} rings={rings} members={members} channel={channel_w0} "
+                 f"slice={n}")
+        _say(f"cluster slice parity {label}")
         s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
         s.wake_solve(n, 1)
         got = s.wake_fields(n)
-        for q in FIELDS:
-            e = float(np.max(np.abs(got[q] - ref[q])))
-            assert e <= _tol(F), (n, q, e, F)
+        check_fields(got, ref, sc, label)
         st = s.wake_get_state()
         assert st["slice"] == n + 1
-        for a, b in (("rho", "rho"), ("ur", "u"), ("f_rho", "fr"), ("f_u", "fu")):
-            assert _rel(st[a], new[b]) <= TOL_SLICE, (n, a)
+        check_state(st, new, label)
         lp, le = s.wake_lineout()
-        assert abs(lp[n] - ref["psi_axis"]) <= _tol(F)
-        assert abs(le[n] - ref["ez_axis"]) <= _tol(F)
+        check_axis(lp, le, n, ref, sc, label)
     s.close()
 
 
 @pytest.mark.parametrize("u_amp", [0.05, 2.0, 40.0])
 def test_cluster_reorder_after_push(wk, u_amp):
     """Pushed rings crossing a few to thousands of neighbours, across member
-    boundaries: block rounds, and the bitonic fallback for the far moves."""
+    boundaries: block rounds, and the bitonic fallback for the far moves.
+    The slice after the push (same launch) against the oracle's slice on
+    the device's pushed state."""
     rng = np.random.default_rng(31)
     inst = _inst(n_xi=40)
     o = _oracle(inst)
@@ -104,19 +88,20 @@ def test_cluster_reorder_after_push(wk, u_amp):
     state["u"] = rng.normal(0, u_amp, inst.n_rings)
     n = 10
     _, mid = o.slice(n, state, keep=True)
-    ref, _ = o.slice(n + 1, mid, keep=True)
-    F = _field_scale(ref)
     wk.wake_set_tiling(256, 0)
     wk.wake_set_cluster(2, 500)
-    _say(f"cluster reorder u_amp={u_amp}")
+    label = f"cluster reorder u_amp={u_amp}"
+    _say(label)
+    st, mid_dev = pushed_by_device(wk, inst, n, state)
+    check_state(st, mid, label)
+    ref, _ = o.slice(n + 1, mid_dev, keep=True)
     s = wk.WakeSolver.from_instance(inst, record_stride=1)
     assert s.layout()[0] == 6
     s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(n, 2)
     got = s.wake_fields(n + 1)
-    for q in FIELDS:
-        assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
-    assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
+    check_fields(got, ref, field_scales(ref), label)
+    assert np.array_equal(got["rho"], mid_dev["rho"])
     s.close()
 
 
@@ -130,7 +115,6 @@ def test_cluster_unsorted_injected_state(wk):
     state["rho"] = inst.r0 * np.exp(rng.normal(0, 0.2, inst.n_rings))
     state["u"] = rng.normal(0, 0.1, inst.n_rings)
     ref, new = o.slice(20, state, keep=True)
-    F = _field_scale(ref)
     wk.wake_set_tiling(256, 0)
     wk.wake_set_cluster(2, 500)
     _say("cluster unsorted injected state")
@@ -138,8 +122,7 @@ def test_cluster_unsorted_injected_state(wk):
     s.wake_set_state(20, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(20, 1)
     got = s.wake_fields(20)
-    for q in FIELDS:
-        assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
+    check_fields(got, ref, field_scales(ref), "cluster unsorted")
     st = s.wake_get_state()
     assert _rel(st["rho"], new["rho"]) <= TOL_SLICE
     s.close()
@@ -255,7 +238,8 @@ def test_cluster_fixups_in_device_memory(wk, u_amp):
     """Members whose keys exceed the LDS area (1024-thread workgroups, eight
     rings per thread: 8192 positions per member) fix their order in device
     memory: member-local rounds, rounds over all members and the bitonic
-    network, after pushes that move rings a few to thousands of places."""
+    network, after pushes that move rings a few to thousands of places.  The
+    slice after the push against the oracle's on the device's pushed state."""
     rng = np.random.default_rng(37)
     inst = W.small_instance(8, n_rings=17000, n_xi=20, n_peak=3.0, sigma_r=0.2, geometric=False, dxi=0.02)
     o = _oracle(inst)
@@ -263,18 +247,18 @@ def test_cluster_fixups_in_device_memory(wk, u_amp):
     state["u"] = rng.normal(0, u_amp, inst.n_rings)
     n = 8
     _, mid = o.slice(n, state, keep=True)
-    ref, _ = o.slice(n + 1, mid, keep=True)
-    F = _field_scale(ref)
     wk.wake_set_tiling(1024, 0)
     wk.wake_set_cluster(8, 500)
-    _say(f"cluster fix-ups in device memory u_amp={u_amp}")
+    label = f"cluster fix-ups in device memory u_amp={u_amp}"
+    _say(label)
+    st, mid_dev = pushed_by_device(wk, inst, n, state)
+    check_state(st, mid, label)
+    ref, _ = o.slice(n + 1, mid_dev, keep=True)
     s = wk.WakeSolver.from_instance(inst, record_stride=1)
     assert s.layout() == (3, 8)
     s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(n, 2)
     got = s.wake_fields(n + 1)
-    for q in FIELDS:
-        assert float(np.max(np.abs(got[q] - ref[q]))) <= _tol(F), q
-    assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
+    check_fields(got, ref, field_scales(ref), label)
+    assert np.array_equal(got["rho"], mid_dev["rho"])
     s.close()
-

@@ -5,7 +5,7 @@ Per-slice parity on identical state: a seeded perturbed state (radii jittered
 across their neighbours, random momenta and Adams-Bashforth history), not the
 product of either march, is given to both sides at a slice inside the driver,
 witness or laser; the fields at that slice and the pushed state must agree to
-the per-slice tolerance (tolerance reading in test_gpu_parity).  The jitter
+the per-slice, per-field tolerance (tests/parity.py).  The jitter
 crosses hundreds of rings, so the device's first order fix-up runs its long-run
 sort at these sizes.
 """
@@ -14,7 +14,7 @@ import pytest
 
 from oracle.wake_oracle import RingOracle, grid_radii
 from paper_2603_16623_amd import workloads as W
-from test_gpu_parity import FIELDS, TOL_SLICE, _field_scale, _field_tol, _rel
+from parity import FIELDS, check_axis, check_fields, check_state, field_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -40,35 +40,33 @@ def _perturbed(inst, seed, jitter):
                 fu=0.02 * rng.standard_normal(N))
 
 
-def _check_slice(wk, inst, n, state, label, grid=None):
-    """grid = (n_r, r_max): also the radial field grid of that slice."""
+def _check_slice(wk, inst, n, state, label, grid=None, layout=None):
+    """grid = (n_r, r_max): also the radial field grid of that slice;
+    layout = (members, rings per thread) the context must have."""
     o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
     ref, new = o.slice(n, state, push=True, keep=True)
     assert ref["status"] == 0, label
-    F = _field_scale(ref)
-    _say(f"full-size slice parity {label}: N={inst.n_rings} slice={n} F={F:.3e} grid={grid}")
+    sc = field_scales(ref)
     s = wk.WakeSolver.from_instance(inst, record_stride=n)
+    lay = s.layout()
+    _say(f"full-size slice parity {label}: N={inst.n_rings} slice={n} layout={lay} grid={grid}")
+    if layout is not None:
+        assert lay == layout, (label, lay, layout)
     if grid is not None:
         s.wake_set_grid(*grid)
     s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(n, 1)
     got = s.wake_fields(n)
-    for q in FIELDS:
-        e = float(np.max(np.abs(got[q] - ref[q])))
-        assert e <= _field_tol(F), (label, q, e, F)
+    check_fields(got, ref, sc, label)
     st = s.wake_get_state()
     assert st["slice"] == n + 1
-    for a, b in (("rho", "rho"), ("ur", "u"), ("f_rho", "fr"), ("f_u", "fu")):
-        assert _rel(st[a], new[b]) <= TOL_SLICE, (label, a, _rel(st[a], new[b]))
+    check_state(st, new, label)
     lp, le = s.wake_lineout()
-    assert abs(lp[n] - ref["psi_axis"]) <= _field_tol(F)
-    assert abs(le[n] - ref["ez_axis"]) <= _field_tol(F)
+    check_axis(lp, le, n, ref, sc, label)
     if grid is not None:
         want = o.fields_at(n, ref, grid_radii(*grid))
         got = s.wake_grid_fields(n)
-        for q in FIELDS:
-            e = float(np.max(np.abs(got[q] - want[q])))
-            assert e <= _field_tol(F), (label, "grid", q, e, F)
+        check_fields(got, ref, field_scales(ref, want), label + " grid", want=want)
     s.close()
 
 
@@ -117,3 +115,60 @@ def test_laser_witness_region_matches_split_launches(wk):
         assert np.array_equal(sa[q], sb[q]), q
     a.close()
     b.close()
+
+
+def _bench_layout(inst, nt=512):
+    """(members, rings per thread) of a context at the benchmark's
+    cooperative layout."""
+    from bench import LARGE_CLUSTER
+    rpt, _ = LARGE_CLUSTER
+    c = max(rpt or 8, -(-inst.n_rings // (64 * nt)))
+    return -(-inst.n_rings // (c * nt)), c
+
+
+def test_large_solves_at_the_benchmark_layout(wk):
+    """The 20000-ring and 200000-ring solves in exactly the layout the
+    benchmark times (512-thread members, two rings per thread where 64
+    members allow it): per-slice parity with a field grid."""
+    from bench import LARGE_CLUSTER
+    wk.wake_set_cluster(*LARGE_CLUSTER)
+    try:
+        inst = W.config2()
+        for n, seed in ((int(2.8 / inst.dxi), 4), (int(7.3 / inst.dxi), 5)):
+            _check_slice(wk, inst, n, _perturbed(inst, seed, 0.01), "blowout-20000x4000 bench layout",
+                         grid=(400, 2.0), layout=_bench_layout(inst))
+        inst = W.config5()
+        _check_slice(wk, inst, int(2.0 / inst.dxi), _perturbed(inst, 6, 0.002),
+                     "laser-200000x8000 bench layout", grid=(600, 18.0), layout=_bench_layout(inst))
+    finally:
+        wk.wake_set_cluster(0, 0)
+
+
+def test_benchmark_layout_split_launches_bitwise(wk):
+    """At the benchmark's layout, the 20000-ring blowout through its driver
+    (slices 0-1200) and the 200000-ring laser case through the start of its
+    witness region: one launch is bitwise the march split into launches."""
+    from bench import LARGE_CLUSTER
+    wk.wake_set_cluster(*LARGE_CLUSTER)
+    try:
+        for mk, stop, start, step in ((W.config2, 1200, 0, 100), (W.config5, 4100, 4000, 10)):
+            inst = mk()
+            _say(f"bench layout split launches N={inst.n_rings} through slice {stop}")
+            a = wk.WakeSolver.from_instance(inst)
+            assert a.layout() == _bench_layout(inst)
+            a.wake_solve(0, stop)
+            b = wk.WakeSolver.from_instance(inst)
+            if start:
+                b.wake_solve(0, start)
+            for n in range(start, stop, step):
+                b.wake_solve(n, step)
+            assert a.wake_status()[0] == -1 and b.wake_status()[0] == -1
+            la, lb = a.wake_lineout(), b.wake_lineout()
+            assert np.array_equal(la[0][:stop], lb[0][:stop]) and np.array_equal(la[1][:stop], lb[1][:stop])
+            fa, fb = a.wake_fields(-1), b.wake_fields(-1)
+            for q in FIELDS + ("rho",):
+                assert np.array_equal(fa[q], fb[q]), q
+            a.close()
+            b.close()
+    finally:
+        wk.wake_set_cluster(0, 0)

@@ -4,27 +4,22 @@ Per-slice cases feed both sides the identical ring state at slice n and
 compare the fields at n and the state pushed to n+1.  End-to-end cases
 compare whole marches (linear regime) to 1e-8.
 
-Tolerance reading.  Fields: max_i |gpu - oracle| <= 1e-12 * F_n, with F_n
-the slice's field scale: the largest magnitude among psi, E_r - B_theta,
-E_z, B_theta, the beam field B^(b) and the B_theta jumps C_i at that slice.
-B^(p) is assembled from the jumps C_i and can be orders of magnitude smaller
-than them (behind a linear driver, or under a weak laser), so it is measured
-against the scale of what it is computed from.  Ring state: elementwise,
-1e-12 of the largest magnitude of each quantity.  Both sides accumulate the
-cancelling Gauss/log sums beyond binary64, so what remains is O(1e-16)
-rounding times the O(1e2..1e3) cancellation of the B^(p) products.
+Tolerance reading (tests/parity.py).  Fields: per slice and per field,
+max_i |gpu - oracle| <= 1e-12 * scale of that field at that slice (B_theta's
+scale also takes the beam field B^(b) and the jumps C_i it is assembled
+from); every margin is printed.  Ring state: elementwise, 1e-12 of the
+largest magnitude of each quantity.  End to end: 1e-8 of each quantity's
+largest magnitude.
 """
 import numpy as np
 import pytest
 
 from oracle.wake_oracle import RingOracle
 from paper_2603_16623_amd import workloads as W
+from parity import (FIELDS, TOL_E2E, TOL_SLICE, check_axis, check_fields, check_state, field_scales,
+                    pushed_by_device, rel as _rel, say as _say)
 
 pytestmark = pytest.mark.gpu
-
-FIELDS = ("psi", "er_bt", "ez", "bt")
-TOL_SLICE = 1e-12
-TOL_E2E = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -33,30 +28,6 @@ def wk():
     wake.load()
     yield wake
     wake.wake_set_tiling(512, 0)
-
-
-def _say(*a):
-    print(*a, flush=True)
-
-
-def _rel(gpu, ref, scale=None):
-    if scale is None:
-        scale = float(np.max(np.abs(ref))) if ref.size else 0.0
-    return float(np.max(np.abs(gpu - ref))) / (scale if scale > 0 else 1.0)
-
-
-def _field_tol(F):
-    """Absolute field tolerance of a slice: 1e-12 of its field scale, or the
-    unperturbed-plasma bound 1e-15 when every field vanishes."""
-    return TOL_SLICE * F if F > 0 else 1e-15
-
-
-def _field_scale(ref):
-    """Field scale F_n of one oracle slice (fields, beam field, B jumps)."""
-    parts = [np.abs(ref[q]).max() for q in FIELDS]
-    parts += [np.abs(ref["C"]).max(), np.abs(ref["bb"]).max(), abs(ref["psi_axis"]),
-              abs(ref["ez_axis"])]
-    return float(max(parts))
 
 
 def _oracle(inst):
@@ -111,23 +82,20 @@ def test_slice_parity_on_identical_state(wk, case, tiling, slices):
         at = n
         ref, new = o.slice(n, state, push=n < inst.n_xi - 1, keep=True)
         assert ref["status"] == 0
-        F = _field_scale(ref)
-        _say(f"slice parity {case} tiling={tiling} slice={n} N={inst.n_rings} F={F:.3e}")
+        sc = field_scales(ref)
+        label = f"{case} tiling={tiling} slice={n} N={inst.n_rings}"
+        _say(f"slice parity {label}")
         s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
         s.wake_solve(n, 1)
         got = s.wake_fields(n)
-        for q in FIELDS:
-            e = float(np.max(np.abs(got[q] - ref[q])))
-            assert e <= _field_tol(F), (case, n, q, e, F)
+        check_fields(got, ref, sc, label)
         assert np.array_equal(got["rho"], state["rho"])
         if new is not None:
             st = s.wake_get_state()
             assert st["slice"] == n + 1
-            for a, b in (("rho", "rho"), ("ur", "u"), ("f_rho", "fr"), ("f_u", "fu")):
-                assert _rel(st[a], new[b]) <= TOL_SLICE, (case, n, a, _rel(st[a], new[b]))
+            check_state(st, new, label)
         lp, le = s.wake_lineout()
-        assert abs(lp[n] - ref["psi_axis"]) <= _field_tol(F)
-        assert abs(le[n] - ref["ez_axis"]) <= _field_tol(F)
+        check_axis(lp, le, n, ref, sc, label)
     s.close()
 
 
@@ -218,13 +186,11 @@ def test_unsorted_injected_state_is_sorted_first(wk):
         wk.wake_set_tiling(*tiling)
         _say(f"unsorted state tiling={tiling}")
         ref, new = o.slice(20, state, keep=True)
-        F = _field_scale(ref)
         s = wk.WakeSolver.from_instance(inst, record_stride=1)
         s.wake_set_state(20, state["rho"], state["u"], state["fr"], state["fu"])
         s.wake_solve(20, 1)
         got = s.wake_fields(20)
-        for q in FIELDS:
-            assert float(np.max(np.abs(got[q] - ref[q]))) <= _field_tol(F), (tiling, q)
+        check_fields(got, ref, field_scales(ref), f"unsorted tiling={tiling}")
         st = s.wake_get_state()
         assert _rel(st["rho"], new["rho"]) <= TOL_SLICE
         assert _rel(st["ur"], new["u"]) <= TOL_SLICE
@@ -235,7 +201,8 @@ def test_unsorted_injected_state_is_sorted_first(wk):
 def test_reorder_after_push(wk, u_amp):
     """Rings pushed past many neighbours in one step (from a few positions up
     to thousands) come out in the same order as the oracle's sort: the slice
-    after the push matches."""
+    after the push, marched in the same launch, matches the oracle's slice
+    on the device's pushed state (itself within 1e-12 of the oracle's)."""
     rng = np.random.default_rng(31)
     inst = W.small_instance(5, n_rings=3000, n_xi=40, n_peak=2.0, geometric=False)
     o = _oracle(inst)
@@ -243,20 +210,21 @@ def test_reorder_after_push(wk, u_amp):
     state["u"] = rng.normal(0, u_amp, inst.n_rings)
     n = 10
     _, mid = o.slice(n, state, keep=True)
-    ref, _ = o.slice(n + 1, mid, keep=True)
-    F = _field_scale(ref)
     order = np.lexsort((np.arange(inst.n_rings), mid["rho"]))
     disp = int(np.abs(np.argsort(order) - np.arange(inst.n_rings)).max())
     for tiling in ((512, 0), (256, 0)):
         wk.wake_set_tiling(*tiling)
-        _say(f"reorder after push u_amp={u_amp} tiling={tiling} max displacement {disp}")
+        label = f"reorder after push u_amp={u_amp} tiling={tiling}"
+        _say(f"{label} max displacement {disp}")
+        st, mid_dev = pushed_by_device(wk, inst, n, state)
+        check_state(st, mid, label)
+        ref, _ = o.slice(n + 1, mid_dev, keep=True)
         s = wk.WakeSolver.from_instance(inst, record_stride=1)
         s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
         s.wake_solve(n, 2)
         got = s.wake_fields(n + 1)
-        for q in FIELDS:
-            assert float(np.max(np.abs(got[q] - ref[q]))) <= _field_tol(F), (tiling, q)
-        assert _rel(got["rho"], mid["rho"]) <= TOL_SLICE
+        check_fields(got, ref, field_scales(ref), label)
+        assert np.array_equal(got["rho"], mid_dev["rho"])
         s.close()
 
 
@@ -385,3 +353,61 @@ def test_graph_replays_match_eager(wk):
     b.close()
     for s in solvers:
         s.close()
+
+
+def test_graph_replay_after_an_eager_solve_of_the_batch(wk):
+    """Capture, then an eager partial solve of the same batch, then a replay:
+    the replay marches every instance through its whole window from slice 0
+    (the graph keeps descriptors of its own), bitwise as the eager solve."""
+    wk.wake_set_tiling(512, 0)
+    rng = np.random.default_rng(46)
+    insts = [W.batched_instance(rng, n, 70, n_drv=2000, n_wit=500, r_max=4.0) for n in (900, 200, 450)]
+    _say("capture, eager solve(25), replay")
+    eager = []
+    for inst in insts:
+        s = wk.WakeSolver.from_instance(inst)
+        s.wake_solve(0, inst.n_xi)
+        eager.append((s.wake_lineout(), s.wake_get_state()["rho"], s.wake_fields(-1)))
+        s.close()
+    solvers = [wk.WakeSolver.from_instance(inst) for inst in insts]
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_capture()
+    b.wake_batch_solve(25)
+    b.wake_batch_sync()
+    for s in solvers:
+        assert s.wake_status() == (-1, 25)
+    b.wake_batch_replay()
+    b.wake_batch_sync()
+    for s, inst, ((lp, le), rho, last) in zip(solvers, insts, eager):
+        assert s.wake_status() == (-1, inst.n_xi)
+        glp, gle = s.wake_lineout()
+        assert np.array_equal(glp, lp) and np.array_equal(gle, le)
+        assert np.array_equal(s.wake_get_state()["rho"], rho)
+        g = s.wake_fields(-1)
+        for q in FIELDS:
+            assert np.array_equal(g[q], last[q]), q
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_snapshots_before_an_injected_state_are_refused(wk):
+    """After wake_set_state(n), recorded slices before n belong to no march of
+    this state: wake_fields refuses them (WAKE_ESTATE); slices marched from n
+    on are served."""
+    wk.wake_set_tiling(512, 0)
+    inst = W.small_instance(3, n_rings=300, n_xi=40, n_peak=1.0)
+    o = _oracle(inst)
+    state = o.initial_state()
+    for m in range(10):
+        _, state = o.slice(m, state)
+    s = wk.WakeSolver.from_instance(inst, record_stride=5)
+    s.wake_set_state(10, state["rho"], state["u"], state["fr"], state["fu"])
+    s.wake_solve(10, 10)
+    for n in (0, 5):
+        with pytest.raises(wk.WakeError) as e:
+            s.wake_fields(n)
+        assert e.value.code == wk.WAKE_ESTATE
+    ref, _ = o.slice(10, state, keep=True)
+    check_fields(s.wake_fields(10), ref, field_scales(ref), "after injected state")
+    s.close()
