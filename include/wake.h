@@ -114,7 +114,11 @@ int wake_add_beam(wake_ctx *ctx, const wake_source *src);
 int wake_prepare(wake_ctx *ctx);
 
 /* March slices [first_slice, first_slice + n_slices) on the context's
- * stream (asynchronous).  first_slice must equal the context's next slice
+ * stream (asynchronous): per slice the sort, sources, psi family, gamma,
+ * d_zeta psi, the coefficients and two-point recursion of B_theta^(p) and
+ * the push of Fig. 2 (right column) and Sec. "Numerical integration of
+ * wakefields" (eqs. dpsi_dr, psi, dpsi_dzeta, b_coeffs_1-3, ai_bi,
+ * plasma_particle_motion_1-4).  first_slice must equal the context's next slice
  * (0 after create, the end of the previous solve, or the slice given to
  * wake_set_state).  A breakdown stops the march at its slice and is
  * reported by wake_status / wake_fields. */
@@ -122,9 +126,13 @@ int wake_solve(wake_ctx *ctx, int32_t first_slice, int32_t n_slices);
 
 /* Fields at the rings of one solved slice, indexed by ring id: psi,
  * E_r - B_theta, E_z, B_theta, and the ring radius and radial momentum at
- * that slice.  slice = -1 means the last slice of the most recent solve;
- * otherwise the slice must be a recorded one (multiple of record_stride).
- * NULL outputs are skipped.  Synchronizes the context's stream. */
+ * that slice (the gauge relations eqs. lorentz_gauge_1-2 turn the solve's
+ * psi, d_rho psi and d_zeta psi into E_r - B_theta = -d_rho psi and
+ * E_z = -d_zeta psi; B_theta = B^(b) + B^(p), eq. b_theta_plasma).  slice = -1 means the last slice of the most recent solve;
+ * otherwise the slice must be a recorded one (multiple of record_stride) and
+ * marched from the current state (WAKE_ESTATE for slices before the slice
+ * of the last wake_set_state).  NULL outputs are skipped.  Synchronizes the
+ * context's stream. */
 int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, double *ez,
                 double *bt, double *rho, double *ur, int32_t dst_is_device);
 
@@ -146,11 +154,10 @@ int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 
 /* Grid fields of one solved slice [n_r each], slice-major storage read out
  * per slice (slice = -1: the slice before the context's next slice, i.e.
- * the last slice of the most recent solve; after wake_set_state without a
- * solve it names a slice this state has not marched; slices never marched
- * since wake_set_grid read as NaN).  WAKE_ESTATE without
- * a grid or for a slice at or after the next slice, WAKE_EBREAKDOWN at or
- * after a breakdown.  NULL outputs are skipped.  Synchronizes the
+ * the last slice of the most recent solve).  WAKE_ESTATE without a grid,
+ * for a slice at or after the next slice, or before the slice of the last
+ * wake_set_state (not marched from the current state); WAKE_EBREAKDOWN at
+ * or after a breakdown.  NULL outputs are skipped.  Synchronizes the
  * context's stream. */
 int wake_grid_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, double *ez,
                      double *bt, int32_t dst_is_device);
