@@ -113,6 +113,22 @@ int wake_add_beam(wake_ctx *ctx, const wake_source *src);
  * implicitly by the first wake_solve).  Synchronous. */
 int wake_prepare(wake_ctx *ctx);
 
+/* wake_prepare for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same beam table, built into `table`, device memory on the context's
+ * device owned by the caller (at least 4 (n_xi + 1) + 32 n_particles + 1024
+ * bytes, n_particles = every particle added with wake_add_beam; it must stay
+ * valid until wake_destroy, which does not free it), with the build staged
+ * in a device array the library holds on each GPU until the process ends
+ * (24 MiB; at most 131072 particles and 131072 slices).  The call allocates
+ * no device memory.  WAKE_EINVAL for a null table, a table too small or
+ * sizes beyond those limits; WAKE_OK with nothing done when the context is
+ * already prepared.  Every call on a GPU shares that GPU's staging array:
+ * calls that overlap on one GPU (several host threads) race.  Synchronous.
+ * A context prepared this way solves, batches and serves as after
+ * wake_prepare, with the same results. */
+int wake_prepare_noalloc(wake_ctx *ctx, void *table, int64_t table_bytes);
+
 /* March slices [first_slice, first_slice + n_slices) on the context's
  * stream (asynchronous): per slice the sort, sources, psi family, gamma,
  * d_zeta psi, the coefficients and two-point recursion of B_theta^(p) and

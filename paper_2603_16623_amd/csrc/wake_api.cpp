@@ -131,7 +131,7 @@ static void release(wake_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->arena.base) (void)hipFree(c->arena.base);
-  if (c->beam_mem) (void)hipFree(c->beam_mem);
+  if (c->beam_mem && !c->beam_external) (void)hipFree(c->beam_mem);
   if (c->grid_mem) (void)hipFree(c->grid_mem);
   if (c->d_inst) (void)hipFree(c->d_inst);
   if (c->d_counter) (void)hipFree(c->d_counter);
@@ -295,78 +295,150 @@ extern "C" int wake_add_beam(wake_ctx* c, const wake_source* s) {
   return WAKE_OK;
 }
 
-extern "C" int wake_prepare(wake_ctx* c) {
-  if (!c) return WAKE_EINVAL;
-  if (c->prepared) return WAKE_OK;
+// Carving of the persistent beam table (offsets per slice, then the radii
+// and cumulative charges of up to ne entries) and of the build's scratch
+// (particle copies, per-slice counts, padded entries).  With A.base null
+// only the sizes are computed.
+struct TableParts {
+  int32_t* off;
+  double *br, *bc;
+};
+static TableParts carve_table(Arena& A, int n_xi, int64_t ne) {
+  TableParts t;
+  t.off = A.take<int32_t>(n_xi + 1);
+  t.br = A.take<double>(std::max<int64_t>(ne, 1));
+  t.bc = A.take<double>(std::max<int64_t>(ne, 1));
+  return t;
+}
+struct BuildParts {
+  double *x, *y, *xi, *w, *q;
+  int32_t *cnt, *cnt2, *cursor, *poff;
+  double *er, *eq;
+  int64_t* ek;
+};
+static BuildParts carve_build(Arena& A, int n_xi, int64_t np) {
+  const int64_t npad = 4 * np + 4;      // power-of-two padded entries
+  BuildParts b;
+  b.x = A.take<double>(np);
+  b.y = A.take<double>(np);
+  b.xi = A.take<double>(np);
+  b.w = A.take<double>(np);
+  b.q = A.take<double>(np);
+  b.cnt = A.take<int32_t>(n_xi + 1);
+  b.cnt2 = A.take<int32_t>(n_xi + 1);
+  b.cursor = A.take<int32_t>(n_xi + 1);
+  b.poff = A.take<int32_t>(n_xi + 1);
+  b.er = A.take<double>(npad);
+  b.eq = A.take<double>(npad);
+  b.ek = A.take<int64_t>(npad);
+  return b;
+}
+
+// The beam table of a context (step a1) and the rest of wake_prepare.
+// table / scratch: device memory for the table and for the build, or null
+// to allocate them here (the table then belongs to the context, the
+// scratch to this call).
+static int prepare_impl(wake_ctx* c, char* table, size_t table_bytes, char* scratch,
+                        size_t scratch_bytes) {
   HIP_TRY(hipSetDevice(c->device));
   WakeInst& I = c->I;
   const int64_t np = (int64_t)c->px.size();
   const int n_xi = I.n_xi;
   const int64_t ne = 2 * np;            // at most two nodes per particle
-  const int64_t npad = 4 * np + 4;      // power-of-two padded entries
-  // persistent: offsets + (r, cumulative charge)
-  const size_t pbytes = 4 * (size_t)(n_xi + 1) + 256 + 16 * (size_t)ne + 512;
-  HIP_TRY(hipMalloc(&c->beam_mem, pbytes));
-  {
-    Arena P;
-    P.base = c->beam_mem;
-    P.size = pbytes;
-    I.boff = P.take<int32_t>(n_xi + 1);
-    double* br = P.take<double>(std::max<int64_t>(ne, 1));
-    double* bc = P.take<double>(std::max<int64_t>(ne, 1));
-    I.br = br;
-    I.bcum = bc;
-    I.nb = (int32_t)ne;
-    if (np > 0) {
-      const size_t tbytes = 40 * (size_t)np + 20 * (size_t)(n_xi + 1) + 24 * (size_t)npad + 4096;
-      char* tmp = nullptr;
-      HIP_TRY(hipMalloc(&tmp, tbytes));
-      Arena Tm;
-      Tm.base = tmp;
-      Tm.size = tbytes;
-      double* x = Tm.take<double>(np);
-      double* y = Tm.take<double>(np);
-      double* xi = Tm.take<double>(np);
-      double* w = Tm.take<double>(np);
-      double* q = Tm.take<double>(np);
-      int32_t* cnt = Tm.take<int32_t>(n_xi + 1);
-      int32_t* cnt2 = Tm.take<int32_t>(n_xi + 1);
-      int32_t* cursor = Tm.take<int32_t>(n_xi + 1);
-      int32_t* poff = Tm.take<int32_t>(n_xi + 1);
-      double* er = Tm.take<double>(npad);
-      double* eq = Tm.take<double>(npad);
-      int64_t* ek = Tm.take<int64_t>(npad);
-      hipError_t e = hipSuccess;
-      const size_t sz = sizeof(double) * np;
-      e = hipMemcpyAsync(x, c->px.data(), sz, hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(y, c->py.data(), sz, hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(xi, c->pxi.data(), sz, hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(w, c->pw.data(), sz, hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(q, c->pq.data(), sz, hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess)
-        e = launch_beam_table(x, y, xi, w, q, np, I.dxi, n_xi, cnt, cnt2, cursor,
-                              const_cast<int32_t*>(I.boff), poff, er, eq, ek, br, bc, c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      (void)hipFree(tmp);
-      if (e != hipSuccess) return dev_err(e);
-      // the table holds only entries that landed on a node
-      int32_t total = 0;
-      HIP_TRY(hipMemcpy(&total, I.boff + n_xi, sizeof(int32_t), hipMemcpyDeviceToHost));
-      I.nb = total;
-    } else {
-      HIP_TRY(hipMemsetAsync(const_cast<int32_t*>(I.boff), 0, 4 * (size_t)(n_xi + 1), c->stream));
-      I.nb = 0;
-    }
+  Arena P;
+  carve_table(P, n_xi, ne);
+  const size_t pbytes = P.used + 256;
+  Arena B;
+  if (np > 0) carve_build(B, n_xi, np);
+  const size_t tbytes = B.used + 256;
+  if (table && table_bytes < pbytes) return WAKE_EINVAL;
+  if (scratch && np > 0 && scratch_bytes < tbytes) return WAKE_EINVAL;
+  char* tmp = nullptr;
+  if (!table) {
+    HIP_TRY(hipMalloc(&c->beam_mem, pbytes));
+    c->beam_external = false;
+  } else {
+    c->beam_mem = table;
+    c->beam_external = true;
   }
-  std::vector<double>().swap(c->px);
-  std::vector<double>().swap(c->py);
-  std::vector<double>().swap(c->pxi);
-  std::vector<double>().swap(c->pw);
-  std::vector<double>().swap(c->pq);
+  P = Arena();
+  P.base = c->beam_mem;
+  P.size = pbytes;
+  const TableParts T = carve_table(P, n_xi, ne);
+  I.boff = T.off;
+  I.br = T.br;
+  I.bcum = T.bc;
+  I.nb = (int32_t)ne;
+  hipError_t e = hipSuccess;
+  if (np > 0) {
+    if (!scratch) {
+      e = hipMalloc(&tmp, tbytes);
+      if (e != hipSuccess) return dev_err(e);
+    }
+    B = Arena();
+    B.base = scratch ? scratch : tmp;
+    B.size = tbytes;
+    const BuildParts b = carve_build(B, n_xi, np);
+    const size_t sz = sizeof(double) * np;
+    e = hipMemcpyAsync(b.x, c->px.data(), sz, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.y, c->py.data(), sz, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.xi, c->pxi.data(), sz, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.w, c->pw.data(), sz, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.q, c->pq.data(), sz, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = launch_beam_table(b.x, b.y, b.xi, b.w, b.q, np, I.dxi, n_xi, b.cnt, b.cnt2, b.cursor, T.off,
+                            b.poff, b.er, b.eq, b.ek, T.br, T.bc, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return dev_err(e);
+    // the table holds only entries that landed on a node
+    int32_t total = 0;
+    HIP_TRY(hipMemcpy(&total, I.boff + n_xi, sizeof(int32_t), hipMemcpyDeviceToHost));
+    I.nb = total;
+  } else {
+    HIP_TRY(launch_zero(T.off, n_xi + 1, c->stream));
+    I.nb = 0;
+  }
+  if (!table) {               // the particles' host copies are no longer needed
+    std::vector<double>().swap(c->px);
+    std::vector<double>().swap(c->py);
+    std::vector<double>().swap(c->pxi);
+    std::vector<double>().swap(c->pw);
+    std::vector<double>().swap(c->pq);
+  }
   HIP_TRY(march_prepare(I.nt));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->prepared = true;
   return WAKE_OK;
+}
+
+extern "C" int wake_prepare(wake_ctx* c) {
+  if (!c) return WAKE_EINVAL;
+  if (c->prepared) return WAKE_OK;
+  const int r = prepare_impl(c, nullptr, 0, nullptr, 0);
+  if (r != WAKE_OK && c->beam_mem) {      // nothing of a failed attempt stays
+    (void)hipFree(c->beam_mem);
+    c->beam_mem = nullptr;
+  }
+  return r;
+}
+
+extern "C" int wake_prepare_noalloc(wake_ctx* c, void* table, int64_t table_bytes) {
+  if (!c || !table || table_bytes <= 0) return WAKE_EINVAL;
+  if (c->prepared) return WAKE_OK;
+  if ((int64_t)c->px.size() > WAKE_NOALLOC_PARTICLES || c->I.n_xi > WAKE_NOALLOC_SLICES)
+    return WAKE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  void* scr = nullptr;
+  size_t scr_bytes = 0;
+  HIP_TRY(beam_scratch(c->device, &scr, &scr_bytes));
+  const int r = prepare_impl(c, static_cast<char*>(table), (size_t)table_bytes, static_cast<char*>(scr),
+                             scr_bytes);
+  if (r != WAKE_OK) {                     // the table stays the caller's
+    c->beam_mem = nullptr;
+    c->beam_external = false;
+  }
+  return r;
 }
 
 int drain(wake_ctx* c) {

@@ -10,6 +10,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #define WAKE_SORT_CAP 2048   // beam entries per slice sorted in LDS
 
 // ---------------------------------------------------------------------------
@@ -183,4 +185,32 @@ hipError_t launch_beam_table(const double* x, const double* y, const double* xi,
 hipError_t launch_zero(int32_t* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(wake_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the beam-table build for callers that cannot allocate device
+// memory (wake_prepare_noalloc): every GPU holds its own copy of this array
+// until the process ends; calls on one GPU share it.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[WAKE_NOALLOC_SCRATCH];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[256];     // device address of `scratch`, per device
+}  // namespace
+
+hipError_t beam_scratch(int dev, void** p, size_t* bytes) {
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    // the array's name is a host-side stand-in: its device address on this
+    // device comes from the runtime, once
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = q;
+  }
+  *p = g_scratch_ptr[dev];
+  *bytes = WAKE_NOALLOC_SCRATCH;
+  return hipSuccess;
 }

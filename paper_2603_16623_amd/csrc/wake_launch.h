@@ -11,6 +11,13 @@ hipError_t launch_beam_table(const double* x, const double* y, const double* xi,
                              int32_t* cnt2, int32_t* cursor, int32_t* off, int32_t* poff, double* er,
                              double* eq, int64_t* ek, double* br, double* bcum, hipStream_t s);
 hipError_t launch_zero(int32_t* p, int n, hipStream_t s);
+// Device scratch of the beam-table build for callers that cannot allocate:
+// a file-scope device array of WAKE_NOALLOC_SCRATCH bytes, its address on
+// device `dev` (which must be current) looked up once per device.
+#define WAKE_NOALLOC_SCRATCH ((size_t)24 << 20)
+#define WAKE_NOALLOC_PARTICLES 131072
+#define WAKE_NOALLOC_SLICES 131072
+hipError_t beam_scratch(int dev, void** p, size_t* bytes);
 hipError_t launch_state_by_id(const WakeInst& I, double* rho, double* u, double* fr, double* fu,
                               hipStream_t s);
 hipError_t launch_state_set(const WakeInst& I, const double* rho, const double* u, const double* fr,

@@ -32,6 +32,7 @@ struct wake_ctx {
   double* staging = nullptr;   // 4N doubles
   // beam table (persistent part)
   char* beam_mem = nullptr;
+  bool beam_external = false;      // beam_mem belongs to the caller (wake_prepare_noalloc)
   // pending particle sources (host copies until the table is built)
   std::vector<double> px, py, pxi, pw, pq;
   double* grid_mem = nullptr;  // field grid: fields [n_xi][4][n_r], then the node table

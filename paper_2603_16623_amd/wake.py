@@ -56,6 +56,7 @@ _SIGS = {
     "wake_create": (_I, [C.POINTER(_P), C.POINTER(_Plasma), C.POINTER(_Domain), _P]),
     "wake_add_beam": (_I, [_P, C.POINTER(_Source)]),
     "wake_prepare": (_I, [_P]),
+    "wake_prepare_noalloc": (_I, [_P, _P, _I64]),
     "wake_solve": (_I, [_P, _I, _I]),
     "wake_fields": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _I]),
     "wake_lineout": (_I, [_P, _P, _P, _I]),
@@ -244,6 +245,11 @@ class WakeSolver:
 
     def wake_prepare(self):
         _check(self._lib.wake_prepare(self.h), "wake_prepare")
+
+    def wake_prepare_noalloc(self, table_ptr: int, table_bytes: int):
+        """Beam table built into caller-owned device memory, no allocation."""
+        _check(self._lib.wake_prepare_noalloc(self.h, table_ptr, int(table_bytes)),
+               "wake_prepare_noalloc")
 
     def wake_solve(self, first: int = 0, count: Optional[int] = None):
         if count is None:
