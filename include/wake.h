@@ -204,6 +204,16 @@ int wake_status(wake_ctx *ctx, int32_t *breakdown_slice, int32_t *next_slice);
 /* Wait for the context's stream. */
 int wake_sync(wake_ctx *ctx);
 
+/* Event counters of the context's marches, summed since creation (or the
+ * last reset), a trace of what the march did: [0] slices marched, [1] order
+ * fix-ups at slice heads (pushed radii out of order), [2] general fix-ups
+ * after the block rounds failed (one workgroup); cooperative instances: [3]
+ * member-local rounds (one per member that sorts), [4] rounds over all
+ * members, [5] sorts by segments, [6] bitonic fallbacks, [7] meetings of the
+ * members through device memory.  The first min(n, 8) go to out (more are
+ * zero); reset != 0 zeroes them.  Synchronizes. */
+int wake_counters(wake_ctx *ctx, int64_t *out, int32_t n, int32_t reset);
+
 /* Device bytes a context of this size holds (for admission control). */
 int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_t record_stride);
 
@@ -232,8 +242,9 @@ int wake_tiling_occupancy(int32_t threads, int32_t wgs_per_cu);
  * rings than one workgroup can keep ordered in LDS (more than 16 * threads
  * at 256 or 512 threads, 7 * 1024 at 1024) is marched by G workgroups
  * together, member g owning the sorted positions [g P, g P + P), P = C *
- * threads, with C = max(rings_per_thread, ceil(n_rings / (64 threads)))
- * and G = ceil(n_rings / P) <= 64.  Per slice the members exchange their
+ * threads, with C = max(rings_per_thread, ceil(n_rings / (M threads)))
+ * and G = ceil(n_rings / P) <= M, M = the smaller of 256 and the
+ * workgroups of that size the device holds at once.  Per slice the members exchange their
  * scan totals through device memory (three all-gathers) and fix the ring
  * order on keys in device memory; the order is the same and the fields
  * agree with a single workgroup's to rounding.  The members of one instance

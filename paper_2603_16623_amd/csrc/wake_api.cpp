@@ -23,15 +23,33 @@ int g_cl_min = 0;    // ring count from which instances are cooperative (0: beyo
 
 }  // namespace
 
+// Most members of one instance: the member scans' limit, and the
+// workgroups of nt threads the current device holds at once (members of an
+// instance must be resident together).
+static int members_max(int nt) {
+  static int cached[3] = {0, 0, 0};
+  const int k = nt == 256 ? 0 : nt == 512 ? 1 : 2;
+  if (cached[k] == 0) {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+      cu = 1;
+    const int occ = std::max(1, march_occupancy(nt));
+    cached[k] = std::max(1, std::min(WAKE_CL_MEMBERS, occ * cu));
+  }
+  return cached[k];
+}
+
 // Layout of an instance of N rings on nt-thread workgroups: one workgroup
 // with C = ceil(N / nt) rings per thread while the keys of every position
 // fit its LDS (and N is at most the cooperative threshold), else G members
-// of C rings per thread (G <= 64).
+// of C rings per thread (G at most members_max).
 void layout_of(int N, int nt, int* C, int* G) {
   const int kcap = march_cmax(nt) * nt;
   const int min_n = g_cl_min > 0 ? g_cl_min : kcap + 1;
   if (N >= min_n && N > nt) {
-    int c = std::max(g_cl_rings > 0 ? g_cl_rings : 8, (N + 64 * nt - 1) / (64 * nt));
+    const int gm = members_max(nt);
+    int c = std::max(g_cl_rings > 0 ? g_cl_rings : 8, (N + gm * nt - 1) / (gm * nt));
     const int g = (N + c * nt - 1) / (c * nt);
     if (g > 1) { *C = c; *G = g; return; }
   }
@@ -68,6 +86,7 @@ size_t arena_bytes(int N, int n_xi, int stride, int nt) {
   d += n_rec * OUT_N * (size_t)N;           // snapshots
   d += OUT_N * (size_t)N;                   // last
   i += CTL_NWORDS;                          // ctl
+  d += CNT_N;                               // event counters
   d += 4 * (size_t)N;                       // staging
   if (Gi > 1) {                             // cooperative: exchange, keys, fallback sort
     const size_t P2 = pow2_at_least((size_t)N);
@@ -215,6 +234,7 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   I.snap = n_rec ? A.take<double>(n_rec * OUT_N * N) : nullptr;
   I.last = A.take<double>((size_t)OUT_N * N);
   I.ctl = A.take<int32_t>(CTL_NWORDS);
+  I.cnt = A.take<unsigned long long>(CNT_N);
   c->staging = A.take<double>(4 * (size_t)N);
   if (I.G > 1) {
     const size_t P2 = pow2_at_least((size_t)N);
@@ -240,6 +260,7 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   if (e == hipSuccess && d_dn)
     e = hipMemcpyAsync(d_dn, plasma->dens, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(I.axis, 0, sizeof(double) * 2 * I.n_xi, c->stream);
+  if (e == hipSuccess) e = launch_zero(reinterpret_cast<int32_t*>(I.cnt), 2 * CNT_N, c->stream);
   if (e == hipSuccess) e = launch_init(I, d_r0, d_dr, d_dn, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) { release(c); return dev_err(e); }
@@ -480,6 +501,22 @@ extern "C" int wake_solve(wake_ctx* c, int32_t first, int32_t count) {
   r = launch_one(c, first, count);
   if (r != WAKE_OK) return r;
   c->next = first + count;
+  return WAKE_OK;
+}
+
+extern "C" int wake_counters(wake_ctx* c, int64_t* out, int32_t n, int32_t reset) {
+  if (!c || n < 0 || (n > 0 && !out)) return WAKE_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  unsigned long long h[CNT_N];
+  HIP_TRY(hipMemcpy(h, c->I.cnt, sizeof(h), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n && i < CNT_N; ++i) out[i] = (int64_t)h[i];
+  for (int i = CNT_N; i < n; ++i) out[i] = 0;
+  if (reset) {
+    HIP_TRY(launch_zero(reinterpret_cast<int32_t*>(c->I.cnt), 2 * CNT_N, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
   return WAKE_OK;
 }
 

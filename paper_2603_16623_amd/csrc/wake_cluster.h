@@ -29,14 +29,16 @@
 #include "wake_common.h"
 #include "wake_device.h"
 
+#define WAKE_CL_GMAX WAKE_CL_MEMBERS       // members per instance at most (four per lane of a wave)
+static_assert(WAKE_CL_GMAX <= 256, "member scans combine four members per lane");
 #define WAKE_CL_WAIT_TICKS 200000000ll     // 2 s of the 100 MHz clock
 #define WAKE_CL_START_TICKS 3000000000ll   // 30 s without a task taken
 
 struct Cluster {
   int g, G;      // this member, members
   int round;     // barriers passed in this launch
-  double* xd;    // [2][G][16]
-  int32_t* xc;   // [0] arrivals, [1] give-up, [2] members started
+  double* xd;    // [2][G][16]: packs, the stamp (round) in word 15
+  int32_t* xc;   // [1] give-up, [2] members started
   const int32_t* queue;   // task queue counter of the launch
 };
 
@@ -46,39 +48,50 @@ __device__ __forceinline__ void cl_start(Cluster& cl) {
   if (threadIdx.x == 0) atomicAdd(cl.xc + 2, 1);
 }
 
-// Thread 0 of a member: counts the member in and waits (bounded) until the
-// round's arrivals reach target.  1 when they did, 0 when a member gave up.
-__device__ __noinline__ int cl_wait(WAKE_GLOBAL int32_t* xc, const WAKE_GLOBAL int32_t* queue, int target, int G) {
-  __hip_atomic_fetch_add(xc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// One thread waits (bounded) until the stamp word of another member's pack
+// reads `want`.  1 when it did, 0 when a member gave up (or this wait gave
+// up and told the others).  The give-up word and the bounds are looked at
+// every sixteenth poll.
+__device__ __noinline__ int cl_await(const WAKE_GLOBAL double* sp, double want, WAKE_GLOBAL int32_t* xc,
+                                     const WAKE_GLOBAL int32_t* queue, int G) {
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   bool all_in = false;
   int q_last = -1;
-  for (;;) {
-    if (__hip_atomic_load(xc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
-    if (__hip_atomic_load(xc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return 1;
-    const uint64_t now = __builtin_amdgcn_s_memrealtime();
-    if (!all_in) {
-      all_in = __hip_atomic_load(xc + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G;
-      const int q = __hip_atomic_load(queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (all_in || q != q_last) { q_last = q; t0 = now; }
+  for (int it = 1;; ++it) {
+    if (__hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) return 1;
+    if ((it & 15) == 0) {
+      if (__hip_atomic_load(xc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
+      const uint64_t now = __builtin_amdgcn_s_memrealtime();
+      if (!all_in) {
+        all_in = __hip_atomic_load(xc + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G;
+        const int q = __hip_atomic_load(queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (all_in || q != q_last) { q_last = q; t0 = now; }
+      }
+      if ((int64_t)(now - t0) > (all_in ? WAKE_CL_WAIT_TICKS : WAKE_CL_START_TICKS)) {
+        __hip_atomic_store(xc + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+      }
     }
-    if ((int64_t)(now - t0) > (all_in ? WAKE_CL_WAIT_TICKS : WAKE_CL_START_TICKS)) {
-      __hip_atomic_store(xc + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return 0;
-    }
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(1);
   }
 }
 
 // All-gather of NF doubles per member; member m's pack lands at s_x[m * NF].
 // Every thread of every member calls it at the same point of the march.
-// FENCED also publishes the plain device-memory writes before it and makes
-// the others' visible after it.  Returns false when a member gave up.
+// Thread 0 writes the member's pack (write-through stores), waits for them
+// to complete and then writes the pack's stamp, the round number; thread m
+// waits for member m's stamp of this round and copies its pack.  There is
+// no shared counter: every member's arrival is its own word.  FENCED also
+// publishes the plain device-memory writes before it (release fence before
+// the stamp) and makes the others' visible after it (acquire fence).
+// Returns false when a member gave up.
 template <int NF, bool FENCED = true>
 __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, double* s_x, int* s_ok) {
-  static_assert(NF <= 16, "exchange packs hold 16 doubles");
+  static_assert(NF <= 15, "exchange packs hold 15 doubles and the stamp");
   const int buf = cl.round & 1;
+  const double stamp = (double)cl.round;
   WAKE_GLOBAL double* const xd = gptr(cl.xd);
+  if (threadIdx.x == 0) *s_ok = 1;
   __syncthreads();                                   // this member's writes of the round are issued
   if (threadIdx.x == 0) {
     WAKE_GLOBAL double* slot = xd + ((size_t)buf * cl.G + cl.g) * 16;
@@ -87,59 +100,97 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
     if (FENCED) {
       __threadfence();
     } else {
-      // the pack's write-through stores complete before the arrival
+      // the pack's write-through stores complete before its stamp
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       __builtin_amdgcn_s_waitcnt(0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    const int ok = cl_wait(gptr(cl.xc), gptr(cl.queue), cl.G * (cl.round + 1), cl.G);
-    if (FENCED) __threadfence();
-    *s_ok = ok;
+    __hip_atomic_store(slot + 15, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const int m = threadIdx.x;
+  if (m < cl.G) {
+    const WAKE_GLOBAL double* p = xd + ((size_t)buf * cl.G + m) * 16;
+    if (cl_await(p + 15, stamp, gptr(cl.xc), gptr(cl.queue), cl.G)) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        s_x[m * NF + f] = __hip_atomic_load(p + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      *s_ok = 0;
+    }
   }
   __syncthreads();
   const int ok = *s_ok;
-  if (ok)
-    for (int i = threadIdx.x; i < cl.G * NF; i += blockDim.x) {
-      const int m = i / NF, f = i - m * NF;
-      s_x[i] = __hip_atomic_load(xd + ((size_t)buf * cl.G + m) * 16 + f, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-    }
-  __syncthreads();
+  if (FENCED) {
+    if (threadIdx.x == 0) __threadfence();
+    __syncthreads();
+  }
   ++cl.round;
   return ok != 0;
 }
 
 // Exclusive prefix over members (op(earlier, later)) of the packs gathered at
 // s_x (field offset off, NFT doubles per member) for member g, and the total.
-// G <= 64: lane m of each wave holds member m's pack.
+// G <= WAKE_CL_GMAX: lane l of each wave combines members 4l .. 4l+3 in
+// order (ident beyond the last member, which op absorbs exactly), a wave scan
+// runs over the lanes, and member g's prefix is the lanes before its own
+// followed by the members of its lane below it.
 template <int NF, int NFT, class Op>
 __device__ __forceinline__ void cl_prefix(const double* s_x, int off, int g, int G, const Pack<NF>& ident,
                                           Op op, Pack<NF>& pre, Pack<NF>& tot) {
   const int lane = threadIdx.x & 63;
-  Pack<NF> a = ident;
-  if (lane < G) {
+  Pack<NF> blk = ident;
 #pragma unroll
-    for (int i = 0; i < NF; ++i) a.v[i] = s_x[lane * NFT + off + i];
+  for (int j = 0; j < 4; ++j) {
+    const int m = 4 * lane + j;
+    if (m < G) {
+      Pack<NF> x;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) x.v[i] = s_x[m * NFT + off + i];
+      blk = op(blk, x);
+    }
   }
-  const Pack<NF> inc = wave_prefix_incl(a, op);
-  const Pack<NF> pg = lane_pack(inc, g > 0 ? g - 1 : 0);
-  pre = g > 0 ? pg : ident;
-  tot = lane_pack(inc, G - 1);
+  const Pack<NF> inc = wave_prefix_incl(blk, op);
+  const int lg = g >> 2;
+  const Pack<NF> before = lane_pack(inc, lg > 0 ? lg - 1 : 0);
+  Pack<NF> p = lg > 0 ? before : ident;
+  for (int m = 4 * lg; m < g; ++m) {
+    Pack<NF> x;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) x.v[i] = s_x[m * NFT + off + i];
+    p = op(p, x);
+  }
+  pre = p;
+  tot = lane_pack(inc, 63);
 }
-// Exclusive suffix over members (op(lower, higher)) and the total.  Lanes
-// past the last member hold ident, which op absorbs exactly.
+// Exclusive suffix over members (op(lower, higher)) and the total, with the
+// same grouping of four members per lane.
 template <int NF, int NFT, class Op>
 __device__ __forceinline__ void cl_suffix(const double* s_x, int off, int g, int G, const Pack<NF>& ident,
                                           Op op, Pack<NF>& suf, Pack<NF>& tot) {
   const int lane = threadIdx.x & 63;
-  Pack<NF> a = ident;
-  if (lane < G) {
+  Pack<NF> blk = ident;
 #pragma unroll
-    for (int i = 0; i < NF; ++i) a.v[i] = s_x[lane * NFT + off + i];
+  for (int j = 3; j >= 0; --j) {
+    const int m = 4 * lane + j;
+    if (m < G) {
+      Pack<NF> x;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) x.v[i] = s_x[m * NFT + off + i];
+      blk = op(x, blk);
+    }
   }
-  const Pack<NF> inc = wave_suffix_incl(a, op);
-  const Pack<NF> sg = lane_pack(inc, g < G - 1 ? g + 1 : 0);
-  suf = g < G - 1 ? sg : ident;
+  const Pack<NF> inc = wave_suffix_incl(blk, op);
+  const int lg = g >> 2;
+  const Pack<NF> after = lane_pack(inc, lg < 63 ? lg + 1 : 63);
+  Pack<NF> p = lg < 63 ? after : ident;
+  const int top = min(4 * lg + 3, G - 1);
+  for (int m = top; m > g; --m) {
+    Pack<NF> x;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) x.v[i] = s_x[m * NFT + off + i];
+    p = op(x, p);
+  }
+  suf = p;
   tot = lane_pack(inc, 0);
 }
 

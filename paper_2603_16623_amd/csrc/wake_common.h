@@ -8,10 +8,18 @@
 #define WAKE_SORTCAP 1024     // rings of long disordered runs sorted in LDS in one piece
 #define WAKE_SEGMAX 64        // disordered runs up to this length are ranked in place
 #define WAKE_ION_REC 8        // doubles per ion interval record
+#define WAKE_CL_MEMBERS 256   // workgroups of one cooperative instance at most
 #define WAKE_GRID_TAB 6       // doubles per field-grid node record
 
 // Control words of one instance (device memory, int32).
 enum { CTL_CUR = 0, CTL_BREAK = 1, CTL_NEXT = 2, CTL_FAULT = 3, CTL_NWORDS = 4 };
+// Event counters of one instance (device memory, 64-bit), summed over its
+// marches: slices marched, order fix-ups at slice heads, general fix-ups
+// after the block rounds (one workgroup), and for cooperative instances the
+// member-local rounds (per member that sorts), rounds over all members,
+// sorts by segments, bitonic fallbacks and meetings.
+enum { CNT_SLICES = 0, CNT_FIXUPS, CNT_GENERAL, CNT_CL_LOCAL, CNT_CL_ROUNDS, CNT_CL_SEGMENTS,
+       CNT_CL_BITONIC, CNT_CL_MEETINGS, CNT_N };
 
 // Ion interval record j (j = 0..N), nodes 0 = axis, j = r0[j-1], N+1 = R_p:
 // [node_j, node_{j+1}), psi-psi(0) at node j (dd), its step to node j+1,
@@ -107,6 +115,7 @@ struct WakeInst {
   double *snap;               // [n_rec][6][N] by ring id
   double *last;               // [6][N] by ring id: last marched slice
   int32_t *ctl;               // [CTL_NWORDS]
+  unsigned long long *cnt;    // [CNT_N]
   // radial field grid (none while grid_n is 0): nodes r_g = (g + 1/2)
   // grid_dr, g < grid_n; fields of every slice [n_xi][4][grid_n] (psi,
   // E_r - B_theta, E_z, B_theta); per node [grid_n][WAKE_GRID_TAB]: ln r_g,

@@ -1221,6 +1221,8 @@ struct MarchLds {
 static_assert(MarchLds<256>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<512>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<1024>::bytes() <= 160 * 1024, "LDS layout too large");
+// a cooperative member gathers the packs of every member into its key area
+static_assert(MarchLds<256>::key_bytes() >= WAKE_CL_GMAX * 16 * sizeof(double), "pack area");
 // field-grid variant: the LDS left beside the layout holds the node records
 // of grids up to grid_lds_nodes nodes (else they are read from device memory)
 template <int NT>
@@ -1458,9 +1460,9 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   const int xo = (int)MarchLds<NT>::head_bytes();
   const int oko = (int)(reinterpret_cast<unsigned char*>(s_ok) - smem);
   // cooperative member-local fix-up rounds in LDS: the key area after the
-  // gathered packs (64 members x 16 doubles)
-  const int lo = xo + 64 * 16 * (int)sizeof(double);
-  const int lo_cap = (int)MarchLds<NT>::key_bytes() - 64 * 16 * (int)sizeof(double);
+  // gathered packs (WAKE_CL_GMAX members x 16 doubles)
+  const int lo = xo + WAKE_CL_GMAX * 16 * (int)sizeof(double);
+  const int lo_cap = (int)MarchLds<NT>::key_bytes() - WAKE_CL_GMAX * 16 * (int)sizeof(double);
 
   if (__builtin_amdgcn_readfirstlane(I.ctl[CTL_BREAK]) >= 0) return;
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
@@ -1469,8 +1471,9 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   double rho_mprev = -1.0;   // field grid, cooperative: radius at the previous member's last position
   double rho_mlast = -1.0;   // field grid, cooperative: radius at this member's last position
   __syncthreads();
-  // a ring at slot s came from another thread's chunk (or member)
-#define WAKE_FOREIGN(s) ((unsigned)((int)(s) - goff) >= (unsigned)P || (((int)(s) - goff) & (NT - 1)) != tid)
+  // the ring at this thread's k-th position (slot s of the current buffer)
+  // is not the one the push wrote there: the chunk's order changed
+#define WAKE_MOVED(s, k) ((int)(s) != goff + (k) * NT + tid)
   // injected states may be unsorted
   bool ident = true;
   bool moved = false;       // a chunk holds rings of another chunk after the fix-up
@@ -1495,7 +1498,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     }
     cl.round = r >> 1;
     ident = false;
-    for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(gperm[goff + k * NT + tid]);
+    for (int k = 0; k < cnt; ++k) moved |= WAKE_MOVED(gperm[goff + k * NT + tid], k);
   } else if (lds_keys) {
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
@@ -1507,11 +1510,11 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     __syncthreads();
     fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
     ident = false;
-    for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(s_perm[k * NT + tid]);
+    for (int k = 0; k < cnt; ++k) moved |= WAKE_MOVED(s_perm[k * NT + tid], k);
   } else {
     fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
     ident = false;
-    for (int k = 0; k < cnt; ++k) moved |= WAKE_FOREIGN(gperm[k * NT + tid]);
+    for (int k = 0; k < cnt; ++k) moved |= WAKE_MOVED(gperm[k * NT + tid], k);
   }
   const dd tot0 = {uni(I.tot0[0]), uni(I.tot0[1])};
   const double dxi = I.dxi;
@@ -1542,8 +1545,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   // The per-thread sums of (w, w ln rho), ln rho as the state carries it.
   // The sums in the order the march itself would have left them in (so that
   // a solve split over several launches is bitwise the one-launch solve):
-  // chunks that took rings of another chunk in the fix-up sum forward, the
-  // others backward as the push does.
+  // chunks whose order the fix-up changed sum forward, the others backward
+  // as the push does.
   dd sw = {0.0, 0.0}, swl = {0.0, 0.0};
   if (moved) {
     chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, s_ki, sw, swl);
@@ -1623,6 +1626,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (t6.v[5] != 0.0) {     // pushed radii out of order: new order, then redo the prefix
       bool restage = true;    // the general fix-ups use the beam-table area of LDS
       double still = 0.0;      // cooperative: this member still out of order after the round
+      if (tid == 0 && member == 0) atomicAdd(I.cnt + CNT_FIXUPS, 1ull);
       if (CL) {
         // disorder inside members only: up to two member-local block rounds
         // (members in order skip them); across member boundaries, or left
@@ -1635,10 +1639,15 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
             dis = 0.0;
             continue;
           }
+          if (tid == 0) atomicAdd(I.cnt + CNT_CL_LOCAL, 1ull);
           still = (16 * P <= lo_cap ? cl_fix_local_lds<NT>(as_global(I), member, ident, lo)
                                     : cl_fix_local<NT>(as_global(I), member, ident)) ? 1.0 : 0.0;
         } else {
           int r = -1;
+          if (tid == 0 && member == 0)
+            atomicAdd(I.cnt + (cl_rounds < 2 ? CNT_CL_ROUNDS
+                               : cl_rounds == 2 && C <= 16 && 16 * P <= lo_cap ? CNT_CL_SEGMENTS
+                                                                                : CNT_CL_BITONIC), 1ull);
           if (cl_rounds < 2) {
             r = cl_fix_round<NT>(as_global(I), cl, xo, oko, ident, 16 * P <= lo_cap ? lo : -1);
             if (r >= 0) {
@@ -1660,16 +1669,20 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         ++fix_rounds;
       } else if (lds_keys) {
         restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm);
-        if (restage) fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
+        if (restage) {
+          if (tid == 0) atomicAdd(I.cnt + CNT_GENERAL, 1ull);
+          fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
+        }
       } else {
+        if (tid == 0) atomicAdd(I.cnt + CNT_GENERAL, 1ull);
         fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
       }
       ident = false;
-      // chunks that took a ring from another chunk sum again
+      // chunks whose order changed sum again
       bool changed = false;
       for (int k = 0; k < cnt; ++k)
-        changed |= WAKE_FOREIGN(lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[goff + k * NT + tid]);
-      // (a chunk back to its own rings after a later round takes the push's sums again)
+        changed |= WAKE_MOVED(lds_keys ? (int32_t)s_perm[k * NT + tid] : gperm[goff + k * NT + tid], k);
+      // (a chunk back to its push order after a later round takes the push's sums again)
       if (changed) {
         chunk_sums<NT>(I, cur, cnt, goff, ps, ident, lds_keys, s_perm, s_ki, sw, swl);
       } else {
@@ -2134,10 +2147,15 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     }
     ++n;
   }
-  if (tid == 0 && member == 0) { I.ctl[CTL_CUR] = cur; I.ctl[CTL_NEXT] = end; }
+  if (tid == 0 && member == 0) {
+    I.ctl[CTL_CUR] = cur;
+    I.ctl[CTL_NEXT] = end;
+    atomicAdd(I.cnt + CNT_SLICES, (unsigned long long)(end - I.first));
+    if (CL) atomicAdd(I.cnt + CNT_CL_MEETINGS, (unsigned long long)cl.round);
+  }
 #undef WAKE_SLOT
 #undef WAKE_ID
-#undef WAKE_FOREIGN
+#undef WAKE_MOVED
 }
 
 // the cooperative march as a function of its own (its registers stay out of
@@ -2182,9 +2200,14 @@ __global__ void counter_zero_kernel(int32_t* p) {
 }
 
 // barrier words of the cooperative instances of a launch start at zero
+// and their packs carry no stamp of this launch's rounds
 __global__ void cluster_reset_kernel(const WakeInst* __restrict__ insts, int n_insts) {
-  for (int i = threadIdx.x; i < n_insts; i += blockDim.x)
-    if (insts[i].G > 1) { insts[i].xc[0] = 0; insts[i].xc[1] = 0; insts[i].xc[2] = 0; }
+  for (int i = threadIdx.x; i < n_insts; i += blockDim.x) {
+    const int G = insts[i].G;
+    if (G <= 1) continue;
+    insts[i].xc[0] = 0; insts[i].xc[1] = 0; insts[i].xc[2] = 0;
+    for (int k = 0; k < 2 * G; ++k) insts[i].xd[(size_t)k * 16 + 15] = -1.0;
+  }
 }
 
 // ---------------------------------------------------------------------------

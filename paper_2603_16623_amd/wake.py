@@ -67,6 +67,7 @@ _SIGS = {
     "wake_reset": (_I, [_P]),
     "wake_status": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
     "wake_sync": (_I, [_P]),
+    "wake_counters": (_I, [_P, C.POINTER(_I64), _I, _I]),
     "wake_footprint": (_I64, [_I, _I, _I64, _I]),
     "wake_destroy": (None, [_P]),
     "wake_strerror": (C.c_char_p, [_I]),
@@ -245,6 +246,15 @@ class WakeSolver:
 
     def wake_prepare(self):
         _check(self._lib.wake_prepare(self.h), "wake_prepare")
+
+    COUNTERS = ("slices", "fixups", "general_fixups", "member_local_rounds", "all_member_rounds",
+                "segment_sorts", "bitonic_fallbacks", "meetings")
+
+    def wake_counters(self, reset: bool = False) -> dict:
+        """Event counters of this context's marches (see wake.h)."""
+        out = (_I64 * 8)()
+        _check(self._lib.wake_counters(self.h, out, 8, int(reset)), "wake_counters")
+        return dict(zip(self.COUNTERS, (int(x) for x in out)))
 
     def wake_prepare_noalloc(self, table_ptr: int, table_bytes: int):
         """Beam table built into caller-owned device memory, no allocation."""

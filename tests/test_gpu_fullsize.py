@@ -122,13 +122,13 @@ def _bench_layout(inst, nt=512):
     cooperative layout."""
     from bench import LARGE_CLUSTER
     rpt, _ = LARGE_CLUSTER
-    c = max(rpt or 8, -(-inst.n_rings // (64 * nt)))
+    c = max(rpt or 8, -(-inst.n_rings // (256 * nt)))
     return -(-inst.n_rings // (c * nt)), c
 
 
 def test_large_solves_at_the_benchmark_layout(wk):
     """The 20000-ring and 200000-ring solves in exactly the layout the
-    benchmark times (512-thread members, two rings per thread where 64
+    benchmark times (512-thread members, two rings per thread where 256
     members allow it): per-slice parity with a field grid."""
     from bench import LARGE_CLUSTER
     wk.wake_set_cluster(*LARGE_CLUSTER)
