@@ -260,6 +260,52 @@ int wake_set_cluster(int32_t rings_per_thread, int32_t min_rings);
 int wake_get_layout(wake_ctx *ctx, int32_t *workgroups, int32_t *rings_per_thread);
 
 /* ---------------------------------------------------------------------
+ * Autotuner of the layout per ring-count bucket (the batched form's
+ * "rings per workgroup and LDS tiling").  Bucket b holds ring counts in
+ * [lo[b], lo[b+1]) (the last has no upper end); a context created while a
+ * tuning is installed takes its bucket's workgroup threads (256, 512 or
+ * 1024: the LDS tiling of the marcher) and rings per thread of cooperative
+ * members (0: one workgroup per context, never cooperative; else
+ * cooperative from the moment it gives two or more members).  Tiling and
+ * cluster settings apply to contexts only while no tuning is installed; the
+ * served form keeps its own threads.  Any choice gives the same results to
+ * rounding; the same choice gives bitwise the same results.
+ * --------------------------------------------------------------------- */
+#define WAKE_TUNE_BUCKETS 8
+typedef struct {
+  int32_t n_buckets;
+  int32_t lo[WAKE_TUNE_BUCKETS];               /* lo[0] = 0, increasing */
+  int32_t threads[WAKE_TUNE_BUCKETS];
+  int32_t rings_per_thread[WAKE_TUNE_BUCKETS];
+  double rate[WAKE_TUNE_BUCKETS];              /* measured ring-slice updates/s of the choice
+                                                  (0: bucket not measured, default layout) */
+} wake_tuning;
+
+/* Measure and install a tuning.  The n instances (plasma, domain, sources as
+ * for wake_create / wake_add_beam; sources[i] points at n_sources[i]
+ * sources; host arrays) are grouped into the buckets lo = 0, 2048, 4096,
+ * 8192, 16384, 32768, 65536, 131072 rings; for every bucket with instances,
+ * each candidate layout (one workgroup of 256, 512 or 1024 threads where
+ * the keys of every position fit its LDS; cooperative members of 512
+ * threads with 1, 2, 4 or 8 rings per thread where the ring counts exceed
+ * 2048) marches all of the bucket's instances together through their first
+ * min(slices, n_xi) slices in one persistent launch, twice, and the larger
+ * ring-slice rate wins (the earlier candidate on a tie, so the choice
+ * follows from the measurements).  Buckets without instances take 512
+ * threads, one workgroup below 8192 rings, else eight rings per member
+ * thread.  *out receives the installed tuning.  Synchronous; allocates and
+ * frees contexts of its own on hip_stream (NULL: a stream of its own). */
+int wake_autotune(const wake_plasma *plasmas, const wake_domain *domains,
+                  const wake_source *const *sources, const int32_t *n_sources, int32_t n,
+                  int32_t slices, void *hip_stream, wake_tuning *out);
+/* Install a tuning (t = NULL removes it).  WAKE_EINVAL for a malformed one. */
+int wake_set_tuning(const wake_tuning *t);
+/* The installed tuning; WAKE_ESTATE when none is. */
+int wake_get_tuning(wake_tuning *t);
+/* Workgroup threads of a context's layout. */
+int wake_get_threads(wake_ctx *ctx, int32_t *threads);
+
+/* ---------------------------------------------------------------------
  * Batched form: many independent contexts (same device) marched by one
  * persistent launch; workgroups take instances longest-first from a device
  * counter.  Per-instance results equal those of solving alone with the same

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwake.so")
 SOURCES = [os.path.join(CSRC, "wake_march.hip"), os.path.join(CSRC, "wake_beam.hip"),
-           os.path.join(CSRC, "wake_api.cpp"), os.path.join(CSRC, "wake_serve.cpp")]
+           os.path.join(CSRC, "wake_api.cpp"), os.path.join(CSRC, "wake_serve.cpp"),
+           os.path.join(CSRC, "wake_tune.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

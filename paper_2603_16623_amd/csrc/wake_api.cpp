@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -19,6 +20,8 @@ int g_nt = 512;      // workgroup threads of new contexts (slot layout)
 int g_wpc = 0;       // workgroups per compute unit of persistent launches (0: occupancy)
 int g_cl_rings = 0;  // rings per thread of cooperative instances (0: 8)
 int g_cl_min = 0;    // ring count from which instances are cooperative (0: beyond one workgroup's LDS keys)
+bool g_tuned = false;   // a tuning table is installed
+wake_tuning g_tuning;   // per ring-count bucket: threads, cooperative rings per thread
 
 
 }  // namespace
@@ -26,6 +29,47 @@ int g_cl_min = 0;    // ring count from which instances are cooperative (0: beyo
 // Most members of one instance: the member scans' limit, and the
 // workgroups of nt threads the current device holds at once (members of an
 // instance must be resident together).
+// The installed tuning's layout for N rings (false when none is installed).
+static bool tuned_layout(int N, Layout* L) {
+  if (!g_tuned) return false;
+  int b = 0;
+  while (b + 1 < g_tuning.n_buckets && N >= g_tuning.lo[b + 1]) ++b;
+  L->nt = g_tuning.threads[b];
+  L->rpt = g_tuning.rings_per_thread[b];
+  L->min_n = L->rpt > 0 ? 1 : INT32_MAX;
+  return true;
+}
+
+extern "C" int wake_set_tuning(const wake_tuning* t) {
+  if (!t) {
+    g_tuned = false;
+    return WAKE_OK;
+  }
+  if (t->n_buckets < 1 || t->n_buckets > WAKE_TUNE_BUCKETS || t->lo[0] != 0) return WAKE_EINVAL;
+  for (int b = 0; b < t->n_buckets; ++b) {
+    if (b > 0 && !(t->lo[b] > t->lo[b - 1])) return WAKE_EINVAL;
+    if (!march_threads_ok(t->threads[b]) || t->rings_per_thread[b] < 0 || t->rings_per_thread[b] > 4096)
+      return WAKE_EINVAL;
+  }
+  for (int b = 0; b < t->n_buckets; ++b) HIP_TRY(march_prepare(t->threads[b]));
+  g_tuning = *t;
+  g_tuned = true;
+  return WAKE_OK;
+}
+
+extern "C" int wake_get_tuning(wake_tuning* t) {
+  if (!t) return WAKE_EINVAL;
+  if (!g_tuned) return WAKE_ESTATE;
+  *t = g_tuning;
+  return WAKE_OK;
+}
+
+extern "C" int wake_get_threads(wake_ctx* c, int32_t* threads) {
+  if (!c || !threads) return WAKE_EINVAL;
+  *threads = c->I.nt;
+  return WAKE_OK;
+}
+
 static int members_max(int nt) {
   static int cached[3] = {0, 0, 0};
   const int k = nt == 256 ? 0 : nt == 512 ? 1 : 2;
@@ -40,16 +84,25 @@ static int members_max(int nt) {
   return cached[k];
 }
 
-// Layout of an instance of N rings on nt-thread workgroups: one workgroup
-// with C = ceil(N / nt) rings per thread while the keys of every position
-// fit its LDS (and N is at most the cooperative threshold), else G members
-// of C rings per thread (G at most members_max).
-void layout_of(int N, int nt, int* C, int* G) {
+Layout layout_default(int nt) { return Layout{nt, g_cl_rings, g_cl_min}; }
+
+Layout layout_for(int N) {
+  Layout L;
+  if (tuned_layout(N, &L)) return L;
+  return layout_default(g_nt);
+}
+
+// Layout of an instance of N rings: one workgroup with C = ceil(N / nt)
+// rings per thread while the keys of every position fit its LDS (and N is
+// below the cooperative threshold), else G members of C rings per thread
+// (G at most members_max).
+void layout_of(int N, const Layout& L, int* C, int* G) {
+  const int nt = L.nt;
   const int kcap = march_cmax(nt) * nt;
-  const int min_n = g_cl_min > 0 ? g_cl_min : kcap + 1;
+  const int min_n = L.min_n > 0 ? L.min_n : kcap + 1;
   if (N >= min_n && N > nt) {
     const int gm = members_max(nt);
-    int c = std::max(g_cl_rings > 0 ? g_cl_rings : 8, (N + gm * nt - 1) / (gm * nt));
+    int c = std::max(L.rpt > 0 ? L.rpt : 8, (N + gm * nt - 1) / (gm * nt));
     const int g = (N + c * nt - 1) / (c * nt);
     if (g > 1) { *C = c; *G = g; return; }
   }
@@ -67,10 +120,10 @@ static size_t pow2_at_least(size_t n) {
 
 // Bytes of the per-context arena (mirrors the carving in wake_create).
 // S = slots of the per-ring arrays (G * C * nt >= N).
-size_t arena_bytes(int N, int n_xi, int stride, int nt) {
+size_t arena_bytes(int N, int n_xi, int stride, const Layout& L) {
   int Ci = 0, Gi = 1;
-  layout_of(N, nt, &Ci, &Gi);
-  const size_t S = (size_t)Gi * Ci * nt;
+  layout_of(N, L, &Ci, &Gi);
+  const size_t S = (size_t)Gi * Ci * L.nt;
   const size_t n_rec = stride > 0 ? (size_t)(n_xi + stride - 1) / stride : 0;
   size_t d = 0, i = 0;
   d += 2 * RC_CHUNKS * S;                   // constants by home slot
@@ -129,9 +182,9 @@ extern "C" const char* wake_strerror(int code) {
 }
 
 int64_t ctx_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_t record_stride,
-                      int nt) {
+                      const Layout& L) {
   if (n_rings <= 0 || n_xi <= 0 || n_particles < 0 || record_stride < 0) return -1;
-  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, nt);
+  int64_t b = (int64_t)arena_bytes(n_rings, n_xi, record_stride, L);
   // persistent beam table: offsets + (r, cumulative charge) per entry
   b += 4 * (int64_t)(n_xi + 1) + 16 * 2 * n_particles + 1024;
   // transient build buffers (particles, counts, padded entries)
@@ -142,7 +195,8 @@ int64_t ctx_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_
 
 extern "C" int64_t wake_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles,
                                   int32_t record_stride) {
-  return ctx_footprint(n_rings, n_xi, n_particles, record_stride, g_nt);
+  if (n_rings <= 0) return -1;
+  return ctx_footprint(n_rings, n_xi, n_particles, record_stride, layout_for(n_rings));
 }
 
 static void release(wake_ctx* c) {
@@ -163,7 +217,8 @@ extern "C" void wake_destroy(wake_ctx* ctx) { release(ctx); }
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
-               int nt) {
+               const Layout& L) {
+  const int nt = L.nt;
   if (!out) return WAKE_EINVAL;
   if (!march_threads_ok(nt)) return WAKE_EINVAL;
   *out = nullptr;
@@ -204,9 +259,9 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   I.Rp = plasma->r0[N - 1] + plasma->dr[N - 1] / 2.0;
   I.inv2pidxi = 1.0 / (2.0 * M_PI * I.dxi);
   I.nt = nt;
-  layout_of(N, nt, &I.C, &I.G);
+  layout_of(N, L, &I.C, &I.G);
   const size_t S = (size_t)I.G * I.C * I.nt;
-  const size_t bytes = arena_bytes(N, I.n_xi, I.stride, I.nt);
+  const size_t bytes = arena_bytes(N, I.n_xi, I.stride, L);
   hipError_t e = hipMalloc(&c->arena.base, bytes);
   if (e != hipSuccess) { c->arena.base = nullptr; release(c); return dev_err(e); }
   c->arena.size = bytes;
@@ -270,7 +325,8 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
 
 extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom,
                            void* hip_stream) {
-  return ctx_create(out, plasma, dom, hip_stream, g_nt);
+  if (!plasma || plasma->n_rings <= 0) return out ? (*out = nullptr, WAKE_EINVAL) : WAKE_EINVAL;
+  return ctx_create(out, plasma, dom, hip_stream, layout_for(plasma->n_rings));
 }
 
 extern "C" int wake_add_beam(wake_ctx* c, const wake_source* s) {

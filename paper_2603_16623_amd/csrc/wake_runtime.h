@@ -56,8 +56,19 @@ int dev_err(hipError_t e);
 int drain(wake_ctx* c);
 // persistent grid for nt-thread workgroups over n instances
 int march_grid(int nt, int n_insts, int dev);
-// layout of an instance (rings per thread C, workgroups G) on nt threads
-void layout_of(int N, int nt, int* C, int* G);
+// How a context is laid out: workgroup threads, rings per thread of
+// cooperative members (0: 8) and the ring count from which contexts are
+// cooperative (0: beyond one workgroup's LDS keys; INT32_MAX: never).
+struct Layout {
+  int nt, rpt, min_n;
+};
+// the layout of wake_set_tiling / wake_set_cluster for nt-thread workgroups
+Layout layout_default(int nt);
+// the layout a new context of N rings takes (the installed tuning, else the
+// tiling and cluster settings)
+Layout layout_for(int N);
+// layout of an instance (rings per thread C, workgroups G)
+void layout_of(int N, const Layout& L, int* C, int* G);
 // first task of each descriptor (members of a cooperative instance are G
 // consecutive tasks); returns the number of tasks
 int assign_tasks(std::vector<WakeInst>& v);
@@ -67,6 +78,6 @@ hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts,
                         int dev, int grid_override, hipStream_t s);
 // context creation / footprint with an explicit workgroup size
 int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
-               int nt);
+               const Layout& L);
 int64_t ctx_footprint(int32_t n_rings, int32_t n_xi, int64_t n_particles, int32_t record_stride,
-                      int nt);
+                      const Layout& L);

@@ -140,7 +140,8 @@ extern "C" int wake_server_submit(wake_server* s, const wake_plasma* plasma, con
   } catch (...) {
     return WAKE_ENOMEM;
   }
-  q.footprint = ctx_footprint(N, dom->n_xi, q.n_particles, dom->record_stride, s->cfg.threads);
+  q.footprint = ctx_footprint(N, dom->n_xi, q.n_particles, dom->record_stride,
+                              layout_default(s->cfg.threads));
   if (q.footprint < 0) return WAKE_EINVAL;
   q.ticket = s->next_ticket++;
   *ticket = q.ticket;
@@ -156,7 +157,7 @@ static int admit(wake_server* s, Request& q, wake_ctx** out) {
   pl.dr = q.dr.data();
   pl.dens = q.dens.empty() ? nullptr : q.dens.data();
   wake_ctx* c = nullptr;
-  int r = ctx_create(&c, &pl, &q.dom, s->stream, s->cfg.threads);
+  int r = ctx_create(&c, &pl, &q.dom, s->stream, layout_default(s->cfg.threads));
   if (r != WAKE_OK) return r;
   size_t pd = 0;
   for (wake_source w : q.src) {
@@ -214,7 +215,7 @@ extern "C" int wake_server_step(wake_server* s, int32_t* n_active, int32_t* n_qu
     if (s->cfg.max_active > 0 && (int)s->active.size() >= s->cfg.max_active) break;
     Request& q = s->queue.front();
     int qc = 0, qg = 1;
-    layout_of((int)q.r0.size(), s->cfg.threads, &qc, &qg);
+    layout_of((int)q.r0.size(), layout_default(s->cfg.threads), &qc, &qg);
     if (used + qg > slots && !s->active.empty()) break;
     const bool fits = s->in_use + q.footprint <= s->cfg.device_bytes;
     if (!fits && !s->active.empty()) break;

@@ -45,6 +45,15 @@ class _Source(C.Structure):
                 ("xi_l", C.c_double)]
 
 
+TUNE_BUCKETS = 8
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("n_buckets", C.c_int32), ("lo", C.c_int32 * TUNE_BUCKETS),
+                ("threads", C.c_int32 * TUNE_BUCKETS),
+                ("rings_per_thread", C.c_int32 * TUNE_BUCKETS), ("rate", C.c_double * TUNE_BUCKETS)]
+
+
 class _ServerConfig(C.Structure):
     _fields_ = [("threads", C.c_int32), ("slices_per_step", C.c_int32), ("max_active", C.c_int32),
                 ("device_bytes", C.c_int64), ("ring_slices_per_step", C.c_int64),
@@ -67,6 +76,11 @@ _SIGS = {
     "wake_reset": (_I, [_P]),
     "wake_status": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
     "wake_sync": (_I, [_P]),
+    "wake_autotune": (_I, [C.POINTER(_Plasma), C.POINTER(_Domain), C.POINTER(C.POINTER(_Source)),
+                           C.POINTER(_I), _I, _I, _P, C.POINTER(_Tuning)]),
+    "wake_set_tuning": (_I, [C.POINTER(_Tuning)]),
+    "wake_get_tuning": (_I, [C.POINTER(_Tuning)]),
+    "wake_get_threads": (_I, [_P, C.POINTER(_I)]),
     "wake_counters": (_I, [_P, C.POINTER(_I64), _I, _I]),
     "wake_footprint": (_I64, [_I, _I, _I64, _I]),
     "wake_destroy": (None, [_P]),
@@ -165,6 +179,67 @@ def wake_footprint(n_rings: int, n_xi: int, n_particles: int, record_stride: int
     return int(load().wake_footprint(n_rings, n_xi, n_particles, record_stride))
 
 
+def _tuning_dict(t) -> dict:
+    n = t.n_buckets
+    return dict(lo=list(t.lo[:n]), threads=list(t.threads[:n]),
+                rings_per_thread=list(t.rings_per_thread[:n]), rate=list(t.rate[:n]))
+
+
+def wake_autotune(insts, slices: int, stream=None) -> dict:
+    """Measure and install the layout per ring-count bucket on these
+    instances (see wake.h); returns the tuning as a dict."""
+    n = len(insts)
+    pls = (_Plasma * n)()
+    dms = (_Domain * n)()
+    srcp = (C.POINTER(_Source) * n)()
+    nsrc = (_I * n)()
+    keep = []
+    for i, inst in enumerate(insts):
+        r0, dr = _host(inst.r0), _host(inst.dr)
+        dens = None if inst.dens is None else _host(inst.dens)
+        keep += [r0, dr, dens]
+        pls[i] = _Plasma(len(r0), r0.ctypes.data, dr.ctypes.data, None if dens is None else dens.ctypes.data)
+        dms[i] = _Domain(float(inst.dxi), int(inst.n_xi), 0)
+        arr = (_Source * max(1, len(inst.sources)))()
+        for k, src in enumerate(inst.sources):
+            st, kp = _source_struct(src)
+            arr[k] = st
+            keep.append(kp)
+        keep.append(arr)
+        srcp[i] = C.cast(arr, C.POINTER(_Source))
+        nsrc[i] = len(inst.sources)
+    t = _Tuning()
+    _check(load().wake_autotune(pls, dms, srcp, nsrc, n, int(slices), stream, C.byref(t)), "wake_autotune")
+    del keep
+    return _tuning_dict(t)
+
+
+def wake_set_tuning(tuning):
+    """Install a tuning (a dict as wake_autotune returns), or remove it (None)."""
+    if tuning is None:
+        _check(load().wake_set_tuning(None), "wake_set_tuning")
+        return
+    t = _Tuning()
+    n = len(tuning["lo"])
+    t.n_buckets = n
+    for b in range(n):
+        t.lo[b] = tuning["lo"][b]
+        t.threads[b] = tuning["threads"][b]
+        t.rings_per_thread[b] = tuning["rings_per_thread"][b]
+        t.rate[b] = tuning.get("rate", [0.0] * n)[b]
+    _check(load().wake_set_tuning(C.byref(t)), "wake_set_tuning")
+
+
+def wake_get_tuning():
+    """The installed tuning as a dict, or None."""
+    t = _Tuning()
+    r = load().wake_get_tuning(C.byref(t))
+    if r == WAKE_ESTATE:
+        return None
+    _check(r, "wake_get_tuning")
+    return _tuning_dict(t)
+
+
 def wake_tiling_count() -> int:
     return int(load().wake_tiling_count())
 
@@ -225,6 +300,12 @@ class WakeSolver:
     def from_instance(cls, inst, record_stride: int = 0, stream=None):
         return cls(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens,
                    record_stride, stream)
+
+    def threads(self) -> int:
+        """Workgroup threads of this context's layout."""
+        t = _I()
+        _check(self._lib.wake_get_threads(self.h, C.byref(t)), "wake_get_threads")
+        return t.value
 
     def layout(self):
         """(workgroups, rings per thread) of this context's layout."""

@@ -117,58 +117,65 @@ def test_laser_witness_region_matches_split_launches(wk):
     b.close()
 
 
-def _bench_layout(inst, nt=512):
-    """(members, rings per thread) of a context at the benchmark's
-    cooperative layout."""
-    from bench import LARGE_CLUSTER
-    rpt, _ = LARGE_CLUSTER
-    c = max(rpt or 8, -(-inst.n_rings // (256 * nt)))
+# The cooperative layouts the autotuner chooses from for instances beyond
+# 2048 rings (512-thread members with 1, 2, 4 or 8 rings per thread): the
+# benchmark times the large solves in the one it measured fastest.
+TUNED_RINGS_PER_THREAD = (1, 2, 4, 8)
+
+
+def _tuned_layout(wk, rpt):
+    return dict(lo=[0, 2048, 4096, 8192, 16384, 32768, 65536, 131072], threads=[512] * 8,
+                rings_per_thread=[0, 0, 0] + [rpt] * 5)
+
+
+def _expect(inst, rpt, nt=512):
+    """(members, rings per thread) of a context under that layout."""
+    c = max(rpt, -(-inst.n_rings // (256 * nt)))
     return -(-inst.n_rings // (c * nt)), c
 
 
-def test_large_solves_at_the_benchmark_layout(wk):
-    """The 20000-ring and 200000-ring solves in exactly the layout the
-    benchmark times (512-thread members, two rings per thread where 256
-    members allow it): per-slice parity with a field grid."""
-    from bench import LARGE_CLUSTER
-    wk.wake_set_cluster(*LARGE_CLUSTER)
+def test_large_solves_at_every_tuned_layout(wk):
+    """The 20000-ring and 200000-ring solves in every layout the autotuner
+    can give them: per-slice parity with a field grid."""
     try:
-        inst = W.config2()
-        for n, seed in ((int(2.8 / inst.dxi), 4), (int(7.3 / inst.dxi), 5)):
-            _check_slice(wk, inst, n, _perturbed(inst, seed, 0.01), "blowout-20000x4000 bench layout",
-                         grid=(400, 2.0), layout=_bench_layout(inst))
-        inst = W.config5()
-        _check_slice(wk, inst, int(2.0 / inst.dxi), _perturbed(inst, 6, 0.002),
-                     "laser-200000x8000 bench layout", grid=(600, 18.0), layout=_bench_layout(inst))
+        for rpt in TUNED_RINGS_PER_THREAD:
+            wk.wake_set_tuning(_tuned_layout(wk, rpt))
+            inst = W.config2()
+            n = int(7.3 / inst.dxi)
+            _check_slice(wk, inst, n, _perturbed(inst, 4 + rpt, 0.01),
+                         f"blowout-20000x4000 {rpt} rings/thread", grid=(400, 2.0), layout=_expect(inst, rpt))
+            inst = W.config5()
+            _check_slice(wk, inst, int(2.0 / inst.dxi), _perturbed(inst, 6 + rpt, 0.002),
+                         f"laser-200000x8000 {rpt} rings/thread", grid=(600, 18.0), layout=_expect(inst, rpt))
     finally:
-        wk.wake_set_cluster(0, 0)
+        wk.wake_set_tuning(None)
 
 
-def test_benchmark_layout_split_launches_bitwise(wk):
-    """At the benchmark's layout, the 20000-ring blowout through its driver
+def test_tuned_layouts_split_launches_bitwise(wk):
+    """In every such layout, the 20000-ring blowout through its driver
     (slices 0-1200) and the 200000-ring laser case through the start of its
     witness region: one launch is bitwise the march split into launches."""
-    from bench import LARGE_CLUSTER
-    wk.wake_set_cluster(*LARGE_CLUSTER)
     try:
-        for mk, stop, start, step in ((W.config2, 1200, 0, 100), (W.config5, 4100, 4000, 10)):
-            inst = mk()
-            _say(f"bench layout split launches N={inst.n_rings} through slice {stop}")
-            a = wk.WakeSolver.from_instance(inst)
-            assert a.layout() == _bench_layout(inst)
-            a.wake_solve(0, stop)
-            b = wk.WakeSolver.from_instance(inst)
-            if start:
-                b.wake_solve(0, start)
-            for n in range(start, stop, step):
-                b.wake_solve(n, step)
-            assert a.wake_status()[0] == -1 and b.wake_status()[0] == -1
-            la, lb = a.wake_lineout(), b.wake_lineout()
-            assert np.array_equal(la[0][:stop], lb[0][:stop]) and np.array_equal(la[1][:stop], lb[1][:stop])
-            fa, fb = a.wake_fields(-1), b.wake_fields(-1)
-            for q in FIELDS + ("rho",):
-                assert np.array_equal(fa[q], fb[q]), q
-            a.close()
-            b.close()
+        for rpt in TUNED_RINGS_PER_THREAD:
+            wk.wake_set_tuning(_tuned_layout(wk, rpt))
+            for mk, stop, start, step in ((W.config2, 1200, 0, 100), (W.config5, 4100, 4000, 10)):
+                inst = mk()
+                _say(f"{rpt} rings/thread: split launches N={inst.n_rings} through slice {stop}")
+                a = wk.WakeSolver.from_instance(inst)
+                assert a.layout() == _expect(inst, rpt)
+                a.wake_solve(0, stop)
+                b = wk.WakeSolver.from_instance(inst)
+                if start:
+                    b.wake_solve(0, start)
+                for n in range(start, stop, step):
+                    b.wake_solve(n, step)
+                assert a.wake_status()[0] == -1 and b.wake_status()[0] == -1
+                la, lb = a.wake_lineout(), b.wake_lineout()
+                assert np.array_equal(la[0][:stop], lb[0][:stop]) and np.array_equal(la[1][:stop], lb[1][:stop])
+                fa, fb = a.wake_fields(-1), b.wake_fields(-1)
+                for q in FIELDS + ("rho",):
+                    assert np.array_equal(fa[q], fb[q]), q
+                a.close()
+                b.close()
     finally:
-        wk.wake_set_cluster(0, 0)
+        wk.wake_set_tuning(None)

@@ -42,3 +42,22 @@ def test_strerror_and_footprint_need_no_device():
     assert 0 < small < big
     assert wake.wake_footprint(-1, 10, 0, 0) < 0
     assert wake.wake_tiling_count() == 3
+
+
+def test_malformed_tunings_are_refused_without_a_device():
+    import ctypes
+    from paper_2603_16623_amd import wake
+    lib = wake.load()
+    t = wake._Tuning()
+    t.n_buckets = 2
+    t.lo[0], t.lo[1] = 5, 100          # first bucket must start at 0
+    t.threads[0] = t.threads[1] = 512
+    assert lib.wake_set_tuning(ctypes.byref(t)) == wake.WAKE_EINVAL
+    t.lo[0], t.lo[1] = 0, 0            # not increasing
+    assert lib.wake_set_tuning(ctypes.byref(t)) == wake.WAKE_EINVAL
+    t.lo[1] = 100
+    t.threads[1] = 300                 # no such workgroup size
+    assert lib.wake_set_tuning(ctypes.byref(t)) == wake.WAKE_EINVAL
+    t.n_buckets = 9                    # more buckets than the table holds
+    assert lib.wake_set_tuning(ctypes.byref(t)) == wake.WAKE_EINVAL
+    assert lib.wake_get_tuning(ctypes.byref(t)) == wake.WAKE_ESTATE
