@@ -7,10 +7,17 @@ the batched workload (512 independent instances, ring counts log-uniform in
 by one persistent launch replayed from a HIP graph.  value = ring-slice
 updates per second over the timed steps (inputs resident in HBM).
 
+Before the timed steps the autotuner measures the marcher's layout per
+ring-count bucket on these instances (and on the two large single solves)
+and installs it; the batch is built with it.
+
 Also reported: the plain single-instance path (the same kernels, one
-instance per launch, instances of the same batch marched one after the
-other), the batched/plain ratio, the roofline of the march kernel from live
-HIP-event timings, and the CPU oracle timed on a bounded sample.
+instance per launch: the linear 1000-ring workload through its 1200 slices,
+and instances of the batch one after the other), the batched/plain ratio,
+the roofline of the march kernel from live HIP-event timings, the large
+single solves on the cooperative path (with their roofline fraction and
+per-slice latency floor), the served form, and the CPU oracle timed on
+bounded samples (the batch on every host core, the other workloads on one).
 """
 from __future__ import annotations
 
@@ -39,10 +46,9 @@ ALG_FLOPS_PER_RING_SLICE = 280
 # history terms, w and w^ (48 B); write rho, u_r and the history (32 B); the
 # ion-table interpolation (32 B, cache resident).
 ALG_BYTES_PER_RING_SLICE = 48 + 32 + 32
-# Cooperative layout of the large single solves (wake_set_cluster arguments):
-# two rings per member thread, cooperative from the LDS limit on.  The
-# full-size parity tests run this same layout.
-LARGE_CLUSTER = (2, 0)
+# Slices each autotuner candidate marches (from slice 0: through the head of
+# the batch's drivers, whose centres lie at slices 200-667).
+TUNE_SLICES = 600
 
 
 def log(*a):
@@ -59,32 +65,63 @@ def build_batch(wake, insts, stream, grid=None):
     return solvers, batch
 
 
-def _oracle_worker(job):
-    """One host process: the oracle on its instances in turn, each from
-    slice 0, for about budget_s seconds in all (numpy on one thread).
-    Returns (ring-slices, per-instance (rings, slices, slices of the
-    window), start, end) with wall-clock times."""
-    insts, budget_s = job
-    from oracle.wake_oracle import RingOracle
-    try:
-        from threadpoolctl import threadpool_limits
-        threadpool_limits(1)
-    except Exception:                       # pragma: no cover
-        pass
-    t0 = time.time()
-    done, parts = 0, []
-    for inst in insts:
+_WORKER = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+try:
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+except Exception:
+    pass
+from oracle.wake_oracle import RingOracle
+from paper_2603_16623_amd import workloads as W
+job = json.loads(sys.argv[2])
+t0 = time.time()
+done, parts = 0, []
+if job["kind"] == "batch":
+    insts = W.config3(n_inst=job["n_inst"], n_xi=job["n_xi"])
+    for i in job["which"]:
+        inst = insts[i]
         o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources)
         state = o.initial_state()
         n = 0
-        while n < inst.n_xi - 1 and time.time() - t0 < budget_s:
+        while n < inst.n_xi - 1 and time.time() - t0 < job["budget"]:
             _, state = o.slice(n, state)
             n += 1
         done += inst.n_rings * n
         parts.append((inst.n_rings, n, inst.n_xi - 1))
-        if time.time() - t0 >= budget_s:
+        if time.time() - t0 >= job["budget"]:
             break
-    return done, parts, t0, time.time()
+else:
+    inst = getattr(W, job["kind"])()
+    o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+    state = o.initial_state()
+    n = 0
+    t0 = time.time()
+    while n < inst.n_xi - 1 and time.time() - t0 < job["budget"]:
+        _, state = o.slice(n, state)
+        n += 1
+    done = inst.n_rings * n
+    parts.append((inst.n_rings, n, inst.n_xi - 1))
+print(json.dumps(dict(done=done, parts=parts, t0=t0, t1=time.time())))
+"""
+
+
+def _run_workers(jobs, budget_s):
+    """One plain host process per job (no process pool: every worker is a
+    child of this process, waited for, and gone when this returns).  Returns
+    the workers' results."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, "-c", _WORKER, ROOT, json.dumps(j)], env=env,
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True) for j in jobs]
+    out = []
+    for p in procs:
+        so, se = p.communicate(timeout=budget_s * 4 + 300)
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed: {se[-2000:]}")
+        out.append(json.loads(so.strip().splitlines()[-1]))
+    return out
 
 
 def host_cores() -> int:
@@ -97,20 +134,18 @@ def host_cores() -> int:
     return max(1, min(16, n or (os.cpu_count() or 1)))
 
 
-def cpu_baseline(insts, budget_s: float = 15.0, cores: int = 0):
-    """Time the oracle on a bounded sample: a pool of host processes (one per
-    core, spawned fresh, so none shares this process's GPU state), each
-    marching a different instance of the batch from slice 0 for about
-    budget_s seconds; rate = all ring-slices over the span from the first
-    worker's start to the last worker's end."""
-    import multiprocessing as mp
-    cores = max(1, min(cores or host_cores(), len(insts)))
-    jobs = [(insts[i::cores], budget_s) for i in range(cores)]
-    with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_worker, jobs, chunksize=1)
-    done = sum(r[0] for r in res)
-    span = max(r[3] for r in res) - min(r[2] for r in res)
-    parts = [p for r in res for p in r[1]]
+def cpu_baseline(n_inst, n_xi, budget_s: float = 15.0, cores: int = 0):
+    """Time the oracle on a bounded sample of the batch: one host process per
+    core (numpy on one thread each), process i marching instances i, i + k,
+    ... from slice 0 for about budget_s seconds; rate = all ring-slices over
+    the span from the first worker's start to the last worker's end."""
+    cores = max(1, min(cores or host_cores(), n_inst))
+    jobs = [dict(kind="batch", n_inst=n_inst, n_xi=n_xi, budget=budget_s,
+                 which=list(range(i, n_inst, cores))) for i in range(cores)]
+    res = _run_workers(jobs, budget_s)
+    done = sum(r["done"] for r in res)
+    span = max(r["t1"] for r in res) - min(r["t0"] for r in res)
+    parts = [p for r in res for p in r["parts"]]
     whole = sum(1 for _, ns, nw in parts if ns == nw)
     rings = [p[0] for p in parts]
     return dict(value=done / span, unit="ring-slice updates/s", cores=cores, kind="oracle",
@@ -119,6 +154,24 @@ def cpu_baseline(insts, budget_s: float = 15.0, cores: int = 0):
                        f"i, i + {cores}, ...): {len(parts)} instances of {min(rings)}-{max(rings)} "
                        f"rings, {whole} of them through the whole window; {done} ring-slices in "
                        f"{span:.1f} s")
+
+
+def cpu_single_core(budget_s: float):
+    """The oracle on one core for the single-instance workloads, side by side
+    (one process each, started together): the linear 1000-ring workload
+    through its whole window, and the first slices of the 20000-ring blowout
+    and of the 200000-ring laser case, about budget_s seconds each."""
+    names = {"config1": "linear 1000 rings x 1200 slices",
+             "config2": "blowout 20000 rings x 4000 slices",
+             "config5": "laser 200000 rings x 8000 slices"}
+    res = _run_workers([dict(kind=k, budget=budget_s) for k in names], budget_s)
+    out = {}
+    for k, r in zip(names, res):
+        n_rings, n, nw = r["parts"][0]
+        out[names[k]] = dict(value=r["done"] / (r["t1"] - r["t0"]), unit="ring-slice updates/s",
+                             cores=1, kind="oracle",
+                             sample=f"slices 0-{n} of {nw + 1} ({n_rings} rings), {r['t1'] - r['t0']:.1f} s")
+    return out
 
 
 C4_MEAN_WORK = (50_000 - 500) / math.log(100.0) * (500 + 8000) / 2.0   # E[N] E[N_xi]
@@ -190,13 +243,15 @@ def main():
     ap.add_argument("--grid-r", type=float, default=1.0, help="field-grid radius")
     ap.add_argument("--grid-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--served-seconds", type=float, default=20.0,
+    ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="arrival window of the served run (0: skip)")
     ap.add_argument("--served-rate", type=float, default=0.0,
-                    help="request rate of the served run (0: 70%% of the measured capacity)")
+                    help="request rate of the served run (0: 85%% of the measured capacity)")
     ap.add_argument("--served-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-large", dest="large", action="store_false",
                     help="skip the large single instances (cooperative path)")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the autotuner (tiling settings instead)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the "
@@ -223,6 +278,14 @@ def main():
     log(f"building {args.n_inst} instances x {args.n_xi} slices")
     insts = W.config3(n_inst=args.n_inst, n_xi=args.n_xi)
     work = sum(i.ring_slices for i in insts)
+    tuning = None
+    if args.tune:
+        log("autotune")
+        t_tune = time.perf_counter()
+        large = [W.config2(), W.config5()] if args.large else []
+        tuning = wake.wake_autotune(insts + large, TUNE_SLICES, stream=stream)
+        tuning["seconds"] = time.perf_counter() - t_tune
+        log(f"tuning {tuning}")
     solvers, batch = build_batch(wake, insts, stream)
     batch.wake_batch_capture()
     log("warmup")
@@ -259,6 +322,19 @@ def main():
     torch.cuda.synchronize()
     tplain = time.perf_counter() - tp
     plain_value = sum(i.ring_slices for i in sample) / tplain
+    # the linear workload (1000 rings x 1200 slices, 10^4 particles) as the
+    # plain single instance: one solve, one launch
+    c1 = W.config1()
+    s1 = wake.WakeSolver.from_instance(c1, stream=stream)
+    s1.wake_prepare()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    s1.wake_solve(0, c1.n_xi)
+    s1.wake_sync()
+    t1 = time.perf_counter() - tp
+    linear = dict(value=c1.ring_slices / t1, unit="ring-slice updates/s", seconds=t1,
+                  us_per_slice=t1 / c1.n_xi * 1e6, threads=s1.threads(), breakdown_slice=s1.wake_status()[0])
+    s1.close()
 
     # measured HBM traffic of one march dispatch of this workload, if the
     # counters were taken on the current marcher sources
@@ -277,6 +353,10 @@ def main():
     flops = ALG_FLOPS_PER_RING_SLICE * work
     roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                 frac=achieved / PEAK_HBM, traffic=traffic,
+                traffic_source=None if traffic is None else
+                "replayed: rocprofv3 FETCH_SIZE and WRITE_SIZE of one march dispatch of this "
+                "workload on the current marcher sources (profiles/wake_march_kernel_traffic.txt, "
+                "copy-calibrated)",
                 kernel="wake_march_kernel", kernel_ms=float(np.mean(kernel_ms)),
                 alg_bytes_per_ring_slice=ALG_BYTES_PER_RING_SLICE,
                 traffic_B_per_ring_slice=None if traffic is None else traffic / work,
@@ -300,9 +380,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload,
                    "instances": args.n_inst, "ring_slices_per_step": work,
-                   "tiling": {"threads": nt, "wgs_per_cu": wpc}, "breakdowns": breakdowns},
+                   "tiling": {"threads": nt, "wgs_per_cu": wpc} if tuning is None else None,
+                   "autotuned_layout": tuning, "breakdowns": breakdowns},
         "plain_single_instance": {"value": plain_value, "unit": "ring-slice updates/s",
-                                  "instances": len(sample)},
+                                  "instances": len(sample),
+                                  "what": "the first instances of the batch, one launch each"},
+        "linear_single_instance": linear,
         "batched_vs_plain": value / plain_value,
         "roofline": roof,
     }
@@ -350,7 +433,7 @@ def main():
                 srv.result(t)
         capacity = (srv.stats()["ring_slices"] - w0) / (time.perf_counter() - c0)
         srv.close()
-        rate = args.served_rate or 0.7 * capacity / C4_MEAN_WORK
+        rate = args.served_rate or 0.85 * capacity / C4_MEAN_WORK
         log(f"served: capacity {capacity:.3e} ring-slices/s -> run at {rate:.1f} requests/s")
         run = served_run(wake, W, stream, rate, args.served_seconds, budget, step_us)
         offered = 2000.0 * C4_MEAN_WORK
@@ -362,13 +445,10 @@ def main():
             max_sustainable_rate_per_s=capacity / C4_MEAN_WORK, **run)
     if args.large:
         # the large single instances on the cooperative (multi-workgroup) path,
-        # two rings per member thread (more members per instance: lower
-        # latency of one solve, 20000 rings: 57 us per slice against 61 with
-        # four and 78 with eight; the served form keeps the default eight,
-        # which gives it more throughput; 200000 rings need seven, the
-        # fewest that keep within 64 members)
+        # in the layout the autotuner chose for their ring counts (or the
+        # default layout without it); the first eighth of each window, before
+        # the drivers disturb the order, gives the per-slice latency floor
         log("large instances")
-        wake.wake_set_cluster(*LARGE_CLUSTER)
         big = {}
         for name, mk in (("blowout 20000 rings x 4000 slices", W.config2),
                          ("laser 200000 rings x 8000 slices", W.config5)):
@@ -377,20 +457,30 @@ def main():
             s.wake_prepare()
             g, c = s.layout()
             torch.cuda.synchronize()
+            q = inst.n_xi // 8
             t1 = time.perf_counter()
-            s.wake_solve(0, inst.n_xi)
+            s.wake_solve(0, q)
+            s.wake_sync()
+            tq = time.perf_counter() - t1
+            s.wake_solve(q, inst.n_xi - q)
             s.wake_sync()
             dt = time.perf_counter() - t1
             brk = s.wake_status()[0]
+            cnt = s.wake_counters()
             s.close()
+            rate = inst.ring_slices / dt
             big[name] = dict(workgroups=g, rings_per_thread=c, seconds=dt, breakdown_slice=brk,
-                             ring_slice_updates_per_s=inst.ring_slices / dt,
-                             us_per_slice=dt / inst.n_xi * 1e6)
-        wake.wake_set_cluster(0, 0)
+                             ring_slice_updates_per_s=rate, us_per_slice=dt / inst.n_xi * 1e6,
+                             floor_us_per_slice=tq / q * 1e6,
+                             roofline_frac=ALG_BYTES_PER_RING_SLICE * rate / PEAK_HBM,
+                             fixups_per_slice=cnt["fixups"] / inst.n_xi,
+                             meetings_per_slice=cnt["meetings"] / inst.n_xi)
         out["large_instances"] = big
     if not args.no_cpu:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.n_inst, args.n_xi, args.cpu_budget)
+        log("cpu baselines of the single-instance workloads (one core each)")
+        out["cpu_baseline_single_core"] = cpu_single_core(args.cpu_budget)
     batch.close()
     for s in solvers + plain_solvers:
         s.close()
