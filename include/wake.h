@@ -221,6 +221,52 @@ void wake_destroy(wake_ctx *ctx);
 const char *wake_strerror(int code);
 
 /* ---------------------------------------------------------------------
+ * Mobile ions (paper, Sec. "Key algorithmic adjustments": several plasma
+ * species, the ions included, each summed on its own at its own rings; the
+ * beam-driven benchmark of Sec. "Validation benchmarks" moves the ions).  A
+ * two-species context holds the electrons (species 0: q = -1, m = 1) and
+ * singly charged ions of mass ion_mass electron masses (species 1: q = +1,
+ * psibar = 1 - psi / ion_mass), both starting at rest at the column's radii
+ * with the column's weights.  Per slice each species is sorted and its psi,
+ * d_rho psi and d_zeta psi sums formed at its own rings (eqs. psi, dpsi_dr,
+ * dpsi_dzeta); at the rings of the other species they are interpolated
+ * linearly between that species' rings, with nodes at the axis (its psi(0),
+ * d_rho psi = 0, its d_zeta psi(0), B^(p) = 0) and at its outer edge (its
+ * outermost ring's radius plus half that ring's initial extent dr: the
+ * exterior field -q Q ln r, -q Q / r, d_zeta psi = 0, B^(p) = b_N / r) and
+ * the exterior field beyond the edge.  B_theta^(p) comes from the electrons
+ * alone (eqs. b_coeffs_1-3, ai_bi: the ion currents are neglected) and
+ * reaches the ions by the same interpolation.  Both species are pushed with
+ * their q and m (eqs. plasma_particle_motion_1-4).  psi(0) and E_z(0) of the
+ * lineout are the sums over both species.
+ *
+ * The context is a wake_ctx: wake_add_beam, wake_prepare(_noalloc),
+ * wake_solve, wake_status, wake_lineout, wake_reset, wake_sync,
+ * wake_counters (slices, order fix-ups), wake_get_layout / wake_get_threads
+ * and wake_destroy work on it as on any context; wake_fields,
+ * wake_get_state and wake_set_state act on the electrons; the calls below
+ * reach either species.  It has no field grid (wake_set_grid: WAKE_EINVAL)
+ * and joins no batch (wake_batch_create: WAKE_EINVAL).  One workgroup of
+ * 1024 threads marches it; n_rings <= 8192 and ion_mass > 0 finite
+ * (WAKE_EINVAL otherwise).
+ * --------------------------------------------------------------------- */
+int wake_create_mobile_ions(wake_ctx **out, const wake_plasma *plasma, double ion_mass,
+                            const wake_domain *domain, void *hip_stream);
+/* wake_fields of species 0 (electrons) or 1 (ions; WAKE_EINVAL on a
+ * one-species context), by ring id of that species. */
+int wake_species_fields(wake_ctx *ctx, int32_t species, int32_t slice, double *psi,
+                        double *er_minus_bt, double *ez, double *bt, double *rho, double *ur,
+                        int32_t dst_is_device);
+/* wake_get_state / wake_set_state of one species.  Setting either species
+ * makes `slice` the next slice of both (set both to start a two-species
+ * march from a given state) and clears a breakdown. */
+int wake_get_species_state(wake_ctx *ctx, int32_t species, int32_t *slice, double *rho, double *ur,
+                           double *f_rho, double *f_u, int32_t dst_is_device);
+int wake_set_species_state(wake_ctx *ctx, int32_t species, int32_t slice, const double *rho,
+                           const double *ur, const double *f_rho, const double *f_u,
+                           int32_t src_is_device);
+
+/* ---------------------------------------------------------------------
  * Tiling of the marcher.  A workgroup of `threads` threads owns one instance;
  * thread t owns the ceil(n_rings / threads) consecutive rings (in radial
  * order) starting at t * ceil(n_rings / threads).  `threads` is fixed for a

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwake.so")
 SOURCES = [os.path.join(CSRC, "wake_march.hip"), os.path.join(CSRC, "wake_beam.hip"),
            os.path.join(CSRC, "wake_api.cpp"), os.path.join(CSRC, "wake_serve.cpp"),
-           os.path.join(CSRC, "wake_tune.cpp")]
+           os.path.join(CSRC, "wake_tune.cpp"), os.path.join(CSRC, "wake_ions.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -208,6 +208,7 @@ static void release(wake_ctx* c) {
   if (c->grid_mem) (void)hipFree(c->grid_mem);
   if (c->d_inst) (void)hipFree(c->d_inst);
   if (c->d_counter) (void)hipFree(c->d_counter);
+  if (c->d_J) (void)hipFree(c->d_J);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -216,18 +217,14 @@ extern "C" void wake_destroy(wake_ctx* ctx) { release(ctx); }
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
-               const Layout& L) {
-  const int nt = L.nt;
-  if (!out) return WAKE_EINVAL;
-  if (!march_threads_ok(nt)) return WAKE_EINVAL;
-  *out = nullptr;
+// The plasma column and window of a new context (wake_plasma, wake_domain).
+static int check_column(const wake_plasma* plasma, const wake_domain* dom) {
   if (!plasma || !dom || plasma->n_rings <= 0 || !plasma->r0 || !plasma->dr) return WAKE_EINVAL;
   const int N = plasma->n_rings;
   if (N > (1 << 28)) return WAKE_EINVAL;
   if (!finite_pos(dom->dxi) || dom->n_xi <= 0 || dom->record_stride < 0) return WAKE_EINVAL;
   // ring geometry: r0_j = sum_{k<j} dr_k + dr_j/2, strictly increasing
-  double edge = 0.0, min_dr = INFINITY;
+  double edge = 0.0;
   for (int j = 0; j < N; ++j) {
     const double d = plasma->dr[j], r = plasma->r0[j];
     if (!finite_pos(d) || !finite_pos(r)) return WAKE_EINVAL;
@@ -236,11 +233,16 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
     if (std::fabs(r - want) > 1e-9 * want) return WAKE_EINVAL;
     if (plasma->dens && !finite_pos(plasma->dens[j])) return WAKE_EINVAL;
     edge += d;
-    min_dr = std::min(min_dr, d);
   }
+  return WAKE_OK;
+}
+
+// A new context with its stream (nothing allocated on the device yet).
+static int ctx_new(wake_ctx** out, void* hip_stream) {
   wake_ctx* c = new (std::nothrow) wake_ctx();
   if (!c) return WAKE_ENOMEM;
   std::memset(&c->I, 0, sizeof(WakeInst));
+  std::memset(&c->J, 0, sizeof(WakeIons));
   if (hipGetDevice(&c->device) != hipSuccess) { release(c); return WAKE_EDEVICE; }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
@@ -251,6 +253,22 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
     }
     c->own_stream = true;
   }
+  *out = c;
+  return WAKE_OK;
+}
+
+int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
+               const Layout& L) {
+  const int nt = L.nt;
+  if (!out) return WAKE_EINVAL;
+  if (!march_threads_ok(nt)) return WAKE_EINVAL;
+  *out = nullptr;
+  int rc = check_column(plasma, dom);
+  if (rc != WAKE_OK) return rc;
+  const int N = plasma->n_rings;
+  wake_ctx* c = nullptr;
+  rc = ctx_new(&c, hip_stream);
+  if (rc != WAKE_OK) return rc;
   WakeInst& I = c->I;
   I.N = N;
   I.n_xi = dom->n_xi;
@@ -327,6 +345,105 @@ extern "C" int wake_create(wake_ctx** out, const wake_plasma* plasma, const wake
                            void* hip_stream) {
   if (!plasma || plasma->n_rings <= 0) return out ? (*out = nullptr, WAKE_EINVAL) : WAKE_EINVAL;
   return ctx_create(out, plasma, dom, hip_stream, layout_for(plasma->n_rings));
+}
+
+// ---------------------------------------------------------------------------
+// two-species contexts: plasma electrons and mobile ions
+// ---------------------------------------------------------------------------
+extern "C" int wake_create_mobile_ions(wake_ctx** out, const wake_plasma* plasma, double ion_mass,
+                                       const wake_domain* dom, void* hip_stream) {
+  if (!out) return WAKE_EINVAL;
+  *out = nullptr;
+  int rc = check_column(plasma, dom);
+  if (rc != WAKE_OK) return rc;
+  if (!finite_pos(ion_mass) || plasma->n_rings > WAKE_IONS_NMAX) return WAKE_EINVAL;
+  const int N = plasma->n_rings;
+  wake_ctx* c = nullptr;
+  rc = ctx_new(&c, hip_stream);
+  if (rc != WAKE_OK) return rc;
+  c->two_species = true;
+  WakeInst& I = c->I;
+  WakeIons& J = c->J;
+  I.N = J.N = N;
+  I.n_xi = J.n_xi = dom->n_xi;
+  I.stride = J.stride = dom->record_stride;
+  I.dxi = J.dxi = dom->dxi;
+  I.Rp = plasma->r0[N - 1] + plasma->dr[N - 1] / 2.0;
+  I.inv2pidxi = 1.0 / (2.0 * M_PI * I.dxi);
+  I.nt = WAKE_IONS_NT;
+  I.G = 1;
+  I.C = J.C = (N + WAKE_IONS_NT - 1) / WAKE_IONS_NT;
+  J.m_i = ion_mass;
+  const size_t S = (size_t)J.C * WAKE_IONS_NT;
+  const size_t n_rec = I.stride > 0 ? (size_t)(I.n_xi + I.stride - 1) / I.stride : 0;
+  // sizes first (a null arena only counts), then the real carve
+  for (int pass = 0; pass < 2; ++pass) {
+    Arena& A = c->arena;
+    if (pass == 1) {
+      const size_t bytes = A.used + 256;
+      A = Arena();
+      hipError_t e = hipMalloc(&A.base, bytes);
+      if (e != hipSuccess) { A.base = nullptr; release(c); return dev_err(e); }
+      A.size = bytes;
+    }
+    J.cst = A.take<double>((size_t)IK_N * N);
+    for (int b = 0; b < 2; ++b) J.st[b] = A.take<double>((size_t)2 * IS_N * N);
+    J.ord = A.take<int32_t>((size_t)2 * N);
+    J.sid = A.take<int32_t>(2 * S);
+    J.jx = A.take<int32_t>(2 * S);
+    J.tab = A.take<double>((size_t)2 * IT_N * S);
+    J.work = A.take<double>((size_t)2 * IW_N * S);
+    J.axis = A.take<double>(2 * (size_t)I.n_xi);
+    for (int sp = 0; sp < 2; ++sp) {
+      J.snap[sp] = n_rec ? A.take<double>(n_rec * OUT_N * N) : nullptr;
+      J.last[sp] = A.take<double>((size_t)OUT_N * N);
+    }
+    J.ctl = A.take<int32_t>(CTL_NWORDS);
+    J.cnt = A.take<unsigned long long>(CNT_N);
+    c->staging = A.take<double>(4 * (size_t)N);
+  }
+  // the electrons' outputs and the control words are read through I
+  I.axis = J.axis;
+  I.snap = J.snap[0];
+  I.last = J.last[0];
+  I.ctl = J.ctl;
+  I.cnt = J.cnt;
+  hipError_t e = hipMalloc(&c->d_J, sizeof(WakeIons));
+  if (e != hipSuccess) { c->d_J = nullptr; release(c); return dev_err(e); }
+  double* d_r0 = c->staging;
+  double* d_dr = c->staging + N;
+  double* d_dn = plasma->dens ? c->staging + 2 * (size_t)N : nullptr;
+  e = hipMemcpyAsync(d_r0, plasma->r0, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_dr, plasma->dr, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && d_dn)
+    e = hipMemcpyAsync(d_dn, plasma->dens, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(J.axis, 0, sizeof(double) * 2 * I.n_xi, c->stream);
+  if (e == hipSuccess) e = launch_zero(reinterpret_cast<int32_t*>(J.cnt), 2 * CNT_N, c->stream);
+  if (e == hipSuccess) e = launch_ions_init(J, d_r0, d_dr, d_dn, true, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) { release(c); return dev_err(e); }
+  *out = c;
+  return WAKE_OK;
+}
+
+// march a two-species context: its record (with the sources and beam table
+// the context gathered in I) to the device, one workgroup
+static int ions_launch(wake_ctx* c, int first, int count) {
+  WakeIons& J = c->J;
+  const WakeInst& I = c->I;
+  J.first = first;
+  J.count = count;
+  J.nb = I.nb;
+  J.n_an = I.n_an;
+  J.has_laser = I.has_laser;
+  for (int k = 0; k < WAKE_MAX_ANALYTIC; ++k) J.an[k] = I.an[k];
+  J.boff = I.boff;
+  J.br = I.br;
+  J.bcum = I.bcum;
+  HIP_TRY(hipMemcpyAsync(c->d_J, &J, sizeof(WakeIons), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_ions_march(c->d_J, 1, c->stream));
+  return WAKE_OK;
 }
 
 extern "C" int wake_add_beam(wake_ctx* c, const wake_source* s) {
@@ -554,7 +671,7 @@ extern "C" int wake_solve(wake_ctx* c, int32_t first, int32_t count) {
   if (r != WAKE_OK) return r;
   r = wake_prepare(c);
   if (r != WAKE_OK) return r;
-  r = launch_one(c, first, count);
+  r = c->two_species ? ions_launch(c, first, count) : launch_one(c, first, count);
   if (r != WAKE_OK) return r;
   c->next = first + count;
   return WAKE_OK;
@@ -599,9 +716,9 @@ static int copy_out(double* dst, const double* src, size_t n, int dev, hipStream
   return WAKE_OK;
 }
 
-extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt, double* ez,
-                           double* bt, double* rho, double* ur, int32_t dev) {
-  if (!c) return WAKE_EINVAL;
+// Recorded fields of one species (snapshots snap, last slice last).
+static int fields_of(wake_ctx* c, const double* snap, const double* last, int32_t slice, double* psi,
+                     double* erbt, double* ez, double* bt, double* rho, double* ur, int32_t dev) {
   const WakeInst& I = c->I;
   int32_t ctl[CTL_NWORDS];
   int r = read_ctl(c, ctl);
@@ -611,13 +728,13 @@ extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt
   if (slice == -1) {
     if (c->next == 0 && brk < 0) return WAKE_ESTATE;
     if (brk >= 0) return WAKE_EBREAKDOWN;
-    base = I.last;
+    base = last;
   } else {
     if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
     if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
     if (slice >= c->next || slice < c->valid_from) return WAKE_ESTATE;
     if (I.stride <= 0 || slice % I.stride != 0) return WAKE_ENOTREC;
-    base = I.snap + (size_t)(slice / I.stride) * OUT_N * I.N;
+    base = snap + (size_t)(slice / I.stride) * OUT_N * I.N;
   }
   const size_t N = I.N;
   double* outs[OUT_N] = {psi, erbt, ez, bt, rho, ur};
@@ -629,8 +746,22 @@ extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt
   return WAKE_OK;
 }
 
-extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
+extern "C" int wake_fields(wake_ctx* c, int32_t slice, double* psi, double* erbt, double* ez,
+                           double* bt, double* rho, double* ur, int32_t dev) {
   if (!c) return WAKE_EINVAL;
+  return fields_of(c, c->I.snap, c->I.last, slice, psi, erbt, ez, bt, rho, ur, dev);
+}
+
+extern "C" int wake_species_fields(wake_ctx* c, int32_t species, int32_t slice, double* psi,
+                                   double* erbt, double* ez, double* bt, double* rho, double* ur,
+                                   int32_t dev) {
+  if (!c || species < 0 || species > 1 || (species == 1 && !c->two_species)) return WAKE_EINVAL;
+  if (species == 0) return wake_fields(c, slice, psi, erbt, ez, bt, rho, ur, dev);
+  return fields_of(c, c->J.snap[1], c->J.last[1], slice, psi, erbt, ez, bt, rho, ur, dev);
+}
+
+extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
+  if (!c || c->two_species) return WAKE_EINVAL;
   if (n_r < 0 || n_r > (1 << 20) || (n_r > 0 && !finite_pos(r_max))) return WAKE_EINVAL;
   if (c->next != 0 || c->batches > 0) return WAKE_ESTATE;
   HIP_TRY(hipSetDevice(c->device));
@@ -705,15 +836,19 @@ extern "C" int wake_lineout(wake_ctx* c, double* psi_axis, double* ez_axis, int3
   return WAKE_OK;
 }
 
-extern "C" int wake_get_state(wake_ctx* c, int32_t* slice, double* rho, double* ur, double* f_rho,
-                              double* f_u, int32_t dev) {
-  if (!c) return WAKE_EINVAL;
+// Ring state of species sp (0: electrons; 1: the ions of a two-species
+// context) at the next slice.
+static int get_state_of(wake_ctx* c, int sp, int32_t* slice, double* rho, double* ur, double* f_rho,
+                        double* f_u, int32_t dev) {
   int32_t brk = -1, next = 0;
   int r = wake_status(c, &brk, &next);
   if (r != WAKE_OK) return r;
   const size_t N = c->I.N;
   double* st = c->staging;
-  HIP_TRY(launch_state_by_id(c->I, st, st + N, st + 2 * N, st + 3 * N, c->stream));
+  if (c->two_species)
+    HIP_TRY(launch_ions_get_state(c->J, sp, st, c->stream));
+  else
+    HIP_TRY(launch_state_by_id(c->I, st, st + N, st + 2 * N, st + 3 * N, c->stream));
   double* outs[4] = {rho, ur, f_rho, f_u};
   for (int q = 0; q < 4; ++q) {
     r = copy_out(outs[q], st + q * N, N, dev, c->stream);
@@ -724,9 +859,9 @@ extern "C" int wake_get_state(wake_ctx* c, int32_t* slice, double* rho, double* 
   return WAKE_OK;
 }
 
-extern "C" int wake_set_state(wake_ctx* c, int32_t slice, const double* rho, const double* ur,
-                              const double* f_rho, const double* f_u, int32_t dev) {
-  if (!c || !rho || !ur) return WAKE_EINVAL;
+static int set_state_of(wake_ctx* c, int sp, int32_t slice, const double* rho, const double* ur,
+                        const double* f_rho, const double* f_u, int32_t dev) {
+  if (!rho || !ur) return WAKE_EINVAL;
   if (slice < 0 || slice >= c->I.n_xi) return WAKE_EINVAL;
   const size_t N = c->I.N;
   if (!dev) {
@@ -742,12 +877,41 @@ extern "C" int wake_set_state(wake_ctx* c, int32_t slice, const double* rho, con
   HIP_TRY(hipMemcpyAsync(st + N, ur, sizeof(double) * N, kind, c->stream));
   if (f_rho) HIP_TRY(hipMemcpyAsync(st + 2 * N, f_rho, sizeof(double) * N, kind, c->stream));
   if (f_u) HIP_TRY(hipMemcpyAsync(st + 3 * N, f_u, sizeof(double) * N, kind, c->stream));
-  HIP_TRY(launch_state_set(c->I, st, st + N, f_rho ? st + 2 * N : nullptr,
-                           f_u ? st + 3 * N : nullptr, slice, c->stream));
+  if (c->two_species)
+    HIP_TRY(launch_ions_set_state(c->J, sp, st, st + N, f_rho ? st + 2 * N : nullptr,
+                                  f_u ? st + 3 * N : nullptr, slice, c->stream));
+  else
+    HIP_TRY(launch_state_set(c->I, st, st + N, f_rho ? st + 2 * N : nullptr,
+                             f_u ? st + 3 * N : nullptr, slice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->next = slice;
   c->valid_from = slice;
   return WAKE_OK;
+}
+
+extern "C" int wake_get_state(wake_ctx* c, int32_t* slice, double* rho, double* ur, double* f_rho,
+                              double* f_u, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  return get_state_of(c, 0, slice, rho, ur, f_rho, f_u, dev);
+}
+
+extern "C" int wake_set_state(wake_ctx* c, int32_t slice, const double* rho, const double* ur,
+                              const double* f_rho, const double* f_u, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  return set_state_of(c, 0, slice, rho, ur, f_rho, f_u, dev);
+}
+
+extern "C" int wake_get_species_state(wake_ctx* c, int32_t species, int32_t* slice, double* rho,
+                                      double* ur, double* f_rho, double* f_u, int32_t dev) {
+  if (!c || species < 0 || species > 1 || (species == 1 && !c->two_species)) return WAKE_EINVAL;
+  return get_state_of(c, species, slice, rho, ur, f_rho, f_u, dev);
+}
+
+extern "C" int wake_set_species_state(wake_ctx* c, int32_t species, int32_t slice, const double* rho,
+                                      const double* ur, const double* f_rho, const double* f_u,
+                                      int32_t dev) {
+  if (!c || species < 0 || species > 1 || (species == 1 && !c->two_species)) return WAKE_EINVAL;
+  return set_state_of(c, species, slice, rho, ur, f_rho, f_u, dev);
 }
 
 extern "C" int wake_reset(wake_ctx* c) {
@@ -755,8 +919,12 @@ extern "C" int wake_reset(wake_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
   int r = drain(c);
   if (r != WAKE_OK) return r;
-  HIP_TRY(hipMemcpyAsync(c->d_inst, &c->I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_reset(c->d_inst, 1, c->stream));
+  if (c->two_species) {
+    HIP_TRY(launch_ions_init(c->J, nullptr, nullptr, nullptr, false, c->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(c->d_inst, &c->I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_reset(c->d_inst, 1, c->stream));
+  }
   c->next = 0;
   c->valid_from = 0;
   return WAKE_OK;
@@ -849,7 +1017,7 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
   *out = nullptr;
   if (!ctxs || n <= 0) return WAKE_EINVAL;
   for (int i = 0; i < n; ++i)
-    if (!ctxs[i]) return WAKE_EINVAL;
+    if (!ctxs[i] || ctxs[i]->two_species) return WAKE_EINVAL;
   wake_batch* b = new (std::nothrow) wake_batch();
   if (!b) return WAKE_ENOMEM;
   b->device = ctxs[0]->device;

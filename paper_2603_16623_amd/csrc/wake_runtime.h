@@ -7,6 +7,7 @@
 
 #include "../../include/wake.h"
 #include "wake_common.h"
+#include "wake_ions.h"
 
 // bump allocation of one context's device arena (256-B aligned pieces)
 struct Arena {
@@ -41,6 +42,12 @@ struct wake_ctx {
   int next = 0;
   int valid_from = 0;              // first slice whose records belong to the current state's march
   hipStream_t pending = nullptr;   // batch stream that last marched this context
+  // two-species context (electrons and mobile ions): its own instance
+  // record and marcher; I keeps the sources, beam table, outputs of the
+  // electrons and control words
+  bool two_species = false;
+  WakeIons J;
+  WakeIons* d_J = nullptr;
 };
 
 

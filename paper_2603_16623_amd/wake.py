@@ -63,6 +63,11 @@ class _ServerConfig(C.Structure):
 _I, _P, _D, _I64 = C.c_int32, C.c_void_p, C.c_double, C.c_int64
 _SIGS = {
     "wake_create": (_I, [C.POINTER(_P), C.POINTER(_Plasma), C.POINTER(_Domain), _P]),
+    "wake_create_mobile_ions": (_I, [C.POINTER(_P), C.POINTER(_Plasma), C.c_double,
+                                     C.POINTER(_Domain), _P]),
+    "wake_species_fields": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _I]),
+    "wake_get_species_state": (_I, [_P, _I, C.POINTER(_I), _P, _P, _P, _P, _I]),
+    "wake_set_species_state": (_I, [_P, _I, _I, _P, _P, _P, _P, _I]),
     "wake_add_beam": (_I, [_P, C.POINTER(_Source)]),
     "wake_prepare": (_I, [_P]),
     "wake_prepare_noalloc": (_I, [_P, _P, _I64]),
@@ -280,7 +285,10 @@ class WakeSolver:
     """One context: a ring column, a window and its sources."""
 
     def __init__(self, r0, dr, dxi: float, n_xi: int, sources: Sequence = (), dens=None,
-                 record_stride: int = 0, stream: Optional[int] = None):
+                 record_stride: int = 0, stream: Optional[int] = None,
+                 ion_mass: Optional[float] = None):
+        """ion_mass (electron masses): a two-species context whose ions move
+        (wake_create_mobile_ions); None: immobile ions (wake_create)."""
         lib = load()
         self._lib = lib
         self.r0, self.dr = _host(r0), _host(dr)
@@ -291,7 +299,12 @@ class WakeSolver:
                      None if self.dens is None else self.dens.ctypes.data)
         dm = _Domain(self.dxi, self.n_xi, self.record_stride)
         h = _P()
-        _check(lib.wake_create(C.byref(h), C.byref(pl), C.byref(dm), stream), "wake_create")
+        self.ion_mass = None if ion_mass is None else float(ion_mass)
+        if self.ion_mass is None:
+            _check(lib.wake_create(C.byref(h), C.byref(pl), C.byref(dm), stream), "wake_create")
+        else:
+            _check(lib.wake_create_mobile_ions(C.byref(h), C.byref(pl), self.ion_mass, C.byref(dm),
+                                               stream), "wake_create_mobile_ions")
         self.h = h
         for s in sources:
             self.wake_add_beam(s)
@@ -400,6 +413,33 @@ class WakeSolver:
                "wake_get_state")
         out["slice"] = sl.value
         return out
+
+    def wake_species_fields(self, species: int, slice_: int = -1, out=None, device: bool = False):
+        """wake_fields of species 0 (electrons) or 1 (mobile ions)."""
+        names = ("psi", "er_bt", "ez", "bt", "rho", "ur")
+        if out is None:
+            out = {k: np.empty(self.N) for k in names}
+        ptrs = [_ptr(out.get(k)) for k in names]
+        _check(self._lib.wake_species_fields(self.h, int(species), slice_, *ptrs, int(device)),
+               "wake_species_fields")
+        return out
+
+    def wake_get_species_state(self, species: int):
+        names = ("rho", "ur", "f_rho", "f_u")
+        out = {k: np.empty(self.N) for k in names}
+        sl = _I()
+        _check(self._lib.wake_get_species_state(self.h, int(species), C.byref(sl),
+                                                *[out[k].ctypes.data for k in names], 0),
+               "wake_get_species_state")
+        out["slice"] = sl.value
+        return out
+
+    def wake_set_species_state(self, species: int, slice_: int, rho, ur, f_rho=None, f_u=None):
+        arrs = [_host(rho), _host(ur), None if f_rho is None else _host(f_rho),
+                None if f_u is None else _host(f_u)]
+        _check(self._lib.wake_set_species_state(self.h, int(species), slice_,
+                                                *[_ptr(a) for a in arrs], 0),
+               "wake_set_species_state")
 
     def wake_set_state(self, slice_: int, rho, ur, f_rho=None, f_u=None):
         arrs = [_host(rho), _host(ur), None if f_rho is None else _host(f_rho),
