@@ -246,9 +246,10 @@ const char *wake_strerror(int code);
  * and wake_destroy work on it as on any context; wake_fields,
  * wake_get_state and wake_set_state act on the electrons; the calls below
  * reach either species.  It has no field grid (wake_set_grid: WAKE_EINVAL)
- * and joins no batch (wake_batch_create: WAKE_EINVAL).  One workgroup of
- * 1024 threads marches it; n_rings <= 8192 and ion_mass > 0 finite
- * (WAKE_EINVAL otherwise).
+ * and is not a request of the served form.  One workgroup of 1024 threads
+ * marches it, alone or in a batch (wake_batch_*: batches may mix one- and
+ * two-species contexts; each result equals the context's alone);
+ * n_rings <= 8192 and ion_mass > 0 finite (WAKE_EINVAL otherwise).
  * --------------------------------------------------------------------- */
 int wake_create_mobile_ions(wake_ctx **out, const wake_plasma *plasma, double ion_mass,
                             const wake_domain *domain, void *hip_stream);
@@ -354,8 +355,9 @@ int wake_get_threads(wake_ctx *ctx, int32_t *threads);
 /* ---------------------------------------------------------------------
  * Batched form: many independent contexts (same device) marched by one
  * persistent launch; workgroups take instances longest-first from a device
- * counter.  Per-instance results equal those of solving alone with the same
- * tiling.
+ * counter.  Two-species contexts of the batch follow in one launch of a
+ * workgroup each (longest first).  Per-instance results equal those of
+ * solving alone with the same tiling.
  * --------------------------------------------------------------------- */
 int wake_batch_create(wake_batch **out, wake_ctx *const *ctxs, int32_t n, void *hip_stream);
 /* Advance every instance by up to n_slices (-1: to its window end) from its

@@ -160,6 +160,8 @@ struct wake_batch {
   int32_t* d_counter = nullptr;
   WakeInst* d_ginsts = nullptr;    // descriptors the captured graph reads (written by capture only)
   int32_t* d_gcounter = nullptr;
+  WakeIons* d_jinsts = nullptr;    // two-species records of eager solves
+  WakeIons* d_gjinsts = nullptr;   // two-species records the captured graph reads
   int cap = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -420,6 +422,7 @@ extern "C" int wake_create_mobile_ions(wake_ctx** out, const wake_plasma* plasma
     e = hipMemcpyAsync(d_dn, plasma->dens, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(J.axis, 0, sizeof(double) * 2 * I.n_xi, c->stream);
   if (e == hipSuccess) e = launch_zero(reinterpret_cast<int32_t*>(J.cnt), 2 * CNT_N, c->stream);
+  if (e == hipSuccess) e = ions_prepare();
   if (e == hipSuccess) e = launch_ions_init(J, d_r0, d_dr, d_dn, true, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) { release(c); return dev_err(e); }
@@ -429,8 +432,8 @@ extern "C" int wake_create_mobile_ions(wake_ctx** out, const wake_plasma* plasma
 
 // march a two-species context: its record (with the sources and beam table
 // the context gathered in I) to the device, one workgroup
-static int ions_launch(wake_ctx* c, int first, int count) {
-  WakeIons& J = c->J;
+WakeIons ions_record(const wake_ctx* c, int first, int count) {
+  WakeIons J = c->J;
   const WakeInst& I = c->I;
   J.first = first;
   J.count = count;
@@ -441,7 +444,12 @@ static int ions_launch(wake_ctx* c, int first, int count) {
   J.boff = I.boff;
   J.br = I.br;
   J.bcum = I.bcum;
-  HIP_TRY(hipMemcpyAsync(c->d_J, &J, sizeof(WakeIons), hipMemcpyHostToDevice, c->stream));
+  return J;
+}
+
+static int ions_launch(wake_ctx* c, int first, int count) {
+  c->J = ions_record(c, first, count);
+  HIP_TRY(hipMemcpyAsync(c->d_J, &c->J, sizeof(WakeIons), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(launch_ions_march(c->d_J, 1, c->stream));
   return WAKE_OK;
 }
@@ -1004,6 +1012,8 @@ static void batch_release(wake_batch* b) {
   if (b->d_counter) (void)hipFree(b->d_counter);
   if (b->d_ginsts) (void)hipFree(b->d_ginsts);
   if (b->d_gcounter) (void)hipFree(b->d_gcounter);
+  if (b->d_jinsts) (void)hipFree(b->d_jinsts);
+  if (b->d_gjinsts) (void)hipFree(b->d_gjinsts);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   if (b->holds)
     for (wake_ctx* c : b->ctxs) --c->batches;
@@ -1017,7 +1027,7 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
   *out = nullptr;
   if (!ctxs || n <= 0) return WAKE_EINVAL;
   for (int i = 0; i < n; ++i)
-    if (!ctxs[i] || ctxs[i]->two_species) return WAKE_EINVAL;
+    if (!ctxs[i]) return WAKE_EINVAL;
   wake_batch* b = new (std::nothrow) wake_batch();
   if (!b) return WAKE_ENOMEM;
   b->device = ctxs[0]->device;
@@ -1040,7 +1050,9 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
   if (hipMalloc(&b->d_insts, sizeof(WakeInst) * n) != hipSuccess ||
       hipMalloc(&b->d_counter, 64) != hipSuccess ||
       hipMalloc(&b->d_ginsts, sizeof(WakeInst) * n) != hipSuccess ||
-      hipMalloc(&b->d_gcounter, 64) != hipSuccess) {
+      hipMalloc(&b->d_gcounter, 64) != hipSuccess ||
+      hipMalloc(&b->d_jinsts, sizeof(WakeIons) * n) != hipSuccess ||
+      hipMalloc(&b->d_gjinsts, sizeof(WakeIons) * n) != hipSuccess) {
     batch_release(b);
     return WAKE_ENOMEM;
   }
@@ -1052,13 +1064,19 @@ extern "C" int wake_batch_create(wake_batch** out, wake_ctx* const* ctxs, int32_
 
 // Fill the device descriptor array with (first, count) per instance, longest
 // first.  Returns the number of instances with work.
-static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vector<WakeInst>& v) {
+static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vector<WakeInst>& v,
+                       std::vector<WakeIons>& vj) {
   v.clear();
+  vj.clear();
   for (wake_ctx* c : b->ctxs) {
     const int first = from_zero ? 0 : c->next;
     int count = c->I.n_xi - first;
     if (n_slices >= 0) count = std::min(count, (int)n_slices);
     if (count <= 0) continue;
+    if (c->two_species) {
+      vj.push_back(ions_record(c, first, count));
+      continue;
+    }
     WakeInst I = c->I;
     I.first = first;
     I.count = count;
@@ -1067,8 +1085,11 @@ static int batch_stage(wake_batch* b, int32_t n_slices, bool from_zero, std::vec
   std::stable_sort(v.begin(), v.end(), [](const WakeInst& a, const WakeInst& c) {
     return (int64_t)a.N * a.count > (int64_t)c.N * c.count;
   });
+  std::stable_sort(vj.begin(), vj.end(), [](const WakeIons& a, const WakeIons& c) {
+    return (int64_t)a.N * a.count > (int64_t)c.N * c.count;
+  });
   assign_tasks(v);
-  return (int)v.size();
+  return (int)(v.size() + vj.size());
 }
 
 // one persistent launch per distinct workgroup size present in v (the
@@ -1103,10 +1124,17 @@ hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts,
   return hipSuccess;
 }
 
-static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v, int grid_override,
-                               bool graph) {
-  return launch_insts(v, graph ? b->d_ginsts : b->d_insts, graph ? b->d_gcounter : b->d_counter,
-                      b->device, grid_override, b->stream);
+// the one-species persistent launches, then one workgroup per two-species
+// instance (longest first)
+static hipError_t batch_launch(wake_batch* b, const std::vector<WakeInst>& v,
+                               const std::vector<WakeIons>& vj, int grid_override, bool graph) {
+  if (!v.empty()) {
+    hipError_t e = launch_insts(v, graph ? b->d_ginsts : b->d_insts, graph ? b->d_gcounter : b->d_counter,
+                                b->device, grid_override, b->stream);
+    if (e != hipSuccess) return e;
+  }
+  if (!vj.empty()) return launch_ions_march(graph ? b->d_gjinsts : b->d_jinsts, (int)vj.size(), b->stream);
+  return hipSuccess;
 }
 
 extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
@@ -1117,10 +1145,16 @@ extern "C" int wake_batch_solve(wake_batch* b, int32_t n_slices) {
     if (r != WAKE_OK) return r;
   }
   std::vector<WakeInst> v;
-  const int n = batch_stage(b, n_slices, false, v);
+  std::vector<WakeIons> vj;
+  const int n = batch_stage(b, n_slices, false, v, vj);
   if (n == 0) return WAKE_OK;
-  HIP_TRY(hipMemcpyAsync(b->d_insts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(batch_launch(b, v, 0, false));
+  if (!v.empty())
+    HIP_TRY(hipMemcpyAsync(b->d_insts, v.data(), sizeof(WakeInst) * v.size(), hipMemcpyHostToDevice,
+                           b->stream));
+  if (!vj.empty())
+    HIP_TRY(hipMemcpyAsync(b->d_jinsts, vj.data(), sizeof(WakeIons) * vj.size(), hipMemcpyHostToDevice,
+                           b->stream));
+  HIP_TRY(batch_launch(b, v, vj, 0, false));
   for (wake_ctx* c : b->ctxs) {
     int count = c->I.n_xi - c->next;
     if (n_slices >= 0) count = std::min(count, (int)n_slices);
@@ -1138,17 +1172,23 @@ extern "C" int wake_batch_capture(wake_batch* b, int32_t grid) {
     if (r != WAKE_OK) return r;
   }
   std::vector<WakeInst> v;
-  const int n = batch_stage(b, -1, true, v);
+  std::vector<WakeIons> vj;
+  const int n = batch_stage(b, -1, true, v, vj);
   if (n == 0) return WAKE_EINVAL;
   // the graph reads descriptors of its own: eager solves of the batch
-  // between a capture and its replays rewrite only d_insts
+  // between a capture and its replays rewrite only d_insts / d_jinsts
   HIP_TRY(hipStreamSynchronize(b->stream));
-  HIP_TRY(hipMemcpy(b->d_ginsts, v.data(), sizeof(WakeInst) * n, hipMemcpyHostToDevice));
+  if (!v.empty())
+    HIP_TRY(hipMemcpy(b->d_ginsts, v.data(), sizeof(WakeInst) * v.size(), hipMemcpyHostToDevice));
+  if (!vj.empty())
+    HIP_TRY(hipMemcpy(b->d_gjinsts, vj.data(), sizeof(WakeIons) * vj.size(), hipMemcpyHostToDevice));
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = launch_reset(b->d_ginsts, n, b->stream);
-  if (e == hipSuccess) e = batch_launch(b, v, grid, true);
+  hipError_t e = hipSuccess;
+  if (!v.empty()) e = launch_reset(b->d_ginsts, (int)v.size(), b->stream);
+  if (e == hipSuccess && !vj.empty()) e = launch_ions_reset(b->d_gjinsts, (int)vj.size(), b->stream);
+  if (e == hipSuccess) e = batch_launch(b, v, vj, grid, true);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {

@@ -54,7 +54,12 @@ struct WakeIons {
 
 hipError_t launch_ions_init(const WakeIons& J, const double* r0, const double* dr, const double* dens,
                             bool constants, hipStream_t s);
+// the marcher's LDS allowance on the current device (before its first launch there)
+hipError_t ions_prepare();
 hipError_t launch_ions_march(const WakeIons* d_insts, int n_insts, hipStream_t s);
+// back to slice 0 with both species at rest, for n records in device memory
+// (the records' own fields are read on the device: capturable)
+hipError_t launch_ions_reset(const WakeIons* d_insts, int n_insts, hipStream_t s);
 // ring state of species sp at the next slice to out [4][N] (rho, u_r, f_rho, f_u)
 hipError_t launch_ions_get_state(const WakeIons& J, int sp, double* out, hipStream_t s);
 // replace species sp's state (f_rho/f_u may be null: zero) and make `slice` the next slice

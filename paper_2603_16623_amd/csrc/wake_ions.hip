@@ -656,6 +656,30 @@ __global__ void ions_init_kernel(WakeIons J, const double* __restrict__ r0, cons
   }
 }
 
+// rest state of both species of instance blockIdx.y in buffer 0 (control
+// words reset), from its constants
+__global__ void ions_reset_kernel(const WakeIons* __restrict__ insts) {
+  const WakeIons& J = insts[blockIdx.y];
+  const int N = J.N;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    J.ctl[CTL_CUR] = 0;
+    J.ctl[CTL_BREAK] = -1;
+    J.ctl[CTL_NEXT] = 0;
+    J.ctl[CTL_FAULT] = 0;
+  }
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const double r = J.cst[IK_R0 * N + j];
+    for (int s = 0; s < 2; ++s) {
+      double* const st = J.st[0] + (size_t)s * IS_N * N;
+      st[IS_RHO * N + j] = r;
+      st[IS_U * N + j] = 0.0;
+      st[IS_FR * N + j] = 0.0;
+      st[IS_FU * N + j] = 0.0;
+      J.ord[(size_t)s * N + j] = j;
+    }
+  }
+}
+
 __global__ void ions_get_state_kernel(WakeIons J, int sp, double* __restrict__ out) {
   const int N = J.N;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -696,11 +720,18 @@ hipError_t launch_ions_init(const WakeIons& J, const double* r0, const double* d
   return hipGetLastError();
 }
 
+hipError_t ions_prepare() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&ions_march_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)IonsLds::bytes);
+}
+
 hipError_t launch_ions_march(const WakeIons* d_insts, int n_insts, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ions_march_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)IonsLds::bytes);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ions_march_kernel, dim3(n_insts), dim3(NT), IonsLds::bytes, s, d_insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_ions_reset(const WakeIons* d_insts, int n_insts, hipStream_t s) {
+  hipLaunchKernelGGL(ions_reset_kernel, dim3(8, n_insts), dim3(256), 0, s, d_insts);
   return hipGetLastError();
 }
 

@@ -83,6 +83,9 @@ int assign_tasks(std::vector<WakeInst>& v);
 // (already copied to d_insts, tasks assigned)
 hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts, int32_t* d_counter,
                         int dev, int grid_override, hipStream_t s);
+// a two-species context's record for a march of slices [first, first+count)
+// (its sources and beam table taken from I)
+WakeIons ions_record(const wake_ctx* c, int first, int count);
 // context creation / footprint with an explicit workgroup size
 int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom, void* hip_stream,
                const Layout& L);

@@ -289,9 +289,6 @@ def test_two_species_refusals(wk):
         s.wake_set_grid(64, 3.0)
     assert e.value.code == wk.WAKE_EINVAL
     with pytest.raises(wk.WakeError) as e:
-        wk.WakeBatch([s])
-    assert e.value.code == wk.WAKE_EINVAL
-    with pytest.raises(wk.WakeError) as e:
         s.wake_species_fields(2, 0)
     assert e.value.code == wk.WAKE_EINVAL
     assert s.threads() == 1024 and s.layout() == (1, 1)
@@ -312,3 +309,66 @@ def test_two_species_refusals(wk):
         wk.WakeSolver(r0, dr, 0.01, 10, [], ion_mass=1836.0)
     assert e.value.code == wk.WAKE_EINVAL
     s.close()
+
+
+def test_two_species_in_a_mixed_batch_and_graph_are_bitwise_alone(wk):
+    """A batch of two-species contexts (several ion masses and sizes) and
+    one-species contexts: every context's lineout, fields of both species
+    and final state are bitwise those of solving it alone, from an eager
+    batch solve in two pieces and from replays of the captured graph (with
+    eager work between replays)."""
+    say("two-species mixed batch")
+    insts = [(W.small_instance(7, n_rings=300, n_xi=120, n_peak=4.0, sigma_r=0.1, dxi=0.01), 1836.0),
+             (W.small_instance(12, n_rings=700, n_xi=90, n_peak=20.0, sigma_r=0.3, dxi=0.01), 1.0),
+             (W.small_instance(8, n_rings=257, n_xi=100, n_peak=1.0, laser=True, dxi=0.01), 25.0),
+             (W.small_instance(9, n_rings=2500, n_xi=60, n_peak=3.0, sigma_r=0.2, dxi=0.01,
+                               geometric=False), 100.0),
+             (W.small_instance(5, n_rings=400, n_xi=80, n_peak=2.0), None)]
+
+    def make(inst, m):
+        if m is None:
+            return wk.WakeSolver.from_instance(inst, record_stride=20)
+        return _solver(wk, inst, m, stride=20)
+
+    def result(s, inst, m):
+        out = {"lineout": s.wake_lineout()}
+        for sp in ((0, 1) if m is not None else (0,)):
+            for n in range(0, inst.n_xi, 20):
+                out[(sp, n)] = s.wake_species_fields(sp, n)
+            out[(sp, "state")] = s.wake_get_species_state(sp)
+        return out
+
+    def same(a, b):
+        for k in a:
+            if k == "lineout":
+                assert all(np.array_equal(x, y) for x, y in zip(a[k], b[k]))
+            else:
+                for q in a[k]:
+                    assert np.array_equal(np.asarray(a[k][q]), np.asarray(b[k][q])), (k, q)
+
+    alone = []
+    for inst, m in insts:
+        s = make(inst, m)
+        s.wake_solve(0, inst.n_xi)
+        alone.append(result(s, inst, m))
+        s.close()
+    solvers = [make(inst, m) for inst, m in insts]
+    b = wk.WakeBatch(solvers)
+    b.wake_batch_solve(50)
+    b.wake_batch_solve(-1)
+    b.wake_batch_sync()
+    for s, (inst, m), ref in zip(solvers, insts, alone):
+        assert s.wake_status() == (-1, inst.n_xi)
+        same(result(s, inst, m), ref)
+    b.wake_batch_capture()
+    for rep in range(3):
+        b.wake_batch_replay()
+        b.wake_batch_sync()
+        for s, (inst, m), ref in zip(solvers, insts, alone):
+            same(result(s, inst, m), ref)
+        solvers[0].wake_reset()                      # eager work between replays
+        solvers[0].wake_solve(0, 10)
+        solvers[0].wake_sync()
+    b.close()
+    for s in solvers:
+        s.close()
