@@ -46,6 +46,12 @@ ALG_FLOPS_PER_RING_SLICE = 280
 # history terms, w and w^ (48 B); write rho, u_r and the history (32 B); the
 # ion-table interpolation (32 B, cache resident).
 ALG_BYTES_PER_RING_SLICE = 48 + 32 + 32
+# Two-species (mobile ion) batch: hydrogen ions (proton over electron mass);
+# bytes the method must move per species-ring-slice: read rho, u_r and the
+# AB2 history (32 B) and the ring's constants w, w^, r0, 1/r0, ln r0 (dd) and
+# dr (56 B); write rho, u_r and the history (32 B).
+ION_MASS_H = 1836.15267
+ALG_BYTES_PER_SPECIES_RING_SLICE = 32 + 56 + 32
 # Slices each autotuner candidate marches (from slice 0: through the head of
 # the batch's drivers, whose centres lie at slices 200-667).
 TUNE_SLICES = 600
@@ -92,6 +98,18 @@ if job["kind"] == "batch":
         parts.append((inst.n_rings, n, inst.n_xi - 1))
         if time.time() - t0 >= job["budget"]:
             break
+elif job["kind"] == "ions":
+    from oracle.mobile_ions import TwoSpeciesOracle
+    inst = W.config3(n_inst=job["n_inst"], n_xi=job["n_xi"])[job["which"]]
+    o = TwoSpeciesOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, job["m_i"], inst.sources)
+    state = o.initial_state()
+    n = 0
+    t0 = time.time()
+    while n < inst.n_xi - 1 and time.time() - t0 < job["budget"]:
+        _, state = o.slice(n, state)
+        n += 1
+    done = 2 * inst.n_rings * n
+    parts.append((inst.n_rings, n, inst.n_xi - 1))
 else:
     inst = getattr(W, job["kind"])()
     o = RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
@@ -252,6 +270,10 @@ def main():
                     help="skip the large single instances (cooperative path)")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="skip the autotuner (tiling settings instead)")
+    ap.add_argument("--ions-inst", type=int, default=256,
+                    help="two-species (mobile hydrogen ion) batch: instances (0: skip)")
+    ap.add_argument("--ions-xi", type=int, default=1000, help="two-species batch: slices each")
+    ap.add_argument("--ions-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the "
@@ -411,6 +433,66 @@ def main():
         gbatch.close()
         for s in gsolvers:
             s.close()
+    if args.ions_inst > 0:
+        # the batch's instances (fewer, shorter windows) with mobile hydrogen
+        # ions: one workgroup per instance, replayed from a HIP graph
+        log("mobile ions batch")
+        iinsts = W.config3(n_inst=args.ions_inst, n_xi=args.ions_xi)
+        isolvers = [wake.WakeSolver(i.r0, i.dr, i.dxi, i.n_xi, i.sources, i.dens, stream=stream,
+                                    ion_mass=ION_MASS_H) for i in iinsts]
+        for s in isolvers:
+            s.wake_prepare()
+        ibatch = wake.WakeBatch(isolvers, stream=stream)
+        ibatch.wake_batch_capture()
+        ibatch.wake_batch_replay()
+        torch.cuda.synchronize()
+        iev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.ions_steps)]
+        ti = time.perf_counter()
+        for a, b in iev:
+            a.record()
+            ibatch.wake_batch_replay()
+            b.record()
+            log("ions step done")
+        torch.cuda.synchronize()
+        iwall = (time.perf_counter() - ti) / args.ions_steps
+        ikern = float(np.mean([a.elapsed_time(b) for a, b in iev])) / 1e3
+        iwork = sum(2 * i.ring_slices for i in iinsts)          # species-ring-slices
+        ibrk = sum(1 for s in isolvers if s.wake_status()[0] >= 0)
+        ibatch.close()
+        for s in isolvers:
+            s.close()
+        iach = ALG_BYTES_PER_SPECIES_RING_SLICE * iwork / ikern
+        iload = f"ions-batched-{args.ions_inst}x[1000,8000]rings-x{args.ions_xi}slices"
+        itr = read_traffic(os.path.join(ROOT, "profiles", "ions_march_kernel_traffic.txt"),
+                           "ions_march_kernel")
+        itraffic = None
+        if itr is not None and itr.get("workload") == iload:
+            itraffic = float(itr["fetch_bytes_per_dispatch"]) + float(itr["write_bytes_per_dispatch"])
+        out["mobile_ions"] = dict(
+            workload=f"batched-{args.ions_inst}x[1000,8000]rings-x{args.ions_xi}slices, electrons "
+                     f"and mobile hydrogen ions (m_i = {ION_MASS_H})",
+            ion_mass=ION_MASS_H, steps=args.ions_steps, ms_per_step=iwall * 1e3,
+            value=iwork / iwall, unit="species-ring-slice updates/s",
+            ring_slice_updates_per_s=iwork / 2 / iwall, breakdowns=ibrk,
+            roofline=dict(bound="hbm", achieved=iach / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                          frac=iach / PEAK_HBM, traffic=itraffic,
+                          traffic_source=None if itraffic is None else
+                          "replayed: rocprofv3 FETCH_SIZE and WRITE_SIZE of one dispatch of this "
+                          "workload on the current two-species sources "
+                          "(profiles/ions_march_kernel_traffic.txt, copy-calibrated)",
+                          traffic_B_per_species_ring_slice=None if itraffic is None else itraffic / iwork,
+                          kernel="ions_march_kernel", kernel_ms=ikern * 1e3,
+                          alg_bytes_per_species_ring_slice=ALG_BYTES_PER_SPECIES_RING_SLICE))
+        if not args.no_cpu:
+            log("cpu baseline of the two-species oracle (one core)")
+            r = _run_workers([dict(kind="ions", n_inst=args.ions_inst, n_xi=args.ions_xi, which=0,
+                                   m_i=ION_MASS_H, budget=args.cpu_budget)], args.cpu_budget)[0]
+            n_r, n_s, n_w = r["parts"][0]
+            out["mobile_ions"]["cpu_baseline"] = dict(
+                value=r["done"] / (r["t1"] - r["t0"]), unit="species-ring-slice updates/s", cores=1,
+                kind="oracle", sample=f"two-species oracle, instance 0 of the batch ({n_r} rings), "
+                                      f"slices 0-{n_s} of {n_w + 1}, {r['t1'] - r['t0']:.1f} s")
     if args.served_seconds > 0:
         # capacity: sustained ring-slice rate of the server on the request mix
         # while it is saturated: a backlog of about 1000 requests submitted at

@@ -7,10 +7,12 @@
 //
 // Barrier.  Each member publishes a pack (agent-scope atomic stores, which
 // write through to the point where all XCDs meet), waits for those stores to
-// complete, counts itself in, waits until every member of this round has, and
-// reads all packs with agent-scope atomic loads.  Packs alternate between two
-// buffers by round; a member writes buffer b again only two rounds later,
-// when every member has finished reading it.  The per-slice exchanges carry
+// complete and then stores the round number as the pack's last word (its
+// stamp); thread m of every member polls member m's stamp until it reads the
+// round and then reads that pack with agent-scope atomic loads.  There is no
+// shared arrival counter.  Packs alternate between two buffers by round; a
+// member writes buffer b again only two rounds later, when every member has
+// read it (it could not have passed the round in between otherwise).  The per-slice exchanges carry
 // nothing but their packs and take no cache maintenance.  The fenced form,
 // used by the order fix-up, also hands over plain device-memory data (keys,
 // permutation, ring state that changes member): a release fence before the

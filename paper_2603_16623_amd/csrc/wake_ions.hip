@@ -157,11 +157,12 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
 
     // ---- order of each species ----
     int bad_order = 0;
+    #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const double* rho_s = stc + (size_t)(s * IS_N + IS_RHO) * N;
       int32_t* const ord = I.ord + (size_t)s * N;
       double* const sr = s_r + s * NMAX;
-      #pragma unroll 1
+      #pragma unroll 4
       for (int k = 0; k < cnt; ++k) {
         const int p = p0 + k;
         const int id = ord[p];
@@ -181,15 +182,30 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         ++fixups;
       }
       int32_t* const sid = I.sid + (size_t)s * S;
-      #pragma unroll 1
+      double* const wk = I.work + (size_t)s * IW_N * S;
+      const double* const st_s = stc + (size_t)s * IS_N * N;
+      // each ring's constants and state into the slots of its position (all
+      // loads of a batch of positions issued before any is used)
+      #pragma unroll 4
       for (int k = 0; k < cnt; ++k) {
         const int p = p0 + k;
+        const unsigned sl = k * NT + tid;
         int id = s_id[p];
         // a padding key among the first N positions: a radius that is not a
         // finite number (state injected from device memory) -- stop there
         if (id >= N) { id = 0; bad_order = 1; }
-        sid[k * NT + tid] = id;
+        sid[sl] = id;
         if (resort) ord[p] = id;
+        wk[IW_W * S + sl] = cst[IK_W * N + id];
+        wk[IW_WH * S + sl] = cst[IK_WH * N + id];
+        wk[IW_R0 * S + sl] = cst[IK_R0 * N + id];
+        wk[IW_IR0 * S + sl] = cst[IK_IR0 * N + id];
+        wk[IW_L0H * S + sl] = cst[IK_LNH * N + id];
+        wk[IW_L0L * S + sl] = cst[IK_LNL * N + id];
+        wk[IW_DR * S + sl] = cst[IK_DR * N + id];
+        wk[IW_U * S + sl] = st_s[IS_U * N + id];
+        wk[IW_FRP * S + sl] = st_s[IS_FR * N + id];
+        wk[IW_FUP * S + sl] = st_s[IS_FU * N + id];
       }
       __syncthreads();              // s_id is the next species' too
     }
@@ -197,18 +213,16 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     // ---- own sums: psi and d_rho psi of each species at its rings ----
     dd sw[2], swl[2];
     for (int s = 0; s < 2; ++s) {
-      const int32_t* sid = I.sid + (size_t)s * S;
       double* const wk = I.work + (size_t)s * IW_N * S;
       const double* sr = s_r + s * NMAX;
       sw[s] = dd_make(0.0);
       swl[s] = dd_make(0.0);
-      #pragma unroll 1
+      #pragma unroll 2
       for (int k = 0; k < cnt; ++k) {
         const unsigned sl = k * NT + tid;
-        const int id = sid[sl];
         const double r = sr[p0 + k];
-        const double w = cst[IK_W * N + id], r0 = cst[IK_R0 * N + id], ir0 = cst[IK_IR0 * N + id];
-        const dd lnr = dd_add_d({cst[IK_LNH * N + id], cst[IK_LNL * N + id]}, log1p_fast((r - r0) * ir0));
+        const double w = wk[IW_W * S + sl], r0 = wk[IW_R0 * S + sl], ir0 = wk[IW_IR0 * S + sl];
+        const dd lnr = dd_add_d({wk[IW_L0H * S + sl], wk[IW_L0L * S + sl]}, log1p_fast((r - r0) * ir0));
         wk[IW_LNH * S + sl] = lnr.hi;
         wk[IW_LNL * S + sl] = lnr.lo;
         sw[s] = dd_add_d(sw[s], w);
@@ -220,23 +234,23 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         Pack<4>{{sw[0].hi, sw[0].lo, sw[1].hi, sw[1].lo}}, Pack<4>{{0.0, 0.0, 0.0, 0.0}}, DD2Op(),
         Pack<4>{{swl[0].hi, swl[0].lo, swl[1].hi, swl[1].lo}}, Pack<4>{{0.0, 0.0, 0.0, 0.0}}, DD2Op(),
         s_scan, exP, totP, exS, totS);
+    #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const double q = s ? 1.0 : -1.0;
-      const int32_t* sid = I.sid + (size_t)s * S;
       double* const wk = I.work + (size_t)s * IW_N * S;
       double* const tb = I.tab + (size_t)s * IT_N * S;
       double* const sc = s_sc + SC_N * s;
       const double* sr = s_r + s * NMAX;
-      const dd Q = {totP.v[2 * s], totP.v[2 * s + 1]};
-      dd below = {exP.v[2 * s], exP.v[2 * s + 1]};
-      dd rest = dd_add({exS.v[2 * s], exS.v[2 * s + 1]}, swl[s]);   // sum over positions >= p
+      const dd Q = s ? dd{totP.v[2], totP.v[3]} : dd{totP.v[0], totP.v[1]};
+      dd below = s ? dd{exP.v[2], exP.v[3]} : dd{exP.v[0], exP.v[1]};
+      // sum over positions >= p
+      dd rest = dd_add(s ? dd{exS.v[2], exS.v[3]} : dd{exS.v[0], exS.v[1]}, s ? swl[1] : swl[0]);
       #pragma unroll 1
       for (int k = 0; k < cnt; ++k) {
         const unsigned sl = k * NT + tid;
         const int p = p0 + k;
-        const int id = sid[sl];
         const double r = sr[p];
-        const double w = cst[IK_W * N + id], wh = cst[IK_WH * N + id];
+        const double w = wk[IW_W * S + sl], wh = wk[IW_WH * S + sl];
         const dd lnr = {wk[IW_LNH * S + sl], wk[IW_LNL * S + sl]};
         const dd above = dd_sub(rest, dd_mul_d(lnr, w));
         // psi = -q ((sum_{k<i} w_k + w_i) ln rho_i + sum_{k>i} w_k ln rho_k)
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         if (p == N - 1) {
           // outer edge: the outermost ring plus half its initial extent, and
           // the exterior field there (-q Q ln r, -q Q / r)
-          const double edge = r + cst[IK_DR * N + id] / 2.0;
+          const double edge = r + wk[IW_DR * S + sl] / 2.0;
           const dd lne = dd_add_d(lnr, log1p_fast((edge - r) / r));
           dd eps = dd_mul(Q, lne);
           dd edp = dd_div_d(Q, edge);
@@ -266,7 +280,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         }
       }
       if (tid == 0) {
-        dd pa = {totS.v[2 * s], totS.v[2 * s + 1]};
+        dd pa = s ? dd{totS.v[2], totS.v[3]} : dd{totS.v[0], totS.v[1]};
         if (q > 0.0) pa = dd_neg(pa);
         sc[SC_PAH] = pa.hi;
         sc[SC_PAL] = pa.lo;
@@ -282,13 +296,13 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     const int bm = I.nb ? I.boff[n + 1] - bt0 : 0;
     const double* const br = I.br + bt0;
     const double* const bcq = I.bcum + bt0;
-    dd szc[2];
+    dd szc0 = dd_make(0.0), szc1 = dd_make(0.0);
+    #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const int o = s ^ 1;
       const double q = s ? 1.0 : -1.0, m = s ? m_ion : 1.0;
       const double qm = q / m, qq2 = (q * q) / (2.0 * m * m);
       const double qo = o ? 1.0 : -1.0;
-      const int32_t* sid = I.sid + (size_t)s * S;
       double* const wk = I.work + (size_t)s * IW_N * S;
       const double* tb = I.tab + (size_t)s * IT_N * S;
       const double* tbo = I.tab + (size_t)o * IT_N * S;
@@ -298,16 +312,14 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
       const double* sco = s_sc + SC_N * o;
       const double edge_o = sco[SC_EDGE];
       const dd Qo = {sco[SC_QH], sco[SC_QL]};
-      const double* u_s = stc + (size_t)(s * IS_N + IS_U) * N;
-      szc[s] = dd_make(0.0);
+      dd szc = dd_make(0.0);
       int lo = 0, blo = 0;
       #pragma unroll 1
       for (int k = 0; k < cnt; ++k) {
         const unsigned sl = k * NT + tid;
-        const int id = sid[sl];
         const double r = sr[p0 + k];
-        const double u = u_s[id];
-        const double w = cst[IK_W * N + id];
+        const double u = wk[IW_U * S + sl];
+        const double w = wk[IW_W * S + sl];
         const dd lnr = {wk[IW_LNH * S + sl], wk[IW_LNL * S + sl]};
         lo = count_below(ro, lo, N, r, k > 0);
         Interval iv;
@@ -366,7 +378,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         const double gm = (1.0 + u * u + pb * pb + qq2 * a2) / (2.0 * pb);
         if (!(pb > 0.0) || !isfinite(pb)) bad = 1;
         const double c = q * u / (r * pb);
-        szc[s] = dd_add_d(szc[s], w * c);
+        szc = dd_add_d(szc, w * c);
         wk[IW_PSI * S + sl] = psi;
         wk[IW_DPSI * S + sl] = dpsi;
         wk[IW_PB * S + sl] = pb;
@@ -374,44 +386,43 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         wk[IW_BB * S + sl] = lam / r;
         wk[IW_A2 * S + sl] = a2;
         wk[IW_DA2 * S + sl] = da2;
-        wk[IW_U * S + sl] = u;
         wk[IW_T * S + sl] = iv.t;
       }
+      if (s) szc1 = szc; else szc0 = szc;
     }
     Pack<4> dzs, dzt;
-    dzs = block_suffix<NT, 4>(Pack<4>{{szc[0].hi, szc[0].lo, szc[1].hi, szc[1].lo}},
+    dzs = block_suffix<NT, 4>(Pack<4>{{szc0.hi, szc0.lo, szc1.hi, szc1.lo}},
                               Pack<4>{{0.0, 0.0, 0.0, 0.0}}, DD2Op(), s_scan, dzt);
     // own d_zeta psi at each ring: the rings outside with w, the ring itself
     // with w - w^
+    #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const double q = s ? 1.0 : -1.0;
-      const int32_t* sid = I.sid + (size_t)s * S;
       const double* wk = I.work + (size_t)s * IW_N * S;
       double* const tb = I.tab + (size_t)s * IT_N * S;
       const double* sr = s_r + s * NMAX;
-      dd above = {dzs.v[2 * s], dzs.v[2 * s + 1]};
+      dd above = s ? dd{dzs.v[2], dzs.v[3]} : dd{dzs.v[0], dzs.v[1]};
       #pragma unroll 1
       for (int k = cnt - 1; k >= 0; --k) {
         const unsigned sl = k * NT + tid;
-        const int id = sid[sl];
         const double r = sr[p0 + k];
-        const double w = cst[IK_W * N + id], wh = cst[IK_WH * N + id];
+        const double w = wk[IW_W * S + sl], wh = wk[IW_WH * S + sl];
         const double c = q * wk[IW_U * S + sl] / (r * wk[IW_PB * S + sl]);
         tb[IT_DZ * S + sl] = dd_round(dd_add_d(above, (w - wh) * c));
         above = dd_add_d(above, w * c);
       }
       if (tid == 0) {
-        s_sc[SC_N * s + SC_DZH] = dzt.v[2 * s];
-        s_sc[SC_N * s + SC_DZL] = dzt.v[2 * s + 1];
+        s_sc[SC_N * s + SC_DZH] = s ? dzt.v[2] : dzt.v[0];
+        s_sc[SC_N * s + SC_DZL] = s ? dzt.v[3] : dzt.v[1];
       }
     }
     __syncthreads();
 
     // ---- gather d_zeta psi; electrons: coefficients and chunk transfer ----
     Pack<4> G = mat_ident();
+    #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const int o = s ^ 1;
-      const int32_t* sid = I.sid + (size_t)s * S;
       double* const wk = I.work + (size_t)s * IW_N * S;
       const double* tb = I.tab + (size_t)s * IT_N * S;
       const double* tbo = I.tab + (size_t)o * IT_N * S;
@@ -431,9 +442,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         }
         wk[IW_DZ * S + sl] = dz;
         if (s == 0) {
-          const int id = sid[sl];
           const double r = sr[p0 + k];
-          const double w = cst[IK_W * N + id];
+          const double w = wk[IW_W * S + sl];
           const double irho = rcp_nr(r);
           const Local L = local_of(irho, wk[IW_U * S + sl], w, wk[IW_PSI * S + sl], wk[IW_A2 * S + sl]);
           double B, Cc, sa, sb;
@@ -492,14 +502,12 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     const double bN = et.v[0] * iW;           // b_N = E_N / W (a_N = 0)
     {
       // x_{i-1} = (h_{i-1} E_{i-1} - g_{i-1} D_{i-1}) / W and B^(p) at ring i
-      const int32_t* sid = I.sid;
       double* const tbe = I.tab;
       double ha = hx.v[1], hb = hx.v[3];
       double D = dsf.v[0];
       #pragma unroll 1
       for (int k = cnt - 1; k >= 0; --k) {
         const unsigned sl = k * NT + tid;
-        const int id = sid[sl];
         const double r = sre[p0 + k];
         const double irho = rcp_nr(r);
         D += wke[IW_SA * S + sl] * hb - wke[IW_SB * S + sl] * ha;
@@ -511,7 +519,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         const double ga = wke[IW_GA * S + sl], gb = wke[IW_GB * S + sl];
         const double a = (ha * E - ga * D) * iW;
         const double b = (hb * E - gb * D) * iW;
-        const double w = cst[IK_W * N + id], wh = cst[IK_WH * N + id];
+        const double w = wke[IW_W * S + sl], wh = wke[IW_WH * S + sl];
         const double bp = a * r + b * irho + (wh / w) * wke[IW_C * S + sl];
         tbe[IT_BP * S + sl] = bp;
         wke[IW_BT * S + sl] = wke[IW_BB * S + sl] + bp;
@@ -547,14 +555,13 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     const bool do_push = n < I.n_xi - 1;
     const bool rec_snap = I.stride > 0 && (n % I.stride) == 0;
     const bool rec_last = n == end - 1;
+    #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const double q = s ? 1.0 : -1.0, m = s ? m_ion : 1.0;
       const double qm = q / m, q24 = (q * q) / (4.0 * m * m);
       const int32_t* sid = I.sid + (size_t)s * S;
       const double* wk = I.work + (size_t)s * IW_N * S;
       const double* sr = s_r + s * NMAX;
-      const double* frp = stc + (size_t)(s * IS_N + IS_FR) * N;
-      const double* fup = stc + (size_t)(s * IS_N + IS_FU) * N;
       double* const rn_s = stn + (size_t)(s * IS_N + IS_RHO) * N;
       double* const un_s = stn + (size_t)(s * IS_N + IS_U) * N;
       double* const fr_s = stn + (size_t)(s * IS_N + IS_FR) * N;
@@ -584,7 +591,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
           const double f_r = u / pb;
           const double f_u = -(qm * (gm * dpsi / pb - bt) + q24 * da2 / pb);
           double pr = f_r, pu = f_u;
-          if (n > 0) { pr = frp[id]; pu = fup[id]; }
+          if (n > 0) { pr = wk[IW_FRP * S + sl]; pu = wk[IW_FUP * S + sl]; }
           double rn = r + dxi * (1.5 * f_r - 0.5 * pr);
           double un = u + dxi * (1.5 * f_u - 0.5 * pu);
           double sr_ = f_r, su = f_u;

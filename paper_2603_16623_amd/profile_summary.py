@@ -1,8 +1,12 @@
 """Summaries of rocprofv3 output for the march kernel (markdown, a few KB).
 
-    python -m paper_2603_16623_amd.profile_summary trace DIR TITLE COMMAND > summary.md
-    python -m paper_2603_16623_amd.profile_summary traffic MARCH_DIR COPY_DIR COPY_MIB WORKLOAD > traffic.txt
+    python -m paper_2603_16623_amd.profile_summary trace DIR TITLE COMMAND [KERNEL] > summary.md
+    python -m paper_2603_16623_amd.profile_summary traffic MARCH_DIR COPY_DIR COPY_MIB WORKLOAD [KERNEL] > traffic.txt
     python -m paper_2603_16623_amd.profile_summary sq DIR RING_SLICES > sq.txt
+
+KERNEL is the marcher whose dispatches are summarised: wake_march_kernel (the
+default; one species over immobile ions) or ions_march_kernel (electrons and
+mobile ions).
 
 `trace`: DIR holds the CSV files of `rocprofv3 --kernel-trace --stats --output-format csv`;
 prints the march dispatches and the top kernels.
@@ -24,12 +28,14 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MARCH_SOURCES = ["wake_march.hip", "wake_device.h", "wake_common.h", "wake_cluster.h"]
+MARCH_SOURCES = ["wake_march.hip", "wake_device.h", "wake_common.h", "wake_cluster.h", "wake_ring.h"]
+ION_SOURCES = ["wake_ions.hip", "wake_ions.h", "wake_ring.h", "wake_device.h", "wake_common.h"]
+SOURCES = {"wake_march_kernel": MARCH_SOURCES, "ions_march_kernel": ION_SOURCES}
 
 
-def source_digest() -> str:
+def source_digest(kernel: str = "wake_march_kernel") -> str:
     h = hashlib.sha256()
-    for f in MARCH_SOURCES:
+    for f in SOURCES[kernel]:
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -43,11 +49,11 @@ def _rows(pattern):
     return out
 
 
-def trace(d, title, command, per_dispatch=True):
+def trace(d, title, command, per_dispatch=True, kernel="wake_march_kernel"):
     trace_rows = _rows(os.path.join(d, "**", "*kernel_trace.csv")) if per_dispatch else []
     stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
     print(f"# {title}\n\nCommand (repository root as $R):\n\n    {command}\n")
-    march = [r for r in trace_rows if "wake_march_kernel" in r.get("Kernel_Name", "")]
+    march = [r for r in trace_rows if kernel in r.get("Kernel_Name", "")]
     if march:
         print("March dispatches in order:\n")
         print("| dispatch | variant | duration ms | grid threads | workgroup | arch VGPR | acc VGPR | SGPR | LDS B | scratch B |")
@@ -81,16 +87,17 @@ def _counter(d, name, kernel_sub):
     return vals
 
 
-def traffic(march_dir, copy_dir, copy_mib, workload):
+def traffic(march_dir, copy_dir, copy_mib, workload, kernel="wake_march_kernel"):
     copy_bytes = float(copy_mib) * (1 << 20)
     out = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         cal = _counter(os.path.join(copy_dir, c), c, "copyBuffer")
-        m = _counter(os.path.join(march_dir, c), c, "wake_march_kernel")
+        m = _counter(os.path.join(march_dir, c), c, kernel)
         scale = copy_bytes / (cal[-1] * 1024.0)
         out[c] = (m[-1] * 1024.0 * scale, scale, m[-1])
     print(f"workload: {workload}")
-    print(f"source_digest: {source_digest()}")
+    print(f"kernel: {kernel}")
+    print(f"source_digest: {source_digest(kernel)}")
     print(f"fetch_bytes_per_dispatch: {out['FETCH_SIZE'][0]:.6e}")
     print(f"write_bytes_per_dispatch: {out['WRITE_SIZE'][0]:.6e}")
     print(f"fetch_counter_KiB: {out['FETCH_SIZE'][2]:.6e}  (copy calibration x{out['FETCH_SIZE'][1]:.4f})")
@@ -124,7 +131,7 @@ def sq(d, ring_slices):
         print(f"LDS instructions per ring-slice: {tot['SQ_INSTS_LDS'] / rs:.3f}")
 
 
-def read_traffic(path):
+def read_traffic(path, kernel="wake_march_kernel"):
     """Traffic figures of a summary file, if it belongs to the current sources."""
     if not os.path.exists(path):
         return None
@@ -134,17 +141,19 @@ def read_traffic(path):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
-    if kv.get("source_digest") != source_digest():
+    if kv.get("source_digest") != source_digest(kernel):
         return None
     return kv
 
 
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
-        trace(sys.argv[2], sys.argv[3], sys.argv[4])
+        trace(sys.argv[2], sys.argv[3], sys.argv[4],
+              kernel=sys.argv[5] if len(sys.argv) > 5 else "wake_march_kernel")
     elif sys.argv[1] == "stats":       # kernels by total time only (many dispatches)
         trace(sys.argv[2], sys.argv[3], sys.argv[4], per_dispatch=False)
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
+                sys.argv[6] if len(sys.argv) > 6 else "wake_march_kernel")
     elif sys.argv[1] == "sq":
         sq(sys.argv[2], sys.argv[3])
