@@ -137,7 +137,12 @@ int wake_prepare_noalloc(wake_ctx *ctx, void *table, int64_t table_bytes);
  * plasma_particle_motion_1-4).  first_slice must equal the context's next slice
  * (0 after create, the end of the previous solve, or the slice given to
  * wake_set_state).  A breakdown stops the march at its slice and is
- * reported by wake_status / wake_fields. */
+ * reported by wake_status / wake_fields.  With WAKE_TRACE set in the
+ * environment ("1" or "stderr": standard error; otherwise a file name,
+ * appended to) the solve is traced: one launch per slice, synchronous, and
+ * one line per slice with its GPU time (HIP events), whether it began with
+ * an order fix-up and the breakdown slice; the results are bitwise those of
+ * an untraced solve. */
 int wake_solve(wake_ctx *ctx, int32_t first_slice, int32_t n_slices);
 
 /* Fields at the rings of one solved slice, indexed by ring id: psi,

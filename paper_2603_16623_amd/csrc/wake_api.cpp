@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -669,6 +671,46 @@ static int launch_one(wake_ctx* c, int first, int count) {
   return WAKE_OK;
 }
 
+// Per-slice trace of a solve (WAKE_TRACE set in the environment: "1" or
+// "stderr" writes to stderr, anything else names a file appended to): the
+// solve marches one slice per launch, each timed with HIP events, and one
+// line per slice gives the context, slice, GPU time, whether the slice began
+// with an order fix-up and the breakdown slice.  Results are bitwise those of
+// an untraced solve (launch splits do not change them).  Synchronous.
+static int traced_solve(wake_ctx* c, int first, int count, const char* where) {
+  FILE* f = (!std::strcmp(where, "1") || !std::strcmp(where, "stderr")) ? stderr : std::fopen(where, "a");
+  if (!f) return WAKE_EINVAL;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int r = WAKE_OK;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  for (int n = first; he == hipSuccess && r == WAKE_OK && n < first + count; ++n) {
+    unsigned long long fx0 = 0, fx1 = 0;
+    he = hipMemcpy(&fx0, c->I.cnt + CNT_FIXUPS, sizeof(fx0), hipMemcpyDeviceToHost);
+    if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+    if (he != hipSuccess) break;
+    r = c->two_species ? ions_launch(c, n, 1) : launch_one(c, n, 1);
+    if (r != WAKE_OK) break;
+    he = hipEventRecord(e1, c->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    int32_t ctl[CTL_NWORDS];
+    if (he == hipSuccess) he = hipMemcpy(ctl, c->I.ctl, sizeof(ctl), hipMemcpyDeviceToHost);
+    if (he == hipSuccess) he = hipMemcpy(&fx1, c->I.cnt + CNT_FIXUPS, sizeof(fx1), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) break;
+    std::fprintf(f, "wake_trace ctx=%p rings=%d slice=%d us=%.2f fixup=%llu breakdown=%d\n", (void*)c,
+                 c->I.N, n, ms * 1e3, fx1 - fx0, ctl[CTL_BREAK]);
+    if (ctl[CTL_BREAK] >= 0) break;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (f != stderr) std::fclose(f);
+  else std::fflush(f);
+  if (he != hipSuccess) return dev_err(he);
+  return r;
+}
+
 extern "C" int wake_solve(wake_ctx* c, int32_t first, int32_t count) {
   if (!c) return WAKE_EINVAL;
   if (count < 0 || first < 0 || (int64_t)first + count > c->I.n_xi) return WAKE_EINVAL;
@@ -679,7 +721,11 @@ extern "C" int wake_solve(wake_ctx* c, int32_t first, int32_t count) {
   if (r != WAKE_OK) return r;
   r = wake_prepare(c);
   if (r != WAKE_OK) return r;
-  r = c->two_species ? ions_launch(c, first, count) : launch_one(c, first, count);
+  const char* trace = std::getenv("WAKE_TRACE");
+  if (trace && *trace)
+    r = traced_solve(c, first, count, trace);
+  else
+    r = c->two_species ? ions_launch(c, first, count) : launch_one(c, first, count);
   if (r != WAKE_OK) return r;
   c->next = first + count;
   return WAKE_OK;

@@ -126,3 +126,51 @@ def test_served_admission_respects_the_footprint_budget(wk):
                     done += 1
         assert steps < 200
     srv.close()
+
+
+def test_breakdown_in_a_served_mix(wk):
+    """One request whose beam drives psibar below zero (a wide, dense
+    positively charged driver pulling the electrons in) is served among
+    others: it comes back WAKE_EBREAKDOWN at the oracle's breakdown slice
+    with its lineout up to there as alone, and every other result is
+    bitwise its result alone."""
+    from oracle.wake_oracle import RingOracle
+    r0, dr = W.geometric_rings(400, 2e-3, 4.0)
+    bad = W.Instance("breakdown-400x150", r0, dr, 0.02, 150, [W.GaussianBeam(+1.0, 20.0, 1.5, 0.5, 1.5)])
+    want = RingOracle(bad.r0, bad.dr, bad.dxi, bad.n_xi, bad.sources).run(record_stride=0)["breakdown"]
+    assert want == 91
+    insts = _mix(62, [(300, 90), (1500, 60), (777, 130), (2100, 75)])
+    insts.insert(2, bad)
+    _say("served mix with a breakdown")
+    ref = [_alone(wk, inst) if inst is not bad else None for inst in insts]
+    alone = wk.WakeSolver.from_instance(bad)
+    alone.wake_solve(0, bad.n_xi)
+    assert alone.wake_status()[0] == want
+    bad_psi, bad_ez = alone.wake_lineout()
+    alone.close()
+    srv = wk.WakeServer(device_bytes=8 << 30, slices_per_step=23)
+    tickets = {srv.submit_instance(inst): i for i, inst in enumerate(insts)}
+    results = {}
+    steps = 0
+    while len(results) < len(insts):
+        srv.step()
+        steps += 1
+        assert steps < 5000
+        for t, i in list(tickets.items()):
+            r = srv.result(t)
+            if r is not None:
+                results[i] = r
+                del tickets[t]
+    for i, r in results.items():
+        if insts[i] is bad:
+            assert r["status"] == wk.WAKE_EBREAKDOWN and r["breakdown"] == want, (r["status"], r["breakdown"])
+            assert np.array_equal(r["psi_axis"][:want], bad_psi[:want])
+            assert np.array_equal(r["ez_axis"][:want], bad_ez[:want])
+            continue
+        assert r["status"] == 0, i
+        for q in FIELDS:
+            assert np.array_equal(r[q], ref[i][q]), (i, q)
+        assert np.array_equal(r["psi_axis"], ref[i]["psi_axis"]), i
+    st = srv.stats()
+    assert st["active"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+    srv.close()
