@@ -173,9 +173,37 @@ int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, 
  * served form (wake_server_*) has no grid.  Synchronous. */
 int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 
-/* Grid fields of one solved slice [n_r each], slice-major storage read out
- * per slice (slice = -1: the slice before the context's next slice, i.e.
- * the last slice of the most recent solve).  WAKE_ESTATE without a grid,
+/* Field grid at radii the caller gives (Sec. "Key algorithmic adjustments":
+ * the sums give the plasma fields at any radius, so they can be sampled with
+ * any radial resolution; the node rule is wake_set_grid's).  slice_off NULL:
+ * the same n_nodes radii at every slice, strictly increasing, > 0, finite,
+ * n_nodes <= 2^20.  Otherwise slice_off holds n_xi + 1 offsets (slice_off[0]
+ * = 0, non-decreasing, slice_off[n_xi] = n_nodes <= 2^28, at most 2^20 per
+ * slice) and slice n takes radii[slice_off[n] .. slice_off[n+1]), ascending
+ * within the slice (equal radii allowed), > 0, finite.  n_nodes = 0 removes
+ * the grid.  Same call order, memory and errors as wake_set_grid; radii
+ * and offsets are copied.  Synchronous. */
+int wake_set_grid_radii(wake_ctx *ctx, int64_t n_nodes, const double *radii,
+                        const int64_t *slice_off);
+
+/* Field grid at the beam particles' own radii: slice n's nodes are the
+ * entries of slice n in the beam table (every macroparticle added with
+ * wake_add_beam that deposits on that slice node, at its radius, ascending;
+ * a particle between two slice nodes appears at both), so the fields reach
+ * the particles with no radial grid (the direct beam-plasma coupling Sec.
+ * "Integration into Wake-T" names).  Prepares the context (wake_prepare) if
+ * it is not yet.  WAKE_EINVAL without particles; otherwise as
+ * wake_set_grid.  Synchronous. */
+int wake_set_grid_beam(wake_ctx *ctx);
+
+/* Node count of a slice's grid (uniform and fixed grids: every slice the
+ * same) and, if radii is not NULL, their radii (host memory, count
+ * doubles).  WAKE_ESTATE without a grid.  Synchronizes. */
+int wake_grid_nodes(wake_ctx *ctx, int32_t slice, int64_t *count, double *radii);
+
+/* Grid fields of one solved slice [the slice's node count each, in node
+ * order], read out per slice (slice = -1: the slice before the context's
+ * next slice, i.e. the last slice of the most recent solve).  WAKE_ESTATE without a grid,
  * for a slice at or after the next slice, or before the slice of the last
  * wake_set_state (not marched from the current state); WAKE_EBREAKDOWN at
  * or after a breakdown.  NULL outputs are skipped.  Synchronizes the

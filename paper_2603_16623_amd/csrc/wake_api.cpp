@@ -814,35 +814,187 @@ extern "C" int wake_species_fields(wake_ctx* c, int32_t species, int32_t slice, 
   return fields_of(c, c->J.snap[1], c->J.last[1], slice, psi, erbt, ez, bt, rho, ur, dev);
 }
 
-extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
-  if (!c || c->two_species) return WAKE_EINVAL;
-  if (n_r < 0 || n_r > (1 << 20) || (n_r > 0 && !finite_pos(r_max))) return WAKE_EINVAL;
-  if (c->next != 0 || c->batches > 0) return WAKE_ESTATE;
-  HIP_TRY(hipSetDevice(c->device));
-  int r = drain(c);
-  if (r != WAKE_OK) return r;
+// Drop a context's field grid (device memory released).
+static int grid_clear(wake_ctx* c) {
   WakeInst& I = c->I;
   if (c->grid_mem) {
     HIP_TRY(hipFree(c->grid_mem));
     c->grid_mem = nullptr;
   }
+  c->grid_off_h.clear();
   I.grid_n = 0;
   I.grid_dr = 0.0;
   I.grid = nullptr;
   I.grid_tab = nullptr;
   I.grid_scr = nullptr;
-  if (n_r == 0) return WAKE_OK;
-  const size_t nf = (size_t)4 * n_r * (size_t)I.n_xi;
-  HIP_TRY(hipMalloc(&c->grid_mem, sizeof(double) * (nf + (WAKE_GRID_TAB + 8) * (size_t)n_r)));
-  I.grid_n = n_r;
-  I.grid_dr = r_max / (double)n_r;
+  I.grid_rad = nullptr;
+  I.grid_off = nullptr;
+  return WAKE_OK;
+}
+
+// Common set-up of a field grid: n_fields slice fields (4 doubles per node
+// and slice), n_tab node records, hand-over scratch for max_nodes nodes of a
+// slice, extra doubles for radii and int32 words for offsets copied in.
+// Unmarched slices read as NaN.  The caller fills the radii / offsets and
+// then calls grid_finish.
+static int grid_alloc(wake_ctx* c, size_t n_fields, size_t n_tab, int max_nodes, size_t n_rad,
+                      size_t n_off, double** rad, int32_t** off) {
+  WakeInst& I = c->I;
+  const size_t nd = 4 * n_fields + WAKE_GRID_TAB * n_tab + 8 * (size_t)max_nodes + n_rad + (n_off + 1) / 2;
+  HIP_TRY(hipMalloc(&c->grid_mem, sizeof(double) * nd));
+  I.grid_n = max_nodes;
   I.grid = c->grid_mem;
-  I.grid_tab = c->grid_mem + nf;
-  I.grid_scr = c->grid_mem + nf + WAKE_GRID_TAB * (size_t)n_r;
-  // slices not marched read as NaN (all-ones bytes)
-  HIP_TRY(hipMemsetAsync(c->grid_mem, 0xFF, sizeof(double) * nf, c->stream));
-  HIP_TRY(launch_grid_init(I, c->grid_mem + nf, c->stream));
+  I.grid_tab = c->grid_mem + 4 * n_fields;
+  I.grid_scr = c->grid_mem + 4 * n_fields + WAKE_GRID_TAB * n_tab;
+  double* tail = I.grid_scr + 8 * (size_t)max_nodes;
+  *rad = n_rad ? tail : nullptr;
+  *off = n_off ? reinterpret_cast<int32_t*>(tail + n_rad) : nullptr;
+  HIP_TRY(hipMemsetAsync(c->grid_mem, 0xFF, sizeof(double) * 4 * n_fields, c->stream));
+  return WAKE_OK;
+}
+
+static int grid_finish(wake_ctx* c, size_t n_tab) {
+  WakeInst& I = c->I;
+  HIP_TRY(launch_grid_init(I, const_cast<double*>(I.grid_tab), (int)n_tab, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+// checks shared by the grid set-up calls
+static int grid_begin(wake_ctx* c) {
+  if (!c || c->two_species) return WAKE_EINVAL;
+  if (c->next != 0 || c->batches > 0) return WAKE_ESTATE;
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  return grid_clear(c);
+}
+
+extern "C" int wake_set_grid(wake_ctx* c, int32_t n_r, double r_max) {
+  if (!c || c->two_species) return WAKE_EINVAL;
+  if (n_r < 0 || n_r > (1 << 20) || (n_r > 0 && !finite_pos(r_max))) return WAKE_EINVAL;
+  int r = grid_begin(c);
+  if (r != WAKE_OK) return r;
+  if (n_r == 0) return WAKE_OK;
+  WakeInst& I = c->I;
+  double* rad;
+  int32_t* off;
+  r = grid_alloc(c, (size_t)n_r * (size_t)I.n_xi, n_r, n_r, 0, 0, &rad, &off);
+  if (r != WAKE_OK) { grid_clear(c); return r; }
+  I.grid_dr = r_max / (double)n_r;
+  r = grid_finish(c, n_r);
+  if (r != WAKE_OK) grid_clear(c);
+  return r;
+}
+
+extern "C" int wake_set_grid_radii(wake_ctx* c, int64_t n_nodes, const double* radii,
+                                   const int64_t* slice_off) {
+  if (!c || c->two_species) return WAKE_EINVAL;
+  if (n_nodes < 0 || (n_nodes > 0 && !radii)) return WAKE_EINVAL;
+  const int n_xi = c->I.n_xi;
+  int max_nodes = 0;
+  if (!slice_off) {
+    if (n_nodes > (1 << 20)) return WAKE_EINVAL;
+    for (int64_t g = 0; g < n_nodes; ++g)
+      if (!finite_pos(radii[g]) || (g > 0 && !(radii[g] > radii[g - 1]))) return WAKE_EINVAL;
+    max_nodes = (int)n_nodes;
+  } else {
+    if (n_nodes > (1 << 28) || slice_off[0] != 0 || slice_off[n_xi] != n_nodes) return WAKE_EINVAL;
+    for (int n = 0; n < n_xi; ++n) {
+      const int64_t k0 = slice_off[n], k1 = slice_off[n + 1];
+      if (k1 < k0 || k1 - k0 > (1 << 20)) return WAKE_EINVAL;
+      for (int64_t g = k0; g < k1; ++g)
+        if (!finite_pos(radii[g]) || (g > k0 && radii[g] < radii[g - 1])) return WAKE_EINVAL;
+      max_nodes = std::max(max_nodes, (int)(k1 - k0));
+    }
+  }
+  int r = grid_begin(c);
+  if (r != WAKE_OK) return r;
+  if (n_nodes == 0) return WAKE_OK;
+  WakeInst& I = c->I;
+  const size_t n_fields = slice_off ? (size_t)n_nodes : (size_t)n_nodes * (size_t)n_xi;
+  double* rad;
+  int32_t* off;
+  r = grid_alloc(c, n_fields, (size_t)n_nodes, max_nodes, (size_t)n_nodes,
+                 slice_off ? (size_t)n_xi + 1 : 0, &rad, &off);
+  if (r != WAKE_OK) { grid_clear(c); return r; }
+  hipError_t e = hipMemcpyAsync(rad, radii, sizeof(double) * n_nodes, hipMemcpyHostToDevice, c->stream);
+  I.grid_rad = rad;
+  if (slice_off && e == hipSuccess) {
+    try {
+      c->grid_off_h.assign(slice_off, slice_off + n_xi + 1);
+    } catch (...) {
+      grid_clear(c);
+      return WAKE_ENOMEM;
+    }
+    e = hipMemcpyAsync(off, c->grid_off_h.data(), sizeof(int32_t) * (n_xi + 1), hipMemcpyHostToDevice,
+                       c->stream);
+    I.grid_off = off;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) { grid_clear(c); return dev_err(e); }
+  r = grid_finish(c, (size_t)n_nodes);
+  if (r != WAKE_OK) grid_clear(c);
+  return r;
+}
+
+extern "C" int wake_set_grid_beam(wake_ctx* c) {
+  if (!c || c->two_species) return WAKE_EINVAL;
+  if (c->next != 0 || c->batches > 0) return WAKE_ESTATE;
+  int r = wake_prepare(c);                        // the beam table is the node set
+  if (r != WAKE_OK) return r;
+  r = grid_begin(c);
+  if (r != WAKE_OK) return r;
+  WakeInst& I = c->I;
+  if (I.nb <= 0) return WAKE_EINVAL;
+  try {
+    c->grid_off_h.resize((size_t)I.n_xi + 1);
+  } catch (...) {
+    return WAKE_ENOMEM;
+  }
+  HIP_TRY(hipMemcpy(c->grid_off_h.data(), I.boff, sizeof(int32_t) * (I.n_xi + 1), hipMemcpyDeviceToHost));
+  int max_nodes = 0;
+  for (int n = 0; n < I.n_xi; ++n) max_nodes = std::max(max_nodes, c->grid_off_h[n + 1] - c->grid_off_h[n]);
+  double* rad;
+  int32_t* off;
+  r = grid_alloc(c, (size_t)I.nb, (size_t)I.nb, max_nodes, 0, 0, &rad, &off);
+  if (r != WAKE_OK) { grid_clear(c); return r; }
+  I.grid_rad = I.br;
+  I.grid_off = I.boff;
+  r = grid_finish(c, (size_t)I.nb);
+  if (r != WAKE_OK) grid_clear(c);
+  return r;
+}
+
+// first entry and node count of a slice's grid nodes
+static void grid_slice(const wake_ctx* c, int slice, size_t* first, size_t* count) {
+  if (c->grid_off_h.empty()) {
+    *first = (size_t)slice * (size_t)c->I.grid_n;
+    *count = (size_t)c->I.grid_n;
+  } else {
+    *first = (size_t)c->grid_off_h[slice];
+    *count = (size_t)(c->grid_off_h[slice + 1] - c->grid_off_h[slice]);
+  }
+}
+
+extern "C" int wake_grid_nodes(wake_ctx* c, int32_t slice, int64_t* count, double* radii) {
+  if (!c || !count) return WAKE_EINVAL;
+  const WakeInst& I = c->I;
+  if (!c->grid_mem) return WAKE_ESTATE;
+  if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
+  size_t first, cnt;
+  grid_slice(c, slice, &first, &cnt);
+  *count = (int64_t)cnt;
+  if (!radii || cnt == 0) return WAKE_OK;
+  if (!I.grid_rad) {
+    for (size_t g = 0; g < cnt; ++g) radii[g] = ((double)g + 0.5) * I.grid_dr;
+    return WAKE_OK;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  const double* src = I.grid_rad + (c->grid_off_h.empty() ? 0 : first);
+  HIP_TRY(hipMemcpy(radii, src, sizeof(double) * cnt, hipMemcpyDeviceToHost));
   return WAKE_OK;
 }
 
@@ -850,7 +1002,7 @@ extern "C" int wake_grid_fields(wake_ctx* c, int32_t slice, double* psi, double*
                                 double* bt, int32_t dev) {
   if (!c) return WAKE_EINVAL;
   const WakeInst& I = c->I;
-  if (I.grid_n <= 0) return WAKE_ESTATE;
+  if (!c->grid_mem) return WAKE_ESTATE;
   int32_t ctl[CTL_NWORDS];
   int r = read_ctl(c, ctl);
   if (r != WAKE_OK) return r;
@@ -863,8 +1015,9 @@ extern "C" int wake_grid_fields(wake_ctx* c, int32_t slice, double* psi, double*
   if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
   if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
   if (slice >= c->next || slice < c->valid_from) return WAKE_ESTATE;
-  const size_t ng = I.grid_n;
-  const double* base = I.grid + (size_t)slice * 4 * ng;
+  size_t first, ng;
+  grid_slice(c, slice, &first, &ng);
+  const double* base = I.grid + 4 * first;
   double* outs[4] = {psi, erbt, ez, bt};
   for (int q = 0; q < 4; ++q) {
     r = copy_out(outs[q], base + q * ng, ng, dev, c->stream);

@@ -125,6 +125,13 @@ struct WakeInst {
   double *grid;
   const double *grid_tab;
   double *grid_scr;           // [grid_n][8]: the owning interval's sums handed to each node
+  // explicit node radii (null: the uniform nodes above).  Without grid_off
+  // the same grid_n radii (ascending) serve every slice; with it, slice n's
+  // nodes are entries grid_off[n] .. grid_off[n+1]-1 (ascending within the
+  // slice), node records and fields are per entry (the slice's fields at
+  // grid + 4 grid_off[n], [4][count]) and grid_n is the most nodes a slice has
+  const double *grid_rad;
+  const int32_t *grid_off;
 };
 
 // Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c

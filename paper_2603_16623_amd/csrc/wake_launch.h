@@ -32,8 +32,9 @@ size_t march_lds_bytes(int nt);
 // grid nodes (instances without a grid march as in the plain variant)
 hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
                         int grid, bool with_grid, hipStream_t s);
-// field-grid node table of I's grid (ln r_g, ion fields at r_g)
-hipError_t launch_grid_init(const WakeInst& I, double* tab, hipStream_t s);
+// field-grid node records of I's grid (ln r_g, ion fields at r_g) for its
+// n_entries nodes (per-slice node sets: every entry)
+hipError_t launch_grid_init(const WakeInst& I, double* tab, int n_entries, hipStream_t s);
 int march_occupancy(int nt);
 int march_cmax(int nt);     // rings per thread up to which the keys of every position fit LDS
 hipError_t march_prepare(int nt);

@@ -1255,9 +1255,25 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
 // (rho_{p-1}, rho_p] lies in interval p of the recursion: below it the
 // rings before position p, at and above it the rest.
 // ---------------------------------------------------------------------------
+// Radius of node g: rad[g] for explicit nodes, else (g + 1/2) dg.
+__device__ __forceinline__ double grid_node_r(int g, double dg, const WAKE_GLOBAL double* rad) {
+  return rad ? rad[g] : ((double)g + 0.5) * dg;
+}
+
 // The largest node g with r_g <= x (-1 if none), decided on the node radii
-// themselves so that neighbouring intervals split the nodes exactly.
-__device__ __forceinline__ int grid_last_below(double x, double dg, double idg, int ng) {
+// themselves so that neighbouring intervals split the nodes exactly
+// (explicit radii: a binary search; uniform nodes: a guess corrected on the
+// radii).
+__device__ __forceinline__ int grid_last_below(double x, double dg, double idg, int ng,
+                                               const WAKE_GLOBAL double* rad) {
+  if (rad) {
+    int a = 0, b = ng;                         // nodes at or below x: [0, a)
+    while (a < b) {
+      const int m = (a + b) >> 1;
+      if (rad[m] <= x) a = m + 1; else b = m;
+    }
+    return a - 1;
+  }
   if (!(x >= 0.5 * dg)) return -1;
   const double t = floor(x * idg - 0.5);      // a guess; the node radii decide
   int g = t >= (double)(ng - 1) ? ng - 1 : (int)t;
@@ -1424,7 +1440,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   const bool lds_ion = N <= KCAP;      // the interval nodes fit the LDS table
   // field-grid node records in the LDS beyond the layout (read after the
   // slice-head scan's barriers)
-  const bool grid_lds = GRID && I.grid_n > 0 && I.grid_n <= grid_lds_nodes<NT>();
+  const bool grid_lds = GRID && I.grid_n > 0 && !I.grid_off && I.grid_n <= grid_lds_nodes<NT>();
   D2* const s_gt = reinterpret_cast<D2*>(smem + MarchLds<NT>::bytes());
   if (grid_lds) {
     const WAKE_GLOBAL D2* const t = reinterpret_cast<const WAKE_GLOBAL D2*>(gptr(I.grid_tab));
@@ -1639,7 +1655,12 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     // B^(p) coefficients); every thread then evaluates nodes.  gb_lo: the
     // last node at or below the previous position, gb_next its successor's
     // radius (a ring at or above it owns nodes)
-    const int ngB = GRID ? I.grid_n : 0;
+    // this slice's nodes: entries [gofs, gofs + ngB) of a per-slice node
+    // set, else the context's nodes (fields of slice n at 4 n grid_n)
+    const size_t gofs = !GRID ? 0 : I.grid_off ? (size_t)gptr(I.grid_off)[n] : (size_t)n * (size_t)I.grid_n;
+    const int ngB = !GRID ? 0 : I.grid_off ? gptr(I.grid_off)[n + 1] - (int)gofs : I.grid_n;
+    const WAKE_GLOBAL double* const grB =
+        (GRID && I.grid_rad) ? gptr(I.grid_rad) + (I.grid_off ? gofs : 0) : nullptr;
     const double dgB = I.grid_dr, idgB = 1.0 / dgB;
     WAKE_GLOBAL D2* const gscr = reinterpret_cast<WAKE_GLOBAL D2*>(gptr(I.grid_scr));
     int gb_lo = -1;
@@ -1648,8 +1669,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       double rb = -1.0;
       if (tid > 0) rb = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
       else if (CL) rb = rho_mprev;
-      gb_lo = grid_last_below(rb, dgB, idgB, ngB);
-      gb_next = gb_lo + 1 < ngB ? ((double)(gb_lo + 1) + 0.5) * dgB : INFINITY;
+      gb_lo = grid_last_below(rb, dgB, idgB, ngB, grB);
+      gb_next = gb_lo + 1 < ngB ? grid_node_r(gb_lo + 1, dgB, grB) : INFINITY;
     }
     #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
@@ -1683,14 +1704,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       const double dpsi = dd_round(dd_add_fast(de, idp));
       if (GRID && rho >= gb_next) {
         // nodes of interval p = (rho_{p-1}, rho_p]: the sums below position p
-        const int ghi = grid_last_below(rho, dgB, idgB, ngB);
+        const int ghi = grid_last_below(rho, dgB, idgB, ngB, grB);
         #pragma unroll 1
         for (int g = gb_lo + 1; g <= ghi; ++g) {
           gscr[4 * g] = d2(S.hi, S.lo);
           gscr[4 * g + 1] = d2(PT.hi, PT.lo);
         }
         gb_lo = ghi;
-        gb_next = gb_lo + 1 < ngB ? ((double)(gb_lo + 1) + 0.5) * dgB : INFINITY;
+        gb_next = gb_lo + 1 < ngB ? grid_node_r(gb_lo + 1, dgB, grB) : INFINITY;
       }
       S = dd_add_d(S, w);
       PT = PTi;
@@ -1751,8 +1772,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     // this member's nodes (all of them for a single workgroup)
     int g_begin = 0, g_end = ngB;
     if (GRID && CL && ngB > 0) {
-      g_begin = grid_last_below(rho_mprev, dgB, idgB, ngB) + 1;
-      if (member < cl.G - 1) g_end = grid_last_below(rho_mlast, dgB, idgB, ngB) + 1;
+      g_begin = grid_last_below(rho_mprev, dgB, idgB, ngB, grB) + 1;
+      if (member < cl.G - 1) g_end = grid_last_below(rho_mlast, dgB, idgB, ngB, grB) + 1;
     }
 
     // ---- growing mode g (prefix) and decaying mode h (suffix) ----
@@ -1764,11 +1785,12 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (GRID && ngB > 0) {
       // psi, E_r - B_theta and the beam field at this member's nodes (the
       // scans' barriers order the sums written in pass B before these reads)
-      const WAKE_GLOBAL D2* const gtab = reinterpret_cast<const WAKE_GLOBAL D2*>(gptr(I.grid_tab));
-      WAKE_GLOBAL double* const gout = gptr(I.grid) + (size_t)n * 4 * (size_t)ngB;
+      const WAKE_GLOBAL D2* const gtab = reinterpret_cast<const WAKE_GLOBAL D2*>(gptr(I.grid_tab)) +
+                                         (I.grid_off ? 3 * gofs : 0);
+      WAKE_GLOBAL double* const gout = gptr(I.grid) + 4 * gofs;
       #pragma unroll 1
       for (int g = g_begin + tid; g < g_end; g += NT) {
-        const double r = ((double)g + 0.5) * dgB;
+        const double r = grid_node_r(g, dgB, grB);
         D2 t0, t1, t2;
         if (grid_lds) {
           t0 = s_gt[3 * g]; t1 = s_gt[3 * g + 1]; t2 = s_gt[3 * g + 2];
@@ -1880,7 +1902,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (GRID && ngB > 0 && cnt > 0) {
       if (tid > 0) g_lo_r = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
       else if (CL) g_lo_r = rho_mprev;
-      ge_hi = grid_last_below(y_ru.x, dgB, idgB, ngB);
+      ge_hi = grid_last_below(y_ru.x, dgB, idgB, ngB, grB);
       if (p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
         // nodes beyond the last ring: interval N (a_N = 0, no ring outside)
         const double a = (ha * E - ga * D) * iW, b = (hb * E - gb * D) * iW;
@@ -1890,7 +1912,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
           gscr[4 * g + 3] = d2(b, 0.0);
         }
       }
-      ge_top = ge_hi >= 0 ? ((double)ge_hi + 0.5) * dgB : -INFINITY;
+      ge_top = ge_hi >= 0 ? grid_node_r(ge_hi, dgB, grB) : -INFINITY;
     }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
@@ -1986,14 +2008,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         const double rlo = k > 0 ? y_ru.x : g_lo_r;
         if (rlo < ge_top) {
           // nodes of interval p = (rho_{p-1}, rho_p]
-          const int glo = grid_last_below(rlo, dgB, idgB, ngB) + 1;
+          const int glo = grid_last_below(rlo, dgB, idgB, ngB, grB) + 1;
           #pragma unroll 1
           for (int g = glo; g <= ge_hi; ++g) {
             gscr[4 * g + 2] = d2(Vgt, a);
             gscr[4 * g + 3] = d2(b, 0.0);
           }
           ge_hi = glo - 1;
-          ge_top = ge_hi >= 0 ? ((double)ge_hi + 0.5) * dgB : -INFINITY;
+          ge_top = ge_hi >= 0 ? grid_node_r(ge_hi, dgB, grB) : -INFINITY;
         }
       }
     }
@@ -2015,10 +2037,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (s_misc[63] != 0.0) end = n + 1;
     if (GRID && ngB > 0) {
       // E_z and B_theta at this member's nodes (after the barrier above)
-      WAKE_GLOBAL double* const gout = gptr(I.grid) + (size_t)n * 4 * (size_t)ngB;
+      WAKE_GLOBAL double* const gout = gptr(I.grid) + 4 * gofs;
       #pragma unroll 1
       for (int g = g_begin + tid; g < g_end; g += NT) {
-        const double r = ((double)g + 0.5) * dgB;
+        const double r = grid_node_r(g, dgB, grB);
         const D2 e0 = gscr[4 * g + 2], e1 = gscr[4 * g + 3];
         grid_node_b(gout, ngB, g, r, e0.x, e0.y, e1.x, gout[3 * ngB + g]);
       }
@@ -2189,10 +2211,10 @@ hipError_t launch_init(const WakeInst& I, const double* r0, const double* dr, co
 // differences and the step between the nodes' double-double values (at the
 // rings the step is rounded to double, which resolves psi to ~1e-16 of the
 // step; nodes between rings at rest see psi of order w dr^2 only).
-__global__ void grid_init_kernel(WakeInst I, double* tab) {
+__global__ void grid_init_kernel(WakeInst I, double* tab, int n_entries) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= I.grid_n) return;
-  const double r = ((double)g + 0.5) * I.grid_dr;
+  if (g >= n_entries) return;
+  const double r = I.grid_rad ? I.grid_rad[g] : ((double)g + 0.5) * I.grid_dr;
   const dd l = dd_log(r);
   IonView IV;
   IV.R = uview(I.ion);
@@ -2225,9 +2247,9 @@ __global__ void grid_init_kernel(WakeInst I, double* tab) {
   t[4] = dp.hi; t[5] = dp.lo;
 }
 
-hipError_t launch_grid_init(const WakeInst& I, double* tab, hipStream_t s) {
-  if (I.grid_n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(grid_init_kernel, dim3((I.grid_n + 255) / 256), dim3(256), 0, s, I, tab);
+hipError_t launch_grid_init(const WakeInst& I, double* tab, int n_entries, hipStream_t s) {
+  if (n_entries <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grid_init_kernel, dim3((n_entries + 255) / 256), dim3(256), 0, s, I, tab, n_entries);
   return hipGetLastError();
 }
 

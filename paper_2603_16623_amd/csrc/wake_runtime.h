@@ -36,7 +36,8 @@ struct wake_ctx {
   bool beam_external = false;      // beam_mem belongs to the caller (wake_prepare_noalloc)
   // pending particle sources (host copies until the table is built)
   std::vector<double> px, py, pxi, pw, pq;
-  double* grid_mem = nullptr;  // field grid: fields [n_xi][4][n_r], then the node table
+  double* grid_mem = nullptr;  // field grid: fields, node records, hand-over scratch, radii, offsets
+  std::vector<int32_t> grid_off_h; // per-slice node sets: host copy of the offsets (empty: fixed nodes)
   bool prepared = false;
   int batches = 0;                 // batches that hold this context
   int next = 0;

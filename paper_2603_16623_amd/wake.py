@@ -76,6 +76,9 @@ _SIGS = {
     "wake_lineout": (_I, [_P, _P, _P, _I]),
     "wake_set_grid": (_I, [_P, _I, C.c_double]),
     "wake_grid_fields": (_I, [_P, _I, _P, _P, _P, _P, _I]),
+    "wake_set_grid_radii": (_I, [_P, _I64, _P, _P]),
+    "wake_set_grid_beam": (_I, [_P]),
+    "wake_grid_nodes": (_I, [_P, _I, C.POINTER(_I64), _P]),
     "wake_get_state": (_I, [_P, C.POINTER(_I), _P, _P, _P, _P, _I]),
     "wake_set_state": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "wake_reset": (_I, [_P]),
@@ -386,16 +389,42 @@ class WakeSolver:
         self.grid_n = int(n_r)
         self.grid_r_max = float(r_max)
 
+    def wake_set_grid_radii(self, radii, slice_off=None):
+        """Field grid at given radii: the same ascending radii every slice, or
+        (slice_off: n_xi + 1 offsets) slice n's radii[slice_off[n]:slice_off[n+1]]."""
+        r = _host(radii)
+        off = None if slice_off is None else np.ascontiguousarray(slice_off, dtype=np.int64)
+        _check(self._lib.wake_set_grid_radii(self.h, len(r), _ptr(r), _ptr(off)),
+               "wake_set_grid_radii")
+        self.grid_n = len(r) if off is None else None
+
+    def wake_set_grid_beam(self):
+        """Field grid at every beam-table entry (the particles' own radii)."""
+        _check(self._lib.wake_set_grid_beam(self.h), "wake_set_grid_beam")
+        self.grid_n = None
+
+    def grid_nodes(self, slice_: int = 0):
+        """Radii of a slice's grid nodes."""
+        n = _I64()
+        _check(self._lib.wake_grid_nodes(self.h, slice_, C.byref(n), None), "wake_grid_nodes")
+        r = np.empty(n.value)
+        if n.value:
+            _check(self._lib.wake_grid_nodes(self.h, slice_, C.byref(n), r.ctypes.data),
+                   "wake_grid_nodes")
+        return r
+
     def grid_radii(self):
-        """The grid's node radii (g + 1/2) r_max / n_r."""
-        dg = self.grid_r_max / self.grid_n
-        return (np.arange(self.grid_n, dtype=np.float64) + 0.5) * dg
+        """The grid's node radii (every slice the same)."""
+        return self.grid_nodes(0)
 
     def wake_grid_fields(self, slice_: int = -1, out=None, device: bool = False):
         """dict of psi, er_bt, ez, bt at the grid nodes of a slice."""
         names = ("psi", "er_bt", "ez", "bt")
         if out is None:
-            out = {k: np.empty(self.grid_n) for k in names}
+            at = slice_ if slice_ >= 0 else max(self.wake_status()[1] - 1, 0)
+            n = _I64()
+            _check(self._lib.wake_grid_nodes(self.h, at, C.byref(n), None), "wake_grid_nodes")
+            out = {k: np.empty(n.value) for k in names}
         ptrs = [_ptr(out.get(k)) for k in names]
         _check(self._lib.wake_grid_fields(self.h, slice_, *ptrs, int(device)), "wake_grid_fields")
         return out
