@@ -65,6 +65,17 @@ only):
       the interval's (a, b); a ring at exactly that radius counts as
       outside.  The field grid is uniform with nodes at cell centres
       (g + 1/2) r_max / n_r.
+  R20 the susceptibility chi = n/gamma on the laser grid (Fig. 2, Sec.
+      "Integration into Wake-T"; the deposit's shape is not given): ring j
+      carries chi(rho) rho = (w_j / psibar_j) delta(rho - rho_j), since
+      eq. fluid_from_mp_1 gives n/gamma = w / (rho (1 - v_z) gamma) delta and
+      (1 - v_z) gamma = gamma - u_z = psibar (eqs. plasma_particle_motion_3-4).
+      Deposited with linear (hat) weights W_g between neighbouring nodes, a
+      ring inside the first node counting wholly to it (folded at the axis),
+      the last node's hat reaching as far above it as the spacing below it,
+      each node normalised by V_g = integral of W_g rho drho:
+      chi_g = sum_j (w_j / psibar_j) W_g(rho_j) / V_g.  A uniform column at
+      rest deposits chi = 1, and sum_g V_g chi_g = sum_j w_j / psibar_j.
 """
 from __future__ import annotations
 
@@ -550,6 +561,46 @@ def grid_radii(n_r, r_max):
     return (np.arange(int(n_r), dtype=np.float64) + 0.5) * dg
 
 
+def chi_volumes(radii):
+    """V_g = integral over rho of W_g(rho) rho for the hat weights of reading
+    R20 on ascending nodes r_g (80-bit).  Below the first node W_0 = 1; above
+    the last node its hat ends at r_{n-1} + (r_{n-1} - r_{n-2}) (2 r_0 for a
+    single node)."""
+    r = np.asarray(radii).astype(LD)
+    n = len(r)
+    top = r[-1] + (r[-1] - r[-2]) if n > 1 else 2 * r[0]
+    lo = np.concatenate([[LD(0)], r[:-1]])
+    hi = np.concatenate([r[1:], [top]])
+    # integral of (rho - a)/(b - a) rho over [a, b] is (b - a)(a + 2b)/6;
+    # of (c - rho)/(c - b) rho over [b, c] is (c - b)(2b + c)/6
+    lower = (r - lo) * (lo + 2 * r) / 6
+    lower[0] = r[0] * r[0] / 2
+    upper = (hi - r) * (2 * r + hi) / 6
+    return lower + upper
+
+
+def chi_deposit(rho, c, radii):
+    """chi at ascending nodes from rings at radii rho carrying c_j = w_j /
+    psibar_j (reading R20): for each node, the sum over the rings in the
+    support of its hat of c_j W_g(rho_j), over V_g.  80-bit sums."""
+    r = np.asarray(radii).astype(LD)
+    rho = np.asarray(rho).astype(LD)
+    c = np.asarray(c).astype(LD)
+    n = len(r)
+    top = r[-1] + (r[-1] - r[-2]) if n > 1 else 2 * r[0]
+    V = chi_volumes(radii)
+    out = np.zeros(n, LD)
+    for g in range(n):
+        lo = r[g - 1] if g > 0 else LD(0)
+        hi = r[g + 1] if g + 1 < n else top
+        below = (rho >= lo) & (rho < r[g]) if g > 0 else (rho < r[g])
+        above = (rho >= r[g]) & (rho < hi)
+        wl = (rho[below] - lo) / (r[g] - lo) if g > 0 else np.ones(int(np.sum(below)), LD)
+        wu = (hi - rho[above]) / (hi - r[g])
+        out[g] = (np.sum(c[below] * wl) + np.sum(c[above] * wu)) / V[g]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # driver (Fig. 2 right column)
 # ---------------------------------------------------------------------------
@@ -678,13 +729,22 @@ class RingOracle:
                     er_bt=(-(dpsi_e + dpsi_i)).astype(np.float64),
                     ez=(-V[k]).astype(np.float64), bt=bt)
 
+    def chi_at(self, out, radii):
+        """chi = n/gamma of slice n deposited at ascending grid radii
+        (reading R20; Fig. 2 "deposit chi in laser grid").  ``out`` is the
+        slice's result with keep=True.  Returns binary64."""
+        ids = out["order"]
+        rho = out["rho"][ids]
+        c = self.w[ids].astype(LD) / np.asarray(out["psibar"]).astype(LD)
+        return chi_deposit(rho, c, radii).astype(np.float64)
+
     def run(self, first=0, count=None, state=None, record_stride=1, grid=None):
         """March slices [first, first+count).  Returns a dict with per-slice
         on-axis lineouts, snapshots every ``record_stride`` slices (by ring
         id), the final state and the breakdown slice (-1 if none); with
         ``grid = (n_r, r_max)`` also the fields at the grid_radii nodes of
         every slice, 'grid' of shape [count][4][n_r] (psi, E_r - B_theta,
-        E_z, B_theta)."""
+        E_z, B_theta), and chi there, 'chi' of shape [count][n_r]."""
         if count is None:
             count = self.n_xi - first
         if state is None:
@@ -693,6 +753,7 @@ class RingOracle:
         axis = np.full((count, 2), np.nan)
         gr = None if grid is None else grid_radii(*grid)
         gfield = None if grid is None else np.full((count, 4, len(gr)), np.nan)
+        gchi = None if grid is None else np.full((count, len(gr)), np.nan)
         breakdown = -1
         for k in range(count):
             n = first + k
@@ -704,6 +765,7 @@ class RingOracle:
             if grid is not None:
                 f = self.fields_at(n, out, gr)
                 gfield[k] = [f["psi"], f["er_bt"], f["ez"], f["bt"]]
+                gchi[k] = self.chi_at(out, gr)
             if record_stride and (n % record_stride == 0 or k == count - 1):
                 rec[n] = {q: out[q] for q in ("psi", "er_bt", "ez", "bt", "rho", "u")}
             if new is not None:
@@ -711,4 +773,5 @@ class RingOracle:
         res = dict(axis=axis, snap=rec, state=state, breakdown=breakdown)
         if grid is not None:
             res["grid"] = gfield
+            res["chi"] = gchi
         return res
