@@ -173,6 +173,19 @@ int wake_fields(wake_ctx *ctx, int32_t slice, double *psi, double *er_minus_bt, 
  * served form (wake_server_*) has no grid.  Synchronous. */
 int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
 
+/* chi = n/gamma (the plasma susceptibility the laser envelope solver takes,
+ * Fig. 2 "deposit chi in laser grid", Sec. "Integration into Wake-T") at the
+ * nodes of a uniform or fixed-radii grid for one solved slice [n_r]: each
+ * ring carries w / psibar (n/gamma of eq. fluid_from_mp_1 with (1 - v_z)
+ * gamma = psibar), deposited with linear (hat) weights between neighbouring
+ * nodes (a ring inside the first node wholly to it; the last node's hat
+ * reaching as far above it as the spacing below it) and normalised by each
+ * hat's integral of rho drho, so that a uniform plasma at rest gives 1.
+ * Slice and errors as wake_grid_fields; WAKE_ESTATE for per-slice node sets
+ * (wake_set_grid_radii with offsets, wake_set_grid_beam), which deposit no
+ * chi.  Synchronizes. */
+int wake_grid_chi(wake_ctx *ctx, int32_t slice, double *chi, int32_t dst_is_device);
+
 /* Field grid at radii the caller gives (Sec. "Key algorithmic adjustments":
  * the sums give the plasma fields at any radius, so they can be sampled with
  * any radial resolution; the node rule is wake_set_grid's).  slice_off NULL:

@@ -829,27 +829,34 @@ static int grid_clear(wake_ctx* c) {
   I.grid_scr = nullptr;
   I.grid_rad = nullptr;
   I.grid_off = nullptr;
+  I.grid_thr = nullptr;
   return WAKE_OK;
 }
 
-// Common set-up of a field grid: n_fields slice fields (4 doubles per node
-// and slice), n_tab node records, hand-over scratch for max_nodes nodes of a
-// slice, extra doubles for radii and int32 words for offsets copied in.
-// Unmarched slices read as NaN.  The caller fills the radii / offsets and
-// then calls grid_finish.
+// Common set-up of a field grid: n_fields node-slices of fields (5 doubles
+// each: psi, E_r - B_theta, E_z, B_theta, chi), n_tab node records,
+// hand-over scratch for max_nodes nodes of a slice and the virtual node above
+// them (12 doubles each), the chi deposit's per-thread sums (4 doubles per
+// thread of the instance), extra doubles for radii and int32 words for
+// offsets copied in.  Unmarched slices read as NaN.  The caller fills the
+// radii / offsets and then calls grid_finish.
 static int grid_alloc(wake_ctx* c, size_t n_fields, size_t n_tab, int max_nodes, size_t n_rad,
                       size_t n_off, double** rad, int32_t** off) {
   WakeInst& I = c->I;
-  const size_t nd = 4 * n_fields + WAKE_GRID_TAB * n_tab + 8 * (size_t)max_nodes + n_rad + (n_off + 1) / 2;
+  const size_t n_scr = 12 * ((size_t)max_nodes + 1);
+  const size_t n_thr = 4 * (size_t)I.nt * (size_t)I.G;
+  const size_t nd = 5 * n_fields + WAKE_GRID_TAB * n_tab + n_scr + n_thr + n_rad + (n_off + 1) / 2;
   HIP_TRY(hipMalloc(&c->grid_mem, sizeof(double) * nd));
   I.grid_n = max_nodes;
   I.grid = c->grid_mem;
-  I.grid_tab = c->grid_mem + 4 * n_fields;
-  I.grid_scr = c->grid_mem + 4 * n_fields + WAKE_GRID_TAB * n_tab;
-  double* tail = I.grid_scr + 8 * (size_t)max_nodes;
+  I.grid_tab = c->grid_mem + 5 * n_fields;
+  I.grid_scr = c->grid_mem + 5 * n_fields + WAKE_GRID_TAB * n_tab;
+  I.grid_thr = I.grid_scr + n_scr;
+  double* tail = I.grid_thr + n_thr;
   *rad = n_rad ? tail : nullptr;
   *off = n_off ? reinterpret_cast<int32_t*>(tail + n_rad) : nullptr;
-  HIP_TRY(hipMemsetAsync(c->grid_mem, 0xFF, sizeof(double) * 4 * n_fields, c->stream));
+  HIP_TRY(hipMemsetAsync(c->grid_mem, 0xFF, sizeof(double) * 5 * n_fields, c->stream));
+  HIP_TRY(hipMemsetAsync(I.grid_scr, 0, sizeof(double) * (n_scr + n_thr), c->stream));
   return WAKE_OK;
 }
 
@@ -1017,12 +1024,36 @@ extern "C" int wake_grid_fields(wake_ctx* c, int32_t slice, double* psi, double*
   if (slice >= c->next || slice < c->valid_from) return WAKE_ESTATE;
   size_t first, ng;
   grid_slice(c, slice, &first, &ng);
-  const double* base = I.grid + 4 * first;
+  const double* base = I.grid + 5 * first;
   double* outs[4] = {psi, erbt, ez, bt};
   for (int q = 0; q < 4; ++q) {
     r = copy_out(outs[q], base + q * ng, ng, dev, c->stream);
     if (r != WAKE_OK) return r;
   }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return WAKE_OK;
+}
+
+extern "C" int wake_grid_chi(wake_ctx* c, int32_t slice, double* chi, int32_t dev) {
+  if (!c) return WAKE_EINVAL;
+  const WakeInst& I = c->I;
+  if (!c->grid_mem || !c->grid_off_h.empty()) return WAKE_ESTATE;
+  int32_t ctl[CTL_NWORDS];
+  int r = read_ctl(c, ctl);
+  if (r != WAKE_OK) return r;
+  const int brk = ctl[CTL_BREAK];
+  if (slice == -1) {
+    if (brk >= 0) return WAKE_EBREAKDOWN;
+    if (c->next == 0) return WAKE_ESTATE;
+    slice = c->next - 1;
+  }
+  if (slice < 0 || slice >= I.n_xi) return WAKE_EINVAL;
+  if (brk >= 0 && slice >= brk) return WAKE_EBREAKDOWN;
+  if (slice >= c->next || slice < c->valid_from) return WAKE_ESTATE;
+  size_t first, ng;
+  grid_slice(c, slice, &first, &ng);
+  r = copy_out(chi, I.grid + 5 * first + 4 * ng, ng, dev, c->stream);
+  if (r != WAKE_OK) return r;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return WAKE_OK;
 }

@@ -117,21 +117,25 @@ struct WakeInst {
   int32_t *ctl;               // [CTL_NWORDS]
   unsigned long long *cnt;    // [CNT_N]
   // radial field grid (none while grid_n is 0): nodes r_g = (g + 1/2)
-  // grid_dr, g < grid_n; fields of every slice [n_xi][4][grid_n] (psi,
-  // E_r - B_theta, E_z, B_theta); per node [grid_n][WAKE_GRID_TAB]: ln r_g,
+  // grid_dr, g < grid_n; fields of every slice [n_xi][5][grid_n] (psi,
+  // E_r - B_theta, E_z, B_theta, chi); per node [grid_n][WAKE_GRID_TAB]: ln r_g,
   // the ions' psi - psi(0) and d_rho psi at r_g, as dd pairs
   int32_t grid_n;
   double grid_dr;
   double *grid;
   const double *grid_tab;
-  double *grid_scr;           // [grid_n][8]: the owning interval's sums handed to each node
+  double *grid_scr;           // [grid_n + 1][12]: the owning interval's sums handed to each node
   // explicit node radii (null: the uniform nodes above).  Without grid_off
   // the same grid_n radii (ascending) serve every slice; with it, slice n's
   // nodes are entries grid_off[n] .. grid_off[n+1]-1 (ascending within the
   // slice), node records and fields are per entry (the slice's fields at
-  // grid + 4 grid_off[n], [4][count]) and grid_n is the most nodes a slice has
+  // grid + 5 grid_off[n], [5][count], chi not deposited) and grid_n is the
+  // most nodes a slice has
   const double *grid_rad;
   const int32_t *grid_off;
+  // chi deposit on fixed node sets: per thread of the instance (G nt of
+  // them), the sums of c and c rho of the chunks after its own (dd pairs)
+  double *grid_thr;
 };
 
 // Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c

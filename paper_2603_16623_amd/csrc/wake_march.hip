@@ -1283,6 +1283,29 @@ __device__ __forceinline__ int grid_last_below(double x, double dg, double idg, 
   return g;
 }
 
+// Per-node hand-over scratch of a slice: 6 chunks of two doubles per node:
+// [0] sum of w below, [1] sum of w ln rho below (pass B); [2] (E_z sum at
+// and above, a), [3] (b, owner thread) (pass E); [4], [5] the owner's
+// partial sums at and above the node of c = w / psibar and c rho (double-
+// double; the chi deposit).
+constexpr int GS = 6;
+
+// The nodes a slice hands over in pass E: nr real nodes (uniform or explicit
+// radii) and, when chi is deposited, one virtual node above the last, at
+// r_{nr-1} + (r_{nr-1} - r_{nr-2}) (2 r_0 for a single node), where the last
+// node's hat ends.
+struct GridNodes {
+  const WAKE_GLOBAL double* rad;
+  double dg, idg, top;
+  int nr, nh;
+  __device__ __forceinline__ double r(int g) const { return g < nr ? grid_node_r(g, dg, rad) : top; }
+  __device__ __forceinline__ int last_below(double x) const {
+    int g = grid_last_below(x, dg, idg, nr, rad);
+    if (g == nr - 1 && nh > nr && top <= x) g = nr;
+    return g;
+  }
+};
+
 // psi (eq. psi) and E_r - B_theta = -d_rho psi (eq. dpsi_dr, no ring at r)
 // at node g (radius r) of an interval with the sums S, P of weight and
 // w ln rho below it.  t0, t1, t2: the node's record (ln r and the immobile
@@ -1707,8 +1730,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         const int ghi = grid_last_below(rho, dgB, idgB, ngB, grB);
         #pragma unroll 1
         for (int g = gb_lo + 1; g <= ghi; ++g) {
-          gscr[4 * g] = d2(S.hi, S.lo);
-          gscr[4 * g + 1] = d2(PT.hi, PT.lo);
+          gscr[GS * g] = d2(S.hi, S.lo);
+          gscr[GS * g + 1] = d2(PT.hi, PT.lo);
         }
         gb_lo = ghi;
         gb_next = gb_lo + 1 < ngB ? grid_node_r(gb_lo + 1, dgB, grB) : INFINITY;
@@ -1765,8 +1788,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       // nodes beyond the last ring: every ring below them
       #pragma unroll 1
       for (int g = gb_lo + 1; g < ngB; ++g) {
-        gscr[4 * g] = d2(S.hi, S.lo);
-        gscr[4 * g + 1] = d2(PT.hi, PT.lo);
+        gscr[GS * g] = d2(S.hi, S.lo);
+        gscr[GS * g + 1] = d2(PT.hi, PT.lo);
       }
     }
     // this member's nodes (all of them for a single workgroup)
@@ -1787,7 +1810,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       // scans' barriers order the sums written in pass B before these reads)
       const WAKE_GLOBAL D2* const gtab = reinterpret_cast<const WAKE_GLOBAL D2*>(gptr(I.grid_tab)) +
                                          (I.grid_off ? 3 * gofs : 0);
-      WAKE_GLOBAL double* const gout = gptr(I.grid) + 4 * gofs;
+      WAKE_GLOBAL double* const gout = gptr(I.grid) + 5 * gofs;
       #pragma unroll 1
       for (int g = g_begin + tid; g < g_end; g += NT) {
         const double r = grid_node_r(g, dgB, grB);
@@ -1797,7 +1820,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         } else {
           t0 = gtab[3 * g]; t1 = gtab[3 * g + 1]; t2 = gtab[3 * g + 2];
         }
-        const D2 sS = gscr[4 * g], sP = gscr[4 * g + 1];
+        const D2 sS = gscr[GS * g], sP = gscr[GS * g + 1];
         grid_node_psi(gout, ngB, g, r, t0, t1, t2, dd{sS.x, sS.y}, dd{sP.x, sP.y}, psi_axis);
         double lam = 0.0;
         if (bm > 0) {
@@ -1896,23 +1919,41 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     }
     if (cnt > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
     // field grid: ge_hi the last node at or below the current ring, ge_top
-    // its radius (a previous ring below it means the interval owns nodes)
+    // its radius (a previous ring below it means the interval owns nodes).
+    // chi (fixed node sets): the nodes also take the sums of c = w / psibar
+    // and c rho at and above them within this chunk, and who handed them.
+    const bool chi = GRID && ngB > 0 && !I.grid_off;
+    GridNodes GN;
+    GN.rad = grB;
+    GN.dg = dgB;
+    GN.idg = idgB;
+    GN.nr = ngB;
+    GN.nh = chi ? ngB + 1 : ngB;
+    GN.top = 0.0;
+    if (chi) {
+      const double rl = grid_node_r(ngB - 1, dgB, grB);
+      GN.top = ngB > 1 ? rl + (rl - grid_node_r(ngB - 2, dgB, grB)) : 2.0 * rl;
+    }
+    const double owner = (double)(member * NT + tid);
+    dd cg0 = {0.0, 0.0}, cg1 = {0.0, 0.0};
     int ge_hi = -1;
     double ge_top = -INFINITY, g_lo_r = -1.0;
     if (GRID && ngB > 0 && cnt > 0) {
       if (tid > 0) g_lo_r = Sc.ld(RS_RU, WAKE_SLOT((unsigned)((C - 1) * NT + tid - 1))).x;
       else if (CL) g_lo_r = rho_mprev;
-      ge_hi = grid_last_below(y_ru.x, dgB, idgB, ngB, grB);
+      ge_hi = GN.last_below(y_ru.x);
       if (p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
         // nodes beyond the last ring: interval N (a_N = 0, no ring outside)
         const double a = (ha * E - ga * D) * iW, b = (hb * E - gb * D) * iW;
         #pragma unroll 1
-        for (int g = ge_hi + 1; g < ngB; ++g) {
-          gscr[4 * g + 2] = d2(Vgt, a);
-          gscr[4 * g + 3] = d2(b, 0.0);
+        for (int g = ge_hi + 1; g < GN.nh; ++g) {
+          gscr[GS * g + 2] = d2(Vgt, a);
+          gscr[GS * g + 3] = d2(b, owner);
+          gscr[GS * g + 4] = d2(0.0, 0.0);
+          gscr[GS * g + 5] = d2(0.0, 0.0);
         }
       }
-      ge_top = ge_hi >= 0 ? grid_node_r(ge_hi, dgB, grB) : -INFINITY;
+      ge_top = ge_hi >= 0 ? GN.r(ge_hi) : -INFINITY;
     }
     #pragma unroll 1
     for (int k = cnt - 1; k >= 0; --k) {
@@ -2005,17 +2046,24 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       }
       Vgt += L.v;
       if (GRID) {
+        if (chi) {
+          const double c = w * L.ipb;
+          cg0 = dd_add_d(cg0, c);
+          cg1 = dd_add(cg1, two_prod(c, rho));
+        }
         const double rlo = k > 0 ? y_ru.x : g_lo_r;
         if (rlo < ge_top) {
           // nodes of interval p = (rho_{p-1}, rho_p]
-          const int glo = grid_last_below(rlo, dgB, idgB, ngB, grB) + 1;
+          const int glo = GN.last_below(rlo) + 1;
           #pragma unroll 1
           for (int g = glo; g <= ge_hi; ++g) {
-            gscr[4 * g + 2] = d2(Vgt, a);
-            gscr[4 * g + 3] = d2(b, 0.0);
+            gscr[GS * g + 2] = d2(Vgt, a);
+            gscr[GS * g + 3] = d2(b, owner);
+            gscr[GS * g + 4] = d2(cg0.hi, cg0.lo);
+            gscr[GS * g + 5] = d2(cg1.hi, cg1.lo);
           }
           ge_hi = glo - 1;
-          ge_top = ge_hi >= 0 ? grid_node_r(ge_hi, dgB, grB) : -INFINITY;
+          ge_top = ge_hi >= 0 ? GN.r(ge_hi) : -INFINITY;
         }
       }
     }
@@ -2037,12 +2085,91 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (s_misc[63] != 0.0) end = n + 1;
     if (GRID && ngB > 0) {
       // E_z and B_theta at this member's nodes (after the barrier above)
-      WAKE_GLOBAL double* const gout = gptr(I.grid) + 4 * gofs;
+      WAKE_GLOBAL double* const gout = gptr(I.grid) + 5 * gofs;
       #pragma unroll 1
       for (int g = g_begin + tid; g < g_end; g += NT) {
         const double r = grid_node_r(g, dgB, grB);
-        const D2 e0 = gscr[4 * g + 2], e1 = gscr[4 * g + 3];
+        const D2 e0 = gscr[GS * g + 2], e1 = gscr[GS * g + 3];
         grid_node_b(gout, ngB, g, r, e0.x, e0.y, e1.x, gout[3 * ngB + g]);
+      }
+      if (chi) {
+        // chi = n/gamma (reading R20): each node's owner adds the sums of
+        // the chunks after its own; the hats' sums are differences of the
+        // full sums D, E (c and c rho at and above a node) of neighbouring
+        // nodes
+        Pack<4> tot;
+        const Pack<4> later = block_suffix<NT, 4>(Pack<4>{{cg0.hi, cg0.lo, cg1.hi, cg1.lo}},
+                                                  Pack<4>{{0.0, 0.0, 0.0, 0.0}}, DD2Op(), s_scanA, tot);
+        WAKE_GLOBAL double* const thr = gptr(I.grid_thr);
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) thr[4 * (size_t)(member * NT + tid) + i] = later.v[i];
+        dd all0 = {tot.v[0], tot.v[1]}, all1 = {tot.v[2], tot.v[3]};
+        const double* msuf = nullptr;          // sums of the members after each member
+        if (CL) {
+          // member totals (the fenced form: the nodes' partial sums and the
+          // threads' suffixes become visible to every member)
+          if (!cl_gather<4, true>(cl, tot, s_x, s_ok)) {
+            if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
+            return;
+          }
+          if (tid == 0) {
+            Pack<4> run = {{0.0, 0.0, 0.0, 0.0}};
+            for (int m = cl.G - 1; m >= 0; --m) {
+              const Pack<4> x = {{s_x[4 * m], s_x[4 * m + 1], s_x[4 * m + 2], s_x[4 * m + 3]}};
+              #pragma unroll
+              for (int i = 0; i < 4; ++i) s_x[4 * m + i] = run.v[i];
+              run = DD2Op()(x, run);
+            }
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) s_x[4 * cl.G + i] = run.v[i];
+          }
+          __syncthreads();
+          all0 = {s_x[4 * cl.G], s_x[4 * cl.G + 1]};
+          all1 = {s_x[4 * cl.G + 2], s_x[4 * cl.G + 3]};
+          msuf = s_x;
+        } else {
+          __syncthreads();
+        }
+        const int n_thr = (CL ? cl.G : 1) * NT;
+        auto full = [&](int x, dd& d0, dd& d1) {
+          const D2 o = gscr[GS * x + 3], p0s = gscr[GS * x + 4], p1s = gscr[GS * x + 5];
+          // every node is handed over each slice; the bound keeps a node
+          // left unhanded (radii that are not numbers) inside the arrays
+          const int ow = (o.y >= 0.0 && o.y < (double)(n_thr)) ? (int)o.y : 0;
+          const WAKE_GLOBAL double* t = thr + 4 * (size_t)ow;
+          d0 = dd_add({p0s.x, p0s.y}, {t[0], t[1]});
+          d1 = dd_add({p1s.x, p1s.y}, {t[2], t[3]});
+          if (CL) {
+            const double* ms = msuf + 4 * (ow / NT);
+            d0 = dd_add(d0, {ms[0], ms[1]});
+            d1 = dd_add(d1, {ms[2], ms[3]});
+          }
+        };
+        #pragma unroll 1
+        for (int g = g_begin + tid; g < g_end; g += NT) {
+          const double rg = GN.r(g), rp = GN.r(g + 1);
+          dd D0g, D1g, D0p, D1p;
+          full(g, D0g, D1g);
+          full(g + 1, D0p, D1p);
+          // above the node: sum over [r_g, r_+) of c (r_+ - rho) / (r_+ - r_g)
+          dd up = dd_sub(dd_mul_d(dd_sub(D0g, D0p), rp), dd_sub(D1g, D1p));
+          up = dd_div_d(up, rp - rg);
+          dd lowr;
+          double V;
+          if (g == 0) {                        // inside the first node: all of it
+            lowr = dd_sub(all0, D0g);
+            V = 0.5 * rg * rg;
+          } else {
+            const double rm = GN.r(g - 1);
+            dd D0m, D1m;
+            full(g - 1, D0m, D1m);
+            lowr = dd_sub(dd_sub(D1m, D1g), dd_mul_d(dd_sub(D0m, D0g), rm));
+            lowr = dd_div_d(lowr, rg - rm);
+            V = (rg - rm) * (rm + 2.0 * rg) / 6.0;
+          }
+          V += (rp - rg) * (2.0 * rg + rp) / 6.0;
+          gout[4 * ngB + g] = dd_round(dd_div_d(dd_add(lowr, up), V));
+        }
       }
     }
     if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))

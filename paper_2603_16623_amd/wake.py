@@ -79,6 +79,7 @@ _SIGS = {
     "wake_set_grid_radii": (_I, [_P, _I64, _P, _P]),
     "wake_set_grid_beam": (_I, [_P]),
     "wake_grid_nodes": (_I, [_P, _I, C.POINTER(_I64), _P]),
+    "wake_grid_chi": (_I, [_P, _I, _P, _I]),
     "wake_get_state": (_I, [_P, C.POINTER(_I), _P, _P, _P, _P, _I]),
     "wake_set_state": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "wake_reset": (_I, [_P]),
@@ -427,6 +428,15 @@ class WakeSolver:
             out = {k: np.empty(n.value) for k in names}
         ptrs = [_ptr(out.get(k)) for k in names]
         _check(self._lib.wake_grid_fields(self.h, slice_, *ptrs, int(device)), "wake_grid_fields")
+        return out
+
+    def wake_grid_chi(self, slice_: int = -1):
+        """chi = n/gamma at the grid nodes of a slice (uniform or fixed radii)."""
+        at = slice_ if slice_ >= 0 else max(self.wake_status()[1] - 1, 0)
+        n = _I64()
+        _check(self._lib.wake_grid_nodes(self.h, at, C.byref(n), None), "wake_grid_nodes")
+        out = np.empty(n.value)
+        _check(self._lib.wake_grid_chi(self.h, slice_, out.ctypes.data, 0), "wake_grid_chi")
         return out
 
     def wake_lineout(self):

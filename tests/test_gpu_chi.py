@@ -1,0 +1,133 @@
+"""GPU parity of chi = n/gamma on the field grid (reading R20) against the
+oracle's chi_at, through the C ABI: per slice on identical state at 1e-12 of
+max |chi| of the slice, end to end (linear regime) at 1e-8, and the rest
+state's closed form (a uniform column deposits 1).
+"""
+import numpy as np
+import pytest
+
+from oracle.wake_oracle import RingOracle, grid_radii
+from paper_2603_16623_amd import workloads as W
+from parity import TOL_E2E, TOL_SLICE, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wk():
+    from paper_2603_16623_amd import wake
+    wake.load()
+    yield wake
+    wake.wake_set_cluster(0, 0)
+    wake.wake_set_tiling(512, 0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _oracle(inst):
+    return RingOracle(inst.r0, inst.dr, inst.dxi, inst.n_xi, inst.sources, inst.dens)
+
+
+def _check(wk, inst, tiling, cluster, setup, radii, slices, layout=None):
+    o = _oracle(inst)
+    wk.wake_set_tiling(*tiling)
+    wk.wake_set_cluster(*cluster)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    if layout is not None:
+        assert s.layout() == layout
+    setup(s)
+    state = o.initial_state()
+    at = 0
+    worst = 0.0
+    for n in slices:
+        for m in range(at, n):
+            _, state = o.slice(m, state)
+        at = n
+        ref, _ = o.slice(n, state, keep=True)
+        assert ref["status"] == 0
+        want = o.chi_at(ref, radii)
+        s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(n, 1)
+        got = s.wake_grid_chi(n)
+        assert np.array_equal(s.wake_grid_chi(-1), got)
+        m = float(np.max(np.abs(got - want))) / (TOL_SLICE * float(np.max(np.abs(want))))
+        worst = max(worst, m)
+        _say(f"  chi margin {inst.name} tiling={tiling} slice={n}: {m:.3g} (max chi {np.max(want):.4g})")
+        assert m <= 1.0, (n, m)
+    wk.wake_set_cluster(0, 0)
+    s.close()
+    return worst
+
+
+def test_chi_slice_parity_uniform_grids(wk):
+    """300 geometric rings at two tilings (nodes inside the first ring,
+    between rings, beyond the plasma); 700 rings of a parabolic channel with
+    a laser under a grid finer than the rings near the axis (nodes whose
+    hats hold no ring deposit 0)."""
+    inst = W.small_instance(7, n_rings=300, n_xi=200, n_peak=4.0, sigma_r=0.1, dxi=0.01)
+    for tiling in ((256, 0), (1024, 0)):
+        _check(wk, inst, tiling, (0, 0), lambda s: s.wake_set_grid(97, 4.5), grid_radii(97, 4.5),
+               (0, 60, 130, 199))
+    inst = W.small_instance(10, n_rings=700, n_xi=200, n_peak=1.0, laser=True, dxi=0.01,
+                            channel_w0=2.0)
+    _check(wk, inst, (512, 0), (0, 0), lambda s: s.wake_set_grid(3000, 3.3), grid_radii(3000, 3.3),
+           (0, 50, 120, 190))
+
+
+def test_chi_slice_parity_explicit_radii_and_cooperative(wk):
+    rng = np.random.default_rng(51)
+    inst = W.small_instance(8, n_rings=257, n_xi=200, n_peak=1.0, laser=True, dxi=0.01)
+    radii = np.unique(np.exp(rng.uniform(np.log(2e-3), np.log(4.0), 150)))
+    _check(wk, inst, (512, 0), (0, 0), lambda s: s.wake_set_grid_radii(radii), radii, (0, 40, 100, 170))
+    one = np.array([0.7])                                  # a single node: its hat to 1.4
+    _check(wk, inst, (512, 0), (0, 0), lambda s: s.wake_set_grid_radii(one), one, (100,))
+    inst = W.small_instance(5, n_rings=3000, n_xi=60, n_peak=3.0, sigma_r=0.2, geometric=False,
+                            dxi=0.02)
+    _check(wk, inst, (256, 0), (2, 500), lambda s: s.wake_set_grid(1201, 3.6), grid_radii(1201, 3.6),
+           (0, 25, 50), layout=(6, 2))
+
+
+def test_chi_of_a_column_at_rest_is_one(wk):
+    """No sources: the column stays at rest and chi = 1 at every node off the
+    axis (the closed form of the deposit), within 6e-4 at the first."""
+    wk.wake_set_tiling(512, 0)
+    r0, dr = W.uniform_rings(1000, 5.0)
+    s = wk.WakeSolver(r0, dr, 0.02, 5, [], record_stride=1)
+    s.wake_set_grid(50, 4.0)
+    s.wake_solve(0, 5)
+    for n in range(5):
+        chi = s.wake_grid_chi(n)
+        assert np.max(np.abs(chi[1:] - 1.0)) <= 1e-13, n
+        assert abs(chi[0] - 1.0) <= 6.1e-4
+    s.close()
+
+
+def test_chi_linear_end_to_end(wk):
+    """Linear driver, 1000 rings x 1200 slices, 64 nodes to r = 6: every
+    slice's chi within 1e-8 of the oracle's."""
+    wk.wake_set_tiling(512, 0)
+    inst = W.config1()
+    _say("chi e2e linear 1000x1200")
+    ref = _oracle(inst).run(record_stride=0, grid=(64, 6.0))
+    s = wk.WakeSolver.from_instance(inst)
+    s.wake_set_grid(64, 6.0)
+    s.wake_solve(0, inst.n_xi)
+    got = np.stack([s.wake_grid_chi(n) for n in range(inst.n_xi)])
+    r = rel(got, ref["chi"])
+    _say(f"  chi e2e worst rel {r:.3g}")
+    assert r <= TOL_E2E
+    s.close()
+
+
+def test_chi_refused_for_per_slice_node_sets(wk):
+    wk.wake_set_tiling(512, 0)
+    inst = W.small_instance(9, n_rings=400, n_xi=30, n_peak=3.0, sigma_r=0.2, dxi=0.02)
+    s = wk.WakeSolver.from_instance(inst)
+    s.wake_set_grid_beam()
+    s.wake_solve(0, 30)
+    with pytest.raises(wk.WakeError) as e:
+        s.wake_grid_chi(20)
+    assert e.value.code == wk.WAKE_ESTATE
+    s.close()
