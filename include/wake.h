@@ -181,10 +181,16 @@ int wake_set_grid(wake_ctx *ctx, int32_t n_r, double r_max);
  * nodes (a ring inside the first node wholly to it; the last node's hat
  * reaching as far above it as the spacing below it) and normalised by each
  * hat's integral of rho drho, so that a uniform plasma at rest gives 1.
- * Slice and errors as wake_grid_fields; WAKE_ESTATE for per-slice node sets
+ * Slice and errors as wake_grid_fields; WAKE_ESTATE unless the deposit was
+ * switched on (wake_set_grid_chi) and for per-slice node sets
  * (wake_set_grid_radii with offsets, wake_set_grid_beam), which deposit no
  * chi.  Synchronizes. */
 int wake_grid_chi(wake_ctx *ctx, int32_t slice, double *chi, int32_t dst_is_device);
+/* Switch the chi deposit on (on != 0) or off for the context's grids (off
+ * after wake_create; Fig. 2 deposits chi when there is a laser).  Only
+ * before the first solve and while no batch holds the context
+ * (WAKE_ESTATE). */
+int wake_set_grid_chi(wake_ctx *ctx, int32_t on);
 
 /* Field grid at radii the caller gives (Sec. "Key algorithmic adjustments":
  * the sums give the plasma fields at any radius, so they can be sampled with

@@ -667,7 +667,8 @@ static int launch_one(wake_ctx* c, int first, int count) {
   I.count = count;
   I.task0 = 0;
   HIP_TRY(hipMemcpyAsync(c->d_inst, &I, sizeof(WakeInst), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_march(I.nt, c->d_inst, 1, I.G, c->d_counter, I.G, I.grid_n > 0, c->stream));
+  const int mode = I.grid_n > 0 ? (I.grid_chi && !I.grid_off ? 2 : 1) : 0;
+  HIP_TRY(launch_march(I.nt, c->d_inst, 1, I.G, c->d_counter, I.G, mode, c->stream));
   return WAKE_OK;
 }
 
@@ -1034,10 +1035,20 @@ extern "C" int wake_grid_fields(wake_ctx* c, int32_t slice, double* psi, double*
   return WAKE_OK;
 }
 
+extern "C" int wake_set_grid_chi(wake_ctx* c, int32_t on) {
+  if (!c || c->two_species) return WAKE_EINVAL;
+  if (c->next != 0 || c->batches > 0) return WAKE_ESTATE;
+  HIP_TRY(hipSetDevice(c->device));
+  int r = drain(c);
+  if (r != WAKE_OK) return r;
+  c->I.grid_chi = on ? 1 : 0;
+  return WAKE_OK;
+}
+
 extern "C" int wake_grid_chi(wake_ctx* c, int32_t slice, double* chi, int32_t dev) {
   if (!c) return WAKE_EINVAL;
   const WakeInst& I = c->I;
-  if (!c->grid_mem || !c->grid_off_h.empty()) return WAKE_ESTATE;
+  if (!c->grid_mem || !c->grid_off_h.empty() || !I.grid_chi) return WAKE_ESTATE;
   int32_t ctl[CTL_NWORDS];
   int r = read_ctl(c, ctl);
   if (r != WAKE_OK) return r;
@@ -1342,13 +1353,17 @@ hipError_t launch_insts(const std::vector<WakeInst>& v, const WakeInst* d_insts,
   for (const WakeInst& I : v) n_tasks += I.G;
   for (int nt : kThreads) {
     int n = 0, gmax = 1;
-    bool with_grid = false;
+    int mode = 0;
     for (const WakeInst& I : v)
-      if (I.nt == nt) { n += I.G; gmax = std::max(gmax, (int)I.G); with_grid |= I.grid_n > 0; }
+      if (I.nt == nt) {
+        n += I.G;
+        gmax = std::max(gmax, (int)I.G);
+        if (I.grid_n > 0) mode = std::max(mode, I.grid_chi && !I.grid_off ? 2 : 1);
+      }
     if (n == 0) continue;
     int g = grid_override > 0 ? std::min(grid_override, n) : march_grid(nt, n, dev);
     g = std::max(g, gmax);
-    hipError_t e = launch_march(nt, d_insts, (int)v.size(), n_tasks, d_counter, g, with_grid, s);
+    hipError_t e = launch_march(nt, d_insts, (int)v.size(), n_tasks, d_counter, g, mode, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

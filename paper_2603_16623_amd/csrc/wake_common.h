@@ -133,9 +133,11 @@ struct WakeInst {
   // most nodes a slice has
   const double *grid_rad;
   const int32_t *grid_off;
-  // chi deposit on fixed node sets: per thread of the instance (G nt of
-  // them), the sums of c and c rho of the chunks after its own (dd pairs)
+  // chi deposit on fixed node sets (when grid_chi is set): per thread of the
+  // instance (G nt of them), the sums of c and c rho of the chunks after its
+  // own (dd pairs)
   double *grid_thr;
+  int32_t grid_chi;
 };
 
 // Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c

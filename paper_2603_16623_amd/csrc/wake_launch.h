@@ -28,10 +28,13 @@ hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipSt
 // marcher: workgroups of nt threads (256, 512 or 1024)
 bool march_threads_ok(int nt);
 size_t march_lds_bytes(int nt);
-// with_grid: the variant that also evaluates the fields at the instances'
-// grid nodes (instances without a grid march as in the plain variant)
+// grid_mode: 0 the plain variant; 1 the variant that also evaluates the
+// fields at the instances' grid nodes; 2 that one with the chi deposit (for
+// instances whose grid deposits chi).  Instances without a grid march in the
+// grid variants as in the plain one, instances without the deposit in
+// variant 2 as in variant 1.
 hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
-                        int grid, bool with_grid, hipStream_t s);
+                        int grid, int grid_mode, hipStream_t s);
 // field-grid node records of I's grid (ln r_g, ion fields at r_g) for its
 // n_entries nodes (per-slice node sets: every entry)
 hipError_t launch_grid_init(const WakeInst& I, double* tab, int n_entries, hipStream_t s);

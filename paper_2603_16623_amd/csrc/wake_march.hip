@@ -1328,6 +1328,58 @@ __device__ __forceinline__ void grid_node_b(WAKE_GLOBAL double* out, int ng, int
   out[3 * ng + g] = bb + (a * r + b * ir);
 }
 
+// chi = n/gamma (reading R20) at the nodes g0, g0 + NT, ... below g1 of a
+// slice: a node's full sums D, E of c = w / psibar and c rho at and above it
+// are its owner's partial sums plus the owner's later chunks (thr) and, on a
+// cooperative instance, the later members (msuf, in LDS); the hats' sums are
+// differences of neighbouring nodes' full sums (the virtual node past the
+// last included), over the hats' volumes.  all0: the sum of c over every
+// ring.  Not inlined: its temporaries stay out of the march's registers.
+template <int NT, bool CL>
+__device__ __noinline__ void chi_nodes(WAKE_GLOBAL double* gout, int ngB, const WAKE_GLOBAL D2* gscr,
+                                       const WAKE_GLOBAL double* thr, const double* msuf, int n_thr,
+                                       GridNodes GN, int g0, int g1, dd all0) {
+  auto full = [&](int x, dd& d0, dd& d1) {
+    const D2 o = gscr[GS * x + 3], p0s = gscr[GS * x + 4], p1s = gscr[GS * x + 5];
+    // every node is handed over each slice; the bound keeps a node left
+    // unhanded (radii that are not numbers) inside the arrays
+    const int ow = (o.y >= 0.0 && o.y < (double)(n_thr)) ? (int)o.y : 0;
+    const WAKE_GLOBAL double* t = thr + 4 * (size_t)ow;
+    d0 = dd_add({p0s.x, p0s.y}, {t[0], t[1]});
+    d1 = dd_add({p1s.x, p1s.y}, {t[2], t[3]});
+    if (CL) {
+      const double* ms = msuf + 4 * (ow / NT);
+      d0 = dd_add(d0, {ms[0], ms[1]});
+      d1 = dd_add(d1, {ms[2], ms[3]});
+    }
+  };
+  #pragma unroll 1
+  for (int g = g0; g < g1; g += NT) {
+    const double rg = GN.r(g), rp = GN.r(g + 1);
+    dd D0g, D1g, D0p, D1p;
+    full(g, D0g, D1g);
+    full(g + 1, D0p, D1p);
+    // above the node: sum over [r_g, r_+) of c (r_+ - rho) / (r_+ - r_g)
+    dd up = dd_sub(dd_mul_d(dd_sub(D0g, D0p), rp), dd_sub(D1g, D1p));
+    up = dd_div_d(up, rp - rg);
+    dd lowr;
+    double V;
+    if (g == 0) {                        // inside the first node: all of it
+      lowr = dd_sub(all0, D0g);
+      V = 0.5 * rg * rg;
+    } else {
+      const double rm = GN.r(g - 1);
+      dd D0m, D1m;
+      full(g - 1, D0m, D1m);
+      lowr = dd_sub(dd_sub(D1m, D1g), dd_mul_d(dd_sub(D0m, D0g), rm));
+      lowr = dd_div_d(lowr, rg - rm);
+      V = (rg - rm) * (rm + 2.0 * rg) / 6.0;
+    }
+    V += (rp - rg) * (2.0 * rg + rp) / 6.0;
+    gout[4 * ngB + g] = dd_round(dd_div_d(dd_add(lowr, up), V));
+  }
+}
+
 // charge of the analytic beams inside r (staged constants of the slice)
 __device__ __forceinline__ double analytic_lam(const double* s_misc, int n_an, double r) {
   double lam = 0.0;
@@ -1337,8 +1389,11 @@ __device__ __forceinline__ double analytic_lam(const double* s_misc, int n_an, d
   return lam;
 }
 
-template <int NT, bool CL, bool GRID>
+template <int NT, bool CL, int GM>
 __device__ __forceinline__ void march(const WakeInst& I, int member, const int32_t* queue, unsigned char* smem) {
+  // GM: 0 no field grid, 1 field grid, 2 field grid with the chi deposit
+  constexpr bool GRID = GM > 0;
+  constexpr bool CHI = GM > 1;
   constexpr int NW = NT / 64;
   constexpr int CMAX = MarchLds<NT>::CMAX;
   constexpr int KCAP = MarchLds<NT>::KCAP;
@@ -1922,7 +1977,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     // its radius (a previous ring below it means the interval owns nodes).
     // chi (fixed node sets): the nodes also take the sums of c = w / psibar
     // and c rho at and above them within this chunk, and who handed them.
-    const bool chi = GRID && ngB > 0 && !I.grid_off;
+    const bool chi = CHI && ngB > 0 && !I.grid_off && I.grid_chi;
     GridNodes GN;
     GN.rad = grB;
     GN.dg = dgB;
@@ -1949,8 +2004,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         for (int g = ge_hi + 1; g < GN.nh; ++g) {
           gscr[GS * g + 2] = d2(Vgt, a);
           gscr[GS * g + 3] = d2(b, owner);
-          gscr[GS * g + 4] = d2(0.0, 0.0);
-          gscr[GS * g + 5] = d2(0.0, 0.0);
+          if (CHI) {
+            gscr[GS * g + 4] = d2(0.0, 0.0);
+            gscr[GS * g + 5] = d2(0.0, 0.0);
+          }
         }
       }
       ge_top = ge_hi >= 0 ? GN.r(ge_hi) : -INFINITY;
@@ -2046,7 +2103,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       }
       Vgt += L.v;
       if (GRID) {
-        if (chi) {
+        if (CHI && chi) {
           const double c = w * L.ipb;
           cg0 = dd_add_d(cg0, c);
           cg1 = dd_add(cg1, two_prod(c, rho));
@@ -2059,8 +2116,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
           for (int g = glo; g <= ge_hi; ++g) {
             gscr[GS * g + 2] = d2(Vgt, a);
             gscr[GS * g + 3] = d2(b, owner);
-            gscr[GS * g + 4] = d2(cg0.hi, cg0.lo);
-            gscr[GS * g + 5] = d2(cg1.hi, cg1.lo);
+            if (CHI) {
+              gscr[GS * g + 4] = d2(cg0.hi, cg0.lo);
+              gscr[GS * g + 5] = d2(cg1.hi, cg1.lo);
+            }
           }
           ge_hi = glo - 1;
           ge_top = ge_hi >= 0 ? GN.r(ge_hi) : -INFINITY;
@@ -2092,7 +2151,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         const D2 e0 = gscr[GS * g + 2], e1 = gscr[GS * g + 3];
         grid_node_b(gout, ngB, g, r, e0.x, e0.y, e1.x, gout[3 * ngB + g]);
       }
-      if (chi) {
+      if (CHI && chi) {
         // chi = n/gamma (reading R20): each node's owner adds the sums of
         // the chunks after its own; the hats' sums are differences of the
         // full sums D, E (c and c rho at and above a node) of neighbouring
@@ -2103,7 +2162,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         WAKE_GLOBAL double* const thr = gptr(I.grid_thr);
         #pragma unroll
         for (int i = 0; i < 4; ++i) thr[4 * (size_t)(member * NT + tid) + i] = later.v[i];
-        dd all0 = {tot.v[0], tot.v[1]}, all1 = {tot.v[2], tot.v[3]};
+        dd all0 = {tot.v[0], tot.v[1]};
         const double* msuf = nullptr;          // sums of the members after each member
         if (CL) {
           // member totals (the fenced form: the nodes' partial sums and the
@@ -2125,51 +2184,11 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
           }
           __syncthreads();
           all0 = {s_x[4 * cl.G], s_x[4 * cl.G + 1]};
-          all1 = {s_x[4 * cl.G + 2], s_x[4 * cl.G + 3]};
           msuf = s_x;
         } else {
           __syncthreads();
         }
-        const int n_thr = (CL ? cl.G : 1) * NT;
-        auto full = [&](int x, dd& d0, dd& d1) {
-          const D2 o = gscr[GS * x + 3], p0s = gscr[GS * x + 4], p1s = gscr[GS * x + 5];
-          // every node is handed over each slice; the bound keeps a node
-          // left unhanded (radii that are not numbers) inside the arrays
-          const int ow = (o.y >= 0.0 && o.y < (double)(n_thr)) ? (int)o.y : 0;
-          const WAKE_GLOBAL double* t = thr + 4 * (size_t)ow;
-          d0 = dd_add({p0s.x, p0s.y}, {t[0], t[1]});
-          d1 = dd_add({p1s.x, p1s.y}, {t[2], t[3]});
-          if (CL) {
-            const double* ms = msuf + 4 * (ow / NT);
-            d0 = dd_add(d0, {ms[0], ms[1]});
-            d1 = dd_add(d1, {ms[2], ms[3]});
-          }
-        };
-        #pragma unroll 1
-        for (int g = g_begin + tid; g < g_end; g += NT) {
-          const double rg = GN.r(g), rp = GN.r(g + 1);
-          dd D0g, D1g, D0p, D1p;
-          full(g, D0g, D1g);
-          full(g + 1, D0p, D1p);
-          // above the node: sum over [r_g, r_+) of c (r_+ - rho) / (r_+ - r_g)
-          dd up = dd_sub(dd_mul_d(dd_sub(D0g, D0p), rp), dd_sub(D1g, D1p));
-          up = dd_div_d(up, rp - rg);
-          dd lowr;
-          double V;
-          if (g == 0) {                        // inside the first node: all of it
-            lowr = dd_sub(all0, D0g);
-            V = 0.5 * rg * rg;
-          } else {
-            const double rm = GN.r(g - 1);
-            dd D0m, D1m;
-            full(g - 1, D0m, D1m);
-            lowr = dd_sub(dd_sub(D1m, D1g), dd_mul_d(dd_sub(D0m, D0g), rm));
-            lowr = dd_div_d(lowr, rg - rm);
-            V = (rg - rm) * (rm + 2.0 * rg) / 6.0;
-          }
-          V += (rp - rg) * (2.0 * rg + rp) / 6.0;
-          gout[4 * ngB + g] = dd_round(dd_div_d(dd_add(lowr, up), V));
-        }
+        chi_nodes<NT, CL>(gout, ngB, gscr, thr, msuf, (CL ? cl.G : 1) * NT, GN, g_begin + tid, g_end, all0);
       }
     }
     if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))
@@ -2200,16 +2219,16 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
 
 // the cooperative march as a function of its own (its registers stay out of
 // the single-workgroup march, which is inlined into the kernel)
-template <int NT, bool GRID>
+template <int NT, int GM>
 __device__ __noinline__ void march_member(const WAKE_GLOBAL WakeInst* I, int member, const int32_t* queue) {
-  march<NT, true, GRID>(*(const WakeInst*)I, member, queue, wake_lds);
+  march<NT, true, GM>(*(const WakeInst*)I, member, queue, wake_lds);
 }
 
 #ifndef WAKE_WAVES_PER_EU
 #define WAKE_WAVES_PER_EU 2
 #endif
 // WAKE_WAVES_PER_EU waves per SIMD (2: up to 256 VGPRs per lane)
-template <int NT, bool GRID>
+template <int NT, int GM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WAKE_WAVES_PER_EU)))
 void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_tasks, int32_t* counter) {
   unsigned char* const smem = wake_lds;
@@ -2228,8 +2247,8 @@ void wake_march_kernel(const WakeInst* __restrict__ insts, int n_insts, int n_ta
     }
     const WakeInst& I = insts[lo];
     if (I.nt == NT) {
-      if (I.G > 1) march_member<NT, GRID>(as_global(I), idx - I.task0, counter);
-      else march<NT, false, GRID>(I, 0, counter, smem);
+      if (I.G > 1) march_member<NT, GM>(as_global(I), idx - I.task0, counter);
+      else march<NT, false, GM>(I, 0, counter, smem);
     }
     __syncthreads();
   }
@@ -2410,17 +2429,21 @@ size_t march_lds_bytes(int nt) {
 }
 
 hipError_t launch_march(int nt, const WakeInst* d_insts, int n_insts, int n_tasks, int32_t* counter,
-                        int grid, bool with_grid, hipStream_t s) {
+                        int grid, int grid_mode, hipStream_t s) {
 #define X(a)                                                                                      \
   if (nt == a) {                                                                                  \
     hipLaunchKernelGGL(counter_zero_kernel, dim3(1), dim3(64), 0, s, counter);                     \
     hipLaunchKernelGGL(cluster_reset_kernel, dim3(1), dim3(256), 0, s, d_insts, n_insts);          \
-    if (with_grid)                                                                                \
-      hipLaunchKernelGGL((wake_march_kernel<a, true>), dim3(grid), dim3(a),                       \
+    if (grid_mode == 2)                                                                           \
+      hipLaunchKernelGGL((wake_march_kernel<a, 2>), dim3(grid), dim3(a),                          \
+                         MarchLds<a>::bytes() + grid_lds_bytes<a>(), s, d_insts, n_insts, n_tasks, \
+                         counter);                                                                \
+    else if (grid_mode == 1)                                                                      \
+      hipLaunchKernelGGL((wake_march_kernel<a, 1>), dim3(grid), dim3(a),                          \
                          MarchLds<a>::bytes() + grid_lds_bytes<a>(), s, d_insts, n_insts, n_tasks, \
                          counter);                                                                \
     else                                                                                          \
-      hipLaunchKernelGGL((wake_march_kernel<a, false>), dim3(grid), dim3(a), MarchLds<a>::bytes(),\
+      hipLaunchKernelGGL((wake_march_kernel<a, 0>), dim3(grid), dim3(a), MarchLds<a>::bytes(),    \
                          s, d_insts, n_insts, n_tasks, counter);                                  \
     return hipGetLastError();                                                                     \
   }
@@ -2441,7 +2464,7 @@ int march_occupancy(int nt) {
   int nb = 0;
 #define X(a)                                                                                      \
   if (nt == a) {                                                                                  \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wake_march_kernel<a, false>, a,         \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wake_march_kernel<a, 0>, a,         \
                                                      MarchLds<a>::bytes()) != hipSuccess)         \
       return 0;                                                                                   \
     return nb;                                                                                    \
@@ -2454,11 +2477,15 @@ int march_occupancy(int nt) {
 hipError_t march_prepare(int nt) {
 #define X(a)                                                                                      \
   if (nt == a) {                                                                                  \
-    hipError_t e = hipFuncSetAttribute((const void*)wake_march_kernel<a, false>,                  \
+    hipError_t e = hipFuncSetAttribute((const void*)wake_march_kernel<a, 0>,                      \
                                        hipFuncAttributeMaxDynamicSharedMemorySize,                \
                                        (int)MarchLds<a>::bytes());                                \
     if (e != hipSuccess) return e;                                                                \
-    return hipFuncSetAttribute((const void*)wake_march_kernel<a, true>,                           \
+    e = hipFuncSetAttribute((const void*)wake_march_kernel<a, 1>,                                 \
+                            hipFuncAttributeMaxDynamicSharedMemorySize,                           \
+                            (int)(MarchLds<a>::bytes() + grid_lds_bytes<a>()));                   \
+    if (e != hipSuccess) return e;                                                                \
+    return hipFuncSetAttribute((const void*)wake_march_kernel<a, 2>,                              \
                                hipFuncAttributeMaxDynamicSharedMemorySize,                        \
                                (int)(MarchLds<a>::bytes() + grid_lds_bytes<a>()));                \
   }

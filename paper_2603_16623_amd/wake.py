@@ -80,6 +80,7 @@ _SIGS = {
     "wake_set_grid_beam": (_I, [_P]),
     "wake_grid_nodes": (_I, [_P, _I, C.POINTER(_I64), _P]),
     "wake_grid_chi": (_I, [_P, _I, _P, _I]),
+    "wake_set_grid_chi": (_I, [_P, _I]),
     "wake_get_state": (_I, [_P, C.POINTER(_I), _P, _P, _P, _P, _I]),
     "wake_set_state": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "wake_reset": (_I, [_P]),
@@ -429,6 +430,10 @@ class WakeSolver:
         ptrs = [_ptr(out.get(k)) for k in names]
         _check(self._lib.wake_grid_fields(self.h, slice_, *ptrs, int(device)), "wake_grid_fields")
         return out
+
+    def wake_set_grid_chi(self, on: bool = True):
+        """Deposit chi = n/gamma on the context's grids (off by default)."""
+        _check(self._lib.wake_set_grid_chi(self.h, int(bool(on))), "wake_set_grid_chi")
 
     def wake_grid_chi(self, slice_: int = -1):
         """chi = n/gamma at the grid nodes of a slice (uniform or fixed radii)."""

@@ -38,6 +38,7 @@ def _check(wk, inst, tiling, cluster, setup, radii, slices, layout=None):
     if layout is not None:
         assert s.layout() == layout
     setup(s)
+    s.wake_set_grid_chi(True)
     state = o.initial_state()
     at = 0
     worst = 0.0
@@ -96,6 +97,7 @@ def test_chi_of_a_column_at_rest_is_one(wk):
     r0, dr = W.uniform_rings(1000, 5.0)
     s = wk.WakeSolver(r0, dr, 0.02, 5, [], record_stride=1)
     s.wake_set_grid(50, 4.0)
+    s.wake_set_grid_chi(True)
     s.wake_solve(0, 5)
     for n in range(5):
         chi = s.wake_grid_chi(n)
@@ -113,6 +115,7 @@ def test_chi_linear_end_to_end(wk):
     ref = _oracle(inst).run(record_stride=0, grid=(64, 6.0))
     s = wk.WakeSolver.from_instance(inst)
     s.wake_set_grid(64, 6.0)
+    s.wake_set_grid_chi(True)
     s.wake_solve(0, inst.n_xi)
     got = np.stack([s.wake_grid_chi(n) for n in range(inst.n_xi)])
     r = rel(got, ref["chi"])
@@ -121,11 +124,22 @@ def test_chi_linear_end_to_end(wk):
     s.close()
 
 
-def test_chi_refused_for_per_slice_node_sets(wk):
+def test_chi_refused_for_per_slice_node_sets_and_when_off(wk):
     wk.wake_set_tiling(512, 0)
     inst = W.small_instance(9, n_rings=400, n_xi=30, n_peak=3.0, sigma_r=0.2, dxi=0.02)
     s = wk.WakeSolver.from_instance(inst)
     s.wake_set_grid_beam()
+    s.wake_set_grid_chi(True)
+    s.wake_solve(0, 30)
+    with pytest.raises(wk.WakeError) as e:
+        s.wake_grid_chi(20)
+    assert e.value.code == wk.WAKE_ESTATE
+    with pytest.raises(wk.WakeError) as e:
+        s.wake_set_grid_chi(False)                        # after the first solve
+    assert e.value.code == wk.WAKE_ESTATE
+    s.close()
+    s = wk.WakeSolver.from_instance(inst)                 # a grid without the deposit
+    s.wake_set_grid(40, 3.0)
     s.wake_solve(0, 30)
     with pytest.raises(wk.WakeError) as e:
         s.wake_grid_chi(20)
