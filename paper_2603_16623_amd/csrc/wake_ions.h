@@ -18,15 +18,14 @@ enum { IS_RHO = 0, IS_U, IS_FR, IS_FU, IS_N };
 // node tables of a species by slot: its own psi (dd), d_rho psi (dd) and
 // d_zeta psi at its rings; B^(p) at the electron rings
 enum { IT_PSH = 0, IT_PSL, IT_DPH, IT_DPL, IT_DZ, IT_BP, IT_N };
-// per-position work by slot: the ring's constants and state gathered at
-// the slice head (w, w^, r0, 1/r0, ln r0 (dd), dr, u_r, the AB2 history),
-// ln rho (dd), the fields (total of both species), psibar, gamma, sources,
-// the interpolation parameter t in the other species' node interval; for
-// the electrons the recursion's A_i, C_i, offset s_i, growing mode g before
-// ring i and the det-sum E before it
-enum { IW_W = 0, IW_WH, IW_R0, IW_IR0, IW_L0H, IW_L0L, IW_DR, IW_U, IW_FRP, IW_FUP, IW_LNH, IW_LNL,
-       IW_PSI, IW_DPSI, IW_DZ, IW_BT, IW_PB, IW_GM, IW_BB, IW_A2, IW_DA2, IW_T, IW_A, IW_C, IW_SA,
-       IW_SB, IW_GA, IW_GB, IW_E, IW_N };
+// per-position work by slot: the ring's weights and momentum gathered at
+// the slice head (w, w^, u_r), the fields (total of both species), psibar,
+// the beam field, the laser's |a|^2 and its gradient (with a laser only);
+// for the electrons the recursion's A_i, C_i, offset s_i, growing mode g
+// before ring i and the det-sum E before it.  ln rho, gamma and the
+// interpolation parameters are formed again where they are used.
+enum { IW_W = 0, IW_WH, IW_U, IW_PSI, IW_DPSI, IW_DZ, IW_BT, IW_PB, IW_BB, IW_A2, IW_DA2, IW_A, IW_C,
+       IW_SA, IW_SB, IW_GA, IW_GB, IW_E, IW_N };
 
 // One two-species instance as the kernels see it.  All pointers are device
 // pointers.  Species 0 are the electrons (q = -1, m = 1), species 1 the

@@ -47,13 +47,15 @@ constexpr int NW = NT / 64;
 constexpr int NMAX = WAKE_IONS_NMAX;
 
 // dynamic LDS: sorted radii of both species, sort ids, scan area, slice
-// constants (analytic source factors, then 16 scalars per species)
+// constants (analytic source factors, then 16 scalars per species), the
+// slice's beam-table radii (when at most WAKE_BCAP of them)
 struct IonsLds {
   static constexpr size_t r_off = 0;
   static constexpr size_t id_off = r_off + (size_t)2 * NMAX * sizeof(double);
   static constexpr size_t scan_off = id_off + (size_t)NMAX * sizeof(uint16_t);
   static constexpr size_t misc_off = scan_off + (size_t)NW * 16 * sizeof(double);
-  static constexpr size_t bytes = misc_off + 64 * sizeof(double);
+  static constexpr size_t br_off = misc_off + 64 * sizeof(double);
+  static constexpr size_t bytes = br_off + (size_t)WAKE_BCAP * sizeof(double);
 };
 static_assert(IonsLds::bytes <= 160 * 1024, "two-species LDS");
 
@@ -113,6 +115,21 @@ __device__ __forceinline__ bool interval_of(const double* ro, int N, double edge
   return true;
 }
 
+// ln rho of ring id at radius r as ln r0 + log1p((r - r0)/r0) (its rounding
+// scales with the ring's displacement, not with |ln rho|)
+__device__ __forceinline__ dd ring_log_id(const double* cst, int N, int id, double r) {
+  return dd_add_d({cst[IK_LNH * N + id], cst[IK_LNL * N + id]},
+                  log1p_fast((r - cst[IK_R0 * N + id]) * cst[IK_IR0 * N + id]));
+}
+
+// t of radius r in the node interval starting at node j of species o (the
+// same expression as interval_of)
+__device__ __forceinline__ double interval_t(const double* ro, int N, double edge, double r, int j) {
+  const double rl = j == 0 ? 0.0 : ro[j - 1];
+  const double rh = j < N ? ro[j] : edge;
+  return (r - rl) / (rh - rl);
+}
+
 __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restrict__ insts) {
   const WakeIons& I = insts[blockIdx.x];
   double* const s_r = reinterpret_cast<double*>(wake_lds + IonsLds::r_off);
@@ -120,6 +137,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
   double* const s_scan = reinterpret_cast<double*>(wake_lds + IonsLds::scan_off);
   double* const s_misc = reinterpret_cast<double*>(wake_lds + IonsLds::misc_off);
   double* const s_sc = s_misc + 32;
+  double* const s_br = reinterpret_cast<double*>(wake_lds + IonsLds::br_off);
 
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C;
@@ -133,6 +151,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
   const double dxi = I.dxi;
   const double* const cst = I.cst;
   const double m_ion = I.m_i;
+  const bool has_laser = I.has_laser != 0;   // else |a|^2 and its gradient are 0 (not stored)
   unsigned long long fixups = 0;
   int n = I.first;
   for (; n < end; ++n) {
@@ -152,6 +171,13 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         s_misc[3 * tid + 2] = 2.0 / (A.w0 * A.w0);
       }
     }
+    // this slice's beam-table radii into LDS (read after the order phase's
+    // barriers; the previous slice's reads ended at its last barrier)
+    const int bt0 = I.nb ? I.boff[n] : 0;
+    const int bm = I.nb ? I.boff[n + 1] - bt0 : 0;
+    const bool b_lds = bm <= WAKE_BCAP;
+    if (b_lds)
+      for (int i = tid; i < bm; i += NT) s_br[i] = I.br[bt0 + i];
     const double* const stc = I.st[cur];
     double* const stn = I.st[cur ^ 1];
 
@@ -184,8 +210,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
       int32_t* const sid = I.sid + (size_t)s * S;
       double* const wk = I.work + (size_t)s * IW_N * S;
       const double* const st_s = stc + (size_t)s * IS_N * N;
-      // each ring's constants and state into the slots of its position (all
-      // loads of a batch of positions issued before any is used)
+      // the ring's weights and momentum into the slots of its position (used
+      // by most phases; the rest is read through the ring id where needed)
       #pragma unroll 4
       for (int k = 0; k < cnt; ++k) {
         const int p = p0 + k;
@@ -198,14 +224,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         if (resort) ord[p] = id;
         wk[IW_W * S + sl] = cst[IK_W * N + id];
         wk[IW_WH * S + sl] = cst[IK_WH * N + id];
-        wk[IW_R0 * S + sl] = cst[IK_R0 * N + id];
-        wk[IW_IR0 * S + sl] = cst[IK_IR0 * N + id];
-        wk[IW_L0H * S + sl] = cst[IK_LNH * N + id];
-        wk[IW_L0L * S + sl] = cst[IK_LNL * N + id];
-        wk[IW_DR * S + sl] = cst[IK_DR * N + id];
         wk[IW_U * S + sl] = st_s[IS_U * N + id];
-        wk[IW_FRP * S + sl] = st_s[IS_FR * N + id];
-        wk[IW_FUP * S + sl] = st_s[IS_FU * N + id];
       }
       __syncthreads();              // s_id is the next species' too
     }
@@ -213,7 +232,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     // ---- own sums: psi and d_rho psi of each species at its rings ----
     dd sw[2], swl[2];
     for (int s = 0; s < 2; ++s) {
-      double* const wk = I.work + (size_t)s * IW_N * S;
+      const double* const wk = I.work + (size_t)s * IW_N * S;
+      const int32_t* const sid = I.sid + (size_t)s * S;
       const double* sr = s_r + s * NMAX;
       sw[s] = dd_make(0.0);
       swl[s] = dd_make(0.0);
@@ -221,10 +241,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
       for (int k = 0; k < cnt; ++k) {
         const unsigned sl = k * NT + tid;
         const double r = sr[p0 + k];
-        const double w = wk[IW_W * S + sl], r0 = wk[IW_R0 * S + sl], ir0 = wk[IW_IR0 * S + sl];
-        const dd lnr = dd_add_d({wk[IW_L0H * S + sl], wk[IW_L0L * S + sl]}, log1p_fast((r - r0) * ir0));
-        wk[IW_LNH * S + sl] = lnr.hi;
-        wk[IW_LNL * S + sl] = lnr.lo;
+        const double w = wk[IW_W * S + sl];
+        const dd lnr = ring_log_id(cst, N, sid[sl], r);
         sw[s] = dd_add_d(sw[s], w);
         swl[s] = dd_add(swl[s], dd_mul_d(lnr, w));
       }
@@ -237,7 +255,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const double q = s ? 1.0 : -1.0;
-      double* const wk = I.work + (size_t)s * IW_N * S;
+      const double* const wk = I.work + (size_t)s * IW_N * S;
+      const int32_t* const sid = I.sid + (size_t)s * S;
       double* const tb = I.tab + (size_t)s * IT_N * S;
       double* const sc = s_sc + SC_N * s;
       const double* sr = s_r + s * NMAX;
@@ -251,7 +270,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         const int p = p0 + k;
         const double r = sr[p];
         const double w = wk[IW_W * S + sl], wh = wk[IW_WH * S + sl];
-        const dd lnr = {wk[IW_LNH * S + sl], wk[IW_LNL * S + sl]};
+        const int id = sid[sl];
+        const dd lnr = ring_log_id(cst, N, id, r);
         const dd above = dd_sub(rest, dd_mul_d(lnr, w));
         // psi = -q ((sum_{k<i} w_k + w_i) ln rho_i + sum_{k>i} w_k ln rho_k)
         dd ps = dd_add(dd_mul(dd_add_d(below, w), lnr), above);
@@ -267,7 +287,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         if (p == N - 1) {
           // outer edge: the outermost ring plus half its initial extent, and
           // the exterior field there (-q Q ln r, -q Q / r)
-          const double edge = r + wk[IW_DR * S + sl] / 2.0;
+          const double edge = r + cst[IK_DR * N + id] / 2.0;
           const dd lne = dd_add_d(lnr, log1p_fast((edge - r) / r));
           dd eps = dd_mul(Q, lne);
           dd edp = dd_div_d(Q, edge);
@@ -292,9 +312,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
 
     // ---- gather psi, d_rho psi; local quantities, sources; d_zeta psi sums ----
     int bad = bad_order;
-    const int bt0 = I.nb ? I.boff[n] : 0;
-    const int bm = I.nb ? I.boff[n + 1] - bt0 : 0;
-    const double* const br = I.br + bt0;
+    const double* const br = b_lds ? s_br : I.br + bt0;
     const double* const bcq = I.bcum + bt0;
     dd szc0 = dd_make(0.0), szc1 = dd_make(0.0);
     #pragma unroll 1
@@ -304,6 +322,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
       const double qm = q / m, qq2 = (q * q) / (2.0 * m * m);
       const double qo = o ? 1.0 : -1.0;
       double* const wk = I.work + (size_t)s * IW_N * S;
+      const int32_t* const sid = I.sid + (size_t)s * S;
       const double* tb = I.tab + (size_t)s * IT_N * S;
       const double* tbo = I.tab + (size_t)o * IT_N * S;
       int32_t* const jx = I.jx + (size_t)s * S;
@@ -320,7 +339,6 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         const double r = sr[p0 + k];
         const double u = wk[IW_U * S + sl];
         const double w = wk[IW_W * S + sl];
-        const dd lnr = {wk[IW_LNH * S + sl], wk[IW_LNL * S + sl]};
         lo = count_below(ro, lo, N, r, k > 0);
         Interval iv;
         dd pg, dg;
@@ -349,7 +367,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
           dg = dd_add(dl, dd_mul_d(dd_sub(dh, dl), iv.t));
           jx[sl] = iv.j;
         } else {                  // beyond the other species' edge: its exterior field
-          pg = dd_mul(Qo, lnr);
+          pg = dd_mul(Qo, ring_log_id(cst, N, sid[sl], r));
           dg = dd_div_d(Qo, r);
           if (qo > 0.0) { pg = dd_neg(pg); dg = dd_neg(dg); }
           jx[sl] = -1;
@@ -375,18 +393,17 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
           }
         }
         const double pb = 1.0 - qm * psi;
-        const double gm = (1.0 + u * u + pb * pb + qq2 * a2) / (2.0 * pb);
         if (!(pb > 0.0) || !isfinite(pb)) bad = 1;
         const double c = q * u / (r * pb);
         szc = dd_add_d(szc, w * c);
         wk[IW_PSI * S + sl] = psi;
         wk[IW_DPSI * S + sl] = dpsi;
         wk[IW_PB * S + sl] = pb;
-        wk[IW_GM * S + sl] = gm;
         wk[IW_BB * S + sl] = lam / r;
-        wk[IW_A2 * S + sl] = a2;
-        wk[IW_DA2 * S + sl] = da2;
-        wk[IW_T * S + sl] = iv.t;
+        if (has_laser) {
+          wk[IW_A2 * S + sl] = a2;
+          wk[IW_DA2 * S + sl] = da2;
+        }
       }
       if (s) szc1 = szc; else szc0 = szc;
     }
@@ -428,6 +445,8 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
       const double* tbo = I.tab + (size_t)o * IT_N * S;
       const int32_t* jx = I.jx + (size_t)s * S;
       const double* sr = s_r + s * NMAX;
+      const double* ro = s_r + o * NMAX;
+      const double edge_o = s_sc[SC_N * o + SC_EDGE];
       const double dza_o = dd_round({s_sc[SC_N * o + SC_DZH], s_sc[SC_N * o + SC_DZL]});
       #pragma unroll 1
       for (int k = 0; k < cnt; ++k) {
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         const int j = jx[sl];
         double dz = tb[IT_DZ * S + sl];
         if (j >= 0) {
-          const double t = wk[IW_T * S + sl];
+          const double t = interval_t(ro, N, edge_o, sr[p0 + k], j);
           const double dl = j == 0 ? dza_o : tbo[IT_DZ * S + pslot(j - 1, C)];
           const double dh = j < N ? tbo[IT_DZ * S + pslot(j, C)] : 0.0;
           dz += (1.0 - t) * dl + t * dh;
@@ -445,10 +464,12 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
           const double r = sr[p0 + k];
           const double w = wk[IW_W * S + sl];
           const double irho = rcp_nr(r);
-          const Local L = local_of(irho, wk[IW_U * S + sl], w, wk[IW_PSI * S + sl], wk[IW_A2 * S + sl]);
+          const double a2 = has_laser ? wk[IW_A2 * S + sl] : 0.0;
+          const double da2 = has_laser ? wk[IW_DA2 * S + sl] : 0.0;
+          const Local L = local_of(irho, wk[IW_U * S + sl], w, wk[IW_PSI * S + sl], a2);
           double B, Cc, sa, sb;
-          ring_BC(irho, wk[IW_U * S + sl], w, L, wk[IW_DPSI * S + sl], dz, wk[IW_BB * S + sl],
-                  wk[IW_DA2 * S + sl], B, Cc);
+          ring_BC(irho, wk[IW_U * S + sl], w, L, wk[IW_DPSI * S + sl], dz, wk[IW_BB * S + sl], da2, B,
+                  Cc);
           rec_offset(L.A, B, Cc, r, sa, sb);
           G = mat_mul(rec_matrix(L.A, r, irho), G);
           wk[IW_A * S + sl] = L.A;
@@ -540,7 +561,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
         const int j = jxi[sl];
         double bp;
         if (j >= 0) {
-          const double t = wki[IW_T * S + sl];
+          const double t = interval_t(s_r, N, edge_e, sri[p0 + k], j);
           const double bl = j == 0 ? 0.0 : tbe[IT_BP * S + pslot(j - 1, C)];
           const double bh = j < N ? tbe[IT_BP * S + pslot(j, C)] : bN / edge_e;
           bp = (1.0 - t) * bl + t * bh;
@@ -558,7 +579,9 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
     #pragma unroll 1
     for (int s = 0; s < 2; ++s) {
       const double q = s ? 1.0 : -1.0, m = s ? m_ion : 1.0;
-      const double qm = q / m, q24 = (q * q) / (4.0 * m * m);
+      const double qm = q / m, q24 = (q * q) / (4.0 * m * m), qq2 = (q * q) / (2.0 * m * m);
+      const double* frp = stc + (size_t)(s * IS_N + IS_FR) * N;
+      const double* fup = stc + (size_t)(s * IS_N + IS_FU) * N;
       const int32_t* sid = I.sid + (size_t)s * S;
       const double* wk = I.work + (size_t)s * IW_N * S;
       const double* sr = s_r + s * NMAX;
@@ -587,11 +610,14 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
           last[OUT_RHO * N + id] = r; last[OUT_UR * N + id] = u;
         }
         if (do_push) {
-          const double pb = wk[IW_PB * S + sl], gm = wk[IW_GM * S + sl], da2 = wk[IW_DA2 * S + sl];
+          const double pb = wk[IW_PB * S + sl];
+          const double a2 = has_laser ? wk[IW_A2 * S + sl] : 0.0;
+          const double da2 = has_laser ? wk[IW_DA2 * S + sl] : 0.0;
+          const double gm = (1.0 + u * u + pb * pb + qq2 * a2) / (2.0 * pb);   // eq. motion_4
           const double f_r = u / pb;
           const double f_u = -(qm * (gm * dpsi / pb - bt) + q24 * da2 / pb);
           double pr = f_r, pu = f_u;
-          if (n > 0) { pr = wk[IW_FRP * S + sl]; pu = wk[IW_FUP * S + sl]; }
+          if (n > 0) { pr = frp[id]; pu = fup[id]; }
           double rn = r + dxi * (1.5 * f_r - 0.5 * pr);
           double un = u + dxi * (1.5 * f_u - 0.5 * pu);
           double sr_ = f_r, su = f_u;
