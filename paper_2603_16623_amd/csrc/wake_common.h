@@ -143,10 +143,11 @@ struct WakeInst {
 // Per-ring records, stored as planes of 16-B chunks of two doubles: chunk c
 // of slot i at element c * S + i of the array (S = C * nt slots), so that a
 // wave reads one chunk of 64 consecutive slots as contiguous 16-B lanes.
-// The state ends with a plane of 8-B words, the home slot and the
-// ion-interval hint in one double's bits (home slot in the low word): word i
-// at double 2 * RS_HH * S + i.  A state buffer holds RS_DOUBLES * S doubles.
-enum { RS_RU = 0, RS_F, RS_LN, RS_HH, RS_DOUBLES = 2 * RS_HH + 1 };   // (rho, u_r) (f_rho, f_u) (ln rho); hs|hint
+// The state ends with two planes of 4-B words where chunk RS_W would start
+// (int32 4 * RS_W * S): the ring's home slot at word i, and at word S + i
+// its ion interval at the previous slice (kept for instances whose ion nodes
+// are not staged in LDS).  A state buffer holds RS_DOUBLES * S doubles.
+enum { RS_RU = 0, RS_F, RS_LN, RS_W, RS_DOUBLES = 2 * RS_W + 1 };   // (rho, u_r) (f_rho, f_u) (ln rho); hs, hint
 enum { RC_W = 0, RC_R0, RC_LN, RC_CHUNKS };             // (w, w^) (r0, 1/r0) (ln r0)
 enum { SC_PSI = 0, SC_CHUNKS };                         // (psi, d_rho psi)
 

@@ -89,16 +89,6 @@ __device__ __forceinline__ D2 d2(double x, double y) {
   r.y = y;
   return r;
 }
-// home slot (low word) and ion-interval hint (high word) in one double's bits
-__device__ __forceinline__ double hh_pack(int32_t hs, int32_t hint) {
-  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hint << 32) | (uint32_t)hs));
-}
-__device__ __forceinline__ int32_t hh_hs(double v) {
-  return (int32_t)(uint32_t)(uint64_t)__double_as_longlong(v);
-}
-__device__ __forceinline__ int32_t hh_hint(double v) {
-  return (int32_t)((uint64_t)__double_as_longlong(v) >> 32);
-}
 // A record array kept as planes of 16-B chunks: chunk c of record i sits at
 // c * ps + i (ps = slots per plane), so a wave's accesses to one chunk are
 // contiguous 16-B lanes.  One uniform base per array.
@@ -116,12 +106,12 @@ struct PV {
     *reinterpret_cast<WAKE_GLOBAL double*>(reinterpret_cast<WAKE_GLOBAL char*>(g.p) + (c * ps + i) * 16u +
                                           half * 8u) = v;
   }
-  // word i of the plane of 8-B words that starts where chunk c would
-  __device__ __forceinline__ double ldw(uint32_t c, uint32_t i) const {
-    return reinterpret_cast<WAKE_GLOBAL const double*>(g.p)[2u * c * ps + i];
+  // word i of the plane of 4-B words that starts where chunk c would
+  __device__ __forceinline__ int32_t ldi(uint32_t c, uint32_t i) const {
+    return reinterpret_cast<WAKE_GLOBAL const int32_t*>(g.p)[4u * c * ps + i];
   }
-  __device__ __forceinline__ void stw(uint32_t c, uint32_t i, double v) const {
-    reinterpret_cast<WAKE_GLOBAL double*>(g.p)[2u * c * ps + i] = v;
+  __device__ __forceinline__ void sti(uint32_t c, uint32_t i, int32_t v) const {
+    reinterpret_cast<WAKE_GLOBAL int32_t*>(g.p)[4u * c * ps + i] = v;
   }
 };
 __device__ __forceinline__ PV pview(const double* p, uint32_t ps) {
@@ -132,7 +122,9 @@ __device__ __forceinline__ PV pview(const double* p, uint32_t ps) {
 }
 // sort keys of the ring at slot sl of a state buffer
 __device__ __forceinline__ double st_rho(const PV& S, unsigned sl) { return S.ldh(RS_RU, sl, 0); }
-__device__ __forceinline__ int32_t st_hs(const PV& S, unsigned sl) { return hh_hs(S.ldw(RS_HH, sl)); }
+__device__ __forceinline__ int32_t st_hs(const PV& S, unsigned sl) { return S.ldi(RS_W, sl); }
+// the ring's ion-interval hint (instances without the LDS node table)
+__device__ __forceinline__ int32_t st_hint(const PV& S, unsigned sl) { return S.ldi(RS_W, S.ps + sl); }
 
 // ln(rho) of the ring with home slot hs as ln r0 + log1p((rho - r0)/r0): its
 // rounding scales with the ring's displacement, not with |ln rho| (the psi
@@ -282,7 +274,7 @@ __global__ __launch_bounds__(NT) void init_rings_kernel(WakeInst I, const double
   const int j = blockIdx.x * NT + threadIdx.x;
   D2* cst = reinterpret_cast<D2*>(const_cast<double*>(I.cst));
   D2* st = reinterpret_cast<D2*>(I.st[0]);
-  double* st_w = I.st[0];
+  int32_t* st_w = reinterpret_cast<int32_t*>(I.st[0]);
   const size_t PS = (size_t)I.G * I.C * I.nt;      // slots per plane
   const bool ok = j < N;
   double w = 0.0, wh = 0.0, r = 1.0;
@@ -302,7 +294,8 @@ __global__ __launch_bounds__(NT) void init_rings_kernel(WakeInst I, const double
     st[RS_RU * PS + hs] = d2(r, 0.0);
     st[RS_F * PS + hs] = d2(0.0, 0.0);
     st[RS_LN * PS + hs] = d2(lr.hi, lr.lo);
-    st_w[2 * RS_HH * PS + hs] = hh_pack((int32_t)hs, j + 1);
+    st_w[4 * RS_W * PS + hs] = (int32_t)hs;
+    st_w[4 * RS_W * PS + PS + hs] = j + 1;
   }
   const dd wl = dd_mul_d(lr, w);
   Pack<4> tot;
@@ -1226,7 +1219,7 @@ __device__ __forceinline__ void chunk_sums(const WakeInst& I, int cur, int cnt, 
       hs[j] = 0;
       if (k0 + j < cnt) {
         s[j] = ident ? goff + sl : min(lds_perm ? (unsigned)perm[sl] : (unsigned)gptr(I.perm)[goff + sl], smax);
-        hs[j] = lds_perm ? (unsigned)pos_index<NT>(ki[s[j]], C, iC) : (unsigned)hh_hs(SC.ldw(RS_HH, s[j]));
+        hs[j] = lds_perm ? (unsigned)pos_index<NT>(ki[s[j]], C, iC) : (unsigned)st_hs(SC, s[j]);
       }
     }
     double w[8];
@@ -1516,6 +1509,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   // ion interval nodes in LDS (float) for the interval search of pass B;
   // read there after the slice-head scan's barriers
   const bool lds_ion = N <= KCAP;      // the interval nodes fit the LDS table
+  int hint0 = goff + p0 + 1;           // interval of the thread's first ring (at rest: its node's)
   // field-grid node records in the LDS beyond the layout (read after the
   // slice-head scan's barriers)
   const bool grid_lds = GRID && I.grid_n > 0 && !I.grid_off && I.grid_n <= grid_lds_nodes<NT>();
@@ -1707,25 +1701,29 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     // loads run ahead: the state of ring k+2 and the constants and ion
     // record of ring k+1 are requested while ring k is computed
     D2 x_ru = d2(1.0, 0.0), x_ln = d2(0.0, 0.0), z_ru = d2(1.0, 0.0), z_ln = d2(0.0, 0.0);
-    double x_hh = 0.0, z_hh = 0.0;                   // (home slot, hint) bits
+    int32_t x_hs = 0, z_hs = 0;                      // home slots
+    int x_hn = 0, z_hn = 0;                          // interval hints (no LDS node table)
     D2 x_wc = d2(0.0, 0.0);                          // (w, w^) of ring k+1
     double x_q[WAKE_ION_REC];
     if (cnt > 0) {
       const unsigned s = WAKE_SLOT(tid);
-      x_ru = Sc.ld(RS_RU, s); x_ln = Sc.ld(RS_LN, s);
-      x_hh = Sc.ldw(RS_HH, s);
+      x_ru = Sc.ld(RS_RU, s); x_ln = Sc.ld(RS_LN, s); x_hs = st_hs(Sc, s);
+      if (!lds_ion) x_hn = st_hint(Sc, s);
     }
     if (cnt > 1) {
       const unsigned s = WAKE_SLOT(NT + tid);
-      z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
-      z_hh = Sc.ldw(RS_HH, s);
+      z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s); z_hs = st_hs(Sc, s);
+      if (!lds_ion) z_hn = st_hint(Sc, s);
     }
     // ion interval of the next ring: searched in LDS from the interval of
-    // the ring before it (sorted order), its record requested one ring ahead
+    // the ring before it (sorted order; the first ring from the interval of
+    // the thread's first ring at the previous slice), its records requested
+    // one ring ahead; without the LDS table the ring's own interval at the
+    // previous slice
     int jn = 0;
     if (cnt > 0) {
-      x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
-      jn = lds_ion ? ion_find(s_ion, N, x_ru.x, hh_hint(x_hh)) : hh_hint(x_hh);
+      x_wc = KC.ld(RC_W, (unsigned)x_hs);
+      jn = lds_ion ? ion_find(s_ion, N, x_ru.x, hint0) : x_hn;
       ion_load(IV, jn, x_q);
     }
     // field grid: the interval owning each node hands the node its sums
@@ -1754,22 +1752,22 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     for (int k = 0; k < cnt; ++k) {
       const unsigned sl = k * NT + tid;
       const double rho = x_ru.x, u = x_ru.y;
-      const int32_t hs = hh_hs(x_hh);
+      const int32_t hs = x_hs;
       int h = jn;
       const dd lnr = {x_ln.x, x_ln.y};
       const double w = x_wc.x, wh = x_wc.y;
       double q[WAKE_ION_REC];
 #pragma unroll
       for (int i = 0; i < WAKE_ION_REC; ++i) q[i] = x_q[i];
-      x_ru = z_ru; x_ln = z_ln; x_hh = z_hh;
+      x_ru = z_ru; x_ln = z_ln; x_hs = z_hs; x_hn = z_hn;
       if (k + 2 < cnt) {
         const unsigned s = WAKE_SLOT(sl + 2 * NT);
-        z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s);
-        z_hh = Sc.ldw(RS_HH, s);
+        z_ru = Sc.ld(RS_RU, s); z_ln = Sc.ld(RS_LN, s); z_hs = st_hs(Sc, s);
+        if (!lds_ion) z_hn = st_hint(Sc, s);
       }
       if (k + 1 < cnt) {
-        x_wc = KC.ld(RC_W, (unsigned)hh_hs(x_hh));
-        jn = lds_ion ? ion_find(s_ion, N, x_ru.x, h) : hh_hint(x_hh);
+        x_wc = KC.ld(RC_W, (unsigned)x_hs);
+        jn = lds_ion ? ion_find(s_ion, N, x_ru.x, h) : x_hn;
         ion_load(IV, jn, x_q);
       }
       const double irho = rcp_nr(rho);
@@ -1835,9 +1833,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       l1b += G.v[1] * s1b - G.v[3] * s1a;
       SCR.st(SC_PSI, goff + sl, d2(psi, dpsi));
       if (has_laser) { A2.st(goff + sl, aa); DA2.st(goff + sl, dda); }
-      // the ring's home slot and hint move to its position slot in the next
-      // buffer (pass E takes the home slot from there)
-      Sn.stw(RS_HH, goff + sl, hh_pack(hs, h));
+      // the ring's interval: its hint at the next slice (the thread's first
+      // ring: the next slice's search starts there)
+      if (!lds_ion) Sn.sti(RS_W, Sn.ps + goff + sl, h);
+      if (k == 0) hint0 = h;
     }
     if (GRID && ngB > 0 && cnt > 0 && p0 + cnt == Ng && (!CL || member == cl.G - 1)) {
       // nodes beyond the last ring: every ring below them
@@ -1963,14 +1962,14 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       const unsigned s = WAKE_SLOT(sl);
       y_ru = Sc.ld(RS_RU, s); y_f = Sc.ld(RS_F, s); y_ln = Sc.ld(RS_LN, s);
       y_ps = SCR.ld(SC_PSI, goff + sl);
-      y_hs = hh_hs(Sn.ldw(RS_HH, goff + sl));
+      y_hs = st_hs(Sc, s);
     }
     if (cnt > 1) {
       const unsigned sl = (cnt - 2) * NT + tid;
       const unsigned s = WAKE_SLOT(sl);
       v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s); v_ln = Sc.ld(RS_LN, s);
       v_ps = SCR.ld(SC_PSI, goff + sl);
-      v_hs = hh_hs(Sn.ldw(RS_HH, goff + sl));
+      v_hs = st_hs(Sc, s);
     }
     if (cnt > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
     // field grid: ge_hi the last node at or below the current ring, ge_top
@@ -2026,7 +2025,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         const unsigned s = WAKE_SLOT(sp);
         v_ru = Sc.ld(RS_RU, s); v_f = Sc.ld(RS_F, s); v_ln = Sc.ld(RS_LN, s);
         v_ps = SCR.ld(SC_PSI, goff + sp);
-        v_hs = hh_hs(Sn.ldw(RS_HH, goff + sp));
+        v_hs = st_hs(Sc, s);
       }
       if (k > 0) c_w = KC.ld(RC_W, (unsigned)y_hs);
       const double a2 = has_laser ? A2[goff + sl] : 0.0, da2 = has_laser ? DA2[goff + sl] : 0.0;
@@ -2092,6 +2091,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         Sn.st(RS_RU, goff + sl, d2(rn, un));
         Sn.st(RS_F, goff + sl, d2(sr, su));
         Sn.st(RS_LN, goff + sl, d2(lr.hi, lr.lo));
+        Sn.sti(RS_W, goff + sl, hs);
         sw2 = dd_add_d(sw2, w);
         swl2 = dd_add_fast(swl2, dd_mul_d(lr, w));
         if (lds_keys) { s_kr[sl] = rn; s_ki[sl] = (uint16_t)id; }
@@ -2279,7 +2279,7 @@ __global__ void state_by_id_kernel(WakeInst I, double* rho, double* u, double* f
   const unsigned sl = slot_of(p, I.C, I.nt);
   const size_t PS = (size_t)I.G * I.C * I.nt;
   const D2* r = reinterpret_cast<const D2*>(I.st[c]) + sl;
-  const int hs = hh_hs(I.st[c][2 * RS_HH * PS + sl]);
+  const int hs = reinterpret_cast<const int32_t*>(I.st[c])[4 * RS_W * PS + sl];
   const int i = pos_of_slot(hs, I.C, I.nt);
   if (rho) rho[i] = r[RS_RU * PS].x;
   if (u) u[i] = r[RS_RU * PS].y;
@@ -2302,7 +2302,9 @@ __global__ void state_set_kernel(WakeInst I, const double* rho, const double* u,
   r[RS_RU * PS] = d2(rho[i], u[i]);
   r[RS_F * PS] = d2(fr ? fr[i] : 0.0, fu ? fu[i] : 0.0);
   r[RS_LN * PS] = d2(lr.hi, lr.lo);
-  I.st[0][2 * RS_HH * PS + sl] = hh_pack((int32_t)sl, i + 1);
+  int32_t* wd = reinterpret_cast<int32_t*>(I.st[0]) + 4 * RS_W * PS;
+  wd[sl] = (int32_t)sl;
+  wd[PS + sl] = i + 1;
 }
 
 // Back to the state at slice 0 (rings at rest at their initial radii);
@@ -2317,7 +2319,9 @@ __global__ void state_reset_kernel(const WakeInst* __restrict__ insts, int n_ins
     r[RS_RU * PS] = d2(k[RC_R0 * PS].x, 0.0);
     r[RS_F * PS] = d2(0.0, 0.0);
     r[RS_LN * PS] = k[RC_LN * PS];
-    I.st[0][2 * RS_HH * PS + sl] = hh_pack((int32_t)sl, j + 1);
+    int32_t* wd = reinterpret_cast<int32_t*>(I.st[0]) + 4 * RS_W * PS;
+    wd[sl] = (int32_t)sl;
+    wd[PS + sl] = j + 1;
   }
   if (threadIdx.x == 0) { I.ctl[CTL_CUR] = 0; I.ctl[CTL_BREAK] = -1; I.ctl[CTL_NEXT] = 0; I.ctl[CTL_FAULT] = 0; }
 }
