@@ -883,6 +883,27 @@ __device__ __forceinline__ void sort_block_wave(int b0, int N, int C, double iC,
     if (sl[j] >= 0) perm[sl[j]] = (uint16_t)(k[j] & 0xffffu);
 }
 
+// Whether any of bits lo..hi (inclusive, lo <= hi) of a bit array is set.
+__device__ __forceinline__ bool bits_any(const uint64_t* m, int lo, int hi) {
+  #pragma unroll 1
+  for (int w = lo >> 6; w <= (hi >> 6); ++w) {
+    uint64_t x = m[w];
+    if (w == (hi >> 6) && (hi & 63) < 63) x &= (2ull << (hi & 63)) - 1ull;
+    if (w == (lo >> 6)) x &= ~0ull << (lo & 63);
+    if (x) return true;
+  }
+  return false;
+}
+
+// Key at position p through the order perm, as sort_block_wave compares them.
+template <int NT>
+__device__ __forceinline__ void key_at(int p, int C, double iC, const double* kr, const uint16_t* ki,
+                                       const uint16_t* perm, double& r, uint32_t& k) {
+  const unsigned src = perm[pos_index<NT>(p, C, iC)];
+  r = kr[src];
+  k = ((uint32_t)ki[src] << 16) | src;
+}
+
 // Order fix-up for nearly sorted keys in LDS: blocks of 256 positions sorted
 // by single waves, first at offsets 0, 256, 512, ... and then at 128, 384,
 // ...  If no ring is more than 128 positions from its place in the order,
@@ -890,20 +911,82 @@ __device__ __forceinline__ void sort_block_wave(int b0, int N, int C, double iC,
 // threshold, the mixed zone left by the first phase lies inside one block
 // of the second).  Up to two such rounds; returns whether the order is
 // complete (else the caller runs the general fix-up).
+//
+// dmask (optional): the push's disorder flags, bit t set if thread t's
+// chunk had a pair of positions out of order (inside it, or its last
+// position against the next chunk's first).  The first round then sorts
+// only the blocks of the first phase whose chunks flagged disorder (the
+// others are in order), only the blocks of the second phase over a junction
+// of the first phase's blocks left out of order, and checks the order at
+// the junctions of the second phase's blocks alone: every segment between
+// them is sorted, so the sequence is in order when they are.
 template <int NT>
 __device__ __noinline__ bool fix_order_blocks(const WakeInst& I, const double* kr, const uint16_t* ki,
-                                              uint16_t* perm) {
+                                              uint16_t* perm, const uint64_t* dmask) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = tid >> 6, lane = tid & 63;
   const int N = I.N, C = I.C;
   const double iC = 1.0 / (double)C;
   const int p0 = tid * C;
   const int cnt = max(0, min(C, N - p0));
   for (int k = 0; k < cnt; ++k) perm[k * NT + tid] = (uint16_t)(k * NT + tid);
   __syncthreads();
+  int round = 0;
+  if (dmask) {
+    round = 1;
+    // the first phase's blocks with flagged chunks, one block per lane
+    uint64_t bm;
+    {
+      const int b0 = lane << 8;
+      bm = __ballot(b0 < N && bits_any(dmask, b0 / C, min((b0 + 255) / C, NT - 1)));
+    }
+    int seen = 0;
+    #pragma unroll 1
+    while (bm) {
+      const int b = __builtin_ctzll(bm);
+      bm &= bm - 1;
+      if (seen++ % NW == wave) sort_block_wave<NT>(b * 256, N, C, iC, kr, ki, perm);
+    }
+    __syncthreads();
+    // junctions q = 256 (j + 1) of the first phase's blocks, one per lane
+    bool out = false;
+    {
+      const int q = 256 * (lane + 1);
+      if (q < N) {
+        double ra, rb;
+        uint32_t ka, kb;
+        key_at<NT>(q - 1, C, iC, kr, ki, perm, ra, ka);
+        key_at<NT>(q, C, iC, kr, ki, perm, rb, kb);
+        out = pk_lt(rb, kb, ra, ka);
+      }
+    }
+    uint64_t jm = __ballot(out);
+    seen = 0;
+    #pragma unroll 1
+    while (jm) {
+      const int b = __builtin_ctzll(jm);
+      jm &= jm - 1;
+      if (seen++ % NW == wave) sort_block_wave<NT>(128 + b * 256, N, C, iC, kr, ki, perm);
+    }
+    __syncthreads();
+    // junctions 128 + 256 j of the second phase's blocks
+    out = false;
+    {
+      const int q = 128 + 256 * lane;
+      if (q < N) {
+        double ra, rb;
+        uint32_t ka, kb;
+        key_at<NT>(q - 1, C, iC, kr, ki, perm, ra, ka);
+        key_at<NT>(q, C, iC, kr, ki, perm, rb, kb);
+        out = pk_lt(rb, kb, ra, ka);
+      }
+    }
+    if (!__ballot(out)) return true;     // the same keys in every wave: a uniform answer
+    __syncthreads();                      // every wave has read the keys before a block moves
+  }
   #pragma unroll 1
-  for (int round = 0; round < 2; ++round) {
+  for (; round < 2; ++round) {
     #pragma unroll 1
     for (int b = wave; b * 256 < N; b += NW) sort_block_wave<NT>(b * 256, N, C, iC, kr, ki, perm);
     __syncthreads();
@@ -1105,6 +1188,9 @@ struct MarchLds {
 static_assert(MarchLds<256>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<512>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<1024>::bytes() <= 160 * 1024, "LDS layout too large");
+// the block fix-up checks one junction of 256-position blocks per lane
+static_assert(MarchLds<256>::KCAP <= 64 * 256 && MarchLds<512>::KCAP <= 64 * 256 &&
+              MarchLds<1024>::KCAP <= 64 * 256, "junctions per lane");
 // a cooperative member gathers the packs of every member into its key area
 static_assert(MarchLds<256>::key_bytes() >= WAKE_CL_GMAX * 16 * sizeof(double), "pack area");
 // field-grid variant: the LDS left beside the layout holds the node records
@@ -1434,6 +1520,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
   if (CL) cl_start(cl);
   double* const s_x = s_kr;                                   // gathered packs (cooperative)
   int* const s_ok = reinterpret_cast<int*>(s_misc + 62);
+  uint64_t* const s_dmask = reinterpret_cast<uint64_t*>(s_misc + 32);   // NW words: the push's disorder flags
   // the same two as byte offsets into the LDS, for the cooperative fix-ups
   const int xo = (int)MarchLds<NT>::head_bytes();
   const int oko = (int)(reinterpret_cast<unsigned char*>(s_ok) - smem);
@@ -1647,7 +1734,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         }
         ++fix_rounds;
       } else if (lds_keys) {
-        restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm);
+        restage = !fix_order_blocks<NT>(I, s_kr, s_ki, s_perm, s_dmask);
         if (restage) {
           if (tid == 0) atomicAdd(I.cnt + CNT_GENERAL, 1ull);
           fix_order_lds<NT, CMAX>(I, s_scanB, s_scanA, region, s_kr, s_ki, s_zf, s_perm);
@@ -2194,6 +2281,10 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     if (do_push && cnt > 0 && tid + 1 < NT && !key_lt(last_r, last_i, s_fr[tid + 1], s_fi[tid + 1]))
       dis_l = 1.0;
     dis = dis_l;
+    if (!CL && lds_keys) {    // the chunks' flags for the fix-up at the next slice head
+      const uint64_t m = __ballot(dis_l != 0.0);
+      if ((tid & 63) == 0) s_dmask[tid >> 6] = m;
+    }
     unpushed = cur;
     if (do_push) {
       // the pushed rings sit at the slots of this slice's positions
