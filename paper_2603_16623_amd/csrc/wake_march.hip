@@ -883,6 +883,94 @@ __device__ __forceinline__ void sort_block_wave(int b0, int N, int C, double iC,
     if (sl[j] >= 0) perm[sl[j]] = (uint16_t)(k[j] & 0xffffu);
 }
 
+// Value of lane 63 - lane of the wave (rows mirrored by DPP, then rows and
+// halves swapped).
+__device__ __forceinline__ uint32_t lane_rev(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+  x = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true);     // row_mirror: lane ^ 15 in the row
+  const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = (lane & 16) ? a[0] : a[1];
+  const auto b = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return (lane & 32) ? b[0] : b[1];
+}
+__device__ __forceinline__ double lane_rev(double x) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = lane_rev((uint32_t)v), hi = lane_rev((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One wave merges the positions [b0, b0 + 256) (clipped at N) whose two
+// halves [b0, b0 + 128) and [b0 + 128, b0 + 256) are each in order: four
+// keys per lane, the first stage compares position i with 255 - i (the
+// second half taken in reverse makes the block bitonic), then the seven
+// half-cleaning stages of a bitonic merge; written back as the new order of
+// these positions.  A block already in order is left alone.
+template <int NT>
+__device__ __forceinline__ void merge_block_wave(int b0, int N, int C, double iC, const double* kr,
+                                                 const uint16_t* ki, uint16_t* perm) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint32_t k[4];
+  int sl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    sl[j] = -1;
+    r[j] = INFINITY;
+    k[j] = 0xffffffffu;
+    if (p < N) {
+      sl[j] = pos_index<NT>(p, C, iC);
+      const unsigned src = perm[sl[j]];
+      r[j] = kr[src];
+      k[j] = ((uint32_t)ki[src] << 16) | src;
+    }
+  }
+  {
+    const double xr = lane_next(r[0]);
+    const uint32_t xk = lane_next(k[0]);
+    const bool ok = (lane == 63 || !pk_lt(xr, xk, r[3], k[3])) && !pk_lt(r[1], k[1], r[0], k[0]) &&
+                    !pk_lt(r[2], k[2], r[1], k[1]) && !pk_lt(r[3], k[3], r[2], k[2]);
+    if (__all(ok)) return;
+  }
+  // position 4 lane + j against 255 - (4 lane + j): lane 63 - lane, register 3 - j
+  {
+    double pr[4];
+    uint32_t pq[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { pr[j] = lane_rev(r[3 - j]); pq[j] = lane_rev(k[3 - j]); }
+    const bool lower = lane < 32;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (pk_lt(pr[j], pq[j], r[j], k[j]) == lower) { r[j] = pr[j]; k[j] = pq[j]; }
+  }
+#pragma unroll
+  for (int d = 64; d > 0; d >>= 1) {
+    if (d >= 4) {                   // partner in lane ^ (d / 4), same register
+      const int lm = d >> 2;
+      const bool lower = (lane & lm) == 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double pr = lane_xor(r[j], lm);
+        const uint32_t pq = lane_xor(k[j], lm);
+        if (pk_lt(pr, pq, r[j], k[j]) == lower) { r[j] = pr; k[j] = pq; }
+      }
+    } else {                        // partner in this lane
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j & d) continue;
+        const int jj = j | d;
+        if (pk_lt(r[jj], k[jj], r[j], k[j])) {
+          const double tr = r[j]; r[j] = r[jj]; r[jj] = tr;
+          const uint32_t tk = k[j]; k[j] = k[jj]; k[jj] = tk;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (sl[j] >= 0) perm[sl[j]] = (uint16_t)(k[j] & 0xffffu);
+}
+
 // Whether any of bits lo..hi (inclusive, lo <= hi) of a bit array is set.
 __device__ __forceinline__ bool bits_any(const uint64_t* m, int lo, int hi) {
   #pragma unroll 1
@@ -906,7 +994,8 @@ __device__ __forceinline__ void key_at(int p, int C, double iC, const double* kr
 
 // Order fix-up for nearly sorted keys in LDS: blocks of 256 positions sorted
 // by single waves, first at offsets 0, 256, 512, ... and then at 128, 384,
-// ...  If no ring is more than 128 positions from its place in the order,
+// ... (the second phase's blocks are two sorted halves, merged).  If no ring
+// is more than 128 positions from its place in the order,
 // the two phases leave the whole sequence sorted (with the keys cut at any
 // threshold, the mixed zone left by the first phase lies inside one block
 // of the second).  Up to two such rounds; returns whether the order is
@@ -967,7 +1056,7 @@ __device__ __noinline__ bool fix_order_blocks(const WakeInst& I, const double* k
     while (jm) {
       const int b = __builtin_ctzll(jm);
       jm &= jm - 1;
-      if (seen++ % NW == wave) sort_block_wave<NT>(128 + b * 256, N, C, iC, kr, ki, perm);
+      if (seen++ % NW == wave) merge_block_wave<NT>(128 + b * 256, N, C, iC, kr, ki, perm);
     }
     __syncthreads();
     // junctions 128 + 256 j of the second phase's blocks
@@ -991,7 +1080,7 @@ __device__ __noinline__ bool fix_order_blocks(const WakeInst& I, const double* k
     for (int b = wave; b * 256 < N; b += NW) sort_block_wave<NT>(b * 256, N, C, iC, kr, ki, perm);
     __syncthreads();
     #pragma unroll 1
-    for (int b = wave; 128 + b * 256 < N; b += NW) sort_block_wave<NT>(128 + b * 256, N, C, iC, kr, ki, perm);
+    for (int b = wave; 128 + b * 256 < N; b += NW) merge_block_wave<NT>(128 + b * 256, N, C, iC, kr, ki, perm);
     __syncthreads();
     // in order? (this chunk, and its last position against the next chunk's first)
     int bad = 0;
