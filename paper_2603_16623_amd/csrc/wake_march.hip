@@ -1630,6 +1630,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
 #define WAKE_MOVED(s, k) ((int)(s) != goff + (k) * NT + tid)
   // injected states may be unsorted
   bool ident = true;
+  bool push_keys = false;   // cooperative: the push's first and last keys of the member are in LDS
   bool moved = false;       // a chunk holds rings of another chunk after the fix-up
   if (CL) {
     #pragma unroll 1
@@ -1742,12 +1743,19 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
 #pragma unroll
       for (int i = 0; i < 6; ++i) mine.v[i] = t6.v[i];
       if (tid == 0) {
-        const int ql = Ng - 1;
-        const unsigned sf = WAKE_SLOT(0u), sL = WAKE_SLOT((unsigned)((ql % C) * NT + ql / C));
-        mine.v[6] = gptr(I.gk_r)[sf];
-        mine.v[7] = (double)gptr(I.gk_i)[sf];
-        mine.v[8] = gptr(I.gk_r)[sL];
-        mine.v[9] = (double)gptr(I.gk_i)[sL];
+        if (push_keys) {       // the push's keys of the first and the last position, kept in LDS
+          mine.v[6] = s_fr[0];
+          mine.v[7] = (double)s_fi[0];
+          mine.v[8] = s_misc[48];
+          mine.v[9] = s_misc[49];
+        } else {
+          const int ql = Ng - 1;
+          const unsigned sf = WAKE_SLOT(0u), sL = WAKE_SLOT((unsigned)((ql % C) * NT + ql / C));
+          mine.v[6] = gptr(I.gk_r)[sf];
+          mine.v[7] = (double)gptr(I.gk_i)[sf];
+          mine.v[8] = gptr(I.gk_r)[sL];
+          mine.v[9] = (double)gptr(I.gk_i)[sL];
+        }
         mine.v[10] = (budget > 0 && n > I.first &&
                       (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) >= budget) ? 1.0 : 0.0;
       }
@@ -1763,15 +1771,19 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         rho_mprev = member > 0 ? s_x[(member - 1) * 11 + 8] : -1.0;
         rho_mlast = s_x[member * 11 + 8];
       }
-      double stop = 0.0;
-      for (int m = 0; m < cl.G; ++m) {
-        stop += s_x[m * 11 + 10];
-        if (m + 1 < cl.G &&
-            key_lt(s_x[(m + 1) * 11 + 6], (int32_t)s_x[(m + 1) * 11 + 7], s_x[m * 11 + 8], (int32_t)s_x[m * 11 + 9]))
-          bnd += 1.0;
+      // a member out of time; boundaries between members out of order (thread
+      // m looks at member m and the one after it)
+      bool m_stop = false, m_bnd = false;
+      if (tid < cl.G) {
+        const int m = tid;
+        m_stop = s_x[m * 11 + 10] != 0.0;
+        m_bnd = m + 1 < cl.G && key_lt(s_x[(m + 1) * 11 + 6], (int32_t)s_x[(m + 1) * 11 + 7], s_x[m * 11 + 8],
+                                       (int32_t)s_x[m * 11 + 9]);
       }
+      bnd = __syncthreads_or(m_bnd) ? 1.0 : 0.0;
+      const bool stop = __syncthreads_or(m_stop) != 0;
       t6.v[5] += bnd;
-      if (stop != 0.0 && t6.v[4] == 0.0) end = n;
+      if (stop && t6.v[4] == 0.0) end = n;
     }
     if (t6.v[4] != 0.0) {     // slice n-1 broke down: stop there
       if (tid == 0 && member == 0) { I.ctl[CTL_BREAK] = n - 1; I.ctl[CTL_CUR] = unpushed; I.ctl[CTL_NEXT] = n - 1; }
@@ -1833,6 +1845,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         fix_order_big<NT>(I, cur, s_scanB, s_scanA, region);
       }
       ident = false;
+      push_keys = false;
       // chunks whose order changed sum again
       bool changed = false;
       for (int k = 0; k < cnt; ++k)
@@ -2307,6 +2320,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
     // empty) against the previous chunk's last one
     s_fr[tid] = nxt_r;
     s_fi[tid] = nxt_i;
+    if (CL && do_push && cnt > 0 && p0 + cnt == Ng) { s_misc[48] = last_r; s_misc[49] = (double)last_i; }
     if (stage_next) {
       __syncthreads();        // every wave is done with this slice's table and constants
       stage_analytic<NT>(I, n + 1, s_misc);
@@ -2379,6 +2393,7 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       // the pushed rings sit at the slots of this slice's positions
       cur = nb;
       ident = true;
+      push_keys = CL;
       sw = sw2;
       swl = swl2;
       sw_push = sw2;
