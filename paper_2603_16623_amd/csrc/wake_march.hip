@@ -1240,6 +1240,100 @@ struct BwdMatSumOp {  // (index-order product of inverse transfers, running sum)
     return {{m.v[0], m.v[1], m.v[2], m.v[3], lo.v[4] + hi.v[4]}};
   }
 };
+// Cooperative instances: the transfer products and the source det-sums of
+// all members from one exchange.  Member m publishes (G_m, V_m), its
+// transfer product and v-sum in FwdMatSumOp form, and four vectors summed
+// over its chunks: A = sum Gl^T mu, B = sum Gl^T l1, A' = sum K^T mu,
+// B' = sum K^T l1 (Gl: the member's transfers before the chunk; K = adj(G)
+// Hl with G the chunk's product and Hl the member's inverse transfers after
+// it; l1: the part of the chunk's lambda that multiplies c; mu = lambda0 -
+// (v of the chunk and of the member's later chunks) l1).  With gin the
+// growing mode entering member m, hin the decaying mode leaving it and Vm
+// the v-sum of the members after it, the member's sums of det[g_i, s_i] and
+// det[s_i, h_i] are gin.A - Vm gin.B and -hin.A' + Vm hin.B'.  Every member
+// forms from the gathered packs (NFT doubles each) its exclusive prefix pg
+// and suffix sg of the transfers (inverse transfers from the adjugates of
+// the published products, det = 1), their totals, and the det-sums of the
+// members before it (e_in) and after it (d_in).  Lane l of each wave takes
+// members 4l .. 4l+3 (G <= 256).
+struct FwdMatSumOp;
+struct BwdMatSumOp;
+template <int NFT, class FOp, class BOp>
+__device__ __forceinline__ void cl_transfer_scan(const double* s_x, int g, int G, Pack<5>& pg, Pack<5>& gt,
+                                                 Pack<5>& sg, Pack<5>& ht, double& e_in, double& d_in) {
+  const int lane = threadIdx.x & 63;
+  const Pack<5> I5 = {{1.0, 0.0, 0.0, 1.0, 0.0}};
+  const FOp fop;
+  const BOp bop;
+  auto fwd_of = [&](int m) {
+    const double* q = s_x + m * NFT;
+    return Pack<5>{{q[0], q[1], q[2], q[3], q[4]}};
+  };
+  auto bwd_of = [&](int m) {
+    const double* q = s_x + m * NFT;
+    return Pack<5>{{q[3], -q[1], -q[2], q[0], q[4]}};
+  };
+  Pack<5> bf = I5, bb = I5;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (4 * lane + j < G) bf = fop(bf, fwd_of(4 * lane + j));
+#pragma unroll
+  for (int j = 3; j >= 0; --j)
+    if (4 * lane + j < G) bb = bop(bwd_of(4 * lane + j), bb);
+  const Pack<5> incF = wave_prefix_incl(bf, fop), incB = wave_suffix_incl(bb, bop);
+  Pack<5> exF, exB;                     // the members before this lane's, after them
+#pragma unroll
+  for (int i = 0; i < 5; ++i) { exF.v[i] = lane_prev(incF.v[i]); exB.v[i] = lane_next(incB.v[i]); }
+  if (lane == 0) exF = I5;
+  if (lane == 63) exB = I5;
+  gt = lane_pack(incF, 63);
+  ht = lane_pack(incB, 0);
+  double vm[4], dtm[4], etm[4];
+  Pack<5> pg_l = I5, sg_l = I5;
+  Pack<5> x = exB;
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {        // descending: the suffix after each member
+    const int m = 4 * lane + j;
+    vm[j] = x.v[4];
+    dtm[j] = 0.0;
+    if (m < G) {
+      const double* q = s_x + m * NFT;
+      const double h0 = x.v[1], h1 = x.v[3];
+      dtm[j] = -(h0 * q[9] + h1 * q[10]) + x.v[4] * (h0 * q[11] + h1 * q[12]);
+      if (m == g) sg_l = x;
+      x = bop(bwd_of(m), x);
+    }
+  }
+  x = exF;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {         // ascending: the prefix before each member
+    const int m = 4 * lane + j;
+    etm[j] = 0.0;
+    if (m < G) {
+      const double* q = s_x + m * NFT;
+      const double g0 = x.v[0], g1 = x.v[2];
+      etm[j] = (g0 * q[5] + g1 * q[6]) - vm[j] * (g0 * q[7] + g1 * q[8]);
+      if (m == g) pg_l = x;
+      x = fop(x, fwd_of(m));
+    }
+  }
+  const Pack<1> eI = wave_prefix_incl(Pack<1>{{(etm[0] + etm[1]) + (etm[2] + etm[3])}}, SumOp<1>());
+  const Pack<1> dI = wave_suffix_incl(Pack<1>{{(dtm[0] + dtm[1]) + (dtm[2] + dtm[3])}}, SumOp<1>());
+  double e_own = lane_prev(eI.v[0]), d_own = lane_next(dI.v[0]);
+  if (lane == 0) e_own = 0.0;
+  if (lane == 63) d_own = 0.0;
+  const int lg = g >> 2, jg = g & 3;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < jg) e_own += etm[j];
+    if (j > jg) d_own += dtm[j];
+  }
+  e_in = lane_pack(Pack<1>{{e_own}}, lg).v[0];
+  d_in = lane_pack(Pack<1>{{d_own}}, lg).v[0];
+  pg = lane_pack(pg_l, lg);
+  sg = lane_pack(sg_l, lg);
+}
+
 struct SliceHeadOp {  // (w, w ln rho) as double-doubles, then two flag counts
   __device__ __forceinline__ Pack<6> operator()(const Pack<6>& a, const Pack<6>& b) const {
     const dd x = dd_add_fast({a.v[0], a.v[1]}, {b.v[0], b.v[1]});
@@ -2080,17 +2174,31 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         gout[3 * ngB + g] = lam * rcp_nr(r);     // B^(b); pass E adds B^(p)
       }
     }
-    if (CL) {                // the other members' chunk products before / after this one
-      Pack<10> mine;
+    double e_in = 0.0, d_in = 0.0;       // cooperative: det-sums of the members before / after
+    if (CL) {
+      // one exchange for the members' transfer products and det-sums: this
+      // chunk's parts of the member's A, B, A', B' (Gl, Hl: the member's
+      // transfers before the chunk and inverse transfers after it)
+      const double vl = Vw + hx.v[4];
+      const double mua = l0a - vl * l1a, mub = l0b - vl * l1b;
+      const double k0 = G.v[3] * hx.v[0] - G.v[1] * hx.v[2], k1 = G.v[3] * hx.v[1] - G.v[1] * hx.v[3];
+      const double k2 = -G.v[2] * hx.v[0] + G.v[0] * hx.v[2], k3 = -G.v[2] * hx.v[1] + G.v[0] * hx.v[3];
+      Pack<8> part = {{gp.v[0] * mua + gp.v[2] * mub, gp.v[1] * mua + gp.v[3] * mub,
+                       gp.v[0] * l1a + gp.v[2] * l1b, gp.v[1] * l1a + gp.v[3] * l1b,
+                       k0 * mua + k2 * mub, k1 * mua + k3 * mub, k0 * l1a + k2 * l1b, k1 * l1a + k3 * l1b}};
+      Pack<8> ab;
+      block_prefix<NT, 8, SumOp<8>, false>(part, Pack<8>{{0, 0, 0, 0, 0, 0, 0, 0}}, SumOp<8>(), s_scanA, ab);
+      Pack<13> mine;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) { mine.v[i] = gt.v[i]; mine.v[5 + i] = ht.v[i]; }
-      if (!cl_gather<10, false>(cl, mine, s_x, s_ok)) {
+      for (int i = 0; i < 5; ++i) mine.v[i] = gt.v[i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) mine.v[5 + i] = ab.v[i];
+      if (!cl_gather<13, false>(cl, mine, s_x, s_ok)) {
         if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
         return;
       }
       Pack<5> pg, sg;
-      cl_prefix<5, 10>(s_x, 0, member, cl.G, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, FwdMatSumOp(), pg, gt);
-      cl_suffix<5, 10>(s_x, 5, member, cl.G, Pack<5>{{1.0, 0.0, 0.0, 1.0, 0.0}}, BwdMatSumOp(), sg, ht);
+      cl_transfer_scan<13, FwdMatSumOp, BwdMatSumOp>(s_x, member, cl.G, pg, gt, sg, ht, e_in, d_in);
       gp = FwdMatSumOp()(pg, gp);
       hx = BwdMatSumOp()(hx, sg);
     }
@@ -2111,15 +2219,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         Pack<1>{{le}}, Pack<1>{{0.0}}, SumOp<1>(), Pack<1>{{lds}}, Pack<1>{{0.0}}, SumOp<1>(),
         s_scanA, ep, et, dsf, dt);
     if (CL) {
-      if (!cl_gather<2, false>(cl, Pack<2>{{et.v[0], dt.v[0]}}, s_x, s_ok)) {
-        if (tid == 0 && member == 0) I.ctl[CTL_FAULT] = 1;
-        return;
-      }
-      Pack<1> pg, sg;
-      cl_prefix<1, 2>(s_x, 0, member, cl.G, Pack<1>{{0.0}}, SumOp<1>(), pg, et);
-      cl_suffix<1, 2>(s_x, 1, member, cl.G, Pack<1>{{0.0}}, SumOp<1>(), sg, dt);
-      ep = SumOp<1>()(pg, ep);
-      dsf = SumOp<1>()(dsf, sg);
+      ep.v[0] = e_in + ep.v[0];
+      dsf.v[0] = dsf.v[0] + d_in;
     }
 
     // ---- pass E: B^(p), outputs, push ----
