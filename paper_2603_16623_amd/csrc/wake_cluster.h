@@ -1,8 +1,9 @@
 // Cooperative instances (device side): G workgroups march one instance that
 // is too large for one workgroup's LDS.  Member g owns the sorted positions
-// [g*P, g*P + P) (P = C * NT).  Per slice the members meet three times
-// (slice head, transfer-matrix scan, source-sum scan) to exchange their scan
-// totals, and a few more times when the order needs fixing; the order
+// [g*P, g*P + P) (P = C * NT).  Per slice the members meet twice (slice
+// head; transfer products with the coefficients of their source det-sums) to
+// exchange their scan totals, and a few more times when the order needs
+// fixing; the order
 // fix-up works on keys and permutation in device memory.
 //
 // Barrier.  Each member publishes a pack (agent-scope atomic stores, which

@@ -92,6 +92,159 @@ __device__ void bitonic_ions(double* kr, uint16_t* ki, int n) {
   }
 }
 
+// (rho, id) order of keys with the id in k (no short-circuit: straight-line
+// selects)
+__device__ __forceinline__ bool ik_lt(double ra, uint32_t ka, double rb, uint32_t kb) {
+  return (ra < rb) | ((ra == rb) & (ka < kb));
+}
+__device__ __forceinline__ void ik_swap(double& ra, uint32_t& ka, double& rb, uint32_t& kb) {
+  const double t = ra; ra = rb; rb = t;
+  const uint32_t u = ka; ka = kb; kb = u;
+}
+// the wave's keys of positions [b0, b0 + 256) (four per lane, +inf past n)
+__device__ __forceinline__ void ik_load(const double* kr, const uint16_t* ki, int b0, int n, double* r,
+                                        uint32_t* k) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    r[j] = p < n ? kr[p] : INFINITY;
+    k[j] = p < n ? (uint32_t)ki[p] : 0xffffffffu;
+  }
+}
+__device__ __forceinline__ void ik_store(double* kr, uint16_t* ki, int b0, int n, const double* r,
+                                         const uint32_t* k) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    if (p < n) { kr[p] = r[j]; ki[p] = (uint16_t)k[j]; }
+  }
+}
+// whether the wave's 256 keys are in order
+__device__ __forceinline__ bool ik_sorted(const double* r, const uint32_t* k) {
+  const int lane = threadIdx.x & 63;
+  const double xr = lane_next(r[0]);
+  const uint32_t xk = lane_next(k[0]);
+  const bool ok = (lane == 63 || !ik_lt(xr, xk, r[3], k[3])) && !ik_lt(r[1], k[1], r[0], k[0]) &&
+                  !ik_lt(r[2], k[2], r[1], k[1]) && !ik_lt(r[3], k[3], r[2], k[2]);
+  return __all(ok);
+}
+// compare-exchange stage of a bitonic network at distance d over the wave's
+// 256 keys (position 4 lane + j), ascending where (position & kk) == 0
+__device__ __forceinline__ void ik_stage(double* r, uint32_t* k, int kk, int d) {
+  const int lane = threadIdx.x & 63;
+  if (d >= 4) {                       // partner in lane ^ (d / 4), same register
+    const int lm = d >> 2;
+    const bool lower = (lane & lm) == 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double pr = lane_xor(r[j], lm);
+      const uint32_t pq = lane_xor(k[j], lm);
+      const bool up = ((4 * lane + j) & kk) == 0;
+      if (ik_lt(pr, pq, r[j], k[j]) == (lower == up)) { r[j] = pr; k[j] = pq; }
+    }
+  } else {                            // partner in this lane
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j & d) continue;
+      const int jj = j | d;
+      const bool up = ((4 * lane + j) & kk) == 0;
+      if (ik_lt(r[jj], k[jj], r[j], k[j]) == up) ik_swap(r[j], k[j], r[jj], k[jj]);
+    }
+  }
+}
+
+// One wave puts positions [b0, b0 + 256) (clipped at n) of the keys in LDS
+// in order, in place: odd-even transposition first (a ring displaced by L
+// positions is in place after L phases; the order is checked every four
+// phases), the full bitonic network after 32 phases.
+__device__ void ions_sort_block(double* kr, uint16_t* ki, int b0, int n) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint32_t k[4];
+  ik_load(kr, ki, b0, n, r, k);
+  if (ik_sorted(r, k)) return;
+  #pragma unroll 1
+  for (int it = 0; it < 8; ++it) {
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+      if (ik_lt(r[1], k[1], r[0], k[0])) ik_swap(r[0], k[0], r[1], k[1]);
+      if (ik_lt(r[3], k[3], r[2], k[2])) ik_swap(r[2], k[2], r[3], k[3]);
+      if (ik_lt(r[2], k[2], r[1], k[1])) ik_swap(r[1], k[1], r[2], k[2]);
+      const double nr = lane_next(r[0]), pr = lane_prev(r[3]);
+      const uint32_t nq = lane_next(k[0]), pq = lane_prev(k[3]);
+      const bool take_next = lane < 63 && ik_lt(nr, nq, r[3], k[3]);    // keep the smaller
+      const bool take_prev = lane > 0 && ik_lt(r[0], k[0], pr, pq);     // keep the larger
+      if (take_next) { r[3] = nr; k[3] = nq; }
+      if (take_prev) { r[0] = pr; k[0] = pq; }
+    }
+    if (ik_sorted(r, k)) {
+      ik_store(kr, ki, b0, n, r, k);
+      return;
+    }
+  }
+#pragma unroll
+  for (int kk = 2; kk <= 256; kk <<= 1) {
+#pragma unroll
+    for (int d = kk >> 1; d > 0; d >>= 1) ik_stage(r, k, kk, d);
+  }
+  ik_store(kr, ki, b0, n, r, k);
+}
+
+// One wave merges positions [b0, b0 + 256) (clipped at n) whose halves are
+// each in order: position i against 255 - i, then the half-cleaners of a
+// bitonic merge.
+__device__ void ions_merge_block(double* kr, uint16_t* ki, int b0, int n) {
+  const int lane = threadIdx.x & 63;
+  double r[4];
+  uint32_t k[4];
+  ik_load(kr, ki, b0, n, r, k);
+  if (ik_sorted(r, k)) return;
+  {
+    double pr[4];
+    uint32_t pq[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {       // lane 63 - lane, register 3 - j
+      const uint64_t v = (uint64_t)__double_as_longlong(r[3 - j]);
+      uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32), q = k[3 - j];
+      lo = lane_xor(lane_xor(lane_xor(lane_xor(lane_xor(lane_xor(lo, 1), 2), 4), 8), 16), 32);
+      hi = lane_xor(lane_xor(lane_xor(lane_xor(lane_xor(lane_xor(hi, 1), 2), 4), 8), 16), 32);
+      q = lane_xor(lane_xor(lane_xor(lane_xor(lane_xor(lane_xor(q, 1), 2), 4), 8), 16), 32);
+      pr[j] = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+      pq[j] = q;
+    }
+    const bool lower = lane < 32;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (ik_lt(pr[j], pq[j], r[j], k[j]) == lower) { r[j] = pr[j]; k[j] = pq[j]; }
+  }
+#pragma unroll
+  for (int d = 64; d > 0; d >>= 1) ik_stage(r, k, 256, d);
+  ik_store(kr, ki, b0, n, r, k);
+}
+
+// Order of n nearly sorted keys in LDS (position order), in place: the
+// wave blocks of 256 positions at 0, 256, ... sorted, those at 128, 384, ...
+// (two sorted halves) merged; if a ring moved more than 128 positions the
+// junctions of the second blocks are left out of order and the bitonic
+// network sorts all positions.
+__device__ void ions_fix_order(double* kr, uint16_t* ki, int n) {
+  constexpr int NW = NT / 64;
+  static_assert(NMAX <= 64 * 256, "a junction per lane");
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  #pragma unroll 1
+  for (int b = wave; b * 256 < n; b += NW) ions_sort_block(kr, ki, b * 256, n);
+  __syncthreads();
+  #pragma unroll 1
+  for (int b = wave; 256 * (b + 1) < n; b += NW) ions_merge_block(kr, ki, 128 + b * 256, n);
+  __syncthreads();
+  bool out = false;
+  const int q = 128 + 256 * lane;
+  if (q < n) out = ik_lt(kr[q], ki[q], kr[q - 1], ki[q - 1]);
+  if (__syncthreads_or(out)) bitonic_ions(kr, ki, n);
+}
+
 // The interval of radius r among the nodes of species o (node 0 the axis,
 // node j = its ring j-1, node N+1 its edge): the lower node is j = cnt, the
 // number of its rings below r; t the fraction of the way to node j+1.
@@ -204,7 +357,7 @@ __global__ __launch_bounds__(NT) void ions_march_kernel(const WakeIons* __restri
       }
       const bool resort = __syncthreads_or(dis) != 0;
       if (resort) {
-        bitonic_ions(sr, s_id, N);
+        ions_fix_order(sr, s_id, N);
         ++fixups;
       }
       int32_t* const sid = I.sid + (size_t)s * S;
