@@ -15,7 +15,9 @@
 //
 // Per slice:
 //   order    each species' (rho, id) order: the previous one if it still
-//            holds, else a bitonic sort in LDS;
+//            holds, else wave blocks of 256 positions sorted in LDS and the
+//            blocks between them merged (the bitonic network over all
+//            positions when a ring moved more than 128 positions);
 //   sums     own psi and d_rho psi at each species' rings (eqs. psi,
 //            dpsi_dr; double-double prefix of w and suffix of w ln rho, the
 //            ring itself with w^), its axis value, outer edge and exterior
