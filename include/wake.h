@@ -323,7 +323,10 @@ int wake_set_species_state(wake_ctx *ctx, int32_t species, int32_t slice, const 
  * Tiling of the marcher.  A workgroup of `threads` threads owns one instance;
  * thread t owns the ceil(n_rings / threads) consecutive rings (in radial
  * order) starting at t * ceil(n_rings / threads).  `threads` is fixed for a
- * context when it is created (256, 512 or 1024).  Persistent launches place
+ * context when it is created (256 or 512; a workgroup of 1024 threads holds
+ * four waves per SIMD, which leaves the marcher 128 registers per lane: it
+ * spilled 167-404 of them and marched slower, so it is not offered).
+ * Persistent launches place
  * `wgs_per_cu` workgroups on each compute unit (0: as many as fit).  The
  * choice changes summation order only (results agree to rounding).
  * wake_tiling_get returns the threads of entry `index` and how many such
@@ -338,8 +341,8 @@ int wake_tiling_occupancy(int32_t threads, int32_t wgs_per_cu);
 
 /* ---------------------------------------------------------------------
  * Cooperative instances (the large-ring-count path).  A context with more
- * rings than one workgroup can keep ordered in LDS (more than 16 * threads
- * at 256 or 512 threads, 7 * 1024 at 1024) is marched by G workgroups
+ * rings than one workgroup can keep ordered in LDS (more than 16 * threads)
+ * is marched by G workgroups
  * together, member g owning the sorted positions [g P, g P + P), P = C *
  * threads, with C = max(rings_per_thread, ceil(n_rings / (M threads)))
  * and G = ceil(n_rings / P) <= M, M = the smaller of 256 and the
@@ -362,8 +365,8 @@ int wake_get_layout(wake_ctx *ctx, int32_t *workgroups, int32_t *rings_per_threa
  * Autotuner of the layout per ring-count bucket (the batched form's
  * "rings per workgroup and LDS tiling").  Bucket b holds ring counts in
  * [lo[b], lo[b+1]) (the last has no upper end); a context created while a
- * tuning is installed takes its bucket's workgroup threads (256, 512 or
- * 1024: the LDS tiling of the marcher) and rings per thread of cooperative
+ * tuning is installed takes its bucket's workgroup threads (256 or 512: the
+ * LDS tiling of the marcher) and rings per thread of cooperative
  * members (0: one workgroup per context, never cooperative; else
  * cooperative from the moment it gives two or more members).  Tiling and
  * cluster settings apply to contexts only while no tuning is installed; the
@@ -384,7 +387,7 @@ typedef struct {
  * for wake_create / wake_add_beam; sources[i] points at n_sources[i]
  * sources; host arrays) are grouped into the buckets lo = 0, 2048, 4096,
  * 8192, 16384, 32768, 65536, 131072 rings; for every bucket with instances,
- * each candidate layout (one workgroup of 256, 512 or 1024 threads where
+ * each candidate layout (one workgroup of 256 or 512 threads where
  * the keys of every position fit its LDS; cooperative members of 512
  * threads with 1, 2, 4 or 8 rings per thread where the ring counts exceed
  * 2048) marches all of the bucket's instances together through their first

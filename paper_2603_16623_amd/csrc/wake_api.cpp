@@ -610,7 +610,7 @@ static int prepare_impl(wake_ctx* c, char* table, size_t table_bytes, char* scra
     std::vector<double>().swap(c->pw);
     std::vector<double>().swap(c->pq);
   }
-  HIP_TRY(march_prepare(I.nt));
+  if (!c->two_species) HIP_TRY(march_prepare(I.nt));   // the two-species marcher is set up at creation
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->prepared = true;
   return WAKE_OK;
@@ -1183,12 +1183,12 @@ extern "C" int wake_reset(wake_ctx* c) {
 // tiling: workgroup threads (fixed per context at creation) and workgroups
 // per compute unit of persistent launches
 // ---------------------------------------------------------------------------
-static const int kThreads[] = {256, 512, 1024};
+static const int kThreads[] = {256, 512};
 
-extern "C" int wake_tiling_count(void) { return 3; }
+extern "C" int wake_tiling_count(void) { return 2; }
 
 extern "C" int wake_tiling_get(int32_t idx, int32_t* nt, int32_t* wpc) {
-  if (!nt || !wpc || idx < 0 || idx >= 3) return WAKE_EINVAL;
+  if (!nt || !wpc || idx < 0 || idx >= 2) return WAKE_EINVAL;
   *nt = kThreads[idx];
   *wpc = march_occupancy(kThreads[idx]);
   return WAKE_OK;

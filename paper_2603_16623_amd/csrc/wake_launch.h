@@ -25,7 +25,7 @@ hipError_t launch_state_set(const WakeInst& I, const double* rho, const double* 
 hipError_t launch_reset(const WakeInst* d_insts, int n_insts, hipStream_t s);
 hipError_t launch_ctl_gather(const WakeInst* d_insts, int n, int32_t* out, hipStream_t s);
 
-// marcher: workgroups of nt threads (256, 512 or 1024)
+// marcher: workgroups of nt threads (256 or 512)
 bool march_threads_ok(int nt);
 size_t march_lds_bytes(int nt);
 // grid_mode: 0 the plain variant; 1 the variant that also evaluates the

@@ -1346,7 +1346,7 @@ template <int NT>
 struct MarchLds {
   static constexpr int NW = NT / 64;
   // rings per thread up to which the keys of every position live in LDS
-  static constexpr int CMAX = NT >= 1024 ? 7 : 16;
+  static constexpr int CMAX = 16;
   static constexpr int KCAP = NT * CMAX;
   static constexpr size_t region_bytes() {
     const size_t beam = 2 * WAKE_BCAP * sizeof(double);
@@ -1370,10 +1370,8 @@ struct MarchLds {
 // one workgroup's LDS must fit the 160 KiB of a compute unit
 static_assert(MarchLds<256>::bytes() <= 160 * 1024, "LDS layout too large");
 static_assert(MarchLds<512>::bytes() <= 160 * 1024, "LDS layout too large");
-static_assert(MarchLds<1024>::bytes() <= 160 * 1024, "LDS layout too large");
 // the block fix-up checks one junction of 256-position blocks per lane
-static_assert(MarchLds<256>::KCAP <= 64 * 256 && MarchLds<512>::KCAP <= 64 * 256 &&
-              MarchLds<1024>::KCAP <= 64 * 256, "junctions per lane");
+static_assert(MarchLds<256>::KCAP <= 64 * 256 && MarchLds<512>::KCAP <= 64 * 256, "junctions per lane");
 // a cooperative member gathers the packs of every member into its key area
 static_assert(MarchLds<256>::key_bytes() >= WAKE_CL_GMAX * 16 * sizeof(double), "pack area");
 // field-grid variant: the LDS left beside the layout holds the node records
@@ -2718,7 +2716,7 @@ hipError_t launch_state_set(const WakeInst& I, const double* rho, const double* 
   return hipGetLastError();
 }
 
-#define WAKE_THREADS(X) X(256) X(512) X(1024)
+#define WAKE_THREADS(X) X(256) X(512)
 
 size_t march_lds_bytes(int nt) {
 #define X(a) \

@@ -25,7 +25,7 @@ struct Cand {
 // members of 512 threads where the ring counts exceed 2048.
 std::vector<Cand> candidates(int nmin, int nmax) {
   std::vector<Cand> v;
-  for (int nt : {256, 512, 1024})
+  for (int nt : {256, 512})
     if (nmax <= march_cmax(nt) * nt) v.push_back({nt, 0});
   if (nmin > 2048)
     for (int rpt : {1, 2, 4, 8})

@@ -68,7 +68,7 @@ def test_chi_slice_parity_uniform_grids(wk):
     a laser under a grid finer than the rings near the axis (nodes whose
     hats hold no ring deposit 0)."""
     inst = W.small_instance(7, n_rings=300, n_xi=200, n_peak=4.0, sigma_r=0.1, dxi=0.01)
-    for tiling in ((256, 0), (1024, 0)):
+    for tiling in ((256, 0), (512, 0)):
         _check(wk, inst, tiling, (0, 0), lambda s: s.wake_set_grid(97, 4.5), grid_radii(97, 4.5),
                (0, 60, 130, 199))
     inst = W.small_instance(10, n_rings=700, n_xi=200, n_peak=1.0, laser=True, dxi=0.01,

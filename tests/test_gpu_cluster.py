@@ -235,7 +235,7 @@ def test_cluster_members_wait_for_busy_workgroups(wk):
 
 @pytest.mark.parametrize("u_amp", [0.5, 40.0])
 def test_cluster_fixups_in_device_memory(wk, u_amp):
-    """Members whose keys exceed the LDS area (1024-thread workgroups, eight
+    """Members whose keys exceed the LDS area (512-thread workgroups, sixteen
     rings per thread: 8192 positions per member) fix their order in device
     memory: member-local rounds, rounds over all members and the bitonic
     network, after pushes that move rings a few to thousands of places.  The
@@ -247,15 +247,15 @@ def test_cluster_fixups_in_device_memory(wk, u_amp):
     state["u"] = rng.normal(0, u_amp, inst.n_rings)
     n = 8
     _, mid = o.slice(n, state, keep=True)
-    wk.wake_set_tiling(1024, 0)
-    wk.wake_set_cluster(8, 500)
+    wk.wake_set_tiling(512, 0)
+    wk.wake_set_cluster(16, 500)
     label = f"cluster fix-ups in device memory u_amp={u_amp}"
     _say(label)
     st, mid_dev = pushed_by_device(wk, inst, n, state)
     check_state(st, mid, label)
     ref, _ = o.slice(n + 1, mid_dev, keep=True)
     s = wk.WakeSolver.from_instance(inst, record_stride=1)
-    assert s.layout() == (3, 8)
+    assert s.layout() == (3, 16)
     s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
     s.wake_solve(n, 2)
     got = s.wake_fields(n + 1)

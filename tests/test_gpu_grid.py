@@ -74,10 +74,10 @@ def _check_slices(wk, inst, tiling, cluster, n_r, r_max, slices, layout=None):
 
 def test_grid_slice_parity_small_tilings(wk):
     """300 geometric rings, 2 per thread (256) and one per thread with idle
-    threads (1024); nodes inside the first ring, between rings, beyond the
+    threads (512); nodes inside the first ring, between rings, beyond the
     last ring and beyond the plasma edge (r_max = 1.5 R_p)."""
     inst = W.small_instance(7, n_rings=300, n_xi=200, n_peak=4.0, sigma_r=0.1, dxi=0.01)
-    for tiling in ((256, 0), (1024, 0)):
+    for tiling in ((256, 0), (512, 0)):
         _check_slices(wk, inst, tiling, (0, 0), 97, 4.5, (0, 60, 130, 199))
 
 

@@ -60,13 +60,12 @@ def _case(name):
 # owns ceil(N / threads) consecutive rings
 SLICE_CASES = [
     ("blowout-geometric", (256, 0), (0, 1, 60, 130, 199)),   # 300 rings: 2 per thread, ragged
-    ("blowout-geometric", (1024, 0), (0, 90, 150)),          # 1 ring per thread, idle threads
+    ("blowout-geometric", (512, 0), (0, 90, 150)),           # 1 ring per thread, idle threads
     ("laser-beam", (512, 0), (0, 40, 100, 170)),
     ("uniform-linear", (512, 0), (0, 250, 700)),
     ("laser-channel", (256, 0), (0, 50, 120, 190)),          # 3 rings per thread, ragged
     ("multitile-1200", (256, 0), (0, 70, 120)),              # 5 rings per thread
     ("multitile-1200", (512, 0), (100,)),
-    ("multitile-1200", (1024, 0), (110,)),
 ]
 
 @pytest.mark.parametrize("case,tiling,slices", SLICE_CASES)

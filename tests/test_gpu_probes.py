@@ -62,7 +62,7 @@ def _march_and_check(wk, s, o, inst, slices, radii_of, label):
         check_fields(got, ref, field_scales(ref, want), f"{label} slice={n} nodes={r.size}", want=want)
 
 
-@pytest.mark.parametrize("tiling,cluster,layout", [((256, 0), (0, 0), None), ((1024, 0), (0, 0), None),
+@pytest.mark.parametrize("tiling,cluster,layout", [((256, 0), (0, 0), None), ((512, 0), (0, 0), None),
                                                    ((256, 0), (2, 500), (6, 2))])
 def test_fixed_radii_slice_parity(wk, tiling, cluster, layout):
     """The same 300-odd radii every slice (inside the first ring, between

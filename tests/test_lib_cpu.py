@@ -41,7 +41,8 @@ def test_strerror_and_footprint_need_no_device():
     big = wake.wake_footprint(20_000, 4000, 70_000, 0)
     assert 0 < small < big
     assert wake.wake_footprint(-1, 10, 0, 0) < 0
-    assert wake.wake_tiling_count() == 3
+    assert wake.wake_tiling_count() == 2
+    assert lib.wake_set_tiling(1024, 0) == wake.WAKE_EINVAL   # 1024-thread marcher not offered
 
 
 def test_malformed_tunings_are_refused_without_a_device():
