@@ -15,9 +15,9 @@
 //
 // Per slice:
 //   order    each species' (rho, id) order: the previous one if it still
-//            holds, else wave blocks of 256 positions sorted in LDS and the
-//            blocks between them merged (the bitonic network over all
-//            positions when a ring moved more than 128 positions);
+//            holds, else rounds of wave blocks of 256 positions sorted in
+//            LDS and the blocks between them merged (the bitonic network
+//            over all positions after three rounds that leave disorder);
 //   sums     own psi and d_rho psi at each species' rings (eqs. psi,
 //            dpsi_dr; double-double prefix of w and suffix of w ln rho, the
 //            ring itself with w^), its axis value, outer edge and exterior
@@ -226,25 +226,31 @@ __device__ void ions_merge_block(double* kr, uint16_t* ki, int b0, int n) {
   ik_store(kr, ki, b0, n, r, k);
 }
 
-// Order of n nearly sorted keys in LDS (position order), in place: the
-// wave blocks of 256 positions at 0, 256, ... sorted, those at 128, 384, ...
-// (two sorted halves) merged; if a ring moved more than 128 positions the
-// junctions of the second blocks are left out of order and the bitonic
-// network sorts all positions.
+// Order of n nearly sorted keys in LDS (position order), in place, in
+// rounds: the wave blocks of 256 positions at 0, 256, ... sorted, those at
+// 128, 384, ... (two sorted halves) merged, and the order checked at the
+// junctions of the second blocks (every segment between them is sorted).
+// A ring that moved more than 128 positions leaves a junction out of order
+// for the next round; after three rounds the bitonic network sorts all
+// positions.
 __device__ void ions_fix_order(double* kr, uint16_t* ki, int n) {
   constexpr int NW = NT / 64;
   static_assert(NMAX <= 64 * 256, "a junction per lane");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   #pragma unroll 1
-  for (int b = wave; b * 256 < n; b += NW) ions_sort_block(kr, ki, b * 256, n);
-  __syncthreads();
-  #pragma unroll 1
-  for (int b = wave; 256 * (b + 1) < n; b += NW) ions_merge_block(kr, ki, 128 + b * 256, n);
-  __syncthreads();
-  bool out = false;
-  const int q = 128 + 256 * lane;
-  if (q < n) out = ik_lt(kr[q], ki[q], kr[q - 1], ki[q - 1]);
-  if (__syncthreads_or(out)) bitonic_ions(kr, ki, n);
+  for (int round = 0; round < 3; ++round) {
+    #pragma unroll 1
+    for (int b = wave; b * 256 < n; b += NW) ions_sort_block(kr, ki, b * 256, n);
+    __syncthreads();
+    #pragma unroll 1
+    for (int b = wave; 256 * (b + 1) < n; b += NW) ions_merge_block(kr, ki, 128 + b * 256, n);
+    __syncthreads();
+    bool out = false;
+    const int q = 128 + 256 * lane;
+    if (q < n) out = ik_lt(kr[q], ki[q], kr[q - 1], ki[q - 1]);
+    if (!__syncthreads_or(out)) return;     // also: every wave has read its junction keys
+  }
+  bitonic_ions(kr, ki, n);
 }
 
 // The interval of radius r among the nodes of species o (node 0 the axis,
