@@ -145,7 +145,7 @@ size_t arena_bytes(int N, int n_xi, int stride, const Layout& L) {
   d += 4 * (size_t)N;                       // staging
   if (Gi > 1) {                             // cooperative: exchange, keys, fallback sort
     const size_t P2 = pow2_at_least((size_t)N);
-    d += 2 * (size_t)Gi * 16 + S + P2;
+    d += 2 * (size_t)Gi * 17 + S + P2;
     i += 4 + S + 2 * P2;
   }
   return d * 8 + i * 4 + 64 * 256;          // + alignment slack
@@ -315,7 +315,7 @@ int ctx_create(wake_ctx** out, const wake_plasma* plasma, const wake_domain* dom
   c->staging = A.take<double>(4 * (size_t)N);
   if (I.G > 1) {
     const size_t P2 = pow2_at_least((size_t)N);
-    I.xd = A.take<double>((size_t)2 * I.G * 16);
+    I.xd = A.take<double>((size_t)2 * I.G * 17);   // packs and stamps
     I.xc = A.take<int32_t>(4);
     I.gk_r = A.take<double>(S);
     I.gk_i = A.take<int32_t>(S);

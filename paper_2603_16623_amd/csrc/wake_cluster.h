@@ -8,10 +8,15 @@
 //
 // Barrier.  Each member publishes a pack (agent-scope atomic stores, which
 // write through to the point where all XCDs meet), waits for those stores to
-// complete and then stores the round number as the pack's last word (its
-// stamp); thread m of every member polls member m's stamp until it reads the
-// round and then reads that pack with agent-scope atomic loads.  There is no
-// shared arrival counter.  Packs alternate between two buffers by round; a
+// complete and then stores the round number in its stamp word (the pack's
+// last word, or a word beside the other members' stamps in instances of many
+// members); thread m of every member polls member m's stamp until it reads the
+// round, and once every stamp has been seen the member reads all the packs
+// with agent-scope atomic loads, consecutive lanes on consecutive words (a
+// wave's loads then fetch each line of the packs once, where one thread per
+// pack made every member fetch every line once per word: at 196 members that
+// was ~5x10^5 requests on 392 lines per meeting).  There is no shared arrival
+// counter.  Packs alternate between two buffers by round; a
 // member writes buffer b again only two rounds later, when every member has
 // read it (it could not have passed the round in between otherwise).  The per-slice exchanges carry
 // nothing but their packs and take no cache maintenance.  The fenced form,
@@ -40,10 +45,22 @@ static_assert(WAKE_CL_GMAX <= 256, "member scans combine four members per lane")
 struct Cluster {
   int g, G;      // this member, members
   int round;     // barriers passed in this launch
-  double* xd;    // [2][G][16]: packs, the stamp (round) in word 15
+  double* xd;    // [2][G][16] packs, then [2][G] stamps (see cl_stamp_at)
   int32_t* xc;   // [1] give-up, [2] members started
   const int32_t* queue;   // task queue counter of the launch
 };
+
+// Index in xd of member m's stamp word in buffer buf.  Below
+// WAKE_CL_DENSE_STAMPS members it is the pack's last word (word 15); from
+// there on the stamps sit side by side after the packs, eight to a 64-B
+// line, so a wave's polls fetch eight stamps per request (with 196 members
+// the polls of every member on every other member's line had become the
+// meetings' main cost; with 40, stamps sharing lines made the stores of the
+// last arrivals slower instead).
+#define WAKE_CL_DENSE_STAMPS 64
+__device__ __forceinline__ size_t cl_stamp_at(int G, int buf, int m) {
+  return G >= WAKE_CL_DENSE_STAMPS ? (size_t)32 * G + (size_t)buf * G + m : ((size_t)buf * G + m) * 16 + 15;
+}
 
 // Counts the member in as started (once per launch, before its first
 // exchange).
@@ -83,8 +100,9 @@ __device__ __noinline__ int cl_await(const WAKE_GLOBAL double* sp, double want, 
 // Every thread of every member calls it at the same point of the march.
 // Thread 0 writes the member's pack (write-through stores), waits for them
 // to complete and then writes the pack's stamp, the round number; thread m
-// waits for member m's stamp of this round and copies its pack.  There is
-// no shared counter: every member's arrival is its own word.  FENCED also
+// waits for member m's stamp of this round; then the member's threads copy
+// all packs, word by word across the lanes.  There is no shared counter:
+// every member's arrival is its own word.  FENCED also
 // publishes the plain device-memory writes before it (release fence before
 // the stamp) and makes the others' visible after it (acquire fence).
 // Returns false when a member gave up.
@@ -108,17 +126,18 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
       __builtin_amdgcn_s_waitcnt(0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    __hip_atomic_store(slot + 15, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(xd + cl_stamp_at(cl.G, buf, cl.g), stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   const int m = threadIdx.x;
   if (m < cl.G) {
-    const WAKE_GLOBAL double* p = xd + ((size_t)buf * cl.G + m) * 16;
-    if (cl_await(p + 15, stamp, gptr(cl.xc), gptr(cl.queue), cl.G)) {
-#pragma unroll
-      for (int f = 0; f < NF; ++f)
-        s_x[m * NF + f] = __hip_atomic_load(p + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      *s_ok = 0;
+    if (!cl_await(xd + cl_stamp_at(cl.G, buf, m), stamp, gptr(cl.xc), gptr(cl.queue), cl.G)) *s_ok = 0;
+  }
+  __syncthreads();                                   // every stamp of the round seen
+  if (*s_ok) {
+    const WAKE_GLOBAL double* base = xd + (size_t)buf * cl.G * 16;
+    for (int i = threadIdx.x; i < cl.G * 16; i += blockDim.x) {
+      const int f = i & 15;
+      if (f < NF) s_x[(i >> 4) * NF + f] = __hip_atomic_load(base + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   __syncthreads();

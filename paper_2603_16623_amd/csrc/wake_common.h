@@ -101,7 +101,7 @@ struct WakeInst {
   double *sk_r[2];
   int32_t *sk_i[2], *sk_s[2];
   int32_t *free_slot;
-  // cooperative instances: exchange packs [2][G][16], control words
+  // cooperative instances: exchange packs [2][G][16] and stamps [2][G], control words
   // (barrier arrivals, give-up flag), sort keys by slot, fallback sort arrays
   // of the next power of two >= N
   double *xd;

@@ -2559,7 +2559,7 @@ __global__ void cluster_reset_kernel(const WakeInst* __restrict__ insts, int n_i
     const int G = insts[i].G;
     if (G <= 1) continue;
     insts[i].xc[0] = 0; insts[i].xc[1] = 0; insts[i].xc[2] = 0;
-    for (int k = 0; k < 2 * G; ++k) insts[i].xd[(size_t)k * 16 + 15] = -1.0;
+    for (int k = 0; k < 2 * G; ++k) insts[i].xd[cl_stamp_at(G, k / G, k % G)] = -1.0;
   }
 }
 
