@@ -152,18 +152,19 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
 
 // Exclusive prefix over members (op(earlier, later)) of the packs gathered at
 // s_x (field offset off, NFT doubles per member) for member g, and the total.
-// G <= WAKE_CL_GMAX: lane l of each wave combines members 4l .. 4l+3 in
-// order (ident beyond the last member, which op absorbs exactly), a wave scan
-// runs over the lanes, and member g's prefix is the lanes before its own
-// followed by the members of its lane below it.
-template <int NF, int NFT, class Op>
+// G <= 64 MPL: lane l of each wave combines members MPL l .. MPL l + MPL-1
+// in order (ident beyond the last member, which op absorbs exactly), a wave
+// scan runs over the lanes, and member g's prefix is the lanes before its
+// own followed by the members of its lane below it.  MPL = 1 (G <= 64)
+// leaves out the serial steps on either side of the wave scan.
+template <int NF, int NFT, class Op, int MPL = 4>
 __device__ __forceinline__ void cl_prefix(const double* s_x, int off, int g, int G, const Pack<NF>& ident,
                                           Op op, Pack<NF>& pre, Pack<NF>& tot) {
   const int lane = threadIdx.x & 63;
   Pack<NF> blk = ident;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int m = 4 * lane + j;
+  for (int j = 0; j < MPL; ++j) {
+    const int m = MPL * lane + j;
     if (m < G) {
       Pack<NF> x;
 #pragma unroll
@@ -172,10 +173,10 @@ __device__ __forceinline__ void cl_prefix(const double* s_x, int off, int g, int
     }
   }
   const Pack<NF> inc = wave_prefix_incl(blk, op);
-  const int lg = g >> 2;
+  const int lg = g / MPL;
   const Pack<NF> before = lane_pack(inc, lg > 0 ? lg - 1 : 0);
   Pack<NF> p = lg > 0 ? before : ident;
-  for (int m = 4 * lg; m < g; ++m) {
+  for (int m = MPL * lg; m < g; ++m) {
     Pack<NF> x;
 #pragma unroll
     for (int i = 0; i < NF; ++i) x.v[i] = s_x[m * NFT + off + i];

@@ -1255,10 +1255,10 @@ struct BwdMatSumOp {  // (index-order product of inverse transfers, running sum)
 // and suffix sg of the transfers (inverse transfers from the adjugates of
 // the published products, det = 1), their totals, and the det-sums of the
 // members before it (e_in) and after it (d_in).  Lane l of each wave takes
-// members 4l .. 4l+3 (G <= 256).
+// members MPL l .. MPL l + MPL-1 (G <= 64 MPL).
 struct FwdMatSumOp;
 struct BwdMatSumOp;
-template <int NFT, class FOp, class BOp>
+template <int NFT, class FOp, class BOp, int MPL>
 __device__ __forceinline__ void cl_transfer_scan(const double* s_x, int g, int G, Pack<5>& pg, Pack<5>& gt,
                                                  Pack<5>& sg, Pack<5>& ht, double& e_in, double& d_in) {
   const int lane = threadIdx.x & 63;
@@ -1275,11 +1275,11 @@ __device__ __forceinline__ void cl_transfer_scan(const double* s_x, int g, int G
   };
   Pack<5> bf = I5, bb = I5;
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (4 * lane + j < G) bf = fop(bf, fwd_of(4 * lane + j));
+  for (int j = 0; j < MPL; ++j)
+    if (MPL * lane + j < G) bf = fop(bf, fwd_of(MPL * lane + j));
 #pragma unroll
-  for (int j = 3; j >= 0; --j)
-    if (4 * lane + j < G) bb = bop(bwd_of(4 * lane + j), bb);
+  for (int j = MPL - 1; j >= 0; --j)
+    if (MPL * lane + j < G) bb = bop(bwd_of(MPL * lane + j), bb);
   const Pack<5> incF = wave_prefix_incl(bf, fop), incB = wave_suffix_incl(bb, bop);
   Pack<5> exF, exB;                     // the members before this lane's, after them
 #pragma unroll
@@ -1288,12 +1288,12 @@ __device__ __forceinline__ void cl_transfer_scan(const double* s_x, int g, int G
   if (lane == 63) exB = I5;
   gt = lane_pack(incF, 63);
   ht = lane_pack(incB, 0);
-  double vm[4], dtm[4], etm[4];
+  double vm[MPL], dtm[MPL], etm[MPL];
   Pack<5> pg_l = I5, sg_l = I5;
   Pack<5> x = exB;
 #pragma unroll
-  for (int j = 3; j >= 0; --j) {        // descending: the suffix after each member
-    const int m = 4 * lane + j;
+  for (int j = MPL - 1; j >= 0; --j) {  // descending: the suffix after each member
+    const int m = MPL * lane + j;
     vm[j] = x.v[4];
     dtm[j] = 0.0;
     if (m < G) {
@@ -1306,8 +1306,8 @@ __device__ __forceinline__ void cl_transfer_scan(const double* s_x, int g, int G
   }
   x = exF;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {         // ascending: the prefix before each member
-    const int m = 4 * lane + j;
+  for (int j = 0; j < MPL; ++j) {       // ascending: the prefix before each member
+    const int m = MPL * lane + j;
     etm[j] = 0.0;
     if (m < G) {
       const double* q = s_x + m * NFT;
@@ -1317,14 +1317,20 @@ __device__ __forceinline__ void cl_transfer_scan(const double* s_x, int g, int G
       x = fop(x, fwd_of(m));
     }
   }
-  const Pack<1> eI = wave_prefix_incl(Pack<1>{{(etm[0] + etm[1]) + (etm[2] + etm[3])}}, SumOp<1>());
-  const Pack<1> dI = wave_suffix_incl(Pack<1>{{(dtm[0] + dtm[1]) + (dtm[2] + dtm[3])}}, SumOp<1>());
+  static_assert(MPL == 1 || MPL == 4, "one or four members per lane");
+  double esum = etm[0], dsum = dtm[0];
+  if constexpr (MPL == 4) {
+    esum = (etm[0] + etm[1]) + (etm[2] + etm[3]);
+    dsum = (dtm[0] + dtm[1]) + (dtm[2] + dtm[3]);
+  }
+  const Pack<1> eI = wave_prefix_incl(Pack<1>{{esum}}, SumOp<1>());
+  const Pack<1> dI = wave_suffix_incl(Pack<1>{{dsum}}, SumOp<1>());
   double e_own = lane_prev(eI.v[0]), d_own = lane_next(dI.v[0]);
   if (lane == 0) e_own = 0.0;
   if (lane == 63) d_own = 0.0;
-  const int lg = g >> 2, jg = g & 3;
+  const int lg = g / MPL, jg = g % MPL;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < MPL; ++j) {
     if (j < jg) e_own += etm[j];
     if (j > jg) d_own += dtm[j];
   }
@@ -1857,7 +1863,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
       }
       Pack<6> pg;
       my_dis = t6.v[5];
-      cl_prefix<6, 11>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
+      if (cl.G <= 64) cl_prefix<6, 11, SliceHeadOp, 1>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
+      else cl_prefix<6, 11>(s_x, 0, member, cl.G, Pack<6>{{0, 0, 0, 0, 0, 0}}, SliceHeadOp(), pg, t6);
       pre = SliceHeadOp()(pg, pre);
       if constexpr (GRID) {
         rho_mprev = member > 0 ? s_x[(member - 1) * 11 + 8] : -1.0;
@@ -2196,7 +2203,8 @@ __device__ __forceinline__ void march(const WakeInst& I, int member, const int32
         return;
       }
       Pack<5> pg, sg;
-      cl_transfer_scan<13, FwdMatSumOp, BwdMatSumOp>(s_x, member, cl.G, pg, gt, sg, ht, e_in, d_in);
+      if (cl.G <= 64) cl_transfer_scan<13, FwdMatSumOp, BwdMatSumOp, 1>(s_x, member, cl.G, pg, gt, sg, ht, e_in, d_in);
+      else cl_transfer_scan<13, FwdMatSumOp, BwdMatSumOp, 4>(s_x, member, cl.G, pg, gt, sg, ht, e_in, d_in);
       gp = FwdMatSumOp()(pg, gp);
       hx = BwdMatSumOp()(hx, sg);
     }
