@@ -333,11 +333,14 @@ __device__ __forceinline__ bool sort_regs256(double* r, uint64_t* k) {
 
 // One wave puts the positions [b0, b0 + 256) of a cooperative instance in
 // order: keys by slot in device memory (gk_r, gk_i), order perm by position
-// slot.
+// slot; only the positions in [w_lo, w_hi) are written back (a block that
+// two members sort alike, each keeping its own positions), and with src_at
+// the order is read from that array by position instead of from perm.
 template <int NT>
 __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double iC, double iP,
                                            const WAKE_GLOBAL double* gk_r, const WAKE_GLOBAL int32_t* gk_i,
-                                           WAKE_GLOBAL int32_t* perm) {
+                                           WAKE_GLOBAL int32_t* perm, int w_lo = 0, int w_hi = 0x7fffffff,
+                                           const WAKE_GLOBAL int32_t* src_at = nullptr) {
   const int lane = threadIdx.x & 63;
   double r[4];
   uint64_t k[4];
@@ -350,15 +353,17 @@ __device__ __noinline__ void cl_sort_block(int b0, int N, int C, int P, double i
     k[j] = ~0ull;
     if (p < N) {
       sl[j] = cl_slot<NT>(p, C, P, iC, iP);
-      const int src = perm[sl[j]];
+      const int src = src_at ? src_at[p] : perm[sl[j]];
       r[j] = gk_r[src];
       k[j] = ((uint64_t)(uint32_t)gk_i[src] << 32) | (uint32_t)src;
     }
   }
   if (!sort_regs256(r, k)) return;
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (sl[j] >= 0) perm[sl[j]] = (int32_t)(uint32_t)(k[j] & 0xffffffffull);
+  for (int j = 0; j < 4; ++j) {
+    const int p = b0 + 4 * lane + j;
+    if (sl[j] >= 0 && p >= w_lo && p < w_hi) perm[sl[j]] = (int32_t)(uint32_t)(k[j] & 0xffffffffull);
+  }
 }
 
 // The same for keys held by position in LDS (L_r, L_k, positions [0, n)).
@@ -531,13 +536,25 @@ __device__ __noinline__ int cl_fix_round(const WAKE_GLOBAL WakeInst* Ig, Cluster
   constexpr int NW = NT / 64;
   const int wave = tid >> 6;
   if (lo >= 0) {
-    // the same blocks with the interior ones sorted in LDS first: only the
-    // block straddling the next member is sorted between the two meetings
-    cl_lds_blocks<NT>(I, cl.g, first, lo, false);
+    // the same blocks with the interior ones sorted in LDS first; after the
+    // meeting the two members a boundary block straddles both sort it, from
+    // the same keys to the same order, and each writes back its own
+    // positions only, so no second meeting has to publish them; the order
+    // across member boundaries is checked at the next slice head
+    // (the order of the first and last 128 positions of every member also by
+    // position in bt_s, which no member writes again before the next slice
+    // head: the straddling sorts read that copy, so one member's write-back
+    // cannot change the other's input)
+    cl_lds_blocks<NT>(I, cl.g, first, lo, false, gptr(I.bt_s));
     if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
-    if (wave == 0 && goff + Ng < N) cl_sort_block<NT>(goff + Ng - 128, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm));
-    if (!cl_gather<1>(cl, Pack<1>{{0.0}}, s_x, s_ok)) return -1;
-    const int bl = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP);
+    if (wave == 0 && goff + Ng < N)
+      cl_sort_block<NT>(goff + Ng - 128, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm), goff, goff + Ng,
+                        gptr(I.bt_s));
+    if (wave == 1 && goff > 0)
+      cl_sort_block<NT>(goff - 128, N, C, P, iC, iP, gptr(I.gk_r), gptr(I.gk_i), gptr(I.perm), goff, goff + Ng,
+                        gptr(I.bt_s));
+    __syncthreads();
+    const int bl = cl_chunk_disordered<NT>(I, goff, cnt, C, P, iC, iP, true);
     return 2 * cl.round + (__syncthreads_or(bl) ? 1 : 0);
   }
   if (first)           // later rounds continue from the order the previous one left
@@ -597,7 +614,8 @@ __device__ __noinline__ int cl_fix_local(const WAKE_GLOBAL WakeInst* Ig, int g, 
 // member's positions are still out of order (the position after its last is
 // the next member's, checked elsewhere).
 template <int NT>
-__device__ __forceinline__ int cl_lds_blocks(const WakeInst& I, int g, bool first, int lo, bool check) {
+__device__ __forceinline__ int cl_lds_blocks(const WakeInst& I, int g, bool first, int lo, bool check,
+                                             WAKE_GLOBAL int32_t* stage = nullptr) {
   const int tid = threadIdx.x;
   const int N = I.N, C = I.C, P = C * NT;
   const int goff = g * P;
@@ -640,7 +658,9 @@ __device__ __forceinline__ int cl_lds_blocks(const WakeInst& I, int g, bool firs
   for (int k = 0; k < cnt; ++k) {
     const int q = tid * C + k;
     if (check && q + 1 < Ng && k64_lt(L_r[q + 1], L_k[q + 1], L_r[q], L_k[q])) bad = 1;
-    perm[goff + k * NT + tid] = (int32_t)(uint32_t)(L_k[q] & 0xffffffffull);
+    const int32_t v = (int32_t)(uint32_t)(L_k[q] & 0xffffffffull);
+    perm[goff + k * NT + tid] = v;
+    if (stage && (q < 128 || q >= Ng - 128)) stage[goff + q] = v;
   }
   return __syncthreads_or(bad);
 }
