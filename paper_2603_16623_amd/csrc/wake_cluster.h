@@ -119,7 +119,9 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
 #pragma unroll
     for (int i = 0; i < NF; ++i) __hip_atomic_store(slot + i, mine.v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (FENCED) {
-      __threadfence();
+      // release only: the XCD's L2 written back (the member's plain stores
+      // are there after the barrier); the acquire half comes after the wait
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     } else {
       // the pack's write-through stores complete before its stamp
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -143,7 +145,7 @@ __device__ __forceinline__ bool cl_gather(Cluster& cl, const Pack<NF>& mine, dou
   __syncthreads();
   const int ok = *s_ok;
   if (FENCED) {
-    if (threadIdx.x == 0) __threadfence();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // stale lines dropped
     __syncthreads();
   }
   ++cl.round;
