@@ -78,7 +78,8 @@ def test_cluster_slice_parity(wk, tiling, rings, members, channel_w0):
 @pytest.mark.parametrize("u_amp", [0.05, 2.0, 40.0])
 def test_cluster_reorder_after_push(wk, u_amp):
     """Pushed rings crossing a few to thousands of neighbours, across member
-    boundaries: block rounds, and the bitonic fallback for the far moves.
+    boundaries: block rounds over all members, and the sort by segments for
+    the far moves.
     The slice after the push (same launch) against the oracle's slice on
     the device's pushed state."""
     rng = np.random.default_rng(31)
@@ -102,6 +103,14 @@ def test_cluster_reorder_after_push(wk, u_amp):
     got = s.wake_fields(n + 1)
     check_fields(got, ref, field_scales(ref), label)
     assert np.array_equal(got["rho"], mid_dev["rho"])
+    c = s.wake_counters()
+    print(label, {k: c[k] for k in ("fixups", "member_local_rounds", "all_member_rounds", "segment_sorts", "bitonic_fallbacks")}, flush=True)
+    # the crossings reach over member boundaries: rounds over all members
+    # (each with one fenced meeting; both members of a straddling block sort
+    # it) ran, and at the largest velocities the sort by segments after them
+    assert c["all_member_rounds"] >= 1
+    if u_amp >= 40.0:
+        assert c["segment_sorts"] + c["bitonic_fallbacks"] >= 1
     s.close()
 
 
