@@ -75,6 +75,35 @@ def test_cluster_slice_parity(wk, tiling, rings, members, channel_w0):
     s.close()
 
 
+@pytest.mark.parametrize("n_rings,members", [(16300, 64), (16500, 65)], ids=["64-members", "65-members"])
+def test_cluster_member_count_edges(wk, n_rings, members):
+    """At 64 members the member scans still take one member per lane while the
+    stamps already sit side by side; at 65 the scans take four members per
+    lane.  Slice parity against the oracle at both edges."""
+    inst = _inst(n=n_rings, n_xi=40)
+    o = _oracle(inst)
+    wk.wake_set_tiling(256, 0)
+    wk.wake_set_cluster(1, 500)
+    s = wk.WakeSolver.from_instance(inst, record_stride=1)
+    assert s.layout() == (members, 1)
+    state = o.initial_state()
+    at = 0
+    for n in (0, 30):
+        for m in range(at, n):
+            _, state = o.slice(m, state)
+        at = n
+        ref, new = o.slice(n, state, keep=True)
+        sc = field_scales(ref)
+        label = f"cluster {members} members slice={n}"
+        _say(f"cluster member-count edge {label}")
+        s.wake_set_state(n, state["rho"], state["u"], state["fr"], state["fu"])
+        s.wake_solve(n, 1)
+        got = s.wake_fields(n)
+        check_fields(got, ref, sc, label)
+        check_state(s.wake_get_state(), new, label)
+    s.close()
+
+
 @pytest.mark.parametrize("u_amp", [0.05, 2.0, 40.0])
 def test_cluster_reorder_after_push(wk, u_amp):
     """Pushed rings crossing a few to thousands of neighbours, across member
